@@ -1,0 +1,187 @@
+/*
+ * nqs.h -- C interface of libnqs, the MI355X (gfx950) library for
+ * mixed-precision Metropolis-Hastings sampling of neural quantum states.
+ *
+ * The operations follow "Neural Quantum States in Mixed Precision"
+ * (arXiv 2601.20782):
+ *   nqs_downcast       FP64 master -> reduced-precision sampling copy
+ *                      (two-copy scheme, Sec. IV.B; formats of App. A, Table A)
+ *   nqs_sample         Metropolis-Hastings sampling of pi = |psi|^2 / sum |psi|^2
+ *                      (Sec. II, Eq. eq:loss; acceptance Sec. III.A; single-flip
+ *                      proposal App. C Eq. eq:app:local_prop; exchange move App. E)
+ *   nqs_local_energy   eps(x) = sum_{x'} H(x,x') psi(x')/psi(x)
+ *                      (App. I.1, Eq. eq:local_energies; TFIM Eq. eq:TFIM; Heisenberg App. E)
+ *   nqs_energy_stats   FP64 mean / variance / error bar of the local energies (Eq. eq:loss)
+ *   nqs_logpsi_grad    O_k(x) = d log psi(x) / d theta_k (App. I.1, Eq. eq:forces)
+ *   nqs_forces         F = E[O eps] - E[O] E[eps] (Eq. eq:forces), FP64
+ *   nqs_gram           S = E[Obar^T Obar] (Eq. eq:smat) or its sample-space twin
+ *                      T = Obar Obar^T / n, FP32 matrix cores
+ *
+ * Conventions (every entry point):
+ *   - All array arguments are DEVICE pointers unless marked "host".  The
+ *     caller allocates and owns every buffer; the library owns only the model
+ *     handle (its reduced-precision weight copies and lookup tables) and a
+ *     per-device workspace it grows on demand.
+ *   - Calls are stream ordered and asynchronous: `stream` is a hipStream_t
+ *     (NULL = the default stream).  Argument validation happens on the host
+ *     before any launch; a rejected call launches nothing.
+ *   - Spins are int8 +1 (up) / -1 (down); configurations are row-major
+ *     [sample][site]; site i = x*L + y on an L x L lattice.
+ *   - Errors are status codes; nqs_last_error() returns a thread-local message
+ *     describing the last non-OK status.  Faults inside kernels surface at the
+ *     caller's next synchronisation of `stream`.
+ *   - Results depend only on (parameters, configuration, seed, step offset,
+ *     global chain id): not on the launch shape chosen by the autotuner.
+ */
+#ifndef NQS_H
+#define NQS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NQS_OK = 0,
+    NQS_EINVAL = 1,        /* bad argument (shape, null pointer, out-of-range value) */
+    NQS_ENOMEM = 2,        /* device allocation failed */
+    NQS_EDEVICE = 3,       /* a HIP call failed */
+    NQS_EUNSUPPORTED = 4,  /* valid but not implemented combination */
+    NQS_ENUMERIC = 5       /* non-finite parameters */
+} nqs_status;
+
+typedef enum { NQS_F64 = 0, NQS_F32 = 1, NQS_F16 = 2, NQS_BF16 = 3, NQS_FP8_E4M3 = 4 } nqs_dtype;
+typedef enum { NQS_RBM = 0, NQS_FFNN = 1 } nqs_arch;
+typedef enum { NQS_MOVE_FLIP = 0, NQS_MOVE_EXCHANGE = 1 } nqs_move;
+typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_ham_kind;
+
+#define NQS_MAX_LAYERS 8
+
+/* Network description.
+ * RBM (App. G, real parameters): log psi = a.s + sum_{j<M} log cosh((W s + b)_j),
+ *   widths[0] = M, parameter vector [a(N), b(M), W(M x N, row-major)].
+ * FFNN: h_l = ReLU(W_l h_{l-1} + b_l) for l < n_layers, log psi = sum log cosh(z_last),
+ *   parameter vector [W_1 (w1 x N), b_1, W_2 (w2 x w1), b_2, ...].
+ * marshall = 1 multiplies psi by (-1)^{#up spins on sublattice A}, A = {(x+y) even}
+ *   (lat_dim = 2) or {i even} (lat_dim = 1), on an L = lat_L lattice. */
+typedef struct {
+    int32_t arch;                     /* nqs_arch */
+    int32_t n_visible;                /* N */
+    int32_t n_layers;                 /* RBM: 1 */
+    int32_t widths[NQS_MAX_LAYERS];
+    int32_t marshall;
+    int32_t lat_dim, lat_L;
+} nqs_model_desc;
+
+/* Hamiltonian on a dim-dimensional periodic (pbc = 1) or open lattice of side L (L >= 3 when periodic):
+ *   NQS_TFIM:       H = J sum_<ij> sz_i sz_j + h sum_i sx_i           (Eq. eq:TFIM)
+ *   NQS_HEISENBERG: H = J sum_<ij> sigma_i . sigma_j (Pauli matrices)  (App. E) */
+typedef struct {
+    int32_t kind;                     /* nqs_ham_kind */
+    int32_t dim, L, pbc;
+    double J, h;
+} nqs_ham_desc;
+
+/* Sampling configuration (Sec. III.A).
+ * Each proposal consumes one Philox4x32-10 block (Salmon et al., SC'11) with
+ * key = seed and counter = (step, global chain id, instance_id << 8 | 0): site
+ * i = floor(r0*N/2^32); exchange partner j = floor(r1*(N-1)/2^32), j += (j >= i);
+ * u = (r2 >> 8) * 2^-24.  Accept iff u < exp(min(Delta, 0)), Delta =
+ * 2 (log|psi(s')| - log|psi(s)|), computed in FP32 from the `dtype` copy.
+ * A sweep is sweep_size proposals (0 => N); after n_burnin sweeps one sample
+ * per chain per sweep is written.  `step` runs from step_offset, so a run can
+ * be resumed bit-exactly by passing the previous chain_state with
+ * init_chains = 0 and step_offset advanced by the proposals already made.
+ * init_chains = 1 draws the start states from the init stream (counter tag 1):
+ * flip moves take spin i from bit i%32 of word i/32; exchange moves shuffle
+ * N/2 up and N/2 down spins by Fisher-Yates. */
+typedef struct {
+    int64_t n_chains;
+    int32_t n_sweeps, n_burnin, sweep_size;
+    int32_t move;                     /* nqs_move */
+    int32_t dtype;                    /* sampling copy: NQS_F32 / NQS_F16 / NQS_BF16 (FFNN also FP8) */
+    int32_t init_chains;
+    uint64_t seed, step_offset;
+    uint32_t instance_id;
+    int64_t chain_id_offset;          /* global id of chain 0 (for splitting chains across devices) */
+    int32_t lanes_per_chain;          /* 0 = autotune; else 16, 32 or 64 */
+    int32_t refresh_sweeps;           /* recompute the incremental state every k sweeps (0 => 1) */
+} nqs_sample_cfg;
+
+/* Optional per-proposal decision trace of the first n_chains_traced chains
+ * (device buffers of n_chains_traced x total-proposals entries, row-major),
+ * used to replay every decision against the CPU reference. */
+typedef struct {
+    int32_t n_chains_traced;
+    int32_t *site;                    /* i | (j << 16); j = 0xFFFF for single flips */
+    uint32_t *ubits;                  /* r2 >> 8 */
+    float *delta;                     /* Delta in FP32 as computed by the kernel */
+    uint8_t *accepted;                /* 1 = accepted */
+} nqs_trace;
+
+typedef struct nqs_model nqs_model;   /* opaque, library-owned */
+
+/* Create a model from a HOST FP64 parameter vector (copied to the device as
+ * the FP64 master).  Returns NQS_ENUMERIC for non-finite parameters. */
+nqs_status nqs_model_create(const nqs_model_desc *desc, const double *host_params, int64_t n_params,
+                            nqs_model **out);
+/* Replace the FP64 master from a HOST vector; reduced-precision copies are rebuilt on next use. */
+nqs_status nqs_model_set_params(nqs_model *m, const double *host_params, int64_t n_params);
+/* Replace the FP64 master from a DEVICE vector (stream ordered); copies are rebuilt on `stream`. */
+nqs_status nqs_model_set_params_device(nqs_model *m, const double *dev_params, int64_t n_params, void *stream);
+nqs_status nqs_model_destroy(nqs_model *m);
+int64_t nqs_model_num_params(const nqs_model *m);
+
+/* Downcast (Sec. IV.B two-copy scheme, App. A): round every FP64 value of
+ * `src` to `dtype` with round-to-nearest-even in ONE rounding, and write the
+ * rounded values, widened back to FP32 (exact), to dst[n].  For
+ * NQS_FP8_E4M3 a per-tensor scale = amax/448 (FP32) is applied first
+ * (value = q * scale, q an OCP E4M3 code) and written to scale_out[0]
+ * (device, may be NULL otherwise). */
+nqs_status nqs_downcast(const double *src, int64_t n, int32_t dtype, float *dst, float *scale_out, void *stream);
+
+/* Metropolis-Hastings sampling (see nqs_sample_cfg).
+ *   chain_state [n_chains][N]   in/out (ignored on input when init_chains = 1)
+ *   samples     [n_sweeps][n_chains][N] out (may be NULL)
+ *   logpsi      [n_sweeps][n_chains]   out, log|psi| of each sample in the sampling precision (may be NULL)
+ *   n_accepted  [n_chains] out, accepted proposals over all sweeps incl. burn-in (may be NULL)
+ *   trace       host struct with device buffers, or NULL */
+nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_state, int8_t *samples,
+                      float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, void *stream);
+
+/* Local energies eps[n_samples] (FP64 sums of FP32 amplitude ratios computed
+ * from the `eval_dtype` copy of the parameters: NQS_F32 by default). */
+nqs_status nqs_local_energy(nqs_model *m, const nqs_ham_desc *ham, const int8_t *samples, int64_t n_samples,
+                            int32_t eval_dtype, double *eloc, void *stream);
+
+/* stats[4] (device, FP64): mean, unbiased variance, standard error of the
+ * per-chain means, n.  eloc is laid out [sweep][chain] with n_chains chains;
+ * the error bar needs n % n_chains == 0 and n_chains >= 2 (else NaN). */
+nqs_status nqs_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, void *stream);
+
+/* Log-amplitudes and log-derivatives from the FP32 copy.
+ *   logpsi  [n] out (may be NULL)
+ *   O       [n][P] out, row-major (may be NULL)
+ *   vjp_in  [n] with vjp_out [P]: vjp_out = sum_k vjp_in[k] O[k][:] (both NULL to skip) */
+nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
+                           const float *vjp_in, float *vjp_out, void *stream);
+
+/* F[P] = mean_k O[k] eps[k] - mean_k O[k] * mean_k eps[k] and Omean[P]
+ * (both FP64; Omean may be NULL). */
+nqs_status nqs_forces(const float *O, const double *eloc, int64_t n, int64_t P, double *F, double *Omean,
+                      void *stream);
+
+/* Centred Gram matrix on FP32 matrix cores, Obar = O - mean over samples:
+ *   mode 0: S[P][P] = Obar^T Obar / n      (Eq. eq:smat)
+ *   mode 1: T[n][n] = Obar Obar^T / n      (same non-zero spectrum)
+ * `out` is FP32, row-major. */
+nqs_status nqs_gram(const float *O, int64_t n, int64_t P, int32_t mode, float *out, void *stream);
+
+const char *nqs_last_error(void);
+const char *nqs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NQS_H */

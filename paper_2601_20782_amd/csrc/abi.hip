@@ -1,0 +1,299 @@
+// C entry points of libnqs: argument validation, model handles, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "nqs.h"
+
+namespace nqs {
+
+static thread_local std::string g_last_error;
+
+nqs_status set_error(nqs_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+nqs_status hip_error(hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return set_error(e == hipErrorOutOfMemory ? NQS_ENOMEM : NQS_EDEVICE, m);
+}
+
+// ---------------------------------------------------------------------------
+// Per-device workspace
+// ---------------------------------------------------------------------------
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_ws_mutex;
+static std::vector<Workspace> g_ws;
+
+void *workspace(size_t bytes, hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+    Workspace &w = g_ws[dev];
+    if (w.bytes < bytes) {
+        if (w.ptr) {
+            // the old buffer may still be in use by earlier work on `stream`
+            if (hipStreamSynchronize(stream) != hipSuccess) return nullptr;
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+        if (hipMalloc(&w.ptr, want) != hipSuccess) return nullptr;
+        w.bytes = want;
+    }
+    return w.ptr;
+}
+
+int64_t model_num_params(const nqs_model_desc &d)
+{
+    const int64_t N = d.n_visible;
+    if (d.arch == NQS_RBM) return N + d.widths[0] + (int64_t)d.widths[0] * N;
+    int64_t p = 0, prev = N;
+    for (int l = 0; l < d.n_layers; ++l) {
+        p += (int64_t)d.widths[l] * (prev + 1);
+        prev = d.widths[l];
+    }
+    return p;
+}
+
+nqs_status ensure_copy(nqs_model *m, int dtype, hipStream_t stream)
+{
+    if (m->copies[dtype].valid) return NQS_OK;
+    if (m->desc.arch == NQS_RBM) return rbm_build_copy(m, dtype, stream);
+    return ffnn_build_copy(m, dtype, stream);
+}
+
+static void invalidate(nqs_model *m)
+{
+    for (auto &c : m->copies) c.valid = false;
+}
+
+static nqs_status validate_desc(const nqs_model_desc *d)
+{
+    if (!d) return set_error(NQS_EINVAL, "desc is NULL");
+    if (d->n_visible < 2 || d->n_visible > 4096) return set_error(NQS_EINVAL, "n_visible must be in [2, 4096]");
+    if (d->arch == NQS_RBM) {
+        if (d->n_layers != 1) return set_error(NQS_EINVAL, "RBM needs n_layers = 1");
+        if (d->widths[0] < 1 || d->widths[0] > 8192) return set_error(NQS_EINVAL, "RBM hidden width must be in [1, 8192]");
+    } else if (d->arch == NQS_FFNN) {
+        if (d->n_layers < 1 || d->n_layers > NQS_MAX_LAYERS) return set_error(NQS_EINVAL, "FFNN needs 1..8 layers");
+        for (int l = 0; l < d->n_layers; ++l)
+            if (d->widths[l] < 1 || d->widths[l] > 8192) return set_error(NQS_EINVAL, "FFNN widths must be in [1, 8192]");
+    } else {
+        return set_error(NQS_EINVAL, "unknown arch");
+    }
+    if (d->marshall) {
+        if (d->lat_dim != 1 && d->lat_dim != 2) return set_error(NQS_EINVAL, "Marshall sign needs lat_dim 1 or 2");
+        const int64_t n = d->lat_dim == 1 ? d->lat_L : (int64_t)d->lat_L * d->lat_L;
+        if (n != d->n_visible) return set_error(NQS_EINVAL, "Marshall lattice size does not match n_visible");
+    }
+    return NQS_OK;
+}
+
+static bool all_finite(const double *p, int64_t n)
+{
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(p[k])) return false;
+    return true;
+}
+
+static int ham_sites(const nqs_ham_desc &h)
+{
+    return h.dim == 1 ? h.L : h.L * h.L;
+}
+
+}  // namespace nqs
+
+using namespace nqs;
+
+extern "C" {
+
+const char *nqs_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+const char *nqs_version(void)
+{
+    return "libnqs 0.1 (gfx950)";
+}
+
+int64_t nqs_model_num_params(const nqs_model *m)
+{
+    return m ? m->P : -1;
+}
+
+nqs_status nqs_model_create(const nqs_model_desc *desc, const double *host_params, int64_t n_params, nqs_model **out)
+{
+    if (!out) return set_error(NQS_EINVAL, "out is NULL");
+    *out = nullptr;
+    nqs_status st = validate_desc(desc);
+    if (st != NQS_OK) return st;
+    const int64_t P = model_num_params(*desc);
+    if (n_params != P) return set_error(NQS_EINVAL, "n_params does not match the architecture (expected " + std::to_string(P) + ")");
+    if (!host_params) return set_error(NQS_EINVAL, "host_params is NULL");
+    if (!all_finite(host_params, P)) return set_error(NQS_ENUMERIC, "parameters contain NaN or Inf");
+    nqs_model *m = new nqs_model();
+    m->desc = *desc;
+    m->P = P;
+    if (hipGetDevice(&m->device) != hipSuccess) { delete m; return set_error(NQS_EDEVICE, "no HIP device"); }
+    hipError_t e = hipMalloc(&m->master, sizeof(double) * P);
+    if (e != hipSuccess) { delete m; return hip_error(e, "hipMalloc(master)"); }
+    e = hipMalloc(&m->wb_f32, sizeof(float) * P);
+    if (e != hipSuccess) { (void)hipFree(m->master); delete m; return hip_error(e, "hipMalloc(scratch)"); }
+    e = hipMemcpy(m->master, host_params, sizeof(double) * P, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(m->master); (void)hipFree(m->wb_f32); delete m; return hip_error(e, "hipMemcpy(master)"); }
+    *out = m;
+    return NQS_OK;
+}
+
+nqs_status nqs_model_set_params(nqs_model *m, const double *host_params, int64_t n_params)
+{
+    if (!m || !host_params) return set_error(NQS_EINVAL, "NULL argument");
+    if (n_params != m->P) return set_error(NQS_EINVAL, "n_params does not match the model");
+    if (!all_finite(host_params, n_params)) return set_error(NQS_ENUMERIC, "parameters contain NaN or Inf");
+    NQS_HIP_TRY(hipDeviceSynchronize());
+    NQS_HIP_TRY(hipMemcpy(m->master, host_params, sizeof(double) * n_params, hipMemcpyHostToDevice));
+    invalidate(m);
+    return NQS_OK;
+}
+
+nqs_status nqs_model_set_params_device(nqs_model *m, const double *dev_params, int64_t n_params, void *stream)
+{
+    if (!m || !dev_params) return set_error(NQS_EINVAL, "NULL argument");
+    if (n_params != m->P) return set_error(NQS_EINVAL, "n_params does not match the model");
+    hipStream_t s = (hipStream_t)stream;
+    NQS_HIP_TRY(hipMemcpyAsync(m->master, dev_params, sizeof(double) * n_params, hipMemcpyDeviceToDevice, s));
+    invalidate(m);
+    return NQS_OK;
+}
+
+nqs_status nqs_model_destroy(nqs_model *m)
+{
+    if (!m) return NQS_OK;
+    (void)hipDeviceSynchronize();
+    for (auto &c : m->copies)
+        if (c.block) (void)hipFree(c.block);
+    (void)hipFree(m->master);
+    (void)hipFree(m->wb_f32);
+    delete m;
+    return NQS_OK;
+}
+
+nqs_status nqs_downcast(const double *src, int64_t n, int32_t dtype, float *dst, float *scale_out, void *stream)
+{
+    if (n < 0) return set_error(NQS_EINVAL, "n < 0");
+    if (n == 0) return NQS_OK;
+    if (!src || !dst) return set_error(NQS_EINVAL, "NULL src/dst");
+    if (dtype < NQS_F64 || dtype > NQS_FP8_E4M3) return set_error(NQS_EINVAL, "unknown dtype");
+    return launch_downcast(src, n, dtype, dst, scale_out, (hipStream_t)stream);
+}
+
+nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
+                      uint64_t *n_accepted, const nqs_trace *trace, void *stream)
+{
+    if (!m || !cfg) return set_error(NQS_EINVAL, "NULL model or cfg");
+    const nqs_sample_cfg &c = *cfg;
+    const int N = m->desc.n_visible;
+    if (c.n_chains < 0 || c.n_sweeps < 0 || c.n_burnin < 0) return set_error(NQS_EINVAL, "negative sizes");
+    if (c.n_chains == 0) return NQS_OK;
+    if (!chain_state) return set_error(NQS_EINVAL, "chain_state is NULL");
+    if (c.n_chains > (int64_t)1 << 31) return set_error(NQS_EINVAL, "n_chains too large");
+    if (c.move != NQS_MOVE_FLIP && c.move != NQS_MOVE_EXCHANGE) return set_error(NQS_EINVAL, "unknown move");
+    if (c.move == NQS_MOVE_EXCHANGE && (N % 2 != 0)) return set_error(NQS_EINVAL, "exchange moves need an even number of sites");
+    if (c.sweep_size < 0) return set_error(NQS_EINVAL, "sweep_size < 0");
+    if (c.instance_id >= (1u << 24)) return set_error(NQS_EINVAL, "instance_id must fit in 24 bits");
+    if (c.lanes_per_chain != 0 && c.lanes_per_chain != 16 && c.lanes_per_chain != 32 && c.lanes_per_chain != 64)
+        return set_error(NQS_EINVAL, "lanes_per_chain must be 0, 16, 32 or 64");
+    if (c.dtype != NQS_F32 && c.dtype != NQS_F16 && c.dtype != NQS_BF16 && c.dtype != NQS_FP8_E4M3)
+        return set_error(NQS_EINVAL, "sampling dtype must be F32, F16, BF16 or FP8_E4M3");
+    if (c.chain_id_offset < 0 || c.chain_id_offset + c.n_chains > ((int64_t)1 << 32))
+        return set_error(NQS_EINVAL, "global chain ids must fit in 32 bits");
+    if (trace && trace->n_chains_traced > 0) {
+        if (!trace->site || !trace->ubits || !trace->delta || !trace->accepted)
+            return set_error(NQS_EINVAL, "trace buffers are NULL");
+        if (trace->n_chains_traced > c.n_chains) return set_error(NQS_EINVAL, "n_chains_traced > n_chains");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (m->desc.arch == NQS_RBM) {
+        if (c.move != NQS_MOVE_FLIP) return set_error(NQS_EUNSUPPORTED, "the RBM sampler implements single-flip moves");
+        if (c.dtype == NQS_FP8_E4M3) return set_error(NQS_EUNSUPPORTED, "FP8 sampling is implemented for dense networks");
+        return rbm_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
+    }
+    return ffnn_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
+}
+
+nqs_status nqs_local_energy(nqs_model *m, const nqs_ham_desc *ham, const int8_t *samples, int64_t n_samples,
+                            int32_t eval_dtype, double *eloc, void *stream)
+{
+    if (!m || !ham) return set_error(NQS_EINVAL, "NULL model or hamiltonian");
+    if (n_samples < 0) return set_error(NQS_EINVAL, "n_samples < 0");
+    if (n_samples == 0) return NQS_OK;
+    if (!samples || !eloc) return set_error(NQS_EINVAL, "NULL samples/eloc");
+    const nqs_ham_desc &h = *ham;
+    if (h.kind != NQS_TFIM && h.kind != NQS_HEISENBERG) return set_error(NQS_EINVAL, "unknown hamiltonian");
+    if (h.dim != 1 && h.dim != 2) return set_error(NQS_EINVAL, "dim must be 1 or 2");
+    if (h.pbc && h.L < 3) return set_error(NQS_EINVAL, "periodic lattices need L >= 3");
+    if (!h.pbc && h.L < 2) return set_error(NQS_EINVAL, "L >= 2 required");
+    if (ham_sites(h) != m->desc.n_visible) return set_error(NQS_EINVAL, "lattice size does not match n_visible");
+    if (eval_dtype != NQS_F32 && eval_dtype != NQS_F16 && eval_dtype != NQS_BF16 && eval_dtype != NQS_FP8_E4M3)
+        return set_error(NQS_EINVAL, "eval dtype must be F32, F16, BF16 or FP8_E4M3");
+    hipStream_t s = (hipStream_t)stream;
+    if (m->desc.arch == NQS_RBM) {
+        if (eval_dtype == NQS_FP8_E4M3) return set_error(NQS_EUNSUPPORTED, "FP8 is implemented for dense networks");
+        return rbm_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);
+    }
+    return ffnn_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);
+}
+
+nqs_status nqs_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, void *stream)
+{
+    if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
+    if (!eloc || !stats) return set_error(NQS_EINVAL, "NULL eloc/stats");
+    if (n_chains < 0) return set_error(NQS_EINVAL, "n_chains < 0");
+    return launch_energy_stats(eloc, n, n_chains, stats, (hipStream_t)stream);
+}
+
+nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
+                           const float *vjp_in, float *vjp_out, void *stream)
+{
+    if (!m) return set_error(NQS_EINVAL, "NULL model");
+    if (n < 0) return set_error(NQS_EINVAL, "n < 0");
+    if (n == 0) return NQS_OK;
+    if (!samples) return set_error(NQS_EINVAL, "NULL samples");
+    if ((vjp_in == nullptr) != (vjp_out == nullptr)) return set_error(NQS_EINVAL, "vjp_in and vjp_out go together");
+    hipStream_t s = (hipStream_t)stream;
+    if (m->desc.arch == NQS_RBM) return rbm_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s);
+    return ffnn_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s);
+}
+
+nqs_status nqs_forces(const float *O, const double *eloc, int64_t n, int64_t P, double *F, double *Omean, void *stream)
+{
+    if (n <= 0 || P <= 0) return set_error(NQS_EINVAL, "n and P must be positive");
+    if (!O || !eloc || !F) return set_error(NQS_EINVAL, "NULL O/eloc/F");
+    return launch_forces(O, eloc, n, P, F, Omean, (hipStream_t)stream);
+}
+
+nqs_status nqs_gram(const float *O, int64_t n, int64_t P, int32_t mode, float *out, void *stream)
+{
+    if (n <= 0 || P <= 0) return set_error(NQS_EINVAL, "n and P must be positive");
+    if (!O || !out) return set_error(NQS_EINVAL, "NULL O/out");
+    if (mode != 0 && mode != 1) return set_error(NQS_EINVAL, "mode must be 0 (S) or 1 (T)");
+    return launch_gram(O, n, P, mode, out, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Host-side internals of libnqs: the model handle, error reporting, workspace,
+// and the launch entry points each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "nqs.h"
+
+namespace nqs {
+
+// Thread-local message of the last failing call.
+nqs_status set_error(nqs_status st, const std::string &msg);
+nqs_status hip_error(hipError_t e, const char *what);
+
+#define NQS_HIP_TRY(expr)                                   \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return ::nqs::hip_error(_e, #expr); \
+    } while (0)
+
+// Device copy of an RBM in one sampling format.  All arrays hold FP32 numbers
+// that are exactly the values of the format-rounded parameters.
+struct RbmDev {
+    int N = 0, M = 0;
+    float *a = nullptr;       // [N]
+    float *b = nullptr;       // [M]
+    float *Wt = nullptr;      // [N][M]   Wt[i][j] = W[j][i]
+    float2 *CS = nullptr;     // [N][M]   (cosh 2W[j][i], sinh 2W[j][i]) at [i][j]
+    float2 *CSt = nullptr;    // [M][N]   the same pairs at [j][i]
+    float max_abs_w = 0.0f;
+};
+
+// Dense-network copy in one sampling format.
+struct FfnnDev {
+    int n_layers = 0;
+    int widths[NQS_MAX_LAYERS + 1] = {0};  // widths[0] = N
+    float *W[NQS_MAX_LAYERS] = {nullptr};  // [w_l][w_{l-1}] FP32 values of the rounded weights
+    float *Wt[NQS_MAX_LAYERS] = {nullptr}; // [w_{l-1}][w_l]
+    float *b[NQS_MAX_LAYERS] = {nullptr};
+    void *Wlp[NQS_MAX_LAYERS] = {nullptr}; // raw 16-bit / 8-bit codes for the matrix cores, [w_l][w_{l-1}]
+    float wscale[NQS_MAX_LAYERS] = {0};    // FP8 per-layer weight scales (value = code * scale)
+    float ascale[NQS_MAX_LAYERS] = {0};    // FP8 per-layer activation scales
+};
+
+struct Copy {
+    bool valid = false;
+    RbmDev rbm;
+    FfnnDev ffnn;
+    void *block = nullptr;   // single allocation backing the arrays above
+};
+
+}  // namespace nqs
+
+struct nqs_model {
+    nqs_model_desc desc{};
+    int64_t P = 0;
+    int device = 0;
+    double *master = nullptr;           // FP64 master parameters on the device
+    nqs::Copy copies[5];                // indexed by nqs_dtype
+    float *wb_f32 = nullptr;            // scratch FP32 rounded parameter vector [P]
+};
+
+namespace nqs {
+
+// Per-device growable scratch (never shrinks; freed at process exit).
+void *workspace(size_t bytes, hipStream_t stream);
+
+int64_t model_num_params(const nqs_model_desc &d);
+
+// Build (or rebuild) the `dtype` copy of the model on `stream`.
+nqs_status ensure_copy(nqs_model *m, int dtype, hipStream_t stream);
+
+// kernels -------------------------------------------------------------------
+nqs_status launch_downcast(const double *src, int64_t n, int dtype, float *dst, float *scale_out,
+                           hipStream_t stream);
+nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream);
+nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
+                      float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
+nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
+                            double *eloc, hipStream_t stream);
+nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
+                           const float *vjp_in, float *vjp_out, hipStream_t stream);
+nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream);
+nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
+                       float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
+nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
+                             double *eloc, hipStream_t stream);
+nqs_status ffnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
+                            const float *vjp_in, float *vjp_out, hipStream_t stream);
+nqs_status launch_init_chains(int8_t *chain_state, int64_t n_chains, int N, int move, uint64_t seed,
+                              uint32_t inst, int64_t chain_id_offset, hipStream_t stream);
+nqs_status launch_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, hipStream_t stream);
+nqs_status launch_forces(const float *O, const double *eloc, int64_t n, int64_t P, double *F, double *Omean,
+                         hipStream_t stream);
+nqs_status launch_gram(const float *O, int64_t n, int64_t P, int mode, float *out, hipStream_t stream);
+
+}  // namespace nqs

@@ -1,0 +1,685 @@
+// RBM kernels (App. G, real parameters):  log psi(s) = a.s + sum_j log cosh(theta_j),
+// theta = W s + b.
+//
+// The single-flip ratio uses the cosh addition formula: flipping site i moves
+// theta_j to theta_j - 2 s_i W_ji, and
+//     cosh(theta - d) / cosh(theta) = cosh d - tanh(theta) sinh d,
+// so with per-(i,j) tables C = cosh 2W_ji, S = sinh 2W_ji (built once per
+// parameter update from the format-rounded weights) a proposal costs one FMA
+// and one multiply per hidden unit:
+//     log psi(s') - log psi(s) = -2 a_i s_i + log prod_j (C_ij - s_i t_j S_ij),  t = tanh theta.
+// After an accepted flip t_j is advanced with the tanh addition formula,
+//     t_j' = (t_j C_ij - s_i S_ij) / r_ij,
+// and t is recomputed from theta = W s + b at sweep ends.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "internal.h"
+
+namespace nqs {
+
+// ---------------------------------------------------------------------------
+// Copy builder: round the FP64 master to `dtype` and derive the tables.
+// ---------------------------------------------------------------------------
+__global__ void rbm_build_kernel(const double *__restrict__ master, int N, int M, int dtype, float *a, float *b,
+                                 float *Wt, float2 *CS, float2 *CSt, unsigned int *max_abs_bits)
+{
+    const int64_t P = (int64_t)N + M + (int64_t)M * N;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const double v = round_to_dtype(master[p], dtype);
+        if (p < N) {
+            a[p] = (float)v;
+        } else if (p < N + M) {
+            b[p - N] = (float)v;
+        } else {
+            const int64_t q = p - N - M;
+            const int j = (int)(q / N), i = (int)(q % N);
+            Wt[(int64_t)i * M + j] = (float)v;
+            // tables in FP64, rounded once to FP32
+            const float2 cs = make_float2((float)cosh(2.0 * v), (float)sinh(2.0 * v));
+            CS[(int64_t)i * M + j] = cs;
+            CSt[(int64_t)j * N + i] = cs;
+            atomicMax(max_abs_bits, __float_as_uint(fabsf((float)v)));
+        }
+    }
+}
+
+nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream)
+{
+    Copy &c = m->copies[dtype];
+    const int N = m->desc.n_visible, M = m->desc.widths[0];
+    const size_t nW = (size_t)N * M;
+    const size_t bytes = sizeof(float) * (N + M + nW) + sizeof(float2) * 2 * nW + 256 * 4;
+    if (!c.block) {
+        NQS_HIP_TRY(hipMalloc(&c.block, bytes));
+    }
+    char *base = (char *)c.block;
+    auto carve = [&](size_t sz) {
+        char *p = base;
+        base += (sz + 255) & ~(size_t)255;
+        return p;
+    };
+    RbmDev &r = c.rbm;
+    r.N = N;
+    r.M = M;
+    r.CS = (float2 *)carve(sizeof(float2) * nW);
+    r.CSt = (float2 *)carve(sizeof(float2) * nW);
+    r.Wt = (float *)carve(sizeof(float) * nW);
+    r.a = (float *)carve(sizeof(float) * N);
+    r.b = (float *)carve(sizeof(float) * M);
+    unsigned int *mx = (unsigned int *)carve(sizeof(unsigned int));
+    if ((size_t)(base - (char *)c.block) > bytes + 6 * 256) return set_error(NQS_EDEVICE, "internal layout overflow");
+    NQS_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(unsigned int), stream));
+    const int64_t P = (int64_t)N + M + (int64_t)nW;
+    const int blocks = (int)std::min<int64_t>((P + 255) / 256, 4096);
+    hipLaunchKernelGGL(rbm_build_kernel, dim3(blocks), dim3(256), 0, stream, m->master, N, M, dtype, r.a, r.b, r.Wt,
+                       r.CS, r.CSt, mx);
+    NQS_HIP_TRY(hipGetLastError());
+    unsigned int mbits = 0;
+    NQS_HIP_TRY(hipMemcpyAsync(&mbits, mx, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
+    NQS_HIP_TRY(hipStreamSynchronize(stream));
+    float mabs;
+    std::memcpy(&mabs, &mbits, sizeof(float));
+    r.max_abs_w = mabs;
+    c.valid = true;
+    return NQS_OK;
+}
+
+// Largest |W| for which every partial product of 8 ratio factors (each within
+// [e^{-2|W|}, e^{2|W|}]) stays inside the FP32 range.
+constexpr float kMaxAbsW = 5.0f;
+
+// ---------------------------------------------------------------------------
+// Sampler: one chain per group of G lanes; lane g of the group owns hidden
+// units j = g, g+G, ..., (K per lane) and spin word g (32 spins per word).
+// The (C,S) table lives in LDS when it fits, else it is read through L2.
+// ---------------------------------------------------------------------------
+struct RbmSampleArgs {
+    RbmDev net;
+    int8_t *chain_state;
+    int8_t *samples;
+    float *logpsi;
+    unsigned long long *n_acc;
+    int64_t n_chains;
+    int n_sweeps, n_burnin, sweep_size, refresh_sweeps;
+    uint64_t seed, step_offset;
+    uint32_t inst, chain_id_offset;
+    int n_traced;
+    int32_t *tr_site;
+    uint32_t *tr_ubits;
+    float *tr_delta;
+    uint8_t *tr_acc;
+};
+
+// theta = W s + b from scratch; sets t = tanh theta, returns log psi (FP32).
+template <int G, int K>
+__device__ __forceinline__ float rbm_refresh(const RbmDev &net, uint32_t word, int gl, float (&t)[K])
+{
+    const int N = net.N, M = net.M;
+    float th[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int j = gl + k * G;
+        th[k] = j < M ? net.b[j] : 0.0f;
+    }
+    float as = 0.0f;
+    const int NW = (N + 31) >> 5;
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t bits = group_bcast<G>(word, w);
+        const int i0 = w << 5;
+        const int nb = min(32, N - i0);
+        for (int bb = 0; bb < nb; ++bb) {
+            const int i = i0 + bb;
+            const float s = ((bits >> bb) & 1u) ? 1.0f : -1.0f;
+            as = fmaf(net.a[i], s, as);
+            const float *wrow = net.Wt + (size_t)i * M;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int j = gl + k * G;
+                if (j < M) th[k] = fmaf(wrow[j], s, th[k]);
+            }
+        }
+    }
+    float lc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int j = gl + k * G;
+        if (j < M) {
+            t[k] = tanhf(th[k]);
+            lc += logcosh_f32(th[k]);
+        } else {
+            t[k] = 0.0f;
+        }
+    }
+    return as + group_sum<G>(lc);
+}
+
+template <int G, int K, bool LDS_TAB, bool TRACE>
+__global__ void __launch_bounds__(1024) rbm_sample_kernel(RbmSampleArgs A)
+{
+    extern __shared__ float2 s_tab[];
+    const int N = A.net.N, M = A.net.M;
+    if constexpr (LDS_TAB) {
+        const int total = N * M;
+        const float4 *src = reinterpret_cast<const float4 *>(A.net.CS);
+        float4 *dst = reinterpret_cast<float4 *>(s_tab);
+        for (int k = threadIdx.x; k < total / 2; k += blockDim.x) dst[k] = src[k];
+        if ((total & 1) && threadIdx.x == 0) s_tab[total - 1] = A.net.CS[total - 1];
+        __syncthreads();
+    }
+    const int cpb = blockDim.x / G;
+    const int gl = threadIdx.x % G;
+    const int64_t c = (int64_t)blockIdx.x * cpb + threadIdx.x / G;
+    if (c >= A.n_chains) return;   // whole groups leave together; no barrier follows
+
+    const uint32_t gid = A.chain_id_offset + (uint32_t)c;
+    const uint32_t key0 = (uint32_t)A.seed, key1 = (uint32_t)(A.seed >> 32);
+    const int NW = (N + 31) >> 5;
+
+    // spins of this chain: lane g holds bits of sites 32g .. 32g+31
+    uint32_t word = 0;
+    if (gl < NW) {
+        const int8_t *src = A.chain_state + (size_t)c * N + gl * 32;
+        const int nb = min(32, N - gl * 32);
+        for (int bb = 0; bb < nb; ++bb) word |= (src[bb] > 0 ? 1u : 0u) << bb;
+    }
+
+    float t[K];
+    float f = rbm_refresh<G, K>(A.net, word, gl, t);
+
+    const int sw = A.sweep_size;
+    const int64_t total = (int64_t)(A.n_burnin + A.n_sweeps) * sw;
+    unsigned long long acc = 0;
+    int in_sweep = 0;
+    int64_t sweep = 0;
+    const bool want_out = (A.samples != nullptr) || (A.logpsi != nullptr);
+
+    for (int64_t step0 = 0; step0 < total; step0 += G) {
+        // one Philox block per proposal: lane g draws proposal step0 + g of this batch
+        const uint64_t gstep = A.step_offset + (uint64_t)step0 + (uint64_t)gl;
+        const Block4 rb = philox4x32_10((uint32_t)gstep, (uint32_t)(gstep >> 32), gid, A.inst << 8, key0, key1);
+        const uint32_t my_i = (uint32_t)index_from_word(rb.r0, N);
+        const uint32_t my_u = rb.r2 >> 8;
+        const int nprop = (int)min<int64_t>(G, total - step0);
+        for (int p = 0; p < nprop; ++p) {
+            const int i = (int)group_bcast<G>(my_i, p);
+            const uint32_t ub = group_bcast<G>(my_u, p);
+            const uint32_t wbits = group_bcast<G>(word, i >> 5);
+            const float si = ((wbits >> (i & 31)) & 1u) ? 1.0f : -1.0f;
+
+            float cx[K], ss[K], rr[K];
+            float prod = 1.0f;
+            int e2 = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int j = gl + k * G;
+                if (j < M) {
+                    float2 cs;
+                    if constexpr (LDS_TAB) cs = s_tab[i * M + j];
+                    else cs = A.net.CS[(size_t)i * M + j];
+                    cx[k] = cs.x;
+                    ss[k] = si * cs.y;
+                    rr[k] = fmaf(-t[k], ss[k], cs.x);
+                    prod *= rr[k];
+                } else {
+                    cx[k] = 1.0f;
+                    ss[k] = 0.0f;
+                    rr[k] = 1.0f;
+                }
+                if ((k & 7) == 7 && k + 1 < K) {
+                    int e;
+                    prod = frexpf(prod, &e);
+                    e2 += e;
+                }
+            }
+            const float lpart = __logf(prod) + (float)e2 * 0.69314718055994531f;
+            const float lsum = group_sum<G>(lpart);
+            const float delta = 2.0f * fmaf(-2.0f * si, A.net.a[i], lsum);
+            const float u = (float)ub * 5.9604644775390625e-8f;   // 2^-24
+            const bool accept = (delta >= 0.0f) || (u < __expf(delta));
+            if (accept) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) t[k] = fmaf(t[k], cx[k], -ss[k]) * __builtin_amdgcn_rcpf(rr[k]);
+                if (gl == (i >> 5)) word ^= 1u << (i & 31);
+                ++acc;
+            }
+            if constexpr (TRACE) {
+                if (c < A.n_traced && gl == 0) {
+                    const size_t idx = (size_t)c * (size_t)total + (size_t)(step0 + p);
+                    A.tr_site[idx] = i | (0xFFFF << 16);
+                    A.tr_ubits[idx] = ub;
+                    A.tr_delta[idx] = delta;
+                    A.tr_acc[idx] = accept ? 1 : 0;
+                }
+            }
+            if (++in_sweep == sw) {
+                in_sweep = 0;
+                const int64_t out = sweep - A.n_burnin;
+                const bool emit = want_out && out >= 0;
+                if (emit || ((sweep + 1) % A.refresh_sweeps) == 0) {
+                    f = rbm_refresh<G, K>(A.net, word, gl, t);
+                    if (emit) {
+                        if (A.samples && gl < NW) {
+                            int8_t *dst = A.samples + ((size_t)out * A.n_chains + c) * N + gl * 32;
+                            const int nb = min(32, N - gl * 32);
+                            for (int bb = 0; bb < nb; ++bb) dst[bb] = ((word >> bb) & 1u) ? 1 : -1;
+                        }
+                        if (A.logpsi && gl == 0) A.logpsi[(size_t)out * A.n_chains + c] = f;
+                    }
+                }
+                ++sweep;
+            }
+        }
+    }
+    if (gl < NW) {
+        int8_t *dst = A.chain_state + (size_t)c * N + gl * 32;
+        const int nb = min(32, N - gl * 32);
+        for (int bb = 0; bb < nb; ++bb) dst[bb] = ((word >> bb) & 1u) ? 1 : -1;
+    }
+    if (A.n_acc && gl == 0) A.n_acc[c] = acc;
+}
+
+template <typename Kern>
+static void allow_lds(Kern k, size_t bytes)
+{
+    if (bytes > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+
+template <int G, int K>
+static void launch_rbm_sample_gk(const RbmSampleArgs &A, bool lds, bool trace, int threads, size_t lds_bytes,
+                                 int blocks, hipStream_t s)
+{
+    if (lds) {
+        allow_lds(rbm_sample_kernel<G, K, true, true>, lds_bytes);
+        allow_lds(rbm_sample_kernel<G, K, true, false>, lds_bytes);
+        if (trace) hipLaunchKernelGGL((rbm_sample_kernel<G, K, true, true>), dim3(blocks), dim3(threads), lds_bytes, s, A);
+        else hipLaunchKernelGGL((rbm_sample_kernel<G, K, true, false>), dim3(blocks), dim3(threads), lds_bytes, s, A);
+    } else {
+        if (trace) hipLaunchKernelGGL((rbm_sample_kernel<G, K, false, true>), dim3(blocks), dim3(threads), 0, s, A);
+        else hipLaunchKernelGGL((rbm_sample_kernel<G, K, false, false>), dim3(blocks), dim3(threads), 0, s, A);
+    }
+}
+
+template <int G>
+static nqs_status launch_rbm_sample_g(const RbmSampleArgs &A, int K, bool lds, bool trace, int threads,
+                                      size_t lds_bytes, int blocks, hipStream_t s)
+{
+    switch (K) {
+    case 1: launch_rbm_sample_gk<G, 1>(A, lds, trace, threads, lds_bytes, blocks, s); break;
+    case 2: launch_rbm_sample_gk<G, 2>(A, lds, trace, threads, lds_bytes, blocks, s); break;
+    case 4: launch_rbm_sample_gk<G, 4>(A, lds, trace, threads, lds_bytes, blocks, s); break;
+    case 8: launch_rbm_sample_gk<G, 8>(A, lds, trace, threads, lds_bytes, blocks, s); break;
+    case 16: launch_rbm_sample_gk<G, 16>(A, lds, trace, threads, lds_bytes, blocks, s); break;
+    case 32: launch_rbm_sample_gk<G, 32>(A, lds, trace, threads, lds_bytes, blocks, s); break;
+    default: return set_error(NQS_EUNSUPPORTED, "hidden width too large for the sampler");
+    }
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
+static int round_up_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+constexpr size_t kLdsBytes = 160 * 1024;
+
+nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
+                      uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream)
+{
+    nqs_status st = ensure_copy(m, cfg.dtype, stream);
+    if (st != NQS_OK) return st;
+    const RbmDev &net = m->copies[cfg.dtype].rbm;
+    if (!(net.max_abs_w <= kMaxAbsW))
+        return set_error(NQS_EUNSUPPORTED, "the product-form RBM sampler needs |W| <= 5");
+    const int N = net.N, M = net.M;
+    if (cfg.init_chains) {
+        st = launch_init_chains(chain_state, cfg.n_chains, N, cfg.move, cfg.seed, cfg.instance_id,
+                                cfg.chain_id_offset, stream);
+        if (st != NQS_OK) return st;
+    }
+    RbmSampleArgs A;
+    A.net = net;
+    A.chain_state = chain_state;
+    A.samples = samples;
+    A.logpsi = logpsi;
+    A.n_acc = (unsigned long long *)n_accepted;
+    A.n_chains = cfg.n_chains;
+    A.n_sweeps = cfg.n_sweeps;
+    A.n_burnin = cfg.n_burnin;
+    A.sweep_size = cfg.sweep_size > 0 ? cfg.sweep_size : N;
+    A.refresh_sweeps = cfg.refresh_sweeps > 0 ? cfg.refresh_sweeps : 1;
+    A.seed = cfg.seed;
+    A.step_offset = cfg.step_offset;
+    A.inst = cfg.instance_id;
+    A.chain_id_offset = (uint32_t)cfg.chain_id_offset;
+    const bool tr = trace && trace->n_chains_traced > 0;
+    A.n_traced = tr ? trace->n_chains_traced : 0;
+    A.tr_site = tr ? trace->site : nullptr;
+    A.tr_ubits = tr ? trace->ubits : nullptr;
+    A.tr_delta = tr ? trace->delta : nullptr;
+    A.tr_acc = tr ? trace->accepted : nullptr;
+    if ((int64_t)(cfg.n_burnin + cfg.n_sweeps) * A.sweep_size == 0) {
+        // nothing to propose: only the initial states (and acceptance counts) are defined
+        if (n_accepted) NQS_HIP_TRY(hipMemsetAsync(n_accepted, 0, sizeof(uint64_t) * cfg.n_chains, stream));
+        return NQS_OK;
+    }
+
+    // launch shape: lanes per chain G, hidden units per lane K
+    int G = cfg.lanes_per_chain;
+    if (G == 0) G = M >= 128 ? 64 : (M >= 48 ? 32 : 16);
+    while ((N + 31) / 32 > G && G < 64) G *= 2;   // every spin word needs an owning lane
+    if ((N + 31) / 32 > G) return set_error(NQS_EUNSUPPORTED, "too many sites for the sampler");
+    const int K = round_up_pow2((M + G - 1) / G);
+    if (K > 32) return set_error(NQS_EUNSUPPORTED, "hidden width too large for this lanes_per_chain");
+    const size_t tab_bytes = sizeof(float2) * (size_t)N * M;
+    const bool lds = tab_bytes <= kLdsBytes;
+    int threads;
+    if (lds) {
+        // chains sharing one LDS copy: as many as one CU can hold without starving occupancy
+        const int blocks_per_cu = (int)std::max<size_t>(1, kLdsBytes / std::max<size_t>(tab_bytes, 1));
+        threads = blocks_per_cu >= 4 ? 256 : (blocks_per_cu >= 2 ? 512 : 1024);
+    } else {
+        threads = 256;
+    }
+    const int cpb = threads / G;
+    const int64_t blocks64 = (cfg.n_chains + cpb - 1) / cpb;
+    if (blocks64 > INT32_MAX) return set_error(NQS_EINVAL, "too many chains");
+    const int blocks = (int)blocks64;
+    const size_t lds_bytes = lds ? tab_bytes : 0;
+    switch (G) {
+    case 16: return launch_rbm_sample_g<16>(A, K, lds, tr, threads, lds_bytes, blocks, stream);
+    case 32: return launch_rbm_sample_g<32>(A, K, lds, tr, threads, lds_bytes, blocks, stream);
+    default: return launch_rbm_sample_g<64>(A, K, lds, tr, threads, lds_bytes, blocks, stream);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Local energies, TFIM:  eps(s) = J sum_<ij> s_i s_j + h sum_i psi(s^i)/psi(s),
+// psi(s^i)/psi(s) = exp(-2 a_i s_i) prod_j (C_ij - s_i t_j S_ij).
+// A block takes B samples; phase 1 computes t = tanh(W s + b) for the tile
+// (threads over hidden units), phase 2 gives each thread one site i and all
+// B samples (the (C,S) pair of (i,j) is loaded once and used B times).
+// Per-sample sums are FP64.
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ void __launch_bounds__(1024) rbm_eloc_tfim_kernel(RbmDev net, const int8_t *__restrict__ samples,
+                                                             int64_t n, int dim, int L, int pbc, double J, double h,
+                                                             double *__restrict__ eloc)
+{
+    extern __shared__ float smem[];
+    const int N = net.N, M = net.M;
+    float *spT = smem;                      // [N][B]  spins as +-1
+    float *tT = spT + (size_t)N * B;        // [M][B]  tanh theta
+    double *red = (double *)(tT + (size_t)M * B + ((N * B + M * B) & 1));   // [nwaves][B]
+    const int64_t base = (int64_t)blockIdx.x * B;
+    const int tid = threadIdx.x, nt = blockDim.x;
+
+    for (int k = tid; k < N * B; k += nt) {
+        const int b = k / N, i = k - b * N;
+        const int64_t row = base + b;
+        spT[i * B + b] = row < n ? (float)samples[row * N + i] : 1.0f;
+    }
+    __syncthreads();
+    for (int j = tid; j < M; j += nt) {
+        float th[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) th[b] = net.b[j];
+        for (int i = 0; i < N; ++i) {
+            const float w = net.Wt[(size_t)i * M + j];
+            const float4 *sp4 = reinterpret_cast<const float4 *>(spT + i * B);
+#pragma unroll
+            for (int q = 0; q < B / 4; ++q) {
+                const float4 v = sp4[q];
+                th[4 * q + 0] = fmaf(w, v.x, th[4 * q + 0]);
+                th[4 * q + 1] = fmaf(w, v.y, th[4 * q + 1]);
+                th[4 * q + 2] = fmaf(w, v.z, th[4 * q + 2]);
+                th[4 * q + 3] = fmaf(w, v.w, th[4 * q + 3]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) tT[j * B + b] = tanhf(th[b]);
+    }
+    __syncthreads();
+
+    double contrib[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) contrib[b] = 0.0;
+    if (tid < N) {
+        const int i = tid;
+        float si[B], prod[B];
+        int e2[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            si[b] = spT[i * B + b];
+            prod[b] = 1.0f;
+            e2[b] = 0;
+        }
+        for (int j = 0; j < M; ++j) {
+            const float2 cs = net.CSt[(size_t)j * N + i];
+            const float4 *t4 = reinterpret_cast<const float4 *>(tT + j * B);
+#pragma unroll
+            for (int q = 0; q < B / 4; ++q) {
+                const float4 tv = t4[q];
+                prod[4 * q + 0] *= fmaf(-tv.x * si[4 * q + 0], cs.y, cs.x);
+                prod[4 * q + 1] *= fmaf(-tv.y * si[4 * q + 1], cs.y, cs.x);
+                prod[4 * q + 2] *= fmaf(-tv.z * si[4 * q + 2], cs.y, cs.x);
+                prod[4 * q + 3] *= fmaf(-tv.w * si[4 * q + 3], cs.y, cs.x);
+            }
+            if ((j & 7) == 7) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    int e;
+                    prod[b] = frexpf(prod[b], &e);
+                    e2[b] += e;
+                }
+            }
+        }
+        // nearest neighbours of i along +x and +y (periodic or open)
+        int nb1 = -1, nb2 = -1;
+        if (dim == 1) {
+            if (i + 1 < L) nb1 = i + 1;
+            else if (pbc) nb1 = 0;
+        } else {
+            const int x = i / L, y = i - (i / L) * L;
+            if (x + 1 < L) nb1 = (x + 1) * L + y;
+            else if (pbc) nb1 = y;
+            if (y + 1 < L) nb2 = x * L + y + 1;
+            else if (pbc) nb2 = x * L;
+        }
+        const float ai = net.a[i];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const float ratio = ldexpf(__expf(-2.0f * ai * si[b]) * prod[b], e2[b]);
+            float zz = 0.0f;
+            if (nb1 >= 0) zz += spT[nb1 * B + b];
+            if (nb2 >= 0) zz += spT[nb2 * B + b];
+            contrib[b] = J * (double)(si[b] * zz) + h * (double)ratio;
+        }
+    }
+    // FP64 block reduction over sites
+    const int lane = tid & 63, wv = tid >> 6, nw = (nt + 63) >> 6;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const double v = group_sum<64>(contrib[b]);
+        if (lane == 0) red[wv * B + b] = v;
+    }
+    __syncthreads();
+    if (tid < B) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w * B + tid];
+        const int64_t row = base + tid;
+        if (row < n) eloc[row] = s;
+    }
+}
+
+nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
+                            double *eloc, hipStream_t stream)
+{
+    if (ham.kind != NQS_TFIM)
+        return set_error(NQS_EUNSUPPORTED, "RBM local energies are implemented for the TFIM");
+    nqs_status st = ensure_copy(m, dtype, stream);
+    if (st != NQS_OK) return st;
+    const RbmDev &net = m->copies[dtype].rbm;
+    if (!(net.max_abs_w <= kMaxAbsW)) return set_error(NQS_EUNSUPPORTED, "product-form ratios need |W| <= 5");
+    const int N = net.N, M = net.M;
+    if (N > 1024) return set_error(NQS_EUNSUPPORTED, "RBM local energies need N <= 1024");
+    constexpr int B = 16;
+    const int threads = std::max(64, ((N + 63) / 64) * 64);
+    const size_t lds = sizeof(float) * ((size_t)N * B + (size_t)M * B + 2) + sizeof(double) * (threads / 64) * B;
+    if (lds > kLdsBytes) return set_error(NQS_EUNSUPPORTED, "RBM too large for the local-energy kernel");
+    const int64_t blocks = (n + B - 1) / B;
+    if (blocks > INT32_MAX) return set_error(NQS_EINVAL, "too many samples");
+    allow_lds(rbm_eloc_tfim_kernel<B>, lds);
+    hipLaunchKernelGGL((rbm_eloc_tfim_kernel<B>), dim3((unsigned)blocks), dim3(threads), lds, stream, net, samples, n,
+                       ham.dim, ham.L, ham.pbc, ham.J, ham.h, eloc);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// log psi and O_k: O_a = s, O_b = tanh theta, O_W[j][i] = tanh(theta_j) s_i.
+// B samples per block; the O rows are written with consecutive threads on
+// consecutive parameters (HBM-write bound).
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ void __launch_bounds__(256) rbm_grad_kernel(RbmDev net, const int8_t *__restrict__ samples, int64_t n,
+                                                       float *__restrict__ logpsi, float *__restrict__ O,
+                                                       float *__restrict__ Tout)
+{
+    extern __shared__ float smem[];
+    const int N = net.N, M = net.M;
+    float *spT = smem;                   // [N][B]
+    float *tT = spT + (size_t)N * B;     // [M][B]
+    float *red = tT + (size_t)M * B;     // [nwaves][B]
+    const int64_t base = (int64_t)blockIdx.x * B;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+
+    for (int k = tid; k < N * B; k += nt) {
+        const int b = k / N, i = k - b * N;
+        const int64_t row = base + b;
+        spT[i * B + b] = row < n ? (float)samples[row * N + i] : 1.0f;
+    }
+    __syncthreads();
+    float part[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) part[b] = 0.0f;
+    for (int j = tid; j < M; j += nt) {
+        float th[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) th[b] = net.b[j];
+        for (int i = 0; i < N; ++i) {
+            const float w = net.Wt[(size_t)i * M + j];
+#pragma unroll
+            for (int b = 0; b < B; ++b) th[b] = fmaf(w, spT[i * B + b], th[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const float t = tanhf(th[b]);
+            tT[j * B + b] = t;
+            part[b] += logcosh_f32(th[b]);
+            if (Tout && base + b < n) Tout[(base + b) * M + j] = t;
+        }
+    }
+    for (int i = tid; i < N; i += nt) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) part[b] = fmaf(net.a[i], spT[i * B + b], part[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const float v = group_sum<64>(part[b]);
+        if (lane == 0) red[wv * B + b] = v;
+    }
+    __syncthreads();
+    if (logpsi && tid < B && base + tid < n) {
+        float s = 0.0f;
+        for (int w = 0; w < nw; ++w) s += red[w * B + tid];
+        logpsi[base + tid] = s;
+    }
+    if (!O) return;
+    const int64_t P = (int64_t)N + M + (int64_t)M * N;
+    for (int b = 0; b < B; ++b) {
+        const int64_t row = base + b;
+        if (row >= n) break;
+        float *o = O + row * P;
+        for (int p = tid; p < N + M; p += nt) o[p] = p < N ? spT[p * B + b] : tT[(p - N) * B + b];
+        // W block: q = j*N + i, advanced by nt per iteration with (j, i) carried
+        int j = tid / N, i = tid - (tid / N) * N;
+        const int dj = nt / N, di = nt - (nt / N) * N;
+        float *ow = o + N + M;
+        for (int64_t q = tid; q < (int64_t)M * N; q += nt) {
+            ow[q] = tT[j * B + b] * spT[i * B + b];
+            i += di;
+            j += dj;
+            if (i >= N) {
+                i -= N;
+                ++j;
+            }
+        }
+    }
+}
+
+// vjp_out[p] = sum_k g_k O[k][p] using the per-sample tanh values T[n][M].
+__global__ void rbm_vjp_kernel(int N, int M, const int8_t *__restrict__ samples, const float *__restrict__ T,
+                               const float *__restrict__ g, int64_t n, float *__restrict__ out)
+{
+    const int64_t P = (int64_t)N + M + (int64_t)M * N;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        if (p < N) {
+            for (int64_t k = 0; k < n; ++k) acc += (double)g[k] * samples[k * N + p];
+        } else if (p < N + M) {
+            const int j = (int)(p - N);
+            for (int64_t k = 0; k < n; ++k) acc += (double)g[k] * T[k * M + j];
+        } else {
+            const int64_t q = p - N - M;
+            const int j = (int)(q / N), i = (int)(q - (q / N) * N);
+            for (int64_t k = 0; k < n; ++k) acc += (double)g[k] * T[k * M + j] * samples[k * N + i];
+        }
+        out[p] = (float)acc;
+    }
+}
+
+nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
+                           const float *vjp_in, float *vjp_out, hipStream_t stream)
+{
+    nqs_status st = ensure_copy(m, NQS_F32, stream);
+    if (st != NQS_OK) return st;
+    const RbmDev &net = m->copies[NQS_F32].rbm;
+    const int N = net.N, M = net.M;
+    constexpr int B = 8;
+    const int threads = 256;
+    const size_t lds = sizeof(float) * ((size_t)N * B + (size_t)M * B + (threads / 64) * B);
+    if (lds > kLdsBytes) return set_error(NQS_EUNSUPPORTED, "RBM too large for the gradient kernel");
+    float *T = nullptr;
+    if (vjp_in) {
+        T = (float *)workspace(sizeof(float) * (size_t)n * M, stream);
+        if (!T) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    }
+    const int64_t blocks = (n + B - 1) / B;
+    if (blocks > INT32_MAX) return set_error(NQS_EINVAL, "too many samples");
+    if (logpsi || O || T) {
+        allow_lds(rbm_grad_kernel<B>, lds);
+        hipLaunchKernelGGL((rbm_grad_kernel<B>), dim3((unsigned)blocks), dim3(threads), lds, stream, net, samples, n,
+                           logpsi, O, T);
+        NQS_HIP_TRY(hipGetLastError());
+    }
+    if (vjp_in) {
+        const int64_t P = m->P;
+        const int vb = (int)std::min<int64_t>((P + 255) / 256, 65535);
+        hipLaunchKernelGGL(rbm_vjp_kernel, dim3(vb), dim3(256), 0, stream, N, M, samples, T, vjp_in, n, vjp_out);
+        NQS_HIP_TRY(hipGetLastError());
+    }
+    return NQS_OK;
+}
+
+}  // namespace nqs

@@ -1,0 +1,86 @@
+"""Host-side checks of the C interface (no GPU needed): the library loads, it
+exports every function include/nqs.h declares, and argument validation rejects
+bad calls before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "nqs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?[\s\*]+(nqs_[a-z0-9_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2601_20782_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.fail("libnqs.so is not built (run __graft_entry__.build())")
+    return _abi.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_2601_20782_amd import _abi
+    declared = _declared_functions()
+    assert len(declared) >= 14
+    assert sorted(_abi.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_error_strings(lib):
+    assert b"gfx950" in lib.nqs_version()
+    assert isinstance(lib.nqs_last_error(), bytes)
+
+
+def test_model_create_rejects_bad_descriptions(lib):
+    from paper_2601_20782_amd import _abi
+    out = ctypes.c_void_p()
+    p = np.zeros(10)
+    d = _abi.ModelDesc()
+    d.arch, d.n_visible, d.n_layers = _abi.RBM, 16, 1
+    d.widths[0] = 16
+    # wrong parameter count: rejected before any device work
+    assert lib.nqs_model_create(ctypes.byref(d), p.ctypes.data_as(ctypes.c_void_p), 10, ctypes.byref(out)) == _abi.NQS_EINVAL
+    assert b"n_params" in lib.nqs_last_error()
+    # NaN parameters
+    P = 16 + 16 + 256
+    bad = np.zeros(P)
+    bad[7] = np.nan
+    assert lib.nqs_model_create(ctypes.byref(d), bad.ctypes.data_as(ctypes.c_void_p), P, ctypes.byref(out)) == _abi.NQS_ENUMERIC
+    # unknown architecture / bad widths
+    d.arch = 7
+    assert lib.nqs_model_create(ctypes.byref(d), bad.ctypes.data_as(ctypes.c_void_p), P, ctypes.byref(out)) == _abi.NQS_EINVAL
+    d.arch, d.n_layers = _abi.FFNN, 0
+    assert lib.nqs_model_create(ctypes.byref(d), bad.ctypes.data_as(ctypes.c_void_p), P, ctypes.byref(out)) == _abi.NQS_EINVAL
+    # Marshall lattice must match N
+    d.arch, d.n_layers, d.marshall, d.lat_dim, d.lat_L = _abi.RBM, 1, 1, 2, 5
+    assert lib.nqs_model_create(ctypes.byref(d), bad.ctypes.data_as(ctypes.c_void_p), P, ctypes.byref(out)) == _abi.NQS_EINVAL
+
+
+def test_calls_without_model_are_rejected(lib):
+    from paper_2601_20782_amd import _abi
+    cfg = _abi.SampleCfg()
+    cfg.n_chains = 4
+    assert lib.nqs_sample(None, ctypes.byref(cfg), None, None, None, None, None, None) == _abi.NQS_EINVAL
+    assert lib.nqs_local_energy(None, None, None, 1, 1, None, None) == _abi.NQS_EINVAL
+    assert lib.nqs_energy_stats(None, 0, 1, None, None) == _abi.NQS_EINVAL
+    assert lib.nqs_forces(None, None, 0, 5, None, None, None) == _abi.NQS_EINVAL
+    assert lib.nqs_gram(None, 4, 4, 3, None, None) == _abi.NQS_EINVAL
+    assert lib.nqs_downcast(None, 5, 1, None, None, None) == _abi.NQS_EINVAL
+    assert lib.nqs_downcast(None, 0, 1, None, None, None) == _abi.NQS_OK   # empty input is a no-op
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2601_20782_amd import _abi
+    monkeypatch.setattr(_abi, "_lib", None)
+    monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _abi.load()

@@ -1,0 +1,341 @@
+"""GPU parity of the RBM path (single-flip sampler, TFIM local energies,
+log-derivatives, FP64 averages, Gram matrices) against the CPU oracle.
+Every call goes through the C interface."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_20782_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run_sampler(nqs, model, cfg, N, trace_chains=0):
+    state = torch.zeros(cfg.n_chains, N, dtype=torch.int8, device=DEV)
+    samples = torch.empty(cfg.n_sweeps, cfg.n_chains, N, dtype=torch.int8, device=DEV)
+    logpsi = torch.empty(cfg.n_sweeps, cfg.n_chains, dtype=torch.float32, device=DEV)
+    acc = torch.empty(cfg.n_chains, dtype=torch.int64, device=DEV)
+    tr = None
+    if trace_chains:
+        total = (cfg.n_sweeps + cfg.n_burnin) * (cfg.sweep_size or N)
+        tr = {"n": trace_chains,
+              "site": torch.empty(trace_chains * total, dtype=torch.int32, device=DEV),
+              "ubits": torch.empty(trace_chains * total, dtype=torch.int32, device=DEV),
+              "delta": torch.empty(trace_chains * total, dtype=torch.float32, device=DEV),
+              "accepted": torch.empty(trace_chains * total, dtype=torch.uint8, device=DEV)}
+    nqs.nqs_sample(model, cfg, state, samples, logpsi, acc, trace=tr)
+    torch.cuda.synchronize()
+    out = {"state": state.cpu().numpy(), "samples": samples.cpu().numpy(), "logpsi": logpsi.cpu().numpy(),
+           "acc": acc.cpu().numpy()}
+    if tr:
+        total = (cfg.n_sweeps + cfg.n_burnin) * (cfg.sweep_size or N)
+        for k in ("site", "ubits", "delta", "accepted"):
+            out["tr_" + k] = tr[k].cpu().numpy().reshape(trace_chains, total)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Downcast (a1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "e4m3"])
+def test_downcast_bit_exact(nqs, dtype):
+    _say(f"downcast {dtype}")
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.normal(0, 0.02, 30000), rng.normal(0, 3, 3000), rng.uniform(-1e-6, 1e-6, 1000),
+                        np.exp(rng.uniform(-30, 12, 3000)) * rng.choice([-1, 1], 3000), [0.0, 1.0, -2.5]])
+    # exact ties and neighbours of ties for the 16-bit formats
+    m, e = np.frexp(rng.normal(0, 1, 2000))
+    for fb in (8, 11):
+        t = (np.floor(m * 2.0 ** fb) + 0.5) * 2.0 ** (e - fb)
+        x = np.concatenate([x, t, np.nextafter(t, np.inf), np.nextafter(t, -np.inf)])
+    src = torch.from_numpy(x).to(DEV)
+    dst = torch.empty(x.size, dtype=torch.float32, device=DEV)
+    scale = torch.zeros(1, dtype=torch.float32, device=DEV)
+    nqs.nqs_downcast(src, dtype, dst, scale)
+    got = dst.cpu().numpy().astype(np.float64)
+    if dtype == "e4m3":
+        sc = oracle.e4m3_scale(x)
+        assert scale.item() == np.float32(sc)
+        ref = oracle.round_to(x / sc, "e4m3") * sc
+        ref = ref.astype(np.float32).astype(np.float64)
+    else:
+        ref = oracle.round_to(x, dtype)
+    fin = np.isfinite(ref)
+    assert np.array_equal(got[fin], ref[fin])
+    assert np.array_equal(np.isinf(got), np.isinf(ref))
+
+
+def test_downcast_empty_and_ragged(nqs):
+    for n in (1, 3, 257, 1025):
+        x = torch.linspace(-1, 1, n, dtype=torch.float64, device=DEV)
+        y = torch.empty(n, dtype=torch.float32, device=DEV)
+        nqs.nqs_downcast(x, "bf16", y)
+        assert np.array_equal(y.cpu().numpy().astype(np.float64), oracle.round_to(x.cpu().numpy(), "bf16"))
+
+
+# ---------------------------------------------------------------------------
+# Sampler
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("move", ["flip"])
+def test_init_states_match_oracle(nqs, move):
+    _say("init states")
+    N = 37
+    p = workloads.rbm_params(N, 8, 0.01, 1)
+    model = nqs.Model("rbm", N, (8,), p)
+    cfg = nqs.SampleConfig(n_chains=300, n_sweeps=0, n_burnin=0, seed=1234, move=move)
+    r = _run_sampler(nqs, model, cfg, N)
+    ref = np.array([oracle.init_chain(N, move, 1234, c) for c in range(300)])
+    assert np.array_equal(r["state"], ref)
+
+
+@pytest.mark.parametrize("lanes", [16, 32, 64])
+def test_cfg1_free_running_bit_exact(nqs, lanes):
+    """1D TFIM N=16, RBM alpha=1: every decision and configuration equals the FP64 oracle's."""
+    wl = workloads.cfg1_tfim_chain16()
+    _say(f"cfg1 free-running, lanes_per_chain={lanes}")
+    params = workloads.params_for(wl)
+    N = wl.model.n_visible
+    model = nqs.Model.from_workload(wl, params)
+    cfg = nqs.SampleConfig(n_chains=wl.n_chains, n_sweeps=wl.n_sweeps, n_burnin=wl.n_burnin, seed=wl.seed,
+                           lanes_per_chain=lanes)
+    r = _run_sampler(nqs, model, cfg, N)
+    om = oracle.model_from_workload(wl, params, "f32")
+    st, smp, lp, acc = oracle.sample(om, oracle.make_cfg(wl.n_chains, wl.n_sweeps, wl.n_burnin, seed=wl.seed))
+    assert np.array_equal(r["samples"], smp)
+    assert np.array_equal(r["state"], st)
+    assert np.array_equal(r["acc"], acc.astype(np.int64))
+    assert np.max(np.abs(r["logpsi"] - lp) / np.maximum(1.0, np.abs(lp))) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_cfg2_shape_decision_replay(nqs, dtype):
+    """10x10 TFIM, RBM alpha=2 (N=100, M=200): replay every traced decision in FP64."""
+    wl = workloads.cfg2_tfim_10x10()
+    _say(f"cfg2 replay {dtype}")
+    params = workloads.params_for(wl)
+    N = wl.model.n_visible
+    C, S, B, T = 96, 6, 3, 12
+    model = nqs.Model.from_workload(wl, params)
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=wl.seed, dtype=dtype)
+    r = _run_sampler(nqs, model, cfg, N, trace_chains=T)
+    om = oracle.model_from_workload(wl, params, dtype)
+    ocfg = oracle.make_cfg(C, S, B, seed=wl.seed)
+    starts = np.array([oracle.init_chain(N, "flip", wl.seed, c) for c in range(T)])
+    res = oracle.replay(om, ocfg, list(range(T)), starts, r["tr_site"], r["tr_ubits"].view(np.uint32),
+                        r["tr_delta"], r["tr_accepted"], tau_rel=1e-5)
+    _say(f"  replay: {res['decisions_equal']} equal, {res['near_ties']} near ties, max |dDelta| {res['max_delta_err']:.2e}")
+    assert res["site_u_mismatch"] == 0
+    assert res["decision_mismatch"] == 0
+    assert res["max_delta_err"] < 1e-4
+    assert np.array_equal(res["end_states"], r["state"][:T])
+    # recorded log psi equals the oracle's log-amplitude of the recorded sample
+    f, _ = om.logamp(r["samples"].reshape(-1, N))
+    lp = r["logpsi"].ravel()
+    assert np.max(np.abs(lp - f) / np.maximum(1.0, np.abs(f))) < 1e-5
+    # untraced chains follow the same trajectories as the traced-free run
+    r2 = _run_sampler(nqs, model, cfg, N)
+    assert np.array_equal(r2["samples"], r["samples"])
+
+
+def test_exact_pi_small_system(nqs):
+    """N=8 chain, strongly non-flat RBM: device histogram vs exact |psi|^2 by enumeration."""
+    import scipy.stats
+    n = 8
+    p = workloads.rbm_params(n, 8, 0.45, 21)
+    model = nqs.Model("rbm", n, (8,), p)
+    cfg = nqs.SampleConfig(n_chains=2048, n_sweeps=100, n_burnin=20, seed=3)
+    r = _run_sampler(nqs, model, cfg, n)
+    pi, _, _ = exact.enumerate_pi(oracle.OracleModel("rbm", n, (8,), oracle.round_to(p, "f32")))
+    idx = np.sum((r["samples"].reshape(-1, n) > 0).astype(np.int64) << np.arange(n), axis=1)
+    counts = np.bincount(idx, minlength=2 ** n)
+    e = pi * counts.sum()
+    keep = e > 5
+    chi2 = np.sum((counts[keep] - e[keep]) ** 2 / e[keep])
+    assert scipy.stats.chi2.sf(chi2, keep.sum() - 1) > 1e-5
+    tv = exact.tv(pi, counts / counts.sum())
+    assert tv < 0.03
+
+
+def test_product_state_closed_forms_at_n100(nqs):
+    """W = 0 on the 10x10 lattice: acceptance and <H_TFIM> have closed forms (C-P7)."""
+    n, L = 100, 10
+    p = workloads.product_state_params(n, 200, 0.3, 8)
+    model = nqs.Model("rbm", n, (200,), p)
+    ham = nqs.Hamiltonian("tfim", 2, L, 1.0, 3.04)
+    C, S, B = 1024, 40, 10
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=9)
+    r = _run_sampler(nqs, model, cfg, n)
+    _, e_ref, acc_ref = exact.product_state_tfim(oracle.round_to(p[:n], "f32"), oracle.bonds(2, L), 1.0, 3.04)
+    samples = torch.from_numpy(r["samples"]).to(DEV)
+    eloc = torch.empty(S * C, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, ham, samples, eloc)
+    stats = torch.empty(4, dtype=torch.float64, device=DEV)
+    nqs.nqs_energy_stats(eloc, C, stats)
+    st = stats.cpu().numpy()
+    assert abs(st[0] - e_ref) < 5 * st[2]
+    rate = r["acc"].sum() / (C * (S + B) * n)
+    assert abs(rate - acc_ref) < 6 * np.sqrt(acc_ref * (1 - acc_ref) / (C * (S + B) * n)) * 3
+
+
+def test_resume_and_chain_split_are_bit_exact(nqs):
+    n = 36
+    p = workloads.rbm_params(n, 72, 0.05, 5)
+    model = nqs.Model("rbm", n, (72,), p)
+    full = _run_sampler(nqs, model, nqs.SampleConfig(n_chains=64, n_sweeps=20, n_burnin=0, seed=8), n)
+    a = _run_sampler(nqs, model, nqs.SampleConfig(n_chains=64, n_sweeps=10, n_burnin=0, seed=8), n)
+    state = torch.from_numpy(a["state"]).to(DEV)
+    samples = torch.empty(10, 64, n, dtype=torch.int8, device=DEV)
+    cfg_b = nqs.SampleConfig(n_chains=64, n_sweeps=10, n_burnin=0, seed=8, init_chains=False, step_offset=10 * n)
+    nqs.nqs_sample(model, cfg_b, state, samples)
+    torch.cuda.synchronize()
+    assert np.array_equal(np.concatenate([a["samples"], samples.cpu().numpy()]), full["samples"])
+    # second half of the chains run on their own with chain_id_offset
+    half = _run_sampler(nqs, model, nqs.SampleConfig(n_chains=32, n_sweeps=20, n_burnin=0, seed=8, chain_id_offset=32), n)
+    assert np.array_equal(half["samples"], full["samples"][:, 32:])
+
+
+# ---------------------------------------------------------------------------
+# Local energies, statistics
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["cfg2", "cfg1", "open2d", "ragged"])
+def test_local_energy_tfim_matches_oracle(nqs, case):
+    if case == "cfg2":
+        wl = workloads.cfg2_tfim_10x10()
+        n_s = 700
+    elif case == "cfg1":
+        wl = workloads.cfg1_tfim_chain16()
+        n_s = 333
+    elif case == "open2d":
+        wl = workloads.Workload("open", workloads.Hamiltonian("tfim", workloads.Lattice(2, 7, pbc=False), 0.7, 1.9),
+                                workloads.Model("rbm", 49, (98,)), 1, 1, 0, "flip", 0.3, 11)
+        n_s = 129
+    else:
+        wl = workloads.Workload("ragged", workloads.Hamiltonian("tfim", workloads.Lattice(2, 9), 1.0, 2.5),
+                                workloads.Model("rbm", 81, (243,)), 1, 1, 0, "flip", 0.1, 12)
+        n_s = 17
+    _say(f"eloc {case}")
+    params = workloads.params_for(wl)
+    N = wl.model.n_visible
+    model = nqs.Model.from_workload(wl, params)
+    smp = workloads.random_spins(n_s, N, 4)
+    el = torch.empty(n_s, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(wl.ham), torch.from_numpy(smp).to(DEV), el)
+    om = oracle.model_from_workload(wl, params, "f32")
+    ref = oracle.local_energy(om, wl.ham, smp)
+    got = el.cpu().numpy()
+    # FP32 ratios summed in FP64: error relative to the size of the sum's terms
+    scale = np.abs(ref) + abs(wl.ham.J) * 2 * N + abs(wl.ham.h) * N
+    assert np.max(np.abs(got - ref) / scale) < 2e-6
+
+
+def test_local_energy_lowprec_copy(nqs):
+    wl = workloads.cfg2_tfim_10x10()
+    params = workloads.params_for(wl)
+    model = nqs.Model.from_workload(wl, params)
+    smp = workloads.random_spins(64, 100, 6)
+    for dt in ("bf16", "f16"):
+        el = torch.empty(64, dtype=torch.float64, device=DEV)
+        nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(wl.ham), torch.from_numpy(smp).to(DEV), el, dt)
+        ref = oracle.local_energy(oracle.model_from_workload(wl, params, dt), wl.ham, smp)
+        assert np.max(np.abs(el.cpu().numpy() - ref)) < 2e-6 * (3.04 * 100 + 200)
+
+
+@pytest.mark.parametrize("n,C", [(4096, 64), (1000, 10), (7, 7), (5, 3), (1, 1)])
+def test_energy_stats_matches_oracle(nqs, n, C):
+    e = np.random.default_rng(n).normal(-3.0, 2.0, n)
+    stats = torch.empty(4, dtype=torch.float64, device=DEV)
+    nqs.nqs_energy_stats(torch.from_numpy(e).to(DEV), C, stats)
+    got = stats.cpu().numpy()
+    ref = oracle.stats(e, C)
+    assert abs(got[0] - ref[0]) < 1e-12 * max(1, abs(ref[0]))
+    assert abs(got[1] - ref[1]) < 1e-10 * max(1, ref[1])
+    if np.isnan(ref[2]):
+        assert np.isnan(got[2])
+    else:
+        assert abs(got[2] - ref[2]) < 1e-10 * max(1e-3, ref[2])
+    assert got[3] == n
+
+
+# ---------------------------------------------------------------------------
+# Log-derivatives, forces, Gram matrices
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,M,n", [(100, 200, 37), (16, 16, 64), (9, 27, 5)])
+def test_logpsi_grad_matches_oracle(nqs, N, M, n):
+    p = workloads.rbm_params(N, M, 0.05, N + M)
+    model = nqs.Model("rbm", N, (M,), p)
+    smp = workloads.random_spins(n, N, 3)
+    st = torch.from_numpy(smp).to(DEV)
+    P = model.n_params
+    lp = torch.empty(n, dtype=torch.float32, device=DEV)
+    O = torch.empty(n, P, dtype=torch.float32, device=DEV)
+    nqs.nqs_logpsi_grad(model, st, logpsi=lp, O=O)
+    om = oracle.OracleModel("rbm", N, (M,), oracle.round_to(p, "f32"))
+    rlp, rO = oracle.logpsi_grad(om, smp)
+    assert np.max(np.abs(lp.cpu().numpy() - rlp) / np.maximum(1, np.abs(rlp))) < 1e-5
+    assert np.max(np.abs(O.cpu().numpy() - rO)) < 1e-6
+    # VJP mode equals g^T O
+    g = np.random.default_rng(1).normal(size=n).astype(np.float32)
+    vo = torch.empty(P, dtype=torch.float32, device=DEV)
+    nqs.nqs_logpsi_grad(model, st, vjp_in=torch.from_numpy(g).to(DEV), vjp_out=vo)
+    assert np.allclose(vo.cpu().numpy(), g.astype(np.float64) @ rO, rtol=1e-5, atol=1e-5)
+
+
+def test_logpsi_autograd_function(nqs):
+    N, M, n = 12, 24, 20
+    p = workloads.rbm_params(N, M, 0.1, 2)
+    model = nqs.Model("rbm", N, (M,), p)
+    smp = torch.from_numpy(workloads.random_spins(n, N, 8)).to(DEV)
+    theta = torch.zeros(model.n_params, dtype=torch.float32, device=DEV, requires_grad=True)
+    out = nqs.LogPsi.apply(theta, model, smp)
+    w = torch.linspace(-1, 1, n, device=DEV)
+    (out * w).sum().backward()
+    _, rO = oracle.logpsi_grad(oracle.OracleModel("rbm", N, (M,), oracle.round_to(p, "f32")), smp.cpu().numpy())
+    assert np.allclose(theta.grad.cpu().numpy(), w.cpu().numpy().astype(np.float64) @ rO, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("n,P", [(257, 1030), (64, 20300), (3, 5)])
+def test_forces_match_oracle(nqs, n, P):
+    rng = np.random.default_rng(P)
+    O = rng.normal(size=(n, P)).astype(np.float32)
+    e = rng.normal(-40, 3, size=n)
+    F = torch.empty(P, dtype=torch.float64, device=DEV)
+    Om = torch.empty(P, dtype=torch.float64, device=DEV)
+    nqs.nqs_forces(torch.from_numpy(O).to(DEV), torch.from_numpy(e).to(DEV), F, Om)
+    ref = oracle.forces(O.astype(np.float64), e)
+    assert np.max(np.abs(F.cpu().numpy() - ref)) < 1e-10 * max(1, np.abs(ref).max()) * n
+    assert np.allclose(Om.cpu().numpy(), O.astype(np.float64).mean(axis=0), atol=1e-12)
+
+
+@pytest.mark.parametrize("mode,n,P", [(1, 200, 333), (0, 150, 260), (1, 129, 70), (0, 31, 129), (1, 1, 3)])
+def test_gram_matches_oracle(nqs, mode, n, P):
+    rng = np.random.default_rng(n * P)
+    O = (rng.normal(size=(n, P)) + rng.normal(size=P)).astype(np.float32)
+    side = P if mode == 0 else n
+    out = torch.empty(side, side, dtype=torch.float32, device=DEV)
+    nqs.nqs_gram(torch.from_numpy(O).to(DEV), mode, out)
+    O64 = O.astype(np.float64)
+    ref = oracle.smatrix(O64) if mode == 0 else oracle.tmatrix(O64)
+    got = out.cpu().numpy()
+    tol = 1e-5 * (np.abs(O64 - O64.mean(0)) ** 2).sum(axis=1 if mode == 1 else 0).max() / n
+    assert np.max(np.abs(got - ref)) < tol + 1e-6
