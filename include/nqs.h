@@ -131,6 +131,10 @@ nqs_status nqs_model_set_params(nqs_model *m, const double *host_params, int64_t
 /* Replace the FP64 master from a DEVICE vector (stream ordered); copies are rebuilt on `stream`. */
 nqs_status nqs_model_set_params_device(nqs_model *m, const double *dev_params, int64_t n_params, void *stream);
 nqs_status nqs_model_destroy(nqs_model *m);
+/* Build the `dtype` sampling copy from the FP64 master now (the downcast of
+ * the two-copy scheme, Sec. IV.B), instead of lazily at the next call that
+ * needs it.  Synchronises `stream` once to read back the weight range. */
+nqs_status nqs_model_prepare(nqs_model *m, int32_t dtype, void *stream);
 int64_t nqs_model_num_params(const nqs_model *m);
 
 /* Downcast (Sec. IV.B two-copy scheme, App. A): round every FP64 value of

@@ -88,6 +88,10 @@ class Model:
     def set_params_device(self, params: torch.Tensor, stream=None) -> None:
         check(load().nqs_model_set_params_device(self._h, _ptr(params), params.numel(), _stream(stream)))
 
+    def prepare(self, dtype, stream=None) -> None:
+        """Build the `dtype` sampling copy from the FP64 master now (the downcast step)."""
+        check(load().nqs_model_prepare(self._h, _dtype(dtype), _stream(stream)))
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             load().nqs_model_destroy(self._h)

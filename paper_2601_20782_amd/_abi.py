@@ -19,7 +19,7 @@ DTYPE_CODES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "e4m3": FP8_E4M
 # every function include/nqs.h declares
 EXPORTS = [
     "nqs_model_create", "nqs_model_set_params", "nqs_model_set_params_device", "nqs_model_destroy",
-    "nqs_model_num_params", "nqs_downcast", "nqs_sample", "nqs_local_energy", "nqs_energy_stats",
+    "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_local_energy", "nqs_energy_stats",
     "nqs_logpsi_grad", "nqs_forces", "nqs_gram", "nqs_last_error", "nqs_version",
 ]
 
@@ -74,6 +74,7 @@ def load() -> ctypes.CDLL:
         "nqs_model_set_params_device": ([P, P, i64, P], st),
         "nqs_model_destroy": ([P], st),
         "nqs_model_num_params": ([P], i64),
+        "nqs_model_prepare": ([P, i32, P], st),
         "nqs_downcast": ([P, i64, i32, P, P, P], st),
         "nqs_sample": ([P, P, P, P, P, P, P, P], st),
         "nqs_local_energy": ([P, P, P, i64, i32, P, P], st),

@@ -194,6 +194,14 @@ nqs_status nqs_model_destroy(nqs_model *m)
     return NQS_OK;
 }
 
+nqs_status nqs_model_prepare(nqs_model *m, int32_t dtype, void *stream)
+{
+    if (!m) return set_error(NQS_EINVAL, "NULL model");
+    if (dtype < NQS_F32 || dtype > NQS_FP8_E4M3) return set_error(NQS_EINVAL, "dtype must be F32, F16, BF16 or FP8_E4M3");
+    m->copies[dtype].valid = false;
+    return ensure_copy(m, dtype, (hipStream_t)stream);
+}
+
 nqs_status nqs_downcast(const double *src, int64_t n, int32_t dtype, float *dst, float *scale_out, void *stream)
 {
     if (n < 0) return set_error(NQS_EINVAL, "n < 0");
