@@ -41,13 +41,15 @@ def _args():
     ap.add_argument("--dtype", default="bf16", choices=["bf16", "f16", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison step")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per chain of the sampler (0 = library default)")
+    ap.add_argument("--refresh", type=int, default=1, help="sweeps between full recomputes of theta = W s + b")
     return ap.parse_args()
 
 
 class Step:
     """Buffers and phases of one hot-path pass for a sampling dtype."""
 
-    def __init__(self, nqs, torch, wl, params, dtype):
+    def __init__(self, nqs, torch, wl, params, dtype, lanes=0, refresh=1):
         self.nqs, self.torch, self.wl, self.dtype = nqs, torch, wl, dtype
         dev = torch.device("cuda:0")
         m = wl.model
@@ -56,7 +58,8 @@ class Step:
         self.model = nqs.Model.from_workload(wl, params)
         self.master = torch.from_numpy(np.asarray(params, dtype=np.float64)).to(dev)
         self.ham = nqs.Hamiltonian.from_workload(wl.ham)
-        self.cfg = nqs.SampleConfig(n_chains=self.C, n_sweeps=self.S, n_burnin=self.B, seed=wl.seed, dtype=dtype)
+        self.cfg = nqs.SampleConfig(n_chains=self.C, n_sweeps=self.S, n_burnin=self.B, seed=wl.seed, dtype=dtype,
+                                    lanes_per_chain=lanes, refresh_sweeps=refresh)
         self.state = torch.empty(self.C, N, dtype=torch.int8, device=dev)
         self.samples = torch.empty(self.S, self.C, N, dtype=torch.int8, device=dev)
         self.acc = torch.empty(self.C, dtype=torch.int64, device=dev)
@@ -165,7 +168,7 @@ def main():
     N, C, S, B = wl.model.n_visible, wl.n_chains, wl.n_sweeps, wl.n_burnin
     props = C * (S + B) * N
 
-    main_step = Step(nqs, torch, wl, params, a.dtype)
+    main_step = Step(nqs, torch, wl, params, a.dtype, a.lanes, a.refresh)
     wall, phases, step_ms = main_step.timed(a.steps, a.warmup)
     ms = max(float(np.mean(step_ms)), 1e3 * wall / a.steps)
     st = main_step.stats.cpu().numpy()
@@ -200,7 +203,7 @@ def main():
     }
 
     if not a.no_compare:
-        ref = Step(nqs, torch, wl, params, "f32")
+        ref = Step(nqs, torch, wl, params, "f32", a.lanes, a.refresh)
         wall32, phases32, step32 = ref.timed(a.steps, a.warmup)
         ms32 = max(float(np.mean(step32)), 1e3 * wall32 / a.steps)
         st32 = ref.stats.cpu().numpy()

@@ -111,6 +111,54 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+// ---------------------------------------------------------------------------
+// DPP reductions (no LDS traffic).  An inclusive Hillis-Steele scan inside
+// each 16-lane row (row_shr 1, 2, 4, 8), then row_bcast:15 / row_bcast:31
+// carry row totals upwards: the total of a group of G lanes ends in the
+// group's last lane.  group_sum_uniform() reads that lane with v_readlane, so
+// every lane of the group receives the same bits (decisions stay uniform).
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, false));
+}
+
+template <int G>
+__device__ __forceinline__ float group_scan_total(float v)
+{
+    v += dpp_f32<0x111, 0xF, 0xF>(v);   // row_shr:1
+    v += dpp_f32<0x112, 0xF, 0xF>(v);   // row_shr:2
+    v += dpp_f32<0x114, 0xF, 0xF>(v);   // row_shr:4
+    v += dpp_f32<0x118, 0xF, 0xF>(v);   // row_shr:8
+    if constexpr (G >= 32) v += dpp_f32<0x142, 0xA, 0xF>(v);   // row_bcast:15 -> rows 1, 3
+    if constexpr (G >= 64) v += dpp_f32<0x143, 0xC, 0xF>(v);   // row_bcast:31 -> rows 2, 3
+    return v;
+}
+
+__device__ __forceinline__ float readlane_f32(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum_uniform(float v)
+{
+    v = group_scan_total<G>(v);
+    if constexpr (G == 64) {
+        return readlane_f32(v, 63);
+    } else {
+        const int grp = (int)(threadIdx.x & 63) / G;
+        float r = readlane_f32(v, G - 1);
+#pragma unroll
+        for (int q = 1; q < 64 / G; ++q) {
+            const float rq = readlane_f32(v, q * G + G - 1);
+            r = grp == q ? rq : r;
+        }
+        return r;
+    }
+}
+
 // value of lane (group base + p) broadcast to the group; p is uniform
 template <int G>
 __device__ __forceinline__ uint32_t group_bcast(uint32_t v, int p)

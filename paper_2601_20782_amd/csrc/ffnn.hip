@@ -1,27 +1,395 @@
-// Dense-network (FFNN) kernels: exchange-move sampler, Heisenberg local energies, backward.
+// Dense networks: h_l = ReLU(W_l h_{l-1} + b_l) for l < L, log psi = sum log cosh(z_L).
+// This file builds the reduced-precision copies and holds the log-derivative
+// (backward) kernel; the MFMA sampler and local energies live in ffnn_mc.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
 #include "common.h"
+#include "ffnn_mc.h"
 #include "internal.h"
 
 namespace nqs {
 
-nqs_status ffnn_build_copy(nqs_model *, int, hipStream_t)
+// ---------------------------------------------------------------------------
+// Copy builder.  For every layer: the format-rounded weights as FP32 values
+// in both orientations and FP32 biases.  For the matrix-core path the second
+// layer is also kept zero-padded to [ceil(w2/64)*64][ceil(w1/16)*16] (FP32
+// values and raw 16-bit codes), and the first layer transposed, [N][w1 pad],
+// as raw codes for the LDS-resident rank-1/2 updates.
+// ---------------------------------------------------------------------------
+__global__ void ffnn_round_layer_kernel(const double *__restrict__ Wsrc, const double *__restrict__ bsrc, int out,
+                                        int in, int dtype, float *W, float *Wt, float *b)
 {
-    return set_error(NQS_EUNSUPPORTED, "dense networks are not built yet");
+    const int64_t n = (int64_t)out * in;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n + out; p += (int64_t)gridDim.x * blockDim.x) {
+        if (p < n) {
+            const int r = (int)(p / in), k = (int)(p % in);
+            const float v = (float)round_to_dtype(Wsrc[p], dtype);
+            W[p] = v;
+            Wt[(int64_t)k * out + r] = v;
+        } else {
+            b[p - n] = (float)round_to_dtype(bsrc[p - n], dtype);
+        }
+    }
 }
-nqs_status ffnn_sample(nqs_model *, const nqs_sample_cfg &, int8_t *, int8_t *, float *, uint64_t *, const nqs_trace *,
-                       hipStream_t)
+
+// dst[r][c] (ld_dst, zero padded to rows_p x cols_p) from src[r][c] (ld_src)
+__global__ void ffnn_pad_kernel(const float *__restrict__ src, int rows, int cols, int ld_src, int rows_p, int cols_p,
+                                int dtype, uint16_t *codes, float *f32)
 {
-    return set_error(NQS_EUNSUPPORTED, "dense networks are not built yet");
+    const int64_t n = (int64_t)rows_p * cols_p;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(p / cols_p), c = (int)(p % cols_p);
+        const float v = (r < rows && c < cols) ? src[(int64_t)r * ld_src + c] : 0.0f;
+        if (f32) f32[p] = v;
+        if (codes) {
+            uint16_t code;
+            if (dtype == kF16) {
+                const _Float16 h = (_Float16)v;   // exact: v is an f16 value
+                memcpy(&code, &h, 2);
+            } else {
+                code = (uint16_t)(__float_as_uint(v) >> 16);   // exact: v is a bf16 value
+            }
+            codes[p] = code;
+        }
+    }
 }
-nqs_status ffnn_local_energy(nqs_model *, const nqs_ham_desc &, const int8_t *, int64_t, int, double *, hipStream_t)
+
+nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream)
 {
-    return set_error(NQS_EUNSUPPORTED, "dense networks are not built yet");
+    const nqs_model_desc &d = m->desc;
+    if (dtype == NQS_FP8_E4M3) return set_error(NQS_EUNSUPPORTED, "FP8 dense copies are not built yet");
+    Copy &c = m->copies[dtype];
+    FfnnDev &f = c.ffnn;
+    f.n_layers = d.n_layers;
+    f.widths[0] = d.n_visible;
+    for (int l = 0; l < d.n_layers; ++l) f.widths[l + 1] = d.widths[l];
+    const bool lp = dtype == NQS_BF16 || dtype == NQS_F16;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int N = f.widths[0], M1 = f.widths[1];
+    f.m1p = (M1 + 15) / 16 * 16;
+    f.m2p = f.n_layers >= 2 ? (f.widths[2] + 63) / 64 * 64 : 0;
+    size_t bytes = 0;
+    for (int l = 0; l < f.n_layers; ++l) {
+        const size_t n = (size_t)f.widths[l + 1] * f.widths[l];
+        bytes += 2 * al(sizeof(float) * n) + al(sizeof(float) * f.widths[l + 1]);
+    }
+    if (f.n_layers >= 2)
+        bytes += al(sizeof(uint16_t) * (size_t)f.m2p * f.m1p) + al(sizeof(uint16_t) * (size_t)N * f.m1p) +
+                 al(sizeof(float) * (size_t)f.m2p * f.m1p) + al(sizeof(float) * (size_t)N * f.m1p) +
+                 al(sizeof(float) * f.m1p) + al(sizeof(float) * f.m2p);
+    if (!c.block) NQS_HIP_TRY(hipMalloc(&c.block, bytes));
+    char *base = (char *)c.block;
+    auto carve = [&](size_t sz) {
+        char *p = base;
+        base += al(sz);
+        return p;
+    };
+    for (int l = 0; l < f.n_layers; ++l) {
+        const size_t n = (size_t)f.widths[l + 1] * f.widths[l];
+        f.W[l] = (float *)carve(sizeof(float) * n);
+        f.Wt[l] = (float *)carve(sizeof(float) * n);
+        f.b[l] = (float *)carve(sizeof(float) * f.widths[l + 1]);
+    }
+    int64_t off = 0;
+    for (int l = 0; l < f.n_layers; ++l) {
+        const int out = f.widths[l + 1], in = f.widths[l];
+        const int64_t n = (int64_t)out * in;
+        const int blocks = (int)std::min<int64_t>((n + out + 255) / 256, 8192);
+        hipLaunchKernelGGL(ffnn_round_layer_kernel, dim3(blocks), dim3(256), 0, stream, m->master + off,
+                           m->master + off + n, out, in, dtype, f.W[l], f.Wt[l], f.b[l]);
+        NQS_HIP_TRY(hipGetLastError());
+        off += n + out;
+    }
+    if (f.n_layers >= 2) {
+        const int M2 = f.widths[2];
+        f.W2c = (uint16_t *)carve(sizeof(uint16_t) * (size_t)f.m2p * f.m1p);
+        f.W1ct = (uint16_t *)carve(sizeof(uint16_t) * (size_t)N * f.m1p);
+        f.W2p = (float *)carve(sizeof(float) * (size_t)f.m2p * f.m1p);
+        f.W1tp = (float *)carve(sizeof(float) * (size_t)N * f.m1p);
+        f.b1p = (float *)carve(sizeof(float) * f.m1p);
+        f.b2p = (float *)carve(sizeof(float) * f.m2p);
+        auto pad = [&](const float *src, int rows, int cols, int ld, int rows_p, int cols_p, uint16_t *codes,
+                       float *f32) {
+            const int64_t n = (int64_t)rows_p * cols_p;
+            const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+            hipLaunchKernelGGL(ffnn_pad_kernel, dim3(blocks), dim3(256), 0, stream, src, rows, cols, ld, rows_p, cols_p,
+                               dtype, codes, f32);
+        };
+        pad(f.W[1], M2, M1, M1, f.m2p, f.m1p, lp ? f.W2c : nullptr, f.W2p);
+        pad(f.Wt[0], N, M1, M1, N, f.m1p, lp ? f.W1ct : nullptr, f.W1tp);
+        pad(f.b[0], 1, M1, M1, 1, f.m1p, nullptr, f.b1p);
+        pad(f.b[1], 1, M2, M2, 1, f.m2p, nullptr, f.b2p);
+        NQS_HIP_TRY(hipGetLastError());
+    }
+    NQS_HIP_TRY(hipStreamSynchronize(stream));
+    c.valid = true;
+    return NQS_OK;
 }
-nqs_status ffnn_logpsi_grad(nqs_model *, const int8_t *, int64_t, float *, float *, const float *, float *, hipStream_t)
+
+// ---------------------------------------------------------------------------
+// log psi and O_k by reverse-mode differentiation written out by hand.
+// One block per sample (grid-stride); activations stay in LDS.
+//   delta_L = tanh(z_L);  O_{b_l} = delta_l;  O_{W_l} = delta_l (x) h_{l-1};
+//   delta_{l-1} = (W_l^T delta_l) * [z_{l-1} > 0]   (ReLU'(0) = 0).
+// O rows are written with consecutive threads on consecutive parameters.
+// ---------------------------------------------------------------------------
+struct GradArgs {
+    FfnnDev net;
+    const int8_t *samples;
+    int64_t n;
+    float *logpsi;
+    float *O;
+    int64_t P;
+    int lds_stride;   // floats reserved per layer activation vector
+};
+
+__global__ void __launch_bounds__(256) ffnn_grad_kernel(GradArgs A)
 {
-    return set_error(NQS_EUNSUPPORTED, "dense networks are not built yet");
+    extern __shared__ float smem[];
+    const FfnnDev &net = A.net;
+    const int L = net.n_layers, N = net.widths[0];
+    const int S = A.lds_stride;
+    float *in0 = smem;                  // [N] spins
+    float *z = smem + S;                // [L][S] pre-activations
+    float *dl = z + (size_t)L * S;      // [2][S] deltas (ping-pong)
+    __shared__ float red[4];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int64_t smp = blockIdx.x; smp < A.n; smp += gridDim.x) {
+        for (int i = tid; i < N; i += nt) in0[i] = (float)A.samples[smp * N + i];
+        __syncthreads();
+        // forward
+        for (int l = 0; l < L; ++l) {
+            const int out = net.widths[l + 1], in = net.widths[l];
+            const float *src = l == 0 ? in0 : z + (size_t)(l - 1) * S;
+            const float *Wt = net.Wt[l];
+            for (int r = tid; r < out; r += nt) {
+                float acc = net.b[l][r];
+                if (l == 0) {
+                    for (int k = 0; k < in; ++k) acc = fmaf(Wt[(size_t)k * out + r], src[k], acc);
+                } else {
+                    for (int k = 0; k < in; ++k) acc = fmaf(Wt[(size_t)k * out + r], fmaxf(src[k], 0.0f), acc);
+                }
+                z[(size_t)l * S + r] = acc;
+            }
+            __syncthreads();
+        }
+        // log psi
+        const int wl = net.widths[L];
+        float part = 0.0f;
+        for (int r = tid; r < wl; r += nt) part += logcosh_f32(z[(size_t)(L - 1) * S + r]);
+        part = group_sum<64>(part);
+        if ((tid & 63) == 0) red[tid >> 6] = part;
+        __syncthreads();
+        if (tid == 0 && A.logpsi) A.logpsi[smp] = red[0] + red[1] + red[2] + red[3];
+        if (A.O) {
+            float *O = A.O + smp * A.P;
+            // parameter offsets
+            int64_t offW[NQS_MAX_LAYERS], offb[NQS_MAX_LAYERS], off = 0;
+            for (int l = 0; l < L; ++l) {
+                offW[l] = off;
+                off += (int64_t)net.widths[l + 1] * net.widths[l];
+                offb[l] = off;
+                off += net.widths[l + 1];
+            }
+            float *d = dl;
+            for (int r = tid; r < wl; r += nt) d[r] = tanhf(z[(size_t)(L - 1) * S + r]);
+            __syncthreads();
+            for (int l = L - 1; l >= 0; --l) {
+                const int out = net.widths[l + 1], in = net.widths[l];
+                const float *src = l == 0 ? in0 : z + (size_t)(l - 1) * S;
+                for (int r = tid; r < out; r += nt) O[offb[l] + r] = d[r];
+                // O_W[r][k] = d[r] * h[k], consecutive threads on consecutive k
+                for (int r = 0; r < out; ++r) {
+                    const float dr = d[r];
+                    float *orow = O + offW[l] + (int64_t)r * in;
+                    if (l == 0) {
+                        for (int k = tid; k < in; k += nt) orow[k] = dr * src[k];
+                    } else {
+                        for (int k = tid; k < in; k += nt) orow[k] = dr * fmaxf(src[k], 0.0f);
+                    }
+                }
+                if (l == 0) break;
+                float *dn = (d == dl) ? dl + S : dl;
+                const float *W = net.W[l];
+                for (int k = tid; k < in; k += nt) {
+                    float g = 0.0f;
+                    for (int r = 0; r < out; ++r) g = fmaf(W[(size_t)r * in + k], d[r], g);
+                    dn[k] = src[k] > 0.0f ? g : 0.0f;
+                }
+                __syncthreads();
+                d = dn;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// vjp_out[p] += sum_k g[k] O[k][p] over a chunk of samples (FP64 accumulation per chunk)
+__global__ void vjp_chunk_kernel(const float *__restrict__ O, const float *__restrict__ g, int64_t n, int64_t P,
+                                 float *__restrict__ out, int first)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double acc = first ? 0.0 : (double)out[p];
+    for (int64_t k = 0; k < n; ++k) acc += (double)g[k] * (double)O[k * P + p];
+    out[p] = (float)acc;
+}
+
+nqs_status ffnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
+                            const float *vjp_in, float *vjp_out, hipStream_t stream)
+{
+    nqs_status st = ensure_copy(m, NQS_F32, stream);
+    if (st != NQS_OK) return st;
+    const FfnnDev &net = m->copies[NQS_F32].ffnn;
+    int maxw = net.widths[0];
+    for (int l = 1; l <= net.n_layers; ++l) maxw = std::max(maxw, net.widths[l]);
+    GradArgs A;
+    A.net = net;
+    A.P = m->P;
+    A.lds_stride = (maxw + 3) & ~3;
+    const size_t lds = sizeof(float) * (size_t)A.lds_stride * (1 + net.n_layers + 2);
+    if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too wide for the gradient kernel");
+    allow_lds(ffnn_grad_kernel, lds);
+    const int blocks = (int)std::min<int64_t>(n, 4096);
+    if (logpsi || O) {
+        A.samples = samples;
+        A.n = n;
+        A.logpsi = logpsi;
+        A.O = O;
+        hipLaunchKernelGGL(ffnn_grad_kernel, dim3(blocks), dim3(256), lds, stream, A);
+        NQS_HIP_TRY(hipGetLastError());
+    }
+    if (vjp_in) {
+        // chunks of samples through a workspace O block
+        const int64_t P = m->P;
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(256ll << 20) / (int64_t)(P * 4)));
+        float *Ow = (float *)workspace(sizeof(float) * (size_t)chunk * P, stream);
+        if (!Ow) return set_error(NQS_ENOMEM, "workspace allocation failed");
+        for (int64_t k0 = 0; k0 < n; k0 += chunk) {
+            const int64_t kn = std::min(chunk, n - k0);
+            A.samples = samples + k0 * net.widths[0];
+            A.n = kn;
+            A.logpsi = nullptr;
+            A.O = Ow;
+            hipLaunchKernelGGL(ffnn_grad_kernel, dim3((unsigned)std::min<int64_t>(kn, 4096)), dim3(256), lds, stream, A);
+            hipLaunchKernelGGL(vjp_chunk_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, Ow,
+                               vjp_in + k0, kn, P, vjp_out, k0 == 0 ? 1 : 0);
+            NQS_HIP_TRY(hipGetLastError());
+        }
+    }
+    return NQS_OK;
+}
+
+}  // namespace nqs
+
+namespace nqs {
+
+nqs_status ffnn_sample_dispatch(int dtype, int QK, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds,
+                                hipStream_t s);
+nqs_status ffnn_eloc_dispatch(int dtype, int QK, const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s);
+
+static nqs_status ffnn_mc_ready(nqs_model *m, int dtype, hipStream_t stream)
+{
+    if (m->desc.n_layers != 2)
+        return set_error(NQS_EUNSUPPORTED, "sampling and local energies of dense networks are implemented for two layers");
+    if (dtype != NQS_F32 && dtype != NQS_BF16 && dtype != NQS_F16)
+        return set_error(NQS_EUNSUPPORTED, "dense networks sample in F32, BF16 or F16");
+    nqs_status st = ensure_copy(m, dtype, stream);
+    if (st != NQS_OK) return st;
+    const FfnnDev &f = m->copies[dtype].ffnn;
+    if (f.m1p > 512) return set_error(NQS_EUNSUPPORTED, "first hidden width must be <= 512");
+    return NQS_OK;
+}
+
+static size_t sample_lds_bytes(int dtype, int N, int m1p, int m2p)
+{
+    if (dtype == NQS_F32) return FfnnLds<float>::bytes(N, m1p, m2p);
+    if (dtype == NQS_F16) return FfnnLds<_Float16>::bytes(N, m1p, m2p);
+    return FfnnLds<__bf16>::bytes(N, m1p, m2p);
+}
+
+nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
+                       uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream)
+{
+    nqs_status st = ffnn_mc_ready(m, cfg.dtype, stream);
+    if (st != NQS_OK) return st;
+    const FfnnDev &f = m->copies[cfg.dtype].ffnn;
+    const int N = f.widths[0];
+    const size_t lds = sample_lds_bytes(cfg.dtype, N, f.m1p, f.m2p);
+    if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too large for the LDS-resident sampler");
+    if (cfg.init_chains) {
+        st = launch_init_chains(chain_state, cfg.n_chains, N, cfg.move, cfg.seed, cfg.instance_id, cfg.chain_id_offset,
+                                stream);
+        if (st != NQS_OK) return st;
+    }
+    FfnnSampleArgs A;
+    A.net = f;
+    A.W2 = cfg.dtype == NQS_F32 ? (const void *)f.W2p : (const void *)f.W2c;
+    A.W1t = cfg.dtype == NQS_F32 ? (const void *)f.W1tp : (const void *)f.W1ct;
+    A.chain_state = chain_state;
+    A.samples = samples;
+    A.logpsi = logpsi;
+    A.n_acc = (unsigned long long *)n_accepted;
+    A.n_chains = cfg.n_chains;
+    A.n_sweeps = cfg.n_sweeps;
+    A.n_burnin = cfg.n_burnin;
+    A.sweep_size = cfg.sweep_size > 0 ? cfg.sweep_size : N;
+    A.refresh_sweeps = cfg.refresh_sweeps > 0 ? cfg.refresh_sweeps : 1;
+    A.move = cfg.move;
+    A.seed = cfg.seed;
+    A.step_offset = cfg.step_offset;
+    A.inst = cfg.instance_id;
+    A.chain_id_offset = (uint32_t)cfg.chain_id_offset;
+    const bool tr = trace && trace->n_chains_traced > 0;
+    A.n_traced = tr ? trace->n_chains_traced : 0;
+    A.tr_site = tr ? trace->site : nullptr;
+    A.tr_ubits = tr ? trace->ubits : nullptr;
+    A.tr_delta = tr ? trace->delta : nullptr;
+    A.tr_acc = tr ? trace->accepted : nullptr;
+    if ((int64_t)(cfg.n_burnin + cfg.n_sweeps) * A.sweep_size == 0) {
+        if (n_accepted) NQS_HIP_TRY(hipMemsetAsync(n_accepted, 0, sizeof(uint64_t) * cfg.n_chains, stream));
+        return NQS_OK;
+    }
+    const int QK = (f.m1p + 63) / 64;
+    const int64_t blocks = (cfg.n_chains + kRows - 1) / kRows;
+    return ffnn_sample_dispatch(cfg.dtype, QK, tr, A, (int)blocks, lds, stream);
+}
+
+nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
+                             double *eloc, hipStream_t stream)
+{
+    nqs_status st = ffnn_mc_ready(m, dtype, stream);
+    if (st != NQS_OK) return st;
+    const FfnnDev &f = m->copies[dtype].ffnn;
+    const int N = f.widths[0];
+    size_t lds;
+    if (dtype == NQS_F32) lds = ffnn_eloc_lds_bytes<float>(N, f.m1p, f.m2p);
+    else if (dtype == NQS_F16) lds = ffnn_eloc_lds_bytes<_Float16>(N, f.m1p, f.m2p);
+    else lds = ffnn_eloc_lds_bytes<__bf16>(N, f.m1p, f.m2p);
+    if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too large for the local-energy kernel");
+    if (m->desc.marshall && (m->desc.lat_dim != ham.dim || m->desc.lat_L != ham.L))
+        return set_error(NQS_EINVAL, "Marshall lattice differs from the Hamiltonian lattice");
+    FfnnElocArgs A;
+    A.net = f;
+    A.W2 = dtype == NQS_F32 ? (const void *)f.W2p : (const void *)f.W2c;
+    A.W1t = dtype == NQS_F32 ? (const void *)f.W1tp : (const void *)f.W1ct;
+    A.samples = samples;
+    A.n = n;
+    A.kind = ham.kind;
+    A.dim = ham.dim;
+    A.L = ham.L;
+    A.pbc = ham.pbc;
+    A.marshall = m->desc.marshall;
+    A.J = ham.J;
+    A.h = ham.h;
+    A.eloc = eloc;
+    const int QK = (f.m1p + 63) / 64;
+    const int blocks = (int)std::min<int64_t>(n, 256 * 4);
+    return ffnn_eloc_dispatch(dtype, QK, A, blocks, lds, stream);
 }
 
 }  // namespace nqs

@@ -26,9 +26,10 @@ nqs_status hip_error(hipError_t e, const char *what);
 struct RbmDev {
     int N = 0, M = 0;
     float *a = nullptr;       // [N]
+    float *a2 = nullptr;      // [N]      4 a_i / ln 2 (the visible-bias term of a flip in log2 units)
     float *b = nullptr;       // [M]
     float *Wt = nullptr;      // [N][M]   Wt[i][j] = W[j][i]
-    float2 *CS = nullptr;     // [N][M]   (cosh 2W[j][i], sinh 2W[j][i]) at [i][j]
+    float2 *CS = nullptr;     // [N*M+1]  (cosh 2W[j][i], sinh 2W[j][i]) at [i][j]; entry N*M = (1, 0)
     float2 *CSt = nullptr;    // [M][N]   the same pairs at [j][i]
     float max_abs_w = 0.0f;
 };
@@ -40,9 +41,14 @@ struct FfnnDev {
     float *W[NQS_MAX_LAYERS] = {nullptr};  // [w_l][w_{l-1}] FP32 values of the rounded weights
     float *Wt[NQS_MAX_LAYERS] = {nullptr}; // [w_{l-1}][w_l]
     float *b[NQS_MAX_LAYERS] = {nullptr};
-    void *Wlp[NQS_MAX_LAYERS] = {nullptr}; // raw 16-bit / 8-bit codes for the matrix cores, [w_l][w_{l-1}]
-    float wscale[NQS_MAX_LAYERS] = {0};    // FP8 per-layer weight scales (value = code * scale)
-    float ascale[NQS_MAX_LAYERS] = {0};    // FP8 per-layer activation scales
+    // matrix-core path of a two-layer network (w1 padded to m1p, w2 to m2p)
+    int m1p = 0, m2p = 0;
+    uint16_t *W2c = nullptr;               // [m2p][m1p] raw bf16/f16 codes of layer 2
+    uint16_t *W1ct = nullptr;              // [N][m1p]   raw codes of layer 1, transposed
+    float *W2p = nullptr;                  // [m2p][m1p] FP32 values of layer 2
+    float *W1tp = nullptr;                 // [N][m1p]   FP32 values of layer 1, transposed
+    float *b1p = nullptr;                  // [m1p]
+    float *b2p = nullptr;                  // [m2p]
 };
 
 struct Copy {
@@ -65,6 +71,15 @@ struct nqs_model {
 
 namespace nqs {
 
+// Kernels that take more than 64 KiB of dynamic LDS must say so before launch.
+template <typename Kern>
+static inline void allow_lds(Kern k, size_t bytes)
+{
+    if (bytes > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+
 // Per-device growable scratch (never shrinks; freed at process exit).
 void *workspace(size_t bytes, hipStream_t stream);
 
@@ -79,6 +94,32 @@ nqs_status launch_downcast(const double *src, int64_t n, int dtype, float *dst, 
 nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream);
 nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
                       float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
+
+// Sampler launch (one translation unit per lanes-per-chain G).
+struct RbmSampleArgs {
+    RbmDev net;
+    int8_t *chain_state;
+    int8_t *samples;
+    float *logpsi;
+    unsigned long long *n_acc;
+    int64_t n_chains;
+    int n_sweeps, n_burnin, sweep_size, refresh_sweeps;
+    uint64_t seed, step_offset;
+    uint32_t inst, chain_id_offset;
+    int n_traced;
+    int32_t *tr_site;
+    uint32_t *tr_ubits;
+    float *tr_delta;
+    uint8_t *tr_acc;
+};
+struct RbmLaunch {
+    int K, threads, blocks;
+    bool lds, trace;
+    size_t lds_bytes;
+};
+nqs_status rbm_sample_launch_g16(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s);
+nqs_status rbm_sample_launch_g32(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s);
+nqs_status rbm_sample_launch_g64(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s);
 nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
                             double *eloc, hipStream_t stream);
 nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,

@@ -25,14 +25,16 @@ namespace nqs {
 // ---------------------------------------------------------------------------
 // Copy builder: round the FP64 master to `dtype` and derive the tables.
 // ---------------------------------------------------------------------------
-__global__ void rbm_build_kernel(const double *__restrict__ master, int N, int M, int dtype, float *a, float *b,
-                                 float *Wt, float2 *CS, float2 *CSt, unsigned int *max_abs_bits)
+__global__ void rbm_build_kernel(const double *__restrict__ master, int N, int M, int dtype, float *a, float *a2,
+                                 float *b, float *Wt, float2 *CS, float2 *CSt, unsigned int *max_abs_bits)
 {
     const int64_t P = (int64_t)N + M + (int64_t)M * N;
+    if (blockIdx.x == 0 && threadIdx.x == 0) CS[(int64_t)N * M] = make_float2(1.0f, 0.0f);   // neutral entry
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         const double v = round_to_dtype(master[p], dtype);
         if (p < N) {
             a[p] = (float)v;
+            a2[p] = (float)(4.0 * v / 0.69314718055994530942);
         } else if (p < N + M) {
             b[p - N] = (float)v;
         } else {
@@ -53,7 +55,7 @@ nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream)
     Copy &c = m->copies[dtype];
     const int N = m->desc.n_visible, M = m->desc.widths[0];
     const size_t nW = (size_t)N * M;
-    const size_t bytes = sizeof(float) * (N + M + nW) + sizeof(float2) * 2 * nW + 256 * 4;
+    const size_t bytes = sizeof(float) * (2 * N + M + nW) + sizeof(float2) * (2 * nW + 1) + 256 * 8;
     if (!c.block) {
         NQS_HIP_TRY(hipMalloc(&c.block, bytes));
     }
@@ -66,17 +68,18 @@ nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream)
     RbmDev &r = c.rbm;
     r.N = N;
     r.M = M;
-    r.CS = (float2 *)carve(sizeof(float2) * nW);
+    r.CS = (float2 *)carve(sizeof(float2) * (nW + 1));
     r.CSt = (float2 *)carve(sizeof(float2) * nW);
     r.Wt = (float *)carve(sizeof(float) * nW);
     r.a = (float *)carve(sizeof(float) * N);
+    r.a2 = (float *)carve(sizeof(float) * N);
     r.b = (float *)carve(sizeof(float) * M);
     unsigned int *mx = (unsigned int *)carve(sizeof(unsigned int));
-    if ((size_t)(base - (char *)c.block) > bytes + 6 * 256) return set_error(NQS_EDEVICE, "internal layout overflow");
+    if ((size_t)(base - (char *)c.block) > bytes) return set_error(NQS_EDEVICE, "internal layout overflow");
     NQS_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(unsigned int), stream));
     const int64_t P = (int64_t)N + M + (int64_t)nW;
     const int blocks = (int)std::min<int64_t>((P + 255) / 256, 4096);
-    hipLaunchKernelGGL(rbm_build_kernel, dim3(blocks), dim3(256), 0, stream, m->master, N, M, dtype, r.a, r.b, r.Wt,
+    hipLaunchKernelGGL(rbm_build_kernel, dim3(blocks), dim3(256), 0, stream, m->master, N, M, dtype, r.a, r.a2, r.b, r.Wt,
                        r.CS, r.CSt, mx);
     NQS_HIP_TRY(hipGetLastError());
     unsigned int mbits = 0;
@@ -93,244 +96,20 @@ nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream)
 // [e^{-2|W|}, e^{2|W|}]) stays inside the FP32 range.
 constexpr float kMaxAbsW = 5.0f;
 
-// ---------------------------------------------------------------------------
-// Sampler: one chain per group of G lanes; lane g of the group owns hidden
-// units j = g, g+G, ..., (K per lane) and spin word g (32 spins per word).
-// The (C,S) table lives in LDS when it fits, else it is read through L2.
-// ---------------------------------------------------------------------------
-struct RbmSampleArgs {
-    RbmDev net;
-    int8_t *chain_state;
-    int8_t *samples;
-    float *logpsi;
-    unsigned long long *n_acc;
-    int64_t n_chains;
-    int n_sweeps, n_burnin, sweep_size, refresh_sweeps;
-    uint64_t seed, step_offset;
-    uint32_t inst, chain_id_offset;
-    int n_traced;
-    int32_t *tr_site;
-    uint32_t *tr_ubits;
-    float *tr_delta;
-    uint8_t *tr_acc;
-};
-
-// theta = W s + b from scratch; sets t = tanh theta, returns log psi (FP32).
-template <int G, int K>
-__device__ __forceinline__ float rbm_refresh(const RbmDev &net, uint32_t word, int gl, float (&t)[K])
-{
-    const int N = net.N, M = net.M;
-    float th[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int j = gl + k * G;
-        th[k] = j < M ? net.b[j] : 0.0f;
-    }
-    float as = 0.0f;
-    const int NW = (N + 31) >> 5;
-    for (int w = 0; w < NW; ++w) {
-        const uint32_t bits = group_bcast<G>(word, w);
-        const int i0 = w << 5;
-        const int nb = min(32, N - i0);
-        for (int bb = 0; bb < nb; ++bb) {
-            const int i = i0 + bb;
-            const float s = ((bits >> bb) & 1u) ? 1.0f : -1.0f;
-            as = fmaf(net.a[i], s, as);
-            const float *wrow = net.Wt + (size_t)i * M;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int j = gl + k * G;
-                if (j < M) th[k] = fmaf(wrow[j], s, th[k]);
-            }
-        }
-    }
-    float lc = 0.0f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int j = gl + k * G;
-        if (j < M) {
-            t[k] = tanhf(th[k]);
-            lc += logcosh_f32(th[k]);
-        } else {
-            t[k] = 0.0f;
-        }
-    }
-    return as + group_sum<G>(lc);
-}
-
-template <int G, int K, bool LDS_TAB, bool TRACE>
-__global__ void __launch_bounds__(1024) rbm_sample_kernel(RbmSampleArgs A)
-{
-    extern __shared__ float2 s_tab[];
-    const int N = A.net.N, M = A.net.M;
-    if constexpr (LDS_TAB) {
-        const int total = N * M;
-        const float4 *src = reinterpret_cast<const float4 *>(A.net.CS);
-        float4 *dst = reinterpret_cast<float4 *>(s_tab);
-        for (int k = threadIdx.x; k < total / 2; k += blockDim.x) dst[k] = src[k];
-        if ((total & 1) && threadIdx.x == 0) s_tab[total - 1] = A.net.CS[total - 1];
-        __syncthreads();
-    }
-    const int cpb = blockDim.x / G;
-    const int gl = threadIdx.x % G;
-    const int64_t c = (int64_t)blockIdx.x * cpb + threadIdx.x / G;
-    if (c >= A.n_chains) return;   // whole groups leave together; no barrier follows
-
-    const uint32_t gid = A.chain_id_offset + (uint32_t)c;
-    const uint32_t key0 = (uint32_t)A.seed, key1 = (uint32_t)(A.seed >> 32);
-    const int NW = (N + 31) >> 5;
-
-    // spins of this chain: lane g holds bits of sites 32g .. 32g+31
-    uint32_t word = 0;
-    if (gl < NW) {
-        const int8_t *src = A.chain_state + (size_t)c * N + gl * 32;
-        const int nb = min(32, N - gl * 32);
-        for (int bb = 0; bb < nb; ++bb) word |= (src[bb] > 0 ? 1u : 0u) << bb;
-    }
-
-    float t[K];
-    float f = rbm_refresh<G, K>(A.net, word, gl, t);
-
-    const int sw = A.sweep_size;
-    const int64_t total = (int64_t)(A.n_burnin + A.n_sweeps) * sw;
-    unsigned long long acc = 0;
-    int in_sweep = 0;
-    int64_t sweep = 0;
-    const bool want_out = (A.samples != nullptr) || (A.logpsi != nullptr);
-
-    for (int64_t step0 = 0; step0 < total; step0 += G) {
-        // one Philox block per proposal: lane g draws proposal step0 + g of this batch
-        const uint64_t gstep = A.step_offset + (uint64_t)step0 + (uint64_t)gl;
-        const Block4 rb = philox4x32_10((uint32_t)gstep, (uint32_t)(gstep >> 32), gid, A.inst << 8, key0, key1);
-        const uint32_t my_i = (uint32_t)index_from_word(rb.r0, N);
-        const uint32_t my_u = rb.r2 >> 8;
-        const int nprop = (int)min<int64_t>(G, total - step0);
-        for (int p = 0; p < nprop; ++p) {
-            const int i = (int)group_bcast<G>(my_i, p);
-            const uint32_t ub = group_bcast<G>(my_u, p);
-            const uint32_t wbits = group_bcast<G>(word, i >> 5);
-            const float si = ((wbits >> (i & 31)) & 1u) ? 1.0f : -1.0f;
-
-            float cx[K], ss[K], rr[K];
-            float prod = 1.0f;
-            int e2 = 0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int j = gl + k * G;
-                if (j < M) {
-                    float2 cs;
-                    if constexpr (LDS_TAB) cs = s_tab[i * M + j];
-                    else cs = A.net.CS[(size_t)i * M + j];
-                    cx[k] = cs.x;
-                    ss[k] = si * cs.y;
-                    rr[k] = fmaf(-t[k], ss[k], cs.x);
-                    prod *= rr[k];
-                } else {
-                    cx[k] = 1.0f;
-                    ss[k] = 0.0f;
-                    rr[k] = 1.0f;
-                }
-                if ((k & 7) == 7 && k + 1 < K) {
-                    int e;
-                    prod = frexpf(prod, &e);
-                    e2 += e;
-                }
-            }
-            const float lpart = __logf(prod) + (float)e2 * 0.69314718055994531f;
-            const float lsum = group_sum<G>(lpart);
-            const float delta = 2.0f * fmaf(-2.0f * si, A.net.a[i], lsum);
-            const float u = (float)ub * 5.9604644775390625e-8f;   // 2^-24
-            const bool accept = (delta >= 0.0f) || (u < __expf(delta));
-            if (accept) {
-#pragma unroll
-                for (int k = 0; k < K; ++k) t[k] = fmaf(t[k], cx[k], -ss[k]) * __builtin_amdgcn_rcpf(rr[k]);
-                if (gl == (i >> 5)) word ^= 1u << (i & 31);
-                ++acc;
-            }
-            if constexpr (TRACE) {
-                if (c < A.n_traced && gl == 0) {
-                    const size_t idx = (size_t)c * (size_t)total + (size_t)(step0 + p);
-                    A.tr_site[idx] = i | (0xFFFF << 16);
-                    A.tr_ubits[idx] = ub;
-                    A.tr_delta[idx] = delta;
-                    A.tr_acc[idx] = accept ? 1 : 0;
-                }
-            }
-            if (++in_sweep == sw) {
-                in_sweep = 0;
-                const int64_t out = sweep - A.n_burnin;
-                const bool emit = want_out && out >= 0;
-                if (emit || ((sweep + 1) % A.refresh_sweeps) == 0) {
-                    f = rbm_refresh<G, K>(A.net, word, gl, t);
-                    if (emit) {
-                        if (A.samples && gl < NW) {
-                            int8_t *dst = A.samples + ((size_t)out * A.n_chains + c) * N + gl * 32;
-                            const int nb = min(32, N - gl * 32);
-                            for (int bb = 0; bb < nb; ++bb) dst[bb] = ((word >> bb) & 1u) ? 1 : -1;
-                        }
-                        if (A.logpsi && gl == 0) A.logpsi[(size_t)out * A.n_chains + c] = f;
-                    }
-                }
-                ++sweep;
-            }
-        }
-    }
-    if (gl < NW) {
-        int8_t *dst = A.chain_state + (size_t)c * N + gl * 32;
-        const int nb = min(32, N - gl * 32);
-        for (int bb = 0; bb < nb; ++bb) dst[bb] = ((word >> bb) & 1u) ? 1 : -1;
-    }
-    if (A.n_acc && gl == 0) A.n_acc[c] = acc;
-}
-
-template <typename Kern>
-static void allow_lds(Kern k, size_t bytes)
-{
-    if (bytes > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)bytes);
-}
-
-template <int G, int K>
-static void launch_rbm_sample_gk(const RbmSampleArgs &A, bool lds, bool trace, int threads, size_t lds_bytes,
-                                 int blocks, hipStream_t s)
-{
-    if (lds) {
-        allow_lds(rbm_sample_kernel<G, K, true, true>, lds_bytes);
-        allow_lds(rbm_sample_kernel<G, K, true, false>, lds_bytes);
-        if (trace) hipLaunchKernelGGL((rbm_sample_kernel<G, K, true, true>), dim3(blocks), dim3(threads), lds_bytes, s, A);
-        else hipLaunchKernelGGL((rbm_sample_kernel<G, K, true, false>), dim3(blocks), dim3(threads), lds_bytes, s, A);
-    } else {
-        if (trace) hipLaunchKernelGGL((rbm_sample_kernel<G, K, false, true>), dim3(blocks), dim3(threads), 0, s, A);
-        else hipLaunchKernelGGL((rbm_sample_kernel<G, K, false, false>), dim3(blocks), dim3(threads), 0, s, A);
-    }
-}
-
-template <int G>
-static nqs_status launch_rbm_sample_g(const RbmSampleArgs &A, int K, bool lds, bool trace, int threads,
-                                      size_t lds_bytes, int blocks, hipStream_t s)
-{
-    switch (K) {
-    case 1: launch_rbm_sample_gk<G, 1>(A, lds, trace, threads, lds_bytes, blocks, s); break;
-    case 2: launch_rbm_sample_gk<G, 2>(A, lds, trace, threads, lds_bytes, blocks, s); break;
-    case 4: launch_rbm_sample_gk<G, 4>(A, lds, trace, threads, lds_bytes, blocks, s); break;
-    case 8: launch_rbm_sample_gk<G, 8>(A, lds, trace, threads, lds_bytes, blocks, s); break;
-    case 16: launch_rbm_sample_gk<G, 16>(A, lds, trace, threads, lds_bytes, blocks, s); break;
-    case 32: launch_rbm_sample_gk<G, 32>(A, lds, trace, threads, lds_bytes, blocks, s); break;
-    default: return set_error(NQS_EUNSUPPORTED, "hidden width too large for the sampler");
-    }
-    NQS_HIP_TRY(hipGetLastError());
-    return NQS_OK;
-}
-
-static int round_up_pow2(int v)
-{
-    int p = 1;
-    while (p < v) p <<= 1;
-    return p;
-}
-
 constexpr size_t kLdsBytes = 160 * 1024;
+
+static int device_cus()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
 
 nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
                       uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream)
@@ -373,32 +152,34 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
         return NQS_OK;
     }
 
-    // launch shape: lanes per chain G, hidden units per lane K
+    // launch shape: lanes per chain G, hidden units per lane K = ceil(M/G), chains per block
     int G = cfg.lanes_per_chain;
-    if (G == 0) G = M >= 128 ? 64 : (M >= 48 ? 32 : 16);
-    while ((N + 31) / 32 > G && G < 64) G *= 2;   // every spin word needs an owning lane
+    if (G == 0) G = M > 256 ? 64 : (M > 48 ? 32 : 16);
+    auto kmax = [](int g) { return g == 16 ? 13 : 16; };
+    while (G < 64 && ((N + 31) / 32 > G || (M + G - 1) / G > kmax(G))) G *= 2;   // spin words and hidden units fit
     if ((N + 31) / 32 > G) return set_error(NQS_EUNSUPPORTED, "too many sites for the sampler");
-    const int K = round_up_pow2((M + G - 1) / G);
-    if (K > 32) return set_error(NQS_EUNSUPPORTED, "hidden width too large for this lanes_per_chain");
-    const size_t tab_bytes = sizeof(float2) * (size_t)N * M;
+    const int K = (M + G - 1) / G;
+    if (K > kmax(G)) return set_error(NQS_EUNSUPPORTED, "hidden width too large for the sampler (M <= 1024)");
+    const size_t tab_bytes = sizeof(float2) * ((size_t)N * M + 1);
     const bool lds = tab_bytes <= kLdsBytes;
-    int threads;
-    if (lds) {
-        // chains sharing one LDS copy: as many as one CU can hold without starving occupancy
-        const int blocks_per_cu = (int)std::max<size_t>(1, kLdsBytes / std::max<size_t>(tab_bytes, 1));
-        threads = blocks_per_cu >= 4 ? 256 : (blocks_per_cu >= 2 ? 512 : 1024);
-    } else {
-        threads = 256;
-    }
-    const int cpb = threads / G;
+    // one LDS copy of the table per block; spread the chains over every CU
+    const int max_threads = G == 16 ? 256 : (G == 32 ? 512 : 1024);
+    const int blocks_per_cu = lds ? (int)std::max<size_t>(1, std::min<size_t>(8, kLdsBytes / tab_bytes)) : 8;
+    const int64_t slots = (int64_t)device_cus() * blocks_per_cu;
+    const int cpb = (int)std::min<int64_t>(max_threads / G, std::max<int64_t>(1, (cfg.n_chains + slots - 1) / slots));
     const int64_t blocks64 = (cfg.n_chains + cpb - 1) / cpb;
     if (blocks64 > INT32_MAX) return set_error(NQS_EINVAL, "too many chains");
-    const int blocks = (int)blocks64;
-    const size_t lds_bytes = lds ? tab_bytes : 0;
+    RbmLaunch L;
+    L.K = K;
+    L.threads = cpb * G;
+    L.blocks = (int)blocks64;
+    L.lds = lds;
+    L.trace = tr;
+    L.lds_bytes = lds ? tab_bytes : 0;
     switch (G) {
-    case 16: return launch_rbm_sample_g<16>(A, K, lds, tr, threads, lds_bytes, blocks, stream);
-    case 32: return launch_rbm_sample_g<32>(A, K, lds, tr, threads, lds_bytes, blocks, stream);
-    default: return launch_rbm_sample_g<64>(A, K, lds, tr, threads, lds_bytes, blocks, stream);
+    case 16: return rbm_sample_launch_g16(A, L, stream);
+    case 32: return rbm_sample_launch_g32(A, L, stream);
+    default: return rbm_sample_launch_g64(A, L, stream);
     }
 }
 

@@ -1,0 +1,214 @@
+"""GPU parity of the dense-network path (exchange/flip MH on the matrix cores,
+Heisenberg/TFIM local energies with the Marshall sign, backward kernel) against
+the CPU oracle.  Every call goes through the C interface."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_20782_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _small_heis(L=4, widths=(24, 12), seed=3, dim=2, scale=1.0):
+    n = L if dim == 1 else L * L
+    return workloads.Workload(f"heis{dim}d_{L}", workloads.Hamiltonian("heisenberg", workloads.Lattice(dim, L), 1.0, 0.0, True),
+                              workloads.Model("ffnn", n, widths), n_chains=1, n_sweeps=1, n_burnin=0,
+                              move="exchange", seed=seed), scale
+
+
+def _run(nqs, model, cfg, N, trace_chains=0):
+    state = torch.zeros(cfg.n_chains, N, dtype=torch.int8, device=DEV)
+    samples = torch.empty(cfg.n_sweeps, cfg.n_chains, N, dtype=torch.int8, device=DEV)
+    logpsi = torch.empty(cfg.n_sweeps, cfg.n_chains, dtype=torch.float32, device=DEV)
+    acc = torch.empty(cfg.n_chains, dtype=torch.int64, device=DEV)
+    tr = None
+    total = (cfg.n_sweeps + cfg.n_burnin) * (cfg.sweep_size or N)
+    if trace_chains:
+        tr = {"n": trace_chains,
+              "site": torch.empty(trace_chains * total, dtype=torch.int32, device=DEV),
+              "ubits": torch.empty(trace_chains * total, dtype=torch.int32, device=DEV),
+              "delta": torch.empty(trace_chains * total, dtype=torch.float32, device=DEV),
+              "accepted": torch.empty(trace_chains * total, dtype=torch.uint8, device=DEV)}
+    nqs.nqs_sample(model, cfg, state, samples, logpsi, acc, trace=tr)
+    torch.cuda.synchronize()
+    out = {"state": state.cpu().numpy(), "samples": samples.cpu().numpy(), "logpsi": logpsi.cpu().numpy(),
+           "acc": acc.cpu().numpy()}
+    if tr:
+        for k in ("site", "ubits", "delta", "accepted"):
+            out["tr_" + k] = tr[k].cpu().numpy().reshape(trace_chains, total)
+    return out
+
+
+def test_exchange_init_states_match_oracle(nqs):
+    N = 100
+    p = workloads.ffnn_params(N, (16, 8), 1)
+    model = nqs.Model("ffnn", N, (16, 8), p)
+    cfg = nqs.SampleConfig(n_chains=150, n_sweeps=0, n_burnin=0, seed=77, move="exchange")
+    r = _run(nqs, model, cfg, N)
+    ref = np.array([oracle.init_chain(N, "exchange", 77, c) for c in range(150)])
+    assert np.array_equal(r["state"], ref)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "f32"])
+def test_cfg3_shape_exchange_replay(nqs, dtype):
+    """10x10 Heisenberg, FFNN 100 -> 400 -> 200, exchange moves: replay every traced decision in FP64."""
+    wl = workloads.cfg3_heis_10x10()
+    _say(f"cfg3 replay {dtype}")
+    params = workloads.params_for(wl)
+    N = wl.model.n_visible
+    C, S, B, T = 128, 3, 2, 16
+    model = nqs.Model.from_workload(wl, params)
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=wl.seed, dtype=dtype, move="exchange")
+    r = _run(nqs, model, cfg, N, trace_chains=T)
+    assert np.all(r["samples"].sum(axis=2) == 0)   # zero magnetisation is conserved
+    om = oracle.model_from_workload(wl, params, dtype)
+    ocfg = oracle.make_cfg(C, S, B, move="exchange", seed=wl.seed)
+    starts = np.array([oracle.init_chain(N, "exchange", wl.seed, c) for c in range(T)])
+    res = oracle.replay(om, ocfg, list(range(T)), starts, r["tr_site"], r["tr_ubits"].view(np.uint32),
+                        r["tr_delta"], r["tr_accepted"], tau_rel=1e-5)
+    _say(f"  replay: {res['decisions_equal']} equal, {res['near_ties']} near ties, "
+         f"max |dDelta| {res['max_delta_err']:.2e}")
+    assert res["site_u_mismatch"] == 0
+    assert res["decision_mismatch"] == 0
+    assert np.array_equal(res["end_states"], r["state"][:T])
+    f, _ = om.logamp(r["samples"].reshape(-1, N))
+    lp = r["logpsi"].ravel()
+    assert np.max(np.abs(lp - f) / np.maximum(1.0, np.abs(f))) < 1e-5
+
+
+def test_flip_moves_replay_tfim(nqs):
+    """FFNN with single-flip moves on a 1D TFIM chain (rank-1 first-layer update)."""
+    N = 20
+    p = workloads.ffnn_params(N, (40, 24), 5, bias_std=0.2)
+    model = nqs.Model("ffnn", N, (40, 24), p)
+    C, S, B, T = 80, 5, 3, 10
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=4, dtype="f32", move="flip")
+    r = _run(nqs, model, cfg, N, trace_chains=T)
+    om = oracle.OracleModel("ffnn", N, (40, 24), oracle.round_to(p, "f32"), act_dtype="f32")
+    ocfg = oracle.make_cfg(C, S, B, move="flip", seed=4)
+    starts = np.array([oracle.init_chain(N, "flip", 4, c) for c in range(T)])
+    res = oracle.replay(om, ocfg, list(range(T)), starts, r["tr_site"], r["tr_ubits"].view(np.uint32),
+                        r["tr_delta"], r["tr_accepted"], tau_rel=1e-5)
+    assert res["site_u_mismatch"] == 0 and res["decision_mismatch"] == 0
+    # free-running trajectories equal the oracle sampler's
+    st, smp, _, acc = oracle.sample(om, ocfg)
+    assert np.array_equal(r["samples"], smp)
+
+
+def test_exchange_exact_pi_small(nqs):
+    """1D Heisenberg N=8, zero-magnetisation sector: device histogram vs exact |psi|^2."""
+    import scipy.stats
+    n = 8
+    p = 0.5 * workloads.ffnn_params(n, (12, 6), 31, bias_std=0.3)
+    model = nqs.Model("ffnn", n, (12, 6), p, marshall=True, lat_dim=1, lat_L=n)
+    cfg = nqs.SampleConfig(n_chains=2048, n_sweeps=60, n_burnin=10, seed=5, move="exchange", dtype="f32")
+    r = _run(nqs, model, cfg, n)
+    om = oracle.OracleModel("ffnn", n, (12, 6), oracle.round_to(p, "f32"), act_dtype="f32", marshall=True,
+                            lattice=workloads.Lattice(1, n))
+    pi, _, _ = exact.enumerate_pi(om)
+    cfgs = exact.all_configs(n)
+    sector = cfgs.sum(axis=1) == 0
+    ps = np.where(sector, pi, 0.0)
+    ps /= ps.sum()
+    idx = np.sum((r["samples"].reshape(-1, n) > 0).astype(np.int64) << np.arange(n), axis=1)
+    counts = np.bincount(idx, minlength=2 ** n)[sector]
+    e = ps[sector] * counts.sum()
+    chi2 = np.sum((counts - e) ** 2 / e)
+    assert scipy.stats.chi2.sf(chi2, sector.sum() - 1) > 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_local_energy_heisenberg_cfg3_shape(nqs, dtype):
+    wl = workloads.cfg3_heis_10x10()
+    _say(f"eloc heisenberg {dtype}")
+    params = workloads.params_for(wl)
+    model = nqs.Model.from_workload(wl, params)
+    smp = workloads.random_spins(37, 100, 9, zero_mag=True)
+    el = torch.empty(37, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(wl.ham), torch.from_numpy(smp).to(DEV), el, dtype)
+    ref = oracle.local_energy(oracle.model_from_workload(wl, params, dtype), wl.ham, smp)
+    got = el.cpu().numpy()
+    # ratios exp(f' - f) carry FP32 errors of |f| * 2^-22 in the exponent
+    f, _ = oracle.model_from_workload(wl, params, dtype).logamp(smp)
+    scale = np.abs(ref) + 2 * 200 + 2 * 200 * np.exp(1.0)
+    tol = 4e-6 * np.maximum(1.0, np.abs(f)) * scale
+    assert np.all(np.abs(got - ref) < tol)
+
+
+@pytest.mark.parametrize("kind,dim,L,marshall", [("heisenberg", 2, 4, True), ("heisenberg", 1, 12, True),
+                                                 ("tfim", 1, 14, False), ("tfim", 2, 4, False), ("heisenberg", 2, 4, False)])
+def test_local_energy_small_lattices(nqs, kind, dim, L, marshall):
+    n = L if dim == 1 else L * L
+    widths = (3 * n, n)
+    p = workloads.ffnn_params(n, widths, 17, bias_std=0.1)
+    model = nqs.Model("ffnn", n, widths, p, marshall=marshall, lat_dim=dim, lat_L=L)
+    ham = workloads.Hamiltonian(kind, workloads.Lattice(dim, L), 0.9, 1.3 if kind == "tfim" else 0.0, marshall)
+    smp = workloads.random_spins(50, n, 2, zero_mag=(kind == "heisenberg"))
+    el = torch.empty(50, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(ham), torch.from_numpy(smp).to(DEV), el, "f32")
+    om = oracle.OracleModel("ffnn", n, widths, oracle.round_to(p, "f32"), act_dtype="f32", marshall=marshall,
+                            lattice=workloads.Lattice(dim, L))
+    ref = oracle.local_energy(om, ham, smp)
+    assert np.allclose(el.cpu().numpy(), ref, rtol=2e-5, atol=2e-5)
+
+
+def test_exact_energy_heisenberg_enumeration(nqs):
+    """sum_x pi(x) eps(x) on the 4x4 lattice (sector) equals the oracle's exact energy."""
+    n, L = 16, 4
+    widths = (48, 16)
+    p = 0.7 * workloads.ffnn_params(n, widths, 23, bias_std=0.1)
+    model = nqs.Model("ffnn", n, widths, p, marshall=True, lat_dim=2, lat_L=L)
+    ham = workloads.Hamiltonian("heisenberg", workloads.Lattice(2, L), 1.0, 0.0, True)
+    cfgs = exact.all_configs(n)
+    sec = cfgs[cfgs.sum(axis=1) == 0]
+    el = torch.empty(sec.shape[0], dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(ham), torch.from_numpy(sec).to(DEV), el, "f32")
+    om = oracle.OracleModel("ffnn", n, widths, oracle.round_to(p, "f32"), act_dtype="f32", marshall=True,
+                            lattice=workloads.Lattice(2, L))
+    f, _ = om.logamp(sec)
+    w = np.exp(2 * (f - f.max()))
+    w /= w.sum()
+    e_dev = float(np.sum(w * el.cpu().numpy()))
+    e0, _ = exact.ground_state("heisenberg", 2, L, 1.0)
+    assert e_dev >= e0 - 1e-6
+    e_ref = float(np.sum(w * oracle.local_energy(om, ham, sec)))
+    assert abs(e_dev - e_ref) < 1e-5 * abs(e_ref)
+
+
+@pytest.mark.parametrize("widths,n,N", [((400, 200), 9, 100), ((12, 7, 5), 13, 10), ((33,), 6, 8)])
+def test_ffnn_logpsi_grad_matches_oracle(nqs, widths, n, N):
+    p = workloads.ffnn_params(N, widths, 8, bias_std=0.1)
+    model = nqs.Model("ffnn", N, widths, p)
+    smp = workloads.random_spins(n, N, 12)
+    st = torch.from_numpy(smp).to(DEV)
+    P = model.n_params
+    lp = torch.empty(n, dtype=torch.float32, device=DEV)
+    O = torch.empty(n, P, dtype=torch.float32, device=DEV)
+    nqs.nqs_logpsi_grad(model, st, logpsi=lp, O=O)
+    om = oracle.OracleModel("ffnn", N, widths, oracle.round_to(p, "f32"), act_dtype="f32")
+    rlp, rO = oracle.logpsi_grad(om, smp)
+    assert np.max(np.abs(lp.cpu().numpy() - rlp) / np.maximum(1, np.abs(rlp))) < 1e-5
+    got = O.cpu().numpy()
+    assert np.max(np.abs(got - rO) / np.maximum(1.0, np.abs(rO))) < 2e-5
+    g = np.random.default_rng(2).normal(size=n).astype(np.float32)
+    vo = torch.empty(P, dtype=torch.float32, device=DEV)
+    nqs.nqs_logpsi_grad(model, st, vjp_in=torch.from_numpy(g).to(DEV), vjp_out=vo)
+    assert np.allclose(vo.cpu().numpy(), g.astype(np.float64) @ rO, rtol=1e-4, atol=1e-4)
