@@ -154,6 +154,26 @@ nqs_status nqs_downcast(const double *src, int64_t n, int32_t dtype, float *dst,
 nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_state, int8_t *samples,
                       float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, void *stream);
 
+/* One sampling job of a batch: a model, its configuration and its buffers
+ * (same meaning as the arguments of nqs_sample). */
+typedef struct {
+    nqs_model *model;
+    nqs_sample_cfg cfg;
+    int8_t *chain_state;
+    int8_t *samples;
+    float *logpsi;
+    uint64_t *n_accepted;
+} nqs_sample_job;
+
+/* Sample many independent instances (RBM, single flips) of uneven sizes.
+ *   mode 0: one persistent launch; work items of 4 chains are sorted by
+ *           decreasing cost and taken from a shared counter.
+ *   mode 1: one launch per job, in order, on `stream`.
+ * Both modes produce identical samples (64 lanes per chain).  The batch
+ * descriptors are staged in the library workspace; the call synchronises
+ * `stream` once before launching. */
+nqs_status nqs_sample_batched(const nqs_sample_job *jobs, int32_t n_jobs, int32_t mode, void *stream);
+
 /* Local energies eps[n_samples] (FP64 sums of FP32 amplitude ratios computed
  * from the `eval_dtype` copy of the parameters: NQS_F32 by default). */
 nqs_status nqs_local_energy(nqs_model *m, const nqs_ham_desc *ham, const int8_t *samples, int64_t n_samples,

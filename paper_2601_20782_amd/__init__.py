@@ -20,7 +20,7 @@ from . import _abi
 from ._abi import DTYPE_CODES, NqsError, check, load
 
 __all__ = [
-    "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
+    "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
     "nqs_forces", "nqs_gram", "nqs_downcast", "LogPsi", "NqsError", "load",
 ]
 
@@ -184,6 +184,25 @@ def nqs_sample(model: Model, cfg: SampleConfig, chain_state: torch.Tensor, sampl
     c = cfg.to_c()
     check(load().nqs_sample(model.handle, ctypes.byref(c), _ptr(chain_state), _ptr(samples), _ptr(logpsi),
                             _ptr(n_accepted), ctypes.byref(tr) if tr is not None else None, _stream(stream)))
+
+
+def nqs_sample_batched(jobs, mode: int = 0, stream=None) -> None:
+    """Sample many RBM instances; `jobs` is a list of dicts with keys model, cfg, chain_state and
+    optionally samples, logpsi, n_accepted (same meaning as for nqs_sample)."""
+    arr = (_abi.SampleJob * len(jobs))()
+    for k, j in enumerate(jobs):
+        model, cfg = j["model"], j["cfg"]
+        N = model.n_visible
+        assert j["chain_state"].dtype == torch.int8 and j["chain_state"].numel() == cfg.n_chains * N
+        if j.get("samples") is not None:
+            assert j["samples"].numel() == cfg.n_sweeps * cfg.n_chains * N
+        arr[k].model = model.handle.value
+        arr[k].cfg = cfg.to_c()
+        arr[k].chain_state = j["chain_state"].data_ptr()
+        arr[k].samples = j["samples"].data_ptr() if j.get("samples") is not None else None
+        arr[k].logpsi = j["logpsi"].data_ptr() if j.get("logpsi") is not None else None
+        arr[k].n_accepted = j["n_accepted"].data_ptr() if j.get("n_accepted") is not None else None
+    check(load().nqs_sample_batched(arr, len(jobs), mode, _stream(stream)))
 
 
 def nqs_local_energy(model: Model, ham: Hamiltonian, samples: torch.Tensor, eloc: torch.Tensor,

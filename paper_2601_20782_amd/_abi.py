@@ -19,7 +19,8 @@ DTYPE_CODES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "e4m3": FP8_E4M
 # every function include/nqs.h declares
 EXPORTS = [
     "nqs_model_create", "nqs_model_set_params", "nqs_model_set_params_device", "nqs_model_destroy",
-    "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_local_energy", "nqs_energy_stats",
+    "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched",
+    "nqs_local_energy", "nqs_energy_stats",
     "nqs_logpsi_grad", "nqs_forces", "nqs_gram", "nqs_last_error", "nqs_version",
 ]
 
@@ -41,6 +42,11 @@ class SampleCfg(ctypes.Structure):
                 ("init_chains", ctypes.c_int32), ("seed", ctypes.c_uint64), ("step_offset", ctypes.c_uint64),
                 ("instance_id", ctypes.c_uint32), ("chain_id_offset", ctypes.c_int64),
                 ("lanes_per_chain", ctypes.c_int32), ("refresh_sweeps", ctypes.c_int32)]
+
+
+class SampleJob(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_void_p), ("cfg", SampleCfg), ("chain_state", ctypes.c_void_p),
+                ("samples", ctypes.c_void_p), ("logpsi", ctypes.c_void_p), ("n_accepted", ctypes.c_void_p)]
 
 
 class Trace(ctypes.Structure):
@@ -77,6 +83,7 @@ def load() -> ctypes.CDLL:
         "nqs_model_prepare": ([P, i32, P], st),
         "nqs_downcast": ([P, i64, i32, P, P, P], st),
         "nqs_sample": ([P, P, P, P, P, P, P, P], st),
+        "nqs_sample_batched": ([P, i32, i32, P], st),
         "nqs_local_energy": ([P, P, P, i64, i32, P, P], st),
         "nqs_energy_stats": ([P, i64, i64, P, P], st),
         "nqs_logpsi_grad": ([P, P, i64, P, P, P, P, P], st),

@@ -245,6 +245,15 @@ nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_sta
     return ffnn_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
 }
 
+nqs_status nqs_sample_batched(const nqs_sample_job *jobs, int32_t n_jobs, int32_t mode, void *stream)
+{
+    if (n_jobs < 0) return set_error(NQS_EINVAL, "n_jobs < 0");
+    if (n_jobs == 0) return NQS_OK;
+    if (!jobs) return set_error(NQS_EINVAL, "jobs is NULL");
+    if (mode != 0 && mode != 1) return set_error(NQS_EINVAL, "mode must be 0 (persistent) or 1 (one launch per job)");
+    return rbm_sample_batched(jobs, n_jobs, mode, (hipStream_t)stream);
+}
+
 nqs_status nqs_local_energy(nqs_model *m, const nqs_ham_desc *ham, const int8_t *samples, int64_t n_samples,
                             int32_t eval_dtype, double *eloc, void *stream)
 {

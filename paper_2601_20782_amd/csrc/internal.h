@@ -115,11 +115,13 @@ struct RbmSampleArgs {
 struct RbmLaunch {
     int K, threads, blocks;
     bool lds, trace;
+    int init;              // 1: draw the start states inside the kernel (flip moves)
     size_t lds_bytes;
 };
 nqs_status rbm_sample_launch_g16(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s);
 nqs_status rbm_sample_launch_g32(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s);
 nqs_status rbm_sample_launch_g64(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s);
+nqs_status rbm_sample_batched(const nqs_sample_job *jobs, int n_jobs, int mode, hipStream_t stream);
 nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
                             double *eloc, hipStream_t stream);
 nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,

@@ -120,11 +120,6 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
     if (!(net.max_abs_w <= kMaxAbsW))
         return set_error(NQS_EUNSUPPORTED, "the product-form RBM sampler needs |W| <= 5");
     const int N = net.N, M = net.M;
-    if (cfg.init_chains) {
-        st = launch_init_chains(chain_state, cfg.n_chains, N, cfg.move, cfg.seed, cfg.instance_id,
-                                cfg.chain_id_offset, stream);
-        if (st != NQS_OK) return st;
-    }
     RbmSampleArgs A;
     A.net = net;
     A.chain_state = chain_state;
@@ -148,6 +143,11 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
     A.tr_acc = tr ? trace->accepted : nullptr;
     if ((int64_t)(cfg.n_burnin + cfg.n_sweeps) * A.sweep_size == 0) {
         // nothing to propose: only the initial states (and acceptance counts) are defined
+        if (cfg.init_chains) {
+            st = launch_init_chains(chain_state, cfg.n_chains, N, cfg.move, cfg.seed, cfg.instance_id,
+                                    cfg.chain_id_offset, stream);
+            if (st != NQS_OK) return st;
+        }
         if (n_accepted) NQS_HIP_TRY(hipMemsetAsync(n_accepted, 0, sizeof(uint64_t) * cfg.n_chains, stream));
         return NQS_OK;
     }
@@ -175,6 +175,7 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
     L.blocks = (int)blocks64;
     L.lds = lds;
     L.trace = tr;
+    L.init = cfg.init_chains ? 1 : 0;
     L.lds_bytes = lds ? tab_bytes : 0;
     switch (G) {
     case 16: return rbm_sample_launch_g16(A, L, stream);

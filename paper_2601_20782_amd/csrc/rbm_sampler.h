@@ -133,22 +133,15 @@ __device__ __forceinline__ void load_column(const float2 *__restrict__ tab, int 
     cs[K - 1] = tab[last_ok ? base + (K - 1) * G : last_off];
 }
 
+// Runs chain c on the G lanes of its group (gl = lane in group).  s_tab is the
+// LDS copy of the table when LDS_TAB.  With init, the start state is drawn
+// from the init stream (counter tag 1, spin i = bit i%32 of word i/32) instead
+// of being read from chain_state.
 template <int G, int K, bool LDS_TAB, bool TRACE>
-__global__ void __launch_bounds__(G == 16 ? 256 : (G == 32 ? 512 : 1024)) rbm_sample_kernel(RbmSampleArgs A)
+__device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c, int gl, const float2 *s_tab, bool init)
 {
-    extern __shared__ float2 s_tab[];
     const int N = A.net.N, M = A.net.M;
     const float2 *tab = A.net.CS;
-    if constexpr (LDS_TAB) {
-        const int total = N * M + 1;   // includes the neutral entry
-        for (int k = threadIdx.x; k < total; k += blockDim.x) s_tab[k] = A.net.CS[k];
-        __syncthreads();
-    }
-    const int cpb = blockDim.x / G;
-    const int gl = threadIdx.x % G;
-    const int64_t c = (int64_t)blockIdx.x * cpb + threadIdx.x / G;
-    if (c >= A.n_chains) return;   // whole groups leave together; no barrier follows
-
     const uint32_t gid = A.chain_id_offset + (uint32_t)c;
     const uint32_t key0 = (uint32_t)A.seed, key1 = (uint32_t)(A.seed >> 32);
     const int NW = (N + 31) >> 5;
@@ -157,9 +150,15 @@ __global__ void __launch_bounds__(G == 16 ? 256 : (G == 32 ? 512 : 1024)) rbm_sa
 
     uint32_t word = 0;
     if (gl < NW) {
-        const int8_t *src = A.chain_state + (size_t)c * N + gl * 32;
         const int nb = min(32, N - gl * 32);
-        for (int bb = 0; bb < nb; ++bb) word |= (src[bb] > 0 ? 1u : 0u) << bb;
+        if (init) {
+            const Block4 ib = stream_block(A.seed, (uint64_t)(gl >> 2), gid, A.inst, 1u);
+            const uint32_t r = (gl & 3) == 0 ? ib.r0 : (gl & 3) == 1 ? ib.r1 : (gl & 3) == 2 ? ib.r2 : ib.r3;
+            word = nb == 32 ? r : (r & ((1u << nb) - 1u));
+        } else {
+            const int8_t *src = A.chain_state + (size_t)c * N + gl * 32;
+            for (int bb = 0; bb < nb; ++bb) word |= (src[bb] > 0 ? 1u : 0u) << bb;
+        }
     }
 
     float cc[K], sh[K], lpart;
@@ -295,20 +294,37 @@ __global__ void __launch_bounds__(G == 16 ? 256 : (G == 32 ? 512 : 1024)) rbm_sa
     if (A.n_acc && gl == 0) A.n_acc[c] = acc;
 }
 
+template <int G, int K, bool LDS_TAB, bool TRACE>
+__global__ void __launch_bounds__(G == 16 ? 256 : (G == 32 ? 512 : 1024)) rbm_sample_kernel(RbmSampleArgs A, int init)
+{
+    extern __shared__ float2 s_tab[];
+    const int N = A.net.N, M = A.net.M;
+    if constexpr (LDS_TAB) {
+        const int total = N * M + 1;   // includes the neutral entry
+        for (int k = threadIdx.x; k < total; k += blockDim.x) s_tab[k] = A.net.CS[k];
+        __syncthreads();
+    }
+    const int cpb = blockDim.x / G;
+    const int gl = threadIdx.x % G;
+    const int64_t c = (int64_t)blockIdx.x * cpb + threadIdx.x / G;
+    if (c >= A.n_chains) return;   // whole groups leave together; no barrier follows
+    rbm_run_chain<G, K, LDS_TAB, TRACE>(A, c, gl, s_tab, init != 0);
+}
+
 template <int G, int K>
 static void launch_rbm_sample_gk(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s)
 {
     if (L.lds) {
         if (L.trace) {
             allow_lds(rbm_sample_kernel<G, K, true, true>, L.lds_bytes);
-            hipLaunchKernelGGL((rbm_sample_kernel<G, K, true, true>), dim3(L.blocks), dim3(L.threads), L.lds_bytes, s, A);
+            hipLaunchKernelGGL((rbm_sample_kernel<G, K, true, true>), dim3(L.blocks), dim3(L.threads), L.lds_bytes, s, A, L.init);
         } else {
             allow_lds(rbm_sample_kernel<G, K, true, false>, L.lds_bytes);
-            hipLaunchKernelGGL((rbm_sample_kernel<G, K, true, false>), dim3(L.blocks), dim3(L.threads), L.lds_bytes, s, A);
+            hipLaunchKernelGGL((rbm_sample_kernel<G, K, true, false>), dim3(L.blocks), dim3(L.threads), L.lds_bytes, s, A, L.init);
         }
     } else {
-        if (L.trace) hipLaunchKernelGGL((rbm_sample_kernel<G, K, false, true>), dim3(L.blocks), dim3(L.threads), 0, s, A);
-        else hipLaunchKernelGGL((rbm_sample_kernel<G, K, false, false>), dim3(L.blocks), dim3(L.threads), 0, s, A);
+        if (L.trace) hipLaunchKernelGGL((rbm_sample_kernel<G, K, false, true>), dim3(L.blocks), dim3(L.threads), 0, s, A, L.init);
+        else hipLaunchKernelGGL((rbm_sample_kernel<G, K, false, false>), dim3(L.blocks), dim3(L.threads), 0, s, A, L.init);
     }
 }
 
