@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark of the hot path on one MI355X.
+"""Benchmark of the hot path on one MI355X.  Prints ONE JSON line.
 
-One step = one pass of the whole path over the 10x10 TFIM workload (N = 100,
-RBM alpha = 2, 4096 chains, 100 burn-in + 1000 measured sweeps):
+Default workload (the headline): 2D TFIM 10x10 (N = 100, J = 1, h = 3.04), RBM
+alpha = 2 (M = 200), 4096 chains, 100 burn-in + 1000 measured sweeps.  One step
+is one pass of the whole path:
   downcast of the FP64 master -> chain init + MH sampling -> local energies of
   all 4.096e6 samples -> FP64 energy statistics -> log-derivatives of the last
-  sweep's samples -> FP64 forces -> centred Gram matrix (sample space).
+  sweep's samples -> FP64 forces -> centred Gram matrix in sample space.
 `value` = MH proposals per second of whole-step time with the sampling copy in
-BF16 (inputs resident in HBM).  The same step with an FP32 sampling copy is
-timed beside it, and the energy bias between the two is reported with its
-paired error bar.  The CPU oracle is timed on a bounded sample of the same
+BF16, inputs resident in HBM.  The same step with an FP32 sampling copy is
+timed beside it, and the energy difference between the two is reported with
+its paired error bar.  The CPU oracle is timed on a bounded sample of the same
 workload on the host cores.
 
-Prints ONE JSON line.
+Other workloads (--workload):
+  heis10   2D Heisenberg 10x10, Marshall sign, FFNN 100->400->200, exchange
+           moves, 16384 chains x (50 + 500) sweeps; sampling and local
+           energies in the chosen dtype, O_k of the last sweep, forces.
+  uneven   32 uneven 2D TFIM instances (L in 6..16, h ~ U[2,4], alpha in
+           {1,2,4}), 1024 chains x (20 + 200) sweeps each: one persistent
+           launch, compared with 32 separate launches (plain and graph-replayed).
 """
 from __future__ import annotations
 
@@ -30,7 +37,9 @@ if ROOT not in sys.path:
 
 # MI355X published peaks
 PEAK_FP32_VALU_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+METRIC = "MH proposals/s + E_loc samples/s, BF16 vs FP32 on 1 GPU, at stated dE vs FP64"
 
 
 def _args():
@@ -38,28 +47,60 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven"])
     ap.add_argument("--dtype", default="bf16", choices=["bf16", "f16", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison step")
-    ap.add_argument("--lanes", type=int, default=0, help="lanes per chain of the sampler (0 = library default)")
-    ap.add_argument("--refresh", type=int, default=1, help="sweeps between full recomputes of theta = W s + b")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per chain of the RBM sampler (0 = library default)")
+    ap.add_argument("--refresh", type=int, default=4, help="sweeps between full recomputes of theta = W s + b")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device three times (HBM counter calibration)")
     return ap.parse_args()
 
 
-class Step:
-    """Buffers and phases of one hot-path pass for a sampling dtype."""
+def kernel_traffic(kernel, profile):
+    """HBM bytes per launch of `kernel` from a committed counter summary, or None when the kernel's
+    sources have changed since the counters were taken (the summary records their hash)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    want, files, nbytes = None, [], None
+    for line in open(path):
+        f = line.split()
+        if len(f) >= 4 and f[0] == "source_sha256" and f[1] == kernel:
+            want, files = f[2], f[3].split(",")
+        elif f and not line.startswith("#") and kernel in line and len(f) >= 4:
+            nbytes = float(f[-1])
+    if want is None or nbytes is None:
+        return None
+    h = hashlib.sha256()
+    for name in files:
+        with open(os.path.join(ROOT, "paper_2601_20782_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return nbytes if h.hexdigest() == want else None
 
-    def __init__(self, nqs, torch, wl, params, dtype, lanes=0, refresh=1):
+
+def _events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+class Step:
+    """Buffers and phases of one hot-path pass for one workload and sampling dtype."""
+
+    phase_names = ["downcast", "sample", "local_energy", "stats", "logpsi_grad", "forces", "gram"]
+
+    def __init__(self, nqs, torch, wl, params, dtype, lanes=0, refresh=1, eloc_dtype="f32", with_gram=True):
         self.nqs, self.torch, self.wl, self.dtype = nqs, torch, wl, dtype
+        self.eloc_dtype, self.with_gram = eloc_dtype, with_gram
         dev = torch.device("cuda:0")
-        m = wl.model
-        self.N = N = m.n_visible
+        self.N = N = wl.model.n_visible
         self.C, self.S, self.B = wl.n_chains, wl.n_sweeps, wl.n_burnin
         self.model = nqs.Model.from_workload(wl, params)
         self.master = torch.from_numpy(np.asarray(params, dtype=np.float64)).to(dev)
         self.ham = nqs.Hamiltonian.from_workload(wl.ham)
         self.cfg = nqs.SampleConfig(n_chains=self.C, n_sweeps=self.S, n_burnin=self.B, seed=wl.seed, dtype=dtype,
-                                    lanes_per_chain=lanes, refresh_sweeps=refresh)
+                                    lanes_per_chain=lanes, refresh_sweeps=refresh, move=wl.move)
         self.state = torch.empty(self.C, N, dtype=torch.int8, device=dev)
         self.samples = torch.empty(self.S, self.C, N, dtype=torch.int8, device=dev)
         self.acc = torch.empty(self.C, dtype=torch.int64, device=dev)
@@ -68,12 +109,10 @@ class Step:
         self.P = self.model.n_params
         self.O = torch.empty(self.C, self.P, dtype=torch.float32, device=dev)
         self.F = torch.empty(self.P, dtype=torch.float64, device=dev)
-        self.T = torch.empty(self.C, self.C, dtype=torch.float32, device=dev)
-        self.phase_names = ["downcast", "sample", "local_energy", "stats", "logpsi_grad", "forces", "gram"]
+        self.T = torch.empty(self.C, self.C, dtype=torch.float32, device=dev) if with_gram else None
 
-    def run(self, events=None):
-        nqs, torch = self.nqs, self.torch
-        ev = events
+    def run(self, ev=None):
+        nqs = self.nqs
         k = 0
 
         def mark():
@@ -83,30 +122,30 @@ class Step:
             k += 1
 
         mark()
-        self.model.set_params_device(self.master)          # a1: FP64 master -> sampling copy
+        self.model.set_params_device(self.master)          # FP64 master -> sampling copy
         self.model.prepare(self.dtype)
         mark()
-        nqs.nqs_sample(self.model, self.cfg, self.state, self.samples, None, self.acc)   # a2-a6
+        nqs.nqs_sample(self.model, self.cfg, self.state, self.samples, None, self.acc)
         mark()
-        nqs.nqs_local_energy(self.model, self.ham, self.samples, self.eloc, "f32")       # a7
+        nqs.nqs_local_energy(self.model, self.ham, self.samples, self.eloc, self.eloc_dtype)
         mark()
-        nqs.nqs_energy_stats(self.eloc, self.C, self.stats)                              # a9 (energy)
+        nqs.nqs_energy_stats(self.eloc, self.C, self.stats)
         mark()
-        last = self.samples[self.S - 1]
-        nqs.nqs_logpsi_grad(self.model, last, O=self.O)                                  # a8
+        nqs.nqs_logpsi_grad(self.model, self.samples[self.S - 1], O=self.O)
         mark()
-        nqs.nqs_forces(self.O, self.eloc[(self.S - 1) * self.C:], self.F)                # a9 (forces)
+        nqs.nqs_forces(self.O, self.eloc[(self.S - 1) * self.C:], self.F)
         mark()
-        nqs.nqs_gram(self.O, 1, self.T)                                                  # a9 (T = Obar Obar^T / n)
+        if self.with_gram:
+            nqs.nqs_gram(self.O, 1, self.T)                 # T = Obar Obar^T / n (sample space)
         mark()
 
     def timed(self, steps, warmup):
+        """Mean step time in ms (the larger of the event and wall-clock figures) and per-phase means."""
         torch = self.torch
         for _ in range(warmup):
             self.run()
         torch.cuda.synchronize()
-        n_ev = len(self.phase_names) + 1
-        all_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)] for _ in range(steps)]
+        all_ev = [_events(torch, len(self.phase_names) + 1) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(steps):
@@ -119,7 +158,9 @@ class Step:
             for i, name in enumerate(self.phase_names):
                 phases[name] += ev[i].elapsed_time(ev[i + 1]) / steps
             step_ms.append(ev[0].elapsed_time(ev[-1]))
-        return wall, phases, step_ms
+        if not self.with_gram:
+            phases.pop("gram")
+        return max(float(np.mean(step_ms)), 1e3 * wall / steps), phases
 
 
 def cpu_baseline(wl, params, budget_s=20.0):
@@ -129,22 +170,25 @@ def cpu_baseline(wl, params, budget_s=20.0):
     om = oracle.model_from_workload(wl, params, "f64")
     threads = oracle.num_threads()
     N = wl.model.n_visible
-    # calibrate on a small run, then size the measured run to the time budget
+    # calibrate on a small run, then size the measured runs to the time budget
     c0 = max(threads, 8)
     t = time.perf_counter()
-    oracle.sample(om, oracle.make_cfg(c0, 1, 0, seed=wl.seed))
-    per_prop = (time.perf_counter() - t) / (c0 * N)
+    oracle.sample(om, oracle.make_cfg(c0, 1, 0, move=wl.move, seed=wl.seed))
+    per_prop = max(1e-9, (time.perf_counter() - t) / (c0 * N))
     chains = int(max(threads, min(wl.n_chains, (0.6 * budget_s) / (per_prop * N * 2))))
     sweeps = int(max(2, min(8, (0.6 * budget_s) / (per_prop * N * chains))))
-    cfg = oracle.make_cfg(chains, sweeps, 0, seed=wl.seed)
+    cfg = oracle.make_cfg(chains, sweeps, 0, move=wl.move, seed=wl.seed)
     t = time.perf_counter()
     _, smp, _, _ = oracle.sample(om, cfg)
     ts = time.perf_counter() - t
     props = chains * sweeps * N
-    n_el = max(threads, min(smp.shape[0] * smp.shape[1], int(0.4 * budget_s / (per_prop * N))))
-    flat = smp.reshape(-1, N)[:n_el]
+    flat = smp.reshape(-1, N)
     t = time.perf_counter()
-    oracle.local_energy(om, wl.ham, flat)
+    oracle.local_energy(om, wl.ham, flat[:threads])
+    per_el = max(1e-9, (time.perf_counter() - t) / threads)
+    n_el = int(max(threads, min(flat.shape[0], 0.4 * budget_s / per_el)))
+    t = time.perf_counter()
+    oracle.local_energy(om, wl.ham, flat[:n_el])
     te = time.perf_counter() - t
     return {"value": props / ts, "unit": "proposals/s", "cores": threads, "kind": "oracle",
             "eloc_samples_per_s": n_el / te,
@@ -152,76 +196,172 @@ def cpu_baseline(wl, params, budget_s=20.0):
                       f"local energies of {n_el} samples, {wl.name}"}
 
 
-def main():
-    a = _args()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported (chains shard "
-                                   "by global id, see DESIGN.md)", "n_gpus": a.gpus}))
-        sys.exit(2)
-    import torch
+def _common(a, wl, props, ms, phases, step, data):
+    st = step.stats.cpu().numpy()
+    return {
+        "metric": METRIC, "value": props / (ms * 1e-3), "unit": "proposals/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": a.dtype, "data": data,
+        "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+        "sampler_proposals_per_s": props / (phases["sample"] * 1e-3),
+        "eloc_samples_per_s": wl.n_sweeps * wl.n_chains / (phases["local_energy"] * 1e-3),
+        "acceptance": float(step.acc.sum().item()) / props,
+        "energy": {"mean": st[0], "stderr": st[2], "var": st[1]},
+    }
 
-    import paper_2601_20782_amd as nqs
-    import workloads
 
+def _compare_fp32(a, nqs, torch, wl, params, step, ms, props, eloc_dtype, with_gram):
+    ref = Step(nqs, torch, wl, params, "f32", a.lanes, a.refresh, eloc_dtype="f32", with_gram=with_gram)
+    ms32, ph32 = ref.timed(a.steps, a.warmup)
+    st32 = ref.stats.cpu().numpy()
+    diff = (step.eloc - ref.eloc).contiguous()
+    dstats = torch.empty(4, dtype=torch.float64, device=diff.device)
+    nqs.nqs_energy_stats(diff, wl.n_chains, dstats)
+    d = dstats.cpu().numpy()
+    return {"fp32": {"proposals_per_s": props / (ms32 * 1e-3), "ms_per_step": ms32,
+                     "sampler_proposals_per_s": props / (ph32["sample"] * 1e-3),
+                     "phases_ms": {k: round(v, 3) for k, v in ph32.items()},
+                     "energy": {"mean": st32[0], "stderr": st32[2]}},
+            "speedup_vs_fp32": ms32 / ms,
+            "dE_vs_fp32": {"value": d[0], "stderr_paired": d[2],
+                           "note": "same seeds; chain-mean standard error of the paired local-energy differences; "
+                                   "the FP32 path's accept decisions equal the FP64 oracle's outside near ties"}}
+
+
+def run_tfim10(a, torch, nqs, workloads):
     wl = workloads.cfg2_tfim_10x10()
     params = workloads.params_for(wl)
     N, C, S, B = wl.model.n_visible, wl.n_chains, wl.n_sweeps, wl.n_burnin
-    props = C * (S + B) * N
-
-    main_step = Step(nqs, torch, wl, params, a.dtype, a.lanes, a.refresh)
-    wall, phases, step_ms = main_step.timed(a.steps, a.warmup)
-    ms = max(float(np.mean(step_ms)), 1e3 * wall / a.steps)
-    st = main_step.stats.cpu().numpy()
-    acc_rate = float(main_step.acc.sum().item()) / props
-
-    # roofline of the dominant kernel (the sampler): FP32 VALU work of the
-    # product-form single flip, per proposal: 3M flops (one FMA + one multiply
-    # per hidden unit), 4M flops per accepted proposal (tanh update), and the
-    # per-sweep refresh theta = W s + b (2 N M flops per N proposals).
     M = wl.model.widths[0]
-    flops = props * (3.0 * M + 4.0 * M * acc_rate + 2.0 * M)
-    sample_ms = phases["sample"]
-    achieved = flops / (sample_ms * 1e-3) / 1e12
-    roof = {"kernel": "rbm_sample_kernel", "bound": "alu", "achieved": round(achieved, 2),
-            "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
-            "traffic": None}
-
-    out = {
-        "metric": "MH proposals/s + E_loc samples/s, BF16 vs FP32 on 1 GPU, at stated dE vs FP64",
-        "value": props / (ms * 1e-3), "unit": "proposals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": a.dtype, "data": "synthetic (seeded random RBM weights, N(0, 0.02^2))",
-        "config": {"workload": wl.name, "lattice": "10x10 periodic", "J": 1.0, "h": 3.04, "rbm_hidden": M,
-                   "chains": C, "sweeps": S, "burnin": B, "proposals_per_step": props,
-                   "samples_per_step": S * C, "parallelism": "single GPU"},
-        "phases_ms": {k: round(v, 3) for k, v in phases.items()},
-        "sampler_proposals_per_s": props / (sample_ms * 1e-3),
-        "eloc_samples_per_s": S * C / (phases["local_energy"] * 1e-3),
-        "acceptance": acc_rate,
-        "energy": {"mean": st[0], "stderr": st[2], "var": st[1]},
-        "roofline": roof,
-    }
-
+    props = C * (S + B) * N
+    step = Step(nqs, torch, wl, params, a.dtype, a.lanes, a.refresh)
+    ms, phases = step.timed(a.steps, a.warmup)
+    out = _common(a, wl, props, ms, phases, step, "synthetic (seeded random RBM weights, N(0, 0.02^2))")
+    out["config"] = {"workload": wl.name, "lattice": "10x10 periodic", "J": 1.0, "h": 3.04, "rbm_hidden": M,
+                     "chains": C, "sweeps": S, "burnin": B, "proposals_per_step": props, "samples_per_step": S * C,
+                     "refresh_sweeps": a.refresh, "lanes_per_chain": a.lanes or "default",
+                     "parallelism": "single GPU"}
+    # FP32-VALU work of the product-form single flip: 3M per proposal (ratio
+    # factors), 4M per accepted proposal (state update), and the refresh
+    # theta = W s + b (2 N M flops every `refresh` sweeps of N proposals).
+    acc = out["acceptance"]
+    fpp = 3.0 * M + 4.0 * M * acc + 2.0 * M / a.refresh
+    achieved = props * fpp / (phases["sample"] * 1e-3) / 1e12
+    out["roofline"] = {"kernel": "rbm_sample_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                       "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
+                       "traffic": kernel_traffic("rbm_sample_kernel", "tfim2d_10x10_rbm_bf16_hbm_traffic.txt"),
+                       "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
+                       "flops_per_proposal": round(fpp, 2), "proposals_per_launch": props}
     if not a.no_compare:
-        ref = Step(nqs, torch, wl, params, "f32", a.lanes, a.refresh)
-        wall32, phases32, step32 = ref.timed(a.steps, a.warmup)
-        ms32 = max(float(np.mean(step32)), 1e3 * wall32 / a.steps)
-        st32 = ref.stats.cpu().numpy()
-        diff = (main_step.eloc - ref.eloc).contiguous()
-        dstats = torch.empty(4, dtype=torch.float64, device=diff.device)
-        nqs.nqs_energy_stats(diff, C, dstats)
-        d = dstats.cpu().numpy()
-        out["fp32"] = {"proposals_per_s": props / (ms32 * 1e-3), "ms_per_step": ms32,
-                       "sampler_proposals_per_s": props / (phases32["sample"] * 1e-3),
-                       "phases_ms": {k: round(v, 3) for k, v in phases32.items()},
-                       "energy": {"mean": st32[0], "stderr": st32[2]}}
-        out["speedup_vs_fp32"] = ms32 / ms
-        out["dE_vs_fp32"] = {"value": d[0], "stderr_paired": d[2],
-                             "note": "same seeds: per-chain paired difference of local energies"}
-
+        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, "f32", True))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, params)
-    print(json.dumps(out))
+    return out
+
+
+def run_heis10(a, torch, nqs, workloads):
+    wl = workloads.cfg3_heis_10x10()
+    params = workloads.params_for(wl)
+    N, C, S, B = wl.model.n_visible, wl.n_chains, wl.n_sweeps, wl.n_burnin
+    props = C * (S + B) * N
+    step = Step(nqs, torch, wl, params, a.dtype, 0, a.refresh, eloc_dtype=a.dtype, with_gram=False)
+    ms, phases = step.timed(a.steps, a.warmup)
+    out = _common(a, wl, props, ms, phases, step, "synthetic (seeded He-initialised FFNN)")
+    w1, w2 = wl.model.widths
+    out["config"] = {"workload": wl.name, "lattice": "10x10 periodic", "J": 1.0, "marshall": True,
+                     "ffnn": [N, w1, w2], "move": "exchange", "chains": C, "sweeps": S, "burnin": B,
+                     "proposals_per_step": props, "samples_per_step": S * C, "parallelism": "single GPU"}
+    # dominant contraction of the sampler: layer 2 of the proposed state,
+    # 2 w1 w2 flops per proposal on the matrix cores
+    fpp = 2.0 * w1 * w2
+    achieved = props * fpp / (phases["sample"] * 1e-3) / 1e12
+    out["roofline"] = {"kernel": "ffnn_sample_kernel", "bound": "mfma", "achieved": round(achieved, 2),
+                       "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
+                       "flops_per_proposal": fpp, "proposals_per_launch": props}
+    if not a.no_compare:
+        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, a.dtype, False))
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, params, budget_s=15.0)
+    return out
+
+
+def run_uneven(a, torch, nqs, workloads):
+    insts = workloads.cfg4_instances()
+    dev = torch.device("cuda:0")
+    models, jobs = [], []
+    props = 0
+    for k, wl in enumerate(insts):
+        m = nqs.Model.from_workload(wl)
+        m.prepare(a.dtype)
+        models.append(m)
+        N = wl.model.n_visible
+        cfg = nqs.SampleConfig(n_chains=wl.n_chains, n_sweeps=wl.n_sweeps, n_burnin=wl.n_burnin, seed=wl.seed,
+                               dtype=a.dtype, instance_id=k, refresh_sweeps=a.refresh)
+        jobs.append({"model": m, "cfg": cfg,
+                     "chain_state": torch.empty(wl.n_chains, N, dtype=torch.int8, device=dev),
+                     "samples": torch.empty(wl.n_sweeps, wl.n_chains, N, dtype=torch.int8, device=dev),
+                     "n_accepted": torch.empty(wl.n_chains, dtype=torch.int64, device=dev)})
+        props += wl.n_chains * (wl.n_sweeps + wl.n_burnin) * N
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / a.steps
+
+    ms0 = timed(lambda: nqs.nqs_sample_batched(jobs, mode=0))
+    ms1 = timed(lambda: nqs.nqs_sample_batched(jobs, mode=1))
+    # the 32 separate launches captured once into a graph and replayed
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        nqs.nqs_sample_batched(jobs, mode=1)
+        s.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            nqs.nqs_sample_batched(jobs, mode=1)
+    torch.cuda.synchronize()
+    ms2 = timed(g.replay)
+    out = {
+        "metric": METRIC, "value": props / (ms0 * 1e-3), "unit": "proposals/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": a.dtype, "data": "synthetic (32 seeded uneven TFIM/RBM instances)",
+        "config": {"workload": "tfim2d_uneven_32", "instances": [w.name for w in insts], "chains_each": 1024,
+                   "sweeps": 200, "burnin": 20, "proposals_per_step": props, "parallelism": "single GPU"},
+        "persistent_ms": ms0, "separate_launches_ms": ms1, "separate_launches_graph_ms": ms2,
+        "speedup_vs_separate": ms1 / ms0, "speedup_vs_graph": ms2 / ms0,
+    }
+    for m in models:
+        m.close()
+    return out
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "only the one-GPU path is built; --gpus above 1 is not supported", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    if a.copy_probe:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 4, "copies": 3}))
+        return
+    import paper_2601_20782_amd as nqs
+    import workloads
+    run = {"tfim10": run_tfim10, "heis10": run_heis10, "uneven": run_uneven}[a.workload]
+    print(json.dumps(run(a, torch, nqs, workloads)))
 
 
 if __name__ == "__main__":

@@ -127,7 +127,8 @@ def test_cfg1_free_running_bit_exact(nqs, lanes):
 
 
 @pytest.mark.parametrize("dtype,lanes,refresh", [("f32", 0, 1), ("bf16", 0, 1), ("f16", 0, 1), ("f32", 16, 1),
-                                                 ("bf16", 32, 1), ("bf16", 16, 4), ("bf16", 64, 4)])
+                                                 ("bf16", 32, 1), ("bf16", 16, 4), ("bf16", 64, 4), ("bf16", 0, 4),
+                                                 ("f32", 0, 4)])
 def test_cfg2_shape_decision_replay(nqs, dtype, lanes, refresh):
     """10x10 TFIM, RBM alpha=2 (N=100, M=200): replay every traced decision in FP64."""
     wl = workloads.cfg2_tfim_10x10()
