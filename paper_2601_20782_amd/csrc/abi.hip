@@ -36,6 +36,22 @@ struct Workspace {
 static std::mutex g_ws_mutex;
 static std::vector<Workspace> g_ws;
 
+int device_cus()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+    static std::mutex mu;
+    static std::vector<int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
 void *workspace(size_t bytes, hipStream_t stream)
 {
     int dev = 0;
@@ -239,7 +255,6 @@ nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_sta
     hipStream_t s = (hipStream_t)stream;
     if (m->desc.arch == NQS_RBM) {
         if (c.move != NQS_MOVE_FLIP) return set_error(NQS_EUNSUPPORTED, "the RBM sampler implements single-flip moves");
-        if (c.dtype == NQS_FP8_E4M3) return set_error(NQS_EUNSUPPORTED, "FP8 sampling is implemented for dense networks");
         return rbm_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
     }
     return ffnn_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
@@ -271,7 +286,6 @@ nqs_status nqs_local_energy(nqs_model *m, const nqs_ham_desc *ham, const int8_t 
         return set_error(NQS_EINVAL, "eval dtype must be F32, F16, BF16 or FP8_E4M3");
     hipStream_t s = (hipStream_t)stream;
     if (m->desc.arch == NQS_RBM) {
-        if (eval_dtype == NQS_FP8_E4M3) return set_error(NQS_EUNSUPPORTED, "FP8 is implemented for dense networks");
         return rbm_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);
     }
     return ffnn_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);

@@ -8,7 +8,7 @@
 #include <cstring>
 
 #include "common.h"
-#include "ffnn_mc.h"
+#include "ffnn_reg.h"
 #include "internal.h"
 
 namespace nqs {
@@ -70,7 +70,7 @@ nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream)
     const bool lp = dtype == NQS_BF16 || dtype == NQS_F16;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const int N = f.widths[0], M1 = f.widths[1];
-    f.m1p = (M1 + 15) / 16 * 16;
+    f.m1p = (M1 + 63) / 64 * 64;   // lane k of a wave owns hidden units k + 64 q
     f.m2p = f.n_layers >= 2 ? (f.widths[2] + 63) / 64 * 64 : 0;
     size_t bytes = 0;
     for (int l = 0; l < f.n_layers; ++l) {
@@ -291,6 +291,19 @@ namespace nqs {
 nqs_status ffnn_sample_dispatch(int dtype, int QK, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds,
                                 hipStream_t s);
 nqs_status ffnn_eloc_dispatch(int dtype, int QK, const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s);
+size_t ffnn_reg_sample_lds(int dtype, int N, int m1p, int m2p);
+size_t ffnn_reg_eloc_lds(int dtype, int N, int m1p, int m2p);
+nqs_status ffnn_reg_sample_dispatch(int dtype, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds,
+                                    hipStream_t s);
+nqs_status ffnn_reg_eloc_dispatch(int dtype, const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s);
+
+// Layer 2 can live in registers (8 waves x 32 output rows) for 16-bit operands
+// with 128 <= m1p <= 512 and m2p <= 256.
+static_assert(kRows == kRegRows, "both samplers take 64 chains per block");
+static bool reg_path(int dtype, const FfnnDev &f)
+{
+    return (dtype == NQS_BF16 || dtype == NQS_F16) && f.m1p >= 128 && f.m1p <= 512 && f.m2p <= 256;
+}
 
 static nqs_status ffnn_mc_ready(nqs_model *m, int dtype, hipStream_t stream)
 {
@@ -319,7 +332,9 @@ nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     if (st != NQS_OK) return st;
     const FfnnDev &f = m->copies[cfg.dtype].ffnn;
     const int N = f.widths[0];
-    const size_t lds = sample_lds_bytes(cfg.dtype, N, f.m1p, f.m2p);
+    const size_t reg_lds = ffnn_reg_sample_lds(cfg.dtype, N, f.m1p, f.m2p);
+    const bool use_reg = reg_path(cfg.dtype, f) && reg_lds <= 160 * 1024;
+    const size_t lds = use_reg ? reg_lds : sample_lds_bytes(cfg.dtype, N, f.m1p, f.m2p);
     if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too large for the LDS-resident sampler");
     if (cfg.init_chains) {
         st = launch_init_chains(chain_state, cfg.n_chains, N, cfg.move, cfg.seed, cfg.instance_id, cfg.chain_id_offset,
@@ -351,11 +366,12 @@ nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     A.tr_delta = tr ? trace->delta : nullptr;
     A.tr_acc = tr ? trace->accepted : nullptr;
     if ((int64_t)(cfg.n_burnin + cfg.n_sweeps) * A.sweep_size == 0) {
-        if (n_accepted) NQS_HIP_TRY(hipMemsetAsync(n_accepted, 0, sizeof(uint64_t) * cfg.n_chains, stream));
+        if (n_accepted) return launch_zero_u64(n_accepted, cfg.n_chains, stream);
         return NQS_OK;
     }
     const int QK = (f.m1p + 63) / 64;
-    const int64_t blocks = (cfg.n_chains + kRows - 1) / kRows;
+    const int64_t blocks = (cfg.n_chains + kRows - 1) / kRows;   // kRows == kRegRows: 64 chains per block
+    if (use_reg) return ffnn_reg_sample_dispatch(cfg.dtype, tr, A, (int)blocks, lds, stream);
     return ffnn_sample_dispatch(cfg.dtype, QK, tr, A, (int)blocks, lds, stream);
 }
 
@@ -367,7 +383,10 @@ nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
     const FfnnDev &f = m->copies[dtype].ffnn;
     const int N = f.widths[0];
     size_t lds;
-    if (dtype == NQS_F32) lds = ffnn_eloc_lds_bytes<float>(N, f.m1p, f.m2p);
+    const size_t reg_lds = ffnn_reg_eloc_lds(dtype, N, f.m1p, f.m2p);
+    const bool use_reg = reg_path(dtype, f) && reg_lds <= 160 * 1024;
+    if (use_reg) lds = reg_lds;
+    else if (dtype == NQS_F32) lds = ffnn_eloc_lds_bytes<float>(N, f.m1p, f.m2p);
     else if (dtype == NQS_F16) lds = ffnn_eloc_lds_bytes<_Float16>(N, f.m1p, f.m2p);
     else lds = ffnn_eloc_lds_bytes<__bf16>(N, f.m1p, f.m2p);
     if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too large for the local-energy kernel");
@@ -388,6 +407,10 @@ nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
     A.h = ham.h;
     A.eloc = eloc;
     const int QK = (f.m1p + 63) / 64;
+    if (use_reg) {
+        const int blocks = (int)std::min<int64_t>((n + kRegGroup - 1) / kRegGroup, device_cus());
+        return ffnn_reg_eloc_dispatch(dtype, A, blocks, lds, stream);
+    }
     const int blocks = (int)std::min<int64_t>(n, 256 * 4);
     return ffnn_eloc_dispatch(dtype, QK, A, blocks, lds, stream);
 }

@@ -1,15 +1,29 @@
 // Centred Gram matrices of the log-derivatives on FP32 matrix cores:
 //   mode 0:  S = Obar^T Obar / n   (Eq. eq:smat, P x P)
 //   mode 1:  T = Obar Obar^T / n   (n x n; same non-zero spectrum as S)
-// with Obar = O - (column means over samples).  One 128 x 128 output tile per
-// block of four waves; each wave owns a 64 x 64 quadrant as 2 x 2
-// v_mfma_f32_32x32x2f32 tiles.  The centring is applied while staging tiles
-// into LDS, so Obar is never written to memory.  Only tiles on or above the
-// block diagonal are computed; the mirror tile is written from the same
-// registers.
+// with Obar = O - (column means over samples).
+//
+// Work decomposition ("stream-K"): the output is cut into 128 x 128 tiles, of
+// which only those on or above the diagonal are computed; the contraction of a
+// tile is cut into steps of 32.  The (tile, step) pairs are laid end to end and
+// every block of the grid (two per compute unit) takes one contiguous, equal
+// share, so no compute unit idles at the end of the launch.  A block that owns
+// a whole tile writes it (and its mirror) directly; a tile shared by several
+// blocks is written by each of them to a per-block partial slot and summed in
+// block order by a second kernel, so results do not depend on timing.
+// Blocks are renumbered so that consecutive shares land on the same XCD and
+// share the operand panels in its L2.
+//
+// Inside a block: four waves, each owns a 64 x 64 quadrant as 2 x 2
+// v_mfma_f32_32x32x2f32 accumulators.  Operand tiles are staged through
+// registers into double-buffered LDS (one barrier per step), centred while
+// staging, and stored row-major with a 36-float row stride so that each lane
+// reads its 16 contraction values with four conflict-free 128-bit loads (the
+// contraction index is assigned to MFMA steps in a permuted but fixed order).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "common.h"
 #include "internal.h"
@@ -18,127 +32,339 @@ namespace nqs {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kBM = 128, kBK = 16;
+constexpr int kGT = 128;                        // output tile side
+constexpr int kGK = 32;                         // contraction step
+constexpr int kGLd = kGK + 4;                   // LDS row stride in floats
+constexpr int kGTile = kGT * kGLd;              // floats per staged operand tile
+constexpr size_t kGramLds = sizeof(float) * 4 * kGTile;   // 2 buffers x (A, B): 73,728 B
+constexpr int kColChunks = 64;
 
-__global__ void colmean_kernel(const float *__restrict__ O, int64_t n, int64_t P, float *__restrict__ mu)
+// ---- column means (FP64 sums over fixed row chunks, summed in chunk order) ----
+
+__global__ void colmean_partial_kernel(const float *__restrict__ O, int64_t n, int64_t P, int chunks,
+                                       double *__restrict__ part)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (p >= P) return;
+    const int64_t r0 = c * n / chunks, r1 = (c + 1) * n / chunks;
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) s += (double)O[r * P + p];
+    part[(int64_t)c * P + p] = s;
+}
+
+__global__ void colmean_final_kernel(const double *__restrict__ part, int64_t n, int64_t P, int chunks,
+                                     float *__restrict__ mu)
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= P) return;
     double s = 0.0;
-    for (int64_t k = 0; k < n; ++k) s += (double)O[k * P + p];
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * P + p];
     mu[p] = (float)(s / (double)n);
 }
 
-// Operand access: element (m, k) of the centred matrix that plays "A" (and "B").
-//   TMODE (T = Obar Obar^T): A(m,k) = O[m][k] - mu[k]; m < n, k < P
-//   SMODE (S = Obar^T Obar): A(m,k) = O[k][m] - mu[m]; m < P, k < n
-template <bool TMODE>
-__global__ void __launch_bounds__(256) gram_kernel(const float *__restrict__ O, const float *__restrict__ mu,
-                                                   int64_t n, int64_t P, float alpha, float *__restrict__ out)
-{
-    const int64_t Mdim = TMODE ? n : P;   // output side
-    const int64_t Kdim = TMODE ? P : n;   // contraction length
-    // map the linear block id onto the upper triangle of tiles (bi <= bj)
-    const int64_t nt = (Mdim + kBM - 1) / kBM;
-    int64_t t = blockIdx.x, bi = 0;
-    while (t >= nt - bi) {
-        t -= nt - bi;
-        ++bi;
-    }
-    const int64_t bj = bi + t;
-    const int64_t m0 = bi * kBM, n0 = bj * kBM;
+// ---- the contraction ----
 
-    __shared__ float As[kBK][kBM];
-    __shared__ float Bs[kBK][kBM];
+struct GramArgs {
+    const float *O;     // [n][P] row-major
+    const float *mu;    // [P] column means
+    float *out;         // [side][side]
+    float *part;        // [grid][2][kGT * kGT] partial tiles
+    int64_t P;          // row length of O
+    int64_t side;       // output side: n (T) or P (S)
+    int64_t kdim;       // contraction length: P (T) or n (S)
+    int64_t nt;         // tiles per output side
+    int64_t ksteps;     // contraction steps per tile
+    int64_t work;       // (upper-triangle tiles) x ksteps
+    int grid;
+    float alpha;
+};
+
+// Block (in the renumbered order) whose share contains work item w.
+__device__ __host__ inline int64_t gram_block_of(int64_t w, int64_t work, int64_t grid)
+{
+    return ((w + 1) * grid - 1) / work;
+}
+
+// Tile t of the upper triangle in row-major order -> (bi, bj), bi <= bj.
+__device__ inline void gram_tile(int64_t t, int64_t nt, int64_t &bi, int64_t &bj)
+{
+    const double a = (double)(2 * nt + 1);
+    int64_t r = (int64_t)((a - sqrt(a * a - 8.0 * (double)t)) * 0.5);
+    r = r < 0 ? 0 : (r > nt - 1 ? nt - 1 : r);
+    auto start = [nt](int64_t row) { return row * nt - row * (row - 1) / 2; };
+    while (r > 0 && start(r) > t) --r;
+    while (r + 1 < nt && start(r + 1) <= t) ++r;
+    bi = r;
+    bj = r + (t - start(r));
+}
+
+// Global -> registers for contraction step ks: 4 x float4 of each operand per thread.
+//   T: element (m, k) = O[m][k] - mu[k]; thread covers rows r + 32q, columns k4..k4+3
+//   S: element (m, k) = O[k][m] - mu[m]; thread covers k-rows kk + 8q, columns m4..m4+3
+template <bool TMODE, bool VEC>
+__device__ inline void gram_load(const GramArgs &g, int64_t m0, int64_t ks, float4 (&v)[4])
+{
+    const int tid = threadIdx.x;
+    if constexpr (TMODE) {
+        const int r = tid >> 3, k4 = (tid & 7) * 4;
+        const int64_t k = ks * kGK + k4;
+        if constexpr (VEC) {
+            const float4 m = k < g.kdim ? *(const float4 *)(g.mu + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = m0 + r + 32 * q;
+                if (row < g.side && k < g.kdim) {
+                    const float4 o = *(const float4 *)(g.O + row * g.P + k);
+                    v[q] = make_float4(o.x - m.x, o.y - m.y, o.z - m.z, o.w - m.w);
+                } else {
+                    v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = m0 + r + 32 * q;
+                float e[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    e[c] = (row < g.side && k + c < g.kdim) ? g.O[row * g.P + k + c] - g.mu[k + c] : 0.0f;
+                v[q] = make_float4(e[0], e[1], e[2], e[3]);
+            }
+        }
+    } else {
+        const int kk = tid >> 5, m4 = (tid & 31) * 4;
+        const int64_t m = m0 + m4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = ks * kGK + kk + 8 * q;
+            if constexpr (VEC) {
+                if (m < g.side && k < g.kdim) {
+                    const float4 o = *(const float4 *)(g.O + k * g.P + m);
+                    const float4 mm = *(const float4 *)(g.mu + m);
+                    v[q] = make_float4(o.x - mm.x, o.y - mm.y, o.z - mm.z, o.w - mm.w);
+                } else {
+                    v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            } else {
+                float e[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    e[c] = (m + c < g.side && k < g.kdim) ? g.O[k * g.P + m + c] - g.mu[m + c] : 0.0f;
+                v[q] = make_float4(e[0], e[1], e[2], e[3]);
+            }
+        }
+    }
+}
+
+// Registers -> LDS tile [kGT rows (output index)][kGLd] (contraction index contiguous).
+template <bool TMODE>
+__device__ inline void gram_store(float *__restrict__ dst, const float4 (&v)[4])
+{
+    const int tid = threadIdx.x;
+    if constexpr (TMODE) {
+        const int r = tid >> 3, k4 = (tid & 7) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(float4 *)(dst + (r + 32 * q) * kGLd + k4) = v[q];
+    } else {
+        const int kk = tid >> 5, m4 = (tid & 31) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            dst[(m4 + 0) * kGLd + kk + 8 * q] = v[q].x;
+            dst[(m4 + 1) * kGLd + kk + 8 * q] = v[q].y;
+            dst[(m4 + 2) * kGLd + kk + 8 * q] = v[q].z;
+            dst[(m4 + 3) * kGLd + kk + 8 * q] = v[q].w;
+        }
+    }
+}
+
+template <bool TMODE, bool VEC>
+__global__ void __launch_bounds__(256, 2) gram_kernel(GramArgs g)
+{
+    extern __shared__ __align__(16) float gsm[];
+    // renumber: the hardware deals blocks to the 8 XCDs round-robin
+    const int x = blockIdx.x, q8 = g.grid >> 3, r8 = g.grid & 7, xcd = x & 7;
+    const int lb = xcd * q8 + min(xcd, r8) + (x >> 3);
+    const int64_t w0 = (int64_t)lb * g.work / g.grid, w1 = (int64_t)(lb + 1) * g.work / g.grid;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    floatx16 acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    const int h = lane >> 5, l32 = lane & 31;
 
-    for (int64_t k0 = 0; k0 < Kdim; k0 += kBK) {
-        // stage 128 x 16 elements of each operand (8 per thread)
-        if constexpr (TMODE) {
-            const int r = tid >> 1, kh = (tid & 1) * 8;
+    for (int64_t w = w0; w < w1;) {
+        const int64_t tile = w / g.ksteps, kb = w % g.ksteps;
+        const int64_t ke = min(g.ksteps, kb + (w1 - w));
+        int64_t bi, bj;
+        gram_tile(tile, g.nt, bi, bj);
+        const int64_t m0 = bi * kGT, n0 = bj * kGT;
+
+        floatx16 acc[2][2];
 #pragma unroll
-            for (int which = 0; which < 2; ++which) {
-                const int64_t row = (which == 0 ? m0 : n0) + r;
-                float v[8];
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int64_t k = k0 + kh + q;
-                    v[q] = (row < Mdim && k < Kdim) ? O[row * P + k] - mu[k] : 0.0f;
-                }
-                float(*dst)[kBM] = which == 0 ? As : Bs;
+            for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int q = 0; q < 8; ++q) dst[kh + q][r] = v[q];
+                for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+        float4 va[4], vb[4];
+        gram_load<TMODE, VEC>(g, m0, kb, va);
+        gram_load<TMODE, VEC>(g, n0, kb, vb);
+        gram_store<TMODE>(gsm, va);
+        gram_store<TMODE>(gsm + kGTile, vb);
+        __syncthreads();
+        for (int64_t ks = kb; ks < ke; ++ks) {
+            const int cur = (int)((ks - kb) & 1);
+            const float *As = gsm + (2 * cur) * kGTile;
+            const float *Bs = As + kGTile;
+            const bool more = ks + 1 < ke;
+            if (more) {
+                gram_load<TMODE, VEC>(g, m0, ks + 1, va);
+                gram_load<TMODE, VEC>(g, n0, ks + 1, vb);
             }
-        } else {
-            const int c = tid & 127, kh = (tid >> 7) * 8;
 #pragma unroll
-            for (int which = 0; which < 2; ++which) {
-                const int64_t col = (which == 0 ? m0 : n0) + c;
-                const float muc = col < Mdim ? mu[col] : 0.0f;
-                float(*dst)[kBM] = which == 0 ? As : Bs;
+            for (int c = 0; c < 4; ++c) {
+                const int kof = h * 16 + 4 * c;
+                const float4 a0 = *(const float4 *)(As + (wm + l32) * kGLd + kof);
+                const float4 a1 = *(const float4 *)(As + (wm + 32 + l32) * kGLd + kof);
+                const float4 b0 = *(const float4 *)(Bs + (wn + l32) * kGLd + kof);
+                const float4 b1 = *(const float4 *)(Bs + (wn + 32 + l32) * kGLd + kof);
+                const float av0[4] = {a0.x, a0.y, a0.z, a0.w}, av1[4] = {a1.x, a1.y, a1.z, a1.w};
+                const float bv0[4] = {b0.x, b0.y, b0.z, b0.w}, bv1[4] = {b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int64_t k = k0 + kh + q;
-                    dst[kh + q][c] = (col < Mdim && k < Kdim) ? O[k * P + col] - muc : 0.0f;
+                for (int e = 0; e < 4; ++e) {
+                    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0[e], bv0[e], acc[0][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0[e], bv1[e], acc[0][1], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[e], bv0[e], acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[e], bv1[e], acc[1][1], 0, 0, 0);
                 }
             }
+            if (more) {
+                float *nxt = gsm + (2 * (cur ^ 1)) * kGTile;
+                gram_store<TMODE>(nxt, va);
+                gram_store<TMODE>(nxt + kGTile, vb);
+            }
+            __syncthreads();
+        }
+
+        const bool whole = kb == 0 && ke == g.ksteps;
+        const int slot = w == w0 ? 0 : 1;
+        float *pt = g.part + ((int64_t)lb * 2 + slot) * (kGT * kGT);
+        // D[i][j] of a 32x32 accumulator: lane = j + 32*((i/4)%2), register = i%4 + 4*(i/8)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int ti = wm + 32 * a + 8 * (r >> 2) + 4 * h + (r & 3);
+                    const int tj = wn + 32 * b + l32;
+                    if (whole) {
+                        const int64_t gi = m0 + ti, gj = n0 + tj;
+                        if (gi < g.side && gj < g.side) {
+                            const float v = g.alpha * acc[a][b][r];
+                            g.out[gi * g.side + gj] = v;
+                            if (bi != bj) g.out[gj * g.side + gi] = v;
+                        }
+                    } else {
+                        pt[ti * kGT + tj] = acc[a][b][r];
+                    }
+                }
+        w += ke - kb;
+    }
+}
+
+// Tiles shared by several blocks: sum the partial slots in block order, scale,
+// and write the tile and its mirror (the mirror through an LDS transpose).
+__global__ void __launch_bounds__(256) gram_fixup_kernel(GramArgs g)
+{
+    constexpr int kHalf = kGT / 2;
+    __shared__ float tileS[kHalf][kGT + 1];
+    const int64_t tile = blockIdx.x;
+    const int64_t ws = tile * g.ksteps, we = ws + g.ksteps - 1;
+    const int64_t blo = gram_block_of(ws, g.work, g.grid), bhi = gram_block_of(we, g.work, g.grid);
+    if (blo == bhi) return;   // written whole by one block
+    int64_t bi, bj;
+    gram_tile(tile, g.nt, bi, bj);
+    const int64_t m0 = bi * kGT, n0 = bj * kGT;
+    for (int r0 = 0; r0 < kGT; r0 += kHalf) {
+        for (int idx = threadIdx.x; idx < kHalf * kGT; idx += blockDim.x) {
+            const int ti = r0 + idx / kGT, tj = idx % kGT;
+            float s = 0.0f;
+            for (int64_t b = blo; b <= bhi; ++b) {
+                const int64_t wb = b * g.work / g.grid;   // first item of block b
+                const int slot = wb >= ws ? 0 : 1;        // b starts inside this tile, or runs into it
+                s += g.part[(b * 2 + slot) * (kGT * kGT) + ti * kGT + tj];
+            }
+            tileS[idx / kGT][tj] = g.alpha * s;
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kBK; kk += 2) {
-            const int kq = kk + (lane >> 5);
-            const float a0 = As[kq][wm + (lane & 31)];
-            const float a1 = As[kq][wm + 32 + (lane & 31)];
-            const float b0 = Bs[kq][wn + (lane & 31)];
-            const float b1 = Bs[kq][wn + 32 + (lane & 31)];
-            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        for (int idx = threadIdx.x; idx < kHalf * kGT; idx += blockDim.x) {
+            const int ti = idx / kGT, tj = idx % kGT;
+            const int64_t gi = m0 + r0 + ti, gj = n0 + tj;
+            if (gi < g.side && gj < g.side) g.out[gi * g.side + gj] = tileS[ti][tj];
+        }
+        if (bi != bj) {
+            for (int idx = threadIdx.x; idx < kHalf * kGT; idx += blockDim.x) {
+                const int tj = idx / kHalf, ti = idx % kHalf;   // mirror row n0 + tj, column m0 + r0 + ti
+                const int64_t gj = n0 + tj, gi = m0 + r0 + ti;
+                if (gi < g.side && gj < g.side) g.out[gj * g.side + gi] = tileS[ti][tj];
+            }
         }
         __syncthreads();
     }
-    // D[i][j] of a 32x32 tile: lane = j + 32*((i/4)%2), register = i%4 + 4*(i/8)
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int j = lane & 31;
-                const int64_t gi = m0 + wm + 32 * a + i, gj = n0 + wn + 32 * b + j;
-                const float v = alpha * acc[a][b][r];
-                if (gi < Mdim && gj < Mdim) {
-                    out[gi * Mdim + gj] = v;
-                    if (bi != bj) out[gj * Mdim + gi] = v;
-                }
-            }
+}
+
+template <bool TMODE, bool VEC>
+static void launch_gram_kernel(const GramArgs &g, hipStream_t stream)
+{
+    allow_lds(gram_kernel<TMODE, VEC>, kGramLds);
+    hipLaunchKernelGGL((gram_kernel<TMODE, VEC>), dim3(g.grid), dim3(256), kGramLds, stream, g);
 }
 
 nqs_status launch_gram(const float *O, int64_t n, int64_t P, int mode, float *out, hipStream_t stream)
 {
-    float *mu = (float *)workspace(sizeof(float) * (size_t)P, stream);
-    if (!mu) return set_error(NQS_ENOMEM, "workspace allocation failed");
-    hipLaunchKernelGGL(colmean_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, O, n, P, mu);
-    const int64_t side = mode == 1 ? n : P;
-    const int64_t nt = (side + kBM - 1) / kBM;
-    const int64_t tiles = nt * (nt + 1) / 2;
-    if (tiles > INT32_MAX) return set_error(NQS_EINVAL, "Gram matrix too large");
-    const float alpha = (float)(1.0 / (double)n);
-    if (mode == 1)
-        hipLaunchKernelGGL((gram_kernel<true>), dim3((unsigned)tiles), dim3(256), 0, stream, O, mu, n, P, alpha, out);
-    else
-        hipLaunchKernelGGL((gram_kernel<false>), dim3((unsigned)tiles), dim3(256), 0, stream, O, mu, n, P, alpha, out);
+    const bool tmode = mode == 1;
+    GramArgs g;
+    g.O = O;
+    g.out = out;
+    g.P = P;
+    g.side = tmode ? n : P;
+    g.kdim = tmode ? P : n;
+    g.nt = (g.side + kGT - 1) / kGT;
+    g.ksteps = (g.kdim + kGK - 1) / kGK;
+    const int64_t tiles = g.nt * (g.nt + 1) / 2;
+    if (tiles > INT32_MAX || tiles > INT64_MAX / g.ksteps) return set_error(NQS_EINVAL, "Gram matrix too large");
+    g.work = tiles * g.ksteps;
+    const int64_t slots = (int64_t)device_cus() * 2;
+    g.grid = (int)std::min<int64_t>(slots, g.work);
+    g.alpha = (float)(1.0 / (double)n);
+
+    const size_t mu_bytes = (sizeof(float) * (size_t)P + 255) & ~(size_t)255;
+    const size_t part_bytes = sizeof(float) * (size_t)g.grid * 2 * kGT * kGT;
+    const size_t cm_bytes = sizeof(double) * (size_t)kColChunks * (size_t)P;
+    char *ws = (char *)workspace(mu_bytes + std::max(part_bytes, cm_bytes), stream);
+    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    float *mu = (float *)ws;
+    g.mu = mu;
+    g.part = (float *)(ws + mu_bytes);
+
+    // column means; the partial sums reuse the space of the partial tiles
+    const int chunks = (int)std::min<int64_t>(kColChunks, n);
+    double *cm = (double *)(ws + mu_bytes);
+    const unsigned pb = (unsigned)((P + 255) / 256);
+    hipLaunchKernelGGL(colmean_partial_kernel, dim3(pb, chunks), dim3(256), 0, stream, O, n, P, chunks, cm);
+    hipLaunchKernelGGL(colmean_final_kernel, dim3(pb), dim3(256), 0, stream, cm, n, P, chunks, mu);
+
+    const bool vec = (P % 4 == 0) && ((uintptr_t)O % 16 == 0);
+    if (tmode) {
+        if (vec) launch_gram_kernel<true, true>(g, stream);
+        else launch_gram_kernel<true, false>(g, stream);
+    } else {
+        if (vec) launch_gram_kernel<false, true>(g, stream);
+        else launch_gram_kernel<false, false>(g, stream);
+    }
+    NQS_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(gram_fixup_kernel, dim3((unsigned)tiles), dim3(256), 0, stream, g);
     NQS_HIP_TRY(hipGetLastError());
     return NQS_OK;
 }

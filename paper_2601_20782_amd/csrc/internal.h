@@ -30,7 +30,7 @@ struct RbmDev {
     float *b = nullptr;       // [M]
     float *Wt = nullptr;      // [N][M]   Wt[i][j] = W[j][i]
     float2 *CS = nullptr;     // [N*M+1]  (cosh 2W[j][i], sinh 2W[j][i]) at [i][j]; entry N*M = (1, 0)
-    float2 *CSt = nullptr;    // [M][N]   the same pairs at [j][i]
+    float2 *CSt = nullptr;    // [M][N]   the same pairs at [j][i], then 8 N slack entries
     float max_abs_w = 0.0f;
 };
 
@@ -79,6 +79,16 @@ static inline void allow_lds(Kern k, size_t bytes)
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)bytes);
 }
+
+// FP8 (E4M3) copy of one tensor with its per-tensor scale amax/448; `amax` is
+// one 64-bit word of device scratch.
+nqs_status launch_e4m3_tensor(const double *src, int64_t n, unsigned long long *amax, float *dst, hipStream_t stream);
+
+// Zero n 64-bit words with a kernel (usable inside captured graphs).
+nqs_status launch_zero_u64(void *p, int64_t n, hipStream_t stream);
+
+// Compute units of the current device (cached per device).
+int device_cus();
 
 // Per-device growable scratch (never shrinks; freed at process exit).
 void *workspace(size_t bytes, hipStream_t stream);

@@ -53,7 +53,7 @@ nqs_status launch_downcast(const double *src, int64_t n, int dtype, float *dst, 
     if (dtype == kE4M3) {
         amax = (unsigned long long *)workspace(256, stream);
         if (!amax) return set_error(NQS_ENOMEM, "workspace allocation failed");
-        NQS_HIP_TRY(hipMemsetAsync(amax, 0, sizeof(unsigned long long), stream));
+        if (nqs_status z = launch_zero_u64(amax, 1, stream); z != NQS_OK) return z;
         hipLaunchKernelGGL(amax_kernel, dim3(std::min(blocks, 1024)), dim3(256), 0, stream, src, n, amax);
         NQS_HIP_TRY(hipGetLastError());
     }
@@ -101,6 +101,35 @@ __global__ void init_chains_kernel(int8_t *__restrict__ state, int64_t n_chains,
             s[j] = t;
         }
     }
+}
+
+// Zero fill by a kernel (not hipMemsetAsync), so that the call can sit in a captured graph.
+__global__ void zero_u64_kernel(unsigned long long *p, int64_t n)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) p[k] = 0ull;
+}
+
+// One tensor of an FP8 copy: scale = amax / 448 (FP32), values round(x / scale) * scale.
+// `amax` is one 64-bit word of caller-owned device memory.
+nqs_status launch_e4m3_tensor(const double *src, int64_t n, unsigned long long *amax, float *dst, hipStream_t stream)
+{
+    if (n <= 0) return NQS_OK;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, stream, amax, (int64_t)1);
+    hipLaunchKernelGGL(amax_kernel, dim3(std::min(blocks, 1024)), dim3(256), 0, stream, src, n, amax);
+    hipLaunchKernelGGL(downcast_kernel, dim3(blocks), dim3(256), 0, stream, src, n, (int)kE4M3, dst,
+                       (const unsigned long long *)amax, (float *)nullptr);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
+nqs_status launch_zero_u64(void *p, int64_t n, hipStream_t stream)
+{
+    if (n <= 0) return NQS_OK;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(blocks), dim3(256), 0, stream, (unsigned long long *)p, n);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
 }
 
 nqs_status launch_init_chains(int8_t *chain_state, int64_t n_chains, int N, int move, uint64_t seed, uint32_t inst,

@@ -25,13 +25,15 @@ namespace nqs {
 // ---------------------------------------------------------------------------
 // Copy builder: round the FP64 master to `dtype` and derive the tables.
 // ---------------------------------------------------------------------------
-__global__ void rbm_build_kernel(const double *__restrict__ master, int N, int M, int dtype, float *a, float *a2,
-                                 float *b, float *Wt, float2 *CS, float2 *CSt, unsigned int *max_abs_bits)
+__global__ void rbm_build_kernel(const double *__restrict__ master, const float *__restrict__ pre, int N, int M,
+                                 int dtype, float *a, float *a2, float *b, float *Wt, float2 *CS, float2 *CSt,
+                                 unsigned int *max_abs_bits)
 {
     const int64_t P = (int64_t)N + M + (int64_t)M * N;
     if (blockIdx.x == 0 && threadIdx.x == 0) CS[(int64_t)N * M] = make_float2(1.0f, 0.0f);   // neutral entry
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        const double v = round_to_dtype(master[p], dtype);
+        // FP8 values come pre-rounded with their per-tensor scales
+        const double v = pre ? (double)pre[p] : round_to_dtype(master[p], dtype);
         if (p < N) {
             a[p] = (float)v;
             a2[p] = (float)(4.0 * v / 0.69314718055994530942);
@@ -55,7 +57,9 @@ nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream)
     Copy &c = m->copies[dtype];
     const int N = m->desc.n_visible, M = m->desc.widths[0];
     const size_t nW = (size_t)N * M;
-    const size_t bytes = sizeof(float) * (2 * N + M + nW) + sizeof(float2) * (2 * nW + 1) + 256 * 8;
+    const size_t P = (size_t)N + M + nW;
+    const size_t bytes = sizeof(float) * (2 * N + M + nW) + sizeof(float2) * (2 * nW + 1 + 8 * (size_t)N) + 256 * 10 +
+                         (dtype == NQS_FP8_E4M3 ? sizeof(float) * P + 3 * sizeof(unsigned long long) : 0);
     if (!c.block) {
         NQS_HIP_TRY(hipMalloc(&c.block, bytes));
     }
@@ -69,18 +73,31 @@ nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream)
     r.N = N;
     r.M = M;
     r.CS = (float2 *)carve(sizeof(float2) * (nW + 1));
-    r.CSt = (float2 *)carve(sizeof(float2) * nW);
+    r.CSt = (float2 *)carve(sizeof(float2) * (nW + 8 * (size_t)N));   // 8 N slack entries for look-ahead loads
     r.Wt = (float *)carve(sizeof(float) * nW);
     r.a = (float *)carve(sizeof(float) * N);
     r.a2 = (float *)carve(sizeof(float) * N);
     r.b = (float *)carve(sizeof(float) * M);
-    unsigned int *mx = (unsigned int *)carve(sizeof(unsigned int));
+    unsigned int *mx = (unsigned int *)carve(sizeof(unsigned long long));
+    float *pre = nullptr;
+    unsigned long long *amax = nullptr;
+    if (dtype == NQS_FP8_E4M3) {
+        pre = (float *)carve(sizeof(float) * P);
+        amax = (unsigned long long *)carve(3 * sizeof(unsigned long long));
+    }
     if ((size_t)(base - (char *)c.block) > bytes) return set_error(NQS_EDEVICE, "internal layout overflow");
-    NQS_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(unsigned int), stream));
-    const int64_t P = (int64_t)N + M + (int64_t)nW;
-    const int blocks = (int)std::min<int64_t>((P + 255) / 256, 4096);
-    hipLaunchKernelGGL(rbm_build_kernel, dim3(blocks), dim3(256), 0, stream, m->master, N, M, dtype, r.a, r.a2, r.b, r.Wt,
-                       r.CS, r.CSt, mx);
+    if (pre) {
+        // per-tensor scales for a, b and W (the same tensors the oracle scales)
+        const int64_t off[3] = {0, N, (int64_t)N + M}, len[3] = {N, M, (int64_t)nW};
+        for (int t = 0; t < 3; ++t) {
+            nqs_status e = launch_e4m3_tensor(m->master + off[t], len[t], amax + t, pre + off[t], stream);
+            if (e != NQS_OK) return e;
+        }
+    }
+    if (nqs_status z = launch_zero_u64(mx, 1, stream); z != NQS_OK) return z;
+    const int blocks = (int)std::min<int64_t>(((int64_t)P + 255) / 256, 4096);
+    hipLaunchKernelGGL(rbm_build_kernel, dim3(blocks), dim3(256), 0, stream, m->master, pre, N, M, dtype, r.a, r.a2, r.b,
+                       r.Wt, r.CS, r.CSt, mx);
     NQS_HIP_TRY(hipGetLastError());
     unsigned int mbits = 0;
     NQS_HIP_TRY(hipMemcpyAsync(&mbits, mx, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
@@ -97,19 +114,6 @@ nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream)
 constexpr float kMaxAbsW = 5.0f;
 
 constexpr size_t kLdsBytes = 160 * 1024;
-
-static int device_cus()
-{
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            cus = prop.multiProcessorCount;
-        if (cus <= 0) cus = 256;
-    }
-    return cus;
-}
 
 nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
                       uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream)
@@ -148,7 +152,7 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
                                     cfg.chain_id_offset, stream);
             if (st != NQS_OK) return st;
         }
-        if (n_accepted) NQS_HIP_TRY(hipMemsetAsync(n_accepted, 0, sizeof(uint64_t) * cfg.n_chains, stream));
+        if (n_accepted) return launch_zero_u64(n_accepted, cfg.n_chains, stream);
         return NQS_OK;
     }
 
@@ -186,86 +190,145 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
 
 // ---------------------------------------------------------------------------
 // Local energies, TFIM:  eps(s) = J sum_<ij> s_i s_j + h sum_i psi(s^i)/psi(s),
-// psi(s^i)/psi(s) = exp(-2 a_i s_i) prod_j (C_ij - s_i t_j S_ij).
-// A block takes B samples; phase 1 computes t = tanh(W s + b) for the tile
-// (threads over hidden units), phase 2 gives each thread one site i and all
-// B samples (the (C,S) pair of (i,j) is loaded once and used B times).
-// Per-sample sums are FP64.
+// psi(s^i)/psi(s) = exp(-2 a_i s_i) prod_j (C_ij - s_i t_j S_ij),  t = tanh(W s + b).
+// A block takes 16 samples.
+//  Phase 1: theta = W s + b for the 16 samples on the matrix cores
+//   (v_mfma_f32_16x16x4f32; hidden units x samples tiles spread over the waves),
+//   t = tanh(theta) into LDS as tT[j][b] (row stride 20 floats).
+//  Phase 2: Q adjacent lanes share a site i and split the hidden units
+//   (lane q takes j = q, q + Q, ...), each keeping 16 running products; the
+//   (C, S) pair is loaded once per (i, j) and used for 16 samples.  Products
+//   are renormalised (frexp) every `renorm` factors, a count chosen on the host
+//   from max |W| so that no partial product leaves the normal FP32 range.
+//  Combine: a reduce-scatter butterfly over the Q lanes multiplies the partial
+//   products and leaves 16/Q samples per lane; the per-site terms are formed in
+//   FP32, converted, and summed over sites in FP64 in a fixed order.
 // ---------------------------------------------------------------------------
-template <int B>
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int Q, int B>
 __global__ void __launch_bounds__(1024) rbm_eloc_tfim_kernel(RbmDev net, const int8_t *__restrict__ samples,
                                                              int64_t n, int dim, int L, int pbc, double J, double h,
-                                                             double *__restrict__ eloc)
+                                                             int renorm, double *__restrict__ eloc)
 {
-    extern __shared__ float smem[];
+    constexpr int BL = B / Q;            // samples per lane after the butterfly
+    constexpr int kElocTLd = B + 4;      // row stride of tT (floats)
+    extern __shared__ __align__(16) float smem[];
     const int N = net.N, M = net.M;
-    float *spT = smem;                      // [N][B]  spins as +-1
-    float *tT = spT + (size_t)N * B;        // [M][B]  tanh theta
-    double *red = (double *)(tT + (size_t)M * B + ((N * B + M * B) & 1));   // [nwaves][B]
+    const int nwaves = blockDim.x >> 6;
+    float *spT = smem;                                   // [N][B] spins as +-1
+    float *tT = spT + (size_t)N * B;                     // [M][kElocTLd]
+    double *red = (double *)(tT + (size_t)M * kElocTLd); // [nwaves][B]  (offset is a multiple of 16 floats)
     const int64_t base = (int64_t)blockIdx.x * B;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    for (int k = tid; k < N * B; k += nt) {
+    for (int k = tid; k < N * B; k += blockDim.x) {
         const int b = k / N, i = k - b * N;
         const int64_t row = base + b;
         spT[i * B + b] = row < n ? (float)samples[row * N + i] : 1.0f;
     }
     __syncthreads();
-    for (int j = tid; j < M; j += nt) {
-        float th[B];
+
+    // phase 1: D[j][b] = sum_i W[j][i] s_i^b, 16 x 16 tiles; lane holds D[j0 + 4*(lane/16) + r][lane % 16]
+    {
+        const int jt_count = (M + 15) >> 4, ksteps = (N + 3) >> 2;
+        const int la = lane & 15, lk = lane >> 4;
+        for (int jt = wave; jt < jt_count; jt += nwaves) {
+            const int j0 = jt * 16, ja = j0 + la;
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int ks = 0; ks < ksteps; ++ks) {
+                const int k = ks * 4 + lk;
+                const float av = (ja < M && k < N) ? net.Wt[(size_t)k * M + ja] : 0.0f;
+                const float bv = k < N ? spT[k * B + la] : 0.0f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+            }
 #pragma unroll
-        for (int b = 0; b < B; ++b) th[b] = net.b[j];
-        for (int i = 0; i < N; ++i) {
-            const float w = net.Wt[(size_t)i * M + j];
-            const float4 *sp4 = reinterpret_cast<const float4 *>(spT + i * B);
-#pragma unroll
-            for (int q = 0; q < B / 4; ++q) {
-                const float4 v = sp4[q];
-                th[4 * q + 0] = fmaf(w, v.x, th[4 * q + 0]);
-                th[4 * q + 1] = fmaf(w, v.y, th[4 * q + 1]);
-                th[4 * q + 2] = fmaf(w, v.z, th[4 * q + 2]);
-                th[4 * q + 3] = fmaf(w, v.w, th[4 * q + 3]);
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 + 4 * lk + r;
+                if (j < M && la < B) tT[j * kElocTLd + la] = tanhf(acc[r] + net.b[j]);
             }
         }
-#pragma unroll
-        for (int b = 0; b < B; ++b) tT[j * B + b] = tanhf(th[b]);
     }
     __syncthreads();
 
-    double contrib[B];
+    // phase 2: lanes q of site i (item = i * Q + q)
+    const int item = tid, i = item / Q, q = item - (item / Q) * Q;
+    const bool active = i < N;
+    float prod[B];
+    int e2[B];
 #pragma unroll
-    for (int b = 0; b < B; ++b) contrib[b] = 0.0;
-    if (tid < N) {
-        const int i = tid;
-        float si[B], prod[B];
-        int e2[B];
+    for (int b = 0; b < B; ++b) {
+        prod[b] = 1.0f;
+        e2[b] = 0;
+    }
+    if (active) {
+        float si[B];
+        const float4 *s4 = reinterpret_cast<const float4 *>(spT + i * B);
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            si[b] = spT[i * B + b];
-            prod[b] = 1.0f;
-            e2[b] = 0;
+        for (int c = 0; c < B / 4; ++c) {
+            const float4 v = s4[c];
+            si[4 * c + 0] = v.x;
+            si[4 * c + 1] = v.y;
+            si[4 * c + 2] = v.z;
+            si[4 * c + 3] = v.w;
         }
-        for (int j = 0; j < M; ++j) {
-            const float2 cs = net.CSt[(size_t)j * N + i];
-            const float4 *t4 = reinterpret_cast<const float4 *>(tT + j * B);
+        const int iters = (M - q + Q - 1) / Q;
+        // (C, S) of hidden unit j = t Q + q; the load for the next unit is issued one step
+        // ahead (CSt carries 8 N slack entries, so the step past the last unit stays inside)
+        const size_t cstep = (size_t)Q * N;
+        const float2 *csp = net.CSt + (size_t)q * N + i;
+        const float *tp = tT + q * kElocTLd;
+        float2 cs = *csp;
+        int t = 0;
+        while (t < iters) {
+            const int t1 = min(iters, t + renorm);
+            for (; t < t1; ++t) {
+                csp += cstep;
+                const float2 nxt = *csp;
+                const float4 *t4 = reinterpret_cast<const float4 *>(tp);
+                tp += Q * kElocTLd;
 #pragma unroll
-            for (int q = 0; q < B / 4; ++q) {
-                const float4 tv = t4[q];
-                prod[4 * q + 0] *= fmaf(-tv.x * si[4 * q + 0], cs.y, cs.x);
-                prod[4 * q + 1] *= fmaf(-tv.y * si[4 * q + 1], cs.y, cs.x);
-                prod[4 * q + 2] *= fmaf(-tv.z * si[4 * q + 2], cs.y, cs.x);
-                prod[4 * q + 3] *= fmaf(-tv.w * si[4 * q + 3], cs.y, cs.x);
-            }
-            if ((j & 7) == 7) {
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    int e;
-                    prod[b] = frexpf(prod[b], &e);
-                    e2[b] += e;
+                for (int c = 0; c < B / 4; ++c) {
+                    const float4 tv = t4[c];
+                    prod[4 * c + 0] *= fmaf(-tv.x * si[4 * c + 0], cs.y, cs.x);
+                    prod[4 * c + 1] *= fmaf(-tv.y * si[4 * c + 1], cs.y, cs.x);
+                    prod[4 * c + 2] *= fmaf(-tv.z * si[4 * c + 2], cs.y, cs.x);
+                    prod[4 * c + 3] *= fmaf(-tv.w * si[4 * c + 3], cs.y, cs.x);
                 }
+                cs = nxt;
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                int e;
+                prod[b] = frexpf(prod[b], &e);
+                e2[b] += e;
             }
         }
-        // nearest neighbours of i along +x and +y (periodic or open)
+    }
+    // reduce-scatter over the Q lanes: after the step with bit m, a lane keeps
+    // the upper or lower half of its samples according to bit m of q
+    int keep_base = 0;   // first sample index held (in units of the full B)
+#pragma unroll
+    for (int step = 0, half = B / 2; half >= BL; ++step, half >>= 1) {
+        const int bit = (q >> step) & 1;
+#pragma unroll
+        for (int b = 0; b < half; ++b) {
+            const float pk = bit ? prod[b + half] : prod[b], ps = bit ? prod[b] : prod[b + half];
+            const int ek = bit ? e2[b + half] : e2[b], es = bit ? e2[b] : e2[b + half];
+            const float pr = __shfl_xor(ps, 1 << step, 64);
+            const int er = __shfl_xor(es, 1 << step, 64);
+            int e;
+            prod[b] = frexpf(pk * pr, &e);
+            e2[b] = ek + er + e;
+        }
+        keep_base += bit * half;
+    }
+    // this lane now holds samples keep_base .. keep_base + BL - 1 of site i
+    double contrib[BL];
+#pragma unroll
+    for (int b = 0; b < BL; ++b) contrib[b] = 0.0;
+    if (active) {
         int nb1 = -1, nb2 = -1;
         if (dim == 1) {
             if (i + 1 < L) nb1 = i + 1;
@@ -279,28 +342,49 @@ __global__ void __launch_bounds__(1024) rbm_eloc_tfim_kernel(RbmDev net, const i
         }
         const float ai = net.a[i];
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const float ratio = ldexpf(__expf(-2.0f * ai * si[b]) * prod[b], e2[b]);
+        for (int b = 0; b < BL; ++b) {
+            const int bb = keep_base + b;
+            const float s = spT[i * B + bb];
+            const float ratio = ldexpf(__expf(-2.0f * ai * s) * prod[b], e2[b]);
             float zz = 0.0f;
-            if (nb1 >= 0) zz += spT[nb1 * B + b];
-            if (nb2 >= 0) zz += spT[nb2 * B + b];
-            contrib[b] = J * (double)(si[b] * zz) + h * (double)ratio;
+            if (nb1 >= 0) zz += spT[nb1 * B + bb];
+            if (nb2 >= 0) zz += spT[nb2 * B + bb];
+            contrib[b] = J * (double)(s * zz) + h * (double)ratio;
         }
     }
-    // FP64 block reduction over sites
-    const int lane = tid & 63, wv = tid >> 6, nw = (nt + 63) >> 6;
+    // sum over the sites of the wave: lanes with equal q hold the same samples
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const double v = group_sum<64>(contrib[b]);
-        if (lane == 0) red[wv * B + b] = v;
+    for (int off = Q; off < 64; off <<= 1)
+#pragma unroll
+        for (int b = 0; b < BL; ++b) contrib[b] += __shfl_xor(contrib[b], off, 64);
+    if (lane < Q) {
+#pragma unroll
+        for (int b = 0; b < BL; ++b) red[wave * B + keep_base + b] = contrib[b];
     }
     __syncthreads();
     if (tid < B) {
         double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += red[w * B + tid];
+        for (int w = 0; w < nwaves; ++w) s += red[w * B + tid];
         const int64_t row = base + tid;
         if (row < n) eloc[row] = s;
     }
+}
+
+template <int Q, int B>
+static nqs_status launch_eloc_q(const RbmDev &net, const nqs_ham_desc &ham, const int8_t *samples, int64_t n,
+                                int renorm, double *eloc, hipStream_t stream)
+{
+    const int N = net.N, M = net.M;
+    const int threads = std::max(64, (int)(((int64_t)N * Q + 63) / 64 * 64));
+    const size_t lds = sizeof(float) * ((size_t)N * B + (size_t)M * (B + 4)) + sizeof(double) * (threads / 64) * B;
+    if (lds > kLdsBytes) return set_error(NQS_EUNSUPPORTED, "RBM too large for the local-energy kernel");
+    const int64_t blocks = (n + B - 1) / B;
+    if (blocks > INT32_MAX) return set_error(NQS_EINVAL, "too many samples");
+    allow_lds(rbm_eloc_tfim_kernel<Q, B>, lds);
+    hipLaunchKernelGGL((rbm_eloc_tfim_kernel<Q, B>), dim3((unsigned)blocks), dim3(threads), lds, stream, net, samples,
+                       n, ham.dim, ham.L, ham.pbc, ham.J, ham.h, renorm, eloc);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
 }
 
 nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
@@ -314,17 +398,34 @@ nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t 
     if (!(net.max_abs_w <= kMaxAbsW)) return set_error(NQS_EUNSUPPORTED, "product-form ratios need |W| <= 5");
     const int N = net.N, M = net.M;
     if (N > 1024) return set_error(NQS_EUNSUPPORTED, "RBM local energies need N <= 1024");
-    constexpr int B = 16;
-    const int threads = std::max(64, ((N + 63) / 64) * 64);
-    const size_t lds = sizeof(float) * ((size_t)N * B + (size_t)M * B + 2) + sizeof(double) * (threads / 64) * B;
-    if (lds > kLdsBytes) return set_error(NQS_EUNSUPPORTED, "RBM too large for the local-energy kernel");
-    const int64_t blocks = (n + B - 1) / B;
-    if (blocks > INT32_MAX) return set_error(NQS_EINVAL, "too many samples");
-    allow_lds(rbm_eloc_tfim_kernel<B>, lds);
-    hipLaunchKernelGGL((rbm_eloc_tfim_kernel<B>), dim3((unsigned)blocks), dim3(threads), lds, stream, net, samples, n,
-                       ham.dim, ham.L, ham.pbc, ham.J, ham.h, eloc);
-    NQS_HIP_TRY(hipGetLastError());
-    return NQS_OK;
+    // lanes per site: as many as fit in 1024 threads, at most 8 and at most M
+    int Q = 8;
+    while (Q > 1 && ((int64_t)N * Q > 1024 || Q > M)) Q >>= 1;
+    // factors lie in [e^{-2|W|}, e^{2|W|}]: a run of k of them after a renormalisation
+    // stays within 2^{+-120} when k * 2|W| / ln 2 <= 119
+    const double per = 2.0 * (double)net.max_abs_w / 0.6931471805599453;
+    const int iters = (M + Q - 1) / Q;
+    int renorm = per > 0.0 ? (int)std::min<double>((double)iters, std::floor(119.0 / per)) : iters;
+    renorm = std::max(1, renorm);
+    // 16 samples per block when the block's waves split evenly over the four SIMDs, else 8
+    // (smaller register arrays, so that two blocks share a compute unit)
+    const int waves = (int)(((int64_t)N * Q + 63) / 64);
+    int B = (waves % 4 == 0) ? 16 : 8;
+    if (const char *e = getenv("NQS_ELOC_B")) B = atoi(e) == 16 ? 16 : 8;
+    if (B == 16) {
+        switch (Q) {
+        case 8: return launch_eloc_q<8, 16>(net, ham, samples, n, renorm, eloc, stream);
+        case 4: return launch_eloc_q<4, 16>(net, ham, samples, n, renorm, eloc, stream);
+        case 2: return launch_eloc_q<2, 16>(net, ham, samples, n, renorm, eloc, stream);
+        default: return launch_eloc_q<1, 16>(net, ham, samples, n, renorm, eloc, stream);
+        }
+    }
+    switch (Q) {
+    case 8: return launch_eloc_q<8, 8>(net, ham, samples, n, renorm, eloc, stream);
+    case 4: return launch_eloc_q<4, 8>(net, ham, samples, n, renorm, eloc, stream);
+    case 2: return launch_eloc_q<2, 8>(net, ham, samples, n, renorm, eloc, stream);
+    default: return launch_eloc_q<1, 8>(net, ham, samples, n, renorm, eloc, stream);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -164,9 +164,7 @@ nqs_status rbm_sample_batched(const nqs_sample_job *jobs, int n_jobs, int mode, 
     NQS_HIP_TRY(hipMemcpyAsync(d_items, sorted.data(), bytes_items, hipMemcpyHostToDevice, stream));
     NQS_HIP_TRY(hipStreamSynchronize(stream));   // the host vectors go out of scope
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, stream, d_counter);
-    int dev = 0, cus = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    const int cus = device_cus();
     const int per_cu = lds_need > 80 * 1024 ? 1 : (lds_need > 40 * 1024 ? 2 : 4);
     const int grid = (int)std::min<size_t>(sorted.size(), (size_t)cus * per_cu);
     allow_lds(rbm_batched_kernel, lds_need);

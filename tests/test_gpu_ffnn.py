@@ -212,3 +212,60 @@ def test_ffnn_logpsi_grad_matches_oracle(nqs, widths, n, N):
     vo = torch.empty(P, dtype=torch.float32, device=DEV)
     nqs.nqs_logpsi_grad(model, st, vjp_in=torch.from_numpy(g).to(DEV), vjp_out=vo)
     assert np.allclose(vo.cpu().numpy(), g.astype(np.float64) @ rO, rtol=1e-4, atol=1e-4)
+
+
+# ---------------------------------------------------------------------------
+# Register-resident layer 2 (16-bit operands, 128 <= padded width 1 <= 512)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,move,L,widths,C", [("f16", "exchange", 6, (200, 100), 100),
+                                                   ("bf16", "flip", 6, (144, 72), 70),
+                                                   ("bf16", "exchange", 8, (256, 250), 64)])
+def test_register_path_replay(nqs, dtype, move, L, widths, C):
+    """Other first-layer widths (fragment counts), partial blocks, few output tiles, flip moves."""
+    N = L * L
+    kind = "heisenberg" if move == "exchange" else "tfim"
+    wl = workloads.Workload(f"reg_{kind}_{L}", workloads.Hamiltonian(kind, workloads.Lattice(2, L), 1.0, 2.0,
+                                                                     move == "exchange"),
+                            workloads.Model("ffnn", N, widths), n_chains=C, n_sweeps=3, n_burnin=2, move=move, seed=21)
+    _say(f"register-path replay {dtype} {move} {widths}")
+    params = 0.7 * workloads.params_for(wl)
+    model = nqs.Model.from_workload(wl, params)
+    T = 12
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=3, n_burnin=2, seed=21, dtype=dtype, move=move)
+    r = _run(nqs, model, cfg, N, trace_chains=T)
+    om = oracle.model_from_workload(wl, params, dtype)
+    ocfg = oracle.make_cfg(C, 3, 2, move=move, seed=21)
+    starts = np.array([oracle.init_chain(N, move, 21, c) for c in range(T)])
+    res = oracle.replay(om, ocfg, list(range(T)), starts, r["tr_site"], r["tr_ubits"].view(np.uint32),
+                        r["tr_delta"], r["tr_accepted"], tau_rel=1e-5)
+    _say(f"  replay: {res['decisions_equal']} equal, {res['near_ties']} near ties, "
+         f"max |dDelta| {res['max_delta_err']:.2e}")
+    assert res["site_u_mismatch"] == 0 and res["decision_mismatch"] == 0
+    assert np.array_equal(res["end_states"], r["state"][:T])
+    f, _ = om.logamp(r["samples"].reshape(-1, N))
+    assert np.max(np.abs(r["logpsi"].ravel() - f) / np.maximum(1.0, np.abs(f))) < 1e-5
+
+
+@pytest.mark.parametrize("dtype,kind,dim,L,widths,n_s", [("bf16", "tfim", 2, 6, (144, 72), 41),
+                                                         ("f16", "heisenberg", 2, 6, (130, 40), 37),
+                                                         ("bf16", "heisenberg", 1, 16, (256, 250), 10)])
+def test_register_path_local_energy(nqs, dtype, kind, dim, L, widths, n_s):
+    n = L if dim == 1 else L * L
+    marshall = kind == "heisenberg"
+    wl = workloads.Workload(f"reg_eloc_{kind}", workloads.Hamiltonian(kind, workloads.Lattice(dim, L), 1.0, 2.0, marshall),
+                            workloads.Model("ffnn", n, widths), n_chains=1, n_sweeps=1, n_burnin=0,
+                            move="exchange" if marshall else "flip", seed=22)
+    params = 0.7 * workloads.params_for(wl)
+    model = nqs.Model.from_workload(wl, params)
+    smp = workloads.random_spins(n_s, n, 10, zero_mag=marshall)
+    el = torch.empty(n_s, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(wl.ham), torch.from_numpy(smp).to(DEV), el, dtype)
+    om = oracle.model_from_workload(wl, params, dtype)
+    ref = oracle.local_energy(om, wl.ham, smp)
+    got = el.cpu().numpy()
+    f, _ = om.logamp(smp)
+    nterms = 2 * n
+    scale = np.abs(ref) + 2 * nterms * 2.0 * np.exp(1.0)
+    tol = 4e-6 * np.maximum(1.0, np.abs(f)) * scale
+    assert np.all(np.abs(got - ref) < tol)

@@ -128,7 +128,7 @@ def test_cfg1_free_running_bit_exact(nqs, lanes):
 
 @pytest.mark.parametrize("dtype,lanes,refresh", [("f32", 0, 1), ("bf16", 0, 1), ("f16", 0, 1), ("f32", 16, 1),
                                                  ("bf16", 32, 1), ("bf16", 16, 4), ("bf16", 64, 4), ("bf16", 0, 4),
-                                                 ("f32", 0, 4)])
+                                                 ("f32", 0, 4), ("e4m3", 0, 4)])
 def test_cfg2_shape_decision_replay(nqs, dtype, lanes, refresh):
     """10x10 TFIM, RBM alpha=2 (N=100, M=200): replay every traced decision in FP64."""
     wl = workloads.cfg2_tfim_10x10()
@@ -220,7 +220,7 @@ def test_resume_and_chain_split_are_bit_exact(nqs):
 # Local energies, statistics
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("case", ["cfg2", "cfg1", "open2d", "ragged"])
+@pytest.mark.parametrize("case", ["cfg2", "cfg1", "open2d", "ragged", "l16", "bigw"])
 def test_local_energy_tfim_matches_oracle(nqs, case):
     if case == "cfg2":
         wl = workloads.cfg2_tfim_10x10()
@@ -232,13 +232,25 @@ def test_local_energy_tfim_matches_oracle(nqs, case):
         wl = workloads.Workload("open", workloads.Hamiltonian("tfim", workloads.Lattice(2, 7, pbc=False), 0.7, 1.9),
                                 workloads.Model("rbm", 49, (98,)), 1, 1, 0, "flip", 0.3, 11)
         n_s = 129
-    else:
+    elif case == "ragged":
         wl = workloads.Workload("ragged", workloads.Hamiltonian("tfim", workloads.Lattice(2, 9), 1.0, 2.5),
                                 workloads.Model("rbm", 81, (243,)), 1, 1, 0, "flip", 0.1, 12)
         n_s = 17
+    elif case == "l16":
+        # 16 x 16 sites: four lanes per site, 16 waves, 16 samples per block
+        wl = workloads.Workload("l16", workloads.Hamiltonian("tfim", workloads.Lattice(2, 16), 1.0, 3.0),
+                                workloads.Model("rbm", 256, (256,)), 1, 1, 0, "flip", 0.02, 13)
+        n_s = 45
+    else:
+        # large weights: the running products are renormalised inside the hidden-unit loop
+        wl = workloads.Workload("bigw", workloads.Hamiltonian("tfim", workloads.Lattice(2, 6), 1.0, 2.0),
+                                workloads.Model("rbm", 36, (144,)), 1, 1, 0, "flip", 0.7, 14)
+        n_s = 77
     _say(f"eloc {case}")
     params = workloads.params_for(wl)
     N = wl.model.n_visible
+    if case == "bigw":
+        assert 2.0 < np.abs(params[N + wl.model.widths[0]:]).max() <= 5.0
     model = nqs.Model.from_workload(wl, params)
     smp = workloads.random_spins(n_s, N, 4)
     el = torch.empty(n_s, dtype=torch.float64, device=DEV)
@@ -260,7 +272,7 @@ def test_local_energy_lowprec_copy(nqs):
     params = workloads.params_for(wl)
     model = nqs.Model.from_workload(wl, params)
     smp = workloads.random_spins(64, 100, 6)
-    for dt in ("bf16", "f16"):
+    for dt in ("bf16", "f16", "e4m3"):
         el = torch.empty(64, dtype=torch.float64, device=DEV)
         nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(wl.ham), torch.from_numpy(smp).to(DEV), el, dt)
         ref = oracle.local_energy(oracle.model_from_workload(wl, params, dt), wl.ham, smp)
