@@ -100,12 +100,15 @@ typedef struct {
     int64_t n_chains;
     int32_t n_sweeps, n_burnin, sweep_size;
     int32_t move;                     /* nqs_move */
-    int32_t dtype;                    /* sampling copy: NQS_F32 / NQS_F16 / NQS_BF16 (FFNN also FP8) */
+    int32_t dtype;                    /* sampling copy: NQS_F32 / NQS_F16 / NQS_BF16, or NQS_FP8_E4M3 for an RBM */
     int32_t init_chains;
     uint64_t seed, step_offset;
     uint32_t instance_id;
     int64_t chain_id_offset;          /* global id of chain 0 (for splitting chains across devices) */
-    int32_t lanes_per_chain;          /* 0 = autotune; else 16, 32 or 64 */
+    int32_t lanes_per_chain;          /* RBM: 0 = autotune, else 16, 32 or 64 lanes per chain.
+                                         Dense network: 0 = automatic, -1 = the batched-GEMM path
+                                         (a full forward pass of every proposal; the path taken
+                                         anyway for depth != 2 or wide first layers) */
     int32_t refresh_sweeps;           /* recompute the incremental state every k sweeps (0 => 1) */
 } nqs_sample_cfg;
 

@@ -81,6 +81,12 @@ nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream)
         bytes += al(sizeof(uint16_t) * (size_t)f.m2p * f.m1p) + al(sizeof(uint16_t) * (size_t)N * f.m1p) +
                  al(sizeof(float) * (size_t)f.m2p * f.m1p) + al(sizeof(float) * (size_t)N * f.m1p) +
                  al(sizeof(float) * f.m1p) + al(sizeof(float) * f.m2p);
+    const size_t esize = lp ? sizeof(uint16_t) : sizeof(float);
+    for (int l = 0; l < f.n_layers; ++l) {
+        f.Kp[l] = (f.widths[l] + 63) / 64 * 64;
+        f.Np[l] = (f.widths[l + 1] + 127) / 128 * 128;
+        bytes += al(esize * (size_t)f.Np[l] * f.Kp[l]) + al(sizeof(float) * f.Np[l]);
+    }
     if (!c.block) NQS_HIP_TRY(hipMalloc(&c.block, bytes));
     char *base = (char *)c.block;
     auto carve = [&](size_t sz) {
@@ -123,6 +129,18 @@ nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream)
         pad(f.Wt[0], N, M1, M1, N, f.m1p, lp ? f.W1ct : nullptr, f.W1tp);
         pad(f.b[0], 1, M1, M1, 1, f.m1p, nullptr, f.b1p);
         pad(f.b[1], 1, M2, M2, 1, f.m2p, nullptr, f.b2p);
+        NQS_HIP_TRY(hipGetLastError());
+    }
+    for (int l = 0; l < f.n_layers; ++l) {
+        const int out = f.widths[l + 1], in = f.widths[l];
+        f.Wd[l] = carve(esize * (size_t)f.Np[l] * f.Kp[l]);
+        f.bd[l] = (float *)carve(sizeof(float) * f.Np[l]);
+        const int64_t n = (int64_t)f.Np[l] * f.Kp[l];
+        const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+        hipLaunchKernelGGL(ffnn_pad_kernel, dim3(blocks), dim3(256), 0, stream, f.W[l], out, in, in, f.Np[l], f.Kp[l],
+                           dtype, lp ? (uint16_t *)f.Wd[l] : nullptr, lp ? nullptr : (float *)f.Wd[l]);
+        hipLaunchKernelGGL(ffnn_pad_kernel, dim3((f.Np[l] + 255) / 256), dim3(256), 0, stream, f.b[l], 1, out, out, 1,
+                           f.Np[l], dtype, (uint16_t *)nullptr, f.bd[l]);
         NQS_HIP_TRY(hipGetLastError());
     }
     NQS_HIP_TRY(hipStreamSynchronize(stream));
@@ -305,16 +323,21 @@ static bool reg_path(int dtype, const FfnnDev &f)
     return (dtype == NQS_BF16 || dtype == NQS_F16) && f.m1p >= 128 && f.m1p <= 512 && f.m2p <= 256;
 }
 
-static nqs_status ffnn_mc_ready(nqs_model *m, int dtype, hipStream_t stream)
+nqs_status deep_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
+                       uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
+nqs_status deep_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
+                             double *eloc, hipStream_t stream);
+
+// Copy ready; *deep tells whether the network goes through the batched-GEMM path
+// (any depth) instead of the two-layer kernels with an incremental first layer.
+static nqs_status ffnn_mc_ready(nqs_model *m, int dtype, hipStream_t stream, bool *deep)
 {
-    if (m->desc.n_layers != 2)
-        return set_error(NQS_EUNSUPPORTED, "sampling and local energies of dense networks are implemented for two layers");
     if (dtype != NQS_F32 && dtype != NQS_BF16 && dtype != NQS_F16)
         return set_error(NQS_EUNSUPPORTED, "dense networks sample in F32, BF16 or F16");
     nqs_status st = ensure_copy(m, dtype, stream);
     if (st != NQS_OK) return st;
     const FfnnDev &f = m->copies[dtype].ffnn;
-    if (f.m1p > 512) return set_error(NQS_EUNSUPPORTED, "first hidden width must be <= 512");
+    *deep = m->desc.n_layers != 2 || f.m1p > 512 || (int64_t)f.widths[0] * f.m1p * (dtype == NQS_F32 ? 0 : 2) > 96 * 1024;
     return NQS_OK;
 }
 
@@ -328,8 +351,21 @@ static size_t sample_lds_bytes(int dtype, int N, int m1p, int m2p)
 nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
                        uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream)
 {
-    nqs_status st = ffnn_mc_ready(m, cfg.dtype, stream);
+    bool deep = false;
+    nqs_status st = ffnn_mc_ready(m, cfg.dtype, stream, &deep);
     if (st != NQS_OK) return st;
+    if (deep || cfg.lanes_per_chain == -1) {
+        if ((int64_t)(cfg.n_burnin + cfg.n_sweeps) * (cfg.sweep_size > 0 ? cfg.sweep_size : m->desc.n_visible) == 0) {
+            if (cfg.init_chains) {
+                st = launch_init_chains(chain_state, cfg.n_chains, m->desc.n_visible, cfg.move, cfg.seed,
+                                        cfg.instance_id, cfg.chain_id_offset, stream);
+                if (st != NQS_OK) return st;
+            }
+            if (n_accepted) return launch_zero_u64(n_accepted, cfg.n_chains, stream);
+            return NQS_OK;
+        }
+        return deep_sample(m, cfg, chain_state, samples, logpsi, n_accepted, trace, stream);
+    }
     const FfnnDev &f = m->copies[cfg.dtype].ffnn;
     const int N = f.widths[0];
     const size_t reg_lds = ffnn_reg_sample_lds(cfg.dtype, N, f.m1p, f.m2p);
@@ -378,8 +414,12 @@ nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
 nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
                              double *eloc, hipStream_t stream)
 {
-    nqs_status st = ffnn_mc_ready(m, dtype, stream);
+    bool deep = false;
+    nqs_status st = ffnn_mc_ready(m, dtype, stream, &deep);
     if (st != NQS_OK) return st;
+    if (m->desc.marshall && (m->desc.lat_dim != ham.dim || m->desc.lat_L != ham.L))
+        return set_error(NQS_EINVAL, "Marshall lattice differs from the Hamiltonian lattice");
+    if (deep) return deep_local_energy(m, ham, samples, n, dtype, eloc, stream);
     const FfnnDev &f = m->copies[dtype].ffnn;
     const int N = f.widths[0];
     size_t lds;

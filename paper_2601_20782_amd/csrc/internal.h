@@ -49,6 +49,11 @@ struct FfnnDev {
     float *W1tp = nullptr;                 // [N][m1p]   FP32 values of layer 1, transposed
     float *b1p = nullptr;                  // [m1p]
     float *b2p = nullptr;                  // [m2p]
+    // batched-GEMM path of any depth: layer l padded to Np[l] outputs (multiple
+    // of 128) x Kp[l] inputs (multiple of 64), zeros in the padding
+    int Kp[NQS_MAX_LAYERS] = {0}, Np[NQS_MAX_LAYERS] = {0};
+    void *Wd[NQS_MAX_LAYERS] = {nullptr};  // [Np][Kp] bf16/f16 codes, or FP32 values
+    float *bd[NQS_MAX_LAYERS] = {nullptr}; // [Np]
 };
 
 struct Copy {

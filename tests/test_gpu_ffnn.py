@@ -269,3 +269,85 @@ def test_register_path_local_energy(nqs, dtype, kind, dim, L, widths, n_s):
     scale = np.abs(ref) + 2 * nterms * 2.0 * np.exp(1.0)
     tol = 4e-6 * np.maximum(1.0, np.abs(f)) * scale
     assert np.all(np.abs(got - ref) < tol)
+
+
+# ---------------------------------------------------------------------------
+# Batched-GEMM path (any depth; every proposal a full forward pass)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,move,L,widths,C,force", [("f32", "exchange", 6, (64, 48, 32), 100, False),
+                                                         ("bf16", "exchange", 6, (96, 64, 40), 130, False),
+                                                         ("f16", "flip", 6, (72, 40, 24), 70, False),
+                                                         ("bf16", "exchange", 10, (400, 200), 64, True)])
+def test_deep_path_replay(nqs, dtype, move, L, widths, C, force):
+    N = L * L
+    kind = "heisenberg" if move == "exchange" else "tfim"
+    wl = workloads.Workload(f"deep_{kind}_{L}", workloads.Hamiltonian(kind, workloads.Lattice(2, L), 1.0, 2.0,
+                                                                      move == "exchange"),
+                            workloads.Model("ffnn", N, widths), n_chains=C, n_sweeps=3, n_burnin=1, move=move, seed=31)
+    _say(f"deep-path replay {dtype} {move} {widths}")
+    params = 0.8 * workloads.params_for(wl)
+    model = nqs.Model.from_workload(wl, params)
+    T = 12
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=3, n_burnin=1, seed=31, dtype=dtype, move=move,
+                           lanes_per_chain=-1 if force else 0)
+    r = _run(nqs, model, cfg, N, trace_chains=T)
+    om = oracle.model_from_workload(wl, params, dtype)
+    ocfg = oracle.make_cfg(C, 3, 1, move=move, seed=31)
+    starts = np.array([oracle.init_chain(N, move, 31, c) for c in range(T)])
+    res = oracle.replay(om, ocfg, list(range(T)), starts, r["tr_site"], r["tr_ubits"].view(np.uint32),
+                        r["tr_delta"], r["tr_accepted"], tau_rel=1e-5)
+    _say(f"  replay: {res['decisions_equal']} equal, {res['near_ties']} near ties, "
+         f"max |dDelta| {res['max_delta_err']:.2e}")
+    assert res["site_u_mismatch"] == 0 and res["decision_mismatch"] == 0
+    assert np.array_equal(res["end_states"], r["state"][:T])
+    f, _ = om.logamp(r["samples"].reshape(-1, N))
+    assert np.max(np.abs(r["logpsi"].ravel() - f) / np.maximum(1.0, np.abs(f))) < 1e-5
+    acc = r["acc"]
+    assert np.all(acc <= (3 + 1) * N) and np.all(acc >= 0)
+
+
+def test_deep_path_exact_pi_small(nqs):
+    """Three layers, 1D Heisenberg N=8, zero-magnetisation sector: histogram vs exact |psi|^2."""
+    import scipy.stats
+    n, widths = 8, (12, 10, 6)
+    p = 0.6 * workloads.ffnn_params(n, widths, 41, bias_std=0.3)
+    model = nqs.Model("ffnn", n, widths, p, marshall=True, lat_dim=1, lat_L=n)
+    cfg = nqs.SampleConfig(n_chains=2048, n_sweeps=40, n_burnin=10, seed=6, move="exchange", dtype="f32")
+    r = _run(nqs, model, cfg, n)
+    om = oracle.OracleModel("ffnn", n, widths, oracle.round_to(p, "f32"), act_dtype="f32", marshall=True,
+                            lattice=workloads.Lattice(1, n))
+    pi, _, _ = exact.enumerate_pi(om)
+    cfgs = exact.all_configs(n)
+    sector = cfgs.sum(axis=1) == 0
+    ps = np.where(sector, pi, 0.0)
+    ps /= ps.sum()
+    idx = np.sum((r["samples"].reshape(-1, n) > 0).astype(np.int64) << np.arange(n), axis=1)
+    counts = np.bincount(idx, minlength=2 ** n)[sector]
+    e = ps[sector] * counts.sum()
+    chi2 = np.sum((counts - e) ** 2 / e)
+    assert scipy.stats.chi2.sf(chi2, sector.sum() - 1) > 1e-5
+
+
+@pytest.mark.parametrize("dtype,kind,dim,L,widths,n_s", [("f32", "heisenberg", 2, 6, (64, 48, 32), 23),
+                                                         ("bf16", "tfim", 1, 20, (60, 40, 20), 19),
+                                                         ("bf16", "heisenberg", 2, 6, (96, 64, 40), 30)])
+def test_deep_path_local_energy(nqs, dtype, kind, dim, L, widths, n_s):
+    n = L if dim == 1 else L * L
+    marshall = kind == "heisenberg"
+    wl = workloads.Workload(f"deep_eloc_{kind}", workloads.Hamiltonian(kind, workloads.Lattice(dim, L), 1.0, 2.0,
+                                                                       marshall),
+                            workloads.Model("ffnn", n, widths), n_chains=1, n_sweeps=1, n_burnin=0,
+                            move="exchange" if marshall else "flip", seed=32)
+    params = 0.8 * workloads.params_for(wl)
+    model = nqs.Model.from_workload(wl, params)
+    smp = workloads.random_spins(n_s, n, 11, zero_mag=marshall)
+    el = torch.empty(n_s, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(wl.ham), torch.from_numpy(smp).to(DEV), el, dtype)
+    om = oracle.model_from_workload(wl, params, dtype)
+    ref = oracle.local_energy(om, wl.ham, smp)
+    got = el.cpu().numpy()
+    f, _ = om.logamp(smp)
+    scale = np.abs(ref) + 2 * (2 * n) * 2.0 * np.exp(1.0)
+    tol = 4e-6 * np.maximum(1.0, np.abs(f)) * scale
+    assert np.all(np.abs(got - ref) < tol)
