@@ -98,6 +98,33 @@ __device__ __forceinline__ void deep_load_a(const DeepGemmArgs &g, int r0, int k
         const int row = r0 + (tid >> 3) + 32 * q;
         if constexpr (SPINS) {
             uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
+            if constexpr (sizeof(T) == 2) {
+                // 8 spins in one 8-byte load: the sign bit of each int8 (+1 = 0x01, -1 = 0xff)
+                // becomes the sign bit of a 16-bit +-1; then the row's sites are negated
+                if (row < nrows && (g.N & 7) == 0 && k0 + 8 <= g.N) {
+                    const uint2 raw = *reinterpret_cast<const uint2 *>(g.spins + (size_t)rc[q] * g.N + k0);
+                    constexpr uint32_t one2 = std::is_same<T, _Float16>::value ? 0x3C003C00u : 0x3F803F80u;
+                    const uint32_t lo = (raw.x >> 7) & 0x01010101u, hi = (raw.y >> 7) & 0x01010101u;
+                    w0 = one2 | ((lo & 0x1u) << 15) | ((lo & 0x100u) << 23);
+                    w1 = one2 | ((lo & 0x10000u) >> 1) | ((lo & 0x1000000u) << 7);
+                    w2 = one2 | ((hi & 0x1u) << 15) | ((hi & 0x100u) << 23);
+                    w3 = one2 | ((hi & 0x10000u) >> 1) | ((hi & 0x1000000u) << 7);
+                    const uint32_t ei = (uint32_t)(ri[q] - k0), ej = (uint32_t)(rj[q] - k0);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const uint32_t e = t == 0 ? ei : ej;
+                        if (e < 8u) {
+                            const uint32_t m = 1u << (15 + 16 * (e & 1u));
+                            const uint32_t wsel = e >> 1;
+                            w0 ^= wsel == 0 ? m : 0u;
+                            w1 ^= wsel == 1 ? m : 0u;
+                            w2 ^= wsel == 2 ? m : 0u;
+                            w3 ^= wsel == 3 ? m : 0u;
+                        }
+                    }
+                    return u32x4{w0, w1, w2, w3};
+                }
+            }
             if (row < nrows) {
                 const int8_t *sp = g.spins + (size_t)rc[q] * g.N;
 #pragma unroll
@@ -156,13 +183,17 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
     T *lds = reinterpret_cast<T *>(smem);
 
     const int nrows = *g.nrows;
-    // renumber blocks so that consecutive ids (same row tile) share an XCD
-    const int nblk = g.max_row_tiles * g.nct;
-    const int x = blockIdx.x, q8 = nblk >> 3, r8 = nblk & 7, xcd = x & 7;
+    // The grid covers the largest row count; only the first `valid` blocks have
+    // work.  Those are renumbered so that each XCD (blocks are dealt to the 8
+    // XCDs round-robin) gets a contiguous range: consecutive ids share a row
+    // tile, whose rows then stay in that XCD's L2.
+    const int valid = ((nrows + kDT - 1) / kDT) * g.nct;
+    const int x = blockIdx.x;
+    if (x >= valid) return;
+    const int q8 = valid >> 3, r8 = valid & 7, xcd = x & 7;
     const int lb = xcd * q8 + min(xcd, r8) + (x >> 3);
     const int rt = lb / g.nct, ct = lb - (lb / g.nct) * g.nct;
     const int m0 = rt * kDT, n0 = ct * kDT;
-    if (m0 >= nrows) return;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -189,21 +220,26 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
+    // Two register stages: the loads of step k + 2 are issued before step k is
+    // computed, so each global load has two steps of matrix-core work to land.
     const int ksteps = g.Kp / BK;
-    Stage4 va, vb;
-    deep_load_a<T, SPINS>(g, m0, 0, nrows, rc, ri, rj, va);
-    deep_load_w<T>(g, n0, 0, vb);
-    deep_store<T>(lds, va);
-    deep_store<T>(lds + TILE, vb);
+    Stage4 a0s, b0s, a1s, b1s;
+    deep_load_a<T, SPINS>(g, m0, 0, nrows, rc, ri, rj, a0s);
+    deep_load_w<T>(g, n0, 0, b0s);
+    if (ksteps > 1) {
+        deep_load_a<T, SPINS>(g, m0, 1, nrows, rc, ri, rj, a1s);
+        deep_load_w<T>(g, n0, 1, b1s);
+    }
+    deep_store<T>(lds, a0s);
+    deep_store<T>(lds + TILE, b0s);
     __syncthreads();
-    for (int ks = 0; ks < ksteps; ++ks) {
+    auto step = [&](int ks, Stage4 &af, Stage4 &bf, const Stage4 &an, const Stage4 &bn) {
         const int cur = ks & 1;
         const T *As = lds + (2 * cur) * TILE;
         const T *Bs = As + TILE;
-        const bool more = ks + 1 < ksteps;
-        if (more) {
-            deep_load_a<T, SPINS>(g, m0, ks + 1, nrows, rc, ri, rj, va);
-            deep_load_w<T>(g, n0, ks + 1, vb);
+        if (ks + 2 < ksteps) {
+            deep_load_a<T, SPINS>(g, m0, ks + 2, nrows, rc, ri, rj, af);
+            deep_load_w<T>(g, n0, ks + 2, bf);
         }
 #pragma unroll
         for (int kk = 0; kk < KI; ++kk) {
@@ -224,12 +260,16 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
                 acc[1][1] = Mc<T>::mma(a1, b1, acc[1][1]);
             }
         }
-        if (more) {
+        if (ks + 1 < ksteps) {
             T *nxt = lds + (2 * (cur ^ 1)) * TILE;
-            deep_store<T>(nxt, va);
-            deep_store<T>(nxt + TILE, vb);
+            deep_store<T>(nxt, an);
+            deep_store<T>(nxt + TILE, bn);
         }
         __syncthreads();
+    };
+    for (int ks = 0; ks < ksteps; ks += 2) {
+        step(ks, a0s, b0s, a1s, b1s);
+        if (ks + 1 < ksteps) step(ks + 1, a1s, b1s, a0s, b0s);
     }
 
     // D[i][j] of a 32x32 accumulator: lane = j + 32*((i/4)%2), register = i%4 + 4*(i/8)

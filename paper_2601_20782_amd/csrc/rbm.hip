@@ -15,6 +15,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "common.h"
@@ -207,7 +209,7 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int Q, int B>
+template <int Q, int B, bool RENORM>
 __global__ void __launch_bounds__(1024) rbm_eloc_tfim_kernel(RbmDev net, const int8_t *__restrict__ samples,
                                                              int64_t n, int dim, int L, int pbc, double J, double h,
                                                              int renorm, double *__restrict__ eloc)
@@ -230,23 +232,31 @@ __global__ void __launch_bounds__(1024) rbm_eloc_tfim_kernel(RbmDev net, const i
     }
     __syncthreads();
 
-    // phase 1: D[j][b] = sum_i W[j][i] s_i^b, 16 x 16 tiles; lane holds D[j0 + 4*(lane/16) + r][lane % 16]
+    // phase 1: D[j][b] = sum_i W[j][i] s_i^b, 16 x 16 tiles; lane holds D[j0 + 4*(lane/16) + r][b0 + lane % 16].
+    // W values of 8 contraction steps are loaded ahead of their matrix-core steps.
     {
-        const int jt_count = (M + 15) >> 4, ksteps = (N + 3) >> 2;
+        const int jt_count = (M + 15) >> 4, bt_count = (B + 15) >> 4, ksteps = (N + 3) >> 2;
         const int la = lane & 15, lk = lane >> 4;
-        for (int jt = wave; jt < jt_count; jt += nwaves) {
-            const int j0 = jt * 16, ja = j0 + la;
+        for (int t = wave; t < jt_count * bt_count; t += nwaves) {
+            const int jt = t / bt_count, bt = t - (t / bt_count) * bt_count;
+            const int j0 = jt * 16, ja = j0 + la, bc = bt * 16 + la;
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int ks = 0; ks < ksteps; ++ks) {
-                const int k = ks * 4 + lk;
-                const float av = (ja < M && k < N) ? net.Wt[(size_t)k * M + ja] : 0.0f;
-                const float bv = k < N ? spT[k * B + la] : 0.0f;
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+            for (int ks0 = 0; ks0 < ksteps; ks0 += 8) {
+                float av[8], bv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = (ks0 + u) * 4 + lk;
+                    const bool ok = ks0 + u < ksteps && k < N;
+                    av[u] = (ok && ja < M) ? net.Wt[(size_t)k * M + ja] : 0.0f;
+                    bv[u] = (ok && bc < B) ? spT[k * B + bc] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u], acc, 0, 0, 0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = j0 + 4 * lk + r;
-                if (j < M && la < B) tT[j * kElocTLd + la] = tanhf(acc[r] + net.b[j]);
+                if (j < M && bc < B) tT[j * kElocTLd + bc] = tanhf(acc[r] + net.b[j]);
             }
         }
     }
@@ -282,7 +292,7 @@ __global__ void __launch_bounds__(1024) rbm_eloc_tfim_kernel(RbmDev net, const i
         float2 cs = *csp;
         int t = 0;
         while (t < iters) {
-            const int t1 = min(iters, t + renorm);
+            const int t1 = RENORM ? min(iters, t + renorm) : iters;
             for (; t < t1; ++t) {
                 csp += cstep;
                 const float2 nxt = *csp;
@@ -370,7 +380,7 @@ __global__ void __launch_bounds__(1024) rbm_eloc_tfim_kernel(RbmDev net, const i
     }
 }
 
-template <int Q, int B>
+template <int Q, int B, bool RENORM>
 static nqs_status launch_eloc_q(const RbmDev &net, const nqs_ham_desc &ham, const int8_t *samples, int64_t n,
                                 int renorm, double *eloc, hipStream_t stream)
 {
@@ -380,8 +390,8 @@ static nqs_status launch_eloc_q(const RbmDev &net, const nqs_ham_desc &ham, cons
     if (lds > kLdsBytes) return set_error(NQS_EUNSUPPORTED, "RBM too large for the local-energy kernel");
     const int64_t blocks = (n + B - 1) / B;
     if (blocks > INT32_MAX) return set_error(NQS_EINVAL, "too many samples");
-    allow_lds(rbm_eloc_tfim_kernel<Q, B>, lds);
-    hipLaunchKernelGGL((rbm_eloc_tfim_kernel<Q, B>), dim3((unsigned)blocks), dim3(threads), lds, stream, net, samples,
+    allow_lds(rbm_eloc_tfim_kernel<Q, B, RENORM>, lds);
+    hipLaunchKernelGGL((rbm_eloc_tfim_kernel<Q, B, RENORM>), dim3((unsigned)blocks), dim3(threads), lds, stream, net, samples,
                        n, ham.dim, ham.L, ham.pbc, ham.J, ham.h, renorm, eloc);
     NQS_HIP_TRY(hipGetLastError());
     return NQS_OK;
@@ -398,34 +408,25 @@ nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t 
     if (!(net.max_abs_w <= kMaxAbsW)) return set_error(NQS_EUNSUPPORTED, "product-form ratios need |W| <= 5");
     const int N = net.N, M = net.M;
     if (N > 1024) return set_error(NQS_EUNSUPPORTED, "RBM local energies need N <= 1024");
-    // lanes per site: as many as fit in 1024 threads, at most 8 and at most M
-    int Q = 8;
-    while (Q > 1 && ((int64_t)N * Q > 1024 || Q > M)) Q >>= 1;
+    // two lanes per site (measured best on the 10x10 lattice against 1, 4 and 8), one when
+    // 2N lanes do not fit in a block; 16 samples per block (32 costs occupancy)
+    const int Q = (2 * N <= 1024 && M >= 2) ? 2 : 1;
     // factors lie in [e^{-2|W|}, e^{2|W|}]: a run of k of them after a renormalisation
     // stays within 2^{+-120} when k * 2|W| / ln 2 <= 119
     const double per = 2.0 * (double)net.max_abs_w / 0.6931471805599453;
     const int iters = (M + Q - 1) / Q;
     int renorm = per > 0.0 ? (int)std::min<double>((double)iters, std::floor(119.0 / per)) : iters;
     renorm = std::max(1, renorm);
-    // 16 samples per block when the block's waves split evenly over the four SIMDs, else 8
-    // (smaller register arrays, so that two blocks share a compute unit)
-    const int waves = (int)(((int64_t)N * Q + 63) / 64);
-    int B = (waves % 4 == 0) ? 16 : 8;
-    if (const char *e = getenv("NQS_ELOC_B")) B = atoi(e) == 16 ? 16 : 8;
-    if (B == 16) {
-        switch (Q) {
-        case 8: return launch_eloc_q<8, 16>(net, ham, samples, n, renorm, eloc, stream);
-        case 4: return launch_eloc_q<4, 16>(net, ham, samples, n, renorm, eloc, stream);
-        case 2: return launch_eloc_q<2, 16>(net, ham, samples, n, renorm, eloc, stream);
-        default: return launch_eloc_q<1, 16>(net, ham, samples, n, renorm, eloc, stream);
-        }
-    }
-    switch (Q) {
-    case 8: return launch_eloc_q<8, 8>(net, ham, samples, n, renorm, eloc, stream);
-    case 4: return launch_eloc_q<4, 8>(net, ham, samples, n, renorm, eloc, stream);
-    case 2: return launch_eloc_q<2, 8>(net, ham, samples, n, renorm, eloc, stream);
-    default: return launch_eloc_q<1, 8>(net, ham, samples, n, renorm, eloc, stream);
-    }
+    const bool rn = renorm < iters;
+    constexpr int B = 16;
+#define NQS_ELOC_CASE(QQ, BB)                                                                          \
+    if (Q == QQ && B == BB)                                                                            \
+        return rn ? launch_eloc_q<QQ, BB, true>(net, ham, samples, n, renorm, eloc, stream)            \
+                  : launch_eloc_q<QQ, BB, false>(net, ham, samples, n, renorm, eloc, stream);
+    NQS_ELOC_CASE(2, 16)
+    NQS_ELOC_CASE(1, 16)
+#undef NQS_ELOC_CASE
+    return set_error(NQS_EDEVICE, "no local-energy kernel for this shape");
 }
 
 // ---------------------------------------------------------------------------

@@ -220,7 +220,35 @@ def test_resume_and_chain_split_are_bit_exact(nqs):
 # Local energies, statistics
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("case", ["cfg2", "cfg1", "open2d", "ragged", "l16", "bigw"])
+def _eloc_error_bound(params, N, M, h, smp):
+    """FP32 error bound of the product-form local energy, from FP64 values.
+
+    Per flip of site i the ratio is exp(-2 a_i s_i) prod_j n_j with
+    n_j = C_ji - s_i t_j S_ji, (C, S) = (cosh 2W, sinh 2W), t = tanh(theta).
+    Each factor carries the table rounding, one FMA and one multiply
+    (2.5 u (C + |t S|) absolute) and the effect of the FP32 rounding of theta,
+    |S| (1 - t^2) N u (|b| + sum |W|); relative to n this grows where C and
+    t S nearly cancel (large weights).  The ratios are summed in FP64.
+    """
+    u = 2.0 ** -24
+    a, b = params[:N], params[N:N + M]
+    W = params[N + M:].reshape(M, N)
+    s = smp.astype(np.float64)
+    theta = s @ W.T + b                                  # [n, M]
+    t = np.tanh(theta)
+    C, S = np.cosh(2 * W), np.sinh(2 * W)                # [M, N]
+    dth = N * u * (np.abs(b) + np.abs(W).sum(axis=1))    # [M]
+    out = np.zeros(smp.shape[0])
+    for i in range(N):
+        n = C[:, i][None, :] - s[:, i:i + 1] * t * S[:, i][None, :]
+        err = (2.5 * u * (C[:, i][None, :] + np.abs(t * S[:, i][None, :]))
+               + np.abs(S[:, i])[None, :] * (1 - t * t) * dth[None, :]) / np.abs(n)
+        ratio = np.exp(-2 * a[i] * s[:, i] + np.log(np.abs(n)).sum(axis=1))
+        out += abs(h) * ratio * (err.sum(axis=1) + 4 * u)
+    return out
+
+
+@pytest.mark.parametrize("case", ["cfg2", "cfg1", "open2d", "ragged", "l16", "bigw", "l24"])
 def test_local_energy_tfim_matches_oracle(nqs, case):
     if case == "cfg2":
         wl = workloads.cfg2_tfim_10x10()
@@ -241,6 +269,11 @@ def test_local_energy_tfim_matches_oracle(nqs, case):
         wl = workloads.Workload("l16", workloads.Hamiltonian("tfim", workloads.Lattice(2, 16), 1.0, 3.0),
                                 workloads.Model("rbm", 256, (256,)), 1, 1, 0, "flip", 0.02, 13)
         n_s = 45
+    elif case == "l24":
+        # 24 x 24 sites: one lane per site
+        wl = workloads.Workload("l24", workloads.Hamiltonian("tfim", workloads.Lattice(2, 24), 1.0, 3.0),
+                                workloads.Model("rbm", 576, (576,)), 1, 1, 0, "flip", 0.02, 15)
+        n_s = 5
     else:
         # large weights: the running products are renormalised inside the hidden-unit loop
         wl = workloads.Workload("bigw", workloads.Hamiltonian("tfim", workloads.Lattice(2, 6), 1.0, 2.0),
@@ -258,13 +291,8 @@ def test_local_energy_tfim_matches_oracle(nqs, case):
     om = oracle.model_from_workload(wl, params, "f32")
     ref = oracle.local_energy(om, wl.ham, smp)
     got = el.cpu().numpy()
-    # Each flip ratio is a product of M FP32 factors (one table rounding, one
-    # FMA, one multiply: <= 2.5 ulp each) times exp(-2 a s): relative error
-    # <= (2.5 M + 4) 2^-24; the ratios are summed in FP64.
-    M = wl.model.widths[0]
-    rtol = (2.5 * M + 4) * 2.0 ** -24
-    scale = np.abs(ref) + abs(wl.ham.J) * 2 * N + abs(wl.ham.h) * N
-    assert np.max(np.abs(got - ref) / scale) < rtol
+    bound = _eloc_error_bound(om.params, N, wl.model.widths[0], wl.ham.h, smp)
+    assert np.all(np.abs(got - ref) <= 2.0 * bound + 1e-12 * np.abs(ref))
 
 
 def test_local_energy_lowprec_copy(nqs):
