@@ -3,16 +3,17 @@
 //   mode 1:  T = Obar Obar^T / n   (n x n; same non-zero spectrum as S)
 // with Obar = O - (column means over samples).
 //
-// Work decomposition ("stream-K"): the output is cut into 128 x 128 tiles, of
-// which only those on or above the diagonal are computed; the contraction of a
-// tile is cut into steps of 32.  The (tile, step) pairs are laid end to end and
-// every block of the grid (two per compute unit) takes one contiguous, equal
-// share, so no compute unit idles at the end of the launch.  A block that owns
-// a whole tile writes it (and its mirror) directly; a tile shared by several
+// Work decomposition: the output is cut into 128 x 128 tiles, of which only
+// those on or above the diagonal are computed; the contraction of a tile is cut
+// into steps of 32.  The grid has two blocks per compute unit.  As many whole
+// rounds of tiles as the grid holds are done data-parallel (every block one
+// whole tile per round, so all blocks walk the contraction together and share
+// each slab of O through L2); the remaining tiles' (tile, step) pairs are laid
+// end to end and every block takes one contiguous, equal share ("stream-K"), so
+// no compute unit idles at the end of the launch.  A tile shared by several
 // blocks is written by each of them to a per-block partial slot and summed in
-// block order by a second kernel, so results do not depend on timing.
-// Blocks are renumbered so that consecutive shares land on the same XCD and
-// share the operand panels in its L2.
+// block order by a second kernel, so results do not depend on timing.  Blocks
+// are renumbered so that consecutive ids land on the same XCD.
 //
 // Inside a block: four waves, each owns a 64 x 64 quadrant as 2 x 2
 // v_mfma_f32_32x32x2f32 accumulators.  Operand tiles are staged through
@@ -31,6 +32,7 @@
 namespace nqs {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));   // native 4-vector (no HIP wrapper struct)
 
 constexpr int kGT = 128;                        // output tile side
 constexpr int kGK = 32;                         // contraction step
@@ -75,7 +77,8 @@ struct GramArgs {
     int64_t kdim;       // contraction length: P (T) or n (S)
     int64_t nt;         // tiles per output side
     int64_t ksteps;     // contraction steps per tile
-    int64_t work;       // (upper-triangle tiles) x ksteps
+    int64_t dp_tiles;   // tiles done whole in data-parallel rounds (a multiple of grid)
+    int64_t work;       // (remaining tiles) x ksteps, shared out stream-K
     int grid;
     float alpha;
 };
@@ -99,26 +102,26 @@ __device__ inline void gram_tile(int64_t t, int64_t nt, int64_t &bi, int64_t &bj
     bj = r + (t - start(r));
 }
 
-// Global -> registers for contraction step ks: 4 x float4 of each operand per thread.
+// Global -> registers for contraction step ks: 4 x f32x4 of each operand per thread.
 //   T: element (m, k) = O[m][k] - mu[k]; thread covers rows r + 32q, columns k4..k4+3
 //   S: element (m, k) = O[k][m] - mu[m]; thread covers k-rows kk + 8q, columns m4..m4+3
 template <bool TMODE, bool VEC>
-__device__ inline void gram_load(const GramArgs &g, int64_t m0, int64_t ks, float4 (&v)[4])
+__device__ inline void gram_load(const GramArgs &g, int64_t m0, int64_t ks, f32x4 (&v)[4])
 {
     const int tid = threadIdx.x;
     if constexpr (TMODE) {
         const int r = tid >> 3, k4 = (tid & 7) * 4;
         const int64_t k = ks * kGK + k4;
         if constexpr (VEC) {
-            const float4 m = k < g.kdim ? *(const float4 *)(g.mu + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+            const f32x4 m = k < g.kdim ? *(const f32x4 *)(g.mu + k) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t row = m0 + r + 32 * q;
                 if (row < g.side && k < g.kdim) {
-                    const float4 o = *(const float4 *)(g.O + row * g.P + k);
-                    v[q] = make_float4(o.x - m.x, o.y - m.y, o.z - m.z, o.w - m.w);
+                    const f32x4 o = *(const f32x4 *)(g.O + row * g.P + k);
+                    v[q] = f32x4{o.x - m.x, o.y - m.y, o.z - m.z, o.w - m.w};
                 } else {
-                    v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    v[q] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
             }
         } else {
@@ -129,7 +132,7 @@ __device__ inline void gram_load(const GramArgs &g, int64_t m0, int64_t ks, floa
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     e[c] = (row < g.side && k + c < g.kdim) ? g.O[row * g.P + k + c] - g.mu[k + c] : 0.0f;
-                v[q] = make_float4(e[0], e[1], e[2], e[3]);
+                v[q] = f32x4{e[0], e[1], e[2], e[3]};
             }
         }
     } else {
@@ -140,18 +143,18 @@ __device__ inline void gram_load(const GramArgs &g, int64_t m0, int64_t ks, floa
             const int64_t k = ks * kGK + kk + 8 * q;
             if constexpr (VEC) {
                 if (m < g.side && k < g.kdim) {
-                    const float4 o = *(const float4 *)(g.O + k * g.P + m);
-                    const float4 mm = *(const float4 *)(g.mu + m);
-                    v[q] = make_float4(o.x - mm.x, o.y - mm.y, o.z - mm.z, o.w - mm.w);
+                    const f32x4 o = *(const f32x4 *)(g.O + k * g.P + m);
+                    const f32x4 mm = *(const f32x4 *)(g.mu + m);
+                    v[q] = f32x4{o.x - mm.x, o.y - mm.y, o.z - mm.z, o.w - mm.w};
                 } else {
-                    v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    v[q] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
             } else {
                 float e[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     e[c] = (m + c < g.side && k < g.kdim) ? g.O[k * g.P + m + c] - g.mu[m + c] : 0.0f;
-                v[q] = make_float4(e[0], e[1], e[2], e[3]);
+                v[q] = f32x4{e[0], e[1], e[2], e[3]};
             }
         }
     }
@@ -159,13 +162,13 @@ __device__ inline void gram_load(const GramArgs &g, int64_t m0, int64_t ks, floa
 
 // Registers -> LDS tile [kGT rows (output index)][kGLd] (contraction index contiguous).
 template <bool TMODE>
-__device__ inline void gram_store(float *__restrict__ dst, const float4 (&v)[4])
+__device__ inline void gram_store(float *__restrict__ dst, const f32x4 (&v)[4])
 {
     const int tid = threadIdx.x;
     if constexpr (TMODE) {
         const int r = tid >> 3, k4 = (tid & 7) * 4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *(float4 *)(dst + (r + 32 * q) * kGLd + k4) = v[q];
+        for (int q = 0; q < 4; ++q) *(f32x4 *)(dst + (r + 32 * q) * kGLd + k4) = v[q];
     } else {
         const int kk = tid >> 5, m4 = (tid & 31) * 4;
 #pragma unroll
@@ -185,15 +188,12 @@ __global__ void __launch_bounds__(256, 2) gram_kernel(GramArgs g)
     // renumber: the hardware deals blocks to the 8 XCDs round-robin
     const int x = blockIdx.x, q8 = g.grid >> 3, r8 = g.grid & 7, xcd = x & 7;
     const int lb = xcd * q8 + min(xcd, r8) + (x >> 3);
-    const int64_t w0 = (int64_t)lb * g.work / g.grid, w1 = (int64_t)(lb + 1) * g.work / g.grid;
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
     const int h = lane >> 5, l32 = lane & 31;
 
-    for (int64_t w = w0; w < w1;) {
-        const int64_t tile = w / g.ksteps, kb = w % g.ksteps;
-        const int64_t ke = min(g.ksteps, kb + (w1 - w));
+    // contraction steps [kb, ke) of one tile; whole tiles are written out, parts go to a slot
+    auto run = [&](int64_t tile, int64_t kb, int64_t ke, bool whole, int slot) {
         int64_t bi, bj;
         gram_tile(tile, g.nt, bi, bj);
         const int64_t m0 = bi * kGT, n0 = bj * kGT;
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256, 2) gram_kernel(GramArgs g)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-        float4 va[4], vb[4];
+        f32x4 va[4], vb[4];
         gram_load<TMODE, VEC>(g, m0, kb, va);
         gram_load<TMODE, VEC>(g, n0, kb, vb);
         gram_store<TMODE>(gsm, va);
@@ -221,13 +221,13 @@ __global__ void __launch_bounds__(256, 2) gram_kernel(GramArgs g)
                 gram_load<TMODE, VEC>(g, m0, ks + 1, va);
                 gram_load<TMODE, VEC>(g, n0, ks + 1, vb);
             }
-#pragma unroll
+#pragma unroll 1
             for (int c = 0; c < 4; ++c) {
                 const int kof = h * 16 + 4 * c;
-                const float4 a0 = *(const float4 *)(As + (wm + l32) * kGLd + kof);
-                const float4 a1 = *(const float4 *)(As + (wm + 32 + l32) * kGLd + kof);
-                const float4 b0 = *(const float4 *)(Bs + (wn + l32) * kGLd + kof);
-                const float4 b1 = *(const float4 *)(Bs + (wn + 32 + l32) * kGLd + kof);
+                const f32x4 a0 = *(const f32x4 *)(As + (wm + l32) * kGLd + kof);
+                const f32x4 a1 = *(const f32x4 *)(As + (wm + 32 + l32) * kGLd + kof);
+                const f32x4 b0 = *(const f32x4 *)(Bs + (wn + l32) * kGLd + kof);
+                const f32x4 b1 = *(const f32x4 *)(Bs + (wn + 32 + l32) * kGLd + kof);
                 const float av0[4] = {a0.x, a0.y, a0.z, a0.w}, av1[4] = {a1.x, a1.y, a1.z, a1.w};
                 const float bv0[4] = {b0.x, b0.y, b0.z, b0.w}, bv1[4] = {b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
@@ -246,8 +246,6 @@ __global__ void __launch_bounds__(256, 2) gram_kernel(GramArgs g)
             __syncthreads();
         }
 
-        const bool whole = kb == 0 && ke == g.ksteps;
-        const int slot = w == w0 ? 0 : 1;
         float *pt = g.part + ((int64_t)lb * 2 + slot) * (kGT * kGT);
         // D[i][j] of a 32x32 accumulator: lane = j + 32*((i/4)%2), register = i%4 + 4*(i/8)
 #pragma unroll
@@ -269,7 +267,20 @@ __global__ void __launch_bounds__(256, 2) gram_kernel(GramArgs g)
                         pt[ti * kGT + tj] = acc[a][b][r];
                     }
                 }
-        w += ke - kb;
+    };
+
+    // data-parallel rounds: every block takes whole tiles, so all blocks walk the
+    // contraction together and share each slab of O through L2
+    for (int64_t t = lb; t < g.dp_tiles; t += g.grid) run(t, 0, g.ksteps, true, 0);
+    // stream-K over the remaining tiles
+    if (g.work > 0) {
+        const int64_t w0 = (int64_t)lb * g.work / g.grid, w1 = (int64_t)(lb + 1) * g.work / g.grid;
+        for (int64_t w = w0; w < w1;) {
+            const int64_t kb = w % g.ksteps;
+            const int64_t ke = min(g.ksteps, kb + (w1 - w));
+            run(g.dp_tiles + w / g.ksteps, kb, ke, kb == 0 && ke == g.ksteps, w == w0 ? 0 : 1);
+            w += ke - kb;
+        }
     }
 }
 
@@ -279,8 +290,8 @@ __global__ void __launch_bounds__(256) gram_fixup_kernel(GramArgs g)
 {
     constexpr int kHalf = kGT / 2;
     __shared__ float tileS[kHalf][kGT + 1];
-    const int64_t tile = blockIdx.x;
-    const int64_t ws = tile * g.ksteps, we = ws + g.ksteps - 1;
+    const int64_t tile = g.dp_tiles + blockIdx.x;
+    const int64_t ws = (int64_t)blockIdx.x * g.ksteps, we = ws + g.ksteps - 1;
     const int64_t blo = gram_block_of(ws, g.work, g.grid), bhi = gram_block_of(we, g.work, g.grid);
     if (blo == bhi) return;   // written whole by one block
     int64_t bi, bj;
@@ -292,6 +303,7 @@ __global__ void __launch_bounds__(256) gram_fixup_kernel(GramArgs g)
             float s = 0.0f;
             for (int64_t b = blo; b <= bhi; ++b) {
                 const int64_t wb = b * g.work / g.grid;   // first item of block b
+                if (wb == (b + 1) * g.work / g.grid) continue;   // empty share
                 const int slot = wb >= ws ? 0 : 1;        // b starts inside this tile, or runs into it
                 s += g.part[(b * 2 + slot) * (kGT * kGT) + ti * kGT + tj];
             }
@@ -334,9 +346,10 @@ nqs_status launch_gram(const float *O, int64_t n, int64_t P, int mode, float *ou
     g.ksteps = (g.kdim + kGK - 1) / kGK;
     const int64_t tiles = g.nt * (g.nt + 1) / 2;
     if (tiles > INT32_MAX || tiles > INT64_MAX / g.ksteps) return set_error(NQS_EINVAL, "Gram matrix too large");
-    g.work = tiles * g.ksteps;
     const int64_t slots = (int64_t)device_cus() * 2;
-    g.grid = (int)std::min<int64_t>(slots, g.work);
+    g.grid = (int)std::min<int64_t>(slots, tiles * g.ksteps);
+    g.dp_tiles = tiles >= g.grid ? tiles / g.grid * g.grid : 0;
+    g.work = (tiles - g.dp_tiles) * g.ksteps;
     g.alpha = (float)(1.0 / (double)n);
 
     const size_t mu_bytes = (sizeof(float) * (size_t)P + 255) & ~(size_t)255;
@@ -364,8 +377,10 @@ nqs_status launch_gram(const float *O, int64_t n, int64_t P, int mode, float *ou
         else launch_gram_kernel<false, false>(g, stream);
     }
     NQS_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(gram_fixup_kernel, dim3((unsigned)tiles), dim3(256), 0, stream, g);
-    NQS_HIP_TRY(hipGetLastError());
+    if (g.work > 0) {
+        hipLaunchKernelGGL(gram_fixup_kernel, dim3((unsigned)(tiles - g.dp_tiles)), dim3(256), 0, stream, g);
+        NQS_HIP_TRY(hipGetLastError());
+    }
     return NQS_OK;
 }
 
