@@ -53,7 +53,7 @@ def _args():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20"])
     ap.add_argument("--sweeps", type=int, default=0, help="heis20: measured sweeps per step (default 1)")
-    ap.add_argument("--dtype", default="bf16", choices=["bf16", "f16", "f32"])
+    ap.add_argument("--dtype", default="bf16", choices=["bf16", "f16", "f32", "e4m3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison step")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per chain of the RBM sampler (0 = library default)")
@@ -215,22 +215,39 @@ def _common(a, wl, props, ms, phases, step, data):
     }
 
 
-def _compare_fp32(a, nqs, torch, wl, params, step, ms, props, eloc_dtype, with_gram):
+def _paired(nqs, torch, x, y, n_chains):
+    """Mean of the paired local-energy differences x - y and its chain-mean standard error."""
+    diff = (x - y).contiguous()
+    dstats = torch.empty(4, dtype=torch.float64, device=diff.device)
+    nqs.nqs_energy_stats(diff, n_chains, dstats)
+    d = dstats.cpu().numpy()
+    return {"value": float(d[0]), "stderr_paired": float(d[2])}
+
+
+def _compare_fp32(a, nqs, torch, wl, params, step, ms, props, eloc_dtype, with_gram, others=()):
     ref = Step(nqs, torch, wl, params, "f32", a.lanes, a.refresh, eloc_dtype="f32", with_gram=with_gram)
     ms32, ph32 = ref.timed(a.steps, a.warmup)
     st32 = ref.stats.cpu().numpy()
-    diff = (step.eloc - ref.eloc).contiguous()
-    dstats = torch.empty(4, dtype=torch.float64, device=diff.device)
-    nqs.nqs_energy_stats(diff, wl.n_chains, dstats)
-    d = dstats.cpu().numpy()
-    return {"fp32": {"proposals_per_s": props / (ms32 * 1e-3), "ms_per_step": ms32,
-                     "sampler_proposals_per_s": props / (ph32["sample"] * 1e-3),
-                     "phases_ms": {k: round(v, 3) for k, v in ph32.items()},
-                     "energy": {"mean": st32[0], "stderr": st32[2]}},
-            "speedup_vs_fp32": ms32 / ms,
-            "dE_vs_fp32": {"value": d[0], "stderr_paired": d[2],
-                           "note": "same seeds; chain-mean standard error of the paired local-energy differences; "
-                                   "the FP32 path's accept decisions equal the FP64 oracle's outside near ties"}}
+    out = {"fp32": {"proposals_per_s": props / (ms32 * 1e-3), "ms_per_step": ms32,
+                    "sampler_proposals_per_s": props / (ph32["sample"] * 1e-3),
+                    "phases_ms": {k: round(v, 3) for k, v in ph32.items()},
+                    "energy": {"mean": st32[0], "stderr": st32[2]}},
+           "speedup_vs_fp32": ms32 / ms,
+           "dE_vs_fp32": dict(_paired(nqs, torch, step.eloc, ref.eloc, wl.n_chains),
+                              note="same seeds; chain-mean standard error of the paired local-energy differences; "
+                                   "the FP32 path's accept decisions equal the FP64 oracle's outside near ties")}
+    # the other sampling formats, one timed step each, same seeds
+    for dt in others:
+        if dt == a.dtype:
+            continue
+        o = Step(nqs, torch, wl, params, dt, a.lanes, a.refresh, eloc_dtype=dt if eloc_dtype != "f32" else "f32",
+                 with_gram=with_gram)
+        mso, pho = o.timed(1, 1)
+        out.setdefault("other_formats", {})[dt] = {
+            "ms_per_step": round(mso, 3), "sample_ms": round(pho["sample"], 3),
+            "dE_vs_fp32": _paired(nqs, torch, o.eloc, ref.eloc, wl.n_chains)}
+        del o
+    return out
 
 
 def run_tfim10(a, torch, nqs, workloads):
@@ -246,11 +263,12 @@ def run_tfim10(a, torch, nqs, workloads):
                      "chains": C, "sweeps": S, "burnin": B, "proposals_per_step": props, "samples_per_step": S * C,
                      "refresh_sweeps": a.refresh, "lanes_per_chain": a.lanes or "default",
                      "parallelism": "single GPU"}
-    # FP32-VALU work of the product-form single flip: 3M per proposal (ratio
-    # factors), 4M per accepted proposal (state update), and the refresh
-    # theta = W s + b (2 N M flops every `refresh` sweeps of N proposals).
+    # FP32-VALU work of the product-form single flip: 4M per proposal (per hidden
+    # unit c C, the FMA with s S, the product), 3M per accepted proposal (the
+    # state update s C - s_i c S), and the refresh theta = W s + b (2 N M flops
+    # every `refresh` sweeps of N proposals).
     acc = out["acceptance"]
-    fpp = 3.0 * M + 4.0 * M * acc + 2.0 * M / a.refresh
+    fpp = 4.0 * M + 3.0 * M * acc + 2.0 * M / a.refresh
     achieved = props * fpp / (phases["sample"] * 1e-3) / 1e12
     out["roofline"] = {"kernel": "rbm_sample_kernel", "bound": "alu", "achieved": round(achieved, 3),
                        "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
@@ -259,7 +277,7 @@ def run_tfim10(a, torch, nqs, workloads):
                        "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
                        "flops_per_proposal": round(fpp, 2), "proposals_per_launch": props}
     if not a.no_compare:
-        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, "f32", True))
+        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, "f32", True, others=("f16", "e4m3")))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, params)
     return out
@@ -286,7 +304,7 @@ def run_heis10(a, torch, nqs, workloads):
                        "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
                        "flops_per_proposal": fpp, "proposals_per_launch": props}
     if not a.no_compare:
-        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, a.dtype, False))
+        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, a.dtype, False, others=("f16",)))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, params, budget_s=15.0)
     return out

@@ -105,18 +105,21 @@ struct RegSampleLds {
         b += sizeof(float) * m2p;                             // b2
         b += sizeof(float) * kRegWaves * kRegRows;            // partial sums
         b += sizeof(uint32_t) * (size_t)kRegRows * NW;        // spin words
-        b += sizeof(int) * kRegRows * 5 + sizeof(float) * kRegRows * 3;   // per-chain proposal state
-        b += 16;
+        b += sizeof(int) * 4 + 16;                            // slot counters
         return b;
     }
 };
 
+// Each wave owns 8 chains: it draws their proposals (lanes 0..7), stages the
+// effective ones at slots taken from a shared counter, and after the matrix
+// product decides them and updates their state.  Two barriers per step: after
+// the staging (h1 rows complete) and after the product (partial sums complete).
 template <typename T, int KF, bool TRACE>
 __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSampleArgs A)
 {
     typedef typename Mc<T>::frag frag;
     constexpr int QK = KF / 4;                      // hidden units per lane (m1p = 64 QK)
-    constexpr int RPW = kRegRows / kRegWaves;       // chains per wave
+    constexpr int RPW = kRegRows / kRegWaves;       // chains per wave (8)
     extern __shared__ __align__(16) unsigned char smem[];
     const FfnnDev &net = A.net;
     const int N = net.widths[0], m1p = net.m1p, m2p = net.m2p, m2 = net.widths[2];
@@ -128,19 +131,13 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     float *b2s = reinterpret_cast<float *>(Hs + (size_t)kRegRows * ldh);
     float *part = b2s + m2p;
     uint32_t *words = reinterpret_cast<uint32_t *>(part + kRegWaves * kRegRows);
-    int *pi = reinterpret_cast<int *>(words + kRegRows * NW);
-    int *pj = pi + kRegRows;
-    int *peff = pj + kRegRows;
-    int *pslot = peff + kRegRows;
-    int *pupd = pslot + kRegRows;
-    float *pl2u = reinterpret_cast<float *>(pupd + kRegRows);
-    float *fcur = pl2u + kRegRows;
-    float *psgn = fcur + kRegRows;
-    int *s_neff = reinterpret_cast<int *>(psgn + kRegRows);
+    int *cnt = reinterpret_cast<int *>(words + kRegRows * NW);   // [2] slots taken in the current / next step
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * kRegRows;
     const int nvalid = (int)min<int64_t>(kRegRows, A.n_chains - c0);
+    const int myrow = wave * RPW + (lane & (RPW - 1));           // the chain of proposal lanes 0..7
+    const bool plane = lane < RPW && myrow < nvalid;
 
     frag a[KF];
     reg_load_w2<T, KF>(reinterpret_cast<const T *>(A.W2), m1p, m2p, a);
@@ -159,6 +156,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             }
             words[k] = bits;
         }
+        if (tid < 2) cnt[tid] = 0;
     }
     __syncthreads();
 
@@ -181,10 +179,9 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             }
         }
     };
-    // layer-1 change of a chain's proposal (i, j >= 0 for an exchange)
-    auto delta_z1 = [&](int row, float (&dz)[QK]) {
-        const int i = pi[row], j = pj[row];
-        const float g = -2.0f * psgn[row];
+    // layer-1 change of flipping i (and j >= 0) where site i holds spin si
+    auto delta_z1 = [&](int i, int j, float si, float (&dz)[QK]) {
+        const float g = -2.0f * si;
 #pragma unroll
         for (int q = 0; q < QK; ++q) {
             const int k = lane + 64 * q;
@@ -193,8 +190,8 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             dz[q] = g * d;
         }
     };
-    // f of all 64 chains from the current z1 (h1 staged at slot = chain)
-    auto full_eval = [&]() {
+    // log|psi| of this wave's chains from the current z1 (lanes 0..7 return their chain's value)
+    auto full_eval = [&]() -> float {
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int row = wave * RPW + r;
@@ -207,15 +204,13 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
         }
         __syncthreads();
-        if (tid < kRegRows) {
-            float f = 0.0f;
-            for (int w = 0; w < nwt; ++w) f += part[w * kRegRows + tid];
-            fcur[tid] = f;
-        }
+        float f = 0.0f;
+        for (int w = 0; w < nwt; ++w) f += part[w * kRegRows + myrow];
+        return f;
     };
 
     refresh_z1();
-    full_eval();
+    float fcur = full_eval();   // meaningful on proposal lanes
 
     const int sw = A.sweep_size;
     const int64_t total = (int64_t)(A.n_burnin + A.n_sweeps) * sw;
@@ -224,90 +219,85 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     int in_sweep = 0, since_refresh = 0;
     int64_t sweep = 0;
     for (int64_t k = 0; k < total; ++k) {
-        // proposals: wave 0, one lane per chain; effective ones get consecutive slots
-        if (tid < kRegRows) {
+        // proposals of this wave's chains (lanes 0..7); effective ones take a slot
+        int pi = 0, pj = -1, slot = -1;
+        float si = 1.0f;
+        uint32_t ub = 0;
+        if (plane) {
             const uint64_t step = A.step_offset + (uint64_t)k;
-            const uint32_t gid = A.chain_id_offset + (uint32_t)(c0 + tid);
+            const uint32_t gid = A.chain_id_offset + (uint32_t)(c0 + myrow);
             const Block4 rb = philox4x32_10((uint32_t)step, (uint32_t)(step >> 32), gid, A.inst << 8, key0, key1);
-            const int i = index_from_word(rb.r0, N);
-            int j = -1;
+            pi = index_from_word(rb.r0, N);
             if (A.move == 1) {
-                j = index_from_word(rb.r1, N - 1);
-                j += (j >= i) ? 1 : 0;
+                pj = index_from_word(rb.r1, N - 1);
+                pj += (pj >= pi) ? 1 : 0;
             }
-            const uint32_t *w = words + tid * NW;
-            const bool si = (w[i >> 5] >> (i & 31)) & 1u;
-            const bool eff = tid < nvalid && (j < 0 || si != (bool)((w[j >> 5] >> (j & 31)) & 1u));
-            const unsigned long long bal = __ballot(eff);
-            pi[tid] = i;
-            pj[tid] = j;
-            peff[tid] = eff ? 1 : 0;
-            pslot[tid] = eff ? (int)__popcll(bal & ((1ull << tid) - 1ull)) : -1;
-            if (tid == 0) *s_neff = (int)__popcll(bal);
-            psgn[tid] = si ? 1.0f : -1.0f;
-            const uint32_t ub = rb.r2 >> 8;
-            pl2u[tid] = __builtin_amdgcn_logf((float)ub * 5.9604644775390625e-8f);
-            pupd[tid] = (int)ub;   // u bits kept for the trace until the decision
+            const uint32_t *w = words + myrow * NW;
+            const bool up = (w[pi >> 5] >> (pi & 31)) & 1u;
+            si = up ? 1.0f : -1.0f;
+            const bool eff = pj < 0 || up != (bool)((w[pj >> 5] >> (pj & 31)) & 1u);
+            if (eff) slot = atomicAdd(&cnt[k & 1], 1);
+            ub = rb.r2 >> 8;
         }
-        __syncthreads();
-        // stage h1 of this wave's effective proposals
+        // stage h1 of the effective proposals (rows are wave-uniform)
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const int row = wave * RPW + r;
-            const int slot = pslot[row];
-            if (slot >= 0) {
+            const int sl = __builtin_amdgcn_readlane(slot, r);
+            if (sl >= 0) {
+                const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
+                const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
                 float dz[QK];
-                delta_z1(row, dz);
+                delta_z1(i, j, s_i, dz);
 #pragma unroll
                 for (int q = 0; q < QK; ++q)
-                    Hs[slot * ldh + lane + 64 * q] = Mc<T>::from_f32(fmaxf(z1[r][q] + dz[q], 0.0f));
+                    Hs[sl * ldh + lane + 64 * q] = Mc<T>::from_f32(fmaxf(z1[r][q] + dz[q], 0.0f));
             }
         }
         __syncthreads();
-        const int neff = *s_neff;
+        const int neff = cnt[k & 1];
         for (int t = 0; 32 * t < neff; ++t) {
             const float s = reg_tile_logcosh<T, KF>(a, Hs, ldh, 32 * t, b2s, m2);
             if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
         }
+        if (tid == 0) cnt[(k + 1) & 1] = 0;   // read next in step k + 1, after the barrier below
         __syncthreads();
-        if (tid < kRegRows) {
-            const int slot = pslot[tid];
-            const bool eff = slot >= 0;
+        // decisions of this wave's chains
+        bool upd = false;
+        if (plane) {
             float fnew = 0.0f;
-            if (eff)
+            if (slot >= 0)
                 for (int w = 0; w < nwt; ++w) fnew += part[w * kRegRows + slot];
-            const float d2 = eff ? 2.0f * (fnew - fcur[tid]) / kLn2f : 0.0f;
-            const bool accept = pl2u[tid] < d2;
-            const uint32_t ub = (uint32_t)pupd[tid];
-            if (tid < nvalid && accept) ++acc;
-            const bool upd = accept && eff;
+            const float d2 = slot >= 0 ? 2.0f * (fnew - fcur) / kLn2f : 0.0f;
+            const float l2u = __builtin_amdgcn_logf((float)ub * 5.9604644775390625e-8f);
+            const bool accept = l2u < d2;   // NaN rejects
+            if (accept) ++acc;
+            upd = accept && slot >= 0;
             if (upd) {
-                uint32_t *w = words + tid * NW;
-                const int i = pi[tid], j = pj[tid];
-                w[i >> 5] ^= 1u << (i & 31);
-                if (j >= 0) w[j >> 5] ^= 1u << (j & 31);
-                fcur[tid] = fnew;
+                uint32_t *w = words + myrow * NW;
+                w[pi >> 5] ^= 1u << (pi & 31);
+                if (pj >= 0) w[pj >> 5] ^= 1u << (pj & 31);
+                fcur = fnew;
             }
             if constexpr (TRACE) {
-                const int64_t c = c0 + tid;
+                const int64_t c = c0 + myrow;
                 if (c < A.n_traced) {
                     const size_t idx = (size_t)c * (size_t)total + (size_t)k;
-                    A.tr_site[idx] = pi[tid] | ((pj[tid] < 0 ? 0xFFFF : pj[tid]) << 16);
+                    A.tr_site[idx] = pi | ((pj < 0 ? 0xFFFF : pj) << 16);
                     A.tr_ubits[idx] = ub;
                     A.tr_delta[idx] = d2 * kLn2f;
                     A.tr_acc[idx] = accept ? 1 : 0;
                 }
             }
-            pupd[tid] = upd ? 1 : 0;
         }
-        __syncthreads();
-        // apply accepted moves to z1 (psgn still holds the pre-move spin)
+        // apply the accepted moves to z1
+        const unsigned long long um = __ballot(upd);
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const int row = wave * RPW + r;
-            if (pupd[row]) {
+            if ((um >> r) & 1ull) {
+                const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
+                const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
                 float dz[QK];
-                delta_z1(row, dz);
+                delta_z1(i, j, s_i, dz);
 #pragma unroll
                 for (int q = 0; q < QK; ++q) z1[r][q] += dz[q];
             }
@@ -316,31 +306,32 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             in_sweep = 0;
             const int64_t out = sweep - A.n_burnin;
             if (++since_refresh == A.refresh_sweeps) {
-                __syncthreads();   // every wave has read pupd/pslot of this step
                 refresh_z1();
-                full_eval();
+                const float f = full_eval();
+                if (plane) fcur = f;
                 since_refresh = 0;
             }
-            __syncthreads();
             if (out >= 0) {
                 if (A.samples) {
-                    for (int idx = tid; idx < nvalid * N; idx += kRegThreads) {
-                        const int r = idx / N, i = idx % N;
-                        A.samples[((size_t)out * A.n_chains + c0 + r) * N + i] =
-                            ((words[r * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1 : -1;
+                    // this wave's chains: lane = site within a word row
+                    for (int idx = lane; idx < RPW * N; idx += 64) {
+                        const int r = idx / N, i = idx % N, row = wave * RPW + r;
+                        if (row < nvalid)
+                            A.samples[((size_t)out * A.n_chains + c0 + row) * N + i] =
+                                ((words[row * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1 : -1;
                     }
                 }
-                if (A.logpsi && tid < nvalid) A.logpsi[(size_t)out * A.n_chains + c0 + tid] = fcur[tid];
+                if (A.logpsi && plane) A.logpsi[(size_t)out * A.n_chains + c0 + myrow] = fcur;
             }
             ++sweep;
         }
-        __syncthreads();
     }
-    for (int idx = tid; idx < nvalid * N; idx += kRegThreads) {
-        const int r = idx / N, i = idx % N;
-        A.chain_state[(c0 + r) * N + i] = ((words[r * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1 : -1;
+    for (int idx = lane; idx < RPW * N; idx += 64) {
+        const int r = idx / N, i = idx % N, row = wave * RPW + r;
+        if (row < nvalid)
+            A.chain_state[(c0 + row) * N + i] = ((words[row * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1 : -1;
     }
-    if (A.n_acc && tid < nvalid) A.n_acc[c0 + tid] = acc;
+    if (A.n_acc && plane) A.n_acc[c0 + myrow] = acc;
 }
 
 // ---------------------------------------------------------------------------
