@@ -62,15 +62,25 @@ __device__ __forceinline__ float reg_tile_logcosh(const typename Mc<T>::frag (&a
     typedef typename Mc<T>::frag frag;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 31, lh = lane >> 5;
-    mc_floatx16 acc;
+    // two accumulators (even / odd fragments), so consecutive matrix-core steps do not wait on each other
+    mc_floatx16 acc, acc1;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    for (int r = 0; r < 16; ++r) {
+        acc[r] = 0.0f;
+        acc1[r] = 0.0f;
+    }
     const T *hrow = Hs + (row0 + lr) * ldh + 8 * lh;
 #pragma unroll
-    for (int kf = 0; kf < KF; ++kf) {
-        const frag b = *reinterpret_cast<const frag *>(hrow + kf * 16);
-        acc = Mc<T>::mma(a[kf], b, acc);
+    for (int kf = 0; kf < KF; kf += 2) {
+        const frag b0 = *reinterpret_cast<const frag *>(hrow + kf * 16);
+        acc = Mc<T>::mma(a[kf], b0, acc);
+        if (kf + 1 < KF) {
+            const frag b1 = *reinterpret_cast<const frag *>(hrow + (kf + 1) * 16);
+            acc1 = Mc<T>::mma(a[kf + 1], b1, acc1);
+        }
     }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] += acc1[r];
     // D[i][j]: i = output (row of W2), j = staged row; lane = j + 32*((i/4)%2), register = i%4 + 4*(i/8)
     float abs_sum = 0.0f, prod = 1.0f;
     int cnt = 0;
