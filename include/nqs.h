@@ -14,8 +14,11 @@
  *   nqs_energy_stats   FP64 mean / variance / error bar of the local energies (Eq. eq:loss)
  *   nqs_logpsi_grad    O_k(x) = d log psi(x) / d theta_k (App. I.1, Eq. eq:forces)
  *   nqs_forces         F = E[O eps] - E[O] E[eps] (Eq. eq:forces), FP64
+ *   nqs_logpsi_grad_cols  a column block of O (same equation)
  *   nqs_gram           S = E[Obar^T Obar] (Eq. eq:smat) or its sample-space twin
  *                      T = Obar Obar^T / n, FP32 matrix cores
+ *   nqs_sample_gram    T accumulated over column blocks of O, so that O is
+ *                      never held whole (large networks)
  *
  * Conventions (every entry point):
  *   - All array arguments are DEVICE pointers unless marked "host".  The
@@ -194,6 +197,13 @@ nqs_status nqs_energy_stats(const double *eloc, int64_t n, int64_t n_chains, dou
 nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
                            const float *vjp_in, float *vjp_out, void *stream);
 
+/* Columns [p0, p1) of O (Eq. eq:forces, the log-derivatives): O[n][p1 - p0],
+ * row-major, O[k][p - p0] = d log psi(x_k) / d theta_p, FP32 copy.  The
+ * parameter order is the one of nqs_logpsi_grad.  NQS_EINVAL unless
+ * 0 <= p0 < p1 <= P. */
+nqs_status nqs_logpsi_grad_cols(nqs_model *m, const int8_t *samples, int64_t n, int64_t p0, int64_t p1, float *O,
+                                void *stream);
+
 /* F[P] = mean_k O[k] eps[k] - mean_k O[k] * mean_k eps[k] and Omean[P]
  * (both FP64; Omean may be NULL). */
 nqs_status nqs_forces(const float *O, const double *eloc, int64_t n, int64_t P, double *F, double *Omean,
@@ -202,8 +212,20 @@ nqs_status nqs_forces(const float *O, const double *eloc, int64_t n, int64_t P, 
 /* Centred Gram matrix on FP32 matrix cores, Obar = O - mean over samples:
  *   mode 0: S[P][P] = Obar^T Obar / n      (Eq. eq:smat)
  *   mode 1: T[n][n] = Obar Obar^T / n      (same non-zero spectrum)
- * `out` is FP32, row-major. */
+ *   mode 2: T[n][n] += Obar Obar^T / n     (O a column block; summing the
+ *           blocks of all parameters gives the T of mode 1)
+ * `out` is FP32, row-major; in mode 2 it must hold the sum so far. */
 nqs_status nqs_gram(const float *O, int64_t n, int64_t P, int32_t mode, float *out, void *stream);
+
+/* T[n][n] = Obar Obar^T / n of the samples (Eq. eq:smat taken in sample
+ * space), without ever holding all of O: the parameters are walked in column
+ * blocks of `chunk_params` (0 = automatic, blocks of at most 1 GiB), each block
+ * of O is recomputed by the gradient kernel into the library workspace and its
+ * T accumulated on the matrix cores.  T is overwritten.  Blocks are summed in
+ * parameter order, so the result does not depend on timing but does depend
+ * on chunk_params through FP32 rounding. */
+nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64_t chunk_params, float *T,
+                           void *stream);
 
 const char *nqs_last_error(void);
 const char *nqs_version(void);

@@ -21,7 +21,7 @@ from ._abi import DTYPE_CODES, NqsError, check, load
 
 __all__ = [
     "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
-    "nqs_forces", "nqs_gram", "nqs_downcast", "LogPsi", "NqsError", "load",
+    "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_downcast", "LogPsi", "NqsError", "load",
 ]
 
 
@@ -233,6 +233,20 @@ def nqs_logpsi_grad(model: Model, samples: torch.Tensor, logpsi: Optional[torch.
         assert vjp_out is not None and vjp_out.dtype == torch.float32 and vjp_out.numel() == P
     check(load().nqs_logpsi_grad(model.handle, _ptr(samples), n, _ptr(logpsi), _ptr(O), _ptr(vjp_in), _ptr(vjp_out),
                                  _stream(stream)))
+
+
+def nqs_logpsi_grad_cols(model: Model, samples: torch.Tensor, p0: int, p1: int, O: torch.Tensor,
+                         stream=None) -> None:
+    n = samples.numel() // model.n_visible
+    assert O.dtype == torch.float32 and O.numel() == n * (p1 - p0)
+    check(load().nqs_logpsi_grad_cols(model.handle, _ptr(samples), n, p0, p1, _ptr(O), _stream(stream)))
+
+
+def nqs_sample_gram(model: Model, samples: torch.Tensor, T: torch.Tensor, chunk_params: int = 0,
+                    stream=None) -> None:
+    n = samples.numel() // model.n_visible
+    assert T.dtype == torch.float32 and T.numel() == n * n
+    check(load().nqs_sample_gram(model.handle, _ptr(samples), n, chunk_params, _ptr(T), _stream(stream)))
 
 
 def nqs_forces(O: torch.Tensor, eloc: torch.Tensor, F: torch.Tensor, Omean: Optional[torch.Tensor] = None,

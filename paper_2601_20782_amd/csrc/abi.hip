@@ -1,6 +1,7 @@
 // C entry points of libnqs: argument validation, model handles, dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -309,8 +310,52 @@ nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float
     if (!samples) return set_error(NQS_EINVAL, "NULL samples");
     if ((vjp_in == nullptr) != (vjp_out == nullptr)) return set_error(NQS_EINVAL, "vjp_in and vjp_out go together");
     hipStream_t s = (hipStream_t)stream;
-    if (m->desc.arch == NQS_RBM) return rbm_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s);
-    return ffnn_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s);
+    if (m->desc.arch == NQS_RBM) return rbm_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s, 0, m->P);
+    return ffnn_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s, 0, m->P);
+}
+
+nqs_status nqs_logpsi_grad_cols(nqs_model *m, const int8_t *samples, int64_t n, int64_t p0, int64_t p1, float *O,
+                                void *stream)
+{
+    if (!m) return set_error(NQS_EINVAL, "NULL model");
+    if (n < 0) return set_error(NQS_EINVAL, "n < 0");
+    if (p0 < 0 || p1 <= p0 || p1 > m->P) return set_error(NQS_EINVAL, "need 0 <= p0 < p1 <= P");
+    if (n == 0) return NQS_OK;
+    if (!samples || !O) return set_error(NQS_EINVAL, "NULL samples/O");
+    hipStream_t s = (hipStream_t)stream;
+    if (m->desc.arch == NQS_RBM) return rbm_logpsi_grad(m, samples, n, nullptr, O, nullptr, nullptr, s, p0, p1);
+    return ffnn_logpsi_grad(m, samples, n, nullptr, O, nullptr, nullptr, s, p0, p1);
+}
+
+nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64_t chunk_params, float *T,
+                           void *stream)
+{
+    if (!m) return set_error(NQS_EINVAL, "NULL model");
+    if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
+    if (!samples || !T) return set_error(NQS_EINVAL, "NULL samples/T");
+    if (chunk_params < 0) return set_error(NQS_EINVAL, "chunk_params < 0");
+    const int64_t P = m->P;
+    int64_t chunk = chunk_params;
+    if (chunk == 0) {
+        // automatic: a column block of at most 1 GiB, a multiple of the contraction step
+        chunk = std::max<int64_t>(32, ((int64_t)(1ll << 28) / n) & ~(int64_t)31);
+    }
+    chunk = std::min(chunk, P);
+    const size_t oc_bytes = (sizeof(float) * (size_t)n * (size_t)chunk + 255) & ~(size_t)255;
+    char *ws = (char *)workspace(oc_bytes + gram_workspace_bytes(n, chunk), (hipStream_t)stream);
+    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    float *Oc = (float *)ws;
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t p0 = 0; p0 < P; p0 += chunk) {
+        const int64_t p1 = std::min(P, p0 + chunk);
+        nqs_status st = m->desc.arch == NQS_RBM
+                            ? rbm_logpsi_grad(m, samples, n, nullptr, Oc, nullptr, nullptr, s, p0, p1)
+                            : ffnn_logpsi_grad(m, samples, n, nullptr, Oc, nullptr, nullptr, s, p0, p1);
+        if (st != NQS_OK) return st;
+        st = launch_gram_ws(Oc, n, p1 - p0, p0 == 0 ? 1 : 2, T, ws + oc_bytes, s);
+        if (st != NQS_OK) return st;
+    }
+    return NQS_OK;
 }
 
 nqs_status nqs_forces(const float *O, const double *eloc, int64_t n, int64_t P, double *F, double *Omean, void *stream)
@@ -324,7 +369,7 @@ nqs_status nqs_gram(const float *O, int64_t n, int64_t P, int32_t mode, float *o
 {
     if (n <= 0 || P <= 0) return set_error(NQS_EINVAL, "n and P must be positive");
     if (!O || !out) return set_error(NQS_EINVAL, "NULL O/out");
-    if (mode != 0 && mode != 1) return set_error(NQS_EINVAL, "mode must be 0 (S) or 1 (T)");
+    if (mode < 0 || mode > 2) return set_error(NQS_EINVAL, "mode must be 0 (S), 1 (T) or 2 (T accumulate)");
     return launch_gram(O, n, P, mode, out, (hipStream_t)stream);
 }
 

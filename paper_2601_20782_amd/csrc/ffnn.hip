@@ -160,8 +160,9 @@ struct GradArgs {
     const int8_t *samples;
     int64_t n;
     float *logpsi;
-    float *O;
+    float *O;         // columns [p0, p1) of O, row stride p1 - p0
     int64_t P;
+    int64_t p0, p1;
     int lds_stride;   // floats reserved per layer activation vector
 };
 
@@ -204,7 +205,8 @@ __global__ void __launch_bounds__(256) ffnn_grad_kernel(GradArgs A)
         __syncthreads();
         if (tid == 0 && A.logpsi) A.logpsi[smp] = red[0] + red[1] + red[2] + red[3];
         if (A.O) {
-            float *O = A.O + smp * A.P;
+            const int64_t p0 = A.p0, p1 = A.p1;
+            float *O = A.O + smp * (p1 - p0) - p0;   // O[p] for p in [p0, p1)
             // parameter offsets
             int64_t offW[NQS_MAX_LAYERS], offb[NQS_MAX_LAYERS], off = 0;
             for (int l = 0; l < L; ++l) {
@@ -219,18 +221,25 @@ __global__ void __launch_bounds__(256) ffnn_grad_kernel(GradArgs A)
             for (int l = L - 1; l >= 0; --l) {
                 const int out = net.widths[l + 1], in = net.widths[l];
                 const float *src = l == 0 ? in0 : z + (size_t)(l - 1) * S;
-                for (int r = tid; r < out; r += nt) O[offb[l] + r] = d[r];
-                // O_W[r][k] = d[r] * h[k], consecutive threads on consecutive k
-                for (int r = 0; r < out; ++r) {
+                for (int r = tid; r < out; r += nt)
+                    if (offb[l] + r >= p0 && offb[l] + r < p1) O[offb[l] + r] = d[r];
+                // O_W[r][k] = d[r] * h[k], consecutive threads on consecutive k; rows
+                // [r0, r1) of this layer meet the column range
+                const int r0 = (int)min((int64_t)out, max((int64_t)0, (p0 - offW[l]) / in));
+                const int r1 = (int)min((int64_t)out, max((int64_t)0, (p1 - offW[l] + in - 1) / in));
+                for (int r = r0; r < r1; ++r) {
                     const float dr = d[r];
-                    float *orow = O + offW[l] + (int64_t)r * in;
+                    const int64_t rb = offW[l] + (int64_t)r * in;
+                    const int k0 = (int)max((int64_t)0, p0 - rb), k1 = (int)min((int64_t)in, p1 - rb);
+                    float *orow = O + rb;
                     if (l == 0) {
-                        for (int k = tid; k < in; k += nt) orow[k] = dr * src[k];
+                        for (int k = k0 + tid; k < k1; k += nt) orow[k] = dr * src[k];
                     } else {
-                        for (int k = tid; k < in; k += nt) orow[k] = dr * fmaxf(src[k], 0.0f);
+                        for (int k = k0 + tid; k < k1; k += nt) orow[k] = dr * fmaxf(src[k], 0.0f);
                     }
                 }
-                if (l == 0) break;
+                // parameters of the layers below lie before offW[l]
+                if (l == 0 || offW[l] <= p0) break;
                 float *dn = (d == dl) ? dl + S : dl;
                 const float *W = net.W[l];
                 for (int k = tid; k < in; k += nt) {
@@ -258,7 +267,7 @@ __global__ void vjp_chunk_kernel(const float *__restrict__ O, const float *__res
 }
 
 nqs_status ffnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
-                            const float *vjp_in, float *vjp_out, hipStream_t stream)
+                            const float *vjp_in, float *vjp_out, hipStream_t stream, int64_t p0, int64_t p1)
 {
     nqs_status st = ensure_copy(m, NQS_F32, stream);
     if (st != NQS_OK) return st;
@@ -268,6 +277,8 @@ nqs_status ffnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, floa
     GradArgs A;
     A.net = net;
     A.P = m->P;
+    A.p0 = p0;
+    A.p1 = p1;
     A.lds_stride = (maxw + 3) & ~3;
     const size_t lds = sizeof(float) * (size_t)A.lds_stride * (1 + net.n_layers + 2);
     if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too wide for the gradient kernel");
@@ -293,6 +304,8 @@ nqs_status ffnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, floa
             A.n = kn;
             A.logpsi = nullptr;
             A.O = Ow;
+            A.p0 = 0;
+            A.p1 = P;
             hipLaunchKernelGGL(ffnn_grad_kernel, dim3((unsigned)std::min<int64_t>(kn, 4096)), dim3(256), lds, stream, A);
             hipLaunchKernelGGL(vjp_chunk_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, Ow,
                                vjp_in + k0, kn, P, vjp_out, k0 == 0 ? 1 : 0);

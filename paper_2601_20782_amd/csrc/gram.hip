@@ -1,7 +1,9 @@
 // Centred Gram matrices of the log-derivatives on FP32 matrix cores:
 //   mode 0:  S = Obar^T Obar / n   (Eq. eq:smat, P x P)
 //   mode 1:  T = Obar Obar^T / n   (n x n; same non-zero spectrum as S)
-// with Obar = O - (column means over samples).
+//   mode 2:  T += Obar Obar^T / n  (T summed over column blocks of O)
+// with Obar = O - (column means over samples).  Centring is per column, so the
+// T of a column block of O is that block's share of the whole T.
 //
 // Work decomposition: the output is cut into 128 x 128 tiles, of which only
 // those on or above the diagonal are computed; the contraction of a tile is cut
@@ -80,6 +82,7 @@ struct GramArgs {
     int64_t dp_tiles;   // tiles done whole in data-parallel rounds (a multiple of grid)
     int64_t work;       // (remaining tiles) x ksteps, shared out stream-K
     int grid;
+    int accum;          // add into out instead of overwriting it
     float alpha;
 };
 
@@ -260,8 +263,12 @@ __global__ void __launch_bounds__(256, 2) gram_kernel(GramArgs g)
                         const int64_t gi = m0 + ti, gj = n0 + tj;
                         if (gi < g.side && gj < g.side) {
                             const float v = g.alpha * acc[a][b][r];
-                            g.out[gi * g.side + gj] = v;
-                            if (bi != bj) g.out[gj * g.side + gi] = v;
+                            float *o1 = g.out + gi * g.side + gj;
+                            *o1 = g.accum ? *o1 + v : v;
+                            if (bi != bj) {
+                                float *o2 = g.out + gj * g.side + gi;
+                                *o2 = g.accum ? *o2 + v : v;
+                            }
                         }
                     } else {
                         pt[ti * kGT + tj] = acc[a][b][r];
@@ -313,13 +320,19 @@ __global__ void __launch_bounds__(256) gram_fixup_kernel(GramArgs g)
         for (int idx = threadIdx.x; idx < kHalf * kGT; idx += blockDim.x) {
             const int ti = idx / kGT, tj = idx % kGT;
             const int64_t gi = m0 + r0 + ti, gj = n0 + tj;
-            if (gi < g.side && gj < g.side) g.out[gi * g.side + gj] = tileS[ti][tj];
+            if (gi < g.side && gj < g.side) {
+                float *o = g.out + gi * g.side + gj;
+                *o = g.accum ? *o + tileS[ti][tj] : tileS[ti][tj];
+            }
         }
         if (bi != bj) {
             for (int idx = threadIdx.x; idx < kHalf * kGT; idx += blockDim.x) {
                 const int tj = idx / kHalf, ti = idx % kHalf;   // mirror row n0 + tj, column m0 + r0 + ti
                 const int64_t gj = n0 + tj, gi = m0 + r0 + ti;
-                if (gi < g.side && gj < g.side) g.out[gj * g.side + gi] = tileS[ti][tj];
+                if (gi < g.side && gj < g.side) {
+                    float *o = g.out + gj * g.side + gi;
+                    *o = g.accum ? *o + tileS[ti][tj] : tileS[ti][tj];
+                }
             }
         }
         __syncthreads();
@@ -333,30 +346,55 @@ static void launch_gram_kernel(const GramArgs &g, hipStream_t stream)
     hipLaunchKernelGGL((gram_kernel<TMODE, VEC>), dim3(g.grid), dim3(256), kGramLds, stream, g);
 }
 
-nqs_status launch_gram(const float *O, int64_t n, int64_t P, int mode, float *out, hipStream_t stream)
+// Launch geometry shared by the workspace size and the launch.
+static nqs_status gram_plan(int64_t n, int64_t P, int mode, GramArgs &g, int64_t &tiles)
 {
-    const bool tmode = mode == 1;
-    GramArgs g;
-    g.O = O;
-    g.out = out;
+    const bool tmode = mode != 0;
     g.P = P;
     g.side = tmode ? n : P;
     g.kdim = tmode ? P : n;
     g.nt = (g.side + kGT - 1) / kGT;
     g.ksteps = (g.kdim + kGK - 1) / kGK;
-    const int64_t tiles = g.nt * (g.nt + 1) / 2;
+    tiles = g.nt * (g.nt + 1) / 2;
     if (tiles > INT32_MAX || tiles > INT64_MAX / g.ksteps) return set_error(NQS_EINVAL, "Gram matrix too large");
     const int64_t slots = (int64_t)device_cus() * 2;
     g.grid = (int)std::min<int64_t>(slots, tiles * g.ksteps);
     g.dp_tiles = tiles >= g.grid ? tiles / g.grid * g.grid : 0;
     g.work = (tiles - g.dp_tiles) * g.ksteps;
+    g.accum = mode == 2;
     g.alpha = (float)(1.0 / (double)n);
+    return NQS_OK;
+}
 
-    const size_t mu_bytes = (sizeof(float) * (size_t)P + 255) & ~(size_t)255;
-    const size_t part_bytes = sizeof(float) * (size_t)g.grid * 2 * kGT * kGT;
+static size_t gram_mu_bytes(int64_t P) { return (sizeof(float) * (size_t)P + 255) & ~(size_t)255; }
+
+size_t gram_workspace_bytes(int64_t n, int64_t P)
+{
+    // the larger of the two modes' partial-tile areas (both use the same grid bound)
+    const size_t part_bytes = sizeof(float) * (size_t)device_cus() * 2 * 2 * kGT * kGT;
     const size_t cm_bytes = sizeof(double) * (size_t)kColChunks * (size_t)P;
-    char *ws = (char *)workspace(mu_bytes + std::max(part_bytes, cm_bytes), stream);
+    (void)n;
+    return gram_mu_bytes(P) + std::max(part_bytes, cm_bytes);
+}
+
+nqs_status launch_gram(const float *O, int64_t n, int64_t P, int mode, float *out, hipStream_t stream)
+{
+    void *ws = workspace(gram_workspace_bytes(n, P), stream);
     if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    return launch_gram_ws(O, n, P, mode, out, ws, stream);
+}
+
+nqs_status launch_gram_ws(const float *O, int64_t n, int64_t P, int mode, float *out, void *wsp, hipStream_t stream)
+{
+    const bool tmode = mode != 0;
+    GramArgs g;
+    int64_t tiles = 0;
+    nqs_status st = gram_plan(n, P, mode, g, tiles);
+    if (st != NQS_OK) return st;
+    g.O = O;
+    g.out = out;
+    char *ws = (char *)wsp;
+    const size_t mu_bytes = gram_mu_bytes(P);
     float *mu = (float *)ws;
     g.mu = mu;
     g.part = (float *)(ws + mu_bytes);

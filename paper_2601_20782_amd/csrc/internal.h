@@ -139,20 +139,25 @@ nqs_status rbm_sample_launch_g64(const RbmSampleArgs &A, const RbmLaunch &L, hip
 nqs_status rbm_sample_batched(const nqs_sample_job *jobs, int n_jobs, int mode, hipStream_t stream);
 nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
                             double *eloc, hipStream_t stream);
+// O holds parameter columns [p0, p1) (row stride p1 - p0); the full matrix is p0 = 0, p1 = P
 nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
-                           const float *vjp_in, float *vjp_out, hipStream_t stream);
+                           const float *vjp_in, float *vjp_out, hipStream_t stream, int64_t p0, int64_t p1);
 nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream);
 nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
                        float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
 nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
                              double *eloc, hipStream_t stream);
 nqs_status ffnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
-                            const float *vjp_in, float *vjp_out, hipStream_t stream);
+                            const float *vjp_in, float *vjp_out, hipStream_t stream, int64_t p0, int64_t p1);
 nqs_status launch_init_chains(int8_t *chain_state, int64_t n_chains, int N, int move, uint64_t seed,
                               uint32_t inst, int64_t chain_id_offset, hipStream_t stream);
 nqs_status launch_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, hipStream_t stream);
 nqs_status launch_forces(const float *O, const double *eloc, int64_t n, int64_t P, double *F, double *Omean,
                          hipStream_t stream);
+// mode 0 S, 1 T, 2 T accumulated into `out`; the _ws form takes a caller-carved
+// workspace of gram_workspace_bytes(n, P) bytes
 nqs_status launch_gram(const float *O, int64_t n, int64_t P, int mode, float *out, hipStream_t stream);
+size_t gram_workspace_bytes(int64_t n, int64_t P);
+nqs_status launch_gram_ws(const float *O, int64_t n, int64_t P, int mode, float *out, void *ws, hipStream_t stream);
 
 }  // namespace nqs

@@ -437,7 +437,7 @@ nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t 
 template <int B>
 __global__ void __launch_bounds__(256) rbm_grad_kernel(RbmDev net, const int8_t *__restrict__ samples, int64_t n,
                                                        float *__restrict__ logpsi, float *__restrict__ O,
-                                                       float *__restrict__ Tout)
+                                                       float *__restrict__ Tout, int64_t p0, int64_t p1)
 {
     extern __shared__ float smem[];
     const int N = net.N, M = net.M;
@@ -490,17 +490,19 @@ __global__ void __launch_bounds__(256) rbm_grad_kernel(RbmDev net, const int8_t 
         logpsi[base + tid] = s;
     }
     if (!O) return;
-    const int64_t P = (int64_t)N + M + (int64_t)M * N;
+    // columns [p0, p1) of the parameter order (a, b, W), row stride p1 - p0
+    const int64_t NM = (int64_t)N + M, ldo = p1 - p0;
+    const int64_t q0 = max(p0 - NM, (int64_t)0), q1 = min(p1 - NM, (int64_t)M * N);
     for (int b = 0; b < B; ++b) {
         const int64_t row = base + b;
         if (row >= n) break;
-        float *o = O + row * P;
-        for (int p = tid; p < N + M; p += nt) o[p] = p < N ? spT[p * B + b] : tT[(p - N) * B + b];
+        float *o = O + row * ldo - p0;   // o[p] for p in [p0, p1)
+        for (int64_t p = p0 + tid; p < min(p1, NM); p += nt) o[p] = p < N ? spT[p * B + b] : tT[(p - N) * B + b];
         // W block: q = j*N + i, advanced by nt per iteration with (j, i) carried
-        int j = tid / N, i = tid - (tid / N) * N;
+        int j = (int)((q0 + tid) / N), i = (int)((q0 + tid) - (int64_t)j * N);
         const int dj = nt / N, di = nt - (nt / N) * N;
-        float *ow = o + N + M;
-        for (int64_t q = tid; q < (int64_t)M * N; q += nt) {
+        float *ow = o + NM;
+        for (int64_t q = q0 + tid; q < q1; q += nt) {
             ow[q] = tT[j * B + b] * spT[i * B + b];
             i += di;
             j += dj;
@@ -534,7 +536,7 @@ __global__ void rbm_vjp_kernel(int N, int M, const int8_t *__restrict__ samples,
 }
 
 nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
-                           const float *vjp_in, float *vjp_out, hipStream_t stream)
+                           const float *vjp_in, float *vjp_out, hipStream_t stream, int64_t p0, int64_t p1)
 {
     nqs_status st = ensure_copy(m, NQS_F32, stream);
     if (st != NQS_OK) return st;
@@ -554,7 +556,7 @@ nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float
     if (logpsi || O || T) {
         allow_lds(rbm_grad_kernel<B>, lds);
         hipLaunchKernelGGL((rbm_grad_kernel<B>), dim3((unsigned)blocks), dim3(threads), lds, stream, net, samples, n,
-                           logpsi, O, T);
+                           logpsi, O, T, p0, p1);
         NQS_HIP_TRY(hipGetLastError());
     }
     if (vjp_in) {
