@@ -23,7 +23,10 @@ Other workloads (--workload):
   heis20   2D Heisenberg 20x20, Marshall sign, FFNN 400->1600->800->400,
            65536 chains, exchange moves through the batched-GEMM path; a step
            is --sweeps sweeps (default 1; the full 220-sweep run is ~10^3 times
-           longer) plus local energies of 1024 of the last sweep's samples.
+           longer), local energies of 1024 of the last sweep's samples and the
+           sample-space Gram matrix T of --gram-samples of them (default 1024),
+           accumulated over parameter column blocks so that O (P = 2,242,800
+           per sample) is never held whole.
 """
 from __future__ import annotations
 
@@ -53,6 +56,7 @@ def _args():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20"])
     ap.add_argument("--sweeps", type=int, default=0, help="heis20: measured sweeps per step (default 1)")
+    ap.add_argument("--gram-samples", type=int, default=1024, help="heis20: samples in the chunked T (0 = skip)")
     ap.add_argument("--dtype", default="bf16", choices=["bf16", "f16", "f32", "e4m3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison step")
@@ -378,6 +382,8 @@ def run_heis20(a, torch, nqs, workloads):
     acc = torch.empty(C, dtype=torch.int64, device=dev)
     n_el = 1024
     eloc = torch.empty(n_el, dtype=torch.float64, device=dev)
+    n_t = min(a.gram_samples, C)
+    T = torch.empty(n_t, n_t, dtype=torch.float32, device=dev) if n_t else None
     model.prepare(a.dtype)
     props = C * sweeps * N
     res = {}
@@ -386,18 +392,25 @@ def run_heis20(a, torch, nqs, workloads):
         for _ in range(a.warmup):
             nqs.nqs_sample(model, cfg, state, samples, None, acc)
         torch.cuda.synchronize()
-        ev = _events(torch, 3)
-        t_s = t_e = 0.0
+        if n_t and dt == a.dtype:
+            nqs.nqs_sample_gram(model, samples[sweeps - 1, :n_t], T)   # warm the workspace
+        ev = _events(torch, 4)
+        t_s = t_e = t_t = 0.0
         for _ in range(a.steps):
             ev[0].record()
             nqs.nqs_sample(model, cfg, state, samples, None, acc)
             ev[1].record()
             nqs.nqs_local_energy(model, ham, samples[sweeps - 1, :n_el], eloc, dt)
             ev[2].record()
+            # O and T come from the FP32 copy whatever the sampling dtype: timed once
+            if n_t and dt == a.dtype:
+                nqs.nqs_sample_gram(model, samples[sweeps - 1, :n_t], T)
+            ev[3].record()
             torch.cuda.synchronize()
             t_s += ev[0].elapsed_time(ev[1]) / a.steps
             t_e += ev[1].elapsed_time(ev[2]) / a.steps
-        res[dt] = {"sample_ms": t_s, "eloc_ms": t_e, "acceptance": float(acc.sum().item()) / props,
+            t_t += ev[2].elapsed_time(ev[3]) / a.steps
+        res[dt] = {"sample_ms": t_s, "eloc_ms": t_e, "gram_ms": t_t, "acceptance": float(acc.sum().item()) / props,
                    "eloc_mean": float(eloc.mean().item())}
     w = wl.model.widths
     flops = 2.0 * (N * w[0] + w[0] * w[1] + w[1] * w[2])   # full forward per proposal
@@ -406,12 +419,14 @@ def run_heis20(a, torch, nqs, workloads):
     achieved = eff * flops / (r0["sample_ms"] * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": props / (r0["sample_ms"] * 1e-3), "unit": "proposals/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": r0["sample_ms"] + r0["eloc_ms"], "higher_is_better": True,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": r0["sample_ms"] + r0["eloc_ms"] + r0["gram_ms"],
+        "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": a.dtype, "data": "synthetic (seeded He-initialised FFNN)",
         "config": {"workload": wl.name, "lattice": "20x20 periodic", "J": 1.0, "marshall": True, "ffnn": [N, *w],
                    "move": "exchange", "chains": C, "sweeps_per_step": sweeps, "burnin": 0,
                    "proposals_per_step": props, "eloc_samples": n_el, "parallelism": "single GPU"},
-        "phases_ms": {"sample": round(r0["sample_ms"], 3), "local_energy": round(r0["eloc_ms"], 3)},
+        "phases_ms": {"sample": round(r0["sample_ms"], 3), "local_energy": round(r0["eloc_ms"], 3),
+                      "gram_T_chunked": round(r0["gram_ms"], 3)},
         "eloc_samples_per_s": n_el / (r0["eloc_ms"] * 1e-3),
         "acceptance": r0["acceptance"],
         "roofline": {"kernel": "deep_gemm_kernel (all layers)", "bound": "mfma", "achieved": round(achieved, 2),
@@ -422,7 +437,18 @@ def run_heis20(a, torch, nqs, workloads):
     }
     if "f32" in res and a.dtype != "f32":
         out["fp32"] = {"sample_ms": res["f32"]["sample_ms"], "eloc_ms": res["f32"]["eloc_ms"]}
-        out["speedup_vs_fp32"] = (res["f32"]["sample_ms"] + res["f32"]["eloc_ms"]) / out["ms_per_step"]
+        out["speedup_vs_fp32"] = ((res["f32"]["sample_ms"] + res["f32"]["eloc_ms"])
+                                  / (r0["sample_ms"] + r0["eloc_ms"]))
+    if n_t:
+        P = model.n_params
+        chunk = max(32, ((1 << 28) // n_t) & ~31)
+        t_flops = 1.0 * n_t * (n_t + 1) * P    # 2P flops per entry of the upper triangle of the symmetric T
+        tf = t_flops / (r0["gram_ms"] * 1e-3) / 1e12
+        out["gram_T"] = {"samples": n_t, "params": P, "column_block": chunk, "blocks": -(-P // chunk),
+                         "ms": round(r0["gram_ms"], 3), "tflops": round(tf, 2), "peak_fp32_mfma": 157.3,
+                         "frac": round(tf / 157.3, 4),
+                         "note": "whole phase: per-sample factors of O once, then per column block the "
+                                 "expansion of O, its column means and the contraction"}
     return out
 
 

@@ -19,6 +19,7 @@
  *                      T = Obar Obar^T / n, FP32 matrix cores
  *   nqs_sample_gram    T accumulated over column blocks of O, so that O is
  *                      never held whole (large networks)
+ *   nqs_sample_gram_factored  the same T from the per-layer factors of O, FP64
  *
  * Conventions (every entry point):
  *   - All array arguments are DEVICE pointers unless marked "host".  The
@@ -220,12 +221,27 @@ nqs_status nqs_gram(const float *O, int64_t n, int64_t P, int32_t mode, float *o
 /* T[n][n] = Obar Obar^T / n of the samples (Eq. eq:smat taken in sample
  * space), without ever holding all of O: the parameters are walked in column
  * blocks of `chunk_params` (0 = automatic, blocks of at most 1 GiB), each block
- * of O is recomputed by the gradient kernel into the library workspace and its
- * T accumulated on the matrix cores.  T is overwritten.  Blocks are summed in
+ * of O is formed in the library workspace and its T accumulated on the matrix
+ * cores.  A dense network's blocks are expanded from per-sample layer inputs
+ * and deltas (computed once, n x (sum of widths) floats each), an RBM's are
+ * recomputed from the samples.  Block values equal the columns of
+ * nqs_logpsi_grad bit for bit.  T is overwritten.  Blocks are summed in
  * parameter order, so the result does not depend on timing but does depend
- * on chunk_params through FP32 rounding. */
+ * on chunk_params through FP32 rounding.  n is at most 1,048,560. */
 nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64_t chunk_params, float *T,
                            void *stream);
+
+/* The same T[n][n] evaluated from the factors of O instead of O itself.  Each
+ * layer's O is an outer product per sample (dense layer l: delta_l x a_{l-1}
+ * plus delta_l for the bias; RBM: tanh(theta) x s plus tanh(theta) and s), so
+ *   O_k . O_l = sum_layers (U_k.U_l + c)(V_k.V_l + 1) - c
+ * needs Gram matrices of the per-sample factors (a few thousand values)
+ * rather than of all P parameters, and the centring is exact algebra with the
+ * means of O.  Factors are FP32 (as in nqs_logpsi_grad); means, centring and
+ * the contraction (FP64 matrix cores) are FP64; T is rounded to FP32 once.
+ * Workspace: n x (sum of factor widths) floats plus the mean matrices
+ * (about P doubles) and a few n-vectors.  T is overwritten; deterministic. */
+nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t n, float *T, void *stream);
 
 const char *nqs_last_error(void);
 const char *nqs_version(void);

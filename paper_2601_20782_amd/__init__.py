@@ -21,7 +21,8 @@ from ._abi import DTYPE_CODES, NqsError, check, load
 
 __all__ = [
     "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
-    "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_downcast", "LogPsi", "NqsError", "load",
+    "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
+    "nqs_downcast", "LogPsi", "NqsError", "load",
 ]
 
 
@@ -247,6 +248,12 @@ def nqs_sample_gram(model: Model, samples: torch.Tensor, T: torch.Tensor, chunk_
     n = samples.numel() // model.n_visible
     assert T.dtype == torch.float32 and T.numel() == n * n
     check(load().nqs_sample_gram(model.handle, _ptr(samples), n, chunk_params, _ptr(T), _stream(stream)))
+
+
+def nqs_sample_gram_factored(model: Model, samples: torch.Tensor, T: torch.Tensor, stream=None) -> None:
+    n = samples.numel() // model.n_visible
+    assert T.dtype == torch.float32 and T.numel() == n * n
+    check(load().nqs_sample_gram_factored(model.handle, _ptr(samples), n, _ptr(T), _stream(stream)))
 
 
 def nqs_forces(O: torch.Tensor, eloc: torch.Tensor, F: torch.Tensor, Omean: Optional[torch.Tensor] = None,

@@ -21,7 +21,8 @@ EXPORTS = [
     "nqs_model_create", "nqs_model_set_params", "nqs_model_set_params_device", "nqs_model_destroy",
     "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched",
     "nqs_local_energy", "nqs_energy_stats",
-    "nqs_logpsi_grad", "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_last_error",
+    "nqs_logpsi_grad", "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
+    "nqs_last_error",
     "nqs_version",
 ]
 
@@ -92,6 +93,7 @@ def load() -> ctypes.CDLL:
         "nqs_gram": ([P, i64, i64, i32, P, P], st),
         "nqs_logpsi_grad_cols": ([P, P, i64, i64, i64, P, P], st),
         "nqs_sample_gram": ([P, P, i64, i64, P, P], st),
+        "nqs_sample_gram_factored": ([P, P, i64, P, P], st),
         "nqs_last_error": ([], ctypes.c_char_p),
         "nqs_version": ([], ctypes.c_char_p),
     }

@@ -327,6 +327,67 @@ nqs_status nqs_logpsi_grad_cols(nqs_model *m, const int8_t *samples, int64_t n, 
     return ffnn_logpsi_grad(m, samples, n, nullptr, O, nullptr, nullptr, s, p0, p1);
 }
 
+nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t n, float *T, void *stream)
+{
+    if (!m) return set_error(NQS_EINVAL, "NULL model");
+    if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
+    if (!samples || !T) return set_error(NQS_EINVAL, "NULL samples/T");
+    hipStream_t s = (hipStream_t)stream;
+    const nqs_model_desc &d = m->desc;
+    FacLayerDesc lay[NQS_MAX_LAYERS];
+    int L = 0;
+    size_t fbytes = 0;
+    int64_t sa = 0, sd = 0;
+    if (d.arch == NQS_RBM) {
+        L = 1;
+        fbytes = sizeof(float) * (size_t)n * (size_t)(d.n_visible + d.widths[0]);
+    } else {
+        L = d.n_layers;
+        for (int l = 0; l < L; ++l) {
+            sa += l == 0 ? d.n_visible : d.widths[l - 1];
+            sd += d.widths[l];
+        }
+        fbytes = sizeof(float) * (size_t)n * (size_t)(sa + sd);
+    }
+    fbytes = (fbytes + 255) & ~(size_t)255;
+    // the factor layout is fixed before the workspace size is known: fill the
+    // descriptors with offsets first, then rebase them on the workspace
+    if (d.arch == NQS_RBM) {
+        const int N = d.n_visible, M = d.widths[0];
+        lay[0] = FacLayerDesc{nullptr, nullptr, M, N, M, N, 1};
+    } else {
+        int64_t oa = 0, od = 0;
+        for (int l = 0; l < L; ++l) {
+            const int in = l == 0 ? d.n_visible : d.widths[l - 1], out = d.widths[l];
+            lay[l] = FacLayerDesc{(const float *)(uintptr_t)(od * sizeof(float)),
+                                  (const float *)(uintptr_t)(oa * sizeof(float)), sd, sa, out, in, 0};
+            oa += in;
+            od += out;
+        }
+    }
+    char *ws = (char *)workspace(fbytes + fac_workspace_bytes(lay, L, n), s);
+    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    nqs_status st = NQS_OK;
+    if (d.arch == NQS_RBM) {
+        const int N = d.n_visible;
+        float *t = (float *)ws, *sf = t + (size_t)n * d.widths[0];
+        st = rbm_tanh_theta(m, samples, n, t, s);
+        if (st != NQS_OK) return st;
+        launch_spins_to_f32(samples, n * N, sf, s);
+        lay[0].U = t;
+        lay[0].V = sf;
+    } else {
+        float *dels = (float *)ws, *acts = dels + (size_t)n * sd;
+        st = ffnn_factors(m, samples, n, acts, dels, s);
+        if (st != NQS_OK) return st;
+        for (int l = 0; l < L; ++l) {
+            lay[l].U = dels + (uintptr_t)lay[l].U / sizeof(float);
+            lay[l].V = acts + (uintptr_t)lay[l].V / sizeof(float);
+        }
+    }
+    return launch_fac_gram(lay, L, n, T, ws + fbytes, s);
+}
+
 nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64_t chunk_params, float *T,
                            void *stream)
 {
@@ -341,16 +402,16 @@ nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64
         chunk = std::max<int64_t>(32, ((int64_t)(1ll << 28) / n) & ~(int64_t)31);
     }
     chunk = std::min(chunk, P);
+    hipStream_t s = (hipStream_t)stream;
+    if (m->desc.arch != NQS_RBM) return ffnn_sample_gram(m, samples, n, chunk, T, s);
+    // RBM: each block of O is recomputed from the samples (theta is cheap next to the block)
     const size_t oc_bytes = (sizeof(float) * (size_t)n * (size_t)chunk + 255) & ~(size_t)255;
     char *ws = (char *)workspace(oc_bytes + gram_workspace_bytes(n, chunk), (hipStream_t)stream);
     if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
     float *Oc = (float *)ws;
-    hipStream_t s = (hipStream_t)stream;
     for (int64_t p0 = 0; p0 < P; p0 += chunk) {
         const int64_t p1 = std::min(P, p0 + chunk);
-        nqs_status st = m->desc.arch == NQS_RBM
-                            ? rbm_logpsi_grad(m, samples, n, nullptr, Oc, nullptr, nullptr, s, p0, p1)
-                            : ffnn_logpsi_grad(m, samples, n, nullptr, Oc, nullptr, nullptr, s, p0, p1);
+        nqs_status st = rbm_logpsi_grad(m, samples, n, nullptr, Oc, nullptr, nullptr, s, p0, p1);
         if (st != NQS_OK) return st;
         st = launch_gram_ws(Oc, n, p1 - p0, p0 == 0 ? 1 : 2, T, ws + oc_bytes, s);
         if (st != NQS_OK) return st;

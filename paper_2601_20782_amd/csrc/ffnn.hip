@@ -163,6 +163,8 @@ struct GradArgs {
     float *O;         // columns [p0, p1) of O, row stride p1 - p0
     int64_t P;
     int64_t p0, p1;
+    float *acts;      // if set: [n][sum of layer inputs] inputs a_{l-1} of every layer, post-ReLU
+    float *dels;      // with acts: [n][sum of layer outputs] backpropagated deltas; O is not written
     int lds_stride;   // floats reserved per layer activation vector
 };
 
@@ -204,7 +206,42 @@ __global__ void __launch_bounds__(256) ffnn_grad_kernel(GradArgs A)
         if ((tid & 63) == 0) red[tid >> 6] = part;
         __syncthreads();
         if (tid == 0 && A.logpsi) A.logpsi[smp] = red[0] + red[1] + red[2] + red[3];
-        if (A.O) {
+        if (A.acts) {
+            // factors of O: a_{l-1} per layer input, then delta_l per layer from the top
+            int64_t sa = 0, sd = 0;
+            for (int l = 0; l < L; ++l) {
+                sa += net.widths[l];
+                sd += net.widths[l + 1];
+            }
+            float *ar = A.acts + smp * sa, *dr = A.dels + smp * sd;
+            int64_t oa = 0;
+            for (int l = 0; l < L; ++l) {
+                const int in = net.widths[l];
+                const float *src = l == 0 ? in0 : z + (size_t)(l - 1) * S;
+                for (int k = tid; k < in; k += nt) ar[oa + k] = l == 0 ? src[k] : fmaxf(src[k], 0.0f);
+                oa += in;
+            }
+            float *d = dl;
+            for (int r = tid; r < wl; r += nt) d[r] = tanhf(z[(size_t)(L - 1) * S + r]);
+            __syncthreads();
+            int64_t od = sd;
+            for (int l = L - 1; l >= 0; --l) {
+                const int out = net.widths[l + 1], in = net.widths[l];
+                od -= out;
+                for (int r = tid; r < out; r += nt) dr[od + r] = d[r];
+                if (l == 0) break;
+                const float *src = z + (size_t)(l - 1) * S;
+                float *dn = (d == dl) ? dl + S : dl;
+                const float *W = net.W[l];
+                for (int k = tid; k < in; k += nt) {
+                    float g = 0.0f;
+                    for (int r = 0; r < out; ++r) g = fmaf(W[(size_t)r * in + k], d[r], g);
+                    dn[k] = src[k] > 0.0f ? g : 0.0f;
+                }
+                __syncthreads();
+                d = dn;
+            }
+        } else if (A.O) {
             const int64_t p0 = A.p0, p1 = A.p1;
             float *O = A.O + smp * (p1 - p0) - p0;   // O[p] for p in [p0, p1)
             // parameter offsets
@@ -279,6 +316,8 @@ nqs_status ffnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, floa
     A.P = m->P;
     A.p0 = p0;
     A.p1 = p1;
+    A.acts = nullptr;
+    A.dels = nullptr;
     A.lds_stride = (maxw + 3) & ~3;
     const size_t lds = sizeof(float) * (size_t)A.lds_stride * (1 + net.n_layers + 2);
     if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too wide for the gradient kernel");
@@ -466,6 +505,135 @@ nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
     }
     const int blocks = (int)std::min<int64_t>(n, 256 * 4);
     return ffnn_eloc_dispatch(dtype, QK, A, blocks, lds, stream);
+}
+
+// ---- sample-space Gram matrix from the factors of O ----
+//
+// O of a dense layer is an outer product per sample: O_{W_l}[r][c] = delta_l[r] *
+// a_{l-1}[c], O_{b_l}[r] = delta_l[r].  The factors (a few thousand floats per
+// sample) are computed once; each column block of O is then expanded from them
+// (a write-bound pass) instead of rerunning the forward and backward passes.
+
+struct ExpandArgs {
+    const float *acts, *dels;
+    float *O;                     // [n][p1 - p0]
+    int64_t n, p0, p1, sa, sd;    // sa, sd: row lengths of acts and dels
+    int L;
+    int64_t offW[NQS_MAX_LAYERS + 1];   // first parameter of layer l; offW[L] = P
+    int in[NQS_MAX_LAYERS], out[NQS_MAX_LAYERS];
+    int64_t offA[NQS_MAX_LAYERS], offD[NQS_MAX_LAYERS];
+};
+
+constexpr int kExpandRows = 16;
+
+__global__ void __launch_bounds__(256) ffnn_expand_kernel(ExpandArgs E)
+{
+    const int64_t p = E.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= E.p1) return;
+    int l = 0;
+    while (l + 1 < E.L && p >= E.offW[l + 1]) ++l;
+    const int64_t q = p - E.offW[l], nw = (int64_t)E.out[l] * E.in[l];
+    int64_t ai, di;
+    if (q < nw) {
+        const int64_t r = q / E.in[l];
+        ai = E.offA[l] + (q - r * E.in[l]);
+        di = E.offD[l] + r;
+    } else {
+        ai = -1;
+        di = E.offD[l] + (q - nw);
+    }
+    const int64_t ldo = E.p1 - E.p0;
+    const int64_t k0 = blockIdx.y * (int64_t)kExpandRows, k1 = min(E.n, k0 + kExpandRows);
+    for (int64_t k = k0; k < k1; ++k) {
+        const float d = E.dels[k * E.sd + di];
+        E.O[k * ldo + (p - E.p0)] = ai >= 0 ? d * E.acts[k * E.sa + ai] : d;
+    }
+}
+
+nqs_status ffnn_factors(nqs_model *m, const int8_t *samples, int64_t n, float *acts, float *dels, hipStream_t stream)
+{
+    nqs_status st = ensure_copy(m, NQS_F32, stream);
+    if (st != NQS_OK) return st;
+    const FfnnDev &net = m->copies[NQS_F32].ffnn;
+    const int L = net.n_layers;
+    int maxw = net.widths[0];
+    for (int l = 1; l <= L; ++l) maxw = std::max(maxw, net.widths[l]);
+    GradArgs A;
+    A.net = net;
+    A.samples = samples;
+    A.n = n;
+    A.logpsi = nullptr;
+    A.O = nullptr;
+    A.P = m->P;
+    A.p0 = 0;
+    A.p1 = m->P;
+    A.acts = acts;
+    A.dels = dels;
+    A.lds_stride = (maxw + 3) & ~3;
+    const size_t lds = sizeof(float) * (size_t)A.lds_stride * (1 + L + 2);
+    if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too wide for the gradient kernel");
+    allow_lds(ffnn_grad_kernel, lds);
+    hipLaunchKernelGGL(ffnn_grad_kernel, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), lds, stream, A);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
+nqs_status ffnn_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64_t chunk, float *T,
+                            hipStream_t stream)
+{
+    nqs_status st = ensure_copy(m, NQS_F32, stream);
+    if (st != NQS_OK) return st;
+    const FfnnDev &net = m->copies[NQS_F32].ffnn;
+    const int L = net.n_layers;
+    int maxw = net.widths[0];
+    for (int l = 1; l <= L; ++l) maxw = std::max(maxw, net.widths[l]);
+    ExpandArgs E;
+    E.L = L;
+    E.n = n;
+    int64_t off = 0, sa = 0, sd = 0;
+    for (int l = 0; l < L; ++l) {
+        E.in[l] = net.widths[l];
+        E.out[l] = net.widths[l + 1];
+        E.offW[l] = off;
+        off += (int64_t)E.out[l] * E.in[l] + E.out[l];
+        E.offA[l] = sa;
+        sa += E.in[l];
+    }
+    E.offW[L] = off;
+    for (int l = 0; l < L; ++l) {   // delta_l sits after the deltas of the layers below it
+        E.offD[l] = sd;
+        sd += E.out[l];
+    }
+    E.sa = sa;
+    E.sd = sd;
+    const int64_t P = m->P;
+    const size_t fa = (sizeof(float) * (size_t)n * sa + 255) & ~(size_t)255;
+    const size_t fd = (sizeof(float) * (size_t)n * sd + 255) & ~(size_t)255;
+    const size_t oc = (sizeof(float) * (size_t)n * chunk + 255) & ~(size_t)255;
+    char *ws = (char *)workspace(fa + fd + oc + gram_workspace_bytes(n, chunk), stream);
+    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    float *acts = (float *)ws, *dels = (float *)(ws + fa);
+    E.acts = acts;
+    E.dels = dels;
+    float *Oc = (float *)(ws + fa + fd);
+
+    st = ffnn_factors(m, samples, n, acts, dels, stream);
+    if (st != NQS_OK) return st;
+
+    const int64_t ry = (n + kExpandRows - 1) / kExpandRows;
+    if (ry > 65535) return set_error(NQS_EINVAL, "too many samples for the expansion grid");
+    for (int64_t p0 = 0; p0 < P; p0 += chunk) {
+        const int64_t p1 = std::min(P, p0 + chunk);
+        E.O = Oc;
+        E.p0 = p0;
+        E.p1 = p1;
+        hipLaunchKernelGGL(ffnn_expand_kernel, dim3((unsigned)((p1 - p0 + 255) / 256), (unsigned)ry), dim3(256), 0,
+                           stream, E);
+        NQS_HIP_TRY(hipGetLastError());
+        st = launch_gram_ws(Oc, n, p1 - p0, p0 == 0 ? 1 : 2, T, ws + fa + fd + oc, stream);
+        if (st != NQS_OK) return st;
+    }
+    return NQS_OK;
 }
 
 }  // namespace nqs

@@ -149,11 +149,30 @@ nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
                              double *eloc, hipStream_t stream);
 nqs_status ffnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
                             const float *vjp_in, float *vjp_out, hipStream_t stream, int64_t p0, int64_t p1);
+// T of the samples, column blocks of `chunk` parameters expanded from per-sample
+// activations and deltas computed once
+nqs_status ffnn_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64_t chunk, float *T,
+                            hipStream_t stream);
 nqs_status launch_init_chains(int8_t *chain_state, int64_t n_chains, int N, int move, uint64_t seed,
                               uint32_t inst, int64_t chain_id_offset, hipStream_t stream);
 nqs_status launch_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, hipStream_t stream);
 nqs_status launch_forces(const float *O, const double *eloc, int64_t n, int64_t P, double *F, double *Omean,
                          hipStream_t stream);
+// One layer of factors of O for the factored sample-space Gram matrix:
+// O_layer(k) = U_k (x) V_k and U_k, plus V_k when c = 1 (all FP32, row-major).
+struct FacLayerDesc {
+    const float *U, *V;
+    int64_t ldu, ldv;
+    int du, dv, c;
+};
+size_t fac_workspace_bytes(const FacLayerDesc *lay, int L, int64_t n);
+nqs_status launch_fac_gram(const FacLayerDesc *lay, int L, int64_t n, float *T, void *ws, hipStream_t stream);
+void launch_spins_to_f32(const int8_t *s, int64_t count, float *out, hipStream_t stream);
+// factors of an RBM: t = tanh(theta) [n][M]
+nqs_status rbm_tanh_theta(nqs_model *m, const int8_t *samples, int64_t n, float *t, hipStream_t stream);
+// factors of a dense network: layer inputs a_{l-1} [n][sum of inputs] and deltas [n][sum of outputs]
+nqs_status ffnn_factors(nqs_model *m, const int8_t *samples, int64_t n, float *acts, float *dels, hipStream_t stream);
+
 // mode 0 S, 1 T, 2 T accumulated into `out`; the _ws form takes a caller-carved
 // workspace of gram_workspace_bytes(n, P) bytes
 nqs_status launch_gram(const float *O, int64_t n, int64_t P, int mode, float *out, hipStream_t stream);

@@ -535,6 +535,24 @@ __global__ void rbm_vjp_kernel(int N, int M, const int8_t *__restrict__ samples,
     }
 }
 
+nqs_status rbm_tanh_theta(nqs_model *m, const int8_t *samples, int64_t n, float *t, hipStream_t stream)
+{
+    nqs_status st = ensure_copy(m, NQS_F32, stream);
+    if (st != NQS_OK) return st;
+    const RbmDev &net = m->copies[NQS_F32].rbm;
+    constexpr int B = 8;
+    const int threads = 256;
+    const size_t lds = sizeof(float) * ((size_t)net.N * B + (size_t)net.M * B + (threads / 64) * B);
+    if (lds > kLdsBytes) return set_error(NQS_EUNSUPPORTED, "RBM too large for the gradient kernel");
+    const int64_t blocks = (n + B - 1) / B;
+    if (blocks > INT32_MAX) return set_error(NQS_EINVAL, "too many samples");
+    allow_lds(rbm_grad_kernel<B>, lds);
+    hipLaunchKernelGGL((rbm_grad_kernel<B>), dim3((unsigned)blocks), dim3(threads), lds, stream, net, samples, n,
+                       nullptr, nullptr, t, (int64_t)0, (int64_t)0);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
 nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
                            const float *vjp_in, float *vjp_out, hipStream_t stream, int64_t p0, int64_t p1)
 {

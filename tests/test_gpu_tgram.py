@@ -168,3 +168,122 @@ def test_sample_gram_20x20_network_sampled_entries(nqs):
     assert np.array_equal(ga, ga.T) and np.array_equal(gb, gb.T)
     scale = np.sqrt(np.outer(np.diag(ga), np.diag(ga)))
     assert np.max(np.abs(ga - gb) / np.maximum(scale, 1e-30)) < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# T from the per-layer factors of O (FP64 means, centring and contraction)
+# ---------------------------------------------------------------------------
+
+def _rbm_biased(nqs, N, M, seed, bshift):
+    """RBM whose hidden biases are shifted by bshift: tanh(theta) then has a
+    mean far larger than its spread, so centring cancels heavily."""
+    p = workloads.rbm_params(N, M, 0.05, seed).copy()
+    p[N:N + M] += bshift
+    return nqs.Model("rbm", N, (M,), p), oracle.OracleModel("rbm", N, (M,), oracle.round_to(p, "f32"))
+
+
+@pytest.mark.parametrize("arch,N,widths,n", [("rbm", 16, (32,), 300), ("rbm", 100, (200,), 130),
+                                             ("rbm", 9, (27,), 1), ("rbm", 9, (27,), 65),
+                                             ("ffnn", 36, (64, 48, 32), 200), ("ffnn", 16, (40, 20), 77),
+                                             ("ffnn", 10, (12, 7, 5), 129), ("ffnn", 100, (400, 200), 64)])
+def test_sample_gram_factored_matches_oracle(nqs, arch, N, widths, n):
+    model, om = _rbm(nqs, N, widths[0]) if arch == "rbm" else _ffnn(nqs, N, widths)
+    smp = workloads.random_spins(n, N, 6)
+    st = torch.from_numpy(smp).to(DEV)
+    _, rO = oracle.logpsi_grad(om, smp)
+    ref = oracle.tmatrix(rO)
+    T = torch.full((n, n), float("nan"), dtype=torch.float32, device=DEV)
+    nqs.nqs_sample_gram_factored(model, st, T)
+    got = T.cpu().numpy()
+    assert np.array_equal(got, got.T)
+    assert np.max(np.abs(got - ref)) < _t_tol(rO), (np.max(np.abs(got - ref)), _t_tol(rO))
+    T2 = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_sample_gram_factored(model, st, T2)
+    assert torch.equal(T, T2)
+
+
+@pytest.mark.parametrize("bshift", [2.0, 4.0])
+def test_sample_gram_factored_heavy_centring(nqs, bshift):
+    """Means of O much larger than its spread: the FP64 centring keeps T at the
+    FP32 rounding of the factors, relative to the centred O."""
+    N, M, n = 24, 48, 257
+    model, om = _rbm_biased(nqs, N, M, 3, bshift)
+    smp = workloads.random_spins(n, N, 7)
+    st = torch.from_numpy(smp).to(DEV)
+    _, rO = oracle.logpsi_grad(om, smp)
+    ref = oracle.tmatrix(rO)
+    c = rO - rO.mean(axis=0)
+    T = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_sample_gram_factored(model, st, T)
+    got = T.cpu().numpy()
+    # per entry: FP32 factor rounding (tanh near +-1 is exact to 6e-8 relative) against |Obar_k| |Obar_l|
+    nrm = np.sqrt((c ** 2).sum(axis=1))
+    bound = 1e-5 * np.outer(nrm, nrm) / n + 2e-6 * np.abs(ref) + 1e-12
+    assert np.all(np.abs(got - ref) <= bound + 1e-6 * np.abs(ref).max())
+
+
+def test_sample_gram_factored_tfim10_4096(nqs):
+    """The 10x10 TFIM RBM (alpha = 2) on 4096 samples, the size of the sample
+    set whose T the benchmark step forms: against the FP32 contraction of the
+    materialised O, and at sampled entries against the oracle."""
+    wl = workloads.cfg2_tfim_10x10()
+    params = workloads.params_for(wl)
+    N = wl.model.n_visible
+    model = nqs.Model.from_workload(wl, params)
+    n = 4096
+    smp = workloads.random_spins(n, N, 12)
+    st = torch.from_numpy(smp).to(DEV)
+    Tf = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_sample_gram_factored(model, st, Tf)
+    O = torch.empty(n, model.n_params, dtype=torch.float32, device=DEV)
+    nqs.nqs_logpsi_grad(model, st, O=O)
+    Tg = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_gram(O, 1, Tg)
+    torch.cuda.synchronize()
+    gf, gg = Tf.cpu().numpy(), Tg.cpu().numpy()
+    om = oracle.OracleModel("rbm", N, wl.model.widths, oracle.round_to(params, "f32"))
+    _, rO = oracle.logpsi_grad(om, smp)
+    mu = rO.mean(axis=0)
+    c = rO - mu
+    nrm = np.sqrt((c ** 2).sum(axis=1))
+    rng = np.random.default_rng(5)
+    pairs = [(0, 0), (n - 1, n - 1), (0, n - 1)] + [tuple(int(v) for v in rng.choice(n, 2)) for _ in range(20)]
+    for i, j in pairs:
+        ref = float(np.dot(c[i], c[j])) / n
+        tol = 1e-5 * nrm[i] * nrm[j] / n + 1e-9
+        assert abs(gf[i, j] - ref) < tol, (i, j, gf[i, j], ref, tol)
+    assert np.array_equal(gf, gf.T)
+    scale = np.outer(nrm, nrm) / n
+    assert np.max(np.abs(gf - gg) / scale) < 1e-4
+
+
+def test_sample_gram_factored_20x20_network(nqs):
+    """The 20x20 Heisenberg network (400-1600-800-400) on 512 samples: the
+    factored T against the column-block T and, at sampled entries, the oracle."""
+    wl = workloads.cfg5_heis_20x20()
+    params = workloads.params_for(wl)
+    N, widths = wl.model.n_visible, wl.model.widths
+    model = nqs.Model.from_workload(wl, params)
+    n = 512
+    smp = workloads.random_spins(n, N, 9)
+    st = torch.from_numpy(smp).to(DEV)
+    Tf = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_sample_gram_factored(model, st, Tf)
+    Tc = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_sample_gram(model, st, Tc, chunk_params=0)
+    torch.cuda.synchronize()
+    gf, gc = Tf.cpu().numpy(), Tc.cpu().numpy()
+    _say("20x20 network (factored): oracle log-derivatives")
+    om = oracle.OracleModel("ffnn", N, widths, oracle.round_to(params, "f32"), act_dtype="f32")
+    _, rO = oracle.logpsi_grad(om, smp)
+    mu = rO.mean(axis=0)
+    rng = np.random.default_rng(13)
+    pairs = [(0, 0), (n - 1, n - 1), (0, n - 1)] + [tuple(int(v) for v in rng.choice(n, 2)) for _ in range(9)]
+    for i, j in pairs:
+        ci, cj = rO[i] - mu, rO[j] - mu
+        ref = float(np.dot(ci, cj)) / n
+        tol = 1e-5 * np.linalg.norm(ci) * np.linalg.norm(cj) / n + 1e-9
+        assert abs(gf[i, j] - ref) < tol, (i, j, gf[i, j], ref, tol)
+    assert np.array_equal(gf, gf.T)
+    d = np.sqrt(np.outer(np.diag(gf), np.diag(gf)))
+    assert np.max(np.abs(gf - gc) / np.maximum(d, 1e-30)) < 1e-4
