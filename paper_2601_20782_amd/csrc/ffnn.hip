@@ -163,8 +163,8 @@ struct GradArgs {
     float *O;         // columns [p0, p1) of O, row stride p1 - p0
     int64_t P;
     int64_t p0, p1;
-    float *acts;      // if set: [n][sum of layer inputs] inputs a_{l-1} of every layer, post-ReLU
-    float *dels;      // with acts: [n][sum of layer outputs] backpropagated deltas; O is not written
+    float *acts;      // factor kernel: [n][sum of layer inputs] inputs a_{l-1} of every layer, post-ReLU
+    float *dels;      // factor kernel: [n][sum of layer outputs] backpropagated deltas
     int lds_stride;   // floats reserved per layer activation vector
 };
 
@@ -206,42 +206,7 @@ __global__ void __launch_bounds__(256) ffnn_grad_kernel(GradArgs A)
         if ((tid & 63) == 0) red[tid >> 6] = part;
         __syncthreads();
         if (tid == 0 && A.logpsi) A.logpsi[smp] = red[0] + red[1] + red[2] + red[3];
-        if (A.acts) {
-            // factors of O: a_{l-1} per layer input, then delta_l per layer from the top
-            int64_t sa = 0, sd = 0;
-            for (int l = 0; l < L; ++l) {
-                sa += net.widths[l];
-                sd += net.widths[l + 1];
-            }
-            float *ar = A.acts + smp * sa, *dr = A.dels + smp * sd;
-            int64_t oa = 0;
-            for (int l = 0; l < L; ++l) {
-                const int in = net.widths[l];
-                const float *src = l == 0 ? in0 : z + (size_t)(l - 1) * S;
-                for (int k = tid; k < in; k += nt) ar[oa + k] = l == 0 ? src[k] : fmaxf(src[k], 0.0f);
-                oa += in;
-            }
-            float *d = dl;
-            for (int r = tid; r < wl; r += nt) d[r] = tanhf(z[(size_t)(L - 1) * S + r]);
-            __syncthreads();
-            int64_t od = sd;
-            for (int l = L - 1; l >= 0; --l) {
-                const int out = net.widths[l + 1], in = net.widths[l];
-                od -= out;
-                for (int r = tid; r < out; r += nt) dr[od + r] = d[r];
-                if (l == 0) break;
-                const float *src = z + (size_t)(l - 1) * S;
-                float *dn = (d == dl) ? dl + S : dl;
-                const float *W = net.W[l];
-                for (int k = tid; k < in; k += nt) {
-                    float g = 0.0f;
-                    for (int r = 0; r < out; ++r) g = fmaf(W[(size_t)r * in + k], d[r], g);
-                    dn[k] = src[k] > 0.0f ? g : 0.0f;
-                }
-                __syncthreads();
-                d = dn;
-            }
-        } else if (A.O) {
+        if (A.O) {
             const int64_t p0 = A.p0, p1 = A.p1;
             float *O = A.O + smp * (p1 - p0) - p0;   // O[p] for p in [p0, p1)
             // parameter offsets
@@ -301,6 +266,108 @@ __global__ void vjp_chunk_kernel(const float *__restrict__ O, const float *__res
     double acc = first ? 0.0 : (double)out[p];
     for (int64_t k = 0; k < n; ++k) acc += (double)g[k] * (double)O[k * P + p];
     out[p] = (float)acc;
+}
+
+// Factors of O for B samples per block: the layer inputs a_{l-1} (post-ReLU) and
+// the deltas of every layer.  Each weight read from memory serves B samples;
+// per sample the arithmetic (and its order) is that of ffnn_grad_kernel, so
+// delta_l[r] * a_{l-1}[c] reproduces its O bit for bit.
+template <int B>
+__global__ void __launch_bounds__(256) ffnn_factor_kernel(GradArgs A)
+{
+    extern __shared__ float smem[];
+    const FfnnDev &net = A.net;
+    const int L = net.n_layers, N = net.widths[0];
+    // per sample, packed: spins [N], pre-activations of every layer, two delta vectors of S floats
+    const int S = A.lds_stride;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    int64_t sa = 0, sd = 0;
+    int zoff[NQS_MAX_LAYERS];
+    int R = (N + 3) & ~3;
+    for (int l = 0; l < L; ++l) {
+        sa += net.widths[l];
+        sd += net.widths[l + 1];
+        zoff[l] = R;
+        R += (net.widths[l + 1] + 3) & ~3;
+    }
+    const int doff = R;
+    R += 2 * S;
+    auto in0 = [&](int b) { return smem + (size_t)b * R; };
+    auto zl = [&](int b, int l) { return smem + (size_t)b * R + zoff[l]; };
+    auto dlb = [&](int b, int h) { return smem + (size_t)b * R + doff + (size_t)h * S; };
+    for (int64_t s0 = (int64_t)blockIdx.x * B; s0 < A.n; s0 += (int64_t)gridDim.x * B) {
+        const int nb = (int)min((int64_t)B, A.n - s0);
+        for (int e = tid; e < B * N; e += nt) {
+            const int b = e / N, i = e - b * N;
+            in0(b)[i] = b < nb ? (float)A.samples[(s0 + b) * N + i] : 0.0f;
+        }
+        __syncthreads();
+        for (int l = 0; l < L; ++l) {
+            const int out = net.widths[l + 1], in = net.widths[l];
+            const float *Wt = net.Wt[l];
+            for (int r = tid; r < out; r += nt) {
+                float acc[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) acc[b] = net.b[l][r];
+#pragma unroll 4
+                for (int k = 0; k < in; ++k) {
+                    const float w = Wt[(size_t)k * out + r];
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        const float x = l == 0 ? in0(b)[k] : fmaxf(zl(b, l - 1)[k], 0.0f);
+                        acc[b] = fmaf(w, x, acc[b]);
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) zl(b, l)[r] = acc[b];
+            }
+            __syncthreads();
+        }
+        // layer inputs
+        for (int b = 0; b < nb; ++b) {
+            float *ar = A.acts + (s0 + b) * sa;
+            int64_t oa = 0;
+            for (int l = 0; l < L; ++l) {
+                const int in = net.widths[l];
+                for (int k = tid; k < in; k += nt) ar[oa + k] = l == 0 ? in0(b)[k] : fmaxf(zl(b, l - 1)[k], 0.0f);
+                oa += in;
+            }
+        }
+        const int wl = net.widths[L];
+        for (int e = tid; e < B * wl; e += nt) {
+            const int b = e / wl, r = e - b * wl;
+            dlb(b, 0)[r] = tanhf(zl(b, L - 1)[r]);
+        }
+        __syncthreads();
+        int h = 0;
+        int64_t od = sd;
+        for (int l = L - 1; l >= 0; --l) {
+            const int out = net.widths[l + 1], in = net.widths[l];
+            od -= out;
+            for (int b = 0; b < nb; ++b) {
+                float *dr = A.dels + (s0 + b) * sd + od;
+                for (int r = tid; r < out; r += nt) dr[r] = dlb(b, h)[r];
+            }
+            if (l == 0) break;
+            const float *W = net.W[l];
+            for (int k = tid; k < in; k += nt) {
+                float g[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) g[b] = 0.0f;
+#pragma unroll 4
+                for (int r = 0; r < out; ++r) {
+                    const float w = W[(size_t)r * in + k];
+#pragma unroll
+                    for (int b = 0; b < B; ++b) g[b] = fmaf(w, dlb(b, h)[r], g[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) dlb(b, h ^ 1)[k] = zl(b, l - 1)[k] > 0.0f ? g[b] : 0.0f;
+            }
+            __syncthreads();
+            h ^= 1;
+        }
+        __syncthreads();
+    }
 }
 
 nqs_status ffnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
@@ -570,10 +637,22 @@ nqs_status ffnn_factors(nqs_model *m, const int8_t *samples, int64_t n, float *a
     A.acts = acts;
     A.dels = dels;
     A.lds_stride = (maxw + 3) & ~3;
-    const size_t lds = sizeof(float) * (size_t)A.lds_stride * (1 + L + 2);
-    if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too wide for the gradient kernel");
-    allow_lds(ffnn_grad_kernel, lds);
-    hipLaunchKernelGGL(ffnn_grad_kernel, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), lds, stream, A);
+    size_t per = (size_t)((net.widths[0] + 3) & ~3) + 2 * (size_t)A.lds_stride;   // LDS floats per sample
+    for (int l = 1; l <= L; ++l) per += (size_t)((net.widths[l] + 3) & ~3);
+    per *= sizeof(float);
+    const int64_t blocks_cap = (int64_t)device_cus() * 16;
+    auto launch = [&](auto kernel, int B) {
+        allow_lds(kernel, per * B);
+        const int64_t blocks = std::min<int64_t>((n + B - 1) / B, blocks_cap);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(256), per * B, stream, A);
+    };
+    // samples per block: each weight read serves B samples, while at least two
+    // blocks (eight waves) fit a compute unit's 160 KB of LDS to hide load latency
+    if (per * 8 <= 80 * 1024) launch(ffnn_factor_kernel<8>, 8);
+    else if (per * 4 <= 80 * 1024) launch(ffnn_factor_kernel<4>, 4);
+    else if (per * 2 <= 80 * 1024) launch(ffnn_factor_kernel<2>, 2);
+    else if (per <= 160 * 1024) launch(ffnn_factor_kernel<1>, 1);
+    else return set_error(NQS_EUNSUPPORTED, "network too wide for the gradient kernel");
     NQS_HIP_TRY(hipGetLastError());
     return NQS_OK;
 }

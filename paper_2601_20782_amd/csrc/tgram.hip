@@ -16,7 +16,7 @@
 // (products of FP32 factors are exact in FP64); T is rounded to FP32 once.
 //
 // Kernels: fac_mean (tiled FP64, one block per 64 x 64 tile of a layer's mean
-// matrix), fac_v (tiled FP64, per-sample bilinear forms, partials per row
+// matrix and range of samples; the ranges summed in order by fac_mean_reduce), fac_v (tiled FP64, per-sample bilinear forms, partials per row
 // tile summed in fixed order), fac_gram (FP64 matrix cores,
 // v_mfma_f64_16x16x4f64, one block per 64 x 64 tile of T's upper triangle).
 #include <hip/hip_runtime.h>
@@ -36,7 +36,8 @@ struct FacLayer {
     int64_t ldu, ldv;
     int du, dv;
     int c;            // 1: V is also a block of O by itself
-    double *M;        // [(du + 1) x (dv + 1)] masked mean matrix
+    double *M;        // [(du + 1) x (dv + 1)] masked mean matrix (inside FacArgs::Mall)
+    int64_t moff;     // offset of M in Mall
     int64_t mt0;      // first mean tile of this layer (flattened over layers)
     int64_t vs0;      // first v-partial slot of this layer
 };
@@ -45,6 +46,12 @@ struct FacArgs {
     FacLayer lay[NQS_MAX_LAYERS + 1];
     int L;
     int64_t n;
+    double *Mall;     // [mtot] the layers' mean matrices, one after the other
+    double *mpart;    // [splits][mtot] per-split sums of the mean matrices
+    int64_t mtot;
+    int splits;       // sample ranges of the mean sums
+    double *m2part;   // [m2blocks] sums of squares of Mall per reduction block
+    int m2blocks;
     double *vpart;    // [slots][n]
     int64_t slots;
     double *v;        // [n]
@@ -70,8 +77,8 @@ __device__ inline double fac_aug(const float *F, int64_t ld, int d, int64_t n, i
     return j == d ? 1.0 : (double)F[k * ld + j];
 }
 
-// M_l = (1/n) [U,1]^T [V,1], masked: the (du, dv) corner is 0 and row du (the
-// mean of V alone) is kept only when c = 1.
+// Sums of [U,1]^T [V,1] over the samples of one split (blockIdx.y), one 64 x 64
+// tile of one layer per block (blockIdx.x), to mpart.
 __global__ void __launch_bounds__(256) fac_mean_kernel(FacArgs A)
 {
     __shared__ double Us[kFK][kFT], Vs[kFK][kFT];
@@ -81,12 +88,14 @@ __global__ void __launch_bounds__(256) fac_mean_kernel(FacArgs A)
     const int ctiles = (y.dv + 1 + kFT - 1) / kFT;
     const int r0 = (int)(t / ctiles) * kFT, c0 = (int)(t % ctiles) * kFT;
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    const int64_t kb = blockIdx.y * A.n / A.splits, ke = (blockIdx.y + 1) * A.n / A.splits;
     double acc[4][4] = {};
-    for (int64_t k0 = 0; k0 < A.n; k0 += kFK) {
+    for (int64_t k0 = kb; k0 < ke; k0 += kFK) {
         for (int e = tid; e < kFK * kFT; e += 256) {
             const int kk = e / kFT, j = e % kFT;
-            Us[kk][j] = fac_aug(y.U, y.ldu, y.du, A.n, k0 + kk, r0 + j);
-            Vs[kk][j] = fac_aug(y.V, y.ldv, y.dv, A.n, k0 + kk, c0 + j);
+            const int64_t k = k0 + kk < ke ? k0 + kk : A.n;   // A.n reads as zero
+            Us[kk][j] = fac_aug(y.U, y.ldu, y.du, A.n, k, r0 + j);
+            Vs[kk][j] = fac_aug(y.V, y.ldv, y.dv, A.n, k, c0 + j);
         }
         __syncthreads();
         for (int kk = 0; kk < kFK; ++kk) {
@@ -102,17 +111,43 @@ __global__ void __launch_bounds__(256) fac_mean_kernel(FacArgs A)
         }
         __syncthreads();
     }
-    const double inv = 1.0 / (double)A.n;
+    double *out = A.mpart + (int64_t)blockIdx.y * A.mtot + y.moff;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = r0 + ty * 4 + i, c = c0 + tx * 4 + j;
-            if (r > y.du || c > y.dv) continue;
-            double m = acc[i][j] * inv;
-            if (r == y.du && (c == y.dv || !y.c)) m = 0.0;
-            y.M[(int64_t)r * (y.dv + 1) + c] = m;
+            if (r <= y.du && c <= y.dv) out[(int64_t)r * (y.dv + 1) + c] = acc[i][j];
         }
+}
+
+// M_l = (1/n) (sum of the splits in order), masked: the (du, dv) corner is 0 and
+// row du (the mean of V alone) is kept only when c = 1.  Per block, the sum of
+// squares of its entries goes to m2part.
+__global__ void __launch_bounds__(256) fac_mean_reduce_kernel(FacArgs A)
+{
+    __shared__ double red[256];
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double m = 0.0;
+    if (e < A.mtot) {
+        int l = 0;
+        while (l + 1 < A.L && e >= A.lay[l + 1].moff) ++l;
+        const FacLayer &y = A.lay[l];
+        const int64_t q = e - y.moff;
+        const int r = (int)(q / (y.dv + 1)), c = (int)(q - (int64_t)r * (y.dv + 1));
+        double s = 0.0;
+        for (int sp = 0; sp < A.splits; ++sp) s += A.mpart[(int64_t)sp * A.mtot + e];
+        m = s / (double)A.n;
+        if (r == y.du && (c == y.dv || !y.c)) m = 0.0;
+        A.Mall[e] = m;
+    }
+    red[threadIdx.x] = m * m;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) A.m2part[blockIdx.x] = red[0];
 }
 
 // vpart[slot][k] = sum over the slot's 64 rows r of [U_k,1]_r (M [V_k,1])_r
@@ -160,7 +195,7 @@ __global__ void __launch_bounds__(256) fac_v_kernel(FacArgs A)
     }
 }
 
-// v[k] = sum of the slots in order; block 0 also forms |mu|^2 from the mean matrices
+// v[k] = sum of the slots in order; block 0 also sums |mu|^2 from the reduction blocks
 __global__ void __launch_bounds__(256) fac_vsum_kernel(FacArgs A)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -172,11 +207,7 @@ __global__ void __launch_bounds__(256) fac_vsum_kernel(FacArgs A)
     if (blockIdx.x != 0) return;
     __shared__ double red[256];
     double s = 0.0;
-    for (int l = 0; l < A.L; ++l) {
-        const FacLayer &y = A.lay[l];
-        const int64_t cnt = (int64_t)(y.du + 1) * (y.dv + 1);
-        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) s = fma(y.M[e], y.M[e], s);
-    }
+    for (int b = threadIdx.x; b < A.m2blocks; b += blockDim.x) s += A.m2part[b];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o >= 1; o >>= 1) {
@@ -300,29 +331,63 @@ __global__ void spins_to_f32_kernel(const int8_t *__restrict__ s, int64_t count,
 
 // ---- host ----
 
+// Launch geometry shared by the workspace size and the launch.
+struct FacPlan {
+    int64_t mt = 0, mtot = 0, vs = 0;
+    int splits = 1, m2blocks = 1;
+};
+
+static FacPlan fac_plan(const FacLayerDesc *lay, int L, int64_t n)
+{
+    FacPlan p;
+    for (int l = 0; l < L; ++l) {
+        const int64_t rt = (lay[l].du + 1 + kFT - 1) / kFT, ct = (lay[l].dv + 1 + kFT - 1) / kFT;
+        p.mt += rt * ct;
+        p.mtot += (int64_t)(lay[l].du + 1) * (lay[l].dv + 1);
+        p.vs += rt;
+    }
+    // enough sample splits for about eight blocks per compute unit, at least 64 samples each
+    const int64_t want = ((int64_t)device_cus() * 8 + p.mt - 1) / p.mt;
+    p.splits = (int)std::max<int64_t>(1, std::min<int64_t>({want, n / 64, 1024}));
+    p.m2blocks = (int)((p.mtot + 255) / 256);
+    return p;
+}
+
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 size_t fac_workspace_bytes(const FacLayerDesc *lay, int L, int64_t n)
 {
-    size_t b = 0;
-    int64_t slots = 0;
-    for (int l = 0; l < L; ++l) {
-        b += (sizeof(double) * (size_t)(lay[l].du + 1) * (size_t)(lay[l].dv + 1) + 255) & ~(size_t)255;
-        slots += (lay[l].du + 1 + kFT - 1) / kFT;
-    }
-    b += (sizeof(double) * (size_t)slots * (size_t)n + 255) & ~(size_t)255;
-    b += (sizeof(double) * (size_t)n + 255) & ~(size_t)255;
-    b += 256;
-    return b;
+    const FacPlan p = fac_plan(lay, L, n);
+    return round256(sizeof(double) * (size_t)p.mtot) + round256(sizeof(double) * (size_t)p.splits * p.mtot) +
+           round256(sizeof(double) * (size_t)p.m2blocks) + round256(sizeof(double) * (size_t)p.vs * (size_t)n) +
+           round256(sizeof(double) * (size_t)n) + 256;
 }
 
 nqs_status launch_fac_gram(const FacLayerDesc *lay, int L, int64_t n, float *T, void *wsp, hipStream_t stream)
 {
     if (L < 1 || L > NQS_MAX_LAYERS + 1) return set_error(NQS_EINVAL, "bad factor layer count");
+    const FacPlan p = fac_plan(lay, L, n);
     FacArgs A;
     A.L = L;
     A.n = n;
     A.T = T;
     char *ws = (char *)wsp;
-    int64_t mt = 0, vs = 0;
+    A.Mall = (double *)ws;
+    ws += round256(sizeof(double) * (size_t)p.mtot);
+    A.mpart = (double *)ws;
+    ws += round256(sizeof(double) * (size_t)p.splits * p.mtot);
+    A.m2part = (double *)ws;
+    ws += round256(sizeof(double) * (size_t)p.m2blocks);
+    A.vpart = (double *)ws;
+    ws += round256(sizeof(double) * (size_t)p.vs * (size_t)n);
+    A.v = (double *)ws;
+    ws += round256(sizeof(double) * (size_t)n);
+    A.m2 = (double *)ws;
+    A.mtot = p.mtot;
+    A.splits = p.splits;
+    A.m2blocks = p.m2blocks;
+    A.slots = p.vs;
+    int64_t mt = 0, vs = 0, moff = 0;
     for (int l = 0; l < L; ++l) {
         FacLayer &y = A.lay[l];
         y.U = lay[l].U;
@@ -332,26 +397,22 @@ nqs_status launch_fac_gram(const FacLayerDesc *lay, int L, int64_t n, float *T, 
         y.du = lay[l].du;
         y.dv = lay[l].dv;
         y.c = lay[l].c;
-        y.M = (double *)ws;
-        ws += (sizeof(double) * (size_t)(y.du + 1) * (size_t)(y.dv + 1) + 255) & ~(size_t)255;
+        y.moff = moff;
+        y.M = A.Mall + moff;
+        moff += (int64_t)(y.du + 1) * (y.dv + 1);
         y.mt0 = mt;
         mt += (int64_t)((y.du + 1 + kFT - 1) / kFT) * ((y.dv + 1 + kFT - 1) / kFT);
         y.vs0 = vs;
         vs += (y.du + 1 + kFT - 1) / kFT;
     }
-    A.slots = vs;
-    A.vpart = (double *)ws;
-    ws += (sizeof(double) * (size_t)vs * (size_t)n + 255) & ~(size_t)255;
-    A.v = (double *)ws;
-    ws += (sizeof(double) * (size_t)n + 255) & ~(size_t)255;
-    A.m2 = (double *)ws;
     A.nt = (n + kFT - 1) / kFT;
     const int64_t tiles = A.nt * (A.nt + 1) / 2;
     const int64_t ktiles = (n + kFT - 1) / kFT;
-    if (tiles > INT32_MAX || mt > INT32_MAX || ktiles > INT32_MAX || vs > 65535)
+    if (tiles > INT32_MAX || mt > INT32_MAX || ktiles > INT32_MAX || vs > 65535 || p.m2blocks > INT32_MAX / 2)
         return set_error(NQS_EINVAL, "sample-space Gram matrix too large");
 
-    hipLaunchKernelGGL(fac_mean_kernel, dim3((unsigned)mt), dim3(256), 0, stream, A);
+    hipLaunchKernelGGL(fac_mean_kernel, dim3((unsigned)mt, (unsigned)p.splits), dim3(256), 0, stream, A);
+    hipLaunchKernelGGL(fac_mean_reduce_kernel, dim3((unsigned)p.m2blocks), dim3(256), 0, stream, A);
     hipLaunchKernelGGL(fac_v_kernel, dim3((unsigned)ktiles, (unsigned)vs), dim3(256), 0, stream, A);
     hipLaunchKernelGGL(fac_vsum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, A);
     hipLaunchKernelGGL(fac_gram_kernel, dim3((unsigned)tiles), dim3(256), 0, stream, A);
