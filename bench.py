@@ -24,9 +24,9 @@ Other workloads (--workload):
            65536 chains, exchange moves through the batched-GEMM path; a step
            is --sweeps sweeps (default 1; the full 220-sweep run is ~10^3 times
            longer), local energies of 1024 of the last sweep's samples and the
-           sample-space Gram matrix T of --gram-samples of them (default 1024),
-           accumulated over parameter column blocks so that O (P = 2,242,800
-           per sample) is never held whole.
+           sample-space Gram matrix T of --gram-samples of them (default 4096)
+           from the per-layer factors of O (P = 2,242,800 per sample, never
+           held whole); --gram-chunked times the column-block path instead.
 """
 from __future__ import annotations
 
@@ -56,7 +56,8 @@ def _args():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20"])
     ap.add_argument("--sweeps", type=int, default=0, help="heis20: measured sweeps per step (default 1)")
-    ap.add_argument("--gram-samples", type=int, default=1024, help="heis20: samples in the chunked T (0 = skip)")
+    ap.add_argument("--gram-samples", type=int, default=4096, help="heis20: samples in T (0 = skip)")
+    ap.add_argument("--gram-chunked", action="store_true", help="heis20: T by parameter column blocks")
     ap.add_argument("--dtype", default="bf16", choices=["bf16", "f16", "f32", "e4m3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison step")
@@ -145,7 +146,8 @@ class Step:
         nqs.nqs_forces(self.O, self.eloc[(self.S - 1) * self.C:], self.F)
         mark()
         if self.with_gram:
-            nqs.nqs_gram(self.O, 1, self.T)                 # T = Obar Obar^T / n (sample space)
+            # T = Obar Obar^T / n (sample space) from the factors of O, FP64 matrix cores
+            nqs.nqs_sample_gram_factored(self.model, self.samples[self.S - 1], self.T)
         mark()
 
     def timed(self, steps, warmup):
@@ -292,7 +294,7 @@ def run_heis10(a, torch, nqs, workloads):
     params = workloads.params_for(wl)
     N, C, S, B = wl.model.n_visible, wl.n_chains, wl.n_sweeps, wl.n_burnin
     props = C * (S + B) * N
-    step = Step(nqs, torch, wl, params, a.dtype, 0, a.refresh, eloc_dtype=a.dtype, with_gram=False)
+    step = Step(nqs, torch, wl, params, a.dtype, 0, a.refresh, eloc_dtype=a.dtype, with_gram=True)
     ms, phases = step.timed(a.steps, a.warmup)
     out = _common(a, wl, props, ms, phases, step, "synthetic (seeded He-initialised FFNN)")
     w1, w2 = wl.model.widths
@@ -303,12 +305,12 @@ def run_heis10(a, torch, nqs, workloads):
     # 2 w1 w2 flops per proposal on the matrix cores
     fpp = 2.0 * w1 * w2
     achieved = props * fpp / (phases["sample"] * 1e-3) / 1e12
-    out["roofline"] = {"kernel": "ffnn_sample_kernel", "bound": "mfma", "achieved": round(achieved, 2),
+    out["roofline"] = {"kernel": "ffnn_sample_reg_kernel", "bound": "mfma", "achieved": round(achieved, 2),
                        "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
                        "flops_per_proposal": fpp, "proposals_per_launch": props}
     if not a.no_compare:
-        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, a.dtype, False, others=("f16",)))
+        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, a.dtype, True, others=("f16",)))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, params, budget_s=15.0)
     return out
@@ -392,8 +394,13 @@ def run_heis20(a, torch, nqs, workloads):
         for _ in range(a.warmup):
             nqs.nqs_sample(model, cfg, state, samples, None, acc)
         torch.cuda.synchronize()
+        def gram():
+            if a.gram_chunked:
+                nqs.nqs_sample_gram(model, samples[sweeps - 1, :n_t], T)
+            else:
+                nqs.nqs_sample_gram_factored(model, samples[sweeps - 1, :n_t], T)
         if n_t and dt == a.dtype:
-            nqs.nqs_sample_gram(model, samples[sweeps - 1, :n_t], T)   # warm the workspace
+            gram()   # warm the workspace
         ev = _events(torch, 4)
         t_s = t_e = t_t = 0.0
         for _ in range(a.steps):
@@ -404,7 +411,7 @@ def run_heis20(a, torch, nqs, workloads):
             ev[2].record()
             # O and T come from the FP32 copy whatever the sampling dtype: timed once
             if n_t and dt == a.dtype:
-                nqs.nqs_sample_gram(model, samples[sweeps - 1, :n_t], T)
+                gram()
             ev[3].record()
             torch.cuda.synchronize()
             t_s += ev[0].elapsed_time(ev[1]) / a.steps
@@ -426,7 +433,7 @@ def run_heis20(a, torch, nqs, workloads):
                    "move": "exchange", "chains": C, "sweeps_per_step": sweeps, "burnin": 0,
                    "proposals_per_step": props, "eloc_samples": n_el, "parallelism": "single GPU"},
         "phases_ms": {"sample": round(r0["sample_ms"], 3), "local_energy": round(r0["eloc_ms"], 3),
-                      "gram_T_chunked": round(r0["gram_ms"], 3)},
+                      ("gram_T_chunked" if a.gram_chunked else "gram_T_factored"): round(r0["gram_ms"], 3)},
         "eloc_samples_per_s": n_el / (r0["eloc_ms"] * 1e-3),
         "acceptance": r0["acceptance"],
         "roofline": {"kernel": "deep_gemm_kernel (all layers)", "bound": "mfma", "achieved": round(achieved, 2),
@@ -441,14 +448,27 @@ def run_heis20(a, torch, nqs, workloads):
                                   / (r0["sample_ms"] + r0["eloc_ms"]))
     if n_t:
         P = model.n_params
-        chunk = max(32, ((1 << 28) // n_t) & ~31)
-        t_flops = 1.0 * n_t * (n_t + 1) * P    # 2P flops per entry of the upper triangle of the symmetric T
-        tf = t_flops / (r0["gram_ms"] * 1e-3) / 1e12
-        out["gram_T"] = {"samples": n_t, "params": P, "column_block": chunk, "blocks": -(-P // chunk),
-                         "ms": round(r0["gram_ms"], 3), "tflops": round(tf, 2), "peak_fp32_mfma": 157.3,
-                         "frac": round(tf / 157.3, 4),
-                         "note": "whole phase: per-sample factors of O once, then per column block the "
-                                 "expansion of O, its column means and the contraction"}
+        if a.gram_chunked:
+            chunk = max(32, ((1 << 28) // n_t) & ~31)
+            t_flops = 1.0 * n_t * (n_t + 1) * P    # 2P flops per entry of the upper triangle of the symmetric T
+            tf = t_flops / (r0["gram_ms"] * 1e-3) / 1e12
+            out["gram_T"] = {"path": "column blocks", "samples": n_t, "params": P, "column_block": chunk,
+                             "blocks": -(-P // chunk), "ms": round(r0["gram_ms"], 3), "tflops": round(tf, 2),
+                             "peak_fp32_mfma": 157.3, "frac": round(tf / 157.3, 4),
+                             "note": "whole phase: per-sample factors of O once, then per column block the "
+                                     "expansion of O, its column means and the contraction"}
+        else:
+            dsum = sum([N, *w[:-1]]) + sum(w)   # factor widths: layer inputs and deltas
+            nt = -(-n_t // 64)
+            fac_flops = 2.0 * (nt * (nt + 1) // 2) * 64 * 64 * dsum   # contraction of the factor Gram tiles
+            param_flops = 1.0 * n_t * (n_t + 1) * P                   # the same T contracted over all P
+            out["gram_T"] = {"path": "factored", "samples": n_t, "params": P, "factor_width": dsum,
+                             "ms": round(r0["gram_ms"], 3),
+                             "factor_contraction_tflop": round(fac_flops / 1e12, 3),
+                             "parameter_space_equivalent_tflop": round(param_flops / 1e12, 2),
+                             "note": "whole phase: per-sample factors (layer inputs and deltas), FP64 means, "
+                                     "per-sample centring terms, FP64 matrix-core contraction of the factor "
+                                     "Gram tiles"}
     return out
 
 
