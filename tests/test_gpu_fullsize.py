@@ -150,3 +150,41 @@ def test_heis20_full_size_sweep(nqs):
     f, _ = om.logamp(smp)
     scale = np.abs(ref) + 2 * 800 + 2 * 800 * np.exp(1.0)
     assert np.all(np.abs(el.cpu().numpy() - ref) < 4e-6 * np.maximum(1.0, np.abs(f)) * scale)
+
+
+@pytest.mark.parametrize("which,n", [("heis10", 16384), ("heis20", 4096)])
+def test_factored_T_bench_size(nqs, which, n):
+    """T of the sample set the benchmark step forms (16384 samples of the 10x10
+    network, 4096 of the 20x20 one), from the factors of O: entries at sampled
+    (i, j) against the oracle, whose column means are accumulated over the
+    samples in batches of its FP64 log-derivatives."""
+    wl = workloads.cfg3_heis_10x10() if which == "heis10" else workloads.cfg5_heis_20x20()
+    params = workloads.params_for(wl)
+    N, widths = wl.model.n_visible, wl.model.widths
+    model = nqs.Model.from_workload(wl, params)
+    smp = workloads.random_spins(n, N, 21, zero_mag=True)
+    st = torch.from_numpy(smp).to(DEV)
+    T = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_sample_gram_factored(model, st, T)
+    torch.cuda.synchronize()
+    _say(f"{which}: factored T of {n} samples done; oracle column means")
+    om = oracle.OracleModel("ffnn", N, widths, oracle.round_to(params, "f32"), act_dtype="f32")
+    mu = np.zeros(model.n_params)
+    batch = max(1, (1 << 30) // (8 * model.n_params))
+    for k0 in range(0, n, batch):
+        _, Ob = oracle.logpsi_grad(om, smp[k0:k0 + batch])
+        mu += Ob.sum(axis=0)
+        del Ob
+    mu /= n
+    rng = np.random.default_rng(17)
+    pairs = [(0, 0), (n - 1, n - 1), (0, n - 1)] + [tuple(int(v) for v in rng.choice(n, 2)) for _ in range(9)]
+    idx = sorted({i for p in pairs for i in p})
+    _, Orows = oracle.logpsi_grad(om, smp[idx])
+    row = {k: Orows[m] - mu for m, k in enumerate(idx)}
+    got = T.cpu().numpy()
+    for i, j in pairs:
+        ref = float(np.dot(row[i], row[j])) / n
+        tol = 1e-5 * np.linalg.norm(row[i]) * np.linalg.norm(row[j]) / n + 1e-9
+        assert abs(got[i, j] - ref) < tol, (i, j, got[i, j], ref, tol)
+    assert np.array_equal(got[:256, :256], got[:256, :256].T)
+    assert np.all(np.diag(got) >= 0)
