@@ -20,6 +20,9 @@
  *   nqs_sample_gram    T accumulated over column blocks of O, so that O is
  *                      never held whole (large networks)
  *   nqs_sample_gram_factored  the same T from the per-layer factors of O, FP64
+ *   nqs_sr_solve / nqs_sr_update  the stochastic-reconfiguration step in
+ *                      sample space: (T + shift) y = eps - mean eps, then
+ *                      master -= lr O^T (y - mean y) / n (App. I.2)
  *
  * Conventions (every entry point):
  *   - All array arguments are DEVICE pointers unless marked "host".  The
@@ -242,6 +245,29 @@ nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64
  * Workspace: n x (sum of factor widths) floats plus the mean matrices
  * (about P doubles) and a few n-vectors.  T is overwritten; deterministic. */
 nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t n, float *T, void *stream);
+
+/* Stochastic-reconfiguration step in sample space (App. I.2, Eq. eq:smat;
+ * forces of Eq. eq:forces).  The direction delta of (S + shift) delta = F,
+ * S = Obar^T Obar / n, F = Obar^T (eps - mean eps) / n, equals Obar^T y / n
+ * with (T + shift) y = eps - mean eps, T = Obar Obar^T / n (push-through
+ * identity; S and T share their non-zero spectrum).
+ *
+ * nqs_sr_solve: y[n] (FP64, device) from T[n][n] (FP32, e.g. from
+ *   nqs_sample_gram_factored) and eloc[n] (FP64), by Jacobi-preconditioned
+ *   conjugate gradients in FP64 until ||r|| <= tol ||b|| or max_iter
+ *   iterations.  shift >= 0 (T is singular along the constant vector, which
+ *   the centred right-hand side avoids).  Synchronises `stream`; *iters and
+ *   *rel_resid (host pointers, may be NULL) report the iteration count and
+ *   ||r|| / ||b|| (0 when b = 0).  Deterministic.
+ * nqs_sr_update: master[P] (FP64, device, the caller's parameter vector) -=
+ *   lr * delta, delta = O^T (y - mean y) / n through the FP32 copy's
+ *   log-derivatives of `samples` (the n samples T was formed from).  The
+ *   model's own copies are not touched: pass `master` to
+ *   nqs_model_set_params_device for the next step. */
+nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double shift, double tol, int32_t max_iter,
+                        double *y, int32_t *iters, double *rel_resid, void *stream);
+nqs_status nqs_sr_update(nqs_model *m, const int8_t *samples, int64_t n, const double *y, double lr, double *master,
+                         void *stream);
 
 const char *nqs_last_error(void);
 const char *nqs_version(void);

@@ -339,6 +339,15 @@ def smatrix(O: np.ndarray, weights=None) -> np.ndarray:
     return S
 
 
+def sr_direction(O: np.ndarray, eloc: np.ndarray, shift: float, weights=None) -> np.ndarray:
+    """Stochastic-reconfiguration direction in parameter space (App. I.2,
+    Eq. eq:smat with the forces of Eq. eq:forces): delta solving
+    (S + shift I) delta = F, S and F as defined above, FP64, dense solve."""
+    S = smatrix(O, weights)
+    F = forces(O, eloc, weights)
+    return np.linalg.solve(S + shift * np.eye(S.shape[0]), F)
+
+
 def tmatrix(O: np.ndarray) -> np.ndarray:
     O = np.ascontiguousarray(O, dtype=np.float64)
     T = np.empty((O.shape[0], O.shape[0]))

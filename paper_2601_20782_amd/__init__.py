@@ -22,7 +22,7 @@ from ._abi import DTYPE_CODES, NqsError, check, load
 __all__ = [
     "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
     "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
-    "nqs_downcast", "LogPsi", "NqsError", "load",
+    "nqs_sr_solve", "nqs_sr_update", "nqs_downcast", "LogPsi", "NqsError", "load",
 ]
 
 
@@ -254,6 +254,27 @@ def nqs_sample_gram_factored(model: Model, samples: torch.Tensor, T: torch.Tenso
     n = samples.numel() // model.n_visible
     assert T.dtype == torch.float32 and T.numel() == n * n
     check(load().nqs_sample_gram_factored(model.handle, _ptr(samples), n, _ptr(T), _stream(stream)))
+
+
+def nqs_sr_solve(T: torch.Tensor, eloc: torch.Tensor, shift: float, y: torch.Tensor, tol: float = 1e-10,
+                 max_iter: int = 1000, stream=None):
+    """(T + shift) y = eloc - mean(eloc); returns (iterations, relative residual)."""
+    n = eloc.numel()
+    assert T.dtype == torch.float32 and T.numel() == n * n
+    assert eloc.dtype == torch.float64 and y.dtype == torch.float64 and y.numel() == n
+    it = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    check(load().nqs_sr_solve(_ptr(T), _ptr(eloc), n, float(shift), float(tol), int(max_iter), _ptr(y),
+                              ctypes.byref(it), ctypes.byref(rr), _stream(stream)))
+    return it.value, rr.value
+
+
+def nqs_sr_update(model: Model, samples: torch.Tensor, y: torch.Tensor, lr: float, master: torch.Tensor,
+                  stream=None) -> None:
+    n = samples.numel() // model.n_visible
+    assert y.dtype == torch.float64 and y.numel() == n
+    assert master.dtype == torch.float64 and master.numel() == model.n_params
+    check(load().nqs_sr_update(model.handle, _ptr(samples), n, _ptr(y), float(lr), _ptr(master), _stream(stream)))
 
 
 def nqs_forces(O: torch.Tensor, eloc: torch.Tensor, F: torch.Tensor, Omean: Optional[torch.Tensor] = None,

@@ -35,7 +35,7 @@ struct Workspace {
     size_t bytes = 0;
 };
 static std::mutex g_ws_mutex;
-static std::vector<Workspace> g_ws;
+static std::vector<Workspace> g_ws;   // [device * kWorkspaceSlots + slot]
 
 int device_cus()
 {
@@ -53,13 +53,14 @@ int device_cus()
     return cache[dev];
 }
 
-void *workspace(size_t bytes, hipStream_t stream)
+void *workspace_slot(int slot, size_t bytes, hipStream_t stream)
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess || slot < 0 || slot >= kWorkspaceSlots) return nullptr;
     std::lock_guard<std::mutex> lock(g_ws_mutex);
-    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
-    Workspace &w = g_ws[dev];
+    const size_t idx = (size_t)dev * kWorkspaceSlots + slot;
+    if (g_ws.size() <= idx) g_ws.resize(idx + 1);
+    Workspace &w = g_ws[idx];
     if (w.bytes < bytes) {
         if (w.ptr) {
             // the old buffer may still be in use by earlier work on `stream`
@@ -74,6 +75,8 @@ void *workspace(size_t bytes, hipStream_t stream)
     }
     return w.ptr;
 }
+
+void *workspace(size_t bytes, hipStream_t stream) { return workspace_slot(0, bytes, stream); }
 
 int64_t model_num_params(const nqs_model_desc &d)
 {

@@ -97,6 +97,10 @@ int device_cus();
 
 // Per-device growable scratch (never shrinks; freed at process exit).
 void *workspace(size_t bytes, hipStream_t stream);
+// Slot 1 is for entry points that hold vectors across calls into others
+// (which use slot 0).
+constexpr int kWorkspaceSlots = 2;
+void *workspace_slot(int slot, size_t bytes, hipStream_t stream);
 
 int64_t model_num_params(const nqs_model_desc &d);
 

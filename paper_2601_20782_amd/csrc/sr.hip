@@ -1,0 +1,206 @@
+// Stochastic reconfiguration step in sample space (App. I.2, Eq. eq:smat, with
+// the forces of Eq. eq:forces).  The update direction delta solves
+//     (S + shift) delta = F,   S = Obar^T Obar / n,   F = Obar^T e / n,
+// e = eps - mean(eps).  S and T = Obar Obar^T / n share their non-zero
+// spectrum, and (S + shift)^{-1} Obar^T = Obar^T (T + shift)^{-1}, so
+//     delta = Obar^T y / n,   (T + shift) y = e:
+// an n x n system in place of a P x P one.  Obar^T y = O^T (y - mean y), one
+// vector-Jacobian product of the log-derivatives.
+//
+// nqs_sr_solve: Jacobi-preconditioned conjugate gradients, FP64 vectors and
+//   scalars, FP32 T read once per iteration (one wave per row, FP64 sums).
+//   Every reduction is a fixed-order single-block tree, so the iterates do
+//   not depend on timing.  Scalars stay on the device (one slot per
+//   iteration); the host reads the residual every kCheck iterations.
+// nqs_sr_update: delta = O^T (y - mean y) / n through the FP32 copy's VJP,
+//   master -= lr * delta in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "internal.h"
+#include "nqs.h"
+
+namespace nqs {
+
+constexpr int kSumThreads = 1024;
+constexpr int kCheck = 8;
+
+// out[0] = sum_k a[k] * (b ? b[k] : 1), one block, fixed order
+__global__ void __launch_bounds__(kSumThreads) sr_dot_kernel(const double *__restrict__ a,
+                                                             const double *__restrict__ b, int64_t n,
+                                                             double *__restrict__ out)
+{
+    __shared__ double red[kSumThreads];
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += kSumThreads) s = fma(a[k], b ? b[k] : 1.0, s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kSumThreads / 2; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Ap = (T + shift) p, one wave per row
+__global__ void __launch_bounds__(256) sr_matvec_kernel(const float *__restrict__ T, const double *__restrict__ p,
+                                                        int64_t n, double shift, double *__restrict__ Ap)
+{
+    const int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const float *t = T + row * n;
+    double s = 0.0;
+    for (int64_t k = lane; k < n; k += 64) s = fma((double)t[k], p[k], s);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) Ap[row] = s + shift * p[row];
+}
+
+// b = eps - mean (sum[0] = sum of eps); d = diag(T) + shift; x = 0, r = b, z = r / d, p = z
+__global__ void sr_init_kernel(const float *__restrict__ T, const double *__restrict__ eps,
+                               const double *__restrict__ sum, int64_t n, double shift, double *__restrict__ d,
+                               double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
+                               double *__restrict__ p)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double b = eps[k] - sum[0] / (double)n;
+    const double dk = (double)T[k * n + k] + shift;
+    const double inv = dk > 0.0 ? 1.0 / dk : 1.0;
+    d[k] = inv;
+    x[k] = 0.0;
+    r[k] = b;
+    z[k] = b * inv;
+    p[k] = b * inv;
+}
+
+// alpha = rz / pAp;  x += alpha p;  r -= alpha Ap;  z = r / d
+__global__ void sr_step_kernel(const double *__restrict__ rz, const double *__restrict__ pap, int64_t n,
+                               const double *__restrict__ d, const double *__restrict__ p,
+                               const double *__restrict__ Ap, double *__restrict__ x, double *__restrict__ r,
+                               double *__restrict__ z)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double alpha = pap[0] != 0.0 ? rz[0] / pap[0] : 0.0;
+    x[k] = fma(alpha, p[k], x[k]);
+    const double rk = fma(-alpha, Ap[k], r[k]);
+    r[k] = rk;
+    z[k] = rk * d[k];
+}
+
+// p = z + (rz_new / rz_old) p
+__global__ void sr_dir_kernel(const double *__restrict__ rz_old, const double *__restrict__ rz_new, int64_t n,
+                              const double *__restrict__ z, double *__restrict__ p)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double beta = rz_old[0] != 0.0 ? rz_new[0] / rz_old[0] : 0.0;
+    p[k] = fma(beta, p[k], z[k]);
+}
+
+// yc = (y - mean y) / n as FP32 (sum[0] = sum of y)
+__global__ void sr_center_kernel(const double *__restrict__ y, const double *__restrict__ sum, int64_t n,
+                                 float *__restrict__ yc)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) yc[k] = (float)((y[k] - sum[0] / (double)n) / (double)n);
+}
+
+__global__ void sr_apply_kernel(const float *__restrict__ g, int64_t P, double lr, double *__restrict__ master)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < P) master[p] = fma(-lr, (double)g[p], master[p]);
+}
+
+static inline size_t r256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace nqs
+
+using namespace nqs;
+
+extern "C" {
+
+nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double shift, double tol, int32_t max_iter,
+                        double *y, int32_t *iters, double *rel_resid, void *stream)
+{
+    if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
+    if (!T || !eloc || !y) return set_error(NQS_EINVAL, "NULL T/eloc/y");
+    if (!(shift >= 0.0) || !(tol > 0.0) || max_iter < 1) return set_error(NQS_EINVAL, "need shift >= 0, tol > 0, max_iter >= 1");
+    if (n > (int64_t)INT32_MAX * 4) return set_error(NQS_EINVAL, "n too large");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t vec = r256(sizeof(double) * (size_t)n);
+    const size_t nsc = (size_t)max_iter + 2;
+    char *ws = (char *)workspace_slot(1, 5 * vec + 3 * r256(sizeof(double) * nsc) + 256, s);
+    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    double *d = (double *)ws, *r = (double *)(ws + vec), *z = (double *)(ws + 2 * vec), *p = (double *)(ws + 3 * vec),
+           *Ap = (double *)(ws + 4 * vec);
+    double *rz = (double *)(ws + 5 * vec);                       // rz[k]: r.z after k iterations
+    double *pap = rz + r256(sizeof(double) * nsc) / sizeof(double);
+    double *misc = pap + r256(sizeof(double) * nsc) / sizeof(double);   // [0] sum of eps, [1] b.b, [2] r.r
+    const unsigned eb = (unsigned)((n + 255) / 256), mb = (unsigned)((n + 3) / 4);
+
+    hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, eloc, (const double *)nullptr, n, misc);
+    hipLaunchKernelGGL(sr_init_kernel, dim3(eb), dim3(256), 0, s, T, eloc, misc, n, shift, d, y, r, z, p);
+    hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, r, n, misc + 1);
+    hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, z, n, rz);
+    NQS_HIP_TRY(hipGetLastError());
+    double bb = 0.0;
+    NQS_HIP_TRY(hipMemcpyAsync(&bb, misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    NQS_HIP_TRY(hipStreamSynchronize(s));
+    double rel = 0.0;
+    int k = 0;
+    if (bb > 0.0) {
+        rel = 1.0;
+        while (k < max_iter) {
+            hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, T, p, n, shift, Ap);
+            hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, p, Ap, n, pap + k);
+            hipLaunchKernelGGL(sr_step_kernel, dim3(eb), dim3(256), 0, s, rz + k, pap + k, n, d, p, Ap, y, r, z);
+            hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, z, n, rz + k + 1);
+            hipLaunchKernelGGL(sr_dir_kernel, dim3(eb), dim3(256), 0, s, rz + k, rz + k + 1, n, z, p);
+            ++k;
+            if (k % kCheck == 0 || k == max_iter) {
+                hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, r, n, misc + 2);
+                NQS_HIP_TRY(hipGetLastError());
+                double rr = 0.0;
+                NQS_HIP_TRY(hipMemcpyAsync(&rr, misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+                NQS_HIP_TRY(hipStreamSynchronize(s));
+                rel = std::sqrt(rr / bb);
+                if (!(rel > tol)) break;   // converged (or NaN: stop and report it)
+            }
+        }
+    }
+    if (iters) *iters = k;
+    if (rel_resid) *rel_resid = rel;
+    return NQS_OK;
+}
+
+nqs_status nqs_sr_update(nqs_model *m, const int8_t *samples, int64_t n, const double *y, double lr, double *master,
+                         void *stream)
+{
+    if (!m) return set_error(NQS_EINVAL, "NULL model");
+    if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
+    if (!samples || !y || !master) return set_error(NQS_EINVAL, "NULL samples/y/master");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t P = m->P;
+    const size_t yb = r256(sizeof(float) * (size_t)n), gb = r256(sizeof(float) * (size_t)P);
+    char *ws = (char *)workspace_slot(1, yb + gb + 256, s);
+    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    float *yc = (float *)ws, *g = (float *)(ws + yb);
+    double *sum = (double *)(ws + yb + gb);
+    hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, y, (const double *)nullptr, n, sum);
+    hipLaunchKernelGGL(sr_center_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, sum, n, yc);
+    NQS_HIP_TRY(hipGetLastError());
+    nqs_status st = m->desc.arch == NQS_RBM ? rbm_logpsi_grad(m, samples, n, nullptr, nullptr, yc, g, s, 0, P)
+                                             : ffnn_logpsi_grad(m, samples, n, nullptr, nullptr, yc, g, s, 0, P);
+    if (st != NQS_OK) return st;
+    hipLaunchKernelGGL(sr_apply_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, g, P, lr, master);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+"""GPU parity of the stochastic-reconfiguration step in sample space (App. I.2,
+Eq. eq:smat with the forces of Eq. eq:forces): the conjugate-gradient solve of
+(T + shift) y = eps - mean eps, the parameter update master -= lr O^T (y -
+mean y) / n against the oracle's parameter-space direction, and a short
+training run on a 12-site TFIM chain against exact diagonalisation.  Every
+call goes through the C interface."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_20782_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("n,P,shift", [(300, 500, 1e-2), (200, 50, 1e-3), (65, 65, 0.3), (1, 3, 1e-2)])
+def test_sr_solve_matches_dense_solve(nqs, n, P, shift):
+    rng = np.random.default_rng(n + P)
+    O = (rng.normal(size=(n, P)) + rng.normal(size=P)).astype(np.float32)
+    T = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_gram(torch.from_numpy(O).to(DEV), 1, T)
+    eps = rng.normal(-3.0, 1.5, size=n)
+    y = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+    its, rr = nqs.nqs_sr_solve(T, torch.from_numpy(eps).to(DEV), shift, y, tol=1e-12, max_iter=2000)
+    T64 = T.cpu().numpy().astype(np.float64)
+    b = eps - eps.mean()
+    got = y.cpu().numpy()
+    if n == 1:
+        assert its == 0 and rr == 0.0 and got[0] == 0.0
+        return
+    ref = np.linalg.solve(T64 + shift * np.eye(n), b)
+    _say(f"  n={n} shift={shift}: {its} iterations, relative residual {rr:.2e}")
+    assert rr <= 1e-12
+    assert np.max(np.abs(got - ref)) <= 1e-8 * np.abs(ref).max()
+    # the same call again gives the same bits
+    y2 = torch.empty_like(y)
+    nqs.nqs_sr_solve(T, torch.from_numpy(eps).to(DEV), shift, y2, tol=1e-12, max_iter=2000)
+    assert torch.equal(y, y2)
+
+
+def test_sr_solve_reports_the_iteration_cap(nqs):
+    n = 256
+    rng = np.random.default_rng(1)
+    O = rng.normal(size=(n, 400)).astype(np.float32)
+    T = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_gram(torch.from_numpy(O).to(DEV), 1, T)
+    y = torch.empty(n, dtype=torch.float64, device=DEV)
+    its, rr = nqs.nqs_sr_solve(T, torch.from_numpy(rng.normal(size=n)).to(DEV), 1e-4, y, tol=1e-14, max_iter=3)
+    assert its == 3 and 0.0 < rr < 1.0
+
+
+@pytest.mark.parametrize("arch,N,widths,n,shift", [("rbm", 12, (24,), 512, 1e-2), ("rbm", 16, (16,), 300, 1e-3),
+                                                   ("ffnn", 16, (24, 12), 400, 1e-2)])
+def test_sr_update_matches_oracle_direction(nqs, arch, N, widths, n, shift):
+    """master -= lr * delta with delta from T (factored), the CG solve and the
+    VJP, against the oracle's (S + shift)^{-1} F in parameter space (FP64)."""
+    ham_w = workloads.Hamiltonian("tfim", workloads.Lattice(1, N), 1.0, -1.0)
+    p = workloads.rbm_params(N, widths[0], 0.1, 4) if arch == "rbm" else workloads.ffnn_params(N, widths, 4, 0.1)
+    model = nqs.Model(arch, N, widths, p)
+    smp = workloads.random_spins(n, N, 8)
+    st = torch.from_numpy(smp).to(DEV)
+    eloc = torch.empty(n, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(ham_w), st, eloc)
+    T = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    nqs.nqs_sample_gram_factored(model, st, T)
+    y = torch.empty(n, dtype=torch.float64, device=DEV)
+    its, rr = nqs.nqs_sr_solve(T, eloc, shift, y, tol=1e-12, max_iter=5000)
+    master = torch.from_numpy(p.copy()).to(DEV)
+    lr = 0.25
+    nqs.nqs_sr_update(model, st, y, lr, master)
+    delta = (p - master.cpu().numpy()) / lr
+    om = oracle.OracleModel(arch, N, widths, oracle.round_to(p, "f32"),
+                            **({} if arch == "rbm" else {"act_dtype": "f32"}))
+    _, rO = oracle.logpsi_grad(om, smp)
+    reps = oracle.local_energy(om, ham_w, smp)
+    ref = oracle.sr_direction(rO, reps, shift)
+    err = np.linalg.norm(delta - ref) / np.linalg.norm(ref)
+    _say(f"  {arch} {widths}: CG {its} iterations (residual {rr:.1e}), |delta - ref| / |ref| = {err:.2e}")
+    assert err < 2e-3
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_vmc_training_tfim12_reaches_ground_state(nqs, dtype):
+    """120 SR steps of an RBM (alpha = 2) on the 12-site TFIM chain at the
+    critical field (J = 1, h = -1, periodic), sampling from the `dtype` copy:
+    the energy reaches the exact ground-state energy to 1e-3 (both copies
+    reach about 1.2e-4)."""
+    N, M = 12, 24
+    ham_w = workloads.Hamiltonian("tfim", workloads.Lattice(1, N), 1.0, -1.0)
+    ham = nqs.Hamiltonian.from_workload(ham_w)
+    e0, _ = exact.ground_state("tfim", 1, N, 1.0, -1.0)
+    p = workloads.rbm_params(N, M, 0.01, 3)
+    model = nqs.Model("rbm", N, (M,), p)
+    master = torch.from_numpy(p.copy()).to(DEV)
+    C, S = 512, 4
+    n = C * S
+    state = torch.empty(C, N, dtype=torch.int8, device=DEV)
+    samples = torch.empty(S, C, N, dtype=torch.int8, device=DEV)
+    acc = torch.empty(C, dtype=torch.int64, device=DEV)
+    eloc = torch.empty(n, dtype=torch.float64, device=DEV)
+    stats = torch.empty(4, dtype=torch.float64, device=DEV)
+    T = torch.empty(n, n, dtype=torch.float32, device=DEV)
+    y = torch.empty(n, dtype=torch.float64, device=DEV)
+    energies, offset = [], 0
+    for it in range(120):
+        model.set_params_device(master)
+        model.prepare(dtype)
+        burn = 20 if it == 0 else 2
+        cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=burn, seed=11, dtype=dtype, step_offset=offset,
+                               init_chains=it == 0)
+        nqs.nqs_sample(model, cfg, state, samples, None, acc)
+        offset += (burn + S) * N
+        flat = samples.reshape(n, N)
+        nqs.nqs_local_energy(model, ham, flat, eloc)
+        nqs.nqs_energy_stats(eloc, C, stats)
+        nqs.nqs_sample_gram_factored(model, flat, T)
+        nqs.nqs_sr_solve(T, eloc, 1e-2, y, tol=1e-6, max_iter=300)
+        nqs.nqs_sr_update(model, flat, y, 0.05, master)
+        energies.append(float(stats[0].item()))
+        if it % 20 == 0:
+            _say(f"  {dtype} iteration {it}: E = {energies[-1]:.5f} (exact {e0:.5f})")
+    e_end = float(np.mean(energies[-10:]))
+    _say(f"  {dtype}: mean of the last 10 energies {e_end:.5f}, exact {e0:.5f}, rel {abs(e_end - e0) / abs(e0):.2e}")
+    assert abs(e_end - e0) <= 1e-3 * abs(e0)
