@@ -256,6 +256,26 @@ def _compare_fp32(a, nqs, torch, wl, params, step, ms, props, eloc_dtype, with_g
     return out
 
 
+def _sr_step(nqs, torch, step, shift=1e-2, lr=1e-2):
+    """The stochastic-reconfiguration step that would follow the timed step (not part of it): CG solve of
+    (T + shift) y = eps - mean eps on the last sweep's samples, then the FP64 parameter update."""
+    C, S = step.C, step.S
+    y = torch.empty(C, dtype=torch.float64, device="cuda:0")
+    master = step.master.clone()
+    eps = step.eloc[(S - 1) * C:]
+    nqs.nqs_sr_solve(step.T, eps, shift, y, tol=1e-8, max_iter=2000)   # warm the workspace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, rr = nqs.nqs_sr_solve(step.T, eps, shift, y, tol=1e-8, max_iter=2000)
+    t1 = time.perf_counter()
+    nqs.nqs_sr_update(step.model, step.samples[S - 1], y, lr, master)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"samples": C, "shift": shift, "tol": 1e-8, "cg_iterations": its, "rel_residual": rr,
+            "solve_ms": round(1e3 * (t1 - t0), 3), "update_ms": round(1e3 * (t2 - t1), 3),
+            "note": "outside the timed step; T from the step's factored Gram phase"}
+
+
 def run_tfim10(a, torch, nqs, workloads):
     wl = workloads.cfg2_tfim_10x10()
     params = workloads.params_for(wl)
@@ -282,6 +302,7 @@ def run_tfim10(a, torch, nqs, workloads):
                        "traffic": kernel_traffic("rbm_sample_kernel", "tfim2d_10x10_rbm_bf16_hbm_traffic.txt"),
                        "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
                        "flops_per_proposal": round(fpp, 2), "proposals_per_launch": props}
+    out["sr_step"] = _sr_step(nqs, torch, step)
     if not a.no_compare:
         out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, "f32", True, others=("f16", "e4m3")))
     if not a.no_cpu_baseline:
