@@ -9,6 +9,8 @@
  *   nqs_sample         Metropolis-Hastings sampling of pi = |psi|^2 / sum |psi|^2
  *                      (Sec. II, Eq. eq:loss; acceptance Sec. III.A; single-flip
  *                      proposal App. C Eq. eq:app:local_prop; exchange move App. E)
+ *   nqs_sample_noisy   the same sampler on log pi + zeta(x), zeta fixed per x
+ *                      (Sec. V.A, Eq. eq:pert_chain)
  *   nqs_local_energy   eps(x) = sum_{x'} H(x,x') psi(x')/psi(x)
  *                      (App. I.1, Eq. eq:local_energies; TFIM Eq. eq:TFIM; Heisenberg App. E)
  *   nqs_energy_stats   FP64 mean / variance / error bar of the local energies (Eq. eq:loss)
@@ -183,6 +185,20 @@ typedef struct {
  * descriptors are staged in the library workspace; the call synchronises
  * `stream` once before launching. */
 nqs_status nqs_sample_batched(const nqs_sample_job *jobs, int32_t n_jobs, int32_t mode, void *stream);
+
+/* Metropolis-Hastings sampling of the noisy target of Sec. V.A:
+ *   log pi~(x) = log pi(x) + zeta(x),  zeta(x) = noise_sigma * g(x),
+ * g(x) a standard normal held fixed per configuration: Philox4x32-10 with the
+ * configuration's four 32-bit words as counter (spin i up = bit i % 32 of word
+ * i / 32, sites >= N zero) and noise_seed as key; then Box-Muller on the first
+ * two outputs, u1 = ((r0 >> 8) + 1) 2^-24, u2 = (r1 >> 8) 2^-24,
+ * g = sqrt(-2 ln u1) cos(2 pi u2).  (The paper's log psi~ = log psi + zeta/2.)
+ * The proposal stream, arguments and outputs are those of nqs_sample; logpsi
+ * is the noiseless log|psi|.  RBM with single flips, N <= 128, the ratio table
+ * in LDS; noise_sigma = 0 is nqs_sample.  For studying how a perturbation of
+ * log pi biases expectation values and acceptance (Eq. eq:pert_chain). */
+nqs_status nqs_sample_noisy(nqs_model *m, const nqs_sample_cfg *cfg, double noise_sigma, uint64_t noise_seed,
+                            int8_t *chain_state, int8_t *samples, float *logpsi, uint64_t *n_accepted, void *stream);
 
 /* Local energies eps[n_samples] (FP64 sums of FP32 amplitude ratios computed
  * from the `eval_dtype` copy of the parameters: NQS_F32 by default). */

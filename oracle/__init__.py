@@ -68,6 +68,7 @@ def lib():
         _lib = ctypes.CDLL(build())
         P = ctypes.c_void_p
         _lib.orc_philox4x32_10.argtypes = [P, P, P]
+        _lib.orc_noise_zeta.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, P]
         _lib.orc_round.argtypes = [ctypes.c_double, ctypes.c_int32]
         _lib.orc_round.restype = ctypes.c_double
         _lib.orc_round_array.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P]
@@ -337,6 +338,17 @@ def smatrix(O: np.ndarray, weights=None) -> np.ndarray:
     S = np.empty((O.shape[1], O.shape[1]))
     lib().orc_smatrix(_ptr(O), _ptr(w), O.shape[0], O.shape[1], _ptr(S))
     return S
+
+
+def noise_zeta(configs: np.ndarray, sigma: float, seed: int) -> np.ndarray:
+    """zeta(x) of the noisy target log pi~ = log pi + zeta (Sec. V.A): sigma times a
+    standard normal fixed per configuration (Philox keyed by the configuration
+    bits, Box-Muller), FP64, one value per row of `configs` (N <= 128)."""
+    c = np.ascontiguousarray(configs, dtype=np.int8)
+    n, N = c.shape
+    out = np.empty(n)
+    lib().orc_noise_zeta(_ptr(c), n, N, float(sigma), int(seed), _ptr(out))
+    return out
 
 
 def sr_direction(O: np.ndarray, eloc: np.ndarray, shift: float, weights=None) -> np.ndarray:

@@ -103,6 +103,26 @@ static void stream_block(uint64_t seed, uint64_t step, uint32_t chain, uint32_t 
     orc_philox4x32_10(ctr, key, out);
 }
 
+/* zeta(x) = sigma g(x) of the noisy target log pi~ = log pi + zeta (Sec. V.A):
+ * g a standard normal fixed per configuration.  Philox4x32-10 with the
+ * configuration's 32-bit words as counter (spin i up = bit i % 32 of word i / 32)
+ * and the seed as key; Box-Muller (Box and Muller 1958) on the first two
+ * outputs: u1 = ((r0 >> 8) + 1) 2^-24 in (0, 1], u2 = (r1 >> 8) 2^-24,
+ * g = sqrt(-2 ln u1) cos(2 pi u2).  N <= 128. */
+void orc_noise_zeta(const int8_t *configs, int64_t n, int32_t N, double sigma, uint64_t seed, double *out)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t w[4] = {0u, 0u, 0u, 0u}, r[4];
+        for (int32_t i = 0; i < N && i < 128; ++i)
+            if (configs[k * N + i] > 0) w[i >> 5] |= 1u << (i & 31);
+        orc_philox4x32_10(w, key, r);
+        const double u1 = (double)((r[0] >> 8) + 1u) / 16777216.0;
+        const double u2 = (double)(r[1] >> 8) / 16777216.0;
+        out[k] = sigma * sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);
+    }
+}
+
 /* uniform index in [0, n) from a 32-bit word: floor(r * n / 2^32) */
 static int32_t index_from_word(uint32_t r, int32_t n)
 {

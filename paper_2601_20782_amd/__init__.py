@@ -22,7 +22,7 @@ from ._abi import DTYPE_CODES, NqsError, check, load
 __all__ = [
     "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
     "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
-    "nqs_sr_solve", "nqs_sr_update", "nqs_downcast", "LogPsi", "NqsError", "load",
+    "nqs_sr_solve", "nqs_sr_update", "nqs_sample_noisy", "nqs_downcast", "LogPsi", "NqsError", "load",
 ]
 
 
@@ -185,6 +185,22 @@ def nqs_sample(model: Model, cfg: SampleConfig, chain_state: torch.Tensor, sampl
     c = cfg.to_c()
     check(load().nqs_sample(model.handle, ctypes.byref(c), _ptr(chain_state), _ptr(samples), _ptr(logpsi),
                             _ptr(n_accepted), ctypes.byref(tr) if tr is not None else None, _stream(stream)))
+
+
+def nqs_sample_noisy(model: Model, cfg: SampleConfig, noise_sigma: float, noise_seed: int, chain_state: torch.Tensor,
+                     samples: Optional[torch.Tensor] = None, logpsi: Optional[torch.Tensor] = None,
+                     n_accepted: Optional[torch.Tensor] = None, stream=None) -> None:
+    N = model.n_visible
+    assert chain_state.dtype == torch.int8 and chain_state.numel() == cfg.n_chains * N
+    if samples is not None:
+        assert samples.dtype == torch.int8 and samples.numel() == cfg.n_sweeps * cfg.n_chains * N
+    if logpsi is not None:
+        assert logpsi.dtype == torch.float32 and logpsi.numel() == cfg.n_sweeps * cfg.n_chains
+    if n_accepted is not None:
+        assert n_accepted.dtype in (torch.int64, torch.uint64) and n_accepted.numel() == cfg.n_chains
+    c = cfg.to_c()
+    check(load().nqs_sample_noisy(model.handle, ctypes.byref(c), float(noise_sigma), int(noise_seed),
+                                  _ptr(chain_state), _ptr(samples), _ptr(logpsi), _ptr(n_accepted), _stream(stream)))
 
 
 def nqs_sample_batched(jobs, mode: int = 0, stream=None) -> None:

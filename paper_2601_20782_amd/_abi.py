@@ -22,7 +22,7 @@ EXPORTS = [
     "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched",
     "nqs_local_energy", "nqs_energy_stats",
     "nqs_logpsi_grad", "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
-    "nqs_sr_solve", "nqs_sr_update",
+    "nqs_sr_solve", "nqs_sr_update", "nqs_sample_noisy",
     "nqs_last_error",
     "nqs_version",
 ]
@@ -97,6 +97,7 @@ def load() -> ctypes.CDLL:
         "nqs_sample_gram_factored": ([P, P, i64, P, P], st),
         "nqs_sr_solve": ([P, P, i64, ctypes.c_double, ctypes.c_double, i32, P, P, P, P], st),
         "nqs_sr_update": ([P, P, i64, P, ctypes.c_double, P, P], st),
+        "nqs_sample_noisy": ([P, P, ctypes.c_double, ctypes.c_uint64, P, P, P, P, P], st),
         "nqs_last_error": ([], ctypes.c_char_p),
         "nqs_version": ([], ctypes.c_char_p),
     }

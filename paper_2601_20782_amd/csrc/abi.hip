@@ -265,6 +265,33 @@ nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_sta
     return ffnn_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
 }
 
+nqs_status nqs_sample_noisy(nqs_model *m, const nqs_sample_cfg *cfg, double noise_sigma, uint64_t noise_seed,
+                            int8_t *chain_state, int8_t *samples, float *logpsi, uint64_t *n_accepted, void *stream)
+{
+    if (!m || !cfg) return set_error(NQS_EINVAL, "NULL model or cfg");
+    if (!(noise_sigma >= 0.0) || !std::isfinite(noise_sigma)) return set_error(NQS_EINVAL, "noise_sigma must be finite and >= 0");
+    if (m->desc.arch != NQS_RBM || cfg->move != NQS_MOVE_FLIP)
+        return set_error(NQS_EUNSUPPORTED, "the noisy target is implemented for the RBM with single flips");
+    if (m->desc.n_visible > 128) return set_error(NQS_EUNSUPPORTED, "the noisy target takes at most 128 sites");
+    if (noise_sigma == 0.0) return nqs_sample(m, cfg, chain_state, samples, logpsi, n_accepted, nullptr, stream);
+    // the same argument checks as nqs_sample, then the noisy kernels
+    const nqs_sample_cfg &c = *cfg;
+    if (c.n_chains < 0 || c.n_sweeps < 0 || c.n_burnin < 0) return set_error(NQS_EINVAL, "negative sizes");
+    if (c.n_chains == 0) return NQS_OK;
+    if (!chain_state) return set_error(NQS_EINVAL, "chain_state is NULL");
+    if (c.n_chains > (int64_t)1 << 31) return set_error(NQS_EINVAL, "n_chains too large");
+    if (c.sweep_size < 0) return set_error(NQS_EINVAL, "sweep_size < 0");
+    if (c.instance_id >= (1u << 24)) return set_error(NQS_EINVAL, "instance_id must fit in 24 bits");
+    if (c.lanes_per_chain != 0 && c.lanes_per_chain != 16 && c.lanes_per_chain != 32 && c.lanes_per_chain != 64)
+        return set_error(NQS_EINVAL, "lanes_per_chain must be 0, 16, 32 or 64");
+    if (c.dtype != NQS_F32 && c.dtype != NQS_F16 && c.dtype != NQS_BF16 && c.dtype != NQS_FP8_E4M3)
+        return set_error(NQS_EINVAL, "sampling dtype must be F32, F16, BF16 or FP8_E4M3");
+    if (c.chain_id_offset < 0 || c.chain_id_offset + c.n_chains > ((int64_t)1 << 32))
+        return set_error(NQS_EINVAL, "global chain ids must fit in 32 bits");
+    return rbm_sample(m, c, chain_state, samples, logpsi, n_accepted, nullptr, (hipStream_t)stream, noise_sigma,
+                      noise_seed);
+}
+
 nqs_status nqs_sample_batched(const nqs_sample_job *jobs, int32_t n_jobs, int32_t mode, void *stream)
 {
     if (n_jobs < 0) return set_error(NQS_EINVAL, "n_jobs < 0");

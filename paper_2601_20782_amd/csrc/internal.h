@@ -112,7 +112,8 @@ nqs_status launch_downcast(const double *src, int64_t n, int dtype, float *dst, 
                            hipStream_t stream);
 nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream);
 nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
-                      float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
+                      float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream,
+                      double noise_sigma = 0.0, uint64_t noise_seed = 0);  // noise_sigma > 0: noisy target
 
 // Sampler launch (one translation unit per lanes-per-chain G).
 struct RbmSampleArgs {
@@ -130,10 +131,13 @@ struct RbmSampleArgs {
     uint32_t *tr_ubits;
     float *tr_delta;
     uint8_t *tr_acc;
+    // noisy target: log pi~(x) = log pi(x) + sigma g(x), g(x) standard normal fixed per x
+    float noise_sigma;
+    uint32_t noise_key0, noise_key1;
 };
 struct RbmLaunch {
     int K, threads, blocks;
-    bool lds, trace;
+    bool lds, trace, noise;
     int init;              // 1: draw the start states inside the kernel (flip moves)
     size_t lds_bytes;
 };

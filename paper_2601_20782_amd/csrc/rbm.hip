@@ -118,7 +118,8 @@ constexpr float kMaxAbsW = 5.0f;
 constexpr size_t kLdsBytes = 160 * 1024;
 
 nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
-                      uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream)
+                      uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream, double noise_sigma,
+                      uint64_t noise_seed)
 {
     nqs_status st = ensure_copy(m, cfg.dtype, stream);
     if (st != NQS_OK) return st;
@@ -147,6 +148,11 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
     A.tr_ubits = tr ? trace->ubits : nullptr;
     A.tr_delta = tr ? trace->delta : nullptr;
     A.tr_acc = tr ? trace->accepted : nullptr;
+    A.noise_sigma = (float)noise_sigma;
+    A.noise_key0 = (uint32_t)noise_seed;
+    A.noise_key1 = (uint32_t)(noise_seed >> 32);
+    const bool noisy = noise_sigma > 0.0;
+    if (noisy && (tr || N > 128)) return set_error(NQS_EUNSUPPORTED, "the noisy sampler takes N <= 128 and no trace");
     if ((int64_t)(cfg.n_burnin + cfg.n_sweeps) * A.sweep_size == 0) {
         // nothing to propose: only the initial states (and acceptance counts) are defined
         if (cfg.init_chains) {
@@ -168,6 +174,7 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
     if (K > kmax(G)) return set_error(NQS_EUNSUPPORTED, "hidden width too large for the sampler (M <= 1024)");
     const size_t tab_bytes = sizeof(float2) * ((size_t)N * M + 1);
     const bool lds = tab_bytes <= kLdsBytes;
+    if (noisy && !lds) return set_error(NQS_EUNSUPPORTED, "the noisy sampler needs the ratio table in LDS");
     // one LDS copy of the table per block; spread the chains over every CU
     const int max_threads = G == 16 ? 256 : (G == 32 ? 512 : 1024);
     const int blocks_per_cu = lds ? (int)std::max<size_t>(1, std::min<size_t>(8, kLdsBytes / tab_bytes)) : 8;
@@ -181,6 +188,7 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
     L.blocks = (int)blocks64;
     L.lds = lds;
     L.trace = tr;
+    L.noise = noisy;
     L.init = cfg.init_chains ? 1 : 0;
     L.lds_bytes = lds ? tab_bytes : 0;
     switch (G) {

@@ -132,6 +132,8 @@ nqs_status rbm_sample_batched(const nqs_sample_job *jobs, int n_jobs, int mode, 
         A.inst = j.cfg.instance_id;
         A.chain_id_offset = (uint32_t)j.cfg.chain_id_offset;
         A.n_traced = 0;
+        A.noise_sigma = 0.0f;
+        A.noise_key0 = A.noise_key1 = 0u;
         A.tr_site = nullptr;
         A.tr_ubits = nullptr;
         A.tr_delta = nullptr;

@@ -133,11 +133,26 @@ __device__ __forceinline__ void load_column(const float2 *__restrict__ tab, int 
     cs[K - 1] = tab[last_ok ? base + (K - 1) * G : last_off];
 }
 
+// zeta(x) / ln 2 of the noisy target, log pi~ = log pi + zeta: Philox4x32-10 with
+// the configuration's four 32-bit words as the counter (spin i up = bit i % 32 of
+// word i / 32) and the noise seed as the key, then Box-Muller on the first two
+// outputs, u1 in (0, 1] and u2 in [0, 1) on the 2^-24 grid.
+__device__ __forceinline__ float noise_zeta_log2(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                                 const RbmSampleArgs &A)
+{
+    const Block4 r = philox4x32_10(w0, w1, w2, w3, A.noise_key0, A.noise_key1);
+    const float u1 = (float)((r.r0 >> 8) + 1u) * 5.9604644775390625e-8f;
+    const float u2 = (float)(r.r1 >> 8) * 5.9604644775390625e-8f;
+    const float g = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+    return A.noise_sigma * g * 1.4426950408889634f;
+}
+
 // Runs chain c on the G lanes of its group (gl = lane in group).  s_tab is the
 // LDS copy of the table when LDS_TAB.  With init, the start state is drawn
 // from the init stream (counter tag 1, spin i = bit i%32 of word i/32) instead
 // of being read from chain_state.
-template <int G, int K, bool LDS_TAB, bool TRACE>
+// With NOISE the target is the noisy pi~ (every lane keeps all configuration words).
+template <int G, int K, bool LDS_TAB, bool TRACE, bool NOISE = false>
 __device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c, int gl, const float2 *s_tab, bool init)
 {
     const int N = A.net.N, M = A.net.M;
@@ -163,6 +178,15 @@ __device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c,
 
     float cc[K], sh[K], lpart;
     float f = rbm_refresh<G, K>(A.net, word, gl, cc, sh, lpart, false);
+    uint32_t nw0 = 0u, nw1 = 0u, nw2 = 0u, nw3 = 0u;
+    float zc = 0.0f;
+    if constexpr (NOISE) {
+        nw0 = group_bcast<G>(word, 0);
+        if (NW > 1) nw1 = group_bcast<G>(word, 1);
+        if (NW > 2) nw2 = group_bcast<G>(word, 2);
+        if (NW > 3) nw3 = group_bcast<G>(word, 3);
+        zc = noise_zeta_log2(nw0, nw1, nw2, nw3, A);
+    }
 
     const int sw = A.sweep_size;
     const int64_t total = (int64_t)(A.n_burnin + A.n_sweeps) * sw;
@@ -225,7 +249,15 @@ __device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c,
         }
         const float lnew = __builtin_amdgcn_logf(prod) + (float)e2;    // log2
         const float dsum = group_sum_uniform<G>(lnew - lpart);
-        const float d2 = fmaf(2.0f, dsum, up ? -a2_c : a2_c);          // log2 of the acceptance ratio
+        float d2 = fmaf(2.0f, dsum, up ? -a2_c : a2_c);                // log2 of the acceptance ratio
+        float zn = 0.0f;
+        const uint32_t fbit = 1u << (i_c & 31);
+        const int fw = i_c >> 5;
+        if constexpr (NOISE) {
+            zn = noise_zeta_log2(nw0 ^ (fw == 0 ? fbit : 0u), nw1 ^ (fw == 1 ? fbit : 0u),
+                                 nw2 ^ (fw == 2 ? fbit : 0u), nw3 ^ (fw == 3 ? fbit : 0u), A);
+            d2 += zn - zc;
+        }
         const bool accept = l2u_c < d2;                                // NaN rejects
         if (accept) {
 #pragma unroll
@@ -235,6 +267,13 @@ __device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c,
             }
             lpart = lnew;
             if (gl == (i_c >> 5)) word ^= 1u << (i_c & 31);
+            if constexpr (NOISE) {
+                nw0 ^= fw == 0 ? fbit : 0u;
+                nw1 ^= fw == 1 ? fbit : 0u;
+                nw2 ^= fw == 2 ? fbit : 0u;
+                nw3 ^= fw == 3 ? fbit : 0u;
+                zc = zn;
+            }
             ++acc;
         }
         if constexpr (TRACE) {
@@ -294,7 +333,7 @@ __device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c,
     if (A.n_acc && gl == 0) A.n_acc[c] = acc;
 }
 
-template <int G, int K, bool LDS_TAB, bool TRACE>
+template <int G, int K, bool LDS_TAB, bool TRACE, bool NOISE = false>
 __global__ void __launch_bounds__(G == 16 ? 256 : (G == 32 ? 512 : 1024)) rbm_sample_kernel(RbmSampleArgs A, int init)
 {
     extern __shared__ float2 s_tab[];
@@ -308,12 +347,18 @@ __global__ void __launch_bounds__(G == 16 ? 256 : (G == 32 ? 512 : 1024)) rbm_sa
     const int gl = threadIdx.x % G;
     const int64_t c = (int64_t)blockIdx.x * cpb + threadIdx.x / G;
     if (c >= A.n_chains) return;   // whole groups leave together; no barrier follows
-    rbm_run_chain<G, K, LDS_TAB, TRACE>(A, c, gl, s_tab, init != 0);
+    rbm_run_chain<G, K, LDS_TAB, TRACE, NOISE>(A, c, gl, s_tab, init != 0);
 }
 
 template <int G, int K>
 static void launch_rbm_sample_gk(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s)
 {
+    if (L.noise) {   // table in LDS, no trace (checked by the launcher)
+        allow_lds(rbm_sample_kernel<G, K, true, false, true>, L.lds_bytes);
+        hipLaunchKernelGGL((rbm_sample_kernel<G, K, true, false, true>), dim3(L.blocks), dim3(L.threads), L.lds_bytes, s,
+                           A, L.init);
+        return;
+    }
     if (L.lds) {
         if (L.trace) {
             allow_lds(rbm_sample_kernel<G, K, true, true>, L.lds_bytes);
