@@ -27,6 +27,11 @@ Other workloads (--workload):
            sample-space Gram matrix T of --gram-samples of them (default 4096)
            from the per-layer factors of O (P = 2,242,800 per sample, never
            held whole); --gram-chunked times the column-block path instead.
+  noise    noisy-RBM study on the 16-site TFIM chain: relative bias of
+           <sigma^x> and <Pi_even> against the noise sigma (exact by
+           enumeration and from 2^18 samples) beside the KL and average
+           bounds, and the acceptance rate against sigma for RBMs trained
+           here at h/J = 0.5, 1, 5.
 """
 from __future__ import annotations
 
@@ -54,7 +59,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20"])
+    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20", "noise"])
     ap.add_argument("--sweeps", type=int, default=0, help="heis20: measured sweeps per step (default 1)")
     ap.add_argument("--gram-samples", type=int, default=4096, help="heis20: samples in T (0 = skip)")
     ap.add_argument("--gram-chunked", action="store_true", help="heis20: T by parameter column blocks")
@@ -493,6 +498,119 @@ def run_heis20(a, torch, nqs, workloads):
     return out
 
 
+def _train_rbm(nqs, torch, N, M, h, iters, seed):
+    """SR training of an RBM on the N-site TFIM chain (J = 1, field h, periodic); returns FP64 parameters."""
+    import workloads
+    dev = torch.device("cuda:0")
+    ham = nqs.Hamiltonian("tfim", 1, N, 1.0, h, True)
+    p = workloads.rbm_params(N, M, 0.01, seed)
+    model = nqs.Model("rbm", N, (M,), p)
+    master = torch.from_numpy(p.copy()).to(dev)
+    C, S = 512, 4
+    n = C * S
+    state = torch.empty(C, N, dtype=torch.int8, device=dev)
+    samples = torch.empty(S, C, N, dtype=torch.int8, device=dev)
+    eloc = torch.empty(n, dtype=torch.float64, device=dev)
+    T = torch.empty(n, n, dtype=torch.float32, device=dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    offset = 0
+    for it in range(iters):
+        model.set_params_device(master)
+        model.prepare("f32")
+        burn = 20 if it == 0 else 2
+        cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=burn, seed=seed, step_offset=offset,
+                               init_chains=it == 0)
+        nqs.nqs_sample(model, cfg, state, samples)
+        offset += (burn + S) * N
+        flat = samples.reshape(n, N)
+        nqs.nqs_local_energy(model, ham, flat, eloc)
+        nqs.nqs_sample_gram_factored(model, flat, T)
+        nqs.nqs_sr_solve(T, eloc, 1e-2, y, tol=1e-6, max_iter=300)
+        nqs.nqs_sr_update(model, flat, y, 0.05, master)
+    model.close()
+    return master.cpu().numpy()
+
+
+def run_noise(a, torch, nqs, workloads):
+    """Noisy-RBM study (Sec. V.A): relative bias of <sigma^x> and <Pi_even> against sigma with the
+    KL (Pinsker) and average bounds (random RBMs, exact values by enumeration beside 2^18-sample
+    estimates), and the acceptance rate against sigma for RBMs trained at several h/J."""
+    import oracle
+    from oracle import exact
+    oracle.build()
+    dev = torch.device("cuda:0")
+    N, M = 16, 16
+    sigmas = [0.0, 0.01, 0.03, 0.1, 0.3, 1.0, 2.0]
+    cfgs = exact.all_configs(N)
+    even = (np.sum(cfgs > 0, axis=1) % 2 == 0).astype(np.float64)
+    ham_x = workloads.Hamiltonian("tfim", workloads.Lattice(1, N), 0.0, 1.0)   # eps = sum_i psi(x^i)/psi(x)
+    C, S = 1024, 256                                                            # 2^18 samples
+    state = torch.empty(C, N, dtype=torch.int8, device=dev)
+    samples = torch.empty(S, C, N, dtype=torch.int8, device=dev)
+    acc = torch.empty(C, dtype=torch.int64, device=dev)
+    ex = torch.empty(S * C, dtype=torch.float64, device=dev)
+    noise_seed = 20260101
+
+    def sample(model, sigma, seed):
+        cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=50, seed=seed)
+        nqs.nqs_sample_noisy(model, cfg, sigma, noise_seed, state, samples, None, acc)
+        nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(ham_x), samples, ex)
+        sx = ex.cpu().numpy() / N
+        par = (np.sum(samples.cpu().numpy().reshape(-1, N) > 0, axis=1) % 2 == 0).astype(np.float64)
+        rate = float(acc.sum().item()) / (C * (S + 50) * N)
+        return sx, par, rate
+
+    bias = []
+    t0 = time.perf_counter()
+    props = 0
+    for r in range(3):   # random initialisations
+        p = workloads.rbm_params(N, M, 0.25, 100 + r)
+        model = nqs.Model("rbm", N, (M,), p)
+        om = oracle.OracleModel("rbm", N, (M,), oracle.round_to(p, "f32"))
+        pi, _, _ = exact.enumerate_pi(om)
+        sx_x = oracle.local_energy(om, ham_x, cfgs) / N
+        ref = {"sigma_x": float(pi @ sx_x), "Pi_even": float(pi @ even)}
+        amax = {"sigma_x": float(np.max(np.abs(sx_x))), "Pi_even": 1.0}
+        sx0, par0, _ = sample(model, 0.0, 7)
+        props += C * (S + 50) * N
+        for sg in sigmas[1:]:
+            pit = exact.perturbed_pi(pi, oracle.noise_zeta(cfgs, sg, noise_seed))
+            sx1, par1, _ = sample(model, sg, 7)
+            props += C * (S + 50) * N
+            row = {"init": r, "sigma": sg, "tv_exact": exact.tv(pi, pit),
+                   "tv_bound_kl": exact.pinsker_bound(sg), "tv_bound_avg_r0": exact.avg_bound(sg)}
+            for name, x1, x0, fx in (("sigma_x", sx1, sx0, sx_x), ("Pi_even", par1, par0, even)):
+                e_ex = float(pit @ fx)
+                rel_exact = abs(e_ex - ref[name]) / abs(ref[name])
+                rel_mc = abs(x1.mean() - x0.mean()) / abs(x0.mean())
+                ci = 3.0 * np.sqrt(x1.var() / x1.size + x0.var() / x0.size) / abs(x0.mean())
+                bound = 2.0 * amax[name] * min(exact.pinsker_bound(sg), exact.avg_bound(sg)) / abs(ref[name])
+                row[name] = {"rel_err_exact": rel_exact, "rel_err_sampled": float(rel_mc), "mc_3sigma": float(ci),
+                             "rel_bound": bound}
+            bias.append(row)
+        model.close()
+    t_bias = time.perf_counter() - t0
+    accept = []
+    for h in (-0.5, -1.0, -5.0):   # h/J, stoquastic sign (positive amplitudes)
+        p = _train_rbm(nqs, torch, N, 2 * N, h, 150, 5)
+        model = nqs.Model("rbm", N, (2 * N,), p)
+        for sg in sigmas:
+            _, _, rate = sample(model, sg, 9)
+            props += C * (S + 50) * N
+            accept.append({"h_over_J": abs(h), "sigma": sg, "acceptance": rate})
+        model.close()
+    wall = time.perf_counter() - t0
+    return {
+        "metric": METRIC, "value": props / wall, "unit": "proposals/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (random RBMs; RBMs trained here by SR)",
+        "config": {"workload": "noisy_rbm_tfim1d_n16", "sites": N, "samples_per_point": C * S,
+                   "sigmas": sigmas, "parallelism": "single GPU",
+                   "note": "value = proposals/s of the whole study including training and host-side enumeration"},
+        "bias_vs_sigma": bias, "acceptance_vs_sigma": accept, "bias_study_s": round(t_bias, 2),
+    }
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -511,7 +629,8 @@ def main():
         return
     import paper_2601_20782_amd as nqs
     import workloads
-    run = {"tfim10": run_tfim10, "heis10": run_heis10, "uneven": run_uneven, "heis20": run_heis20}[a.workload]
+    run = {"tfim10": run_tfim10, "heis10": run_heis10, "uneven": run_uneven, "heis20": run_heis20,
+           "noise": run_noise}[a.workload]
     print(json.dumps(run(a, torch, nqs, workloads)))
 
 
