@@ -591,13 +591,34 @@ def run_noise(a, torch, nqs, workloads):
         model.close()
     t_bias = time.perf_counter() - t0
     accept = []
+    trained = {}
     for h in (-0.5, -1.0, -5.0):   # h/J, stoquastic sign (positive amplitudes)
         p = _train_rbm(nqs, torch, N, 2 * N, h, 150, 5)
+        trained[abs(h)] = p
         model = nqs.Model("rbm", N, (2 * N,), p)
         for sg in sigmas:
             _, _, rate = sample(model, sg, 9)
             props += C * (S + 50) * N
             accept.append({"h_over_J": abs(h), "sigma": sg, "acceptance": rate})
+        model.close()
+    # law of delta = 2 (f_lp - f_64) (Eq. eq:pert_chain) on sampled configurations: f_lp is the log|psi|
+    # the sampler reports from its reduced-precision copy, f_64 the oracle's FP64 value
+    import scipy.stats
+    lp = torch.empty(S, C, dtype=torch.float32, device=dev)
+    law = []
+    for name, p, m in (("random", workloads.rbm_params(N, M, 0.25, 100), M), ("trained_h0.5", trained[0.5], 2 * N)):
+        om64 = oracle.OracleModel("rbm", N, (m,), p)
+        model = nqs.Model("rbm", N, (m,), p)
+        for dt in ("f32", "bf16", "f16", "e4m3"):
+            cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=50, seed=3, dtype=dt)
+            nqs.nqs_sample(model, cfg, state, samples, lp)
+            x = samples[S - 1].cpu().numpy()
+            f64, _ = om64.logamp(x)
+            d = 2.0 * (lp[S - 1].cpu().numpy().astype(np.float64) - f64)
+            sw = scipy.stats.shapiro(d[:4096]).statistic if np.std(d) > 0 else float("nan")
+            law.append({"state": name, "dtype": dt, "delta_mean": float(d.mean()), "delta_std": float(d.std()),
+                        "shapiro_wilk": float(sw),
+                        "unit_roundoff": 2.0 ** -4 if dt == "e4m3" else exact.unit_roundoff(dt)})
         model.close()
     wall = time.perf_counter() - t0
     return {
@@ -607,7 +628,7 @@ def run_noise(a, torch, nqs, workloads):
         "config": {"workload": "noisy_rbm_tfim1d_n16", "sites": N, "samples_per_point": C * S,
                    "sigmas": sigmas, "parallelism": "single GPU",
                    "note": "value = proposals/s of the whole study including training and host-side enumeration"},
-        "bias_vs_sigma": bias, "acceptance_vs_sigma": accept, "bias_study_s": round(t_bias, 2),
+        "bias_vs_sigma": bias, "acceptance_vs_sigma": accept, "delta_law": law, "bias_study_s": round(t_bias, 2),
     }
 
 
