@@ -98,6 +98,20 @@ def ffnn_params(n: int, widths, seed: int, bias_std: float = 0.0) -> np.ndarray:
     return np.concatenate(out).astype(np.float64)
 
 
+def rescnn_params(F: int, R: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """Residual convolutional network (App. H), in its parameter order: conv weights
+    N(0, scale^2 2/fan_in), biases N(0, 0.1^2), layer-norm scales 1 + N(0, 0.1^2) and
+    shifts N(0, 0.1^2); the final layer norm's scale and shift N(0, (0.1/F)^2)."""
+    rng = np.random.default_rng(seed)
+    out = [rng.normal(0.0, scale * np.sqrt(2.0 / 9.0), size=9 * F), rng.normal(0.0, 0.1, size=F)]
+    for _ in range(R):
+        out += [1.0 + rng.normal(0.0, 0.1, size=F), rng.normal(0.0, 0.1, size=F),
+                rng.normal(0.0, scale * np.sqrt(2.0 / (9 * F)), size=9 * F * F), rng.normal(0.0, 0.1, size=F),
+                rng.normal(0.0, scale * np.sqrt(2.0 / (9 * F)), size=9 * F * F), rng.normal(0.0, 0.1, size=F)]
+    out += [rng.normal(0.0, 0.1 / F, size=F), rng.normal(0.0, 0.1 / F, size=F)]
+    return np.concatenate(out)
+
+
 def params_for(wl: Workload) -> np.ndarray:
     m = wl.model
     if m.arch == "rbm":
