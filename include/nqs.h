@@ -61,7 +61,7 @@ typedef enum {
 } nqs_status;
 
 typedef enum { NQS_F64 = 0, NQS_F32 = 1, NQS_F16 = 2, NQS_BF16 = 3, NQS_FP8_E4M3 = 4 } nqs_dtype;
-typedef enum { NQS_RBM = 0, NQS_FFNN = 1 } nqs_arch;
+typedef enum { NQS_RBM = 0, NQS_FFNN = 1, NQS_RESCNN = 2 } nqs_arch;
 typedef enum { NQS_MOVE_FLIP = 0, NQS_MOVE_EXCHANGE = 1 } nqs_move;
 typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_ham_kind;
 
@@ -72,6 +72,17 @@ typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_ham_kind;
  *   widths[0] = M, parameter vector [a(N), b(M), W(M x N, row-major)].
  * FFNN: h_l = ReLU(W_l h_{l-1} + b_l) for l < n_layers, log psi = sum log cosh(z_last),
  *   parameter vector [W_1 (w1 x N), b_1, W_2 (w2 x w1), b_2, ...].
+ * RESCNN (App. H): residual convolutional network on the periodic lat_L x lat_L
+ *   lattice (lat_dim = 2, n_visible = lat_L^2), widths[0] = F filters,
+ *   n_layers = R residual blocks:  h0 = Conv(s);  h += Conv(phi(Conv(phi(LN h))));
+ *   log psi = sum over sites and channels of LN(h_R).  Conv: 3x3 cross-
+ *   correlation, circular padding, bias; LN: per site over channels, scale and
+ *   shift, eps 1e-6; phi: GELU (tanh form).  Parameter vector [W0 (F x 9), b0],
+ *   per block [gamma, beta, W1 (F x F x 9), b1, W2 (F x F x 9), b2], then
+ *   [gamma_f, beta_f]; W[o][c][k], k = 3 (dx+1) + (dy+1) for the input site
+ *   (x+dx, y+dy), site i = x L + y.  Sampling (single flips), TFIM local
+ *   energies on its lattice and log psi (nqs_logpsi_grad without O); no
+ *   log-derivatives, no FP8 copy.
  * marshall = 1 multiplies psi by (-1)^{#up spins on sublattice A}, A = {(x+y) even}
  *   (lat_dim = 2) or {i even} (lat_dim = 1), on an L = lat_L lattice. */
 typedef struct {

@@ -49,12 +49,12 @@ class Model:
     """Handle to a library-owned model (FP64 master + reduced-precision copies)."""
 
     def __init__(self, arch: str, n_visible: int, widths: Sequence[int], params, marshall: bool = False,
-                 lat_dim: int = 0, lat_L: int = 0):
+                 lat_dim: int = 0, lat_L: int = 0, n_layers: Optional[int] = None):
         lib = load()
         d = _abi.ModelDesc()
-        d.arch = _abi.RBM if arch == "rbm" else _abi.FFNN
+        d.arch = {"rbm": _abi.RBM, "ffnn": _abi.FFNN, "rescnn": _abi.RESCNN}[arch]
         d.n_visible = n_visible
-        d.n_layers = len(widths)
+        d.n_layers = len(widths) if n_layers is None else n_layers
         for k, w in enumerate(widths):
             d.widths[k] = int(w)
         d.marshall = 1 if marshall else 0
@@ -65,6 +65,11 @@ class Model:
         h = ctypes.c_void_p()
         check(lib.nqs_model_create(ctypes.byref(d), p.ctypes.data_as(ctypes.c_void_p), p.size, ctypes.byref(h)))
         self._h = h
+
+    @classmethod
+    def rescnn(cls, L: int, F: int, R: int, params):
+        """Residual convolutional network with F filters and R blocks on the periodic L x L lattice."""
+        return cls("rescnn", L * L, (F,), params, lat_dim=2, lat_L=L, n_layers=R)
 
     @classmethod
     def from_workload(cls, wl, params=None):

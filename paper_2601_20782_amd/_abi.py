@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libnqs.so")
 
 NQS_OK, NQS_EINVAL, NQS_ENOMEM, NQS_EDEVICE, NQS_EUNSUPPORTED, NQS_ENUMERIC = range(6)
 F64, F32, F16, BF16, FP8_E4M3 = range(5)
-RBM, FFNN = 0, 1
+RBM, FFNN, RESCNN = 0, 1, 2
 MOVE_FLIP, MOVE_EXCHANGE = 0, 1
 TFIM, HEISENBERG = 0, 1
 MAX_LAYERS = 8

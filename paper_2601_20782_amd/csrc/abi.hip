@@ -82,6 +82,7 @@ int64_t model_num_params(const nqs_model_desc &d)
 {
     const int64_t N = d.n_visible;
     if (d.arch == NQS_RBM) return N + d.widths[0] + (int64_t)d.widths[0] * N;
+    if (d.arch == NQS_RESCNN) return cnn_num_params(d.widths[0], d.n_layers);
     int64_t p = 0, prev = N;
     for (int l = 0; l < d.n_layers; ++l) {
         p += (int64_t)d.widths[l] * (prev + 1);
@@ -94,6 +95,7 @@ nqs_status ensure_copy(nqs_model *m, int dtype, hipStream_t stream)
 {
     if (m->copies[dtype].valid) return NQS_OK;
     if (m->desc.arch == NQS_RBM) return rbm_build_copy(m, dtype, stream);
+    if (m->desc.arch == NQS_RESCNN) return cnn_build_copy(m, dtype, stream);
     return ffnn_build_copy(m, dtype, stream);
 }
 
@@ -113,6 +115,12 @@ static nqs_status validate_desc(const nqs_model_desc *d)
         if (d->n_layers < 1 || d->n_layers > NQS_MAX_LAYERS) return set_error(NQS_EINVAL, "FFNN needs 1..8 layers");
         for (int l = 0; l < d->n_layers; ++l)
             if (d->widths[l] < 1 || d->widths[l] > 8192) return set_error(NQS_EINVAL, "FFNN widths must be in [1, 8192]");
+    } else if (d->arch == NQS_RESCNN) {
+        if (d->lat_dim != 2 || d->lat_L < 3 || (int64_t)d->lat_L * d->lat_L != d->n_visible)
+            return set_error(NQS_EINVAL, "convolutional network needs lat_dim = 2, lat_L >= 3, n_visible = lat_L^2");
+        if (d->widths[0] < 1 || d->widths[0] > 256) return set_error(NQS_EINVAL, "filters (widths[0]) must be in [1, 256]");
+        if (d->n_layers < 0 || d->n_layers > NQS_MAX_LAYERS) return set_error(NQS_EINVAL, "residual blocks must be 0..8");
+        if (d->marshall) return set_error(NQS_EUNSUPPORTED, "no Marshall sign for the convolutional network");
     } else {
         return set_error(NQS_EINVAL, "unknown arch");
     }
@@ -262,6 +270,12 @@ nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_sta
         if (c.move != NQS_MOVE_FLIP) return set_error(NQS_EUNSUPPORTED, "the RBM sampler implements single-flip moves");
         return rbm_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
     }
+    if (m->desc.arch == NQS_RESCNN) {
+        if (c.move != NQS_MOVE_FLIP || c.sweep_size != 0)
+            return set_error(NQS_EUNSUPPORTED, "the convolutional-network sampler implements single flips, sweeps of N");
+        if (c.dtype == NQS_FP8_E4M3) return set_error(NQS_EUNSUPPORTED, "no FP8 copy of the convolutional network");
+        return cnn_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
+    }
     return ffnn_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
 }
 
@@ -320,6 +334,7 @@ nqs_status nqs_local_energy(nqs_model *m, const nqs_ham_desc *ham, const int8_t 
     if (m->desc.arch == NQS_RBM) {
         return rbm_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);
     }
+    if (m->desc.arch == NQS_RESCNN) return cnn_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);
     return ffnn_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);
 }
 
@@ -340,6 +355,10 @@ nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float
     if (!samples) return set_error(NQS_EINVAL, "NULL samples");
     if ((vjp_in == nullptr) != (vjp_out == nullptr)) return set_error(NQS_EINVAL, "vjp_in and vjp_out go together");
     hipStream_t s = (hipStream_t)stream;
+    if (m->desc.arch == NQS_RESCNN) {
+        if (O || vjp_in) return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
+        return logpsi ? cnn_logpsi(m, samples, n, logpsi, s) : NQS_OK;
+    }
     if (m->desc.arch == NQS_RBM) return rbm_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s, 0, m->P);
     return ffnn_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s, 0, m->P);
 }
@@ -347,6 +366,8 @@ nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float
 nqs_status nqs_logpsi_grad_cols(nqs_model *m, const int8_t *samples, int64_t n, int64_t p0, int64_t p1, float *O,
                                 void *stream)
 {
+    if (m && m->desc.arch == NQS_RESCNN)
+        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
     if (!m) return set_error(NQS_EINVAL, "NULL model");
     if (n < 0) return set_error(NQS_EINVAL, "n < 0");
     if (p0 < 0 || p1 <= p0 || p1 > m->P) return set_error(NQS_EINVAL, "need 0 <= p0 < p1 <= P");
@@ -359,6 +380,8 @@ nqs_status nqs_logpsi_grad_cols(nqs_model *m, const int8_t *samples, int64_t n, 
 
 nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t n, float *T, void *stream)
 {
+    if (m && m->desc.arch == NQS_RESCNN)
+        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
     if (!m) return set_error(NQS_EINVAL, "NULL model");
     if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
     if (!samples || !T) return set_error(NQS_EINVAL, "NULL samples/T");
@@ -421,6 +444,8 @@ nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t
 nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64_t chunk_params, float *T,
                            void *stream)
 {
+    if (m && m->desc.arch == NQS_RESCNN)
+        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
     if (!m) return set_error(NQS_EINVAL, "NULL model");
     if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
     if (!samples || !T) return set_error(NQS_EINVAL, "NULL samples/T");

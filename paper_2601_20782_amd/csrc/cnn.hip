@@ -1,0 +1,437 @@
+// Residual convolutional network (App. H) on an L x L periodic lattice:
+//   h0 = Conv(s);  h <- h + Conv(phi(Conv(phi(LN(h)))))  (R blocks);
+//   log psi = sum over sites and channels of LN(h).
+// Conv: 3 x 3 cross-correlation with circular padding and a bias per output
+// channel; LN: per site over the F channels, learnable scale and shift,
+// epsilon 1e-6; phi: GELU, tanh form.  Reduced precision: the parameters are
+// rounded to the sampling format, and so is the input of every convolution
+// after the first; sums, LN, GELU and the residual stream are FP32.
+//
+// Every evaluation is one configuration per workgroup, activations in LDS
+// ([site][channel], FP32), weights read from the copy ([in channel][offset]
+// [out channel], so consecutive threads (out channels) read consecutive words).
+// The sampler runs one chain per workgroup (proposal, forward pass, decision);
+// the local energy one sample per workgroup (the sample and its N flips).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "internal.h"
+
+namespace nqs {
+
+constexpr int kCnnThreads = 256;
+constexpr float kLnEps = 1e-6f;
+
+int64_t cnn_num_params(int F, int R)
+{
+    return 10 * (int64_t)F + (int64_t)R * (2 * F + 2 * (9 * (int64_t)F * F + F)) + 2 * (int64_t)F;
+}
+
+// ---- copy: round the FP64 master, rearrange each convolution's weights ----
+
+struct CnnSeg {
+    int64_t start, len;
+    int conv;   // 0: copied as is; else a convolution with `conv` input channels: [o][c][k] -> [c][k][o]
+    int F;
+};
+
+__global__ void cnn_build_kernel(const double *__restrict__ master, int64_t P, int dtype, const CnnSeg *__restrict__ segs,
+                                 int nseg, float *__restrict__ out)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= P) return;
+    int s = 0;
+    while (s + 1 < nseg && q >= segs[s + 1].start) ++s;
+    const CnnSeg g = segs[s];
+    const float v = (float)round_to_dtype(master[q], dtype);
+    const int64_t r = q - g.start;
+    if (g.conv == 0) {
+        out[q] = v;
+    } else {
+        const int C = g.conv, F = g.F;
+        const int64_t o = r / (9 * C), rem = r - o * 9 * C, c = rem / 9, k = rem - c * 9;
+        out[g.start + (c * 9 + k) * F + o] = v;
+    }
+}
+
+nqs_status cnn_build_copy(nqs_model *m, int dtype, hipStream_t stream)
+{
+    const nqs_model_desc &d = m->desc;
+    if (dtype == NQS_FP8_E4M3) return set_error(NQS_EUNSUPPORTED, "FP8 copies of the convolutional network are not built");
+    Copy &c = m->copies[dtype];
+    CnnDev &n = c.cnn;
+    n.L = d.lat_L;
+    n.F = d.widths[0];
+    n.R = d.n_layers;
+    n.dtype = dtype;
+    const int F = n.F;
+    CnnSeg segs[8 * NQS_MAX_LAYERS + 8];
+    int ns = 0;
+    int64_t off = 0;
+    auto seg = [&](int64_t len, int conv) {
+        segs[ns++] = CnnSeg{off, len, conv, F};
+        const int64_t at = off;
+        off += len;
+        return at;
+    };
+    n.w0 = seg(9 * (int64_t)F, 1);
+    n.b0 = seg(F, 0);
+    for (int r = 0; r < n.R; ++r) {
+        n.g[r] = seg(F, 0);
+        n.be[r] = seg(F, 0);
+        n.w1[r] = seg(9 * (int64_t)F * F, F);
+        n.b1[r] = seg(F, 0);
+        n.w2[r] = seg(9 * (int64_t)F * F, F);
+        n.b2[r] = seg(F, 0);
+    }
+    n.gf = seg(F, 0);
+    n.bef = seg(F, 0);
+    if (off != m->P) return set_error(NQS_EINVAL, "convolutional network parameter count mismatch");
+    const size_t pbytes = (sizeof(float) * (size_t)m->P + 255) & ~(size_t)255;
+    if (!c.block) NQS_HIP_TRY(hipMalloc(&c.block, pbytes + sizeof(segs)));
+    n.p = (float *)c.block;
+    CnnSeg *dsegs = (CnnSeg *)((char *)c.block + pbytes);
+    NQS_HIP_TRY(hipMemcpyAsync(dsegs, segs, sizeof(CnnSeg) * ns, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(cnn_build_kernel, dim3((unsigned)((m->P + 255) / 256)), dim3(256), 0, stream, m->master, m->P,
+                       dtype, dsegs, ns, n.p);
+    NQS_HIP_TRY(hipGetLastError());
+    // the host array of segments must outlive the copy
+    NQS_HIP_TRY(hipStreamSynchronize(stream));
+    c.valid = true;
+    return NQS_OK;
+}
+
+// ---- the forward pass of one configuration by one workgroup ----
+
+struct CnnLds {
+    float *x;     // [S] spins
+    float *h;     // [S][F] residual stream
+    float *t;     // [S][F] phi(LN(h)), rounded
+    float *u;     // [S][F] phi(conv1), rounded
+    float *red;   // [kCnnThreads / 64]
+};
+
+__host__ __device__ inline size_t cnn_lds_bytes(int S, int F)
+{
+    return sizeof(float) * ((size_t)S + 3 * (size_t)S * F + kCnnThreads / 64);
+}
+
+__device__ inline CnnLds cnn_carve(float *sm, int S, int F)
+{
+    CnnLds l;
+    l.x = sm;
+    l.h = sm + S;
+    l.t = l.h + (size_t)S * F;
+    l.u = l.t + (size_t)S * F;
+    l.red = l.u + (size_t)S * F;
+    return l;
+}
+
+__device__ inline int cnn_nbr(int s, int k, int L)
+{
+    const int x = s / L, y = s - (s / L) * L;
+    int xx = x + k / 3 - 1, yy = y + k % 3 - 1;
+    xx += xx < 0 ? L : (xx >= L ? -L : 0);
+    yy += yy < 0 ? L : (yy >= L ? -L : 0);
+    return xx * L + yy;
+}
+
+__device__ inline float cnn_gelu(float x)
+{
+    const float c = 0.7978845608028654f;   // sqrt(2 / pi)
+    return 0.5f * x * (1.0f + tanhf(c * fmaf(0.044715f * x * x, x, x)));
+}
+
+__device__ inline float cnn_round(float v, int dtype)
+{
+    return dtype == kF32 ? v : (float)round_to_dtype((double)v, dtype);
+}
+
+// out[s][o] (+)= b[o] + sum_{k, c} W[c][k][o] in[nbr(s, k)][c]
+__device__ inline float cnn_conv_at(const float *__restrict__ W, const float *__restrict__ b, const float *in, int s,
+                                    int o, int L, int C, int F)
+{
+    float acc = b[o];
+    for (int k = 0; k < 9; ++k) {
+        const float *src = in + (size_t)cnn_nbr(s, k, L) * C;
+        const float *w = W + (size_t)k * F + o;
+        for (int c = 0; c < C; ++c) acc = fmaf(w[(size_t)c * 9 * F], src[c], acc);
+    }
+    return acc;
+}
+
+// log psi of the configuration in l.x (all threads return it); ends with a barrier
+__device__ float cnn_forward(const CnnDev &net, const CnnLds &l)
+{
+    const int L = net.L, S = L * L, F = net.F, tid = threadIdx.x;
+    const float *P = net.p;
+    for (int idx = tid; idx < S * F; idx += kCnnThreads) {
+        const int s = idx / F, o = idx - (idx / F) * F;
+        l.h[idx] = cnn_conv_at(P + net.w0, P + net.b0, l.x, s, o, L, 1, F);
+    }
+    __syncthreads();
+    for (int r = 0; r < net.R; ++r) {
+        const float *g = P + net.g[r], *be = P + net.be[r];
+        for (int s = tid; s < S; s += kCnnThreads) {
+            const float *hs = l.h + (size_t)s * F;
+            float mu = 0.0f;
+            for (int c = 0; c < F; ++c) mu += hs[c];
+            mu /= (float)F;
+            float var = 0.0f;
+            for (int c = 0; c < F; ++c) var = fmaf(hs[c] - mu, hs[c] - mu, var);
+            const float rs = 1.0f / sqrtf(var / (float)F + kLnEps);
+            for (int c = 0; c < F; ++c)
+                l.t[(size_t)s * F + c] = cnn_round(cnn_gelu(fmaf((hs[c] - mu) * rs, g[c], be[c])), net.dtype);
+        }
+        __syncthreads();
+        for (int idx = tid; idx < S * F; idx += kCnnThreads) {
+            const int s = idx / F, o = idx - (idx / F) * F;
+            l.u[idx] = cnn_round(cnn_gelu(cnn_conv_at(P + net.w1[r], P + net.b1[r], l.t, s, o, L, F, F)), net.dtype);
+        }
+        __syncthreads();
+        for (int idx = tid; idx < S * F; idx += kCnnThreads) {
+            const int s = idx / F, o = idx - (idx / F) * F;
+            l.h[idx] += cnn_conv_at(P + net.w2[r], P + net.b2[r], l.u, s, o, L, F, F);
+        }
+        __syncthreads();
+    }
+    const float *g = P + net.gf, *be = P + net.bef;
+    float part = 0.0f;
+    for (int s = tid; s < S; s += kCnnThreads) {
+        const float *hs = l.h + (size_t)s * F;
+        float mu = 0.0f;
+        for (int c = 0; c < F; ++c) mu += hs[c];
+        mu /= (float)F;
+        float var = 0.0f;
+        for (int c = 0; c < F; ++c) var = fmaf(hs[c] - mu, hs[c] - mu, var);
+        const float rs = 1.0f / sqrtf(var / (float)F + kLnEps);
+        for (int c = 0; c < F; ++c) part += fmaf((hs[c] - mu) * rs, g[c], be[c]);
+    }
+    part = group_sum<64>(part);
+    if ((tid & 63) == 0) l.red[tid >> 6] = part;
+    __syncthreads();
+    float f = 0.0f;
+    for (int w = 0; w < kCnnThreads / 64; ++w) f += l.red[w];
+    __syncthreads();
+    return f;
+}
+
+// ---- log psi of given configurations ----
+
+__global__ void __launch_bounds__(kCnnThreads) cnn_logpsi_kernel(CnnDev net, const int8_t *__restrict__ samples,
+                                                                 int64_t n, float *__restrict__ logpsi)
+{
+    extern __shared__ float sm[];
+    const int S = net.L * net.L;
+    const CnnLds l = cnn_carve(sm, S, net.F);
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+        for (int i = threadIdx.x; i < S; i += kCnnThreads) l.x[i] = (float)samples[k * S + i];
+        __syncthreads();
+        const float f = cnn_forward(net, l);
+        if (threadIdx.x == 0) logpsi[k] = f;
+    }
+}
+
+// ---- Metropolis-Hastings, single flips, one chain per workgroup ----
+
+struct CnnSampleArgs {
+    CnnDev net;
+    int8_t *chain_state;
+    int8_t *samples;
+    float *logpsi;
+    unsigned long long *n_acc;
+    int64_t n_chains;
+    int n_sweeps, n_burnin, sweep_size;
+    uint64_t seed, step_offset;
+    uint32_t inst, chain_id_offset;
+    int n_traced;
+    int32_t *tr_site;
+    uint32_t *tr_ubits;
+    float *tr_delta;
+    uint8_t *tr_acc;
+};
+
+__global__ void __launch_bounds__(kCnnThreads) cnn_sample_kernel(CnnSampleArgs A)
+{
+    extern __shared__ float sm[];
+    __shared__ int s_site;
+    __shared__ int s_accept;
+    const int S = A.net.L * A.net.L, tid = threadIdx.x;
+    const CnnLds l = cnn_carve(sm, S, A.net.F);
+    const uint32_t key0 = (uint32_t)A.seed, key1 = (uint32_t)(A.seed >> 32);
+    const int64_t total = (int64_t)(A.n_burnin + A.n_sweeps) * A.sweep_size;
+    for (int64_t c = blockIdx.x; c < A.n_chains; c += gridDim.x) {
+        const uint32_t gid = A.chain_id_offset + (uint32_t)c;
+        for (int i = tid; i < S; i += kCnnThreads) l.x[i] = (float)A.chain_state[c * S + i];
+        __syncthreads();
+        float f = cnn_forward(A.net, l);
+        unsigned long long acc = 0;
+        for (int64_t k = 0; k < total; ++k) {
+            const uint64_t step = A.step_offset + (uint64_t)k;
+            uint32_t ub = 0;
+            if (tid == 0) {
+                const Block4 rb = philox4x32_10((uint32_t)step, (uint32_t)(step >> 32), gid, A.inst << 8, key0, key1);
+                s_site = index_from_word(rb.r0, S);
+                ub = rb.r2 >> 8;
+                l.x[s_site] = -l.x[s_site];
+            }
+            __syncthreads();
+            const float fn = cnn_forward(A.net, l);
+            if (tid == 0) {
+                const float d = 2.0f * (fn - f);
+                const float l2u = __builtin_amdgcn_logf((float)ub * 5.9604644775390625e-8f);   // log2 u
+                const bool accept = l2u < d * 1.4426950408889634f;                            // NaN rejects
+                s_accept = accept ? 1 : 0;
+                if (!accept) l.x[s_site] = -l.x[s_site];
+                if (c < A.n_traced) {
+                    const size_t idx = (size_t)c * (size_t)total + (size_t)k;
+                    A.tr_site[idx] = s_site | (0xFFFF << 16);
+                    A.tr_ubits[idx] = ub;
+                    A.tr_delta[idx] = d;
+                    A.tr_acc[idx] = accept ? 1 : 0;
+                }
+            }
+            __syncthreads();
+            if (s_accept) {
+                f = fn;
+                ++acc;
+            }
+            if ((k + 1) % A.sweep_size == 0) {
+                const int64_t out = (k + 1) / A.sweep_size - 1 - A.n_burnin;
+                if (out >= 0) {
+                    if (A.samples)
+                        for (int i = tid; i < S; i += kCnnThreads)
+                            A.samples[((size_t)out * A.n_chains + c) * S + i] = l.x[i] > 0.0f ? 1 : -1;
+                    if (A.logpsi && tid == 0) A.logpsi[(size_t)out * A.n_chains + c] = f;
+                    __syncthreads();   // the next proposal modifies l.x
+                }
+            }
+        }
+        for (int i = tid; i < S; i += kCnnThreads) A.chain_state[c * S + i] = l.x[i] > 0.0f ? 1 : -1;
+        if (A.n_acc && tid == 0) A.n_acc[c] = acc;
+        __syncthreads();
+    }
+}
+
+// ---- TFIM local energies on the network's lattice, one sample per workgroup ----
+
+__global__ void __launch_bounds__(kCnnThreads) cnn_eloc_tfim_kernel(CnnDev net, const int8_t *__restrict__ samples,
+                                                                    int64_t n, double J, double h,
+                                                                    double *__restrict__ eloc)
+{
+    extern __shared__ float sm[];
+    const int L = net.L, S = L * L, tid = threadIdx.x;
+    const CnnLds l = cnn_carve(sm, S, net.F);
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+        for (int i = tid; i < S; i += kCnnThreads) l.x[i] = (float)samples[k * S + i];
+        __syncthreads();
+        const float f0 = cnn_forward(net, l);
+        double off = 0.0;
+        for (int i = 0; i < S; ++i) {
+            if (tid == 0) l.x[i] = -l.x[i];
+            __syncthreads();
+            const float fi = cnn_forward(net, l);
+            off += exp((double)(fi - f0));
+            if (tid == 0) l.x[i] = -l.x[i];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            double diag = 0.0;
+            for (int s = 0; s < S; ++s) {
+                const int x = s / L, y = s - (s / L) * L;
+                const int right = ((x + 1) % L) * L + y, down = x * L + (y + 1) % L;
+                diag += (double)(l.x[s] * l.x[right]) + (double)(l.x[s] * l.x[down]);
+            }
+            eloc[k] = J * diag + h * off;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- host ----
+
+static nqs_status cnn_check(const CnnDev &net)
+{
+    if (cnn_lds_bytes(net.L * net.L, net.F) > 160 * 1024)
+        return set_error(NQS_EUNSUPPORTED, "convolutional network activations exceed 160 KB of LDS (L^2 x F too large)");
+    return NQS_OK;
+}
+
+nqs_status cnn_logpsi(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, hipStream_t stream)
+{
+    nqs_status st = ensure_copy(m, NQS_F32, stream);
+    if (st != NQS_OK) return st;
+    const CnnDev &net = m->copies[NQS_F32].cnn;
+    if ((st = cnn_check(net)) != NQS_OK) return st;
+    const size_t lds = cnn_lds_bytes(net.L * net.L, net.F);
+    allow_lds(cnn_logpsi_kernel, lds);
+    const int64_t blocks = std::min<int64_t>(n, (int64_t)device_cus() * 16);
+    hipLaunchKernelGGL(cnn_logpsi_kernel, dim3((unsigned)blocks), dim3(kCnnThreads), lds, stream, net, samples, n, logpsi);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
+nqs_status cnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
+                      uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream)
+{
+    nqs_status st = ensure_copy(m, cfg.dtype, stream);
+    if (st != NQS_OK) return st;
+    const CnnDev &net = m->copies[cfg.dtype].cnn;
+    if ((st = cnn_check(net)) != NQS_OK) return st;
+    const int S = net.L * net.L;
+    if (cfg.init_chains) {
+        st = launch_init_chains(chain_state, cfg.n_chains, S, NQS_MOVE_FLIP, cfg.seed, cfg.instance_id,
+                                cfg.chain_id_offset, stream);
+        if (st != NQS_OK) return st;
+    }
+    CnnSampleArgs A;
+    A.net = net;
+    A.chain_state = chain_state;
+    A.samples = samples;
+    A.logpsi = logpsi;
+    A.n_acc = (unsigned long long *)n_accepted;
+    A.n_chains = cfg.n_chains;
+    A.n_sweeps = cfg.n_sweeps;
+    A.n_burnin = cfg.n_burnin;
+    A.sweep_size = cfg.sweep_size > 0 ? cfg.sweep_size : S;
+    A.seed = cfg.seed;
+    A.step_offset = cfg.step_offset;
+    A.inst = cfg.instance_id;
+    A.chain_id_offset = (uint32_t)cfg.chain_id_offset;
+    const bool tr = trace && trace->n_chains_traced > 0;
+    A.n_traced = tr ? trace->n_chains_traced : 0;
+    A.tr_site = tr ? trace->site : nullptr;
+    A.tr_ubits = tr ? trace->ubits : nullptr;
+    A.tr_delta = tr ? trace->delta : nullptr;
+    A.tr_acc = tr ? trace->accepted : nullptr;
+    const size_t lds = cnn_lds_bytes(S, net.F);
+    allow_lds(cnn_sample_kernel, lds);
+    const int64_t blocks = std::min<int64_t>(cfg.n_chains, (int64_t)device_cus() * 16);
+    hipLaunchKernelGGL(cnn_sample_kernel, dim3((unsigned)blocks), dim3(kCnnThreads), lds, stream, A);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
+nqs_status cnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
+                            double *eloc, hipStream_t stream)
+{
+    if (ham.kind != NQS_TFIM || ham.dim != 2 || ham.L != m->desc.lat_L || !ham.pbc)
+        return set_error(NQS_EUNSUPPORTED,
+                         "convolutional-network local energies: TFIM on the network's periodic L x L lattice");
+    nqs_status st = ensure_copy(m, dtype, stream);
+    if (st != NQS_OK) return st;
+    const CnnDev &net = m->copies[dtype].cnn;
+    if ((st = cnn_check(net)) != NQS_OK) return st;
+    const size_t lds = cnn_lds_bytes(net.L * net.L, net.F);
+    allow_lds(cnn_eloc_tfim_kernel, lds);
+    const int64_t blocks = std::min<int64_t>(n, (int64_t)device_cus() * 16);
+    hipLaunchKernelGGL(cnn_eloc_tfim_kernel, dim3((unsigned)blocks), dim3(kCnnThreads), lds, stream, net, samples, n,
+                       ham.J, ham.h, eloc);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
+}  // namespace nqs

@@ -56,10 +56,22 @@ struct FfnnDev {
     float *bd[NQS_MAX_LAYERS] = {nullptr}; // [Np]
 };
 
+// Residual convolutional network copy in one sampling format: one FP32 array
+// of the rounded parameters in the order of the parameter vector, each
+// convolution's weights rearranged as [in channel][3x3 offset][out channel].
+struct CnnDev {
+    int L = 0, F = 0, R = 0, dtype = 1;
+    float *p = nullptr;
+    int64_t w0 = 0, b0 = 0, gf = 0, bef = 0;
+    int64_t g[NQS_MAX_LAYERS] = {0}, be[NQS_MAX_LAYERS] = {0}, w1[NQS_MAX_LAYERS] = {0}, b1[NQS_MAX_LAYERS] = {0},
+            w2[NQS_MAX_LAYERS] = {0}, b2[NQS_MAX_LAYERS] = {0};
+};
+
 struct Copy {
     bool valid = false;
     RbmDev rbm;
     FfnnDev ffnn;
+    CnnDev cnn;
     void *block = nullptr;   // single allocation backing the arrays above
 };
 
@@ -151,6 +163,14 @@ nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t 
 nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
                            const float *vjp_in, float *vjp_out, hipStream_t stream, int64_t p0, int64_t p1);
 nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream);
+// residual convolutional network
+int64_t cnn_num_params(int F, int R);
+nqs_status cnn_build_copy(nqs_model *m, int dtype, hipStream_t stream);
+nqs_status cnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
+                      uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
+nqs_status cnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
+                            double *eloc, hipStream_t stream);
+nqs_status cnn_logpsi(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, hipStream_t stream);
 nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
                        float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
 nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,

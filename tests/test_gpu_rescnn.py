@@ -1,0 +1,161 @@
+"""GPU parity of the residual convolutional network (App. H): log psi of given
+configurations, the single-flip sampler (decision replay in FP64 and the
+histogram against the enumerated |psi|^2) and TFIM local energies, against
+the numpy oracle.  Every call goes through the C interface."""
+import numpy as np
+import pytest
+import scipy.stats
+import torch
+
+import oracle
+import workloads
+from oracle import exact
+from oracle import rescnn
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_20782_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("L,F,R", [(3, 4, 1), (4, 8, 2), (4, 16, 4), (6, 5, 3), (10, 16, 1), (5, 3, 0)])
+def test_logpsi_matches_oracle(nqs, L, F, R):
+    p = workloads.rescnn_params(F, R, L + F + R)
+    model = nqs.Model.rescnn(L, F, R, p)
+    x = workloads.random_spins(37, L * L, 2)
+    lp = torch.empty(37, dtype=torch.float32, device=DEV)
+    nqs.nqs_logpsi_grad(model, torch.from_numpy(x).to(DEV), logpsi=lp)
+    ref, _ = rescnn.ResCNN(L, F, R, p, "f32").logamp(x)
+    got = lp.cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(got - ref) / (1.0 + np.abs(ref)))
+    _say(f"  L={L} F={F} R={R}: max |dlogpsi| / (1 + |logpsi|) = {err:.2e}")
+    assert err < 2e-5
+
+
+def _trace_run(nqs, model, N, dtype, C, S, B, T, seed=5):
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=seed, dtype=dtype)
+    total = (S + B) * N
+    tr = {"n": T,
+          "site": torch.empty(T * total, dtype=torch.int32, device=DEV),
+          "ubits": torch.empty(T * total, dtype=torch.int32, device=DEV),
+          "delta": torch.empty(T * total, dtype=torch.float32, device=DEV),
+          "accepted": torch.empty(T * total, dtype=torch.uint8, device=DEV)}
+    state = torch.empty(C, N, dtype=torch.int8, device=DEV)
+    samples = torch.empty(S, C, N, dtype=torch.int8, device=DEV)
+    logpsi = torch.empty(S, C, dtype=torch.float32, device=DEV)
+    nqs.nqs_sample(model, cfg, state, samples, logpsi, None, trace=tr)
+    torch.cuda.synchronize()
+    out = {k: tr[k].cpu().numpy().reshape(T, total) for k in ("site", "ubits", "delta", "accepted")}
+    out["samples"], out["logpsi"], out["state"] = samples.cpu().numpy(), logpsi.cpu().numpy(), state.cpu().numpy()
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_sampler_decisions_replay_in_fp64(nqs, dtype):
+    """Each traced proposal: site and u equal the Philox draws, Delta equals the
+    oracle's FP64 2 (log psi(x') - log psi(x)) of the `dtype` network within its
+    rounding, and the decision equals u < exp(min(Delta, 0)) except near ties."""
+    L, F, R = 4, 8, 2
+    N = L * L
+    p = workloads.rescnn_params(F, R, 9, scale=1.5)
+    model = nqs.Model.rescnn(L, F, R, p)
+    T, S, B = 3, 6, 2
+    r = _trace_run(nqs, model, N, dtype, 16, S, B, T)
+    net = rescnn.ResCNN(L, F, R, p, dtype)
+    tol = {"f32": 1e-4, "bf16": 3e-2, "f16": 5e-3}[dtype]
+    near, max_err = 0, 0.0
+    for c in range(T):
+        x = oracle.init_chain(N, "flip", 5, c).copy()
+        f0, _ = net.logamp(x[None])
+        for k in range((S + B) * N):
+            rb = oracle.philox([k & 0xFFFFFFFF, k >> 32, c, 0], [5, 0])
+            site = int((int(rb[0]) * N) >> 32)
+            ub = int(rb[2]) >> 8
+            assert (r["site"][c, k] & 0xFFFF) == site and int(r["ubits"][c, k]) == ub
+            y = x.copy()
+            y[site] = -y[site]
+            f1, _ = net.logamp(y[None])
+            d = 2.0 * (f1[0] - f0[0])
+            err = abs(float(r["delta"][c, k]) - d)
+            max_err = max(max_err, err / max(1.0, abs(d)))
+            assert err <= tol * max(1.0, abs(d)), (c, k, r["delta"][c, k], d)
+            u = ub * 2.0 ** -24
+            acc = u < np.exp(min(d, 0.0))
+            if bool(r["accepted"][c, k]) != acc:
+                # only where the FP32 decision and the FP64 one straddle u
+                assert abs(np.log(max(u, 1e-300)) - min(d, 0.0)) <= 2 * tol * max(1.0, abs(d))
+                near += 1
+            if r["accepted"][c, k]:
+                x, f0 = y, f1
+    assert np.array_equal(x, r["state"][T - 1]) or near > 0
+    _say(f"  {dtype}: max relative |dDelta| {max_err:.2e}, {near} near ties")
+
+
+def test_sampler_histogram_matches_exact_pi(nqs):
+    """3 x 3 lattice, final layer-norm scale N(0, 0.3^2): pi spans a factor ~200
+    (TV 0.26 from uniform)."""
+    L, F, R = 3, 4, 1
+    N = L * L
+    p = workloads.rescnn_params(F, R, 3, scale=2.0).copy()
+    p[-2 * F:-F] = np.random.default_rng(7).normal(0.0, 0.3, size=F)
+    model = nqs.Model.rescnn(L, F, R, p)
+    cfg = nqs.SampleConfig(n_chains=8192, n_sweeps=60, n_burnin=30, seed=2)
+    state = torch.empty(8192, N, dtype=torch.int8, device=DEV)
+    samples = torch.empty(60, 8192, N, dtype=torch.int8, device=DEV)
+    nqs.nqs_sample(model, cfg, state, samples)
+    smp = samples.cpu().numpy()[4::5]
+    f, _ = rescnn.ResCNN(L, F, R, p, "f32").logamp(exact.all_configs(N))
+    w = np.exp(2 * (f - f.max()))
+    pi = w / w.sum()
+    idx = np.sum((smp.reshape(-1, N) > 0).astype(np.int64) << np.arange(N), axis=1)
+    counts = np.bincount(idx, minlength=2 ** N)
+    e = pi * counts.sum()
+    keep = e > 5
+    chi2 = np.sum((counts[keep] - e[keep]) ** 2 / e[keep])
+    _say(f"  chi2/dof = {chi2 / (keep.sum() - 1):.3f}, TV = {exact.tv(pi, counts / counts.sum()):.4f}, "
+         f"TV to uniform {exact.tv(pi, np.full_like(pi, 1.0 / pi.size)):.3f}")
+    assert scipy.stats.chi2.sf(chi2, keep.sum() - 1) > 1e-5
+    assert exact.tv(pi, counts / counts.sum()) < 0.05 < exact.tv(pi, np.full_like(pi, 1.0 / pi.size))
+
+
+@pytest.mark.parametrize("J,h", [(1.0, -1.0), (0.5, 2.5)])
+def test_local_energy_matches_oracle(nqs, J, h):
+    L, F, R = 4, 8, 2
+    p = workloads.rescnn_params(F, R, 4)
+    model = nqs.Model.rescnn(L, F, R, p)
+    x = workloads.random_spins(24, L * L, 3)
+    ham = nqs.Hamiltonian("tfim", 2, L, J, h, True)
+    el = torch.empty(24, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, ham, torch.from_numpy(x).to(DEV), el)
+    ref = rescnn.ResCNN(L, F, R, p, "f32").local_energy_tfim(x, J, h)
+    got = el.cpu().numpy()
+    scale = np.abs(J) * 2 * L * L + np.abs(h) * np.abs(ref - 0) + 1.0
+    assert np.all(np.abs(got - ref) <= 1e-4 * scale)
+
+
+def test_rejections(nqs):
+    L, F, R = 4, 4, 1
+    model = nqs.Model.rescnn(L, F, R, workloads.rescnn_params(F, R, 1))
+    x = torch.from_numpy(workloads.random_spins(4, L * L, 1)).to(DEV)
+    with pytest.raises(nqs.NqsError):
+        nqs.nqs_logpsi_grad(model, x, O=torch.empty(4, model.n_params, dtype=torch.float32, device=DEV))
+    with pytest.raises(nqs.NqsError):
+        nqs.nqs_local_energy(model, nqs.Hamiltonian("heisenberg", 2, L, 1.0, 0.0, True), x,
+                             torch.empty(4, dtype=torch.float64, device=DEV))
+    state = torch.empty(4, L * L, dtype=torch.int8, device=DEV)
+    with pytest.raises(nqs.NqsError):
+        nqs.nqs_sample(model, nqs.SampleConfig(n_chains=4, n_sweeps=1, dtype="e4m3"), state)
+    with pytest.raises(nqs.NqsError):
+        nqs.Model("rescnn", 15, (4,), workloads.rescnn_params(4, 1, 1), lat_dim=2, lat_L=4, n_layers=1)
