@@ -32,6 +32,9 @@ Other workloads (--workload):
            enumeration and from 2^18 samples) beside the KL and average
            bounds, and the acceptance rate against sigma for RBMs trained
            here at h/J = 0.5, 1, 5.
+  rescnn   residual convolutional network: sampling time against samples and
+           filters per format on the 4x4 lattice (four blocks), and one sweep
+           of 4096 chains on the 10x10 lattice with 16 filters.
 """
 from __future__ import annotations
 
@@ -59,7 +62,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20", "noise"])
+    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20", "noise", "rescnn"])
     ap.add_argument("--sweeps", type=int, default=0, help="heis20: measured sweeps per step (default 1)")
     ap.add_argument("--gram-samples", type=int, default=4096, help="heis20: samples in T (0 = skip)")
     ap.add_argument("--gram-chunked", action="store_true", help="heis20: T by parameter column blocks")
@@ -632,6 +635,65 @@ def run_noise(a, torch, nqs, workloads):
     }
 
 
+def run_rescnn(a, torch, nqs, workloads):
+    """Residual convolutional network (App. H): sampling time against the number of samples N_s (chains
+    N_s / 4, four measured sweeps each) and the number of filters on the 4 x 4 lattice with four blocks,
+    per sampling format (the grid of the paper's Fig. A5), and the proposal rate of one sweep of 4096
+    chains on the 10 x 10 lattice with 16 filters (the network of the paper's Fig. 3)."""
+    dev = torch.device("cuda:0")
+    grid = []
+    ev = _events(torch, 2)
+
+    def time_sampling(model, N, C, S, B, dt, reps):
+        cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=1, dtype=dt)
+        state = torch.empty(C, N, dtype=torch.int8, device=dev)
+        samples = torch.empty(S, C, N, dtype=torch.int8, device=dev)
+        nqs.nqs_sample(model, cfg, state, samples)   # warm: copies, first launch
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            nqs.nqs_sample(model, cfg, state, samples)
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    L, R = 4, 4
+    for F in (8, 16, 32):
+        p = workloads.rescnn_params(F, R, F)
+        model = nqs.Model.rescnn(L, F, R, p)
+        for ns in (1 << 12, 1 << 14, 1 << 16):
+            row = {"filters": F, "samples": ns, "chains": ns // 4}
+            for dt in ("f32", "bf16", "f16"):
+                row[dt + "_ms"] = round(time_sampling(model, L * L, ns // 4, 4, 10, dt, 1), 3)
+            row["speedup_bf16"] = round(row["f32_ms"] / row["bf16_ms"], 3)
+            row["speedup_f16"] = round(row["f32_ms"] / row["f16_ms"], 3)
+            grid.append(row)
+        model.close()
+    # the Fig. 3 network: 10 x 10, 16 filters, 4 blocks, one sweep of 4096 chains
+    L, F = 10, 16
+    model = nqs.Model.rescnn(L, F, R, workloads.rescnn_params(F, R, 3))
+    C = 4096
+    props = C * L * L
+    res = {dt: time_sampling(model, L * L, C, 1, 0, dt, a.steps) for dt in ("f32", "bf16")}
+    ms = res[a.dtype if a.dtype in res else "bf16"]
+    macs = L * L * F * 9 * (1 + 2 * R * F)                     # per forward pass
+    achieved = 2.0 * macs * props / (ms * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": props / (ms * 1e-3), "unit": "proposals/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": a.dtype if a.dtype in res else "bf16", "data": "synthetic (seeded random ResCNN weights)",
+        "config": {"workload": "rescnn_tfim2d_10x10_f16_r4", "lattice": "10x10 periodic", "filters": F,
+                   "blocks": R, "kernel": "3x3", "chains": C, "sweeps_per_step": 1, "proposals_per_step": props,
+                   "parallelism": "single GPU"},
+        "fp32_ms": round(res["f32"], 3), "speedup_vs_fp32": round(res["f32"] / ms, 3),
+        "roofline": {"kernel": "cnn_sample_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
+                     "traffic": None, "flops_per_proposal": 2.0 * macs,
+                     "note": "one forward pass per proposal, FP32 VALU convolutions"},
+        "speedup_grid_4x4": grid,
+    }
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -651,7 +713,7 @@ def main():
     import paper_2601_20782_amd as nqs
     import workloads
     run = {"tfim10": run_tfim10, "heis10": run_heis10, "uneven": run_uneven, "heis20": run_heis20,
-           "noise": run_noise}[a.workload]
+           "noise": run_noise, "rescnn": run_rescnn}[a.workload]
     print(json.dumps(run(a, torch, nqs, workloads)))
 
 

@@ -145,9 +145,19 @@ __device__ inline float cnn_gelu(float x)
     return 0.5f * x * (1.0f + tanhf(c * fmaf(0.044715f * x * x, x, x)));
 }
 
+// FP32 -> format -> FP32, round to nearest even: BF16 by rounding the low 16
+// bits of the encoding (same exponent range; NaN kept quiet), FP16 by the
+// hardware conversion (round to nearest even, overflow to infinity).
 __device__ inline float cnn_round(float v, int dtype)
 {
-    return dtype == kF32 ? v : (float)round_to_dtype((double)v, dtype);
+    if (dtype == kBF16) {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return __uint_as_float(u | 0x00400000u);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return __uint_as_float(u & 0xffff0000u);
+    }
+    if (dtype == kF16) return (float)(_Float16)v;
+    return v;
 }
 
 // out[s][o] (+)= b[o] + sum_{k, c} W[c][k][o] in[nbr(s, k)][c]
