@@ -81,8 +81,9 @@ typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_ham_kind;
  *   per block [gamma, beta, W1 (F x F x 9), b1, W2 (F x F x 9), b2], then
  *   [gamma_f, beta_f]; W[o][c][k], k = 3 (dx+1) + (dy+1) for the input site
  *   (x+dx, y+dy), site i = x L + y.  Sampling (single flips), TFIM local
- *   energies on its lattice and log psi (nqs_logpsi_grad without O); no
- *   log-derivatives, no FP8 copy.
+ *   energies on its lattice, log psi and log-derivatives (nqs_logpsi_grad, its
+ *   VJP, nqs_sample_gram with O formed whole, nqs_sr_update); no FP8 copy, no
+ *   factored T, no column blocks of O.
  * marshall = 1 multiplies psi by (-1)^{#up spins on sublattice A}, A = {(x+y) even}
  *   (lat_dim = 2) or {i even} (lat_dim = 1), on an L = lat_L lattice. */
 typedef struct {

@@ -116,3 +116,21 @@ class ResCNN:
             off += np.exp(fi - f0)
         return diag + h * off
 
+
+
+def logpsi_grad_fd(net: ResCNN, samples: np.ndarray, step: float = 1e-5) -> np.ndarray:
+    """O[k][p] = d log psi(x_k) / d theta_p (Eq. eq:forces) by central differences
+    of the FP64 network (dtype "f64"), one parameter at a time."""
+    assert net.dtype == "f64"
+    base = net.params.copy()
+    x = np.asarray(samples, dtype=np.int8).reshape(-1, net.n)
+    O = np.empty((x.shape[0], base.size))
+    for q in range(base.size):
+        net.params = base.copy()
+        net.params[q] += step
+        fp, _ = net.logamp(x)
+        net.params[q] = base[q] - step
+        fm, _ = net.logamp(x)
+        O[:, q] = (fp - fm) / (2.0 * step)
+    net.params = base
+    return O

@@ -356,8 +356,8 @@ nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float
     if ((vjp_in == nullptr) != (vjp_out == nullptr)) return set_error(NQS_EINVAL, "vjp_in and vjp_out go together");
     hipStream_t s = (hipStream_t)stream;
     if (m->desc.arch == NQS_RESCNN) {
-        if (O || vjp_in) return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
-        return logpsi ? cnn_logpsi(m, samples, n, logpsi, s) : NQS_OK;
+        if (!O && !vjp_in) return logpsi ? cnn_logpsi(m, samples, n, logpsi, s) : NQS_OK;
+        return cnn_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s);
     }
     if (m->desc.arch == NQS_RBM) return rbm_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s, 0, m->P);
     return ffnn_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s, 0, m->P);
@@ -444,8 +444,18 @@ nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t
 nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64_t chunk_params, float *T,
                            void *stream)
 {
-    if (m && m->desc.arch == NQS_RESCNN)
-        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
+    if (m && m->desc.arch == NQS_RESCNN) {
+        // weights shared across sites: O is formed whole (one block of all columns)
+        if (n <= 0 || !samples || !T) return set_error(NQS_EINVAL, "bad samples/T");
+        hipStream_t s = (hipStream_t)stream;
+        const size_t ob = (sizeof(float) * (size_t)n * (size_t)m->P + 255) & ~(size_t)255;
+        if (ob > ((size_t)1 << 32)) return set_error(NQS_EUNSUPPORTED, "O of the convolutional network over 4 GiB");
+        char *ws = (char *)workspace_slot(1, ob, s);
+        if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+        nqs_status st = cnn_logpsi_grad(m, samples, n, nullptr, (float *)ws, nullptr, nullptr, s);
+        if (st != NQS_OK) return st;
+        return launch_gram((const float *)ws, n, m->P, 1, T, s);
+    }
     if (!m) return set_error(NQS_EINVAL, "NULL model");
     if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
     if (!samples || !T) return set_error(NQS_EINVAL, "NULL samples/T");

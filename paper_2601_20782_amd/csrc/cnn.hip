@@ -444,4 +444,263 @@ nqs_status cnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t 
     return NQS_OK;
 }
 
+// ---- log-derivatives O = d log psi / d theta (Eq. eq:forces), FP32 copy ----
+//
+// One sample per workgroup.  The forward pass keeps the residual stream before
+// every block and after the last, each block's conv1 pre-activation and the
+// layer-norm statistics in LDS; the backward pass recomputes phi(LN h) and
+// phi(conv1) from them.  Every derivative is a fixed-order sum over sites.
+
+__device__ inline float cnn_gelu_grad(float z)
+{
+    const float c = 0.7978845608028654f;
+    const float a = c * fmaf(0.044715f * z * z, z, z);
+    const float th = tanhf(a);
+    return 0.5f * (1.0f + th) + 0.5f * z * (1.0f - th * th) * c * fmaf(3.0f * 0.044715f, z * z, 1.0f);
+}
+
+__host__ __device__ inline size_t cnn_grad_lds_bytes(int S, int F, int R)
+{
+    const size_t SF = (size_t)S * F;
+    return sizeof(float) * ((size_t)S + (size_t)(2 * R + 1) * SF + 2 * (size_t)(R + 1) * S + 4 * SF +
+                            kCnnThreads / 64);
+}
+
+// per-site layer-norm statistics of h into mu[s], rs[s]
+__device__ inline void cnn_ln_stats(const float *h, int S, int F, float *mu, float *rs)
+{
+    for (int s = threadIdx.x; s < S; s += kCnnThreads) {
+        const float *hs = h + (size_t)s * F;
+        float m = 0.0f;
+        for (int c = 0; c < F; ++c) m += hs[c];
+        m /= (float)F;
+        float v = 0.0f;
+        for (int c = 0; c < F; ++c) v = fmaf(hs[c] - m, hs[c] - m, v);
+        mu[s] = m;
+        rs[s] = 1.0f / sqrtf(v / (float)F + kLnEps);
+    }
+}
+
+// gh[s][:] += LN backward of gz (gradient at the layer-norm output) through scale g
+__device__ inline void cnn_ln_back(const float *h, const float *mu, const float *rs, const float *gz, const float *g,
+                                   int S, int F, float *gh)
+{
+    for (int s = threadIdx.x; s < S; s += kCnnThreads) {
+        const float *hs = h + (size_t)s * F, *gs = gz + (size_t)s * F;
+        float m1 = 0.0f, m2 = 0.0f;
+        for (int c = 0; c < F; ++c) {
+            const float gn = gs[c] * g[c];
+            m1 += gn;
+            m2 = fmaf(gn, (hs[c] - mu[s]) * rs[s], m2);
+        }
+        m1 /= (float)F;
+        m2 /= (float)F;
+        for (int c = 0; c < F; ++c) {
+            const float gn = gs[c] * g[c], nh = (hs[c] - mu[s]) * rs[s];
+            gh[(size_t)s * F + c] += rs[s] * (gn - m1 - nh * m2);
+        }
+    }
+}
+
+// O[off + (o*C + c)*9 + k] = sum_s g[s][o] in[nbr(s,k)][c];  O[boff + o] = sum_s g[s][o]
+__device__ inline void cnn_wgrad(const float *g, const float *in, int S, int L, int C, int F, float *O, int64_t off,
+                                 int64_t boff)
+{
+    const int n = 9 * C * F;
+    for (int q = threadIdx.x; q < n + F; q += kCnnThreads) {
+        if (q < n) {
+            const int o = q / (9 * C), r = q - o * 9 * C, c = r / 9, k = r - c * 9;
+            float a = 0.0f;
+            for (int s = 0; s < S; ++s) a = fmaf(g[(size_t)s * F + o], in[(size_t)cnn_nbr(s, k, L) * C + c], a);
+            O[off + q] = a;
+        } else {
+            const int o = q - n;
+            float a = 0.0f;
+            for (int s = 0; s < S; ++s) a += g[(size_t)s * F + o];
+            O[boff + o] = a;
+        }
+    }
+}
+
+// gin[s'][c] = sum_{k,o} W[c][k][o] g[nbr(s', 8 - k)][o]   (the transposed convolution)
+__device__ inline void cnn_inback(const float *__restrict__ W, const float *g, int S, int L, int F, float *gin)
+{
+    for (int idx = threadIdx.x; idx < S * F; idx += kCnnThreads) {
+        const int s = idx / F, c = idx - (idx / F) * F;
+        float a = 0.0f;
+        for (int k = 0; k < 9; ++k) {
+            const float *gs = g + (size_t)cnn_nbr(s, 8 - k, L) * F;
+            const float *w = W + ((size_t)c * 9 + k) * F;
+            for (int o = 0; o < F; ++o) a = fmaf(w[o], gs[o], a);
+        }
+        gin[idx] = a;
+    }
+}
+
+__global__ void __launch_bounds__(kCnnThreads) cnn_grad_kernel(CnnDev net, const int8_t *__restrict__ samples,
+                                                               int64_t n, int64_t P, float *__restrict__ logpsi,
+                                                               float *__restrict__ O)
+{
+    extern __shared__ float sm[];
+    const int L = net.L, S = L * L, F = net.F, R = net.R, tid = threadIdx.x;
+    const size_t SF = (size_t)S * F;
+    float *x = sm;
+    float *H = x + S;                       // [R+1][S][F]
+    float *A1 = H + (size_t)(R + 1) * SF;   // [R][S][F]
+    float *MU = A1 + (size_t)R * SF;        // [R+1][S]
+    float *RS = MU + (size_t)(R + 1) * S;   // [R+1][S]
+    float *gh = RS + (size_t)(R + 1) * S;   // [S][F]
+    float *gu = gh + SF;
+    float *T1 = gu + SF;
+    float *T2 = T1 + SF;
+    float *red = T2 + SF;
+    const float *Pp = net.p;
+    for (int64_t row = blockIdx.x; row < n; row += gridDim.x) {
+        float *Orow = O ? O + row * P : nullptr;
+        for (int i = tid; i < S; i += kCnnThreads) x[i] = (float)samples[row * S + i];
+        __syncthreads();
+        // forward, keeping what the backward pass needs
+        for (int idx = tid; idx < (int)SF; idx += kCnnThreads) {
+            const int s = idx / F, o = idx - (idx / F) * F;
+            H[idx] = cnn_conv_at(Pp + net.w0, Pp + net.b0, x, s, o, L, 1, F);
+        }
+        __syncthreads();
+        for (int r = 0; r < R; ++r) {
+            const float *h = H + (size_t)r * SF;
+            cnn_ln_stats(h, S, F, MU + (size_t)r * S, RS + (size_t)r * S);
+            __syncthreads();
+            const float *g = Pp + net.g[r], *be = Pp + net.be[r];
+            for (int idx = tid; idx < (int)SF; idx += kCnnThreads) {
+                const int s = idx / F, c = idx - (idx / F) * F;
+                T1[idx] = cnn_gelu(fmaf((h[idx] - MU[r * S + s]) * RS[r * S + s], g[c], be[c]));
+            }
+            __syncthreads();
+            float *a1 = A1 + (size_t)r * SF;
+            for (int idx = tid; idx < (int)SF; idx += kCnnThreads) {
+                const int s = idx / F, o = idx - (idx / F) * F;
+                const float a = cnn_conv_at(Pp + net.w1[r], Pp + net.b1[r], T1, s, o, L, F, F);
+                a1[idx] = a;
+                T2[idx] = cnn_gelu(a);
+            }
+            __syncthreads();
+            float *hn = H + (size_t)(r + 1) * SF;
+            for (int idx = tid; idx < (int)SF; idx += kCnnThreads) {
+                const int s = idx / F, o = idx - (idx / F) * F;
+                hn[idx] = h[idx] + cnn_conv_at(Pp + net.w2[r], Pp + net.b2[r], T2, s, o, L, F, F);
+            }
+            __syncthreads();
+        }
+        const float *hR = H + (size_t)R * SF;
+        float *muR = MU + (size_t)R * S, *rsR = RS + (size_t)R * S;
+        cnn_ln_stats(hR, S, F, muR, rsR);
+        __syncthreads();
+        const float *gf = Pp + net.gf, *bef = Pp + net.bef;
+        float part = 0.0f;
+        for (int idx = tid; idx < (int)SF; idx += kCnnThreads) {
+            const int s = idx / F, c = idx - (idx / F) * F;
+            part += fmaf((hR[idx] - muR[s]) * rsR[s], gf[c], bef[c]);
+        }
+        part = group_sum<64>(part);
+        if ((tid & 63) == 0) red[tid >> 6] = part;
+        __syncthreads();
+        if (tid == 0 && logpsi) {
+            float f = 0.0f;
+            for (int w = 0; w < kCnnThreads / 64; ++w) f += red[w];
+            logpsi[row] = f;
+        }
+        if (Orow) {
+            // readout: d/d gamma_f, d/d beta_f; gradient at the final layer-norm output is 1
+            for (int c = tid; c < F; c += kCnnThreads) {
+                float a = 0.0f;
+                for (int s = 0; s < S; ++s) a += (hR[(size_t)s * F + c] - muR[s]) * rsR[s];
+                Orow[net.gf + c] = a;
+                Orow[net.bef + c] = (float)S;
+            }
+            for (int idx = tid; idx < (int)SF; idx += kCnnThreads) {
+                gu[idx] = 1.0f;
+                gh[idx] = 0.0f;
+            }
+            __syncthreads();
+            cnn_ln_back(hR, muR, rsR, gu, gf, S, F, gh);
+            __syncthreads();
+            for (int r = R - 1; r >= 0; --r) {
+                const float *h = H + (size_t)r * SF, *a1 = A1 + (size_t)r * SF;
+                const float *mu = MU + (size_t)r * S, *rs = RS + (size_t)r * S;
+                const float *g = Pp + net.g[r], *be = Pp + net.be[r];
+                for (int idx = tid; idx < (int)SF; idx += kCnnThreads) {
+                    const int s = idx / F, c = idx - (idx / F) * F;
+                    T1[idx] = cnn_gelu(fmaf((h[idx] - mu[s]) * rs[s], g[c], be[c]));   // t
+                    T2[idx] = cnn_gelu(a1[idx]);                                        // u
+                }
+                __syncthreads();
+                // conv2: weights from gh and u; gradient at u
+                cnn_wgrad(gh, T2, S, L, F, F, Orow, net.w2[r], net.b2[r]);
+                cnn_inback(Pp + net.w2[r], gh, S, L, F, gu);
+                __syncthreads();
+                for (int idx = tid; idx < (int)SF; idx += kCnnThreads) gu[idx] *= cnn_gelu_grad(a1[idx]);
+                __syncthreads();
+                // conv1: weights from the conv1 gradient and t; gradient at t (into T2)
+                cnn_wgrad(gu, T1, S, L, F, F, Orow, net.w1[r], net.b1[r]);
+                cnn_inback(Pp + net.w1[r], gu, S, L, F, T2);
+                __syncthreads();
+                // through phi and the block's layer norm (scale and shift), into gh
+                for (int idx = tid; idx < (int)SF; idx += kCnnThreads) {
+                    const int s = idx / F, c = idx - (idx / F) * F;
+                    T2[idx] *= cnn_gelu_grad(fmaf((h[idx] - mu[s]) * rs[s], g[c], be[c]));
+                }
+                __syncthreads();
+                for (int c = tid; c < F; c += kCnnThreads) {
+                    float ag = 0.0f, ab = 0.0f;
+                    for (int s = 0; s < S; ++s) {
+                        const float gz = T2[(size_t)s * F + c];
+                        ag = fmaf(gz, (h[(size_t)s * F + c] - mu[s]) * rs[s], ag);
+                        ab += gz;
+                    }
+                    Orow[net.g[r] + c] = ag;
+                    Orow[net.be[r] + c] = ab;
+                }
+                cnn_ln_back(h, mu, rs, T2, g, S, F, gh);
+                __syncthreads();
+            }
+            cnn_wgrad(gh, x, S, L, 1, F, Orow, net.w0, net.b0);
+        }
+        __syncthreads();
+    }
+}
+
+nqs_status cnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
+                           const float *vjp_in, float *vjp_out, hipStream_t stream)
+{
+    nqs_status st = ensure_copy(m, NQS_F32, stream);
+    if (st != NQS_OK) return st;
+    const CnnDev &net = m->copies[NQS_F32].cnn;
+    const int S = net.L * net.L;
+    const size_t lds = cnn_grad_lds_bytes(S, net.F, net.R);
+    if (lds > 160 * 1024)
+        return set_error(NQS_EUNSUPPORTED, "convolutional-network gradient: activations exceed 160 KB of LDS");
+    allow_lds(cnn_grad_kernel, lds);
+    const int64_t P = m->P;
+    if (logpsi || O) {
+        const int64_t blocks = std::min<int64_t>(n, (int64_t)device_cus() * 16);
+        hipLaunchKernelGGL(cnn_grad_kernel, dim3((unsigned)blocks), dim3(kCnnThreads), lds, stream, net, samples, n, P,
+                           logpsi, O);
+        NQS_HIP_TRY(hipGetLastError());
+    }
+    if (vjp_in) {
+        // vjp_out = O^T vjp_in through blocks of rows of O in the workspace
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(256ll << 20) / (P * 4)));
+        float *Ow = (float *)workspace(sizeof(float) * (size_t)chunk * P, stream);
+        if (!Ow) return set_error(NQS_ENOMEM, "workspace allocation failed");
+        for (int64_t k0 = 0; k0 < n; k0 += chunk) {
+            const int64_t kn = std::min(chunk, n - k0);
+            const int64_t blocks = std::min<int64_t>(kn, (int64_t)device_cus() * 16);
+            hipLaunchKernelGGL(cnn_grad_kernel, dim3((unsigned)blocks), dim3(kCnnThreads), lds, stream, net,
+                               samples + k0 * S, kn, P, nullptr, Ow);
+            st = launch_vjp_chunk(Ow, vjp_in + k0, kn, P, vjp_out, k0 == 0, stream);
+            if (st != NQS_OK) return st;
+        }
+    }
+    return NQS_OK;
+}
+
 }  // namespace nqs

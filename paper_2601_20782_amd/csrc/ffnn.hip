@@ -268,6 +268,15 @@ __global__ void vjp_chunk_kernel(const float *__restrict__ O, const float *__res
     out[p] = (float)acc;
 }
 
+nqs_status launch_vjp_chunk(const float *O, const float *g, int64_t n, int64_t P, float *out, bool first,
+                            hipStream_t stream)
+{
+    hipLaunchKernelGGL(vjp_chunk_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, O, g, n, P, out,
+                       first ? 1 : 0);
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}
+
 // Factors of O for B samples per block: the layer inputs a_{l-1} (post-ReLU) and
 // the deltas of every layer.  Each weight read from memory serves B samples;
 // per sample the arithmetic (and its order) is that of ffnn_grad_kernel, so

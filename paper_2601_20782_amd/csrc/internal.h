@@ -171,6 +171,11 @@ nqs_status cnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
 nqs_status cnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
                             double *eloc, hipStream_t stream);
 nqs_status cnn_logpsi(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, hipStream_t stream);
+nqs_status cnn_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
+                           const float *vjp_in, float *vjp_out, hipStream_t stream);
+// vjp_out[p] (+)= sum_k g[k] O[k][p] over a block of rows of O (first: overwrite)
+nqs_status launch_vjp_chunk(const float *O, const float *g, int64_t n, int64_t P, float *out, bool first,
+                            hipStream_t stream);
 nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
                        float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
 nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,

@@ -185,8 +185,6 @@ nqs_status nqs_sr_update(nqs_model *m, const int8_t *samples, int64_t n, const d
     if (!m) return set_error(NQS_EINVAL, "NULL model");
     if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
     if (!samples || !y || !master) return set_error(NQS_EINVAL, "NULL samples/y/master");
-    if (m->desc.arch == NQS_RESCNN)
-        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
     hipStream_t s = (hipStream_t)stream;
     const int64_t P = m->P;
     const size_t yb = r256(sizeof(float) * (size_t)n), gb = r256(sizeof(float) * (size_t)P);
@@ -197,8 +195,9 @@ nqs_status nqs_sr_update(nqs_model *m, const int8_t *samples, int64_t n, const d
     hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, y, (const double *)nullptr, n, sum);
     hipLaunchKernelGGL(sr_center_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, sum, n, yc);
     NQS_HIP_TRY(hipGetLastError());
-    nqs_status st = m->desc.arch == NQS_RBM ? rbm_logpsi_grad(m, samples, n, nullptr, nullptr, yc, g, s, 0, P)
-                                             : ffnn_logpsi_grad(m, samples, n, nullptr, nullptr, yc, g, s, 0, P);
+    nqs_status st = m->desc.arch == NQS_RBM      ? rbm_logpsi_grad(m, samples, n, nullptr, nullptr, yc, g, s, 0, P)
+                    : m->desc.arch == NQS_RESCNN ? cnn_logpsi_grad(m, samples, n, nullptr, nullptr, yc, g, s)
+                                                 : ffnn_logpsi_grad(m, samples, n, nullptr, nullptr, yc, g, s, 0, P);
     if (st != NQS_OK) return st;
     hipLaunchKernelGGL(sr_apply_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, g, P, lr, master);
     NQS_HIP_TRY(hipGetLastError());

@@ -66,3 +66,24 @@ def test_local_energy_matches_matrix_expectation():
 def test_parameter_count():
     for F, R in [(4, 1), (16, 4)]:
         assert rescnn.n_params(F, R) == workloads.rescnn_params(F, R, 0).size
+
+
+def test_finite_difference_gradient_is_consistent():
+    """The central-difference log-derivatives of the oracle: translation
+    invariance carries over (O of a translated configuration is the same), the
+    final layer-norm shift has derivative L^2 exactly, and a step along O
+    changes log psi to first order by |O|^2 h."""
+    L, F, R = 3, 4, 1
+    p = workloads.rescnn_params(F, R, 8)
+    net = rescnn.ResCNN(L, F, R, p)
+    x = workloads.random_spins(3, L * L, 5)
+    O = rescnn.logpsi_grad_fd(net, x)
+    g = x.reshape(-1, L, L)
+    Ot = rescnn.logpsi_grad_fd(net, np.roll(g, (1, 2), axis=(1, 2)).reshape(-1, L * L))
+    assert np.allclose(O, Ot, atol=1e-7)
+    assert np.allclose(O[:, -F:], L * L, atol=1e-6)          # d/d beta_f of sum over sites
+    h = 1e-4
+    f0, _ = net.logamp(x[:1])
+    net2 = rescnn.ResCNN(L, F, R, p + h * O[0])
+    f1, _ = net2.logamp(x[:1])
+    assert abs((f1[0] - f0[0]) - h * np.dot(O[0], O[0])) < 1e-3 * h * np.dot(O[0], O[0])
