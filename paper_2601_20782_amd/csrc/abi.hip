@@ -254,7 +254,7 @@ nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_sta
     if (c.sweep_size < 0) return set_error(NQS_EINVAL, "sweep_size < 0");
     if (c.instance_id >= (1u << 24)) return set_error(NQS_EINVAL, "instance_id must fit in 24 bits");
     if (c.lanes_per_chain != 0 && c.lanes_per_chain != 16 && c.lanes_per_chain != 32 && c.lanes_per_chain != 64 &&
-        !(c.lanes_per_chain == -1 && m->desc.arch == NQS_FFNN))
+        !(c.lanes_per_chain == -1 && (m->desc.arch == NQS_FFNN || m->desc.arch == NQS_RESCNN)))
         return set_error(NQS_EINVAL, "lanes_per_chain must be 0, 16, 32 or 64 (or -1 for a dense network)");
     if (c.dtype != NQS_F32 && c.dtype != NQS_F16 && c.dtype != NQS_BF16 && c.dtype != NQS_FP8_E4M3)
         return set_error(NQS_EINVAL, "sampling dtype must be F32, F16, BF16 or FP8_E4M3");

@@ -57,6 +57,30 @@ __global__ void cnn_build_kernel(const double *__restrict__ master, int64_t P, i
     }
 }
 
+// [offset][out][in] operands of the matrix-core convolutions from the rearranged
+// FP32 values ([in][offset][out]); the values are exact in the copy's format.
+__global__ void cnn_build_mc_kernel(CnnDev n, int64_t total)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int F = n.F;
+    const int64_t per = 9 * (int64_t)F * F;
+    const int rj = (int)(q / per);
+    const int64_t e = q - rj * per;
+    const int k = (int)(e / ((int64_t)F * F)), o = (int)((e / F) % F), c = (int)(e % F);
+    const int r = rj >> 1;
+    const float *W = n.p + ((rj & 1) ? n.w2[r] : n.w1[r]);
+    const float v = W[((int64_t)c * 9 + k) * F + o];
+    if (n.dtype == kF32) {
+        reinterpret_cast<float *>(n.wmc)[q] = v;
+    } else if (n.dtype == kBF16) {
+        reinterpret_cast<uint16_t *>(n.wmc)[q] = (uint16_t)(__float_as_uint(v) >> 16);
+    } else {
+        const _Float16 hv = (_Float16)v;
+        reinterpret_cast<uint16_t *>(n.wmc)[q] = *reinterpret_cast<const uint16_t *>(&hv);
+    }
+}
+
 nqs_status cnn_build_copy(nqs_model *m, int dtype, hipStream_t stream)
 {
     const nqs_model_desc &d = m->desc;
@@ -91,13 +115,22 @@ nqs_status cnn_build_copy(nqs_model *m, int dtype, hipStream_t stream)
     n.bef = seg(F, 0);
     if (off != m->P) return set_error(NQS_EINVAL, "convolutional network parameter count mismatch");
     const size_t pbytes = (sizeof(float) * (size_t)m->P + 255) & ~(size_t)255;
-    if (!c.block) NQS_HIP_TRY(hipMalloc(&c.block, pbytes + sizeof(segs)));
+    const size_t esz = dtype == NQS_F32 ? sizeof(float) : sizeof(uint16_t);
+    const int64_t nmc = 2 * (int64_t)n.R * 9 * F * F;
+    const size_t mcbytes = (esz * (size_t)nmc + 255) & ~(size_t)255;
+    const size_t sbytes = (sizeof(segs) + 255) & ~(size_t)255;
+    if (!c.block) NQS_HIP_TRY(hipMalloc(&c.block, pbytes + sbytes + mcbytes));
     n.p = (float *)c.block;
     CnnSeg *dsegs = (CnnSeg *)((char *)c.block + pbytes);
+    n.wmc = (char *)c.block + pbytes + sbytes;
     NQS_HIP_TRY(hipMemcpyAsync(dsegs, segs, sizeof(CnnSeg) * ns, hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(cnn_build_kernel, dim3((unsigned)((m->P + 255) / 256)), dim3(256), 0, stream, m->master, m->P,
                        dtype, dsegs, ns, n.p);
     NQS_HIP_TRY(hipGetLastError());
+    if (nmc > 0) {
+        hipLaunchKernelGGL(cnn_build_mc_kernel, dim3((unsigned)((nmc + 255) / 256)), dim3(256), 0, stream, n, nmc);
+        NQS_HIP_TRY(hipGetLastError());
+    }
     // the host array of segments must outlive the copy
     NQS_HIP_TRY(hipStreamSynchronize(stream));
     c.valid = true;
@@ -361,6 +394,276 @@ __global__ void __launch_bounds__(kCnnThreads) cnn_eloc_tfim_kernel(CnnDev net, 
     }
 }
 
+// ---- sampler with the convolutions on the matrix cores, B chains per workgroup ----
+//
+// The B chains of a workgroup propose in lockstep; the forward pass of their B
+// proposed configurations is one batch: each convolution is a product of the
+// [B*S rows][9 F] im2col matrix (gathered from LDS, the input of the
+// convolution stored in the copy's format) with the [9 F][F] weights, in
+// 16 x 16 tiles (v_mfma_f32_16x16x16_bf16 / _f16 with 16 channels of one
+// offset per step, or v_mfma_f32_16x16x4_f32), FP32 accumulation; layer
+// norms, GELU, biases and the residual stream stay FP32 as in the one-chain
+// kernel.  Only the order of the FP32 sums differs from it.
+
+typedef short cnn_s16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 cnn_h16x4 __attribute__((ext_vector_type(4)));
+typedef float cnn_f32x4 __attribute__((ext_vector_type(4)));
+
+template <int DT> struct CnnMcT;
+template <> struct CnnMcT<kF32> {
+    typedef float E;
+    static constexpr int KS = 4;   // channels per step
+    __device__ static float enc(float v) { return v; }
+    __device__ static float dec(float e) { return e; }
+};
+template <> struct CnnMcT<kBF16> {
+    typedef uint16_t E;
+    static constexpr int KS = 16;
+    __device__ static uint16_t enc(float v) { return (uint16_t)(__float_as_uint(cnn_round(v, kBF16)) >> 16); }
+    __device__ static float dec(uint16_t e) { return __uint_as_float((uint32_t)e << 16); }
+};
+template <> struct CnnMcT<kF16> {
+    typedef uint16_t E;
+    static constexpr int KS = 16;
+    __device__ static uint16_t enc(float v)
+    {
+        const _Float16 h = (_Float16)v;
+        return *reinterpret_cast<const uint16_t *>(&h);
+    }
+    __device__ static float dec(uint16_t e) { return (float)*reinterpret_cast<const _Float16 *>(&e); }
+};
+
+__host__ __device__ inline size_t cnn_mc_lds_bytes(int B, int S, int F, int esz)
+{
+    const size_t rows = (size_t)B * S;
+    size_t b = sizeof(float) * (rows + rows * F);        // x, h
+    b = (b + 15) & ~(size_t)15;
+    b += 2 * (size_t)esz * rows * F;                     // t, u
+    b = (b + 15) & ~(size_t)15;
+    b += sizeof(float) * (rows + 2 * (size_t)B) + 3 * sizeof(int) * (size_t)B;
+    return b;
+}
+
+// one convolution of the batch: out = in (*) W + bias; GELU + store in the format, or add into h
+template <int DT, int F, bool RESID>
+__device__ inline void cnn_mc_conv(const typename CnnMcT<DT>::E *in, const void *wmc, const float *bias, int rows,
+                                   int S, int L, typename CnnMcT<DT>::E *out, float *h)
+{
+    typedef CnnMcT<DT> M;
+    typedef typename M::E E;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, la = lane & 15, lk = lane >> 4;
+    const E *W = reinterpret_cast<const E *>(wmc);
+    for (int mt = wave; mt < rows / 16; mt += kCnnThreads / 64) {
+        const int row = mt * 16 + la, b = row / S, s = row - b * S;
+        int nrow[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) nrow[k] = b * S + cnn_nbr(s, k, L);
+#pragma unroll
+        for (int nt = 0; nt < F / 16; ++nt) {
+            cnn_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            const int o = nt * 16 + la;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+#pragma unroll
+                for (int cs = 0; cs < F / M::KS; ++cs) {
+                    if constexpr (DT == kF32) {
+                        const int c = cs * 4 + lk;
+                        const float a = in[(size_t)nrow[k] * F + c];
+                        const float w = W[((size_t)k * F + o) * F + c];
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w, acc, 0, 0, 0);
+                    } else {
+                        const int c = cs * 16 + 4 * lk;
+                        const uint2 av = *reinterpret_cast<const uint2 *>(in + (size_t)nrow[k] * F + c);
+                        const uint2 wv = *reinterpret_cast<const uint2 *>(W + ((size_t)k * F + o) * F + c);
+                        if constexpr (DT == kBF16) {
+                            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(cnn_s16x4, av),
+                                                                             __builtin_bit_cast(cnn_s16x4, wv), acc,
+                                                                             0, 0, 0);
+                        } else {
+                            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(cnn_h16x4, av),
+                                                                        __builtin_bit_cast(cnn_h16x4, wv), acc, 0, 0,
+                                                                        0);
+                        }
+                    }
+                }
+            }
+            // D[i][j] of a 16 x 16 block: j = lane % 16, i = 4 (lane / 16) + register
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int orow = mt * 16 + 4 * lk + r;
+                const float v = acc[r] + bias[o];
+                if constexpr (RESID) h[(size_t)orow * F + o] += v;
+                else out[(size_t)orow * F + o] = M::enc(cnn_round(cnn_gelu(v), DT));
+            }
+        }
+    }
+}
+
+// log psi of the B configurations in x into f[B]; ends with a barrier
+template <int DT, int F>
+__device__ void cnn_mc_forward(const CnnDev &net, int B, float *x, float *h, typename CnnMcT<DT>::E *t,
+                               typename CnnMcT<DT>::E *u, float *rsum, float *f)
+{
+    typedef CnnMcT<DT> M;
+    const int L = net.L, S = L * L, rows = B * S, tid = threadIdx.x;
+    const float *P = net.p;
+    const int64_t per = 9 * (int64_t)F * F;
+    const size_t esz = sizeof(typename M::E);
+    for (int idx = tid; idx < rows * F; idx += kCnnThreads) {
+        const int row = idx / F, o = idx - (idx / F) * F, b = row / S, s = row - b * S;
+        float a = P[net.b0 + o];
+        for (int k = 0; k < 9; ++k) a = fmaf(P[net.w0 + (int64_t)k * F + o], x[b * S + cnn_nbr(s, k, L)], a);
+        h[idx] = a;
+    }
+    __syncthreads();
+    for (int r = 0; r < net.R; ++r) {
+        const float *g = P + net.g[r], *be = P + net.be[r];
+        for (int row = tid; row < rows; row += kCnnThreads) {
+            const float *hs = h + (size_t)row * F;
+            float mu = 0.0f;
+            for (int c = 0; c < F; ++c) mu += hs[c];
+            mu /= (float)F;
+            float var = 0.0f;
+            for (int c = 0; c < F; ++c) var = fmaf(hs[c] - mu, hs[c] - mu, var);
+            const float rs = 1.0f / sqrtf(var / (float)F + kLnEps);
+            for (int c = 0; c < F; ++c)
+                t[(size_t)row * F + c] = M::enc(cnn_round(cnn_gelu(fmaf((hs[c] - mu) * rs, g[c], be[c])), DT));
+        }
+        __syncthreads();
+        cnn_mc_conv<DT, F, false>(t, (const char *)net.wmc + esz * (size_t)(2 * r) * per, P + net.b1[r], rows, S, L,
+                                  u, h);
+        __syncthreads();
+        cnn_mc_conv<DT, F, true>(u, (const char *)net.wmc + esz * (size_t)(2 * r + 1) * per, P + net.b2[r], rows, S,
+                                 L, u, h);
+        __syncthreads();
+    }
+    const float *gf = P + net.gf, *bef = P + net.bef;
+    for (int row = tid; row < rows; row += kCnnThreads) {
+        const float *hs = h + (size_t)row * F;
+        float mu = 0.0f;
+        for (int c = 0; c < F; ++c) mu += hs[c];
+        mu /= (float)F;
+        float var = 0.0f;
+        for (int c = 0; c < F; ++c) var = fmaf(hs[c] - mu, hs[c] - mu, var);
+        const float rs = 1.0f / sqrtf(var / (float)F + kLnEps);
+        float a = 0.0f;
+        for (int c = 0; c < F; ++c) a += fmaf((hs[c] - mu) * rs, gf[c], bef[c]);
+        rsum[row] = a;
+    }
+    __syncthreads();
+    if (tid < B) {
+        float a = 0.0f;
+        for (int s = 0; s < S; ++s) a += rsum[tid * S + s];
+        f[tid] = a;
+    }
+    __syncthreads();
+}
+
+template <int DT, int F>
+__global__ void __launch_bounds__(kCnnThreads) cnn_sample_mc_kernel(CnnSampleArgs A, int B)
+{
+    typedef typename CnnMcT<DT>::E E;
+    extern __shared__ __align__(16) unsigned char smc[];
+    const int L = A.net.L, S = L * L, rows = B * S, tid = threadIdx.x;
+    float *x = reinterpret_cast<float *>(smc);
+    float *h = x + rows;
+    size_t off = ((sizeof(float) * ((size_t)rows + (size_t)rows * F)) + 15) & ~(size_t)15;
+    E *t = reinterpret_cast<E *>(smc + off);
+    E *u = t + (size_t)rows * F;
+    off = (off + 2 * sizeof(E) * (size_t)rows * F + 15) & ~(size_t)15;
+    float *rsum = reinterpret_cast<float *>(smc + off);
+    float *fcur = rsum + rows, *fnew = fcur + B;
+    int *site = reinterpret_cast<int *>(fnew + B), *accn = site + B;
+    uint32_t *ubs = reinterpret_cast<uint32_t *>(accn + B);
+    const uint32_t key0 = (uint32_t)A.seed, key1 = (uint32_t)(A.seed >> 32);
+    const int64_t total = (int64_t)(A.n_burnin + A.n_sweeps) * A.sweep_size;
+    for (int64_t c0 = (int64_t)blockIdx.x * B; c0 < A.n_chains; c0 += (int64_t)gridDim.x * B) {
+        for (int i = tid; i < rows; i += kCnnThreads) {
+            const int64_t c = c0 + i / S;
+            x[i] = c < A.n_chains ? (float)A.chain_state[c * S + i % S] : 1.0f;
+        }
+        if (tid < B) accn[tid] = 0;
+        __syncthreads();
+        cnn_mc_forward<DT, F>(A.net, B, x, h, t, u, rsum, fcur);
+        for (int64_t k = 0; k < total; ++k) {
+            const uint64_t step = A.step_offset + (uint64_t)k;
+            if (tid < B) {
+                const uint32_t gid = A.chain_id_offset + (uint32_t)(c0 + tid);
+                const Block4 rb = philox4x32_10((uint32_t)step, (uint32_t)(step >> 32), gid, A.inst << 8, key0, key1);
+                const int i = index_from_word(rb.r0, S);
+                site[tid] = i;
+                ubs[tid] = rb.r2 >> 8;
+                x[tid * S + i] = -x[tid * S + i];
+            }
+            __syncthreads();
+            cnn_mc_forward<DT, F>(A.net, B, x, h, t, u, rsum, fnew);
+            if (tid < B) {
+                const int64_t c = c0 + tid;
+                const float d = 2.0f * (fnew[tid] - fcur[tid]);
+                const float l2u = __builtin_amdgcn_logf((float)ubs[tid] * 5.9604644775390625e-8f);
+                const bool accept = l2u < d * 1.4426950408889634f;
+                if (accept) {
+                    fcur[tid] = fnew[tid];
+                    ++accn[tid];
+                } else {
+                    x[tid * S + site[tid]] = -x[tid * S + site[tid]];
+                }
+                if (c < A.n_traced) {
+                    const size_t idx = (size_t)c * (size_t)total + (size_t)k;
+                    A.tr_site[idx] = site[tid] | (0xFFFF << 16);
+                    A.tr_ubits[idx] = ubs[tid];
+                    A.tr_delta[idx] = d;
+                    A.tr_acc[idx] = accept ? 1 : 0;
+                }
+            }
+            __syncthreads();
+            if ((k + 1) % A.sweep_size == 0) {
+                const int64_t out = (k + 1) / A.sweep_size - 1 - A.n_burnin;
+                if (out >= 0) {
+                    for (int i = tid; i < rows; i += kCnnThreads) {
+                        const int64_t c = c0 + i / S;
+                        if (c < A.n_chains && A.samples)
+                            A.samples[((size_t)out * A.n_chains + c) * S + i % S] = x[i] > 0.0f ? 1 : -1;
+                    }
+                    if (A.logpsi && tid < B && c0 + tid < A.n_chains)
+                        A.logpsi[(size_t)out * A.n_chains + c0 + tid] = fcur[tid];
+                    __syncthreads();
+                }
+            }
+        }
+        for (int i = tid; i < rows; i += kCnnThreads) {
+            const int64_t c = c0 + i / S;
+            if (c < A.n_chains) A.chain_state[c * S + i % S] = x[i] > 0.0f ? 1 : -1;
+        }
+        if (A.n_acc && tid < B && c0 + tid < A.n_chains) A.n_acc[c0 + tid] = (unsigned long long)accn[tid];
+        __syncthreads();
+    }
+}
+
+// Chains per workgroup for the matrix-core sampler (0: not applicable): B * S a
+// multiple of 16 and the batch's activations within 160 KB of LDS.
+static int cnn_mc_chains(const CnnDev &net)
+{
+    if (net.F != 16 && net.F != 32) return 0;
+    const int S = net.L * net.L;
+    const int esz = net.dtype == NQS_F32 ? 4 : 2;
+    for (int B : {16, 8, 4, 2, 1})
+        if ((B * S) % 16 == 0 && cnn_mc_lds_bytes(B, S, net.F, esz) <= 160 * 1024) return B;
+    return 0;
+}
+
+template <int DT>
+static void launch_cnn_mc(const CnnSampleArgs &A, int B, int64_t blocks, size_t lds, hipStream_t stream)
+{
+    if (A.net.F == 16) {
+        allow_lds(cnn_sample_mc_kernel<DT, 16>, lds);
+        hipLaunchKernelGGL((cnn_sample_mc_kernel<DT, 16>), dim3((unsigned)blocks), dim3(kCnnThreads), lds, stream, A, B);
+    } else {
+        allow_lds(cnn_sample_mc_kernel<DT, 32>, lds);
+        hipLaunchKernelGGL((cnn_sample_mc_kernel<DT, 32>), dim3((unsigned)blocks), dim3(kCnnThreads), lds, stream, A, B);
+    }
+}
+
 // ---- host ----
 
 static nqs_status cnn_check(const CnnDev &net)
@@ -417,6 +720,17 @@ nqs_status cnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
     A.tr_ubits = tr ? trace->ubits : nullptr;
     A.tr_delta = tr ? trace->delta : nullptr;
     A.tr_acc = tr ? trace->accepted : nullptr;
+    const int B = cfg.lanes_per_chain == -1 ? 0 : cnn_mc_chains(net);
+    if (B > 0) {
+        const size_t lds = cnn_mc_lds_bytes(B, S, net.F, net.dtype == NQS_F32 ? 4 : 2);
+        const int64_t groups = (cfg.n_chains + B - 1) / B;
+        const int64_t blocks = std::min<int64_t>(groups, (int64_t)device_cus() * 16);
+        if (net.dtype == NQS_BF16) launch_cnn_mc<kBF16>(A, B, blocks, lds, stream);
+        else if (net.dtype == NQS_F16) launch_cnn_mc<kF16>(A, B, blocks, lds, stream);
+        else launch_cnn_mc<kF32>(A, B, blocks, lds, stream);
+        NQS_HIP_TRY(hipGetLastError());
+        return NQS_OK;
+    }
     const size_t lds = cnn_lds_bytes(S, net.F);
     allow_lds(cnn_sample_kernel, lds);
     const int64_t blocks = std::min<int64_t>(cfg.n_chains, (int64_t)device_cus() * 16);

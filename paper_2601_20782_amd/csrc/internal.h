@@ -65,6 +65,10 @@ struct CnnDev {
     int64_t w0 = 0, b0 = 0, gf = 0, bef = 0;
     int64_t g[NQS_MAX_LAYERS] = {0}, be[NQS_MAX_LAYERS] = {0}, w1[NQS_MAX_LAYERS] = {0}, b1[NQS_MAX_LAYERS] = {0},
             w2[NQS_MAX_LAYERS] = {0}, b2[NQS_MAX_LAYERS] = {0};
+    // matrix-core operands: block r's conv1 (j = 0) and conv2 (j = 1) weights at
+    // wmc + (2 r + j) 9 F^2 elements, laid out [offset][out channel][in channel];
+    // raw BF16/FP16 codes for those copies, FP32 values for the FP32 copy
+    void *wmc = nullptr;
 };
 
 struct Copy {

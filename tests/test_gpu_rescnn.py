@@ -62,17 +62,21 @@ def _trace_run(nqs, model, N, dtype, C, S, B, T, seed=5):
     return out
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
-def test_sampler_decisions_replay_in_fp64(nqs, dtype):
+@pytest.mark.parametrize("dtype,L,F,C", [("f32", 4, 8, 16), ("bf16", 4, 8, 16), ("f16", 4, 8, 16),
+                                         ("f32", 4, 16, 40), ("bf16", 4, 16, 40), ("f16", 4, 16, 40),
+                                         ("bf16", 5, 32, 7), ("f32", 3, 16, 33)])
+def test_sampler_decisions_replay_in_fp64(nqs, dtype, L, F, C):
     """Each traced proposal: site and u equal the Philox draws, Delta equals the
     oracle's FP64 2 (log psi(x') - log psi(x)) of the `dtype` network within its
-    rounding, and the decision equals u < exp(min(Delta, 0)) except near ties."""
-    L, F, R = 4, 8, 2
+    rounding, and the decision equals u < exp(min(Delta, 0)) except near ties.
+    F = 8 runs one chain per workgroup; F = 16 and 32 the matrix-core kernel with
+    several chains per workgroup (C not a multiple of them: a partial group)."""
+    R = 2
     N = L * L
     p = workloads.rescnn_params(F, R, 9, scale=1.5)
     model = nqs.Model.rescnn(L, F, R, p)
     T, S, B = 3, 6, 2
-    r = _trace_run(nqs, model, N, dtype, 16, S, B, T)
+    r = _trace_run(nqs, model, N, dtype, C, S, B, T)
     net = rescnn.ResCNN(L, F, R, p, dtype)
     tol = {"f32": 1e-4, "bf16": 3e-2, "f16": 5e-3}[dtype]
     near, max_err = 0, 0.0
@@ -100,18 +104,19 @@ def test_sampler_decisions_replay_in_fp64(nqs, dtype):
             if r["accepted"][c, k]:
                 x, f0 = y, f1
     assert np.array_equal(x, r["state"][T - 1]) or near > 0
-    _say(f"  {dtype}: max relative |dDelta| {max_err:.2e}, {near} near ties")
+    _say(f"  {dtype} L={L} F={F}: max relative |dDelta| {max_err:.2e}, {near} near ties")
 
 
-def test_sampler_histogram_matches_exact_pi(nqs):
-    """3 x 3 lattice, final layer-norm scale N(0, 0.3^2): pi spans a factor ~200
-    (TV 0.26 from uniform)."""
-    L, F, R = 3, 4, 1
+@pytest.mark.parametrize("F,lanes", [(4, 0), (16, 0), (16, -1)])
+def test_sampler_histogram_matches_exact_pi(nqs, F, lanes):
+    """3 x 3 lattice, final layer-norm scale N(0, 0.3^2): pi far from uniform.
+    F = 16 runs the matrix-core kernel unless lanes_per_chain = -1."""
+    L, R = 3, 1
     N = L * L
     p = workloads.rescnn_params(F, R, 3, scale=2.0).copy()
     p[-2 * F:-F] = np.random.default_rng(7).normal(0.0, 0.3, size=F)
     model = nqs.Model.rescnn(L, F, R, p)
-    cfg = nqs.SampleConfig(n_chains=8192, n_sweeps=60, n_burnin=30, seed=2)
+    cfg = nqs.SampleConfig(n_chains=8192, n_sweeps=60, n_burnin=30, seed=2, lanes_per_chain=lanes)
     state = torch.empty(8192, N, dtype=torch.int8, device=DEV)
     samples = torch.empty(60, 8192, N, dtype=torch.int8, device=DEV)
     nqs.nqs_sample(model, cfg, state, samples)
