@@ -98,6 +98,13 @@ def ffnn_params(n: int, widths, seed: int, bias_std: float = 0.0) -> np.ndarray:
     return np.concatenate(out).astype(np.float64)
 
 
+def crbm_params(n: int, m: int, std_re: float, std_im: float, seed: int) -> np.ndarray:
+    """Complex RBM: real parts of a, b, W ~ N(0, std_re^2), then imaginary parts ~ N(0, std_im^2)."""
+    rng = np.random.default_rng(seed)
+    P = n + m + m * n
+    return np.concatenate([rng.normal(0.0, std_re, size=P), rng.normal(0.0, std_im, size=P)]).astype(np.float64)
+
+
 def rescnn_params(F: int, R: int, seed: int, scale: float = 1.0) -> np.ndarray:
     """Residual convolutional network (App. H), in its parameter order: conv weights
     N(0, scale^2 2/fan_in), biases N(0, 0.1^2), layer-norm scales 1 + N(0, 0.1^2) and
