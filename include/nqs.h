@@ -61,7 +61,7 @@ typedef enum {
 } nqs_status;
 
 typedef enum { NQS_F64 = 0, NQS_F32 = 1, NQS_F16 = 2, NQS_BF16 = 3, NQS_FP8_E4M3 = 4 } nqs_dtype;
-typedef enum { NQS_RBM = 0, NQS_FFNN = 1, NQS_RESCNN = 2 } nqs_arch;
+typedef enum { NQS_RBM = 0, NQS_FFNN = 1, NQS_RESCNN = 2, NQS_CRBM = 3 } nqs_arch;
 typedef enum { NQS_MOVE_FLIP = 0, NQS_MOVE_EXCHANGE = 1 } nqs_move;
 typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_ham_kind;
 
@@ -84,6 +84,11 @@ typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_ham_kind;
  *   energies on its lattice, log psi and log-derivatives (nqs_logpsi_grad, its
  *   VJP, nqs_sample_gram with O formed whole, nqs_sr_update); no FP8 copy, no
  *   factored T, no column blocks of O.
+ * CRBM: the RBM with complex a, b, W (widths[0] = M, n_layers = 1); |psi|^2 =
+ *   exp(2 Re log psi) is sampled.  Parameter vector of 2 (N + M + M N) reals:
+ *   the real parts in the RBM order, then the imaginary parts; a format rounds
+ *   both parts.  Sampling (single flips), TFIM local energies (nqs_local_energy
+ *   gives the real part, nqs_local_energy_complex both); no log-derivatives.
  * marshall = 1 multiplies psi by (-1)^{#up spins on sublattice A}, A = {(x+y) even}
  *   (lat_dim = 2) or {i even} (lat_dim = 1), on an L = lat_L lattice. */
 typedef struct {
@@ -216,6 +221,12 @@ nqs_status nqs_sample_noisy(nqs_model *m, const nqs_sample_cfg *cfg, double nois
  * from the `eval_dtype` copy of the parameters: NQS_F32 by default). */
 nqs_status nqs_local_energy(nqs_model *m, const nqs_ham_desc *ham, const int8_t *samples, int64_t n_samples,
                             int32_t eval_dtype, double *eloc, void *stream);
+
+/* Complex local energies of a complex RBM (TFIM): eloc_re[n], eloc_im[n]
+ * (FP64 sums of FP32 complex flip ratios).  For the other networks, eloc_re
+ * as nqs_local_energy and eloc_im zero. */
+nqs_status nqs_local_energy_complex(nqs_model *m, const nqs_ham_desc *ham, const int8_t *samples, int64_t n_samples,
+                                   int32_t eval_dtype, double *eloc_re, double *eloc_im, void *stream);
 
 /* stats[4] (device, FP64): mean, unbiased variance, standard error of the
  * per-chain means, n.  eloc is laid out [sweep][chain] with n_chains chains;

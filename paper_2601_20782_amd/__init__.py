@@ -22,7 +22,7 @@ from ._abi import DTYPE_CODES, NqsError, check, load
 __all__ = [
     "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
     "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
-    "nqs_sr_solve", "nqs_sr_update", "nqs_sample_noisy", "nqs_downcast", "LogPsi", "NqsError", "load",
+    "nqs_sr_solve", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
 ]
 
 
@@ -52,7 +52,7 @@ class Model:
                  lat_dim: int = 0, lat_L: int = 0, n_layers: Optional[int] = None):
         lib = load()
         d = _abi.ModelDesc()
-        d.arch = {"rbm": _abi.RBM, "ffnn": _abi.FFNN, "rescnn": _abi.RESCNN}[arch]
+        d.arch = {"rbm": _abi.RBM, "ffnn": _abi.FFNN, "rescnn": _abi.RESCNN, "crbm": _abi.CRBM}[arch]
         d.n_visible = n_visible
         d.n_layers = len(widths) if n_layers is None else n_layers
         for k, w in enumerate(widths):
@@ -234,6 +234,16 @@ def nqs_local_energy(model: Model, ham: Hamiltonian, samples: torch.Tensor, eloc
     h = ham.to_c()
     check(load().nqs_local_energy(model.handle, ctypes.byref(h), _ptr(samples), n, _dtype(eval_dtype), _ptr(eloc),
                                   _stream(stream)))
+
+
+def nqs_local_energy_complex(model: Model, ham: Hamiltonian, samples: torch.Tensor, eloc_re: torch.Tensor,
+                             eloc_im: torch.Tensor, eval_dtype="f32", stream=None) -> None:
+    n = samples.numel() // model.n_visible
+    assert samples.dtype == torch.int8 and eloc_re.dtype == torch.float64 and eloc_re.numel() == n
+    assert eloc_im.dtype == torch.float64 and eloc_im.numel() == n
+    h = ham.to_c()
+    check(load().nqs_local_energy_complex(model.handle, ctypes.byref(h), _ptr(samples), n, _dtype(eval_dtype),
+                                          _ptr(eloc_re), _ptr(eloc_im), _stream(stream)))
 
 
 def nqs_energy_stats(eloc: torch.Tensor, n_chains: int, stats: torch.Tensor, stream=None) -> None:

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libnqs.so")
 
 NQS_OK, NQS_EINVAL, NQS_ENOMEM, NQS_EDEVICE, NQS_EUNSUPPORTED, NQS_ENUMERIC = range(6)
 F64, F32, F16, BF16, FP8_E4M3 = range(5)
-RBM, FFNN, RESCNN = 0, 1, 2
+RBM, FFNN, RESCNN, CRBM = 0, 1, 2, 3
 MOVE_FLIP, MOVE_EXCHANGE = 0, 1
 TFIM, HEISENBERG = 0, 1
 MAX_LAYERS = 8
@@ -22,7 +22,7 @@ EXPORTS = [
     "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched",
     "nqs_local_energy", "nqs_energy_stats",
     "nqs_logpsi_grad", "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
-    "nqs_sr_solve", "nqs_sr_update", "nqs_sample_noisy",
+    "nqs_sr_solve", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex",
     "nqs_last_error",
     "nqs_version",
 ]
@@ -98,6 +98,7 @@ def load() -> ctypes.CDLL:
         "nqs_sr_solve": ([P, P, i64, ctypes.c_double, ctypes.c_double, i32, P, P, P, P], st),
         "nqs_sr_update": ([P, P, i64, P, ctypes.c_double, P, P], st),
         "nqs_sample_noisy": ([P, P, ctypes.c_double, ctypes.c_uint64, P, P, P, P, P], st),
+        "nqs_local_energy_complex": ([P, P, P, i64, i32, P, P, P], st),
         "nqs_last_error": ([], ctypes.c_char_p),
         "nqs_version": ([], ctypes.c_char_p),
     }

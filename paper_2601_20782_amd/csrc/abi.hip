@@ -83,6 +83,7 @@ int64_t model_num_params(const nqs_model_desc &d)
     const int64_t N = d.n_visible;
     if (d.arch == NQS_RBM) return N + d.widths[0] + (int64_t)d.widths[0] * N;
     if (d.arch == NQS_RESCNN) return cnn_num_params(d.widths[0], d.n_layers);
+    if (d.arch == NQS_CRBM) return 2 * (N + d.widths[0] + (int64_t)d.widths[0] * N);
     int64_t p = 0, prev = N;
     for (int l = 0; l < d.n_layers; ++l) {
         p += (int64_t)d.widths[l] * (prev + 1);
@@ -96,6 +97,7 @@ nqs_status ensure_copy(nqs_model *m, int dtype, hipStream_t stream)
     if (m->copies[dtype].valid) return NQS_OK;
     if (m->desc.arch == NQS_RBM) return rbm_build_copy(m, dtype, stream);
     if (m->desc.arch == NQS_RESCNN) return cnn_build_copy(m, dtype, stream);
+    if (m->desc.arch == NQS_CRBM) return crbm_build_copy(m, dtype, stream);
     return ffnn_build_copy(m, dtype, stream);
 }
 
@@ -108,8 +110,9 @@ static nqs_status validate_desc(const nqs_model_desc *d)
 {
     if (!d) return set_error(NQS_EINVAL, "desc is NULL");
     if (d->n_visible < 2 || d->n_visible > 4096) return set_error(NQS_EINVAL, "n_visible must be in [2, 4096]");
-    if (d->arch == NQS_RBM) {
+    if (d->arch == NQS_RBM || d->arch == NQS_CRBM) {
         if (d->n_layers != 1) return set_error(NQS_EINVAL, "RBM needs n_layers = 1");
+        if (d->arch == NQS_CRBM && d->marshall) return set_error(NQS_EINVAL, "the complex RBM carries its own phases");
         if (d->widths[0] < 1 || d->widths[0] > 8192) return set_error(NQS_EINVAL, "RBM hidden width must be in [1, 8192]");
     } else if (d->arch == NQS_FFNN) {
         if (d->n_layers < 1 || d->n_layers > NQS_MAX_LAYERS) return set_error(NQS_EINVAL, "FFNN needs 1..8 layers");
@@ -270,6 +273,10 @@ nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_sta
         if (c.move != NQS_MOVE_FLIP) return set_error(NQS_EUNSUPPORTED, "the RBM sampler implements single-flip moves");
         return rbm_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
     }
+    if (m->desc.arch == NQS_CRBM) {
+        if (c.move != NQS_MOVE_FLIP) return set_error(NQS_EUNSUPPORTED, "the complex RBM sampler implements single flips");
+        return crbm_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
+    }
     if (m->desc.arch == NQS_RESCNN) {
         if (c.move != NQS_MOVE_FLIP || c.sweep_size != 0)
             return set_error(NQS_EUNSUPPORTED, "the convolutional-network sampler implements single flips, sweeps of N");
@@ -335,7 +342,32 @@ nqs_status nqs_local_energy(nqs_model *m, const nqs_ham_desc *ham, const int8_t 
         return rbm_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);
     }
     if (m->desc.arch == NQS_RESCNN) return cnn_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);
+    if (m->desc.arch == NQS_CRBM) return crbm_local_energy(m, h, samples, n_samples, eval_dtype, eloc, nullptr, s);
     return ffnn_local_energy(m, h, samples, n_samples, eval_dtype, eloc, s);
+}
+
+nqs_status nqs_local_energy_complex(nqs_model *m, const nqs_ham_desc *ham, const int8_t *samples, int64_t n_samples,
+                                   int32_t eval_dtype, double *eloc_re, double *eloc_im, void *stream)
+{
+    if (!m || !ham) return set_error(NQS_EINVAL, "NULL model or hamiltonian");
+    if (m->desc.arch != NQS_CRBM) {
+        if (eloc_im && n_samples > 0) {
+            const nqs_status z = launch_zero_u64(reinterpret_cast<uint64_t *>(eloc_im), n_samples, (hipStream_t)stream);
+            if (z != NQS_OK) return z;
+        }
+        return nqs_local_energy(m, ham, samples, n_samples, eval_dtype, eloc_re, stream);
+    }
+    if (n_samples < 0) return set_error(NQS_EINVAL, "n_samples < 0");
+    if (n_samples == 0) return NQS_OK;
+    if (!samples || !eloc_re || !eloc_im) return set_error(NQS_EINVAL, "NULL samples/eloc_re/eloc_im");
+    const nqs_ham_desc &h = *ham;
+    if (h.dim != 1 && h.dim != 2) return set_error(NQS_EINVAL, "dim must be 1 or 2");
+    if (h.pbc && h.L < 3) return set_error(NQS_EINVAL, "periodic lattices need L >= 3");
+    if (!h.pbc && h.L < 2) return set_error(NQS_EINVAL, "L >= 2 required");
+    if (ham_sites(h) != m->desc.n_visible) return set_error(NQS_EINVAL, "lattice size does not match n_visible");
+    if (eval_dtype != NQS_F32 && eval_dtype != NQS_F16 && eval_dtype != NQS_BF16)
+        return set_error(NQS_EINVAL, "eval dtype must be F32, F16 or BF16");
+    return crbm_local_energy(m, h, samples, n_samples, eval_dtype, eloc_re, eloc_im, (hipStream_t)stream);
 }
 
 nqs_status nqs_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, void *stream)
@@ -355,6 +387,7 @@ nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float
     if (!samples) return set_error(NQS_EINVAL, "NULL samples");
     if ((vjp_in == nullptr) != (vjp_out == nullptr)) return set_error(NQS_EINVAL, "vjp_in and vjp_out go together");
     hipStream_t s = (hipStream_t)stream;
+    if (m->desc.arch == NQS_CRBM) return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
     if (m->desc.arch == NQS_RESCNN) {
         if (!O && !vjp_in) return logpsi ? cnn_logpsi(m, samples, n, logpsi, s) : NQS_OK;
         return cnn_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s);
@@ -366,6 +399,8 @@ nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float
 nqs_status nqs_logpsi_grad_cols(nqs_model *m, const int8_t *samples, int64_t n, int64_t p0, int64_t p1, float *O,
                                 void *stream)
 {
+    if (m && m->desc.arch == NQS_CRBM)
+        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
     if (m && m->desc.arch == NQS_RESCNN)
         return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
     if (!m) return set_error(NQS_EINVAL, "NULL model");
@@ -380,6 +415,8 @@ nqs_status nqs_logpsi_grad_cols(nqs_model *m, const int8_t *samples, int64_t n, 
 
 nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t n, float *T, void *stream)
 {
+    if (m && m->desc.arch == NQS_CRBM)
+        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
     if (m && m->desc.arch == NQS_RESCNN)
         return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
     if (!m) return set_error(NQS_EINVAL, "NULL model");
@@ -444,6 +481,8 @@ nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t
 nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64_t chunk_params, float *T,
                            void *stream)
 {
+    if (m && m->desc.arch == NQS_CRBM)
+        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
     if (m && m->desc.arch == NQS_RESCNN) {
         // weights shared across sites: O is formed whole (one block of all columns)
         if (n <= 0 || !samples || !T) return set_error(NQS_EINVAL, "bad samples/T");

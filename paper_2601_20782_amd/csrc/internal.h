@@ -71,11 +71,23 @@ struct CnnDev {
     void *wmc = nullptr;
 };
 
+// Complex-parameter RBM copy: FP32 (real, imaginary) pairs of the rounded
+// parameters and the tables (cosh 2W, sinh 2W) as (re, im, re, im).
+struct CrbmDev {
+    int N = 0, M = 0;
+    float2 *a = nullptr;      // [N]
+    float2 *b = nullptr;      // [M]
+    float2 *Wt = nullptr;     // [N][M]  Wt[i][j] = W[j][i]
+    float4 *CS = nullptr;     // [N][M]
+    float4 *CSt = nullptr;    // [M][N]
+};
+
 struct Copy {
     bool valid = false;
     RbmDev rbm;
     FfnnDev ffnn;
     CnnDev cnn;
+    CrbmDev crbm;
     void *block = nullptr;   // single allocation backing the arrays above
 };
 
@@ -167,6 +179,12 @@ nqs_status rbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t 
 nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
                            const float *vjp_in, float *vjp_out, hipStream_t stream, int64_t p0, int64_t p1);
 nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream);
+// complex-parameter RBM
+nqs_status crbm_build_copy(nqs_model *m, int dtype, hipStream_t stream);
+nqs_status crbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
+                       uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
+nqs_status crbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,
+                             double *eloc_re, double *eloc_im, hipStream_t stream);
 // residual convolutional network
 int64_t cnn_num_params(int F, int R);
 nqs_status cnn_build_copy(nqs_model *m, int dtype, hipStream_t stream);

@@ -185,6 +185,7 @@ nqs_status nqs_sr_update(nqs_model *m, const int8_t *samples, int64_t n, const d
     if (!m) return set_error(NQS_EINVAL, "NULL model");
     if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
     if (!samples || !y || !master) return set_error(NQS_EINVAL, "NULL samples/y/master");
+    if (m->desc.arch == NQS_CRBM) return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
     hipStream_t s = (hipStream_t)stream;
     const int64_t P = m->P;
     const size_t yb = r256(sizeof(float) * (size_t)n), gb = r256(sizeof(float) * (size_t)P);

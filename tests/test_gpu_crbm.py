@@ -1,0 +1,138 @@
+"""GPU parity of the complex-parameter RBM: the single-flip sampler (FP64
+decision replay, histogram against the enumerated |psi|^2) and complex TFIM
+local energies, against the numpy oracle.  Every call goes through the C
+interface."""
+import numpy as np
+import pytest
+import scipy.stats
+import torch
+
+import oracle
+import workloads
+from oracle import crbm
+from oracle import exact
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def nqs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_20782_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("dtype,N,M,C", [("f32", 12, 24, 10), ("bf16", 12, 24, 10), ("f16", 20, 70, 9),
+                                         ("f32", 30, 130, 5)])
+def test_decisions_replay_in_fp64(nqs, dtype, N, M, C):
+    p = workloads.crbm_params(N, M, 0.2, 0.4, N + M)
+    model = nqs.Model("crbm", N, (M,), p)
+    S, B, T = 4, 2, 3
+    total = (S + B) * N
+    tr = {"n": T,
+          "site": torch.empty(T * total, dtype=torch.int32, device=DEV),
+          "ubits": torch.empty(T * total, dtype=torch.int32, device=DEV),
+          "delta": torch.empty(T * total, dtype=torch.float32, device=DEV),
+          "accepted": torch.empty(T * total, dtype=torch.uint8, device=DEV)}
+    state = torch.empty(C, N, dtype=torch.int8, device=DEV)
+    samples = torch.empty(S, C, N, dtype=torch.int8, device=DEV)
+    logpsi = torch.empty(S, C, dtype=torch.float32, device=DEV)
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=6, dtype=dtype)
+    nqs.nqs_sample(model, cfg, state, samples, logpsi, None, trace=tr)
+    torch.cuda.synchronize()
+    r = {k: tr[k].cpu().numpy().reshape(T, total) for k in ("site", "ubits", "delta", "accepted")}
+    net = crbm.ComplexRBM(N, M, p, dtype)
+    tol = {"f32": 2e-5, "bf16": 2e-5, "f16": 2e-5}[dtype]
+    near, max_err = 0, 0.0
+    for c in range(T):
+        x = oracle.init_chain(N, "flip", 6, c).copy()
+        l0 = net.logpsi(x[None])[0]
+        for k in range(total):
+            rb = oracle.philox([k & 0xFFFFFFFF, k >> 32, c, 0], [6, 0])
+            site = int((int(rb[0]) * N) >> 32)
+            ub = int(rb[2]) >> 8
+            assert (r["site"][c, k] & 0xFFFF) == site and int(r["ubits"][c, k]) == ub
+            y = x.copy()
+            y[site] = -y[site]
+            l1 = net.logpsi(y[None])[0]
+            d = 2.0 * (l1 - l0).real
+            err = abs(float(r["delta"][c, k]) - d)
+            max_err = max(max_err, err / max(1.0, abs(d)))
+            assert err <= tol * max(10.0, abs(d)) * M, (c, k, r["delta"][c, k], d)
+            u = ub * 2.0 ** -24
+            acc = u < np.exp(min(d, 0.0))
+            if bool(r["accepted"][c, k]) != acc:
+                assert abs(np.log(max(u, 1e-300)) - min(d, 0.0)) <= 1e-3
+                near += 1
+            if r["accepted"][c, k]:
+                x, l0 = y, l1
+    # the FP64 log|psi| of the emitted samples
+    lp_ref = net.logamp(samples.cpu().numpy().reshape(-1, N))[0]
+    assert np.max(np.abs(logpsi.cpu().numpy().ravel() - lp_ref) / (1 + np.abs(lp_ref))) < 1e-4
+    _say(f"  {dtype} N={N} M={M}: max relative |dDelta| {max_err:.2e}, {near} near ties")
+
+
+def test_histogram_matches_exact_pi(nqs):
+    N, M = 8, 8
+    p = workloads.crbm_params(N, M, 0.4, 0.6, 3)
+    model = nqs.Model("crbm", N, (M,), p)
+    cfg = nqs.SampleConfig(n_chains=16384, n_sweeps=60, n_burnin=30, seed=2)
+    state = torch.empty(16384, N, dtype=torch.int8, device=DEV)
+    samples = torch.empty(60, 16384, N, dtype=torch.int8, device=DEV)
+    nqs.nqs_sample(model, cfg, state, samples)
+    smp = samples.cpu().numpy()[4::5]
+    lp = crbm.ComplexRBM(N, M, p, "f32").logpsi(exact.all_configs(N))
+    w = np.exp(2 * (lp.real - lp.real.max()))
+    pi = w / w.sum()
+    idx = np.sum((smp.reshape(-1, N) > 0).astype(np.int64) << np.arange(N), axis=1)
+    counts = np.bincount(idx, minlength=2 ** N)
+    e = pi * counts.sum()
+    keep = e > 5
+    chi2 = np.sum((counts[keep] - e[keep]) ** 2 / e[keep])
+    _say(f"  chi2/dof = {chi2 / (keep.sum() - 1):.3f}, TV = {exact.tv(pi, counts / counts.sum()):.4f}, "
+         f"TV to uniform {exact.tv(pi, np.full_like(pi, 1.0 / pi.size)):.3f}")
+    assert scipy.stats.chi2.sf(chi2, keep.sum() - 1) > 1e-5
+    assert exact.tv(pi, counts / counts.sum()) < 0.03 < exact.tv(pi, np.full_like(pi, 1.0 / pi.size))
+
+
+@pytest.mark.parametrize("dim,L,M,J,h", [(1, 12, 24, 1.0, 1.0), (2, 4, 16, -0.5, 2.0), (2, 10, 200, 1.0, 3.04)])
+def test_complex_local_energy_matches_oracle(nqs, dim, L, M, J, h):
+    N = L if dim == 1 else L * L
+    p = workloads.crbm_params(N, M, 0.05, 0.3, 7)
+    model = nqs.Model("crbm", N, (M,), p)
+    x = workloads.random_spins(40, N, 8)
+    re = torch.empty(40, dtype=torch.float64, device=DEV)
+    im = torch.empty(40, dtype=torch.float64, device=DEV)
+    ham = nqs.Hamiltonian("tfim", dim, L, J, h, True)
+    nqs.nqs_local_energy_complex(model, ham, torch.from_numpy(x).to(DEV), re, im)
+    ref = crbm.ComplexRBM(N, M, p, "f32").local_energy_tfim(x, dim, L, J, h)
+    got = re.cpu().numpy() + 1j * im.cpu().numpy()
+    scale = abs(J) * 2 * N + abs(h) * np.abs(ref) + 1.0
+    err = np.max(np.abs(got - ref) / scale)
+    _say(f"  dim={dim} L={L} M={M}: max |d eps| / scale = {err:.2e}")
+    assert err < 1e-4
+    re2 = torch.empty(40, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy(model, ham, torch.from_numpy(x).to(DEV), re2)
+    assert torch.equal(re, re2)
+
+
+def test_phase_state_energy(nqs):
+    """a_i = i pi / 2: every flip ratio is -1, eps = -h N for any sample."""
+    N, M = 16, 4
+    P = N + M + M * N
+    p = np.zeros(2 * P)
+    p[P:P + N] = np.pi / 2
+    model = nqs.Model("crbm", N, (M,), p)
+    x = torch.from_numpy(workloads.random_spins(8, N, 1)).to(DEV)
+    re = torch.empty(8, dtype=torch.float64, device=DEV)
+    im = torch.empty(8, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy_complex(model, nqs.Hamiltonian("tfim", 1, N, 0.0, 0.7, True), x, re, im)
+    assert np.allclose(re.cpu().numpy(), -0.7 * N, atol=1e-5) and np.allclose(im.cpu().numpy(), 0.0, atol=1e-5)
