@@ -35,6 +35,9 @@ Other workloads (--workload):
   rescnn   residual convolutional network: sampling time against samples and
            filters per format on the 4x4 lattice (four blocks), and one sweep
            of 4096 chains on the 10x10 lattice with 16 filters.
+  crbm     complex-parameter RBM on the 10x10 TFIM (M = 200), 4096 chains x
+           (10 + 100) sweeps, beside the real RBM sampler at the same shape;
+           complex local energies of the emitted samples.
 """
 from __future__ import annotations
 
@@ -62,7 +65,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20", "noise", "rescnn"])
+    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20", "noise", "rescnn", "crbm"])
     ap.add_argument("--sweeps", type=int, default=0, help="heis20: measured sweeps per step (default 1)")
     ap.add_argument("--gram-samples", type=int, default=4096, help="heis20: samples in T (0 = skip)")
     ap.add_argument("--gram-chunked", action="store_true", help="heis20: T by parameter column blocks")
@@ -697,6 +700,74 @@ def run_rescnn(a, torch, nqs, workloads):
     }
 
 
+def run_crbm(a, torch, nqs, workloads):
+    """Complex-parameter RBM (App. G with complex a, b, W) on the 10 x 10 periodic TFIM at h/J = 3.04 with
+    200 hidden units: single-flip sampling of 4096 chains against the real RBM sampler at the same shape, and
+    the complex local energies of the emitted samples."""
+    dev = torch.device("cuda:0")
+    N, M, C, S, B = 100, 200, 4096, 100, 10
+    ev = _events(torch, 2)
+    ham = nqs.Hamiltonian("tfim", 2, 10, 1.0, 3.04, True)
+
+    def time_sampling(model, dt, reps):
+        cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=1, dtype=dt)
+        state = torch.empty(C, N, dtype=torch.int8, device=dev)
+        samples = torch.empty(S, C, N, dtype=torch.int8, device=dev)
+        n_acc = torch.empty(C, dtype=torch.int64, device=dev)
+        nqs.nqs_sample(model, cfg, state, samples, None, n_acc)   # warm: copies, first launch
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            nqs.nqs_sample(model, cfg, state, samples, None, n_acc)
+        ev[1].record()
+        torch.cuda.synchronize()
+        acc = float(n_acc.sum().item()) / (C * (S + B) * N)
+        return ev[0].elapsed_time(ev[1]) / reps, samples, acc
+
+    p = workloads.crbm_params(N, M, 0.02, 0.02, 5)
+    model = nqs.Model("crbm", N, (M,), p)
+    res = {dt: time_sampling(model, dt, a.steps) for dt in ("f32", "bf16")}
+    dt = a.dtype if a.dtype in res else "bf16"
+    ms, samples, acc = res[dt]
+    flat = samples.reshape(-1, N)
+    re = torch.empty(flat.shape[0], dtype=torch.float64, device=dev)
+    im = torch.empty_like(re)
+    nqs.nqs_local_energy_complex(model, ham, flat, re, im, eval_dtype=dt)
+    torch.cuda.synchronize()
+    ev[0].record()
+    nqs.nqs_local_energy_complex(model, ham, flat, re, im, eval_dtype=dt)
+    ev[1].record()
+    torch.cuda.synchronize()
+    eloc_ms = ev[0].elapsed_time(ev[1])
+    real = nqs.Model("rbm", N, (M,), p[:N + M + M * N])
+    real_ms, _, real_acc = time_sampling(real, dt, a.steps)
+    model.close()
+    real.close()
+    props = C * (S + B) * N
+    # FP32 flops of the complex product-form single flip, per hidden unit: n = c C - s_i s S (14) with its
+    # squared modulus (3) and the running product (1) on every proposal, plus the s_i S products (2); the
+    # state update s <- s C - s_i c S (16) per accepted proposal; the refresh theta = W s + b (4 N M flops
+    # once per sweep of N proposals).  The lane's one logarithm is not counted.
+    fpp = 20.0 * M + 16.0 * M * acc + 4.0 * M
+    achieved = props * fpp / (ms * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": props / (ms * 1e-3), "unit": "proposals/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dt, "data": "synthetic (seeded random complex RBM weights, N(0, 0.02^2) real and imaginary)",
+        "config": {"workload": "crbm_tfim2d_10x10_a2", "lattice": "10x10 periodic", "J": 1.0, "h": 3.04,
+                   "rbm_hidden": M, "chains": C, "sweeps": S, "burnin": B, "proposals_per_step": props,
+                   "parallelism": "single GPU"},
+        "acceptance": round(acc, 4), "fp32_ms": round(res["f32"][0], 3),
+        "real_rbm_ms": round(real_ms, 3), "real_rbm_acceptance": round(real_acc, 4),
+        "complex_vs_real_time": round(ms / real_ms, 3),
+        "eloc_complex_ms": round(eloc_ms, 3), "eloc_samples": int(flat.shape[0]),
+        "roofline": {"kernel": "crbm_sample_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
+                     "flops_per_proposal": round(fpp, 2), "proposals_per_launch": props},
+    }
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -716,7 +787,7 @@ def main():
     import paper_2601_20782_amd as nqs
     import workloads
     run = {"tfim10": run_tfim10, "heis10": run_heis10, "uneven": run_uneven, "heis20": run_heis20,
-           "noise": run_noise, "rescnn": run_rescnn}[a.workload]
+           "noise": run_noise, "rescnn": run_rescnn, "crbm": run_crbm}[a.workload]
     print(json.dumps(run(a, torch, nqs, workloads)))
 
 

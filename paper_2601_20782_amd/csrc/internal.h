@@ -76,9 +76,10 @@ struct CnnDev {
 struct CrbmDev {
     int N = 0, M = 0;
     float2 *a = nullptr;      // [N]
+    float *a2 = nullptr;      // [N]  4 Re(a_i) / ln 2
     float2 *b = nullptr;      // [M]
     float2 *Wt = nullptr;     // [N][M]  Wt[i][j] = W[j][i]
-    float4 *CS = nullptr;     // [N][M]
+    float4 *CS = nullptr;     // [N][M] + one neutral entry (1, 0, 0, 0) at N*M
     float4 *CSt = nullptr;    // [M][N]
 };
 

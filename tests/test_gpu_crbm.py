@@ -30,9 +30,12 @@ def _say(msg):
     print(msg, flush=True)
 
 
-@pytest.mark.parametrize("dtype,N,M,C", [("f32", 12, 24, 10), ("bf16", 12, 24, 10), ("f16", 20, 70, 9),
-                                         ("f32", 30, 130, 5)])
-def test_decisions_replay_in_fp64(nqs, dtype, N, M, C):
+# (format, N, M, chains, lanes per chain): 16, 32 and 64 lanes per chain, one to
+# seven hidden units per lane, the (C, S) table in LDS and (from 160 KB on) in L2
+@pytest.mark.parametrize("dtype,N,M,C,G", [("f32", 12, 24, 10, 0), ("bf16", 12, 24, 10, 64), ("f16", 20, 70, 9, 0),
+                                           ("f32", 30, 130, 5, 0), ("f32", 100, 110, 4, 0), ("bf16", 40, 300, 4, 0),
+                                           ("f32", 70, 200, 3, 32)])
+def test_decisions_replay_in_fp64(nqs, dtype, N, M, C, G):
     p = workloads.crbm_params(N, M, 0.2, 0.4, N + M)
     model = nqs.Model("crbm", N, (M,), p)
     S, B, T = 4, 2, 3
@@ -45,7 +48,7 @@ def test_decisions_replay_in_fp64(nqs, dtype, N, M, C):
     state = torch.empty(C, N, dtype=torch.int8, device=DEV)
     samples = torch.empty(S, C, N, dtype=torch.int8, device=DEV)
     logpsi = torch.empty(S, C, dtype=torch.float32, device=DEV)
-    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=6, dtype=dtype)
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=6, dtype=dtype, lanes_per_chain=G)
     nqs.nqs_sample(model, cfg, state, samples, logpsi, None, trace=tr)
     torch.cuda.synchronize()
     r = {k: tr[k].cpu().numpy().reshape(T, total) for k in ("site", "ubits", "delta", "accepted")}
@@ -78,6 +81,34 @@ def test_decisions_replay_in_fp64(nqs, dtype, N, M, C):
     lp_ref = net.logamp(samples.cpu().numpy().reshape(-1, N))[0]
     assert np.max(np.abs(logpsi.cpu().numpy().ravel() - lp_ref) / (1 + np.abs(lp_ref))) < 1e-4
     _say(f"  {dtype} N={N} M={M}: max relative |dDelta| {max_err:.2e}, {near} near ties")
+
+
+def test_chain_split_and_resume_are_bit_exact(nqs):
+    """Chains are keyed by their global id and the state between sweeps is the
+    spins alone: half the chains with chain_id_offset, and a run continued from
+    its last state with step_offset, reproduce the one-call samples exactly."""
+    N, M, C, S, B = 36, 72, 64, 6, 4
+    p = workloads.crbm_params(N, M, 0.1, 0.3, 9)
+    model = nqs.Model("crbm", N, (M,), p)
+
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=4, dtype="bf16")
+    state = torch.empty(C, N, dtype=torch.int8, device=DEV)
+    full = torch.empty(S, C, N, dtype=torch.int8, device=DEV)
+    nqs.nqs_sample(model, cfg, state, full)
+    half = C // 2
+    st2 = torch.empty(half, N, dtype=torch.int8, device=DEV)
+    part = torch.empty(S, half, N, dtype=torch.int8, device=DEV)
+    nqs.nqs_sample(model, nqs.SampleConfig(n_chains=half, n_sweeps=S, n_burnin=B, seed=4, dtype="bf16",
+                                           chain_id_offset=half), st2, part)
+    assert torch.equal(part, full[:, half:]) and torch.equal(st2, state[half:])
+    # resume: B + 2 sweeps, then the remaining S - 2 from the saved state
+    st3 = torch.empty(C, N, dtype=torch.int8, device=DEV)
+    first = torch.empty(2, C, N, dtype=torch.int8, device=DEV)
+    nqs.nqs_sample(model, nqs.SampleConfig(n_chains=C, n_sweeps=2, n_burnin=B, seed=4, dtype="bf16"), st3, first)
+    rest = torch.empty(S - 2, C, N, dtype=torch.int8, device=DEV)
+    nqs.nqs_sample(model, nqs.SampleConfig(n_chains=C, n_sweeps=S - 2, n_burnin=0, seed=4, dtype="bf16",
+                                           init_chains=False, step_offset=(B + 2) * N), st3, rest)
+    assert torch.equal(first, full[:2]) and torch.equal(rest, full[2:]) and torch.equal(st3, state)
 
 
 def test_histogram_matches_exact_pi(nqs):
@@ -136,3 +167,24 @@ def test_phase_state_energy(nqs):
     im = torch.empty(8, dtype=torch.float64, device=DEV)
     nqs.nqs_local_energy_complex(model, nqs.Hamiltonian("tfim", 1, N, 0.0, 0.7, True), x, re, im)
     assert np.allclose(re.cpu().numpy(), -0.7 * N, atol=1e-5) and np.allclose(im.cpu().numpy(), 0.0, atol=1e-5)
+
+
+def test_rejections(nqs):
+    N, M = 10, 20
+    model = nqs.Model("crbm", N, (M,), workloads.crbm_params(N, M, 0.1, 0.1, 1))
+    x = torch.from_numpy(workloads.random_spins(4, N, 1)).to(DEV)
+    with pytest.raises(nqs.NqsError):   # log-derivatives of the complex network are not built
+        nqs.nqs_logpsi_grad(model, x, O=torch.empty(4, model.n_params, dtype=torch.float32, device=DEV))
+    with pytest.raises(nqs.NqsError):
+        nqs.nqs_local_energy(model, nqs.Hamiltonian("heisenberg", 1, N, 1.0, 0.0, True), x,
+                             torch.empty(4, dtype=torch.float64, device=DEV))
+    state = torch.empty(4, N, dtype=torch.int8, device=DEV)
+    with pytest.raises(nqs.NqsError):
+        nqs.nqs_sample(model, nqs.SampleConfig(n_chains=4, n_sweeps=1, dtype="e4m3"), state)
+    with pytest.raises(nqs.NqsError):
+        nqs.nqs_sample(model, nqs.SampleConfig(n_chains=4, n_sweeps=1, lanes_per_chain=8), state)
+    with pytest.raises(nqs.NqsError):
+        nqs.nqs_sample(model, nqs.SampleConfig(n_chains=4, n_sweeps=1, move="exchange"), state)
+    wide = nqs.Model("crbm", N, (600,), workloads.crbm_params(N, 600, 0.1, 0.1, 1))
+    with pytest.raises(nqs.NqsError):   # more than 8 hidden units per lane at 64 lanes
+        nqs.nqs_sample(wide, nqs.SampleConfig(n_chains=4, n_sweeps=1), state)
