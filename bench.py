@@ -282,8 +282,22 @@ def _sr_step(nqs, torch, step, shift=1e-2, lr=1e-2):
     nqs.nqs_sr_update(step.model, step.samples[S - 1], y, lr, master)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    # the same solve preconditioned by a Cholesky factor in a reduced format, refined in FP64
+    mixed = {}
+    ym = torch.empty_like(y)
+    ref = y.abs().max().item()
+    for fmt in ("f32", "bf16", "f16"):
+        nqs.nqs_sr_solve_mixed(step.T, eps, shift, ym, fmt, tol=1e-8, max_iter=2000)   # warm the workspace
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        mits, mrr, fixed, used = nqs.nqs_sr_solve_mixed(step.T, eps, shift, ym, fmt, tol=1e-8, max_iter=2000)
+        t4 = time.perf_counter()
+        mixed[fmt] = {"ms": round(1e3 * (t4 - t3), 3), "factor_used": used, "iterations": mits,
+                      "rel_residual": mrr, "pivots_replaced": fixed,
+                      "max_rel_diff_vs_cg": (ym - y).abs().max().item() / ref}
     return {"samples": C, "shift": shift, "tol": 1e-8, "cg_iterations": its, "rel_residual": rr,
             "solve_ms": round(1e3 * (t1 - t0), 3), "update_ms": round(1e3 * (t2 - t1), 3),
+            "mixed_solve": mixed,
             "note": "outside the timed step; T from the step's factored Gram phase"}
 
 
@@ -341,6 +355,7 @@ def run_heis10(a, torch, nqs, workloads):
                        "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
                        "flops_per_proposal": fpp, "proposals_per_launch": props}
+    out["sr_step"] = _sr_step(nqs, torch, step)
     if not a.no_compare:
         out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, a.dtype, True, others=("f16",)))
     if not a.no_cpu_baseline:

@@ -25,6 +25,8 @@
  *   nqs_sr_solve / nqs_sr_update  the stochastic-reconfiguration step in
  *                      sample space: (T + shift) y = eps - mean eps, then
  *                      master -= lr O^T (y - mean y) / n (App. I.2)
+ *   nqs_sr_solve_mixed the same solve preconditioned by a Cholesky factor
+ *                      computed in a reduced format, refined in FP64 (Sec. V)
  *
  * Conventions (every entry point):
  *   - All array arguments are DEVICE pointers unless marked "host".  The
@@ -307,6 +309,32 @@ nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double sh
                         double *y, int32_t *iters, double *rel_resid, void *stream);
 nqs_status nqs_sr_update(nqs_model *m, const int8_t *samples, int64_t n, const double *y, double lr, double *master,
                          void *stream);
+
+/* The same y[n] by mixed precision (Sec. V points to mixed-precision
+ * iterative solvers for the preconditioning step; App. I.2 on why its
+ * accuracy matters: errors are amplified by the condition number of S).
+ * T + shift is factorised L L^T in `factor_dtype` (NQS_F32, NQS_BF16 or
+ * NQS_F16: the operands of the blocked trailing updates and of the inverse's
+ * products are rounded to the format on the matrix cores, with FP32
+ * accumulation; diagonal blocks and panels FP32), L^{-1} is formed the same
+ * way, and conjugate gradients in FP64 preconditioned by L^{-T} L^{-1} run
+ * until ||r|| <= tol ||b|| or max_iter iterations.  The preconditioner is
+ * symmetric positive definite whatever the rounding, so the result is the
+ * FP64 solution; the format sets the iteration count.  A pivot not larger than
+ * the format's unit round-off times its original diagonal entry (T + shift
+ * not positive definite at that precision) is replaced by that entry and
+ * counted in *n_pivots_fixed (host pointer, may be NULL).  If a BF16/FP16
+ * factorisation replaces more than n / 8 pivots, or its preconditioned
+ * residual is not a positive finite number (the factor's inverse overflowed),
+ * the solve is redone with an FP32 factor, and failing that with the Jacobi
+ * preconditioner of nqs_sr_solve; *factor_used (host, may be NULL) reports
+ * the factor format that produced y, or -1 for Jacobi.  n <= 65536;
+ * workspace 2 np^2 floats, np = n rounded up to 64.  Synchronises `stream`;
+ * *iters, *rel_resid as for nqs_sr_solve, for the attempt that produced y.
+ * Deterministic. */
+nqs_status nqs_sr_solve_mixed(const float *T, const double *eloc, int64_t n, double shift, int32_t factor_dtype,
+                              double tol, int32_t max_iter, double *y, int32_t *iters, double *rel_resid,
+                              int64_t *n_pivots_fixed, int32_t *factor_used, void *stream);
 
 const char *nqs_last_error(void);
 const char *nqs_version(void);

@@ -22,7 +22,7 @@ from ._abi import DTYPE_CODES, NqsError, check, load
 __all__ = [
     "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
     "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
-    "nqs_sr_solve", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
+    "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
 ]
 
 
@@ -298,6 +298,25 @@ def nqs_sr_solve(T: torch.Tensor, eloc: torch.Tensor, shift: float, y: torch.Ten
     check(load().nqs_sr_solve(_ptr(T), _ptr(eloc), n, float(shift), float(tol), int(max_iter), _ptr(y),
                               ctypes.byref(it), ctypes.byref(rr), _stream(stream)))
     return it.value, rr.value
+
+
+def nqs_sr_solve_mixed(T: torch.Tensor, eloc: torch.Tensor, shift: float, y: torch.Tensor, factor_dtype="bf16",
+                       tol: float = 1e-10, max_iter: int = 1000, stream=None):
+    """The same solve, preconditioned by a Cholesky factor computed in `factor_dtype`;
+    returns (iterations, relative residual, replaced pivots, format used: a dtype
+    name, or "jacobi")."""
+    n = eloc.numel()
+    assert T.dtype == torch.float32 and T.numel() == n * n
+    assert eloc.dtype == torch.float64 and y.dtype == torch.float64 and y.numel() == n
+    it = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    nf = ctypes.c_int64(0)
+    fu = ctypes.c_int32(0)
+    check(load().nqs_sr_solve_mixed(_ptr(T), _ptr(eloc), n, float(shift), _dtype(factor_dtype), float(tol),
+                                    int(max_iter), _ptr(y), ctypes.byref(it), ctypes.byref(rr), ctypes.byref(nf),
+                                    ctypes.byref(fu), _stream(stream)))
+    names = {v: k for k, v in DTYPE_CODES.items()}
+    return it.value, rr.value, nf.value, names.get(fu.value, "jacobi")
 
 
 def nqs_sr_update(model: Model, samples: torch.Tensor, y: torch.Tensor, lr: float, master: torch.Tensor,

@@ -130,6 +130,10 @@ void *workspace(size_t bytes, hipStream_t stream);
 // (which use slot 0).
 constexpr int kWorkspaceSlots = 2;
 void *workspace_slot(int slot, size_t bytes, hipStream_t stream);
+// low-precision Cholesky factor of T + shift and its inverse (srmix.hip)
+size_t mix_workspace_bytes(int64_t n);
+nqs_status mix_factor(const float *T, int64_t n, double shift, int fmt, void *ws, float **Lin, float **LinT,
+                      int64_t *np_out, unsigned long long *nfix, hipStream_t s);
 
 int64_t model_num_params(const nqs_model_desc &d);
 

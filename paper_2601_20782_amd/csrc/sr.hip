@@ -45,22 +45,25 @@ __global__ void __launch_bounds__(kSumThreads) sr_dot_kernel(const double *__res
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
-// Ap = (T + shift) p, one wave per row
-__global__ void __launch_bounds__(256) sr_matvec_kernel(const float *__restrict__ T, const double *__restrict__ p,
-                                                        int64_t n, double shift, double *__restrict__ Ap)
+// Ap = (T + shift) p, one wave per row, T with leading dimension ld; over
+// columns k < n (mode 0), k <= row (1: lower triangle) or k >= row (2: upper)
+__global__ void __launch_bounds__(256) sr_matvec_kernel(const float *__restrict__ T, int64_t ld,
+                                                        const double *__restrict__ p, int64_t n, double shift,
+                                                        int mode, double *__restrict__ Ap)
 {
     const int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
-    const float *t = T + row * n;
+    const float *t = T + row * ld;
+    const int64_t lo = mode == 2 ? row : 0, hi = mode == 1 ? row + 1 : n;
     double s = 0.0;
-    for (int64_t k = lane; k < n; k += 64) s = fma((double)t[k], p[k], s);
+    for (int64_t k = lo + lane; k < hi; k += 64) s = fma((double)t[k], p[k], s);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0) Ap[row] = s + shift * p[row];
 }
 
-// b = eps - mean (sum[0] = sum of eps); d = diag(T) + shift; x = 0, r = b, z = r / d, p = z
+// b = eps - mean (sum[0] = sum of eps); x = 0, r = b; with d: d = 1 / (diag(T) + shift), z = r d, p = z
 __global__ void sr_init_kernel(const float *__restrict__ T, const double *__restrict__ eps,
                                const double *__restrict__ sum, int64_t n, double shift, double *__restrict__ d,
                                double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
@@ -69,16 +72,17 @@ __global__ void sr_init_kernel(const float *__restrict__ T, const double *__rest
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     const double b = eps[k] - sum[0] / (double)n;
+    x[k] = 0.0;
+    r[k] = b;
+    if (!d) return;   // z and p are set by the caller's preconditioner
     const double dk = (double)T[k * n + k] + shift;
     const double inv = dk > 0.0 ? 1.0 / dk : 1.0;
     d[k] = inv;
-    x[k] = 0.0;
-    r[k] = b;
     z[k] = b * inv;
     p[k] = b * inv;
 }
 
-// alpha = rz / pAp;  x += alpha p;  r -= alpha Ap;  z = r / d
+// alpha = rz / pAp;  x += alpha p;  r -= alpha Ap;  with d: z = r d
 __global__ void sr_step_kernel(const double *__restrict__ rz, const double *__restrict__ pap, int64_t n,
                                const double *__restrict__ d, const double *__restrict__ p,
                                const double *__restrict__ Ap, double *__restrict__ x, double *__restrict__ r,
@@ -90,7 +94,7 @@ __global__ void sr_step_kernel(const double *__restrict__ rz, const double *__re
     x[k] = fma(alpha, p[k], x[k]);
     const double rk = fma(-alpha, Ap[k], r[k]);
     r[k] = rk;
-    z[k] = rk * d[k];
+    if (d) z[k] = rk * d[k];
 }
 
 // p = z + (rz_new / rz_old) p
@@ -157,7 +161,7 @@ nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double sh
     if (bb > 0.0) {
         rel = 1.0;
         while (k < max_iter) {
-            hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, T, p, n, shift, Ap);
+            hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, T, n, p, n, shift, 0, Ap);
             hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, p, Ap, n, pap + k);
             hipLaunchKernelGGL(sr_step_kernel, dim3(eb), dim3(256), 0, s, rz + k, pap + k, n, d, p, Ap, y, r, z);
             hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, z, n, rz + k + 1);
@@ -176,6 +180,115 @@ nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double sh
     }
     if (iters) *iters = k;
     if (rel_resid) *rel_resid = rel;
+    return NQS_OK;
+}
+
+nqs_status nqs_sr_solve_mixed(const float *T, const double *eloc, int64_t n, double shift, int32_t factor_dtype,
+                              double tol, int32_t max_iter, double *y, int32_t *iters, double *rel_resid,
+                              int64_t *n_pivots_fixed, int32_t *factor_used, void *stream)
+{
+    if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
+    if (n > 65536) return set_error(NQS_EINVAL, "n must be at most 65536 (two n x n FP32 factors are formed)");
+    if (!T || !eloc || !y) return set_error(NQS_EINVAL, "NULL T/eloc/y");
+    if (!(shift >= 0.0) || !(tol > 0.0) || max_iter < 1) return set_error(NQS_EINVAL, "need shift >= 0, tol > 0, max_iter >= 1");
+    if (factor_dtype != NQS_F32 && factor_dtype != NQS_BF16 && factor_dtype != NQS_F16)
+        return set_error(NQS_EINVAL, "factor dtype must be F32, BF16 or F16");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t fac = r256(mix_workspace_bytes(n));
+    const size_t vec = r256(sizeof(double) * (size_t)n);
+    const size_t nsc = (size_t)max_iter + 2;
+    char *ws = (char *)workspace_slot(1, fac + 6 * vec + 3 * r256(sizeof(double) * nsc) + 256, s);
+    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    char *v = ws + fac;
+    double *r = (double *)v, *z = (double *)(v + vec), *p = (double *)(v + 2 * vec), *Ap = (double *)(v + 3 * vec),
+           *u = (double *)(v + 4 * vec), *d = (double *)(v + 5 * vec);
+    double *rz = (double *)(v + 6 * vec);
+    double *pap = rz + r256(sizeof(double) * nsc) / sizeof(double);
+    double *misc = pap + r256(sizeof(double) * nsc) / sizeof(double);   // [0] sum of eps, [1] b.b, [2] r.r, [3] pivots
+    unsigned long long *nfix = (unsigned long long *)(misc + 3);
+    const unsigned eb = (unsigned)((n + 255) / 256), mb = (unsigned)((n + 3) / 4);
+
+    // Attempts: the requested format, then an FP32 factor, then the Jacobi
+    // preconditioner (-1).  A reduced-precision factor that had to replace
+    // more than n / 8 pivots (T + shift is too ill-conditioned for the
+    // format) is not used; an attempt whose preconditioned residual is not a
+    // positive finite number, or whose iteration turns non-finite, is
+    // abandoned for the next one.
+    int fmts[3] = {factor_dtype, NQS_F32, -1};
+    const int nf = factor_dtype == NQS_F32 ? 2 : 3;
+    if (factor_dtype == NQS_F32) fmts[1] = -1;
+    double rel = 0.0;
+    int k = 0;
+    unsigned long long fixed_total = 0;
+    int used = -1;
+    for (int att = 0; att < nf; ++att) {
+        const int fmt = fmts[att];
+        float *Lin = nullptr, *LinT = nullptr;
+        int64_t np = 0;
+        if (fmt >= 0) {
+            nqs_status st = launch_zero_u64(nfix, 1, s);
+            if (st != NQS_OK) return st;
+            st = mix_factor(T, n, shift, fmt, ws, &Lin, &LinT, &np, nfix, s);
+            if (st != NQS_OK) return st;
+            unsigned long long fixed = 0;
+            NQS_HIP_TRY(hipMemcpyAsync(&fixed, nfix, sizeof(fixed), hipMemcpyDeviceToHost, s));
+            NQS_HIP_TRY(hipStreamSynchronize(s));
+            fixed_total = fixed;
+            if (fmt != NQS_F32 && fixed > (unsigned long long)(n / 8)) continue;
+        }
+        // z = M^{-1} r: L^{-T} (L^{-1} r), or r / diag with the Jacobi preconditioner
+        auto precond = [&]() {
+            hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, (const float *)Lin, np,
+                               (const double *)r, n, 0.0, 1, u);
+            hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, (const float *)LinT, np,
+                               (const double *)u, n, 0.0, 2, z);
+        };
+        double *dj = fmt >= 0 ? nullptr : d;
+        hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, eloc, (const double *)nullptr, n, misc);
+        hipLaunchKernelGGL(sr_init_kernel, dim3(eb), dim3(256), 0, s, T, eloc, misc, n, shift, dj, y, r, z, p);
+        hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, r, n, misc + 1);
+        if (fmt >= 0) {
+            precond();
+            NQS_HIP_TRY(hipMemcpyAsync(p, z, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        }
+        hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, z, n, rz);
+        NQS_HIP_TRY(hipGetLastError());
+        double bb = 0.0, rz0 = 0.0;
+        NQS_HIP_TRY(hipMemcpyAsync(&bb, misc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        NQS_HIP_TRY(hipMemcpyAsync(&rz0, rz, sizeof(double), hipMemcpyDeviceToHost, s));
+        NQS_HIP_TRY(hipStreamSynchronize(s));
+        rel = 0.0;
+        k = 0;
+        used = fmt;
+        if (!(bb > 0.0)) break;
+        if (!(rz0 > 0.0) || !std::isfinite(rz0)) continue;   // preconditioner unusable
+        rel = 1.0;
+        while (k < max_iter) {
+            hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, T, n, (const double *)p, n, shift, 0, Ap);
+            hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, p, Ap, n, pap + k);
+            hipLaunchKernelGGL(sr_step_kernel, dim3(eb), dim3(256), 0, s, rz + k, pap + k, n, (const double *)dj, p,
+                               Ap, y, r, z);
+            if (fmt >= 0) precond();
+            hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, z, n, rz + k + 1);
+            hipLaunchKernelGGL(sr_dir_kernel, dim3(eb), dim3(256), 0, s, rz + k, rz + k + 1, n, z, p);
+            ++k;
+            // a good factor converges in a few iterations: check every iteration
+            if (fmt >= 0 || k % kCheck == 0 || k == max_iter) {
+                hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, r, n, misc + 2);
+                NQS_HIP_TRY(hipGetLastError());
+                double rr = 0.0;
+                NQS_HIP_TRY(hipMemcpyAsync(&rr, misc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+                NQS_HIP_TRY(hipStreamSynchronize(s));
+                rel = std::sqrt(rr / bb);
+                if (!(rel > tol)) break;   // converged, or NaN
+            }
+        }
+        if (std::isfinite(rel)) break;
+    }
+    if (iters) *iters = k;
+    if (rel_resid) *rel_resid = rel;
+    if (n_pivots_fixed) *n_pivots_fixed = (int64_t)fixed_total;
+    if (factor_used) *factor_used = used;
     return NQS_OK;
 }
 

@@ -34,8 +34,7 @@ def _say(msg):
 def test_sr_solve_matches_dense_solve(nqs, n, P, shift):
     rng = np.random.default_rng(n + P)
     O = (rng.normal(size=(n, P)) + rng.normal(size=P)).astype(np.float32)
-    T = torch.empty(n, n, dtype=torch.float32, device=DEV)
-    nqs.nqs_gram(torch.from_numpy(O).to(DEV), 1, T)
+    T = torch.from_numpy(oracle.tmatrix(O).astype(np.float32)).to(DEV)
     eps = rng.normal(-3.0, 1.5, size=n)
     y = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
     its, rr = nqs.nqs_sr_solve(T, torch.from_numpy(eps).to(DEV), shift, y, tol=1e-12, max_iter=2000)
@@ -59,8 +58,7 @@ def test_sr_solve_reports_the_iteration_cap(nqs):
     n = 256
     rng = np.random.default_rng(1)
     O = rng.normal(size=(n, 400)).astype(np.float32)
-    T = torch.empty(n, n, dtype=torch.float32, device=DEV)
-    nqs.nqs_gram(torch.from_numpy(O).to(DEV), 1, T)
+    T = torch.from_numpy(oracle.tmatrix(O).astype(np.float32)).to(DEV)
     y = torch.empty(n, dtype=torch.float64, device=DEV)
     its, rr = nqs.nqs_sr_solve(T, torch.from_numpy(rng.normal(size=n)).to(DEV), 1e-4, y, tol=1e-14, max_iter=3)
     assert its == 3 and 0.0 < rr < 1.0
