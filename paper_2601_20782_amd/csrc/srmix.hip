@@ -16,16 +16,19 @@
 // T + shift, extended by the identity), FP32 row-major with leading
 // dimension np, in 64 x 64 tiles.  Blocked right-looking Cholesky, per block
 // column k:
-//   mix_potrf_kernel   one wave: L_kk and D_k = L_kk^{-1} (FP32, registers + LDS)
-//   mix_panel_kernel   L_Ik = A_Ik D_k^T for I > k (FP32)
+//   mix_potrf_kernel   L_kk and D_k = L_kk^{-1} (FP32, tile in LDS)
+//   mix_panel_kernel   L_Ik = A_Ik D_k^T for I > k (FP32 matrix cores)
 //   mix_update_kernel  A_IJ -= L_Ik L_Jk^T for k < J <= I: the O(n^3) part, on
 //                      the matrix cores with operands rounded to the format
-//                      (16x16x16 BF16/FP16 or 16x16x4 FP32), FP32 accumulation
-// then the inverse row by row (mix_linv_kernel):
-//   Linv_II = D_I,  Linv_IJ = -D_I sum_{K=J}^{I-1} L_IK Linv_KJ   (J < I)
-// written to B (lower tiles) and transposed into A's upper tiles (the L
-// tiles there are dead by then), so both triangular products of the
-// preconditioner read rows.  A pivot that is not larger than the format's
+//                      (16x16x16 BF16/FP16 or 16x16x4 FP32), FP32 accumulation;
+//                      columns outside the current group of four block columns
+//                      take the group's four updates in one pass
+// then L^{-1} by recursive doubling: with groups of s diagonal tiles inverted,
+// adjacent groups join as [[L11, 0], [L21, L22]]^{-1} = [[Linv11, 0],
+// [-Linv22 L21 Linv11, Linv22]] (two batched tile products per doubling,
+// operands in the format), into B's lower tiles; finally the transpose into
+// A's upper tiles (the L tiles there are dead by then), so both triangular
+// products of the preconditioner read rows.  Tile operands are staged in LDS.  A pivot that is not larger than the format's
 // unit round-off times the original diagonal entry is replaced by that
 // entry (counted), which keeps L's diagonal positive.
 #include <hip/hip_runtime.h>
@@ -39,6 +42,7 @@
 namespace nqs {
 
 constexpr int kMixNb = 64;
+constexpr int kMixGroup = 4;   // block columns per trailing update
 
 typedef short mix_s16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 mix_h16x4 __attribute__((ext_vector_type(4)));
@@ -58,85 +62,87 @@ __global__ void mix_build_kernel(const float *__restrict__ T, int64_t n, int64_t
     if (i == j) dg[i] = v;
 }
 
-// Cholesky of the diagonal tile k (one wave, lane i holds row i) and its inverse
-__global__ void __launch_bounds__(64) mix_potrf_kernel(float *__restrict__ A, int64_t np, int k,
-                                                       const float *__restrict__ dg, float eps,
-                                                       float *__restrict__ Dinv,
-                                                       unsigned long long *__restrict__ nfix)
+constexpr int kMixLd = kMixNb + 4;   // LDS row stride (floats): rows stay 16-byte aligned
+
+// stage a 64 x 64 FP32 tile (row-major, leading dimension ld) into LDS with float4 loads (256 threads)
+__device__ __forceinline__ void mix_stage(float (*S)[kMixLd], const float *__restrict__ src, int64_t ld)
 {
-    __shared__ float col[kMixNb];
-    __shared__ float Ls[kMixNb][kMixNb + 1];
-    const int i = threadIdx.x;
-    float *blk = A + (int64_t)k * kMixNb * np + (int64_t)k * kMixNb;
-    float r[kMixNb];
-#pragma unroll
-    for (int m = 0; m < kMixNb; ++m) r[m] = blk[(int64_t)i * np + m];
-    unsigned fixes = 0;
-#pragma unroll
-    for (int j = 0; j < kMixNb; ++j) {
-        float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r[j]), j));
-        const float d0 = dg[(int64_t)k * kMixNb + j];
-        if (!(d > eps * fabsf(d0))) {   // also catches NaN
-            d = fabsf(d0) > 0.0f ? fabsf(d0) : 1.0f;
-            ++fixes;
-        }
-        const float ljj = sqrtf(d);
-        const float lij = i == j ? ljj : r[j] / ljj;
-        r[j] = lij;
-        col[i] = lij;
-        __syncthreads();
-#pragma unroll
-        for (int m = j + 1; m < kMixNb; ++m) r[m] = fmaf(-lij, col[m], r[m]);
-        __syncthreads();
+    for (int e = threadIdx.x; e < kMixNb * kMixNb / 4; e += 256) {
+        const int row = e >> 4, c4 = (e & 15) << 2;
+        *reinterpret_cast<float4 *>(&S[row][c4]) = *reinterpret_cast<const float4 *>(src + (int64_t)row * ld + c4);
     }
-    // L into LDS (lower part), then lane c forms column c of L^{-1} by forward substitution
-#pragma unroll
-    for (int m = 0; m < kMixNb; ++m) Ls[i][m] = m <= i ? r[m] : 0.0f;
-    __syncthreads();
-    const int c = i;
-    float x[kMixNb];
-#pragma unroll
-    for (int q = 0; q < kMixNb; ++q) {
-        float s = q == c ? 1.0f : 0.0f;
-#pragma unroll
-        for (int m = 0; m < q; ++m) s = fmaf(-Ls[q][m], x[m], s);
-        x[q] = s / Ls[q][q];
-    }
-    float *D = Dinv + (int64_t)k * kMixNb * kMixNb;
-#pragma unroll
-    for (int q = 0; q < kMixNb; ++q) D[q * kMixNb + c] = x[q];   // rows q < c hold 0
-    // L_kk back into A (lower triangle, zero above), coalesced along rows
-    for (int q = 0; q < kMixNb; ++q) blk[(int64_t)q * np + i] = Ls[q][i];
-    if (i == 0 && fixes) atomicAdd(nfix, (unsigned long long)fixes);
 }
 
-// L_Ik = A_Ik D_k^T for the block rows I = k + 1 + blockIdx.x (FP32)
-__global__ void __launch_bounds__(256) mix_panel_kernel(float *__restrict__ A, int64_t np, int k,
-                                                        const float *__restrict__ Dinv)
+// Cholesky of the diagonal tile k and its inverse D_k (256 threads).  Thread
+// (wave w, lane m) keeps the entries (w + 4 r, m), r < 16, in registers.  Per
+// column j the owners of column j publish it through LDS (double-buffered, so
+// one barrier per column); every thread derives the same pivot from it and
+// applies the scaling and the rank-1 update to its own entries by selects.
+__global__ void __launch_bounds__(256) mix_potrf_kernel(float *__restrict__ A, int64_t np, int k,
+                                                        const float *__restrict__ dg, float eps,
+                                                        float *__restrict__ Dinv,
+                                                        unsigned long long *__restrict__ nfix)
 {
-    __shared__ float As[kMixNb][kMixNb + 1];
-    __shared__ float Ds[kMixNb][kMixNb + 1];
-    const int I = k + 1 + blockIdx.x;
-    float *blk = A + (int64_t)I * kMixNb * np + (int64_t)k * kMixNb;
-    const float *D = Dinv + (int64_t)k * kMixNb * kMixNb;
-    for (int e = threadIdx.x; e < kMixNb * kMixNb; e += 256) {
-        const int q = e >> 6, m = e & 63;
-        As[q][m] = blk[(int64_t)q * np + m];
-        Ds[q][m] = D[e];
+    __shared__ float S[kMixNb][kMixLd];
+    __shared__ float col[2][kMixNb], rinv[kMixNb], d0s[kMixNb];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float *blk = A + (int64_t)k * kMixNb * np + (int64_t)k * kMixNb;
+    float reg[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) reg[r] = blk[(int64_t)(wave + 4 * r) * np + lane];
+    if (tid < kMixNb) d0s[tid] = dg[(int64_t)k * kMixNb + tid];
+    unsigned fixes = 0;
+    for (int j = 0; j < kMixNb; ++j) {
+        float *cj = col[j & 1];
+        if (lane == j) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) cj[wave + 4 * r] = reg[r];
+        }
+        __syncthreads();
+        float d = cj[j];
+        const float d0 = d0s[j];
+        const bool fix = !(d > eps * fabsf(d0));   // also catches NaN
+        if (fix) d = fabsf(d0) > 0.0f ? fabsf(d0) : 1.0f;
+        fixes += fix ? 1u : 0u;
+        const float l = sqrtf(d), ri = 1.0f / l;
+        if (tid == 0) rinv[j] = ri;
+        const float lm = cj[lane] * ri;               // L[lane][j] for lane > j
+        const bool upd = lane > j, own = lane == j;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = wave + 4 * r;
+            const float li = cj[i] * ri;              // L[i][j]
+            const float u = fmaf(-li, lm, reg[r]);
+            const float o = i > j ? reg[r] * ri : (i == j ? l : reg[r]);
+            reg[r] = upd && i >= lane ? u : (own ? o : reg[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = wave + 4 * r;
+        const float v = i >= lane ? reg[r] : 0.0f;
+        S[lane][i] = v;   // S holds L^T: row q of S is column q of L
+        blk[(int64_t)i * np + lane] = v;
     }
     __syncthreads();
-    // out[q][c] = sum_{m <= c} A[q][m] D[c][m]; thread: column c, rows q = rg, rg + 4, ...
-    const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
-    float acc[16];
+    // wave 0: lane c forms column c of L^{-1}, column-oriented: once x[q] is
+    // known, the partial sums of the later rows take x[q] times column q of L
+    if (wave == 0) {
+        const int c = lane;
+        float x[kMixNb];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t] = 0.0f;
-    for (int m = 0; m <= c; ++m) {
-        const float dv = Ds[c][m];
+        for (int q = 0; q < kMixNb; ++q) x[q] = q == c ? 1.0f : 0.0f;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = fmaf(As[rg + 4 * t][m], dv, acc[t]);
+        for (int q = 0; q < kMixNb; ++q) {
+            x[q] *= rinv[q];
+#pragma unroll
+            for (int qq = q + 1; qq < kMixNb; ++qq) x[qq] = fmaf(-S[q][qq], x[q], x[qq]);
+        }
+        float *D = Dinv + (int64_t)k * kMixNb * kMixNb;
+#pragma unroll
+        for (int q = 0; q < kMixNb; ++q) D[q * kMixNb + c] = x[q];   // rows q < c hold 0
     }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) blk[(int64_t)(rg + 4 * t) * np + c] = acc[t];
+    if (tid == 0 && fixes) atomicAdd(nfix, (unsigned long long)fixes);
 }
 
 // round-to-nearest-even codes of the 16-bit formats
@@ -151,21 +157,33 @@ __device__ __forceinline__ short mix_f16(float v)
     const _Float16 h = (_Float16)v;
     return __builtin_bit_cast(short, h);
 }
+template <int FMT>
+__device__ __forceinline__ mix_s16x4 mix_enc4(float a, float b, float c, float d)
+{
+    mix_s16x4 r;
+    r[0] = FMT == kBF16 ? mix_bf16(a) : mix_f16(a);
+    r[1] = FMT == kBF16 ? mix_bf16(b) : mix_f16(b);
+    r[2] = FMT == kBF16 ? mix_bf16(c) : mix_f16(c);
+    r[3] = FMT == kBF16 ? mix_bf16(d) : mix_f16(d);
+    return r;
+}
 
-// acc[x][y] (16 x 16 blocks x, y of the wave's 32 x 32 quadrant) += sum over
-// kd of fa(i, kk) fb(kk, j), operands rounded to the format; block (x, y)
-// element [4 (lane / 16) + r][lane % 16] sits in acc[x][y][r].
-template <int FMT, class FA, class FB>
-__device__ __forceinline__ void mix_mma(mix_f32x4 (&acc)[2][2], int kd, FA fa, FB fb)
+// acc[x][y] += sum_{kk < 64} As[32 wm + 16 x + i][kk] Bop[kk][32 wn + 16 y + j] for the
+// wave's 32 x 32 quadrant (wm, wn), Bop[kk][j] = BT ? Bs[j][kk] : Bs[kk][j]; operands
+// rounded to the format; block (x, y) element [4 (lane / 16) + r][lane % 16] in acc[x][y][r]
+template <int FMT, bool BT>
+__device__ __forceinline__ void mix_mma_lds(mix_f32x4 (&acc)[2][2], const float (*As)[kMixLd],
+                                            const float (*Bs)[kMixLd], int wm, int wn)
 {
     const int lane = threadIdx.x & 63, la = lane & 15, lk = lane >> 4;
     if constexpr (FMT == kF32) {
-        for (int k0 = 0; k0 < kd; k0 += 4) {
+#pragma unroll 4
+        for (int k0 = 0; k0 < kMixNb; k0 += 4) {
             float a[2], b[2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-                a[x] = fa(16 * x + la, k0 + lk);
-                b[x] = fb(k0 + lk, 16 * x + la);
+                a[x] = As[32 * wm + 16 * x + la][k0 + lk];
+                b[x] = BT ? Bs[32 * wn + 16 * x + la][k0 + lk] : Bs[k0 + lk][32 * wn + 16 * x + la];
             }
 #pragma unroll
             for (int x = 0; x < 2; ++x)
@@ -173,16 +191,22 @@ __device__ __forceinline__ void mix_mma(mix_f32x4 (&acc)[2][2], int kd, FA fa, F
                 for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
         }
     } else {
-        for (int k0 = 0; k0 < kd; k0 += 16) {
+#pragma unroll
+        for (int k0 = 0; k0 < kMixNb; k0 += 16) {
             mix_s16x4 a[2], b[2];
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float av = fa(16 * x + la, k0 + 4 * lk + q), bv = fb(k0 + 4 * lk + q, 16 * x + la);
-                    a[x][q] = FMT == kBF16 ? mix_bf16(av) : mix_f16(av);
-                    b[x][q] = FMT == kBF16 ? mix_bf16(bv) : mix_f16(bv);
+            for (int x = 0; x < 2; ++x) {
+                const float4 av = *reinterpret_cast<const float4 *>(&As[32 * wm + 16 * x + la][k0 + 4 * lk]);
+                a[x] = mix_enc4<FMT>(av.x, av.y, av.z, av.w);
+                const int jj = 32 * wn + 16 * x + la;
+                if constexpr (BT) {
+                    const float4 bv = *reinterpret_cast<const float4 *>(&Bs[jj][k0 + 4 * lk]);
+                    b[x] = mix_enc4<FMT>(bv.x, bv.y, bv.z, bv.w);
+                } else {
+                    const int kk = k0 + 4 * lk;
+                    b[x] = mix_enc4<FMT>(Bs[kk][jj], Bs[kk + 1][jj], Bs[kk + 2][jj], Bs[kk + 3][jj]);
                 }
+            }
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -198,6 +222,36 @@ __device__ __forceinline__ void mix_mma(mix_f32x4 (&acc)[2][2], int kd, FA fa, F
     }
 }
 
+// element (ii, jj) of the workgroup's 64 x 64 output held by this thread: f(ii, jj, value)
+template <class F>
+__device__ __forceinline__ void mix_store(const mix_f32x4 (&acc)[2][2], int wm, int wn, F f)
+{
+    const int lane = threadIdx.x & 63, la = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) f(32 * wm + 16 * x + 4 * lk + q, 32 * wn + 16 * y + la, acc[x][y][q]);
+}
+
+// L_Ik = A_Ik D_k^T for the block rows I = k + 1 + blockIdx.x (FP32 matrix cores)
+__global__ void __launch_bounds__(256) mix_panel_kernel(float *__restrict__ A, int64_t np, int k,
+                                                        const float *__restrict__ Dinv)
+{
+    __shared__ float As[kMixNb][kMixLd];
+    __shared__ float Ds[kMixNb][kMixLd];
+    const int I = k + 1 + blockIdx.x;
+    float *blk = A + (int64_t)I * kMixNb * np + (int64_t)k * kMixNb;
+    mix_stage(As, blk, np);
+    mix_stage(Ds, Dinv + (int64_t)k * kMixNb * kMixNb, kMixNb);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    mix_f32x4 acc[2][2] = {};
+    mix_mma_lds<kF32, true>(acc, As, Ds, wm, wn);
+    mix_store(acc, wm, wn, [&](int ii, int jj, float v) { blk[(int64_t)ii * np + jj] = v; });
+}
+
 // lower-triangular tile pair t -> (r, c), r >= c, t = r (r + 1) / 2 + c
 __device__ __forceinline__ void mix_tri(int t, int &r, int &c)
 {
@@ -207,83 +261,99 @@ __device__ __forceinline__ void mix_tri(int t, int &r, int &c)
     c = t - r * (r + 1) / 2;
 }
 
-// A_IJ -= L_Ik L_Jk^T for k < J <= I (one 64 x 64 tile per workgroup, 4 waves)
+// A_IJ -= sum_{k0 <= k < k1} L_Ik L_Jk^T over the tiles J = j0 + blockIdx.y,
+// I = J + blockIdx.x < nblk (one 64 x 64 tile per workgroup)
 template <int FMT>
-__global__ void __launch_bounds__(256) mix_update_kernel(float *__restrict__ A, int64_t np, int k)
+__global__ void __launch_bounds__(256) mix_update_kernel(float *__restrict__ A, int64_t np, int nblk, int k0, int k1,
+                                                         int j0)
 {
-    int r, c;
-    mix_tri(blockIdx.x, r, c);
-    const int I = k + 1 + r, J = k + 1 + c;
+    __shared__ float As[kMixNb][kMixLd];
+    __shared__ float Bs[kMixNb][kMixLd];
+    const int J = j0 + blockIdx.y, I = J + blockIdx.x;
+    if (I >= nblk) return;
     const int wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
-    const float *Li = A + ((int64_t)I * kMixNb + 32 * wm) * np + (int64_t)k * kMixNb;
-    const float *Lj = A + ((int64_t)J * kMixNb + 32 * wn) * np + (int64_t)k * kMixNb;
     mix_f32x4 acc[2][2] = {};
-    mix_mma<FMT>(acc, kMixNb, [&](int i, int kk) { return Li[(int64_t)i * np + kk]; },
-                 [&](int kk, int j) { return Lj[(int64_t)j * np + kk]; });
-    const int lane = threadIdx.x & 63, la = lane & 15, lk = lane >> 4;
-    float *C = A + ((int64_t)I * kMixNb + 32 * wm) * np + (int64_t)J * kMixNb + 32 * wn;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                float *dst = C + (int64_t)(16 * x + 4 * lk + q) * np + 16 * y + la;
-                *dst -= acc[x][y][q];
-            }
+    for (int k = k0; k < k1; ++k) {
+        mix_stage(As, A + (int64_t)I * kMixNb * np + (int64_t)k * kMixNb, np);
+        mix_stage(Bs, A + (int64_t)J * kMixNb * np + (int64_t)k * kMixNb, np);
+        __syncthreads();
+        mix_mma_lds<FMT, true>(acc, As, Bs, wm, wn);
+        __syncthreads();
+    }
+    float *C = A + (int64_t)I * kMixNb * np + (int64_t)J * kMixNb;
+    mix_store(acc, wm, wn, [&](int ii, int jj, float v) { C[(int64_t)ii * np + jj] -= v; });
 }
 
-// block row I of L^{-1}: workgroup J (0 <= J <= I) forms Linv_IJ, stores it
-// into B and its transpose into A's tile (J, I)
-template <int FMT>
-__global__ void __launch_bounds__(256) mix_linv_kernel(float *__restrict__ A, float *__restrict__ B, int64_t np,
-                                                       int I, const float *__restrict__ Dinv)
+// Inverse of L by recursive doubling.  Groups of s diagonal tiles are already
+// inverted (tiles of Linv in B's lower part); pair p joins group 2p (tiles
+// [g1, g1 + s)) and group 2p + 1 (tiles [g2, g2 + s2), g2 = g1 + s):
+//   X = L21 Linv11,   Linv21 = -Linv22 X,
+// X kept transposed in B's upper tiles (g1 + j, g2 + i), unused otherwise.
+__global__ void mix_inv_diag_kernel(float *__restrict__ B, int64_t np, const float *__restrict__ Dinv)
 {
-    __shared__ float Xs[kMixNb][kMixNb + 1];
-    const int J = blockIdx.x;
+    const int I = blockIdx.x;
     const float *D = Dinv + (int64_t)I * kMixNb * kMixNb;
+    float *dst = B + (int64_t)I * kMixNb * np + (int64_t)I * kMixNb;
+    for (int e = threadIdx.x; e < kMixNb * kMixNb; e += blockDim.x) dst[(int64_t)(e >> 6) * np + (e & 63)] = D[e];
+}
+
+template <int FMT>
+__global__ void __launch_bounds__(256) mix_inv_x_kernel(const float *__restrict__ A, float *__restrict__ B,
+                                                        int64_t np, int nblk, int s)
+{
+    __shared__ float As[kMixNb][kMixLd];
+    __shared__ float Bs[kMixNb][kMixLd];
+    const int g1 = 2 * s * blockIdx.y, g2 = g1 + s;
+    const int s2 = min(s, nblk - g2);
+    const int i = blockIdx.x / s, j = blockIdx.x - i * s;
+    if (i >= s2) return;
     const int wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
-    const int lane = threadIdx.x & 63, la = lane & 15, lk = lane >> 4;
-    float *Bt = B + (int64_t)I * kMixNb * np + (int64_t)J * kMixNb;     // Linv_IJ
-    float *At = A + (int64_t)J * kMixNb * np + (int64_t)I * kMixNb;     // Linv_IJ^T
-    if (J == I) {
-        for (int e = threadIdx.x; e < kMixNb * kMixNb; e += 256) {
-            const int q = e >> 6, m = e & 63;
-            Bt[(int64_t)q * np + m] = D[e];
-            At[(int64_t)m * np + q] = D[e];
-        }
-        return;
-    }
-    // X = sum_{K=J}^{I-1} L_IK Linv_KJ
     mix_f32x4 acc[2][2] = {};
-    for (int K = J; K < I; ++K) {
-        const float *Lik = A + ((int64_t)I * kMixNb + 32 * wm) * np + (int64_t)K * kMixNb;
-        const float *Lkj = B + (int64_t)K * kMixNb * np + (int64_t)J * kMixNb + 32 * wn;
-        mix_mma<FMT>(acc, kMixNb, [&](int i, int kk) { return Lik[(int64_t)i * np + kk]; },
-                     [&](int kk, int j) { return Lkj[(int64_t)kk * np + j]; });
+    for (int kk = j; kk < s; ++kk) {   // Linv11 is lower triangular: tile (kk, j) with kk >= j
+        mix_stage(As, A + (int64_t)(g2 + i) * kMixNb * np + (int64_t)(g1 + kk) * kMixNb, np);
+        mix_stage(Bs, B + (int64_t)(g1 + kk) * kMixNb * np + (int64_t)(g1 + j) * kMixNb, np);
+        __syncthreads();
+        mix_mma_lds<FMT, false>(acc, As, Bs, wm, wn);
+        __syncthreads();
     }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) Xs[32 * wm + 16 * x + 4 * lk + q][32 * wn + 16 * y + la] = acc[x][y][q];
+    float *Xt = B + (int64_t)(g1 + j) * kMixNb * np + (int64_t)(g2 + i) * kMixNb;
+    mix_store(acc, wm, wn, [&](int ii, int jj, float v) { Xt[(int64_t)jj * np + ii] = v; });
+}
+
+template <int FMT>
+__global__ void __launch_bounds__(256) mix_inv_l_kernel(float *__restrict__ B, int64_t np, int nblk, int s)
+{
+    __shared__ float As[kMixNb][kMixLd];
+    __shared__ float Bs[kMixNb][kMixLd];
+    const int g1 = 2 * s * blockIdx.y, g2 = g1 + s;
+    const int s2 = min(s, nblk - g2);
+    const int i = blockIdx.x / s, j = blockIdx.x - i * s;
+    if (i >= s2) return;
+    const int wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+    mix_f32x4 acc[2][2] = {};
+    for (int kk = 0; kk <= i; ++kk) {   // Linv22 tile (i, kk), X tile (kk, j) stored transposed
+        mix_stage(As, B + (int64_t)(g2 + i) * kMixNb * np + (int64_t)(g2 + kk) * kMixNb, np);
+        mix_stage(Bs, B + (int64_t)(g1 + j) * kMixNb * np + (int64_t)(g2 + kk) * kMixNb, np);
+        __syncthreads();
+        mix_mma_lds<FMT, true>(acc, As, Bs, wm, wn);
+        __syncthreads();
+    }
+    float *C = B + (int64_t)(g2 + i) * kMixNb * np + (int64_t)(g1 + j) * kMixNb;
+    mix_store(acc, wm, wn, [&](int ii, int jj, float v) { C[(int64_t)ii * np + jj] = -v; });
+}
+
+// A's upper tiles (J, I), J <= I, <- the transpose of B's lower tiles (I, J)
+__global__ void __launch_bounds__(256) mix_transpose_kernel(const float *__restrict__ B, float *__restrict__ A,
+                                                            int64_t np)
+{
+    __shared__ float S[kMixNb][kMixNb + 1];
+    int I, J;
+    mix_tri(blockIdx.x, I, J);
+    const float *src = B + (int64_t)I * kMixNb * np + (int64_t)J * kMixNb;
+    float *dst = A + (int64_t)J * kMixNb * np + (int64_t)I * kMixNb;
+    for (int e = threadIdx.x; e < kMixNb * kMixNb; e += 256) S[e >> 6][e & 63] = src[(int64_t)(e >> 6) * np + (e & 63)];
     __syncthreads();
-    // Linv_IJ = -D_I X
-    mix_f32x4 out[2][2] = {};
-    const float *Dw = D + (int64_t)(32 * wm) * kMixNb;
-    mix_mma<FMT>(out, kMixNb, [&](int i, int kk) { return Dw[i * kMixNb + kk]; },
-                 [&](int kk, int j) { return Xs[kk][32 * wn + j]; });
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int ii = 32 * wm + 16 * x + 4 * lk + q, jj = 32 * wn + 16 * y + la;
-                Bt[(int64_t)ii * np + jj] = -out[x][y][q];
-                At[(int64_t)jj * np + ii] = -out[x][y][q];
-            }
+    for (int e = threadIdx.x; e < kMixNb * kMixNb; e += 256) dst[(int64_t)(e >> 6) * np + (e & 63)] = S[e & 63][e >> 6];
 }
 
 size_t mix_workspace_bytes(int64_t n)
@@ -298,16 +368,33 @@ template <int FMT>
 static void mix_factor_fmt(int64_t np, int nblk, float *A, float *B, float *Dinv, const float *dg, float eps,
                            unsigned long long *nfix, hipStream_t s)
 {
-    for (int k = 0; k < nblk; ++k) {
-        hipLaunchKernelGGL(mix_potrf_kernel, dim3(1), dim3(64), 0, s, A, np, k, dg, eps, Dinv, nfix);
-        const int rest = nblk - 1 - k;
-        if (rest > 0) {
+    // block columns in groups of kMixGroup: inside a group the columns are
+    // updated one block column at a time; the trailing matrix takes one
+    // rank-(64 x group) update per group, so it is read and written once per
+    // group instead of once per block column
+    for (int g0 = 0; g0 < nblk; g0 += kMixGroup) {
+        const int g1 = min(g0 + kMixGroup, nblk);
+        for (int k = g0; k < g1; ++k) {
+            hipLaunchKernelGGL(mix_potrf_kernel, dim3(1), dim3(256), 0, s, A, np, k, dg, eps, Dinv, nfix);
+            const int rest = nblk - 1 - k;
+            if (rest == 0) break;
             hipLaunchKernelGGL(mix_panel_kernel, dim3(rest), dim3(256), 0, s, A, np, k, (const float *)Dinv);
-            hipLaunchKernelGGL(mix_update_kernel<FMT>, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, A, np, k);
+            if (k + 1 < g1)   // columns k + 1 .. g1 - 1 of the group, every row below
+                hipLaunchKernelGGL(mix_update_kernel<FMT>, dim3(rest, g1 - k - 1), dim3(256), 0, s, A, np, nblk, k,
+                                   k + 1, k + 1);
         }
+        if (g1 < nblk)
+            hipLaunchKernelGGL(mix_update_kernel<FMT>, dim3(nblk - g1, nblk - g1), dim3(256), 0, s, A, np, nblk, g0,
+                               g1, g1);
     }
-    for (int I = 0; I < nblk; ++I)
-        hipLaunchKernelGGL(mix_linv_kernel<FMT>, dim3(I + 1), dim3(256), 0, s, A, B, np, I, (const float *)Dinv);
+    hipLaunchKernelGGL(mix_inv_diag_kernel, dim3(nblk), dim3(256), 0, s, B, np, (const float *)Dinv);
+    for (int sz = 1; sz < nblk; sz *= 2) {
+        const int pairs = (nblk - sz + 2 * sz - 1) / (2 * sz);   // pairs whose second group is not empty
+        hipLaunchKernelGGL(mix_inv_x_kernel<FMT>, dim3(sz * sz, pairs), dim3(256), 0, s, (const float *)A, B, np,
+                           nblk, sz);
+        hipLaunchKernelGGL(mix_inv_l_kernel<FMT>, dim3(sz * sz, pairs), dim3(256), 0, s, B, np, nblk, sz);
+    }
+    hipLaunchKernelGGL(mix_transpose_kernel, dim3(nblk * (nblk + 1) / 2), dim3(256), 0, s, (const float *)B, A, np);
 }
 
 // Factor and invert: on return Lin (np x np) holds L^{-1} in its lower tiles and
