@@ -395,87 +395,126 @@ __global__ void __launch_bounds__(G == 16 ? 256 : 512) crbm_sample_kernel(CrbmSa
     if (A.n_acc && gl == 0) A.n_acc[c] = acc;
 }
 
-// ---- TFIM local energies, complex: one sample per workgroup ----
+// ---- TFIM local energies, complex: B samples per workgroup ----
+//
+// Each table element (W for theta, (C, S) for the flip ratios) read from L2
+// serves the B samples of the workgroup.  Per sample: t = tanh theta in LDS;
+// one thread per site forms the complex flip ratios of all B samples,
+// exp(-2 a_i s_i) prod_j (C - s_i t_j S), with frexp renormalisation every 8
+// factors, and stores them in FP64; then one wave per sample sums ratios and
+// diagonal bonds in a fixed order.
 
-__global__ void __launch_bounds__(kCrbmThreads) crbm_eloc_tfim_kernel(CrbmDev net, const int8_t *__restrict__ samples,
-                                                                      int64_t n, int dim, int L, int pbc, double J,
-                                                                      double h, double *__restrict__ eloc_re,
-                                                                      double *__restrict__ eloc_im)
+__device__ inline double crbm_bonds(const float *s, int i, int dim, int L, int pbc)
 {
-    extern __shared__ float esm[];
-    const int N = net.N, M = net.M, tid = threadIdx.x;
-    float *s = esm;                                          // [N]
-    float2 *tt = reinterpret_cast<float2 *>(esm + ((N + 1) & ~1));   // [M]
-    __shared__ double red[3][kCrbmThreads / 64];
-    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
-        for (int i = tid; i < N; i += kCrbmThreads) s[i] = (float)samples[k * N + i];
-        __syncthreads();
-        for (int j = tid; j < M; j += kCrbmThreads) {
-            float2 a = net.b[j];
-            for (int i = 0; i < N; ++i) {
-                const float2 w = net.Wt[(int64_t)i * M + j];
-                a.x = fmaf(w.x, s[i], a.x);
-                a.y = fmaf(w.y, s[i], a.y);
-            }
-            tt[j] = ctanh(a);
+    const float si = s[i];
+    double dg = 0.0;   // bonds to the right / below, each counted once
+    if (dim == 1) {
+        if (i + 1 < L) dg += (double)(si * s[i + 1]);
+        else if (pbc) dg += (double)(si * s[0]);
+    } else {
+        const int x = i / L, y = i - (i / L) * L;
+        if (x + 1 < L) dg += (double)(si * s[(x + 1) * L + y]);
+        else if (pbc) dg += (double)(si * s[y]);
+        if (y + 1 < L) dg += (double)(si * s[x * L + y + 1]);
+        else if (pbc) dg += (double)(si * s[x * L]);
+    }
+    return dg;
+}
+
+__host__ __device__ inline size_t crbm_eloc_lds(int B, int N, int M)
+{
+    return sizeof(double2) * (size_t)B * N + sizeof(float2) * (size_t)B * M + sizeof(float) * (size_t)B * N;
+}
+
+template <int B>
+__global__ void __launch_bounds__(256) crbm_eloc_tfim_kernel(CrbmDev net, const int8_t *__restrict__ samples,
+                                                             int64_t n, int dim, int L, int pbc, double J, double h,
+                                                             double *__restrict__ eloc_re, double *__restrict__ eloc_im)
+{
+    extern __shared__ double2 crbm_esm[];
+    const int N = net.N, M = net.M, tid = threadIdx.x, nt = blockDim.x;
+    double2 *rat = crbm_esm;                                             // [B][N]
+    float2 *tt = reinterpret_cast<float2 *>(rat + (size_t)B * N);       // [B][M]
+    float *s = reinterpret_cast<float *>(tt + (size_t)B * M);           // [B][N]
+    for (int64_t k0 = (int64_t)blockIdx.x * B; k0 < n; k0 += (int64_t)gridDim.x * B) {
+        const int nb = (int)(n - k0 < B ? n - k0 : B);
+        for (int e = tid; e < B * N; e += nt) {
+            const int bb = e / N, i = e - bb * N;
+            s[e] = bb < nb ? (float)samples[(k0 + bb) * N + i] : 1.0f;
         }
         __syncthreads();
-        double re = 0.0, im = 0.0, dg = 0.0;
-        for (int i = tid; i < N; i += kCrbmThreads) {
-            const float si = s[i];
-            // ratio = exp(-2 a_i s_i) prod_j (C - s_i t_j S), magnitudes renormalised every 8 factors
-            float2 pr = make_float2(1.0f, 0.0f);
-            int e2 = 0;
+        for (int j = tid; j < M; j += nt) {
+            float2 th[B];
+            const float2 bj = net.b[j];
+#pragma unroll
+            for (int bb = 0; bb < B; ++bb) th[bb] = bj;
+            for (int i = 0; i < N; ++i) {
+                const float2 w = net.Wt[(int64_t)i * M + j];
+#pragma unroll
+                for (int bb = 0; bb < B; ++bb) {
+                    const float sb = s[bb * N + i];
+                    th[bb].x = fmaf(w.x, sb, th[bb].x);
+                    th[bb].y = fmaf(w.y, sb, th[bb].y);
+                }
+            }
+#pragma unroll
+            for (int bb = 0; bb < B; ++bb) tt[bb * M + j] = ctanh(th[bb]);
+        }
+        __syncthreads();
+        for (int i = tid; i < N; i += nt) {
+            float2 pr[B];
+            int e2[B];
+            float si[B];
+#pragma unroll
+            for (int bb = 0; bb < B; ++bb) {
+                pr[bb] = make_float2(1.0f, 0.0f);
+                e2[bb] = 0;
+                si[bb] = s[bb * N + i];
+            }
             for (int j = 0; j < M; ++j) {
                 const float4 cs = net.CSt[(int64_t)j * N + i];
-                const float2 ts = cmul(tt[j], make_float2(cs.z, cs.w));
-                pr = cmul(pr, make_float2(fmaf(-si, ts.x, cs.x), fmaf(-si, ts.y, cs.y)));
+#pragma unroll
+                for (int bb = 0; bb < B; ++bb) {
+                    const float2 ts = cmul(tt[bb * M + j], make_float2(cs.z, cs.w));
+                    pr[bb] = cmul(pr[bb], make_float2(fmaf(-si[bb], ts.x, cs.x), fmaf(-si[bb], ts.y, cs.y)));
+                }
                 if ((j & 7) == 7) {
-                    int e;
-                    const float mag = frexpf(fmaxf(fabsf(pr.x), fabsf(pr.y)), &e);
-                    (void)mag;
-                    pr.x = ldexpf(pr.x, -e);
-                    pr.y = ldexpf(pr.y, -e);
-                    e2 += e;
+#pragma unroll
+                    for (int bb = 0; bb < B; ++bb) {
+                        int e;
+                        (void)frexpf(fmaxf(fabsf(pr[bb].x), fabsf(pr[bb].y)), &e);
+                        pr[bb].x = ldexpf(pr[bb].x, -e);
+                        pr[bb].y = ldexpf(pr[bb].y, -e);
+                        e2[bb] += e;
+                    }
                 }
             }
             const float2 ai = net.a[i];
-            const double mg = exp(-2.0 * (double)ai.x * si) * ldexp(1.0, e2);
-            double sn, cn;
-            sincos(-2.0 * (double)ai.y * si, &sn, &cn);
-            const double pre = mg * cn, pim = mg * sn;
-            re += pre * pr.x - pim * pr.y;
-            im += pre * pr.y + pim * pr.x;
-            // bonds to the right / below, each counted once
-            if (dim == 1) {
-                if (i + 1 < L) dg += (double)(si * s[i + 1]);
-                else if (pbc) dg += (double)(si * s[0]);
-            } else {
-                const int x = i / L, y = i - (i / L) * L;
-                if (x + 1 < L) dg += (double)(si * s[(x + 1) * L + y]);
-                else if (pbc) dg += (double)(si * s[y]);
-                if (y + 1 < L) dg += (double)(si * s[x * L + y + 1]);
-                else if (pbc) dg += (double)(si * s[x * L]);
+#pragma unroll
+            for (int bb = 0; bb < B; ++bb) {
+                const double mg = exp(-2.0 * (double)ai.x * si[bb]) * ldexp(1.0, e2[bb]);
+                double sn, cn;
+                sincos(-2.0 * (double)ai.y * si[bb], &sn, &cn);
+                const double pre = mg * cn, pim = mg * sn;
+                rat[bb * N + i] = make_double2(pre * pr[bb].x - pim * pr[bb].y, pre * pr[bb].y + pim * pr[bb].x);
             }
-        }
-        re = group_sum<64>(re);
-        im = group_sum<64>(im);
-        dg = group_sum<64>(dg);
-        if ((tid & 63) == 0) {
-            red[0][tid >> 6] = re;
-            red[1][tid >> 6] = im;
-            red[2][tid >> 6] = dg;
         }
         __syncthreads();
-        if (tid == 0) {
-            double R = 0.0, I = 0.0, D = 0.0;
-            for (int w = 0; w < kCrbmThreads / 64; ++w) {
-                R += red[0][w];
-                I += red[1][w];
-                D += red[2][w];
+        const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
+        for (int bb = wave; bb < nb; bb += nw) {
+            double re = 0.0, im = 0.0, dg = 0.0;
+            for (int i = lane; i < N; i += 64) {
+                re += rat[bb * N + i].x;
+                im += rat[bb * N + i].y;
+                dg += crbm_bonds(s + bb * N, i, dim, L, pbc);
             }
-            eloc_re[k] = J * D + h * R;
-            if (eloc_im) eloc_im[k] = h * I;
+            re = group_sum<64>(re);
+            im = group_sum<64>(im);
+            dg = group_sum<64>(dg);
+            if (lane == 0) {
+                eloc_re[k0 + bb] = J * dg + h * re;
+                if (eloc_im) eloc_im[k0 + bb] = h * im;
+            }
         }
         __syncthreads();
     }
@@ -580,12 +619,29 @@ nqs_status crbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
     nqs_status st = ensure_copy(m, dtype, stream);
     if (st != NQS_OK) return st;
     const CrbmDev &net = m->copies[dtype].crbm;
-    const size_t lds = sizeof(float) * (((size_t)net.N + 1) & ~(size_t)1) + sizeof(float2) * (size_t)net.M;
+    // samples per workgroup: the largest of 16, 8, 4, 2, 1 whose LDS stays within 64 KB
+    int B = 16;
+    while (B > 1 && crbm_eloc_lds(B, net.N, net.M) > 64 * 1024) B /= 2;
+    const size_t lds = crbm_eloc_lds(B, net.N, net.M);
     if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "complex RBM too large for the local-energy kernel");
-    allow_lds(crbm_eloc_tfim_kernel, lds);
-    const int64_t blocks = std::min<int64_t>(n, (int64_t)device_cus() * 16);
-    hipLaunchKernelGGL(crbm_eloc_tfim_kernel, dim3((unsigned)blocks), dim3(kCrbmThreads), lds, stream, net, samples, n,
-                       ham.dim, ham.L, ham.pbc, ham.J, ham.h, eloc_re, eloc_im);
+    if (n == 0) return NQS_OK;
+    const int threads = net.N <= 128 ? 128 : 256;
+    const int64_t blocks = std::min<int64_t>((n + B - 1) / B, (int64_t)device_cus() * 8);
+    switch (B) {
+#define NQS_CE(BB)                                                                                                   \
+    case BB:                                                                                                         \
+        allow_lds(crbm_eloc_tfim_kernel<BB>, lds);                                                                   \
+        hipLaunchKernelGGL(crbm_eloc_tfim_kernel<BB>, dim3((unsigned)blocks), dim3(threads), lds, stream, net,       \
+                           samples, n, ham.dim, ham.L, ham.pbc, ham.J, ham.h, eloc_re, eloc_im);                     \
+        break;
+        NQS_CE(16) NQS_CE(8) NQS_CE(4) NQS_CE(2)
+#undef NQS_CE
+    default:
+        allow_lds(crbm_eloc_tfim_kernel<1>, lds);
+        hipLaunchKernelGGL(crbm_eloc_tfim_kernel<1>, dim3((unsigned)blocks), dim3(threads), lds, stream, net, samples,
+                           n, ham.dim, ham.L, ham.pbc, ham.J, ham.h, eloc_re, eloc_im);
+        break;
+    }
     NQS_HIP_TRY(hipGetLastError());
     return NQS_OK;
 }
