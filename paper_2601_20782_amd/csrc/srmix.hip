@@ -16,7 +16,7 @@
 // T + shift, extended by the identity), FP32 row-major with leading
 // dimension np, in 64 x 64 tiles.  Blocked right-looking Cholesky, per block
 // column k:
-//   mix_potrf_kernel   L_kk and D_k = L_kk^{-1} (FP32, tile in LDS)
+//   mix_potrf_kernel   L_kk and D_k = L_kk^{-1} (FP32, one wave, rows in registers)
 //   mix_panel_kernel   L_Ik = A_Ik D_k^T for I > k (FP32 matrix cores)
 //   mix_update_kernel  A_IJ -= L_Ik L_Jk^T for k < J <= I: the O(n^3) part, on
 //                      the matrix cores with operands rounded to the format
@@ -73,76 +73,70 @@ __device__ __forceinline__ void mix_stage(float (*S)[kMixLd], const float *__res
     }
 }
 
-// Cholesky of the diagonal tile k and its inverse D_k (256 threads).  Thread
-// (wave w, lane m) keeps the entries (w + 4 r, m), r < 16, in registers.  Per
-// column j the owners of column j publish it through LDS (double-buffered, so
-// one barrier per column); every thread derives the same pivot from it and
-// applies the scaling and the rank-1 update to its own entries by selects.
-__global__ void __launch_bounds__(256) mix_potrf_kernel(float *__restrict__ A, int64_t np, int k,
-                                                        const float *__restrict__ dg, float eps,
-                                                        float *__restrict__ Dinv,
-                                                        unsigned long long *__restrict__ nfix)
+// Cholesky of the diagonal tile k and its inverse D_k, one wave.  Lane i keeps
+// row i in registers; per column j the pivot comes from lane j (readlane),
+// the scaled column goes through LDS (one store, broadcast reads), and every
+// lane updates its row.  A single wave needs no barriers: its LDS operations
+// complete in issue order.
+__global__ void __launch_bounds__(64) mix_potrf_kernel(float *__restrict__ A, int64_t np, int k,
+                                                       const float *__restrict__ dg, float eps,
+                                                       float *__restrict__ Dinv,
+                                                       unsigned long long *__restrict__ nfix)
 {
-    __shared__ float S[kMixNb][kMixLd];
-    __shared__ float col[2][kMixNb], rinv[kMixNb], d0s[kMixNb];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ float S[kMixNb][kMixLd];       // L^T: row q of S is column q of L
+    __shared__ float R[kMixNb][kMixNb + 1];   // staging for coalesced global access
+    __shared__ float col[kMixNb], d0s[kMixNb], rinv[kMixNb];
+    const int i = threadIdx.x;
     float *blk = A + (int64_t)k * kMixNb * np + (int64_t)k * kMixNb;
-    float reg[16];
+    for (int q = 0; q < kMixNb; ++q) R[q][i] = blk[(int64_t)q * np + i];
+    d0s[i] = dg[(int64_t)k * kMixNb + i];
+    __syncthreads();
+    float r[kMixNb];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) reg[r] = blk[(int64_t)(wave + 4 * r) * np + lane];
-    if (tid < kMixNb) d0s[tid] = dg[(int64_t)k * kMixNb + tid];
+    for (int m = 0; m < kMixNb; ++m) r[m] = R[i][m];
     unsigned fixes = 0;
-    for (int j = 0; j < kMixNb; ++j) {
-        float *cj = col[j & 1];
-        if (lane == j) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) cj[wave + 4 * r] = reg[r];
-        }
-        __syncthreads();
-        float d = cj[j];
+    for (int j = 0; j < kMixNb; ++j) {
+        float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r[j]), j));
         const float d0 = d0s[j];
         const bool fix = !(d > eps * fabsf(d0));   // also catches NaN
         if (fix) d = fabsf(d0) > 0.0f ? fabsf(d0) : 1.0f;
         fixes += fix ? 1u : 0u;
-        const float l = sqrtf(d), ri = 1.0f / l;
-        if (tid == 0) rinv[j] = ri;
-        const float lm = cj[lane] * ri;               // L[lane][j] for lane > j
-        const bool upd = lane > j, own = lane == j;
+        // hardware reciprocal square root (about 1 ulp): the factor only preconditions the FP64 iteration
+        const float ri = __builtin_amdgcn_rsqf(d), l = d * ri;
+        const float lij = i > j ? r[j] * ri : (i == j ? l : 0.0f);
+        r[j] = lij;
+        rinv[j] = ri;
+        col[i] = lij;
+        __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = wave + 4 * r;
-            const float li = cj[i] * ri;              // L[i][j]
-            const float u = fmaf(-li, lm, reg[r]);
-            const float o = i > j ? reg[r] * ri : (i == j ? l : reg[r]);
-            reg[r] = upd && i >= lane ? u : (own ? o : reg[r]);
-        }
+        for (int m = j + 1; m < kMixNb; ++m) r[m] = fmaf(-lij, col[m], r[m]);
     }
+    // L (zero above the diagonal) into S as L^T and, through R, back to the tile
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int i = wave + 4 * r;
-        const float v = i >= lane ? reg[r] : 0.0f;
-        S[lane][i] = v;   // S holds L^T: row q of S is column q of L
-        blk[(int64_t)i * np + lane] = v;
+    for (int m = 0; m < kMixNb; ++m) {
+        const float v = m <= i ? r[m] : 0.0f;
+        S[m][i] = v;
+        R[i][m] = v;
     }
     __syncthreads();
-    // wave 0: lane c forms column c of L^{-1}, column-oriented: once x[q] is
-    // known, the partial sums of the later rows take x[q] times column q of L
-    if (wave == 0) {
-        const int c = lane;
-        float x[kMixNb];
+    for (int q = 0; q < kMixNb; ++q) blk[(int64_t)q * np + i] = R[q][i];
+    // lane c forms column c of L^{-1}, column-oriented: once x[q] is known, the
+    // partial sums of the later rows take x[q] times column q of L
+    const int c = i;
+    float x[kMixNb];
 #pragma unroll
-        for (int q = 0; q < kMixNb; ++q) x[q] = q == c ? 1.0f : 0.0f;
+    for (int q = 0; q < kMixNb; ++q) x[q] = q == c ? 1.0f : 0.0f;
 #pragma unroll
-        for (int q = 0; q < kMixNb; ++q) {
-            x[q] *= rinv[q];
+    for (int q = 0; q < kMixNb; ++q) {
+        x[q] *= rinv[q];
 #pragma unroll
-            for (int qq = q + 1; qq < kMixNb; ++qq) x[qq] = fmaf(-S[q][qq], x[q], x[qq]);
-        }
-        float *D = Dinv + (int64_t)k * kMixNb * kMixNb;
-#pragma unroll
-        for (int q = 0; q < kMixNb; ++q) D[q * kMixNb + c] = x[q];   // rows q < c hold 0
+        for (int qq = q + 1; qq < kMixNb; ++qq) x[qq] = fmaf(-S[q][qq], x[q], x[qq]);
     }
-    if (tid == 0 && fixes) atomicAdd(nfix, (unsigned long long)fixes);
+    float *D = Dinv + (int64_t)k * kMixNb * kMixNb;
+#pragma unroll
+    for (int q = 0; q < kMixNb; ++q) D[q * kMixNb + c] = x[q];   // rows q < c hold 0
+    if (i == 0 && fixes) atomicAdd(nfix, (unsigned long long)fixes);
 }
 
 // round-to-nearest-even codes of the 16-bit formats
@@ -375,7 +369,7 @@ static void mix_factor_fmt(int64_t np, int nblk, float *A, float *B, float *Dinv
     for (int g0 = 0; g0 < nblk; g0 += kMixGroup) {
         const int g1 = min(g0 + kMixGroup, nblk);
         for (int k = g0; k < g1; ++k) {
-            hipLaunchKernelGGL(mix_potrf_kernel, dim3(1), dim3(256), 0, s, A, np, k, dg, eps, Dinv, nfix);
+            hipLaunchKernelGGL(mix_potrf_kernel, dim3(1), dim3(64), 0, s, A, np, k, dg, eps, Dinv, nfix);
             const int rest = nblk - 1 - k;
             if (rest == 0) break;
             hipLaunchKernelGGL(mix_panel_kernel, dim3(rest), dim3(256), 0, s, A, np, k, (const float *)Dinv);
