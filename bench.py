@@ -38,6 +38,8 @@ Other workloads (--workload):
   crbm     complex-parameter RBM on the 10x10 TFIM (M = 200), 4096 chains x
            (10 + 100) sweeps, beside the real RBM sampler at the same shape;
            complex local energies of the emitted samples.
+  peaks    achievable rates of the device (FP32 FMA, log2/exp2, matrix cores in
+           BF16/FP32/FP64, HBM read and copy) next to the published peaks.
 """
 from __future__ import annotations
 
@@ -65,7 +67,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20", "noise", "rescnn", "crbm"])
+    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20", "noise", "rescnn", "crbm", "peaks"])
     ap.add_argument("--sweeps", type=int, default=0, help="heis20: measured sweeps per step (default 1)")
     ap.add_argument("--gram-samples", type=int, default=4096, help="heis20: samples in T (0 = skip)")
     ap.add_argument("--gram-chunked", action="store_true", help="heis20: T by parameter column blocks")
@@ -783,6 +785,58 @@ def run_crbm(a, torch, nqs, workloads):
     }
 
 
+def run_peaks(a, torch, nqs, workloads):
+    """Achievable rates of this device from the microbenchmarks of include/nqs_probe.h (best of three
+    launches each), next to the published peaks that the roofline figures divide by."""
+    dev = torch.device("cuda:0")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    scratch = torch.empty(cus * 16 * 256, dtype=torch.float32, device=dev)
+    ev = _events(torch, 2)
+
+    def best_rate(kind, size, src=None, dst=scratch):
+        nqs.nqs_probe_rate(kind, size, src, dst)   # warm
+        torch.cuda.synchronize()
+        best = 0.0
+        for _ in range(3):
+            ev[0].record()
+            w = nqs.nqs_probe_rate(kind, size, src, dst)
+            ev[1].record()
+            torch.cuda.synchronize()
+            best = max(best, w / (ev[0].elapsed_time(ev[1]) * 1e-3))
+        return best
+
+    got = {
+        "fma_f32_tflops": best_rate("fma_f32", 4000) / 1e12,
+        "log2_f32_per_s": best_rate("log_f32", 1000),
+        "exp2_f32_per_s": best_rate("exp_f32", 1000),
+        "mfma_bf16_16x16x16_tflops": best_rate("mfma_bf16_k16", 2000) / 1e12,
+        "mfma_bf16_16x16x32_tflops": best_rate("mfma_bf16_k32", 2000) / 1e12,
+        "mfma_f32_16x16x4_tflops": best_rate("mfma_f32", 1000) / 1e12,
+        "mfma_f64_16x16x4_tflops": best_rate("mfma_f64", 500) / 1e12,
+    }
+    nbytes = 2 << 30
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    got["hbm_read_gbs"] = best_rate("hbm_read", nbytes, x) / 1e9
+    y = torch.empty_like(x)
+    got["hbm_copy_gbs"] = best_rate("hbm_copy", nbytes, x, y) / 1e9
+    del x, y
+    published = {"fma_f32_tflops": PEAK_FP32_VALU_TFLOPS, "mfma_bf16_16x16x32_tflops": PEAK_BF16_MFMA_TFLOPS,
+                 "mfma_f32_16x16x4_tflops": 157.3, "mfma_f64_16x16x4_tflops": 78.6, "hbm_read_gbs": 8000.0,
+                 "hbm_copy_gbs": 8000.0}
+    return {
+        "metric": "achievable rates (microbenchmarks)", "value": got["mfma_bf16_16x16x32_tflops"], "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "mixed", "data": "synthetic",
+        "config": {"workload": "peaks", "compute_units": cus, "grid": "8 blocks of 256 threads per CU",
+                   "hbm_bytes": nbytes, "parallelism": "single GPU"},
+        "achieved": {k: round(v, 3) for k, v in got.items()},
+        "published": published,
+        "frac_of_published": {k: round(got[k] / v, 4) for k, v in published.items()},
+        "note": "FP32 FMA without packed FP32 (this library never issues it): its ceiling is half the published "
+                "vector peak; log2 / exp2 in operations per second",
+    }
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -802,7 +856,7 @@ def main():
     import paper_2601_20782_amd as nqs
     import workloads
     run = {"tfim10": run_tfim10, "heis10": run_heis10, "uneven": run_uneven, "heis20": run_heis20,
-           "noise": run_noise, "rescnn": run_rescnn, "crbm": run_crbm}[a.workload]
+           "noise": run_noise, "rescnn": run_rescnn, "crbm": run_crbm, "peaks": run_peaks}[a.workload]
     print(json.dumps(run(a, torch, nqs, workloads)))
 
 

@@ -1,0 +1,44 @@
+/*
+ * nqs_probe.h -- microbenchmarks of the rates this device achieves, used to
+ * put the roofline figures of the method's kernels next to measured ceilings.
+ * Measurement support only: no step of the method goes through these calls.
+ */
+#ifndef NQS_PROBE_H
+#define NQS_PROBE_H
+
+#include <stdint.h>
+
+#include "nqs.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NQS_PROBE_FMA_F32 = 0,        /* v_fma_f32 (packed FP32 is not used by this library) */
+    NQS_PROBE_LOG_F32 = 1,        /* v_log_f32 (log2) */
+    NQS_PROBE_EXP_F32 = 2,        /* v_exp_f32 (exp2) */
+    NQS_PROBE_MFMA_BF16_K16 = 3,  /* v_mfma_f32_16x16x16_bf16 */
+    NQS_PROBE_MFMA_BF16_K32 = 4,  /* v_mfma_f32_16x16x32_bf16 */
+    NQS_PROBE_MFMA_F32 = 5,       /* v_mfma_f32_16x16x4_f32 */
+    NQS_PROBE_MFMA_F64 = 6,       /* v_mfma_f64_16x16x4_f64 */
+    NQS_PROBE_HBM_READ = 7,       /* read `size` bytes of src */
+    NQS_PROBE_HBM_COPY = 8        /* copy `size` bytes from src to dst */
+} nqs_probe_kind;
+
+/* One launch of probe `kind` on `stream` (asynchronous; the caller times it).
+ * Compute probes: `size` = loop iterations per thread (1 .. 2^24), the grid is
+ * 8 blocks of 256 threads per compute unit, `dst` = device scratch of at least
+ * (CUs x 8 x 256) floats, `src` unused; *work = floating-point operations of
+ * the launch (an FMA or a matrix product element counts 2, a log or exp 1).
+ * Memory probes: `size` = bytes, a positive multiple of 16; `src` a device
+ * buffer of that size; `dst` for the copy a second one, for the read a
+ * scratch of at least (CUs x 16 x 256) floats; all 16-byte aligned; *work =
+ * bytes moved (read, or read + written).  *work is a host pointer.  NQS_EINVAL on a
+ * bad kind, size or pointer. */
+nqs_status nqs_probe_rate(int32_t kind, int64_t size, const void *src, void *dst, double *work, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NQS_PROBE_H */

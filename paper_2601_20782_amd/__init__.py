@@ -22,7 +22,7 @@ from ._abi import DTYPE_CODES, NqsError, check, load
 __all__ = [
     "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
     "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
-    "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
+    "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_probe_rate", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
 ]
 
 
@@ -367,3 +367,11 @@ class LogPsi(torch.autograd.Function):
         vjp = torch.empty(ctx.model.n_params, dtype=torch.float32, device=samples.device)
         nqs_logpsi_grad(ctx.model, samples, vjp_in=g, vjp_out=vjp)
         return vjp.to(ctx.pdtype), None, None
+
+
+def nqs_probe_rate(kind: str, size: int, src: Optional[torch.Tensor], dst: torch.Tensor, stream=None) -> float:
+    """One launch of a rate microbenchmark (include/nqs_probe.h); returns its work (flops or bytes)."""
+    w = ctypes.c_double(0.0)
+    check(load().nqs_probe_rate(_abi.PROBE_KINDS[kind], int(size), _ptr(src) if src is not None else None, _ptr(dst),
+                                ctypes.byref(w), _stream(stream)))
+    return w.value

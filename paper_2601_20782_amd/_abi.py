@@ -16,7 +16,7 @@ MAX_LAYERS = 8
 
 DTYPE_CODES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "e4m3": FP8_E4M3, "fp8": FP8_E4M3}
 
-# every function include/nqs.h declares
+# every function the headers under include/ declare
 EXPORTS = [
     "nqs_model_create", "nqs_model_set_params", "nqs_model_set_params_device", "nqs_model_destroy",
     "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched",
@@ -25,7 +25,11 @@ EXPORTS = [
     "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex",
     "nqs_last_error",
     "nqs_version",
+    "nqs_probe_rate",
 ]
+
+PROBE_KINDS = {"fma_f32": 0, "log_f32": 1, "exp_f32": 2, "mfma_bf16_k16": 3, "mfma_bf16_k32": 4, "mfma_f32": 5,
+               "mfma_f64": 6, "hbm_read": 7, "hbm_copy": 8}
 
 
 class ModelDesc(ctypes.Structure):
@@ -96,6 +100,7 @@ def load() -> ctypes.CDLL:
         "nqs_sample_gram": ([P, P, i64, i64, P, P], st),
         "nqs_sample_gram_factored": ([P, P, i64, P, P], st),
         "nqs_sr_solve": ([P, P, i64, ctypes.c_double, ctypes.c_double, i32, P, P, P, P], st),
+        "nqs_probe_rate": ([i32, i64, P, P, P, P], st),
         "nqs_sr_solve_mixed": ([P, P, i64, ctypes.c_double, i32, ctypes.c_double, i32, P, P, P, P, P, P], st),
         "nqs_sr_update": ([P, P, i64, P, ctypes.c_double, P, P], st),
         "nqs_sample_noisy": ([P, P, ctypes.c_double, ctypes.c_uint64, P, P, P, P, P], st),

@@ -1,0 +1,173 @@
+// Microbenchmarks of achievable rates (measurement support for the roofline
+// figures; no step of the method runs here).  Each compute probe keeps eight
+// (VALU) or four (matrix core) independent dependency chains per thread or
+// wave so that issue, not latency, bounds it; a result-dependent store that
+// never fires keeps the chains live.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "internal.h"
+#include "nqs_probe.h"
+
+namespace nqs {
+
+typedef float pk_f32x4 __attribute__((ext_vector_type(4)));
+typedef double pk_f64x4 __attribute__((ext_vector_type(4)));
+typedef short pk_s16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 pk_bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kProbeThreads = 256;
+constexpr int kProbeUnroll = 16;
+
+template <int KIND>
+__global__ void __launch_bounds__(kProbeThreads) probe_valu_kernel(float *__restrict__ out, int iters)
+{
+    const int t = blockIdx.x * kProbeThreads + threadIdx.x;
+    float a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = 1.5f + 1e-3f * (float)((t + k) & 255);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if constexpr (KIND == NQS_PROBE_FMA_F32) a[k] = fmaf(a[k], 0.9999999f, 1e-7f);
+                else if constexpr (KIND == NQS_PROBE_LOG_F32) a[k] = __builtin_amdgcn_logf(a[k]) + 2.0f;
+                else a[k] = __builtin_amdgcn_exp2f(a[k]) * 0.25f;
+            }
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += a[k];
+    if (s == -1.0f) out[t] = s;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(kProbeThreads) probe_mfma_kernel(float *__restrict__ out, int iters)
+{
+    const int t = blockIdx.x * kProbeThreads + threadIdx.x;
+    const float v = 1e-3f * (float)(t & 63);
+    float s = 0.0f;
+    if constexpr (KIND == NQS_PROBE_MFMA_F64) {
+        pk_f64x4 acc[4] = {};
+        const double a = v, b = 1.0 - v;
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int u = 0; u < kProbeUnroll; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += (float)(acc[k][0] + acc[k][3]);
+    } else {
+        pk_f32x4 acc[4] = {};
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int u = 0; u < kProbeUnroll; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if constexpr (KIND == NQS_PROBE_MFMA_F32) {
+                        acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(v, 1.0f - v, acc[k], 0, 0, 0);
+                    } else if constexpr (KIND == NQS_PROBE_MFMA_BF16_K16) {
+                        const short c = (short)(__float_as_uint(v) >> 16);
+                        const pk_s16x4 a = {c, c, c, c};
+                        acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, a, acc[k], 0, 0, 0);
+                    } else {
+                        const __bf16 c = (__bf16)v;
+                        const pk_bf16x8 a = {c, c, c, c, c, c, c, c};
+                        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, a, acc[k], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += acc[k][0] + acc[k][3];
+    }
+    if (s == -1.0f) out[t] = s;
+}
+
+__global__ void __launch_bounds__(kProbeThreads) probe_read_kernel(const float4 *__restrict__ src, int64_t n4,
+                                                                   float *__restrict__ out)
+{
+    float s = 0.0f;
+    for (int64_t k = blockIdx.x * (int64_t)kProbeThreads + threadIdx.x; k < n4;
+         k += (int64_t)gridDim.x * kProbeThreads) {
+        const float4 v = src[k];
+        s += v.x + v.y + v.z + v.w;
+    }
+    if (s == -1.0f) out[blockIdx.x * kProbeThreads + threadIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kProbeThreads) probe_copy_kernel(const float4 *__restrict__ src, int64_t n4,
+                                                                   float4 *__restrict__ dst)
+{
+    for (int64_t k = blockIdx.x * (int64_t)kProbeThreads + threadIdx.x; k < n4;
+         k += (int64_t)gridDim.x * kProbeThreads)
+        dst[k] = src[k];
+}
+
+}  // namespace nqs
+
+using namespace nqs;
+
+extern "C" nqs_status nqs_probe_rate(int32_t kind, int64_t size, const void *src, void *dst, double *work,
+                                     void *stream)
+{
+    if (!work) return set_error(NQS_EINVAL, "NULL work");
+    hipStream_t s = (hipStream_t)stream;
+    const int blocks = device_cus() * 8;
+    const double threads = (double)blocks * kProbeThreads;
+    if (kind >= NQS_PROBE_FMA_F32 && kind <= NQS_PROBE_MFMA_F64) {
+        if (size < 1 || size > (1 << 24)) return set_error(NQS_EINVAL, "iterations must be in [1, 2^24]");
+        if (!dst) return set_error(NQS_EINVAL, "NULL scratch");
+        float *o = (float *)dst;
+        const int it = (int)size;
+        const double per = (double)it * kProbeUnroll;
+        switch (kind) {
+        case NQS_PROBE_FMA_F32:
+            hipLaunchKernelGGL(probe_valu_kernel<NQS_PROBE_FMA_F32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads * per * 8 * 2;
+            break;
+        case NQS_PROBE_LOG_F32:
+            hipLaunchKernelGGL(probe_valu_kernel<NQS_PROBE_LOG_F32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads * per * 8;
+            break;
+        case NQS_PROBE_EXP_F32:
+            hipLaunchKernelGGL(probe_valu_kernel<NQS_PROBE_EXP_F32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads * per * 8;
+            break;
+        case NQS_PROBE_MFMA_BF16_K16:
+            hipLaunchKernelGGL(probe_mfma_kernel<NQS_PROBE_MFMA_BF16_K16>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads / 64 * per * 4 * (2.0 * 16 * 16 * 16);
+            break;
+        case NQS_PROBE_MFMA_BF16_K32:
+            hipLaunchKernelGGL(probe_mfma_kernel<NQS_PROBE_MFMA_BF16_K32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads / 64 * per * 4 * (2.0 * 16 * 16 * 32);
+            break;
+        case NQS_PROBE_MFMA_F32:
+            hipLaunchKernelGGL(probe_mfma_kernel<NQS_PROBE_MFMA_F32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads / 64 * per * 4 * (2.0 * 16 * 16 * 4);
+            break;
+        default:
+            hipLaunchKernelGGL(probe_mfma_kernel<NQS_PROBE_MFMA_F64>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads / 64 * per * 4 * (2.0 * 16 * 16 * 4);
+            break;
+        }
+    } else if (kind == NQS_PROBE_HBM_READ || kind == NQS_PROBE_HBM_COPY) {
+        if (size <= 0 || size % 16 != 0) return set_error(NQS_EINVAL, "size must be a positive multiple of 16");
+        if (!src || ((uintptr_t)src & 15)) return set_error(NQS_EINVAL, "src must be 16-byte aligned");
+        if (!dst || ((uintptr_t)dst & 15)) return set_error(NQS_EINVAL, "dst must be 16-byte aligned");
+        const int64_t n4 = size / 16;
+        const int mb = blocks * 2;
+        if (kind == NQS_PROBE_HBM_READ) {
+            hipLaunchKernelGGL(probe_read_kernel, dim3(mb), dim3(kProbeThreads), 0, s, (const float4 *)src, n4,
+                               (float *)dst);
+            *work = (double)size;
+        } else {
+            hipLaunchKernelGGL(probe_copy_kernel, dim3(mb), dim3(kProbeThreads), 0, s, (const float4 *)src, n4,
+                               (float4 *)dst);
+            *work = 2.0 * (double)size;
+        }
+    } else {
+        return set_error(NQS_EINVAL, "unknown probe kind");
+    }
+    NQS_HIP_TRY(hipGetLastError());
+    return NQS_OK;
+}

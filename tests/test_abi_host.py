@@ -1,5 +1,5 @@
 """Host-side checks of the C interface (no GPU needed): the library loads, it
-exports every function include/nqs.h declares, and argument validation rejects
+exports every function the headers under include/ declare, and argument validation rejects
 bad calls before touching a device."""
 import ctypes
 import os
@@ -12,7 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    text = open(os.path.join(ROOT, "include", "nqs.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "\n".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?[\s\*]+(nqs_[a-z0-9_]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
