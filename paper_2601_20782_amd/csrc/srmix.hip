@@ -20,7 +20,7 @@
 //   mix_panel_kernel   L_Ik = A_Ik D_k^T for I > k (FP32 matrix cores)
 //   mix_update_kernel  A_IJ -= L_Ik L_Jk^T for k < J <= I: the O(n^3) part, on
 //                      the matrix cores with operands rounded to the format
-//                      (16x16x16 BF16/FP16 or 16x16x4 FP32), FP32 accumulation;
+//                      (16x16x32 BF16/FP16 or 16x16x4 FP32), FP32 accumulation;
 //                      columns outside the current group of four block columns
 //                      take the group's four updates in one pass
 // then L^{-1} by recursive doubling: with groups of s diagonal tiles inverted,
@@ -44,8 +44,9 @@ namespace nqs {
 constexpr int kMixNb = 64;
 constexpr int kMixGroup = 4;   // block columns per trailing update
 
-typedef short mix_s16x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 mix_h16x4 __attribute__((ext_vector_type(4)));
+typedef short mix_s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 mix_b16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 mix_h16x8 __attribute__((ext_vector_type(8)));
 typedef float mix_f32x4 __attribute__((ext_vector_type(4)));
 
 // A = T + shift I, padded with the identity; dg = the diagonal of A
@@ -151,20 +152,21 @@ __device__ __forceinline__ short mix_f16(float v)
     const _Float16 h = (_Float16)v;
     return __builtin_bit_cast(short, h);
 }
+// eight values as codes of the format
 template <int FMT>
-__device__ __forceinline__ mix_s16x4 mix_enc4(float a, float b, float c, float d)
+__device__ __forceinline__ mix_s16x8 mix_enc8(const float (&v)[8])
 {
-    mix_s16x4 r;
-    r[0] = FMT == kBF16 ? mix_bf16(a) : mix_f16(a);
-    r[1] = FMT == kBF16 ? mix_bf16(b) : mix_f16(b);
-    r[2] = FMT == kBF16 ? mix_bf16(c) : mix_f16(c);
-    r[3] = FMT == kBF16 ? mix_bf16(d) : mix_f16(d);
+    mix_s16x8 r;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = FMT == kBF16 ? mix_bf16(v[q]) : mix_f16(v[q]);
     return r;
 }
 
 // acc[x][y] += sum_{kk < 64} As[32 wm + 16 x + i][kk] Bop[kk][32 wn + 16 y + j] for the
 // wave's 32 x 32 quadrant (wm, wn), Bop[kk][j] = BT ? Bs[j][kk] : Bs[kk][j]; operands
-// rounded to the format; block (x, y) element [4 (lane / 16) + r][lane % 16] in acc[x][y][r]
+// rounded to the format; block (x, y) element [4 (lane / 16) + r][lane % 16] in acc[x][y][r].
+// The 16-bit formats use the 32-deep instructions (lane group g = lane / 16 supplies
+// k = 8 g .. 8 g + 7 of each 32-step, the same slots for A and B).
 template <int FMT, bool BT>
 __device__ __forceinline__ void mix_mma_lds(mix_f32x4 (&acc)[2][2], const float (*As)[kMixLd],
                                             const float (*Bs)[kMixLd], int wm, int wn)
@@ -186,31 +188,41 @@ __device__ __forceinline__ void mix_mma_lds(mix_f32x4 (&acc)[2][2], const float 
         }
     } else {
 #pragma unroll
-        for (int k0 = 0; k0 < kMixNb; k0 += 16) {
-            mix_s16x4 a[2], b[2];
+        for (int k0 = 0; k0 < kMixNb; k0 += 32) {
+            mix_s16x8 a[2], b[2];
+            const int kb = k0 + 8 * lk;
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-                const float4 av = *reinterpret_cast<const float4 *>(&As[32 * wm + 16 * x + la][k0 + 4 * lk]);
-                a[x] = mix_enc4<FMT>(av.x, av.y, av.z, av.w);
+                float av[8], bv[8];
+                const float4 a0 = *reinterpret_cast<const float4 *>(&As[32 * wm + 16 * x + la][kb]);
+                const float4 a1 = *reinterpret_cast<const float4 *>(&As[32 * wm + 16 * x + la][kb + 4]);
+                av[0] = a0.x; av[1] = a0.y; av[2] = a0.z; av[3] = a0.w;
+                av[4] = a1.x; av[5] = a1.y; av[6] = a1.z; av[7] = a1.w;
                 const int jj = 32 * wn + 16 * x + la;
                 if constexpr (BT) {
-                    const float4 bv = *reinterpret_cast<const float4 *>(&Bs[jj][k0 + 4 * lk]);
-                    b[x] = mix_enc4<FMT>(bv.x, bv.y, bv.z, bv.w);
+                    const float4 b0 = *reinterpret_cast<const float4 *>(&Bs[jj][kb]);
+                    const float4 b1 = *reinterpret_cast<const float4 *>(&Bs[jj][kb + 4]);
+                    bv[0] = b0.x; bv[1] = b0.y; bv[2] = b0.z; bv[3] = b0.w;
+                    bv[4] = b1.x; bv[5] = b1.y; bv[6] = b1.z; bv[7] = b1.w;
                 } else {
-                    const int kk = k0 + 4 * lk;
-                    b[x] = mix_enc4<FMT>(Bs[kk][jj], Bs[kk + 1][jj], Bs[kk + 2][jj], Bs[kk + 3][jj]);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) bv[q] = Bs[kb + q][jj];
                 }
+                a[x] = mix_enc8<FMT>(av);
+                b[x] = mix_enc8<FMT>(bv);
             }
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
                 for (int y = 0; y < 2; ++y) {
                     if constexpr (FMT == kBF16)
-                        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[x], b[y], acc[x][y], 0, 0, 0);
+                        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(mix_b16x8, a[x]),
+                                                                            __builtin_bit_cast(mix_b16x8, b[y]),
+                                                                            acc[x][y], 0, 0, 0);
                     else
-                        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(mix_h16x4, a[x]),
-                                                                          __builtin_bit_cast(mix_h16x4, b[y]),
-                                                                          acc[x][y], 0, 0, 0);
+                        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(mix_h16x8, a[x]),
+                                                                           __builtin_bit_cast(mix_h16x8, b[y]),
+                                                                           acc[x][y], 0, 0, 0);
                 }
         }
     }
