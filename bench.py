@@ -349,14 +349,18 @@ def run_heis10(a, torch, nqs, workloads):
     out["config"] = {"workload": wl.name, "lattice": "10x10 periodic", "J": 1.0, "marshall": True,
                      "ffnn": [N, w1, w2], "move": "exchange", "chains": C, "sweeps": S, "burnin": B,
                      "proposals_per_step": props, "samples_per_step": S * C, "parallelism": "single GPU"}
-    # dominant contraction of the sampler: layer 2 of the proposed state,
-    # 2 w1 w2 flops per proposal on the matrix cores
-    fpp = 2.0 * w1 * w2
+    # dominant contraction of the sampler: layer 2 of the proposed state, 2 w1 w2 flops per evaluated
+    # proposal on the matrix cores.  An exchange of two equal spins changes nothing and is not evaluated;
+    # at zero magnetisation a uniform ordered pair of distinct sites differs with probability exactly
+    # N / (2 (N - 1)), so that is the fraction of proposals that need the product.
+    eff = N / (2.0 * (N - 1))
+    fpp = 2.0 * w1 * w2 * eff
     achieved = props * fpp / (phases["sample"] * 1e-3) / 1e12
     out["roofline"] = {"kernel": "ffnn_sample_reg_kernel", "bound": "mfma", "achieved": round(achieved, 2),
                        "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
-                       "flops_per_proposal": fpp, "proposals_per_launch": props}
+                       "flops_per_proposal": round(fpp, 1), "evaluated_fraction": round(eff, 4),
+                       "proposals_per_launch": props}
     out["sr_step"] = _sr_step(nqs, torch, step)
     if not a.no_compare:
         out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, a.dtype, True, others=("f16",)))
