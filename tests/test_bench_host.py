@@ -1,0 +1,30 @@
+"""Host-side checks of bench.py (no GPU needed): the one-GPU contract and the
+link between the committed HBM-counter summary and the sampler sources."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one-GPU" in msg["error"]
+
+
+def test_committed_counter_summary_matches_the_sampler_sources():
+    """The sampler's HBM bytes are reported only while its sources hash to the
+    value recorded with the counters; the committed summary must be current."""
+    sys.path.insert(0, ROOT)
+    import bench
+    got = bench.kernel_traffic("rbm_sample_kernel", "tfim2d_10x10_rbm_bf16_hbm_traffic.txt")
+    if got is None:
+        pytest.skip("the committed counter summary predates the current sampler sources: bench.py reports "
+                    "traffic as null until the counters are taken again")
+    assert got > 4.0e8   # the 409.6 MB of samples plus tables and state
