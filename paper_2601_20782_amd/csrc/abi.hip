@@ -351,11 +351,10 @@ nqs_status nqs_local_energy_complex(nqs_model *m, const nqs_ham_desc *ham, const
 {
     if (!m || !ham) return set_error(NQS_EINVAL, "NULL model or hamiltonian");
     if (m->desc.arch != NQS_CRBM) {
-        if (eloc_im && n_samples > 0) {
-            const nqs_status z = launch_zero_u64(reinterpret_cast<uint64_t *>(eloc_im), n_samples, (hipStream_t)stream);
-            if (z != NQS_OK) return z;
-        }
-        return nqs_local_energy(m, ham, samples, n_samples, eval_dtype, eloc_re, stream);
+        // real amplitudes: the real part validates the arguments; the imaginary part is zero
+        const nqs_status st = nqs_local_energy(m, ham, samples, n_samples, eval_dtype, eloc_re, stream);
+        if (st != NQS_OK || !eloc_im || n_samples <= 0) return st;
+        return launch_zero_u64(reinterpret_cast<uint64_t *>(eloc_im), n_samples, (hipStream_t)stream);
     }
     if (n_samples < 0) return set_error(NQS_EINVAL, "n_samples < 0");
     if (n_samples == 0) return NQS_OK;

@@ -111,12 +111,20 @@ extern "C" nqs_status nqs_probe_rate(int32_t kind, int64_t size, const void *src
                                      void *stream)
 {
     if (!work) return set_error(NQS_EINVAL, "NULL work");
+    const bool compute = kind >= NQS_PROBE_FMA_F32 && kind <= NQS_PROBE_MFMA_F64;
+    const bool memory = kind == NQS_PROBE_HBM_READ || kind == NQS_PROBE_HBM_COPY;
+    if (!compute && !memory) return set_error(NQS_EINVAL, "unknown probe kind");
+    if (compute && (size < 1 || size > (1 << 24))) return set_error(NQS_EINVAL, "iterations must be in [1, 2^24]");
+    if (compute && !dst) return set_error(NQS_EINVAL, "NULL scratch");
+    if (memory) {
+        if (size <= 0 || size % 16 != 0) return set_error(NQS_EINVAL, "size must be a positive multiple of 16");
+        if (!src || ((uintptr_t)src & 15)) return set_error(NQS_EINVAL, "src must be 16-byte aligned");
+        if (!dst || ((uintptr_t)dst & 15)) return set_error(NQS_EINVAL, "dst must be 16-byte aligned");
+    }
     hipStream_t s = (hipStream_t)stream;
     const int blocks = device_cus() * 8;
     const double threads = (double)blocks * kProbeThreads;
-    if (kind >= NQS_PROBE_FMA_F32 && kind <= NQS_PROBE_MFMA_F64) {
-        if (size < 1 || size > (1 << 24)) return set_error(NQS_EINVAL, "iterations must be in [1, 2^24]");
-        if (!dst) return set_error(NQS_EINVAL, "NULL scratch");
+    if (compute) {
         float *o = (float *)dst;
         const int it = (int)size;
         const double per = (double)it * kProbeUnroll;
@@ -150,10 +158,7 @@ extern "C" nqs_status nqs_probe_rate(int32_t kind, int64_t size, const void *src
             *work = threads / 64 * per * 4 * (2.0 * 16 * 16 * 4);
             break;
         }
-    } else if (kind == NQS_PROBE_HBM_READ || kind == NQS_PROBE_HBM_COPY) {
-        if (size <= 0 || size % 16 != 0) return set_error(NQS_EINVAL, "size must be a positive multiple of 16");
-        if (!src || ((uintptr_t)src & 15)) return set_error(NQS_EINVAL, "src must be 16-byte aligned");
-        if (!dst || ((uintptr_t)dst & 15)) return set_error(NQS_EINVAL, "dst must be 16-byte aligned");
+    } else {
         const int64_t n4 = size / 16;
         const int mb = blocks * 2;
         if (kind == NQS_PROBE_HBM_READ) {
@@ -165,8 +170,6 @@ extern "C" nqs_status nqs_probe_rate(int32_t kind, int64_t size, const void *src
                                (float4 *)dst);
             *work = 2.0 * (double)size;
         }
-    } else {
-        return set_error(NQS_EINVAL, "unknown probe kind");
     }
     NQS_HIP_TRY(hipGetLastError());
     return NQS_OK;

@@ -79,6 +79,40 @@ def test_calls_without_model_are_rejected(lib):
     assert lib.nqs_downcast(None, 0, 1, None, None, None) == _abi.NQS_OK   # empty input is a no-op
 
 
+def test_new_entry_points_reject_bad_arguments(lib):
+    """The SR solves, the complex local energies and the rate probes validate
+    their arguments before any device work."""
+    from paper_2601_20782_amd import _abi
+    it, rr = ctypes.c_int32(0), ctypes.c_double(0.0)
+    nf, fu = ctypes.c_int64(0), ctypes.c_int32(0)
+    fake = ctypes.c_void_p(16)
+    # n = 0, a NULL T, a negative shift, an unsupported factor format
+    assert lib.nqs_sr_solve_mixed(fake, fake, 0, 1e-2, _abi.BF16, 1e-8, 10, fake, ctypes.byref(it), ctypes.byref(rr),
+                                  ctypes.byref(nf), ctypes.byref(fu), None) == _abi.NQS_EINVAL
+    assert lib.nqs_sr_solve_mixed(None, fake, 8, 1e-2, _abi.BF16, 1e-8, 10, fake, ctypes.byref(it), ctypes.byref(rr),
+                                  ctypes.byref(nf), ctypes.byref(fu), None) == _abi.NQS_EINVAL
+    assert lib.nqs_sr_solve_mixed(fake, fake, 8, -1.0, _abi.BF16, 1e-8, 10, fake, ctypes.byref(it), ctypes.byref(rr),
+                                  ctypes.byref(nf), ctypes.byref(fu), None) == _abi.NQS_EINVAL
+    for fmt in (_abi.F64, _abi.FP8_E4M3, 9):
+        assert lib.nqs_sr_solve_mixed(fake, fake, 8, 1e-2, fmt, 1e-8, 10, fake, ctypes.byref(it), ctypes.byref(rr),
+                                      ctypes.byref(nf), ctypes.byref(fu), None) == _abi.NQS_EINVAL
+    assert b"factor dtype" in lib.nqs_last_error()
+    assert lib.nqs_sr_solve_mixed(fake, fake, 70000, 1e-2, _abi.F32, 1e-8, 10, fake, ctypes.byref(it),
+                                  ctypes.byref(rr), ctypes.byref(nf), ctypes.byref(fu), None) == _abi.NQS_EINVAL
+    # complex local energies without a model
+    h = _abi.HamDesc()
+    assert lib.nqs_local_energy_complex(None, ctypes.byref(h), fake, 4, _abi.F32, fake, fake, None) == _abi.NQS_EINVAL
+    # probes: unknown kind, bad sizes, unaligned or missing buffers, NULL work
+    w = ctypes.c_double(0.0)
+    assert lib.nqs_probe_rate(99, 10, None, fake, ctypes.byref(w), None) == _abi.NQS_EINVAL
+    assert lib.nqs_probe_rate(_abi.PROBE_KINDS["fma_f32"], 0, None, fake, ctypes.byref(w), None) == _abi.NQS_EINVAL
+    assert lib.nqs_probe_rate(_abi.PROBE_KINDS["fma_f32"], 10, None, None, ctypes.byref(w), None) == _abi.NQS_EINVAL
+    assert lib.nqs_probe_rate(_abi.PROBE_KINDS["hbm_read"], 24, fake, fake, ctypes.byref(w), None) == _abi.NQS_EINVAL
+    assert lib.nqs_probe_rate(_abi.PROBE_KINDS["hbm_copy"], 32, ctypes.c_void_p(20), fake, ctypes.byref(w),
+                              None) == _abi.NQS_EINVAL
+    assert lib.nqs_probe_rate(_abi.PROBE_KINDS["fma_f32"], 10, None, fake, None, None) == _abi.NQS_EINVAL
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     from paper_2601_20782_amd import _abi
     monkeypatch.setattr(_abi, "_lib", None)
