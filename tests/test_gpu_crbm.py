@@ -188,3 +188,18 @@ def test_rejections(nqs):
     wide = nqs.Model("crbm", N, (600,), workloads.crbm_params(N, 600, 0.1, 0.1, 1))
     with pytest.raises(nqs.NqsError):   # more than 8 hidden units per lane at 64 lanes
         nqs.nqs_sample(wide, nqs.SampleConfig(n_chains=4, n_sweeps=1), state)
+
+
+def test_complex_entry_on_a_real_model(nqs):
+    """For a real-parameter network the complex entry point returns the real local
+    energies and an imaginary part of exactly zero."""
+    N, M = 16, 16
+    model = nqs.Model("rbm", N, (M,), workloads.rbm_params(N, M, 0.1, 3))
+    x = torch.from_numpy(workloads.random_spins(20, N, 4)).to(DEV)
+    ham = nqs.Hamiltonian("tfim", 1, N, 1.0, 0.9, True)
+    re = torch.empty(20, dtype=torch.float64, device=DEV)
+    im = torch.full((20,), float("nan"), dtype=torch.float64, device=DEV)
+    ref = torch.empty(20, dtype=torch.float64, device=DEV)
+    nqs.nqs_local_energy_complex(model, ham, x, re, im)
+    nqs.nqs_local_energy(model, ham, x, ref)
+    assert torch.equal(re, ref) and torch.count_nonzero(im).item() == 0
