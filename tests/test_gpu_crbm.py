@@ -31,10 +31,11 @@ def _say(msg):
 
 
 # (format, N, M, chains, lanes per chain): 16, 32 and 64 lanes per chain, one to
-# seven hidden units per lane, the (C, S) table in LDS and (from 160 KB on) in L2
+# seven hidden units per lane, the (C, S) table in LDS and (from 160 KB on) in L2,
+# two spin words (N = 33, 64) and a single hidden unit
 @pytest.mark.parametrize("dtype,N,M,C,G", [("f32", 12, 24, 10, 0), ("bf16", 12, 24, 10, 64), ("f16", 20, 70, 9, 0),
                                            ("f32", 30, 130, 5, 0), ("f32", 100, 110, 4, 0), ("bf16", 40, 300, 4, 0),
-                                           ("f32", 70, 200, 3, 32)])
+                                           ("f32", 70, 200, 3, 32), ("f32", 33, 1, 6, 0), ("bf16", 64, 17, 4, 0)])
 def test_decisions_replay_in_fp64(nqs, dtype, N, M, C, G):
     p = workloads.crbm_params(N, M, 0.2, 0.4, N + M)
     model = nqs.Model("crbm", N, (M,), p)

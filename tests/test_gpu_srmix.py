@@ -36,9 +36,11 @@ def _system(n, P, seed):
     return T32, eps
 
 
-# n = 64 (one tile), 300 (ragged: five tiles, the last one partly padding), 1000 (16 tiles)
+# n = 64 (one tile), 65 and 129 (a last tile of one row), 300 (five tiles, the last one partly
+# padding), 1000 (16 tiles)
 @pytest.mark.parametrize("fmt", ["f32", "bf16", "f16"])
-@pytest.mark.parametrize("n,P,shift", [(64, 80, 1e-3), (300, 500, 1e-2), (1000, 1500, 1e-3)])
+@pytest.mark.parametrize("n,P,shift", [(64, 80, 1e-3), (65, 90, 1e-2), (129, 200, 1e-2), (300, 500, 1e-2),
+                                       (1000, 1500, 1e-3)])
 def test_mixed_solve_matches_dense_solve(nqs, fmt, n, P, shift):
     T32, eps = _system(n, P, n + P)
     T = torch.from_numpy(T32).to(DEV)
