@@ -9,6 +9,8 @@
 //
 // nqs_sr_solve: Jacobi-preconditioned conjugate gradients, FP64 vectors and
 //   scalars, FP32 T read once per iteration (one wave per row, FP64 sums).
+//   Up to n = 65536 an iteration is two launches: the product with its
+//   per-row p.Ap, then one block for the scalars and the vector updates.
 //   Every reduction is a fixed-order single-block tree, so the iterates do
 //   not depend on timing.  Scalars stay on the device (one slot per
 //   iteration); the host reads the residual every kCheck iterations.
@@ -27,6 +29,7 @@ namespace nqs {
 
 constexpr int kSumThreads = 1024;
 constexpr int kCheck = 8;
+constexpr int64_t kFusedMax = 65536;   // the one-block iteration of the Jacobi CG up to this n
 
 // out[0] = sum_k a[k] * (b ? b[k] : 1), one block, fixed order
 __global__ void __launch_bounds__(kSumThreads) sr_dot_kernel(const double *__restrict__ a,
@@ -61,6 +64,74 @@ __global__ void __launch_bounds__(256) sr_matvec_kernel(const float *__restrict_
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0) Ap[row] = s + shift * p[row];
+}
+
+// Ap = (T + shift) p as sr_matvec_kernel, plus pr[row] = p[row] Ap[row]
+__global__ void __launch_bounds__(256) sr_matvec_dot_kernel(const float *__restrict__ T, const double *__restrict__ p,
+                                                            int64_t n, double shift, double *__restrict__ Ap,
+                                                            double *__restrict__ pr)
+{
+    const int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const float *t = T + row * n;
+    double s = 0.0;
+    for (int64_t k = lane; k < n; k += 64) s = fma((double)t[k], p[k], s);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) {
+        const double a = s + shift * p[row];
+        Ap[row] = a;
+        pr[row] = p[row] * a;
+    }
+}
+
+// fixed-order sum of v[0..n) by one block of kSumThreads (every thread returns the total)
+__device__ inline double sr_block_sum(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kSumThreads / 2; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double t = red[0];
+    __syncthreads();
+    return t;
+}
+
+// The rest of Jacobi-preconditioned CG iteration k in one block: pAp from the
+// per-row products, alpha, x += alpha p, r -= alpha Ap, z = r d, rz[k + 1] =
+// r.z, rr[k] = r.r, beta, p = z + beta p.
+__global__ void __launch_bounds__(kSumThreads) sr_iter_kernel(const double *__restrict__ pr, const double *__restrict__ Ap,
+                                                              const double *__restrict__ d, int64_t n, int k,
+                                                              double *__restrict__ rz, double *__restrict__ rr,
+                                                              double *__restrict__ x, double *__restrict__ r,
+                                                              double *__restrict__ z, double *__restrict__ p)
+{
+    __shared__ double red[kSumThreads];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kSumThreads) a += pr[i];
+    const double pap = sr_block_sum(a, red);
+    const double alpha = pap != 0.0 ? rz[k] / pap : 0.0;
+    double zr = 0.0, q = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kSumThreads) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = fma(-alpha, Ap[i], r[i]);
+        const double zi = ri * d[i];
+        r[i] = ri;
+        z[i] = zi;
+        zr = fma(ri, zi, zr);
+        q = fma(ri, ri, q);
+    }
+    const double rz1 = sr_block_sum(zr, red);
+    const double rr1 = sr_block_sum(q, red);
+    const double beta = rz[k] != 0.0 ? rz1 / rz[k] : 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kSumThreads) p[i] = fma(beta, p[i], z[i]);
+    if (threadIdx.x == 0) {
+        rz[k + 1] = rz1;
+        rr[k] = rr1;
+    }
 }
 
 // b = eps - mean (sum[0] = sum of eps); x = 0, r = b; with d: d = 1 / (diag(T) + shift), z = r d, p = z
@@ -139,13 +210,14 @@ nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double sh
     hipStream_t s = (hipStream_t)stream;
     const size_t vec = r256(sizeof(double) * (size_t)n);
     const size_t nsc = (size_t)max_iter + 2;
-    char *ws = (char *)workspace_slot(1, 5 * vec + 3 * r256(sizeof(double) * nsc) + 256, s);
+    char *ws = (char *)workspace_slot(1, 6 * vec + 3 * r256(sizeof(double) * nsc) + 256, s);
     if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
     double *d = (double *)ws, *r = (double *)(ws + vec), *z = (double *)(ws + 2 * vec), *p = (double *)(ws + 3 * vec),
-           *Ap = (double *)(ws + 4 * vec);
-    double *rz = (double *)(ws + 5 * vec);                       // rz[k]: r.z after k iterations
-    double *pap = rz + r256(sizeof(double) * nsc) / sizeof(double);
+           *Ap = (double *)(ws + 4 * vec), *prow = (double *)(ws + 5 * vec);
+    double *rz = (double *)(ws + 6 * vec);                       // rz[k]: r.z after k iterations
+    double *pap = rz + r256(sizeof(double) * nsc) / sizeof(double);     // p.Ap, or r.r in the fused path
     double *misc = pap + r256(sizeof(double) * nsc) / sizeof(double);   // [0] sum of eps, [1] b.b, [2] r.r
+    double *rrs = pap;
     const unsigned eb = (unsigned)((n + 255) / 256), mb = (unsigned)((n + 3) / 4);
 
     hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, eloc, (const double *)nullptr, n, misc);
@@ -158,7 +230,24 @@ nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double sh
     NQS_HIP_TRY(hipStreamSynchronize(s));
     double rel = 0.0;
     int k = 0;
-    if (bb > 0.0) {
+    if (bb > 0.0 && n <= kFusedMax) {
+        // two launches per iteration: the matrix-vector product with its per-row p.Ap, then one block for
+        // the rest; r.r of every iteration is kept, the host reads it every kCheck iterations
+        rel = 1.0;
+        while (k < max_iter) {
+            hipLaunchKernelGGL(sr_matvec_dot_kernel, dim3(mb), dim3(256), 0, s, T, p, n, shift, Ap, prow);
+            hipLaunchKernelGGL(sr_iter_kernel, dim3(1), dim3(kSumThreads), 0, s, prow, Ap, d, n, k, rz, rrs, y, r, z, p);
+            ++k;
+            if (k % kCheck == 0 || k == max_iter) {
+                NQS_HIP_TRY(hipGetLastError());
+                double rr = 0.0;
+                NQS_HIP_TRY(hipMemcpyAsync(&rr, rrs + (k - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+                NQS_HIP_TRY(hipStreamSynchronize(s));
+                rel = std::sqrt(rr / bb);
+                if (!(rel > tol)) break;   // converged (or NaN: stop and report it)
+            }
+        }
+    } else if (bb > 0.0) {
         rel = 1.0;
         while (k < max_iter) {
             hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, T, n, p, n, shift, 0, Ap);
