@@ -56,6 +56,7 @@ def test_decisions_replay_in_fp64(nqs, dtype, N, M, C, G):
     net = crbm.ComplexRBM(N, M, p, dtype)
     tol = {"f32": 2e-5, "bf16": 2e-5, "f16": 2e-5}[dtype]
     near, max_err = 0, 0.0
+    emitted = np.empty((S, T, N), dtype=np.int8)   # the replay's own state at the end of each measured sweep
     for c in range(T):
         x = oracle.init_chain(N, "flip", 6, c).copy()
         l0 = net.logpsi(x[None])[0]
@@ -78,9 +79,13 @@ def test_decisions_replay_in_fp64(nqs, dtype, N, M, C, G):
                 near += 1
             if r["accepted"][c, k]:
                 x, l0 = y, l1
-    # the FP64 log|psi| of the emitted samples
-    lp_ref = net.logamp(samples.cpu().numpy().reshape(-1, N))[0]
-    assert np.max(np.abs(logpsi.cpu().numpy().ravel() - lp_ref) / (1 + np.abs(lp_ref))) < 1e-4
+            if (k + 1) % N == 0 and (k + 1) // N > B:
+                emitted[(k + 1) // N - 1 - B, c] = x
+    # the traced chains' samples are the replay's states, and their log|psi| is the oracle's FP64 value there
+    assert np.array_equal(samples[:, :T].cpu().numpy(), emitted)
+    lp_ref = net.logamp(emitted.reshape(-1, N))[0].reshape(S, T)
+    got = logpsi[:, :T].cpu().numpy()
+    assert np.max(np.abs(got - lp_ref) / (1 + np.abs(lp_ref))) < 1e-4
     _say(f"  {dtype} N={N} M={M}: max relative |dDelta| {max_err:.2e}, {near} near ties")
 
 
