@@ -38,6 +38,10 @@ Other workloads (--workload):
   crbm     complex-parameter RBM on the 10x10 TFIM (M = 200), 4096 chains x
            (10 + 100) sweeps, beside the real RBM sampler at the same shape;
            complex local energies of the emitted samples.
+  srstudy  SR regularisation study (App. I.2): an RBM on the 16-site critical TFIM
+           chain trained with shifts 1e-3 and 1e-1, FP32 / BF16 sampling / BF16
+           local energies; energy error against the exact ground energy and the
+           condition number of S + shift along the optimisation.
   peaks    achievable rates of the device (FP32 FMA, log2/exp2, matrix cores in
            BF16/FP32/FP64, HBM read and copy) next to the published peaks.
 """
@@ -67,7 +71,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20", "noise", "rescnn", "crbm", "peaks"])
+    ap.add_argument("--workload", default="tfim10", choices=["tfim10", "heis10", "uneven", "heis20", "noise", "rescnn", "crbm", "peaks", "srstudy"])
     ap.add_argument("--sweeps", type=int, default=0, help="heis20: measured sweeps per step (default 1)")
     ap.add_argument("--gram-samples", type=int, default=4096, help="heis20: samples in T (0 = skip)")
     ap.add_argument("--gram-chunked", action="store_true", help="heis20: T by parameter column blocks")
@@ -833,6 +837,76 @@ def run_peaks(a, torch, nqs, workloads):
     }
 
 
+def run_srstudy(a, torch, nqs, workloads):
+    """The SR regularisation study of App. I.2 at a size exact diagonalisation reaches: an RBM (alpha = 1) on
+    the 16-site TFIM chain at the critical field, trained by SR with Tikhonov shifts 1e-3 and 1e-1, three
+    ways: the reference (FP32 sampling copy, FP32 local energies), BF16 sampling, and BF16 local energies
+    (the reduced-precision forces of the paper's study).  Per run: the relative energy error against the
+    exact ground energy along the optimisation, and the condition number of S + shift (S formed in FP64 on
+    the host from the library's log-derivatives every 10 steps)."""
+    dev = torch.device("cuda:0")
+    N, M, J, h = 16, 16, 1.0, -1.0            # h/J = 1 (critical), stoquastic sign
+    steps, lr = 150, 0.05
+    C, S = 256, 4
+    n = C * S
+    k = np.pi * (2 * np.arange(N) + 1) / N     # free-fermion ground energy of the periodic chain
+    e0 = -float(np.sum(np.sqrt(J * J + h * h - 2 * J * abs(h) * np.cos(k))))
+    ham = nqs.Hamiltonian("tfim", 1, N, J, h, True)
+    state = torch.empty(C, N, dtype=torch.int8, device=dev)
+    samples = torch.empty(S, C, N, dtype=torch.int8, device=dev)
+    eloc = torch.empty(n, dtype=torch.float64, device=dev)
+    T = torch.empty(n, n, dtype=torch.float32, device=dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    runs = []
+    t0 = time.perf_counter()
+    for shift in (1e-3, 1e-1):
+        for variant, sdt, edt in (("reference", "f32", "f32"), ("bf16_sampling", "bf16", "f32"),
+                                  ("bf16_local_energies", "f32", "bf16")):
+            p = workloads.rbm_params(N, M, 0.01, 5)
+            model = nqs.Model("rbm", N, (M,), p)
+            P = model.n_params
+            O = torch.empty(n, P, dtype=torch.float32, device=dev)
+            master = torch.from_numpy(p.copy()).to(dev)
+            offset, traj, kappa, iters = 0, [], [], []
+            for it in range(steps):
+                model.set_params_device(master)
+                model.prepare(sdt)
+                burn = 20 if it == 0 else 2
+                cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=burn, seed=5, step_offset=offset,
+                                       init_chains=it == 0, dtype=sdt)
+                nqs.nqs_sample(model, cfg, state, samples)
+                offset += (burn + S) * N
+                flat = samples.reshape(n, N)
+                nqs.nqs_local_energy(model, ham, flat, eloc, edt)
+                e = float(eloc.mean().item())
+                if it % 10 == 0 or it == steps - 1:
+                    nqs.nqs_logpsi_grad(model, flat, O=O)
+                    Oc = O.cpu().numpy().astype(np.float64)
+                    Oc -= Oc.mean(axis=0)
+                    ev = np.linalg.eigvalsh(Oc.T @ Oc / n)
+                    kappa.append({"step": it, "kappa": float((ev[-1] + shift) / (max(ev[0], 0.0) + shift))})
+                    traj.append({"step": it, "rel_err": abs(e - e0) / abs(e0)})
+                nqs.nqs_sample_gram_factored(model, flat, T)
+                its, _ = nqs.nqs_sr_solve(T, eloc, shift, y, tol=1e-8, max_iter=3000)
+                iters.append(its)
+                nqs.nqs_sr_update(model, flat, y, lr, master)
+            model.close()
+            runs.append({"shift": shift, "variant": variant, "final_rel_err": traj[-1]["rel_err"],
+                         "energy_rel_err": traj, "kappa_S_plus_shift": kappa,
+                         "cg_iterations_mean": float(np.mean(iters))})
+    wall = time.perf_counter() - t0
+    return {
+        "metric": "SR study: relative energy error against exact diagonalisation", "value": None,
+        "unit": "relative error", "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": 1e3 * wall / (6 * steps),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "mixed",
+        "data": "synthetic (RBM trained here by SR)",
+        "config": {"workload": "sr_study_tfim1d_n16", "sites": N, "rbm_hidden": M, "h_over_J": abs(h / J),
+                   "samples_per_step": n, "learning_rate": lr, "exact_ground_energy": e0,
+                   "parallelism": "single GPU"},
+        "runs": runs,
+    }
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -852,7 +926,7 @@ def main():
     import paper_2601_20782_amd as nqs
     import workloads
     run = {"tfim10": run_tfim10, "heis10": run_heis10, "uneven": run_uneven, "heis20": run_heis20,
-           "noise": run_noise, "rescnn": run_rescnn, "crbm": run_crbm, "peaks": run_peaks}[a.workload]
+           "noise": run_noise, "rescnn": run_rescnn, "crbm": run_crbm, "peaks": run_peaks, "srstudy": run_srstudy}[a.workload]
     print(json.dumps(run(a, torch, nqs, workloads)))
 
 
