@@ -840,8 +840,9 @@ def run_peaks(a, torch, nqs, workloads):
 def run_srstudy(a, torch, nqs, workloads):
     """The SR regularisation study of App. I.2 at a size exact diagonalisation reaches: an RBM (alpha = 1) on
     the 16-site TFIM chain at the critical field, trained by SR with Tikhonov shifts 1e-3 and 1e-1, three
-    ways: the reference (FP32 sampling copy, FP32 local energies), BF16 sampling, and BF16 local energies
-    (the reduced-precision forces of the paper's study).  Per run: the relative energy error against the
+    ways: the reference (FP32 sampling copy, FP32 local energies), BF16 sampling, BF16 local energies (the
+    reduced-precision forces of the paper's study), and both in FP8 E4M3 (log-derivatives and the solve stay
+    FP32 / FP64).  Per run: the relative energy error against the
     exact ground energy along the optimisation, and the condition number of S + shift (S formed in FP64 on
     the host from the library's log-derivatives every 10 steps)."""
     dev = torch.device("cuda:0")
@@ -861,7 +862,7 @@ def run_srstudy(a, torch, nqs, workloads):
     t0 = time.perf_counter()
     for shift in (1e-3, 1e-1):
         for variant, sdt, edt in (("reference", "f32", "f32"), ("bf16_sampling", "bf16", "f32"),
-                                  ("bf16_local_energies", "f32", "bf16")):
+                                  ("bf16_local_energies", "f32", "bf16"), ("fp8_sampling_and_local_energies", "e4m3", "e4m3")):
             p = workloads.rbm_params(N, M, 0.01, 5)
             model = nqs.Model("rbm", N, (M,), p)
             P = model.n_params
@@ -897,7 +898,7 @@ def run_srstudy(a, torch, nqs, workloads):
     wall = time.perf_counter() - t0
     return {
         "metric": "SR study: relative energy error against exact diagonalisation", "value": None,
-        "unit": "relative error", "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": 1e3 * wall / (6 * steps),
+        "unit": "relative error", "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": 1e3 * wall / (len(runs) * steps),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "mixed",
         "data": "synthetic (RBM trained here by SR)",
         "config": {"workload": "sr_study_tfim1d_n16", "sites": N, "rbm_hidden": M, "h_over_J": abs(h / J),
