@@ -28,3 +28,13 @@ def test_committed_counter_summary_matches_the_sampler_sources():
         pytest.skip("the committed counter summary predates the current sampler sources: bench.py reports "
                     "traffic as null until the counters are taken again")
     assert got > 4.0e8   # the 409.6 MB of samples plus tables and state
+
+
+def test_bench_average_bound_matches_the_oracle():
+    """The noise workload reports the average bound of Thm 3.3 at mu = 0, r = 0
+    from its own closed form; it must equal the oracle's pinned formula."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from oracle import exact
+    for sigma in (0.0, 0.01, 0.1, 0.3, 1.0, 2.0):
+        assert abs(bench._avg_bound(sigma) - exact.avg_bound(sigma)) <= 1e-12
