@@ -868,7 +868,7 @@ def run_srstudy(a, torch, nqs, workloads):
             P = model.n_params
             O = torch.empty(n, P, dtype=torch.float32, device=dev)
             master = torch.from_numpy(p.copy()).to(dev)
-            offset, traj, kappa, iters = 0, [], [], []
+            offset, traj, kappa, iters, energies = 0, [], [], [], []
             for it in range(steps):
                 model.set_params_device(master)
                 model.prepare(sdt)
@@ -880,6 +880,7 @@ def run_srstudy(a, torch, nqs, workloads):
                 flat = samples.reshape(n, N)
                 nqs.nqs_local_energy(model, ham, flat, eloc, edt)
                 e = float(eloc.mean().item())
+                energies.append(e)
                 if it % 10 == 0 or it == steps - 1:
                     nqs.nqs_logpsi_grad(model, flat, O=O)
                     Oc = O.cpu().numpy().astype(np.float64)
@@ -892,7 +893,10 @@ def run_srstudy(a, torch, nqs, workloads):
                 iters.append(its)
                 nqs.nqs_sr_update(model, flat, y, lr, master)
             model.close()
-            runs.append({"shift": shift, "variant": variant, "final_rel_err": traj[-1]["rel_err"],
+            last = np.array(energies[-10:])
+            runs.append({"shift": shift, "variant": variant,
+                         "final_rel_err": abs(float(last.mean()) - e0) / abs(e0),
+                         "final_rel_err_se": float(last.std(ddof=1) / np.sqrt(last.size)) / abs(e0),
                          "energy_rel_err": traj, "kappa_S_plus_shift": kappa,
                          "cg_iterations_mean": float(np.mean(iters))})
     wall = time.perf_counter() - t0
