@@ -8,7 +8,7 @@
 // vector-Jacobian product of the log-derivatives.
 //
 // nqs_sr_solve: Jacobi-preconditioned conjugate gradients, FP64 vectors and
-//   scalars, FP32 T read once per iteration (one wave per row, FP64 sums).
+//   scalars, FP32 T read once per iteration (four rows per wave, FP64 sums).
 //   Up to n = 65536 an iteration is two launches: the product with its
 //   per-row p.Ap, then one block for the scalars and the vector updates.
 //   Every reduction is a fixed-order single-block tree, so the iterates do
@@ -66,24 +66,71 @@ __global__ void __launch_bounds__(256) sr_matvec_kernel(const float *__restrict_
     if (lane == 0) Ap[row] = s + shift * p[row];
 }
 
-// Ap = (T + shift) p as sr_matvec_kernel, plus pr[row] = p[row] Ap[row]
-__global__ void __launch_bounds__(256) sr_matvec_dot_kernel(const float *__restrict__ T, const double *__restrict__ p,
-                                                            int64_t n, double shift, double *__restrict__ Ap,
-                                                            double *__restrict__ pr)
+// Ap = (T + shift) p over all n columns, four consecutive rows per wave (T's
+// row count is n, leading dimension ld); pr[row] = p[row] Ap[row] when pr is
+// given.  Each lane reads T four floats at a time from every row and p once
+// per column group for all four rows, when vec says T's rows and p are 16-byte
+// aligned; otherwise element by element.  Rows past n read row n - 1 and store
+// nothing.
+constexpr int kRowsPerWave = 4;
+
+__global__ void __launch_bounds__(256) sr_matvec_rows_kernel(const float *__restrict__ T, int64_t ld,
+                                                             const double *__restrict__ p, int64_t n, double shift,
+                                                             int vec, double *__restrict__ Ap, double *__restrict__ pr)
 {
-    const int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    constexpr int R = kRowsPerWave;
+    const int64_t row0 = (blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6)) * R;
     const int lane = threadIdx.x & 63;
-    if (row >= n) return;
-    const float *t = T + row * n;
-    double s = 0.0;
-    for (int64_t k = lane; k < n; k += 64) s = fma((double)t[k], p[k], s);
+    if (row0 >= n) return;
+    const float *t[R];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) {
-        const double a = s + shift * p[row];
-        Ap[row] = a;
-        pr[row] = p[row] * a;
+    for (int r = 0; r < R; ++r) t[r] = T + std::min<int64_t>(row0 + r, n - 1) * ld;
+    double s[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[r] = 0.0;
+    int64_t k0 = 0;
+    if (vec) {
+        const int64_t n4 = n >> 2;
+#pragma unroll 2
+        for (int64_t q = lane; q < n4; q += 64) {
+            const double2 pa = *(const double2 *)(p + 4 * q), pb = *(const double2 *)(p + 4 * q + 2);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float4 v = *(const float4 *)(t[r] + 4 * q);
+                s[r] = fma((double)v.x, pa.x, s[r]);
+                s[r] = fma((double)v.y, pa.y, s[r]);
+                s[r] = fma((double)v.z, pb.x, s[r]);
+                s[r] = fma((double)v.w, pb.y, s[r]);
+            }
+        }
+        k0 = n4 << 2;
     }
+    for (int64_t k = k0 + lane; k < n; k += 64) {
+        const double pk = p[k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] = fma((double)t[r][k], pk, s[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s[r] += __shfl_xor(s[r], o, 64);
+    }
+    if (lane < R && row0 + lane < n) {
+        double sl = s[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) sl = lane == r ? s[r] : sl;
+        const int64_t row = row0 + lane;
+        const double a = sl + shift * p[row];
+        Ap[row] = a;
+        if (pr) pr[row] = p[row] * a;
+    }
+}
+
+// grid of sr_matvec_rows_kernel for n rows, and whether its vector loads apply
+inline unsigned sr_rows_blocks(int64_t n) { return (unsigned)((n + 4 * kRowsPerWave - 1) / (4 * kRowsPerWave)); }
+inline int sr_rows_vec(const float *T, int64_t ld, const double *p)
+{
+    return ((uintptr_t)T % 16 == 0 && ld % 4 == 0 && (uintptr_t)p % 16 == 0) ? 1 : 0;
 }
 
 // fixed-order sum of v[0..n) by one block of kSumThreads (every thread returns the total)
@@ -218,7 +265,9 @@ nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double sh
     double *pap = rz + r256(sizeof(double) * nsc) / sizeof(double);     // p.Ap, or r.r in the fused path
     double *misc = pap + r256(sizeof(double) * nsc) / sizeof(double);   // [0] sum of eps, [1] b.b, [2] r.r
     double *rrs = pap;
-    const unsigned eb = (unsigned)((n + 255) / 256), mb = (unsigned)((n + 3) / 4);
+    const unsigned eb = (unsigned)((n + 255) / 256);
+    const unsigned rb = sr_rows_blocks(n);
+    const int rv = sr_rows_vec(T, n, p);
 
     hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, eloc, (const double *)nullptr, n, misc);
     hipLaunchKernelGGL(sr_init_kernel, dim3(eb), dim3(256), 0, s, T, eloc, misc, n, shift, d, y, r, z, p);
@@ -235,7 +284,8 @@ nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double sh
         // the rest; r.r of every iteration is kept, the host reads it every kCheck iterations
         rel = 1.0;
         while (k < max_iter) {
-            hipLaunchKernelGGL(sr_matvec_dot_kernel, dim3(mb), dim3(256), 0, s, T, p, n, shift, Ap, prow);
+            hipLaunchKernelGGL(sr_matvec_rows_kernel, dim3(rb), dim3(256), 0, s, T, n, (const double *)p, n, shift,
+                               rv, Ap, prow);
             hipLaunchKernelGGL(sr_iter_kernel, dim3(1), dim3(kSumThreads), 0, s, prow, Ap, d, n, k, rz, rrs, y, r, z, p);
             ++k;
             if (k % kCheck == 0 || k == max_iter) {
@@ -250,7 +300,8 @@ nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double sh
     } else if (bb > 0.0) {
         rel = 1.0;
         while (k < max_iter) {
-            hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, T, n, p, n, shift, 0, Ap);
+            hipLaunchKernelGGL(sr_matvec_rows_kernel, dim3(rb), dim3(256), 0, s, T, n, (const double *)p, n, shift,
+                               rv, Ap, (double *)nullptr);
             hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, p, Ap, n, pap + k);
             hipLaunchKernelGGL(sr_step_kernel, dim3(eb), dim3(256), 0, s, rz + k, pap + k, n, d, p, Ap, y, r, z);
             hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, r, z, n, rz + k + 1);
@@ -296,6 +347,8 @@ nqs_status nqs_sr_solve_mixed(const float *T, const double *eloc, int64_t n, dou
     double *misc = pap + r256(sizeof(double) * nsc) / sizeof(double);   // [0] sum of eps, [1] b.b, [2] r.r, [3] pivots
     unsigned long long *nfix = (unsigned long long *)(misc + 3);
     const unsigned eb = (unsigned)((n + 255) / 256), mb = (unsigned)((n + 3) / 4);
+    const unsigned rb = sr_rows_blocks(n);
+    const int rv = sr_rows_vec(T, n, p);
 
     // Attempts: the requested format, then an FP32 factor, then the Jacobi
     // preconditioner (-1).  A reduced-precision factor that had to replace
@@ -353,7 +406,8 @@ nqs_status nqs_sr_solve_mixed(const float *T, const double *eloc, int64_t n, dou
         if (!(rz0 > 0.0) || !std::isfinite(rz0)) continue;   // preconditioner unusable
         rel = 1.0;
         while (k < max_iter) {
-            hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, T, n, (const double *)p, n, shift, 0, Ap);
+            hipLaunchKernelGGL(sr_matvec_rows_kernel, dim3(rb), dim3(256), 0, s, T, n, (const double *)p, n, shift,
+                               rv, Ap, (double *)nullptr);
             hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, p, Ap, n, pap + k);
             hipLaunchKernelGGL(sr_step_kernel, dim3(eb), dim3(256), 0, s, rz + k, pap + k, n, (const double *)dj, p,
                                Ap, y, r, z);
