@@ -49,10 +49,12 @@ __global__ void __launch_bounds__(kSumThreads) sr_dot_kernel(const double *__res
 }
 
 // Ap = (T + shift) p, one wave per row, T with leading dimension ld; over
-// columns k < n (mode 0), k <= row (1: lower triangle) or k >= row (2: upper)
+// columns k < n (mode 0), k <= row (1: lower triangle) or k >= row (2: upper).
+// With vec (rows of T and p 16-byte aligned) the columns from the first
+// multiple of four on are read four at a time.
 __global__ void __launch_bounds__(256) sr_matvec_kernel(const float *__restrict__ T, int64_t ld,
                                                         const double *__restrict__ p, int64_t n, double shift,
-                                                        int mode, double *__restrict__ Ap)
+                                                        int mode, int vec, double *__restrict__ Ap)
 {
     const int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -60,7 +62,23 @@ __global__ void __launch_bounds__(256) sr_matvec_kernel(const float *__restrict_
     const float *t = T + row * ld;
     const int64_t lo = mode == 2 ? row : 0, hi = mode == 1 ? row + 1 : n;
     double s = 0.0;
-    for (int64_t k = lo + lane; k < hi; k += 64) s = fma((double)t[k], p[k], s);
+    int64_t k0 = lo;
+    if (vec) {
+        const int64_t a = std::min<int64_t>(hi, (lo + 3) & ~(int64_t)3);
+        if (lo + lane < a) s = fma((double)t[lo + lane], p[lo + lane], s);
+        const int64_t n4 = (hi - a) >> 2;
+        for (int64_t q = lane; q < n4; q += 64) {
+            const int64_t c = a + 4 * q;
+            const float4 v = *(const float4 *)(t + c);
+            const double2 pa = *(const double2 *)(p + c), pb = *(const double2 *)(p + c + 2);
+            s = fma((double)v.x, pa.x, s);
+            s = fma((double)v.y, pa.y, s);
+            s = fma((double)v.z, pb.x, s);
+            s = fma((double)v.w, pb.y, s);
+        }
+        k0 = a + (n4 << 2);
+    }
+    for (int64_t k = k0 + lane; k < hi; k += 64) s = fma((double)t[k], p[k], s);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0) Ap[row] = s + shift * p[row];
@@ -381,9 +399,9 @@ nqs_status nqs_sr_solve_mixed(const float *T, const double *eloc, int64_t n, dou
         // z = M^{-1} r: L^{-T} (L^{-1} r), or r / diag with the Jacobi preconditioner
         auto precond = [&]() {
             hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, (const float *)Lin, np,
-                               (const double *)r, n, 0.0, 1, u);
+                               (const double *)r, n, 0.0, 1, sr_rows_vec(Lin, np, r), u);
             hipLaunchKernelGGL(sr_matvec_kernel, dim3(mb), dim3(256), 0, s, (const float *)LinT, np,
-                               (const double *)u, n, 0.0, 2, z);
+                               (const double *)u, n, 0.0, 2, sr_rows_vec(LinT, np, u), z);
         };
         double *dj = fmt >= 0 ? nullptr : d;
         hipLaunchKernelGGL(sr_dot_kernel, dim3(1), dim3(kSumThreads), 0, s, eloc, (const double *)nullptr, n, misc);
