@@ -569,7 +569,7 @@ def _avg_bound(sigma):
 
 
 def run_noise(a, torch, nqs, workloads):
-    """Noisy-RBM study (Sec. V.A) on the 16-site TFIM chain: the shifts of <sigma^x> and <Pi_even> that noisy
+    """Noisy-RBM study (Sec. IV.A) on the 16-site TFIM chain: the shifts of <sigma^x> and <Pi_even> that noisy
     sampling produces against sigma (2^18 samples per point, chain-mean standard errors) beside the KL
     (Pinsker) and average total-variation bounds; the acceptance rate against sigma for RBMs trained here at
     several h/J; and the law of delta over sampled configurations.  The comparison with the exact perturbed

@@ -10,7 +10,7 @@
  *                      (Sec. II, Eq. eq:loss; acceptance Sec. III.A; single-flip
  *                      proposal App. C Eq. eq:app:local_prop; exchange move App. E)
  *   nqs_sample_noisy   the same sampler on log pi + zeta(x), zeta fixed per x
- *                      (Sec. V.A, Eq. eq:pert_chain)
+ *                      (Sec. IV.A, Eq. eq:pert_chain)
  *   nqs_local_energy   eps(x) = sum_{x'} H(x,x') psi(x')/psi(x)
  *                      (App. I.1, Eq. eq:local_energies; TFIM Eq. eq:TFIM; Heisenberg App. E)
  *   nqs_energy_stats   FP64 mean / variance / error bar of the local energies (Eq. eq:loss)
@@ -42,7 +42,9 @@
  *     describing the last non-OK status.  Faults inside kernels surface at the
  *     caller's next synchronisation of `stream`.
  *   - Results depend only on (parameters, configuration, seed, step offset,
- *     global chain id): not on the launch shape chosen by the autotuner.
+ *     global chain id) and, for the RBM samplers, on the lanes per chain G,
+ *     which fixes the FP32 summation order of the log-ratio.  Chains per
+ *     workgroup and the placement of lookup tables never change a result.
  */
 #ifndef NQS_H
 #define NQS_H
@@ -133,7 +135,7 @@ typedef struct {
     uint64_t seed, step_offset;
     uint32_t instance_id;
     int64_t chain_id_offset;          /* global id of chain 0 (for splitting chains across devices) */
-    int32_t lanes_per_chain;          /* RBM: 0 = autotune, else 16, 32 or 64 lanes per chain.
+    int32_t lanes_per_chain;          /* RBM: 0 = a fixed function of (N, M), else 16, 32 or 64 lanes per chain.
                                          Dense network: 0 = automatic, -1 = the batched-GEMM path
                                          (a full forward pass of every proposal; the path taken
                                          anyway for depth != 2 or wide first layers) */
@@ -205,7 +207,7 @@ typedef struct {
  * `stream` once before launching. */
 nqs_status nqs_sample_batched(const nqs_sample_job *jobs, int32_t n_jobs, int32_t mode, void *stream);
 
-/* Metropolis-Hastings sampling of the noisy target of Sec. V.A:
+/* Metropolis-Hastings sampling of the noisy target of Sec. IV.A:
  *   log pi~(x) = log pi(x) + zeta(x),  zeta(x) = noise_sigma * g(x),
  * g(x) a standard normal held fixed per configuration: Philox4x32-10 with the
  * configuration's four 32-bit words as counter (spin i up = bit i % 32 of word

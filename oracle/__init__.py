@@ -341,7 +341,7 @@ def smatrix(O: np.ndarray, weights=None) -> np.ndarray:
 
 
 def noise_zeta(configs: np.ndarray, sigma: float, seed: int) -> np.ndarray:
-    """zeta(x) of the noisy target log pi~ = log pi + zeta (Sec. V.A): sigma times a
+    """zeta(x) of the noisy target log pi~ = log pi + zeta (Sec. IV.A): sigma times a
     standard normal fixed per configuration (Philox keyed by the configuration
     bits, Box-Muller), FP64, one value per row of `configs` (N <= 128)."""
     c = np.ascontiguousarray(configs, dtype=np.int8)

@@ -103,7 +103,7 @@ static void stream_block(uint64_t seed, uint64_t step, uint32_t chain, uint32_t 
     orc_philox4x32_10(ctr, key, out);
 }
 
-/* zeta(x) = sigma g(x) of the noisy target log pi~ = log pi + zeta (Sec. V.A):
+/* zeta(x) = sigma g(x) of the noisy target log pi~ = log pi + zeta (Sec. IV.A):
  * g a standard normal fixed per configuration.  Philox4x32-10 with the
  * configuration's 32-bit words as counter (spin i up = bit i % 32 of word i / 32)
  * and the seed as key; Box-Muller (Box and Muller 1958) on the first two

@@ -1,4 +1,4 @@
-"""GPU parity of the noisy-target sampler (Sec. V.A, Eq. eq:pert_chain): its
+"""GPU parity of the noisy-target sampler (Sec. IV.A, Eq. eq:pert_chain): its
 histogram against the exactly enumerated pi~ = pi e^zeta / Z with the oracle's
 zeta(x), and its determinism.  Every call goes through the C interface."""
 import numpy as np

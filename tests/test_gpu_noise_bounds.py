@@ -1,4 +1,4 @@
-"""The bound-validation harness on an enumerated system (Sec. V.A, Eqs.
+"""The bound-validation harness on an enumerated system (Sec. IV.A, Eqs.
 eq:tv_gaussian and eq:avg_bound).  For random RBMs on the 16-site TFIM chain,
 the exact perturbed distribution pi~ = pi e^zeta / Z (zeta from the oracle: the
 field the device sampler draws) stays within both total-variation bounds; the

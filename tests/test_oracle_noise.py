@@ -1,4 +1,4 @@
-"""Pins of the oracle's noisy-target perturbation zeta(x) (Sec. V.A, Eq.
+"""Pins of the oracle's noisy-target perturbation zeta(x) (Sec. IV.A, Eq.
 eq:pert_chain): a normal of standard deviation sigma, fixed per configuration."""
 import numpy as np
 import scipy.stats
