@@ -158,6 +158,31 @@ def downcast(params: np.ndarray, arch: str, n: int, widths, dtype: str):
     return out, scales
 
 
+def e4m3_act_scales(rounded: np.ndarray, n: int, widths) -> dict:
+    """E4M3 scales of the hidden-layer outputs of a dense network (the inputs of
+    layers 2..L), {l + 1: scale of the output of layer l} for l < L - 1.
+
+    The paper fixes no FP8 recipe (App. A lists FP16/BF16/FP32/FP64).  Reading:
+    a per-layer power of two 2^ceil(log2(B_l / 448)), where B_l bounds |h_l|
+    over every spin configuration, computed on the rounded weights:
+    B_0 = 1 (spins), B_l = max_k (sum_i |W_l[k, i]| B_{l-1} + |b_l[k]|) (ReLU
+    never increases a magnitude).  No value can exceed 448 after scaling, and
+    multiplying by a power of two is exact, so a layer input is stored as
+    q * scale with q = RNE_e4m3(h / scale) and no saturation."""
+    out = {}
+    B, off, prev = 1.0, 0, n
+    rounded = np.asarray(rounded, dtype=np.float64)
+    for l, w in enumerate(widths[:-1]):
+        W = rounded[off:off + w * prev].reshape(w, prev)
+        off += w * prev
+        b = rounded[off:off + w]
+        off += w
+        B = float(np.max(np.abs(W).sum(axis=1) * B + np.abs(b)))
+        out[l + 1] = float(2.0 ** np.ceil(np.log2(B / E4M3_MAX))) if B > 0 else 1.0
+        prev = w
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Models and Hamiltonians
 # ---------------------------------------------------------------------------
@@ -174,6 +199,8 @@ class OracleModel:
         self.params = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
         self.table_logamp = None if table_logamp is None else np.ascontiguousarray(table_logamp, np.float64)
         self.table_sign = None if table_sign is None else np.ascontiguousarray(table_sign, np.int8)
+        self.act_dtype = act_dtype
+        self.act_scales = dict(act_scales) if act_scales else None
         s = _Model()
         s.arch = {"rbm": RBM, "ffnn": FFNN, "table": TABLE}[arch]
         s.n_visible = n
@@ -217,8 +244,12 @@ def model_from_workload(wl, params=None, dtype: str = "f64") -> OracleModel:
     m = wl.model
     p = workloads.params_for(wl) if params is None else params
     rounded, _ = downcast(p, m.arch, m.n_visible, m.widths, dtype)
-    return OracleModel(m.arch, m.n_visible, m.widths, rounded, act_dtype=dtype if dtype != "e4m3" else "f64",
-                       marshall=wl.ham.marshall, lattice=wl.ham.lattice)
+    act, scales = dtype, None
+    if dtype == "e4m3":
+        # RBM: the only layer input is the spins (exact); dense: layer inputs with per-layer power-of-two scales
+        act, scales = ("e4m3", e4m3_act_scales(rounded, m.n_visible, m.widths)) if m.arch == "ffnn" else ("f64", None)
+    return OracleModel(m.arch, m.n_visible, m.widths, rounded, act_dtype=act, marshall=wl.ham.marshall,
+                       lattice=wl.ham.lattice, act_scales=scales)
 
 
 def ham_struct(ham) -> _Ham:

@@ -167,6 +167,7 @@ double orc_round(double x, int32_t dtype)
 
 void orc_round_array(const double *x, int64_t n, int32_t dtype, double *out)
 {
+#pragma omp parallel for schedule(static) if (n > 65536)
     for (int64_t k = 0; k < n; ++k) out[k] = orc_round(x[k], dtype);
 }
 
