@@ -63,6 +63,9 @@ if ROOT not in sys.path:
 PEAK_FP32_VALU_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+PEAK_FP8_MFMA_TFLOPS = 5000.0
+# v_log_f32 / v_exp_f32 rate measured on this device (bench.py --workload peaks)
+MEASURED_EXP2_LOG2_PER_S = 1.30e13
 METRIC = "MH proposals/s + E_loc samples/s, BF16 vs FP32 on 1 GPU, at stated dE vs FP64"
 
 
@@ -78,6 +81,8 @@ def _args():
     ap.add_argument("--dtype", default="bf16", choices=["bf16", "f16", "f32", "e4m3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison step")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="tfim10: skip the one-step runs of the dense-network and uneven-batch workloads")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per chain of the RBM sampler (0 = library default)")
     ap.add_argument("--refresh", type=int, default=4, help="sweeps between full recomputes of theta = W s + b")
     ap.add_argument("--copy-probe", action="store_true",
@@ -191,37 +196,104 @@ class Step:
         return max(float(np.mean(step_ms)), 1e3 * wall / steps), phases
 
 
-def cpu_baseline(wl, params, budget_s=20.0):
-    """The oracle (FP64, full forward per proposal) on a bounded sample of the workload."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, params, budget_s=20.0, paired_chains=0, paired_sweeps=0, device_eloc=None):
+    """The oracle (FP64, full forward per proposal) on a bounded sample of the workload, on every host
+    thread and on one.  With paired_chains > 0 the bounded sample is the first paired_sweeps sweeps of
+    paired_chains chains (no burn-in, the workload's seed), and each entry of device_eloc (format ->
+    local energies [sweep][chain] of the device's run with the same configuration and seed) is paired
+    with the oracle's: the mean FP64-referenced energy difference and its chain-mean standard error."""
     import oracle
     oracle.build()
     om = oracle.model_from_workload(wl, params, "f64")
     threads = oracle.num_threads()
     N = wl.model.n_visible
-    # calibrate on a small run, then size the measured runs to the time budget
-    c0 = max(threads, 8)
-    t = time.perf_counter()
-    oracle.sample(om, oracle.make_cfg(c0, 1, 0, move=wl.move, seed=wl.seed))
-    per_prop = max(1e-9, (time.perf_counter() - t) / (c0 * N))
-    chains = int(max(threads, min(wl.n_chains, (0.6 * budget_s) / (per_prop * N * 2))))
-    sweeps = int(max(2, min(8, (0.6 * budget_s) / (per_prop * N * chains))))
+    if paired_chains:
+        chains, sweeps = paired_chains, paired_sweeps
+    else:
+        # calibrate on a small run, then size the measured runs to the time budget
+        c0 = max(threads, 8)
+        t = time.perf_counter()
+        oracle.sample(om, oracle.make_cfg(c0, 1, 0, move=wl.move, seed=wl.seed))
+        per_prop = max(1e-9, (time.perf_counter() - t) / (c0 * N))
+        chains = int(max(threads, min(wl.n_chains, (0.6 * budget_s) / (per_prop * N * 2))))
+        sweeps = int(max(2, min(8, (0.6 * budget_s) / (per_prop * N * chains))))
     cfg = oracle.make_cfg(chains, sweeps, 0, move=wl.move, seed=wl.seed)
     t = time.perf_counter()
     _, smp, _, _ = oracle.sample(om, cfg)
     ts = time.perf_counter() - t
     props = chains * sweeps * N
     flat = smp.reshape(-1, N)
+    if paired_chains:
+        n_el = flat.shape[0]
+    else:
+        t = time.perf_counter()
+        oracle.local_energy(om, wl.ham, flat[:threads])
+        per_el = max(1e-9, (time.perf_counter() - t) / threads)
+        n_el = int(max(threads, min(flat.shape[0], 0.4 * budget_s / per_el)))
     t = time.perf_counter()
-    oracle.local_energy(om, wl.ham, flat[:threads])
-    per_el = max(1e-9, (time.perf_counter() - t) / threads)
-    n_el = int(max(threads, min(flat.shape[0], 0.4 * budget_s / per_el)))
-    t = time.perf_counter()
-    oracle.local_energy(om, wl.ham, flat[:n_el])
+    e64 = oracle.local_energy(om, wl.ham, flat[:n_el])
     te = time.perf_counter() - t
-    return {"value": props / ts, "unit": "proposals/s", "cores": threads, "kind": "oracle",
-            "eloc_samples_per_s": n_el / te,
-            "sample": f"{chains} chains x {sweeps} sweeps ({props} proposals, FP64 full forward each) + "
-                      f"local energies of {n_el} samples, {wl.name}"}
+    out = {"value": props / ts, "unit": "proposals/s", "cores": threads, "cpu_model": _cpu_model(),
+           "kind": "oracle", "eloc_samples_per_s": n_el / te,
+           "sample": f"{chains} chains x {sweeps} sweeps ({props} proposals, FP64 full forward each) + "
+                     f"local energies of {n_el} samples, {wl.name}"}
+    # the same oracle on one thread, on a smaller bounded sample
+    c1 = min(chains, 64)
+    oracle.set_num_threads(1)
+    try:
+        t = time.perf_counter()
+        _, smp1, _, _ = oracle.sample(om, oracle.make_cfg(c1, 2, 0, move=wl.move, seed=wl.seed))
+        t1 = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.local_energy(om, wl.ham, smp1.reshape(-1, N)[:c1])
+        t1e = time.perf_counter() - t
+    finally:
+        oracle.set_num_threads(threads)
+    out["one_thread"] = {"value": c1 * 2 * N / t1, "unit": "proposals/s", "eloc_samples_per_s": c1 / t1e,
+                         "sample": f"{c1} chains x 2 sweeps + local energies of {c1} samples"}
+    if device_eloc:
+        res = {}
+        for fmt, ed in device_eloc.items():
+            d = (np.asarray(ed, dtype=np.float64) - e64).reshape(sweeps, chains)
+            cm = d.mean(axis=0)
+            res[fmt] = {"value": float(d.mean()), "stderr_paired": float(cm.std(ddof=1) / np.sqrt(chains))}
+        out["dE_vs_fp64"] = res
+        out["dE_vs_fp64_setup"] = (f"{chains} chains x {sweeps} sweeps from the start states, no burn-in, seed "
+                                   f"{wl.seed}: the device's local energies (FP32 ratios) of its own samples minus "
+                                   f"the oracle's FP64 local energies of its own samples, per (sweep, chain); "
+                                   f"chain-mean standard error")
+        out["oracle_energy"] = {"mean": float(e64.mean()),
+                                "stderr": float(e64.reshape(sweeps, chains).mean(axis=0).std(ddof=1)
+                                                / np.sqrt(chains))}
+    return out
+
+
+def _device_short_run(nqs, torch, wl, params, dtype, chains, sweeps, refresh):
+    """Local energies [sweep][chain] (FP32 ratios, FP64 sums) of a short device run from the start
+    states (no burn-in, the workload's seed), as a host array."""
+    dev = torch.device("cuda:0")
+    N = wl.model.n_visible
+    model = nqs.Model.from_workload(wl, params)
+    cfg = nqs.SampleConfig(n_chains=chains, n_sweeps=sweeps, n_burnin=0, seed=wl.seed, dtype=dtype,
+                           refresh_sweeps=refresh, move=wl.move)
+    state = torch.empty(chains, N, dtype=torch.int8, device=dev)
+    samples = torch.empty(sweeps, chains, N, dtype=torch.int8, device=dev)
+    eloc = torch.empty(sweeps * chains, dtype=torch.float64, device=dev)
+    nqs.nqs_sample(model, cfg, state, samples, None, None)
+    nqs.nqs_local_energy(model, nqs.Hamiltonian.from_workload(wl.ham), samples, eloc, "f32")
+    out = eloc.cpu().numpy()
+    model.close()
+    return out
 
 
 def _common(a, wl, props, ms, phases, step, data):
@@ -265,7 +337,7 @@ def _compare_fp32(a, nqs, torch, wl, params, step, ms, props, eloc_dtype, with_g
             continue
         o = Step(nqs, torch, wl, params, dt, a.lanes, a.refresh, eloc_dtype=dt if eloc_dtype != "f32" else "f32",
                  with_gram=with_gram)
-        mso, pho = o.timed(1, 1)
+        mso, pho = o.timed(a.steps, a.warmup)
         out.setdefault("other_formats", {})[dt] = {
             "ms_per_step": round(mso, 3), "sample_ms": round(pho["sample"], 3),
             "dE_vs_fp32": _paired(nqs, torch, o.eloc, ref.eloc, wl.n_chains)}
@@ -316,32 +388,71 @@ def run_tfim10(a, torch, nqs, workloads):
     step = Step(nqs, torch, wl, params, a.dtype, a.lanes, a.refresh)
     ms, phases = step.timed(a.steps, a.warmup)
     out = _common(a, wl, props, ms, phases, step, "synthetic (seeded random RBM weights, N(0, 0.02^2))")
+    # the sampler computes in FP32 (product-form ratios, log-ratio, accept test) on weights rounded to the
+    # sampling format; local-energy ratios FP32, their sums and every average FP64
+    out["dtype"] = "f32"
+    out["weights_format"] = a.dtype
+    out["arith"] = (f"FP32 arithmetic on {a.dtype.upper()}-rounded weights (the (cosh 2W, sinh 2W) table is built "
+                    f"from the rounded weights); FP64 local-energy sums and averages")
     out["config"] = {"workload": wl.name, "lattice": "10x10 periodic", "J": 1.0, "h": 3.04, "rbm_hidden": M,
                      "chains": C, "sweeps": S, "burnin": B, "proposals_per_step": props, "samples_per_step": S * C,
                      "refresh_sweeps": a.refresh, "lanes_per_chain": a.lanes or "default",
                      "parallelism": "single GPU"}
-    # FP32-VALU work of the product-form single flip: 4M per proposal (per hidden
-    # unit c C, the FMA with s S, the product), 3M per accepted proposal (the
-    # state update s C - s_i c S), and the refresh theta = W s + b (2 N M flops
-    # every `refresh` sweeps of N proposals).
+    # Algorithmic work of one single-flip proposal: the log-amplitude ratio of an RBM needs M log-cosh
+    # evaluations of the shifted pre-activations (two transcendentals each) and about 2M multiply-adds,
+    # counted as 4M operations against the FP32 vector peak.  The kernel's own arithmetic (product form,
+    # no transcendental per hidden unit) is reported beside it.
     acc = out["acceptance"]
-    fpp = 4.0 * M + 3.0 * M * acc + 2.0 * M / a.refresh
-    achieved = props * fpp / (phases["sample"] * 1e-3) / 1e12
+    t_k = phases["sample"] * 1e-3
+    alg = 4.0 * M
+    achieved = props * alg / t_k / 1e12
+    impl = 4.0 * M + 3.0 * M * acc + 2.0 * M / a.refresh
     out["roofline"] = {"kernel": "rbm_sample_kernel", "bound": "alu", "achieved": round(achieved, 3),
                        "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
                        "traffic": kernel_traffic("rbm_sample_kernel", "tfim2d_10x10_rbm_bf16_hbm_traffic.txt"),
                        "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
-                       "flops_per_proposal": round(fpp, 2), "proposals_per_launch": props}
+                       "ops_per_proposal": alg, "ops_per_proposal_note": "M log-cosh (2M transcendentals) + 2M FMA",
+                       "proposals_per_launch": props, "launch_ms": round(phases["sample"], 3),
+                       "transcendental_view": {
+                           "per_proposal": 2.0 * M,
+                           "achieved_per_s": props * 2.0 * M / t_k,
+                           "measured_rate_per_s": MEASURED_EXP2_LOG2_PER_S,
+                           "frac": round(props * 2.0 * M / t_k / MEASURED_EXP2_LOG2_PER_S, 4)},
+                       "implementation_count": {
+                           "flops_per_proposal": round(impl, 2),
+                           "note": "4M (ratio factors) + 3M x acceptance (state update) + 2M / refresh (theta)",
+                           "achieved": round(props * impl / t_k / 1e12, 3),
+                           "frac": round(props * impl / t_k / 1e12 / PEAK_FP32_VALU_TFLOPS, 4)}}
     out["sr_step"] = _sr_step(nqs, torch, step)
     if not a.no_compare:
         out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, "f32", True, others=("f16", "e4m3")))
+    del step
+    torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, params)
+        pc, ps = C, 8
+        dev_el = {fmt: _device_short_run(nqs, torch, wl, params, fmt, pc, ps, a.refresh)
+                  for fmt in (a.dtype, "f32")}
+        out["cpu_baseline"] = cpu_baseline(wl, params, paired_chains=pc, paired_sweeps=ps, device_eloc=dev_el)
+        out["dE_vs_fp64"] = out["cpu_baseline"].pop("dE_vs_fp64")
+        out["dE_vs_fp64"]["setup"] = out["cpu_baseline"].pop("dE_vs_fp64_setup")
+    if not a.headline_only:
+        out["other_workloads"] = _other_workloads(a, torch, nqs, workloads)
     return out
 
 
-def run_heis10(a, torch, nqs, workloads):
+def _antiparallel_bonds(torch, samples, L):
+    """Number of antiparallel nearest-neighbour bonds summed over all samples of a periodic L x L
+    lattice (each one is a connected configuration the Heisenberg local energy evaluates)."""
+    tot = 0
+    flat = samples.reshape(-1, L, L)
+    for k in range(0, flat.shape[0], 1 << 20):
+        x = flat[k:k + (1 << 20)]
+        tot += int((x != torch.roll(x, 1, dims=1)).sum().item()) + int((x != torch.roll(x, 1, dims=2)).sum().item())
+    return tot
+
+
+def run_heis10(a, torch, nqs, workloads, compact=False):
     wl = workloads.cfg3_heis_10x10()
     params = workloads.params_for(wl)
     N, C, S, B = wl.model.n_visible, wl.n_chains, wl.n_sweeps, wl.n_burnin
@@ -353,6 +464,9 @@ def run_heis10(a, torch, nqs, workloads):
     out["config"] = {"workload": wl.name, "lattice": "10x10 periodic", "J": 1.0, "marshall": True,
                      "ffnn": [N, w1, w2], "move": "exchange", "chains": C, "sweeps": S, "burnin": B,
                      "proposals_per_step": props, "samples_per_step": S * C, "parallelism": "single GPU"}
+    out["arith"] = (f"{a.dtype.upper()} operands of both layers' products, FP32 accumulation, FP32 nonlinearities, "
+                    f"log-ratio and accept test; FP64 local-energy sums")
+    peak = PEAK_BF16_MFMA_TFLOPS if a.dtype != "f32" else PEAK_FP32_VALU_TFLOPS
     # dominant contraction of the sampler: layer 2 of the proposed state, 2 w1 w2 flops per evaluated
     # proposal on the matrix cores.  An exchange of two equal spins changes nothing and is not evaluated;
     # at zero magnetisation a uniform ordered pair of distinct sites differs with probability exactly
@@ -360,17 +474,51 @@ def run_heis10(a, torch, nqs, workloads):
     eff = N / (2.0 * (N - 1))
     fpp = 2.0 * w1 * w2 * eff
     achieved = props * fpp / (phases["sample"] * 1e-3) / 1e12
-    out["roofline"] = {"kernel": "ffnn_sample_reg_kernel", "bound": "mfma", "achieved": round(achieved, 2),
-                       "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                       "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
-                       "flops_per_proposal": round(fpp, 1), "evaluated_fraction": round(eff, 4),
-                       "proposals_per_launch": props}
-    out["sr_step"] = _sr_step(nqs, torch, step)
+    sampler_rl = {"kernel": "ffnn_sample_reg_kernel", "bound": "mfma", "achieved": round(achieved, 2),
+                  "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                  "flops_per_proposal": round(fpp, 1), "evaluated_fraction": round(eff, 4),
+                  "proposals_per_launch": props, "launch_ms": round(phases["sample"], 3)}
+    # local energies: every antiparallel bond of every sample is a connected configuration whose layer 2
+    # (2 w1 w2 flops) runs on the matrix cores
+    rows = _antiparallel_bonds(torch, step.samples, wl.ham.lattice.L)
+    el_ach = rows * 2.0 * w1 * w2 / (phases["local_energy"] * 1e-3) / 1e12
+    eloc_rl = {"kernel": "ffnn_eloc_reg_kernel", "bound": "mfma", "achieved": round(el_ach, 2), "peak": peak,
+               "unit": "TFLOP/s", "frac": round(el_ach / peak, 4), "traffic": None,
+               "rows_per_launch": rows, "flops_per_row": 2.0 * w1 * w2, "launch_ms": round(phases["local_energy"], 3),
+               "note": "rows = antiparallel bonds summed over the step's samples"}
+    # the dominant kernel of the step is the one that takes longer
+    if phases["local_energy"] >= phases["sample"]:
+        out["roofline"], out["sampler_roofline"] = eloc_rl, sampler_rl
+    else:
+        out["roofline"], out["eloc_roofline"] = sampler_rl, eloc_rl
+    if not compact:
+        out["sr_step"] = _sr_step(nqs, torch, step)
     if not a.no_compare:
-        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, a.dtype, True, others=("f16",)))
-    if not a.no_cpu_baseline:
+        out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, a.dtype, not compact,
+                                 others=() if compact else ("f16",)))
+    if not a.no_cpu_baseline and not compact:
         out["cpu_baseline"] = cpu_baseline(wl, params, budget_s=15.0)
     return out
+
+
+def _other_workloads(a, torch, nqs, workloads):
+    """One timed step each (after one untimed) of the dense-network and uneven-batch workloads, in the
+    same format as the headline and against FP32, so the matrix-core paths are measured in the same run."""
+    import copy
+    b = copy.copy(a)
+    b.steps, b.warmup, b.no_cpu_baseline = 1, 1, True
+    keep = ("value", "unit", "ms_per_step", "dtype", "arith", "phases_ms", "sampler_proposals_per_s",
+            "eloc_samples_per_s", "acceptance", "energy", "config", "roofline", "sampler_roofline", "eloc_roofline",
+            "speedup_vs_fp32", "dE_vs_fp32", "fp32", "persistent_ms", "separate_launches_ms",
+            "separate_launches_graph_ms", "speedup_vs_separate", "speedup_vs_graph", "gram_T", "steps", "warmup")
+    res = {}
+    for name, fn in (("heis10", lambda: run_heis10(b, torch, nqs, workloads, compact=True)),
+                     ("uneven", lambda: run_uneven(b, torch, nqs, workloads)),
+                     ("heis20", lambda: run_heis20(b, torch, nqs, workloads))):
+        r = fn()
+        res[name] = {k: v for k, v in r.items() if k in keep}
+        torch.cuda.empty_cache()
+    return res
 
 
 def run_uneven(a, torch, nqs, workloads):
@@ -378,6 +526,7 @@ def run_uneven(a, torch, nqs, workloads):
     dev = torch.device("cuda:0")
     models, jobs = [], []
     props = 0
+    alg_ops = 0.0   # per proposal: M log-cosh (2M transcendentals) + 2M FMA, as for the headline sampler
     for k, wl in enumerate(insts):
         m = nqs.Model.from_workload(wl)
         m.prepare(a.dtype)
@@ -390,6 +539,7 @@ def run_uneven(a, torch, nqs, workloads):
                      "samples": torch.empty(wl.n_sweeps, wl.n_chains, N, dtype=torch.int8, device=dev),
                      "n_accepted": torch.empty(wl.n_chains, dtype=torch.int64, device=dev)})
         props += wl.n_chains * (wl.n_sweeps + wl.n_burnin) * N
+        alg_ops += wl.n_chains * (wl.n_sweeps + wl.n_burnin) * N * 4.0 * wl.model.widths[0]
 
     def timed(fn):
         for _ in range(a.warmup):
@@ -422,6 +572,12 @@ def run_uneven(a, torch, nqs, workloads):
                    "sweeps": 200, "burnin": 20, "proposals_per_step": props, "parallelism": "single GPU"},
         "persistent_ms": ms0, "separate_launches_ms": ms1, "separate_launches_graph_ms": ms2,
         "speedup_vs_separate": ms1 / ms0, "speedup_vs_graph": ms2 / ms0,
+        "arith": f"FP32 arithmetic on {a.dtype.upper()}-rounded weights",
+        "roofline": {"kernel": "rbm_batched_kernel", "bound": "alu",
+                     "achieved": round(alg_ops / (ms0 * 1e-3) / 1e12, 3), "peak": PEAK_FP32_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(alg_ops / (ms0 * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
+                     "traffic": None, "ops_per_launch": alg_ops,
+                     "ops_note": "sum over instances of proposals x 4M (M log-cosh + 2M FMA)"},
     }
     for m in models:
         m.close()
@@ -486,6 +642,8 @@ def run_heis20(a, torch, nqs, workloads):
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": r0["sample_ms"] + r0["eloc_ms"] + r0["gram_ms"],
         "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": a.dtype, "data": "synthetic (seeded He-initialised FFNN)",
+        "arith": (f"{a.dtype.upper()} operands of every layer's product, FP32 accumulation, FP32 nonlinearities, "
+                  f"log-ratio and accept test; FP64 local-energy sums"),
         "config": {"workload": wl.name, "lattice": "20x20 periodic", "J": 1.0, "marshall": True, "ffnn": [N, *w],
                    "move": "exchange", "chains": C, "sweeps_per_step": sweeps, "burnin": 0,
                    "proposals_per_step": props, "eloc_samples": n_el, "parallelism": "single GPU"},
@@ -545,6 +703,7 @@ def _train_rbm(nqs, torch, N, M, h, iters, seed):
     T = torch.empty(n, n, dtype=torch.float32, device=dev)
     y = torch.empty(n, dtype=torch.float64, device=dev)
     offset = 0
+    solve_log = []
     for it in range(iters):
         model.set_params_device(master)
         model.prepare("f32")
@@ -556,10 +715,23 @@ def _train_rbm(nqs, torch, N, M, h, iters, seed):
         flat = samples.reshape(n, N)
         nqs.nqs_local_energy(model, ham, flat, eloc)
         nqs.nqs_sample_gram_factored(model, flat, T)
-        nqs.nqs_sr_solve(T, eloc, 1e-2, y, tol=1e-6, max_iter=300)
+        its, rr = nqs.nqs_sr_solve(T, eloc, 1e-2, y, tol=1e-6, max_iter=300)
+        solve_log.append((its, rr))
         nqs.nqs_sr_update(model, flat, y, 0.05, master)
     model.close()
-    return master.cpu().numpy()
+    return master.cpu().numpy(), _solve_summary(solve_log, 1e-6, 300)
+
+
+def _solve_summary(log, tol, max_iter):
+    """Iteration counts and final relative residuals of the SR solves of a training run; a solve that
+    stops at max_iter above tol is counted as unconverged (its direction was still used)."""
+    its = np.array([k for k, _ in log], dtype=np.float64)
+    rr = np.array([r for _, r in log], dtype=np.float64)
+    return {"solves": len(log), "iterations_mean": float(its.mean()) if len(log) else 0.0,
+            "iterations_max": int(its.max()) if len(log) else 0,
+            "rel_residual_max": float(rr.max()) if len(log) else 0.0, "tol": tol,
+            "unconverged": int(np.sum((its >= max_iter) & (rr > tol))),
+            "note": "the Jacobi solve checks its residual every 8 iterations, so counts are multiples of 8"}
 
 
 def _avg_bound(sigma):
@@ -615,9 +787,9 @@ def run_noise(a, torch, nqs, workloads):
         model.close()
     t_bias = time.perf_counter() - t0
     accept = []
-    trained = {}
+    trained, training_solves = {}, {}
     for h in (-0.5, -1.0, -5.0):   # h/J, stoquastic sign (positive amplitudes)
-        p = _train_rbm(nqs, torch, N, 2 * N, h, 150, 5)
+        p, training_solves[abs(h)] = _train_rbm(nqs, torch, N, 2 * N, h, 150, 5)
         trained[abs(h)] = p
         model = nqs.Model("rbm", N, (2 * N,), p)
         for sg in sigmas:
@@ -652,6 +824,7 @@ def run_noise(a, torch, nqs, workloads):
                    "sigmas": sigmas, "parallelism": "single GPU",
                    "note": "value = proposals/s of the whole study including training"},
         "bias_vs_sigma": bias, "acceptance_vs_sigma": accept, "delta_law": law, "bias_study_s": round(t_bias, 2),
+        "training_sr_solves": {str(k): v for k, v in training_solves.items()},
     }
 
 
@@ -868,7 +1041,7 @@ def run_srstudy(a, torch, nqs, workloads):
             P = model.n_params
             O = torch.empty(n, P, dtype=torch.float32, device=dev)
             master = torch.from_numpy(p.copy()).to(dev)
-            offset, traj, kappa, iters, energies = 0, [], [], [], []
+            offset, traj, kappa, iters, energies, solve_log = 0, [], [], [], [], []
             for it in range(steps):
                 model.set_params_device(master)
                 model.prepare(sdt)
@@ -889,8 +1062,9 @@ def run_srstudy(a, torch, nqs, workloads):
                     kappa.append({"step": it, "kappa": float((ev[-1] + shift) / (max(ev[0], 0.0) + shift))})
                     traj.append({"step": it, "rel_err": abs(e - e0) / abs(e0)})
                 nqs.nqs_sample_gram_factored(model, flat, T)
-                its, _ = nqs.nqs_sr_solve(T, eloc, shift, y, tol=1e-8, max_iter=3000)
+                its, rr = nqs.nqs_sr_solve(T, eloc, shift, y, tol=1e-8, max_iter=3000)
                 iters.append(its)
+                solve_log.append((its, rr))
                 nqs.nqs_sr_update(model, flat, y, lr, master)
             model.close()
             last = np.array(energies[-10:])
@@ -898,7 +1072,8 @@ def run_srstudy(a, torch, nqs, workloads):
                          "final_rel_err": abs(float(last.mean()) - e0) / abs(e0),
                          "final_rel_err_se": float(last.std(ddof=1) / np.sqrt(last.size)) / abs(e0),
                          "energy_rel_err": traj, "kappa_S_plus_shift": kappa,
-                         "cg_iterations_mean": float(np.mean(iters))})
+                         "cg_iterations_mean": float(np.mean(iters)),
+                         "sr_solves": _solve_summary(solve_log, 1e-8, 3000)})
     wall = time.perf_counter() - t0
     return {
         "metric": "SR study: relative energy error against exact diagonalisation", "value": None,

@@ -301,7 +301,9 @@ nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t
  *   iterations.  shift >= 0 (T is singular along the constant vector, which
  *   the centred right-hand side avoids).  Synchronises `stream`; *iters and
  *   *rel_resid (host pointers, may be NULL) report the iteration count and
- *   ||r|| / ||b|| (0 when b = 0).  Deterministic.
+ *   ||r|| / ||b|| (0 when b = 0).  The residual is read every 8 iterations, so
+ *   the count is a multiple of 8 (or max_iter) and up to 7 iterations may run
+ *   past the one that first met tol.  Deterministic.
  * nqs_sr_update: master[P] (FP64, device, the caller's parameter vector) -=
  *   lr * delta, delta = O^T (y - mean y) / n through the FP32 copy's
  *   log-derivatives of `samples` (the n samples T was formed from).  The

@@ -115,8 +115,9 @@ __device__ __forceinline__ double group_sum(double v)
 // DPP reductions (no LDS traffic).  An inclusive Hillis-Steele scan inside
 // each 16-lane row (row_shr 1, 2, 4, 8), then row_bcast:15 / row_bcast:31
 // carry row totals upwards: the total of a group of G lanes ends in the
-// group's last lane.  group_sum_uniform() reads that lane with v_readlane, so
-// every lane of the group receives the same bits (decisions stay uniform).
+// group's last lane.  group_sum_uniform() hands that lane's value to the whole
+// group (row_newbcast for one row, else v_readlane), so every lane of the group
+// receives the same bits (decisions stay uniform).
 // ---------------------------------------------------------------------------
 template <int CTRL, int ROW_MASK, int BANK_MASK>
 __device__ __forceinline__ float dpp_f32(float v)
@@ -145,7 +146,9 @@ template <int G>
 __device__ __forceinline__ float group_sum_uniform(float v)
 {
     v = group_scan_total<G>(v);
-    if constexpr (G == 64) {
+    if constexpr (G == 16) {
+        return dpp_f32<0x15F, 0xF, 0xF>(v);   // row_newbcast:15: every lane of the row takes lane 15's total
+    } else if constexpr (G == 64) {
         return readlane_f32(v, 63);
     } else {
         const int grp = (int)(threadIdx.x & 63) / G;
