@@ -237,6 +237,17 @@ nqs_status nqs_local_energy_complex(nqs_model *m, const nqs_ham_desc *ham, const
  * the error bar needs n % n_chains == 0 and n_chains >= 2 (else NaN). */
 nqs_status nqs_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, void *stream);
 
+/* nqs_energy_stats for callers that cannot allocate (code under graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same results, with their scratch (512 block partials and the n_chains chain
+ * means, FP64) in a fixed device array of 131072 doubles (1 MiB) per GPU, held
+ * until the process ends; nothing is allocated.  NQS_EINVAL when the error bar
+ * would need more than 130560 chain means (n % n_chains == 0 and n_chains >= 2
+ * with n_chains > 130560).  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race, so the
+ * caller serialises them.  No part of the array needs to start at zero. */
+nqs_status nqs_energy_stats_noalloc(const double *eloc, int64_t n, int64_t n_chains, double *stats, void *stream);
+
 /* Log-amplitudes and log-derivatives from the FP32 copy.
  *   logpsi  [n] out (may be NULL)
  *   O       [n][P] out, row-major (may be NULL)

@@ -20,7 +20,7 @@ from . import _abi
 from ._abi import DTYPE_CODES, NqsError, check, load
 
 __all__ = [
-    "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_logpsi_grad",
+    "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc", "nqs_logpsi_grad",
     "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
     "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_probe_rate", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
 ]
@@ -249,6 +249,11 @@ def nqs_local_energy_complex(model: Model, ham: Hamiltonian, samples: torch.Tens
 def nqs_energy_stats(eloc: torch.Tensor, n_chains: int, stats: torch.Tensor, stream=None) -> None:
     assert eloc.dtype == torch.float64 and stats.dtype == torch.float64 and stats.numel() >= 4
     check(load().nqs_energy_stats(_ptr(eloc), eloc.numel(), n_chains, _ptr(stats), _stream(stream)))
+
+
+def nqs_energy_stats_noalloc(eloc: torch.Tensor, n_chains: int, stats: torch.Tensor, stream=None) -> None:
+    assert eloc.dtype == torch.float64 and stats.dtype == torch.float64 and stats.numel() >= 4
+    check(load().nqs_energy_stats_noalloc(_ptr(eloc), eloc.numel(), n_chains, _ptr(stats), _stream(stream)))
 
 
 def nqs_logpsi_grad(model: Model, samples: torch.Tensor, logpsi: Optional[torch.Tensor] = None,

@@ -20,7 +20,7 @@ DTYPE_CODES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "e4m3": FP8_E4M
 EXPORTS = [
     "nqs_model_create", "nqs_model_set_params", "nqs_model_set_params_device", "nqs_model_destroy",
     "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched",
-    "nqs_local_energy", "nqs_energy_stats",
+    "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc",
     "nqs_logpsi_grad", "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
     "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex",
     "nqs_last_error",
@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
         "nqs_sample_batched": ([P, i32, i32, P], st),
         "nqs_local_energy": ([P, P, P, i64, i32, P, P], st),
         "nqs_energy_stats": ([P, i64, i64, P, P], st),
+        "nqs_energy_stats_noalloc": ([P, i64, i64, P, P], st),
         "nqs_logpsi_grad": ([P, P, i64, P, P, P, P, P], st),
         "nqs_forces": ([P, P, i64, i64, P, P, P], st),
         "nqs_gram": ([P, i64, i64, i32, P, P], st),

@@ -377,6 +377,14 @@ nqs_status nqs_energy_stats(const double *eloc, int64_t n, int64_t n_chains, dou
     return launch_energy_stats(eloc, n, n_chains, stats, (hipStream_t)stream);
 }
 
+nqs_status nqs_energy_stats_noalloc(const double *eloc, int64_t n, int64_t n_chains, double *stats, void *stream)
+{
+    if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
+    if (!eloc || !stats) return set_error(NQS_EINVAL, "NULL eloc/stats");
+    if (n_chains < 0) return set_error(NQS_EINVAL, "n_chains < 0");
+    return launch_energy_stats_noalloc(eloc, n, n_chains, stats, (hipStream_t)stream);
+}
+
 nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
                            const float *vjp_in, float *vjp_out, void *stream)
 {

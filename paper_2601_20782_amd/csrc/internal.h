@@ -216,6 +216,10 @@ nqs_status ffnn_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int6
 nqs_status launch_init_chains(int8_t *chain_state, int64_t n_chains, int N, int move, uint64_t seed,
                               uint32_t inst, int64_t chain_id_offset, hipStream_t stream);
 nqs_status launch_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, hipStream_t stream);
+// the same with the file-scope scratch (kStatsScratchDoubles doubles per device; no allocation)
+constexpr int64_t kStatsScratchDoubles = 131072;
+nqs_status launch_energy_stats_noalloc(const double *eloc, int64_t n, int64_t n_chains, double *stats,
+                                       hipStream_t stream);
 nqs_status launch_forces(const float *O, const double *eloc, int64_t n, int64_t P, double *F, double *Omean,
                          hipStream_t stream);
 // One layer of factors of O for the factored sample-space Gram matrix:

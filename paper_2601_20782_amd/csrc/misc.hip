@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "common.h"
 #include "internal.h"
@@ -199,12 +201,19 @@ __global__ void set_tail_kernel(double *stats, double n, int valid_se)
     stats[3] = n;
 }
 
-nqs_status launch_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, hipStream_t stream)
+// The statistics with caller-chosen scratch `ws` of at least energy_stats_scratch_doubles(n, n_chains)
+// doubles: block partials, then the chain means.  Every slot is written before it is read, so the
+// scratch needs no clearing.
+static size_t energy_stats_scratch_doubles(int64_t n, int64_t n_chains)
 {
     const bool se = n_chains >= 2 && n % n_chains == 0;
-    const size_t need = sizeof(double) * (kRedBlocks + (se ? n_chains : 0));
-    double *ws = (double *)workspace(need, stream);
-    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    return (size_t)kRedBlocks + (se ? (size_t)n_chains : 0);
+}
+
+static nqs_status energy_stats_with(const double *eloc, int64_t n, int64_t n_chains, double *stats, double *ws,
+                                    hipStream_t stream)
+{
+    const bool se = n_chains >= 2 && n % n_chains == 0;
     double *partial = ws, *cm = ws + kRedBlocks;
     const int nb = (int)std::min<int64_t>(kRedBlocks, (n + 255) / 256);
     hipLaunchKernelGGL(moment_partial_kernel, dim3(nb), dim3(256), 0, stream, eloc, n, (const double *)nullptr, 1, partial);
@@ -223,6 +232,54 @@ nqs_status launch_energy_stats(const double *eloc, int64_t n, int64_t n_chains, 
     hipLaunchKernelGGL(set_tail_kernel, dim3(1), dim3(1), 0, stream, stats, (double)n, se ? 1 : 0);
     NQS_HIP_TRY(hipGetLastError());
     return NQS_OK;
+}
+
+nqs_status launch_energy_stats(const double *eloc, int64_t n, int64_t n_chains, double *stats, hipStream_t stream)
+{
+    double *ws = (double *)workspace(sizeof(double) * energy_stats_scratch_doubles(n, n_chains), stream);
+    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    return energy_stats_with(eloc, n, n_chains, stats, ws, stream);
+}
+
+// ---------------------------------------------------------------------------
+// The same statistics without any allocation, for callers that cannot
+// allocate (graph capture, serving loops): the scratch is a file-scope device
+// array, one copy per GPU, held until the process ends.  Host code never
+// names the array: its device address is looked up once per device with
+// hipGetSymbolAddress (the device current) and kept per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kStatsScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static double *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mutex;
+
+static nqs_status stats_scratch(double **out)
+{
+    int dev = 0;
+    NQS_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(NQS_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        NQS_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return set_error(NQS_EDEVICE, "no device address for the statistics scratch");
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return NQS_OK;
+}
+
+nqs_status launch_energy_stats_noalloc(const double *eloc, int64_t n, int64_t n_chains, double *stats,
+                                       hipStream_t stream)
+{
+    if (energy_stats_scratch_doubles(n, n_chains) > (size_t)kStatsScratchDoubles)
+        return set_error(NQS_EINVAL, "n_chains exceeds the static scratch of nqs_energy_stats_noalloc (at most " +
+                                         std::to_string(kStatsScratchDoubles - kRedBlocks) + " chains)");
+    double *ws = nullptr;
+    nqs_status st = stats_scratch(&ws);
+    if (st != NQS_OK) return st;
+    return energy_stats_with(eloc, n, n_chains, stats, ws, stream);
 }
 
 // ---------------------------------------------------------------------------

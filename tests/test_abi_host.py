@@ -73,6 +73,7 @@ def test_calls_without_model_are_rejected(lib):
     assert lib.nqs_sample(None, ctypes.byref(cfg), None, None, None, None, None, None) == _abi.NQS_EINVAL
     assert lib.nqs_local_energy(None, None, None, 1, 1, None, None) == _abi.NQS_EINVAL
     assert lib.nqs_energy_stats(None, 0, 1, None, None) == _abi.NQS_EINVAL
+    assert lib.nqs_energy_stats_noalloc(None, 0, 1, None, None) == _abi.NQS_EINVAL
     assert lib.nqs_forces(None, None, 0, 5, None, None, None) == _abi.NQS_EINVAL
     assert lib.nqs_gram(None, 4, 4, 3, None, None) == _abi.NQS_EINVAL
     assert lib.nqs_downcast(None, 5, 1, None, None, None) == _abi.NQS_EINVAL
@@ -119,3 +120,13 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _abi.load()
+
+
+def test_noalloc_stats_reject_more_chains_than_the_static_scratch(lib):
+    """The no-allocation statistics hold at most 131072 - 512 chain means; a larger request is refused
+    before any device call (so it is refused here, without a GPU)."""
+    from paper_2601_20782_amd import _abi
+    fake = ctypes.c_void_p(16)
+    n_chains = 131072 - 512 + 1
+    assert lib.nqs_energy_stats_noalloc(fake, 2 * n_chains, n_chains, fake, None) == _abi.NQS_EINVAL
+    assert b"static scratch" in lib.nqs_last_error()
