@@ -512,9 +512,12 @@ def _other_workloads(a, torch, nqs, workloads):
             "speedup_vs_fp32", "dE_vs_fp32", "fp32", "persistent_ms", "separate_launches_ms",
             "separate_launches_graph_ms", "speedup_vs_separate", "speedup_vs_graph", "gram_T", "steps", "warmup")
     res = {}
+    b8 = copy.copy(b)
+    b8.dtype, b8.no_compare, b8.gram_samples = "e4m3", True, 0
     for name, fn in (("heis10", lambda: run_heis10(b, torch, nqs, workloads, compact=True)),
                      ("uneven", lambda: run_uneven(b, torch, nqs, workloads)),
-                     ("heis20", lambda: run_heis20(b, torch, nqs, workloads))):
+                     ("heis20", lambda: run_heis20(b, torch, nqs, workloads)),
+                     ("heis20_e4m3", lambda: run_heis20(b8, torch, nqs, workloads))):
         r = fn()
         res[name] = {k: v for k, v in r.items() if k in keep}
         torch.cuda.empty_cache()
@@ -633,6 +636,7 @@ def run_heis20(a, torch, nqs, workloads):
         res[dt] = {"sample_ms": t_s, "eloc_ms": t_e, "gram_ms": t_t, "acceptance": float(acc.sum().item()) / props,
                    "eloc_mean": float(eloc.mean().item())}
     w = wl.model.widths
+    peak = {"f32": 157.3, "e4m3": PEAK_FP8_MFMA_TFLOPS}.get(a.dtype, PEAK_BF16_MFMA_TFLOPS)
     flops = 2.0 * (N * w[0] + w[0] * w[1] + w[1] * w[2])   # full forward per proposal
     eff = 0.5 * props   # exchange of equal spins is not evaluated
     r0 = res[a.dtype]
@@ -652,8 +656,7 @@ def run_heis20(a, torch, nqs, workloads):
         "eloc_samples_per_s": n_el / (r0["eloc_ms"] * 1e-3),
         "acceptance": r0["acceptance"],
         "roofline": {"kernel": "deep_gemm_kernel (all layers)", "bound": "mfma", "achieved": round(achieved, 2),
-                     "peak": PEAK_BF16_MFMA_TFLOPS if a.dtype != "f32" else 157.3, "unit": "TFLOP/s",
-                     "frac": round(achieved / (PEAK_BF16_MFMA_TFLOPS if a.dtype != "f32" else 157.3), 4),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None, "flops_per_effective_proposal": flops,
                      "note": "about half of the exchange proposals swap equal spins and are not evaluated"},
     }
@@ -987,6 +990,21 @@ def run_peaks(a, torch, nqs, workloads):
         "mfma_f32_16x16x4_tflops": best_rate("mfma_f32", 1000) / 1e12,
         "mfma_f64_16x16x4_tflops": best_rate("mfma_f64", 500) / 1e12,
     }
+    # issue rates of the vector instructions the samplers are made of, as cycles per wave64
+    # instruction per SIMD at the 2.4 GHz peak clock (4 SIMDs per CU)
+    simd_hz = cus * 4 * 2.4e9
+    issue = {}
+    for kind, iters, per_instr in (("fma_f32", 4000, 2), ("mul_f32", 4000, 1), ("xor_u32", 4000, 1),
+                                   ("dpp_add_f32", 2000, 1), ("mulhi_u32", 1000, 1), ("log_f32", 1000, 1),
+                                   ("exp_f32", 1000, 1), ("fma_f32_w2", 4000, 2), ("fma_f32_w1", 4000, 2),
+                                   ("fma_f32_dep", 4000, 2)):
+        if kind == "fma_f32":
+            r = got["fma_f32_tflops"] * 1e12
+        elif kind in ("log_f32", "exp_f32"):
+            r = got[kind[:3] + "2_f32_per_s"]
+        else:
+            r = best_rate(kind, iters)
+        issue[kind] = round(simd_hz / (r / 64 / per_instr), 3)
     nbytes = 2 << 30
     x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
     got["hbm_read_gbs"] = best_rate("hbm_read", nbytes, x) / 1e9
@@ -1005,8 +1023,11 @@ def run_peaks(a, torch, nqs, workloads):
         "achieved": {k: round(v, 3) for k, v in got.items()},
         "published": published,
         "frac_of_published": {k: round(got[k] / v, 4) for k, v in published.items()},
-        "note": "FP32 FMA without packed FP32 (this library never issues it): its ceiling is half the published "
-                "vector peak; log2 / exp2 in operations per second",
+        "cycles_per_wave64_instruction": issue,
+        "issue_note": "eight independent chains per thread at 8 blocks of 256 threads per CU (8 waves per SIMD); "
+                      "fma_f32_w2 / _w1: two / one wave per SIMD; fma_f32_dep: one dependent chain, one wave per "
+                      "SIMD (the dependent-issue latency)",
+        "note": "FP32 FMA without packed FP32 (this library never issues it); log2 / exp2 in operations per second",
     }
 
 

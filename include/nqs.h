@@ -75,7 +75,12 @@ typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_ham_kind;
  * RBM (App. G, real parameters): log psi = a.s + sum_{j<M} log cosh((W s + b)_j),
  *   widths[0] = M, parameter vector [a(N), b(M), W(M x N, row-major)].
  * FFNN: h_l = ReLU(W_l h_{l-1} + b_l) for l < n_layers, log psi = sum log cosh(z_last),
- *   parameter vector [W_1 (w1 x N), b_1, W_2 (w2 x w1), b_2, ...].
+ *   parameter vector [W_1 (w1 x N), b_1, W_2 (w2 x w1), b_2, ...].  Its FP8 E4M3
+ *   copy scales each W_l and b_l by amax/448 and each hidden-layer output h_l
+ *   by 2^ceil(log2(B_l/448)) before rounding it to E4M3, with B_l a bound on
+ *   |h_l| over every configuration (B_0 = 1, B_l = max_k sum_i |W_l[k,i]|
+ *   B_{l-1} + |b_l[k]| on the rounded weights); it samples on the batched-GEMM
+ *   path (lanes_per_chain is ignored) and gives local energies.
  * RESCNN (App. H): residual convolutional network on the periodic lat_L x lat_L
  *   lattice (lat_dim = 2, n_visible = lat_L^2), widths[0] = F filters,
  *   n_layers = R residual blocks:  h0 = Conv(s);  h += Conv(phi(Conv(phi(LN h))));
@@ -130,7 +135,7 @@ typedef struct {
     int64_t n_chains;
     int32_t n_sweeps, n_burnin, sweep_size;
     int32_t move;                     /* nqs_move */
-    int32_t dtype;                    /* sampling copy: NQS_F32 / NQS_F16 / NQS_BF16, or NQS_FP8_E4M3 for an RBM */
+    int32_t dtype;                    /* sampling copy: NQS_F32 / NQS_F16 / NQS_BF16, or NQS_FP8_E4M3 for an RBM or FFNN */
     int32_t init_chains;
     uint64_t seed, step_offset;
     uint32_t instance_id;

@@ -23,14 +23,24 @@ typedef enum {
     NQS_PROBE_MFMA_F32 = 5,       /* v_mfma_f32_16x16x4_f32 */
     NQS_PROBE_MFMA_F64 = 6,       /* v_mfma_f64_16x16x4_f64 */
     NQS_PROBE_HBM_READ = 7,       /* read `size` bytes of src */
-    NQS_PROBE_HBM_COPY = 8        /* copy `size` bytes from src to dst */
+    NQS_PROBE_HBM_COPY = 8,       /* copy `size` bytes from src to dst */
+    NQS_PROBE_MUL_F32 = 9,        /* v_mul_f32 */
+    NQS_PROBE_XOR_U32 = 10,       /* v_xor_b32 (each of the eight values takes the xor of its neighbour) */
+    NQS_PROBE_DPP_ADD_F32 = 11,   /* v_add_f32 with a row_shr:1 DPP source */
+    NQS_PROBE_MULHI_U32 = 12,     /* v_mul_hi_u32 */
+    NQS_PROBE_FMA_F32_W1 = 13,    /* v_fma_f32, one block of 256 threads per CU (one wave per SIMD) */
+    NQS_PROBE_FMA_F32_W2 = 14,    /* v_fma_f32, two blocks per CU (two waves per SIMD) */
+    NQS_PROBE_FMA_F32_DEP = 15    /* one dependent v_fma_f32 chain per thread, one wave per SIMD (latency) */
 } nqs_probe_kind;
 
 /* One launch of probe `kind` on `stream` (asynchronous; the caller times it).
  * Compute probes: `size` = loop iterations per thread (1 .. 2^24), the grid is
- * 8 blocks of 256 threads per compute unit, `dst` = device scratch of at least
- * (CUs x 8 x 256) floats, `src` unused; *work = floating-point operations of
- * the launch (an FMA or a matrix product element counts 2, a log or exp 1).
+ * 8 blocks of 256 threads per compute unit (1 or 2 for the _W1 / _W2 / _DEP
+ * kinds), `dst` = device scratch of at least (CUs x 8 x 256) floats, `src`
+ * unused; every vector probe keeps eight independent chains per thread except
+ * _DEP (one); *work = operations of the launch per lane (an FMA or a matrix
+ * product element counts 2; a multiply, log, exp, DPP add or integer
+ * instruction 1).
  * Memory probes: `size` = bytes, a positive multiple of 16; `src` a device
  * buffer of that size; `dst` for the copy a second one, for the read a
  * scratch of at least (CUs x 16 x 256) floats; all 16-byte aligned; *work =

@@ -35,6 +35,35 @@
 namespace nqs {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 16 staged bytes
+typedef int i32x8 __attribute__((ext_vector_type(8)));             // 32 FP8 codes
+
+// An OCP E4M3 code (1 sign, 4 exponent bits with bias 7, 3 mantissa bits) as a
+// matrix-core operand.  Products on v_mfma_f32_32x32x64_f8f6f4 (both operands
+// E4M3, unscaled), FP32 accumulation; a lane holds 32 consecutive K values.
+struct Fp8 {
+    uint8_t v;
+};
+
+template <>
+struct Mc<Fp8> {
+    static constexpr int EPL = 32;   // K elements per lane per instruction (K = 64)
+    typedef i32x8 frag;
+    static __device__ __forceinline__ mc_floatx16 mma(frag a, frag b, mc_floatx16 c)
+    {
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+    }
+};
+
+// E4M3 code of v, 0 <= v < 464 (the scaled layer outputs never exceed 448), rounded to nearest even:
+// normal values drop 20 of FP32's 23 mantissa bits (the carry of a round-up moves into the exponent),
+// values below 2^-6 are multiples of the subnormal step 2^-9.
+__device__ __forceinline__ uint32_t e4m3_code_nonneg(float v)
+{
+    const uint32_t x = __float_as_uint(v);
+    const uint32_t nrm = ((x + 0x7FFFFu + ((x >> 20) & 1u)) >> 20) - (120u << 3);
+    const uint32_t sub = (uint32_t)__builtin_rintf(v * 512.0f);
+    return v < 0.015625f ? sub : nrm;
+}
 
 constexpr int kDT = 128;   // output tile side
 constexpr int kDBytes = 128;   // contraction bytes per row per step
@@ -55,14 +84,17 @@ struct DeepGemmArgs {
     int ldo;
     int nct;                   // output column tiles
     int max_row_tiles;
+    float acc_scale;           // E4M3: accumulator -> pre-activation scale (weight scale x input scale)
+    float next_inv;            // E4M3: 1 / scale of the next layer's input
 };
 
 // Bit pattern of +-1 (or 0) in the operand format.
 template <typename T>
 __device__ __forceinline__ uint32_t deep_pm1_bits(int s)
 {
-    constexpr uint32_t one = sizeof(T) == 4 ? 0x3F800000u : (std::is_same<T, _Float16>::value ? 0x3C00u : 0x3F80u);
-    constexpr uint32_t sign = sizeof(T) == 4 ? 0x80000000u : 0x8000u;
+    constexpr uint32_t one = sizeof(T) == 4 ? 0x3F800000u
+                           : (sizeof(T) == 1 ? 0x38u : (std::is_same<T, _Float16>::value ? 0x3C00u : 0x3F80u));
+    constexpr uint32_t sign = sizeof(T) == 4 ? 0x80000000u : (sizeof(T) == 1 ? 0x80u : 0x8000u);
     return s == 0 ? 0u : (one | (s < 0 ? sign : 0u));
 }
 
@@ -125,6 +157,31 @@ __device__ __forceinline__ void deep_load_a(const DeepGemmArgs &g, int r0, int k
                     return u32x4{w0, w1, w2, w3};
                 }
             }
+            if constexpr (sizeof(T) == 1) {
+                // 16 spins in one 16-byte load: +1 = 0x01, -1 = 0xff, so the E4M3 code of the spin is
+                // 0x38 (1.0) with the spin's sign bit; then the row's sites are negated
+                if (row < nrows && (g.N & 15) == 0 && k0 + 16 <= g.N) {
+                    const u32x4 raw = *reinterpret_cast<const u32x4 *>(g.spins + (size_t)rc[q] * g.N + k0);
+                    w0 = 0x38383838u | (raw.x & 0x80808080u);
+                    w1 = 0x38383838u | (raw.y & 0x80808080u);
+                    w2 = 0x38383838u | (raw.z & 0x80808080u);
+                    w3 = 0x38383838u | (raw.w & 0x80808080u);
+                    const uint32_t ei = (uint32_t)(ri[q] - k0), ej = (uint32_t)(rj[q] - k0);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const uint32_t e = t == 0 ? ei : ej;
+                        if (e < 16u) {
+                            const uint32_t m = 0x80u << (8 * (e & 3u));
+                            const uint32_t wsel = e >> 2;
+                            w0 ^= wsel == 0 ? m : 0u;
+                            w1 ^= wsel == 1 ? m : 0u;
+                            w2 ^= wsel == 2 ? m : 0u;
+                            w3 ^= wsel == 3 ? m : 0u;
+                        }
+                    }
+                    return u32x4{w0, w1, w2, w3};
+                }
+            }
             if (row < nrows) {
                 const int8_t *sp = g.spins + (size_t)rc[q] * g.N;
 #pragma unroll
@@ -133,8 +190,8 @@ __device__ __forceinline__ void deep_load_a(const DeepGemmArgs &g, int r0, int k
                     int sv = k < g.N ? (int)sp[k] : 0;
                     if (k == ri[q] || k == rj[q]) sv = -sv;
                     const uint32_t bits = deep_pm1_bits<T>(sv);
-                    const int word = sizeof(T) == 4 ? x : (x >> 1);
-                    const uint32_t sh = sizeof(T) == 4 ? 0u : 16u * (x & 1);
+                    const int word = sizeof(T) == 4 ? x : (sizeof(T) == 2 ? (x >> 1) : (x >> 2));
+                    const uint32_t sh = sizeof(T) == 4 ? 0u : (sizeof(T) == 2 ? 16u * (x & 1) : 8u * (x & 3));
                     if (word == 0) w0 |= bits << sh;
                     else if (word == 1) w1 |= bits << sh;
                     else if (word == 2) w2 |= bits << sh;
@@ -168,6 +225,18 @@ __device__ __forceinline__ void deep_store(T *dst, const Stage4 &v)
     p[step] = v.x1;
     p[2 * step] = v.x2;
     p[3 * step] = v.x3;
+}
+
+// A fragment of LDS (rows are 16-byte aligned; the 32-byte FP8 fragment is read as two halves)
+template <typename T>
+__device__ __forceinline__ typename Mc<T>::frag deep_frag(const T *p)
+{
+    if constexpr (sizeof(T) == 1) {
+        const u32x4 lo = *reinterpret_cast<const u32x4 *>(p), hi = *reinterpret_cast<const u32x4 *>(p + 16);
+        return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    } else {
+        return *reinterpret_cast<const typename Mc<T>::frag *>(p);
+    }
 }
 
 template <typename T, bool SPINS, bool LOGCOSH>
@@ -244,10 +313,10 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
 #pragma unroll
         for (int kk = 0; kk < KI; ++kk) {
             const int ko = kk * 2 * EPL + EPL * h;
-            const frag a0 = *reinterpret_cast<const frag *>(As + (wm + l32) * LD + ko);
-            const frag a1 = *reinterpret_cast<const frag *>(As + (wm + 32 + l32) * LD + ko);
-            const frag b0 = *reinterpret_cast<const frag *>(Bs + (wn + l32) * LD + ko);
-            const frag b1 = *reinterpret_cast<const frag *>(Bs + (wn + 32 + l32) * LD + ko);
+            const frag a0 = deep_frag<T>(As + (wm + l32) * LD + ko);
+            const frag a1 = deep_frag<T>(As + (wm + 32 + l32) * LD + ko);
+            const frag b0 = deep_frag<T>(Bs + (wn + l32) * LD + ko);
+            const frag b1 = deep_frag<T>(Bs + (wn + 32 + l32) * LD + ko);
             if constexpr (LOGCOSH) {   // D[i = output][j = row]
                 acc[0][0] = Mc<T>::mma(b0, a0, acc[0][0]);
                 acc[0][1] = Mc<T>::mma(b1, a0, acc[0][1]);
@@ -285,7 +354,9 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
                 for (int r = 0; r < 16; ++r) {
                     const int col = n0 + wn + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3);
                     if (col < g.Nout) {
-                        const float v = fabsf(acc[a][b][r] + g.bias[col]);
+                        const float z = std::is_same<T, Fp8>::value ? fmaf(acc[a][b][r], g.acc_scale, g.bias[col])
+                                                                   : acc[a][b][r] + g.bias[col];
+                        const float v = fabsf(z);
                         abs_sum += v;
                         prod *= 1.0f + __expf(-2.0f * v);   // 32 factors in (1, 2]
                         ++cnt;
@@ -307,8 +378,14 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
                     const int row = m0 + wm + 32 * a + 8 * (r >> 2) + 4 * h + (r & 3);
                     const int col = n0 + wn + 32 * b + l32;
                     if (row < nrows && col < g.ldo) {
-                        const float v = col < g.Nout ? fmaxf(acc[a][b][r] + g.bias[col], 0.0f) : 0.0f;
-                        out[(size_t)row * g.ldo + col] = Mc<T>::from_f32(v);
+                        if constexpr (std::is_same<T, Fp8>::value) {
+                            // the next layer's input: ReLU(z) / s_next as an E4M3 code (s_next a power of two)
+                            const float v = col < g.Nout ? fmaxf(fmaf(acc[a][b][r], g.acc_scale, g.bias[col]), 0.0f) : 0.0f;
+                            out[(size_t)row * g.ldo + col] = Fp8{(uint8_t)e4m3_code_nonneg(v * g.next_inv)};
+                        } else {
+                            const float v = col < g.Nout ? fmaxf(acc[a][b][r] + g.bias[col], 0.0f) : 0.0f;
+                            out[(size_t)row * g.ldo + col] = Mc<T>::from_f32(v);
+                        }
                     }
                 }
     }
@@ -534,8 +611,11 @@ static void deep_forward(int dtype, const FfnnDev &f, const DeepBuffers &b, cons
         g.nct = f.Np[l] / kDT;
         g.out = last ? (void *)b.part : b.H[l & 1];
         g.ldo = last ? 0 : f.Kp[l + 1];
+        g.acc_scale = f.acc_scale[l];
+        g.next_inv = f.next_inv[l];
         if (dtype == NQS_F16) deep_gemm_dispatch<_Float16>(l == 0, last, g, s);
         else if (dtype == NQS_BF16) deep_gemm_dispatch<__bf16>(l == 0, last, g, s);
+        else if (dtype == NQS_FP8_E4M3) deep_gemm_dispatch<Fp8>(l == 0, last, g, s);
         else deep_gemm_dispatch<float>(l == 0, last, g, s);
     }
 }
@@ -546,7 +626,7 @@ nqs_status deep_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     const FfnnDev &f = m->copies[cfg.dtype].ffnn;
     const int N = f.widths[0];
     const int64_t C = cfg.n_chains;
-    const int esize = cfg.dtype == NQS_F32 ? 4 : 2;
+    const int esize = cfg.dtype == NQS_F32 ? 4 : (cfg.dtype == NQS_FP8_E4M3 ? 1 : 2);
     if (C > INT32_MAX / 2) return set_error(NQS_EINVAL, "too many chains");
     // scratch: forward buffers + per-chain state
     const size_t fwd = deep_buffer_bytes(f, C, esize);
@@ -779,7 +859,7 @@ nqs_status deep_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
 {
     const FfnnDev &f = m->copies[dtype].ffnn;
     const int N = f.widths[0];
-    const int esize = dtype == NQS_F32 ? 4 : 2;
+    const int esize = dtype == NQS_F32 ? 4 : (dtype == NQS_FP8_E4M3 ? 1 : 2);
     const int per = 2 * N + 1;                               // rows per sample at most
     const int64_t cap = std::max<int64_t>(per, std::min<int64_t>(65536, (int64_t)per * std::max<int64_t>(1, n)));
     const int bs = (int)std::max<int64_t>(1, cap / per);     // samples per batch

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "common.h"
 #include "ffnn_reg.h"
@@ -58,10 +59,169 @@ __global__ void ffnn_pad_kernel(const float *__restrict__ src, int rows, int col
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP8 (E4M3) copy.  Every weight tensor W_l and bias b_l has its own scale
+// amax/448 (FP32) and values q * scale, q an E4M3 code (the downcast of the
+// two-copy scheme, App. A extended to FP8).  The matrix cores multiply the
+// codes: W_l as [Np][Kp] bytes, the layer input as codes of the spins (+-1,
+// exact) or of h_{l-1} / s_l, where s_l = 2^ceil(log2(B_l / 448)) and B_l
+// bounds |h_l| over every configuration (B_0 = 1, B_l = max_k sum_i
+// |W_l[k,i]| B_{l-1} + |b_l[k]| on the rounded values), so no scaled input
+// exceeds 448.  The products are accumulated in FP32 and scaled back by
+// sW_l s_l.
+// ---------------------------------------------------------------------------
+
+// OCP E4M3 code of a value that is exactly representable in the format.
+__device__ __forceinline__ uint8_t e4m3_code_exact(double q)
+{
+    const uint32_t sign = q < 0.0 || (q == 0.0 && signbit(q)) ? 0x80u : 0u;
+    const double a = fabs(q);
+    if (a == 0.0) return (uint8_t)sign;
+    int e;
+    const double m = frexp(a, &e);            // a = m 2^e, m in [0.5, 1)
+    const int E = e - 1;                      // a = (2m) 2^E, 2m in [1, 2)
+    if (E < -6) return (uint8_t)(sign | (uint32_t)(a * 512.0));        // subnormal: a / 2^-9
+    return (uint8_t)(sign | ((uint32_t)(E + 7) << 3) | (uint32_t)((2.0 * m - 1.0) * 8.0));
+}
+
+// codes[Np][Kp] of W[out][in] / scale (zero padded) and the transposed FP32 values
+__global__ void ffnn_e4m3_codes_kernel(const double *__restrict__ W, int out, int in,
+                                       const unsigned long long *__restrict__ amax_bits, int Np, int Kp,
+                                       uint8_t *__restrict__ codes, float *__restrict__ Wt)
+{
+    const double amax = __longlong_as_double((long long)*amax_bits);
+    const float scale = amax > 0.0 ? (float)(amax / 448.0) : 1.0f;
+    const int64_t n = (int64_t)Np * Kp;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(p / Kp), c = (int)(p % Kp);
+        uint8_t code = 0;
+        if (r < out && c < in) {
+            const double q = round_to_dtype(W[(int64_t)r * in + c] / (double)scale, kE4M3);
+            code = e4m3_code_exact(q);
+            Wt[(int64_t)c * out + r] = (float)(q * (double)scale);
+        }
+        codes[p] = code;
+    }
+}
+
+// Per row k of W (one wave each): rs[k] = sum_i |q_ki| and bq[k] = |q_bk|, with q the E4M3 values
+// before scaling (multiples of 2^-9 below 448: the FP64 sums are exact in any order).
+__global__ void ffnn_e4m3_rowsum_kernel(const double *__restrict__ W, const double *__restrict__ b, int out, int in,
+                                        const unsigned long long *__restrict__ amax_w,
+                                        const unsigned long long *__restrict__ amax_b, double *rs, double *bq)
+{
+    const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= out) return;
+    const double aw = __longlong_as_double((long long)*amax_w), ab = __longlong_as_double((long long)*amax_b);
+    const float sw = aw > 0.0 ? (float)(aw / 448.0) : 1.0f, sb = ab > 0.0 ? (float)(ab / 448.0) : 1.0f;
+    double acc = 0.0;
+    for (int c = lane; c < in; c += 64) acc += fabs(round_to_dtype(W[(int64_t)r * in + c] / (double)sw, kE4M3));
+    acc = group_sum<64>(acc);
+    if (lane == 0) {
+        rs[r] = acc;
+        bq[r] = fabs(round_to_dtype(b[r] / (double)sb, kE4M3));
+    }
+}
+
+static nqs_status ffnn_build_e4m3(nqs_model *m, hipStream_t stream)
+{
+    const nqs_model_desc &d = m->desc;
+    Copy &c = m->copies[NQS_FP8_E4M3];
+    FfnnDev &f = c.ffnn;
+    const int L = d.n_layers;
+    f.n_layers = L;
+    f.widths[0] = d.n_visible;
+    for (int l = 0; l < L; ++l) f.widths[l + 1] = d.widths[l];
+    f.m1p = f.m2p = 0;   // the two-layer register kernels take 16-bit copies only
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t bytes = al(sizeof(unsigned long long) * 2 * L);
+    for (int l = 0; l < L; ++l) {
+        const size_t n = (size_t)f.widths[l + 1] * f.widths[l];
+        f.Kp[l] = (f.widths[l] + 127) / 128 * 128;   // 128 one-byte codes per contraction step
+        f.Np[l] = (f.widths[l + 1] + 127) / 128 * 128;
+        bytes += 2 * al(sizeof(float) * n) + al(sizeof(float) * f.widths[l + 1]) + al((size_t)f.Np[l] * f.Kp[l]) +
+                 al(sizeof(float) * f.Np[l]) + 2 * al(sizeof(double) * f.widths[l + 1]);
+    }
+    if (!c.block) NQS_HIP_TRY(hipMalloc(&c.block, bytes));
+    char *base = (char *)c.block;
+    auto carve = [&](size_t sz) {
+        char *p = base;
+        base += al(sz);
+        return p;
+    };
+    unsigned long long *amax = (unsigned long long *)carve(sizeof(unsigned long long) * 2 * L);
+    double *rs[NQS_MAX_LAYERS], *bq[NQS_MAX_LAYERS];
+    int64_t off = 0;
+    for (int l = 0; l < L; ++l) {
+        const int out = f.widths[l + 1], in = f.widths[l];
+        const int64_t n = (int64_t)out * in;
+        f.W[l] = (float *)carve(sizeof(float) * n);
+        f.Wt[l] = (float *)carve(sizeof(float) * n);
+        f.b[l] = (float *)carve(sizeof(float) * out);
+        f.Wd[l] = carve((size_t)f.Np[l] * f.Kp[l]);
+        f.bd[l] = (float *)carve(sizeof(float) * f.Np[l]);
+        rs[l] = (double *)carve(sizeof(double) * out);
+        bq[l] = (double *)carve(sizeof(double) * out);
+        const double *Wm = m->master + off, *bm = m->master + off + n;
+        nqs_status e = launch_e4m3_tensor(Wm, n, amax + 2 * l, f.W[l], stream);
+        if (e != NQS_OK) return e;
+        e = launch_e4m3_tensor(bm, out, amax + 2 * l + 1, f.b[l], stream);
+        if (e != NQS_OK) return e;
+        const int64_t nc = (int64_t)f.Np[l] * f.Kp[l];
+        hipLaunchKernelGGL(ffnn_e4m3_codes_kernel, dim3((unsigned)std::min<int64_t>((nc + 255) / 256, 8192)), dim3(256),
+                           0, stream, Wm, out, in, (const unsigned long long *)(amax + 2 * l), f.Np[l], f.Kp[l],
+                           (uint8_t *)f.Wd[l], f.Wt[l]);
+        hipLaunchKernelGGL(ffnn_pad_kernel, dim3((f.Np[l] + 255) / 256), dim3(256), 0, stream, f.b[l], 1, out, out, 1,
+                           f.Np[l], (int)kF32, (uint16_t *)nullptr, f.bd[l]);
+        hipLaunchKernelGGL(ffnn_e4m3_rowsum_kernel, dim3((out + 3) / 4), dim3(256), 0, stream, Wm, bm, out, in,
+                           (const unsigned long long *)(amax + 2 * l), (const unsigned long long *)(amax + 2 * l + 1),
+                           rs[l], bq[l]);
+        NQS_HIP_TRY(hipGetLastError());
+        off += n + out;
+    }
+    if ((size_t)(base - (char *)c.block) > bytes) return set_error(NQS_EDEVICE, "internal layout overflow");
+    // scales on the host: weight scales from the amax words, input scales from the bounds B_l
+    std::vector<unsigned long long> hmax(2 * L);
+    NQS_HIP_TRY(hipMemcpyAsync(hmax.data(), amax, sizeof(unsigned long long) * 2 * L, hipMemcpyDeviceToHost, stream));
+    std::vector<std::vector<double>> hrs(L), hbq(L);
+    for (int l = 0; l + 1 < L; ++l) {
+        hrs[l].resize(f.widths[l + 1]);
+        hbq[l].resize(f.widths[l + 1]);
+        NQS_HIP_TRY(hipMemcpyAsync(hrs[l].data(), rs[l], sizeof(double) * f.widths[l + 1], hipMemcpyDeviceToHost, stream));
+        NQS_HIP_TRY(hipMemcpyAsync(hbq[l].data(), bq[l], sizeof(double) * f.widths[l + 1], hipMemcpyDeviceToHost, stream));
+    }
+    NQS_HIP_TRY(hipStreamSynchronize(stream));
+    auto scale_of = [](unsigned long long bits) {
+        double a;
+        std::memcpy(&a, &bits, sizeof(double));
+        return a > 0.0 ? (float)(a / 448.0) : 1.0f;
+    };
+    double B = 1.0;          // bound on |input of layer l| (spins)
+    float s_in = 1.0f;       // scale of the input of layer l
+    for (int l = 0; l < L; ++l) {
+        const float sw = scale_of(hmax[2 * l]), sb = scale_of(hmax[2 * l + 1]);
+        f.acc_scale[l] = sw * s_in;   // s_in is a power of two: exact
+        if (l + 1 < L) {
+            double Bn = 0.0;
+            for (int k = 0; k < f.widths[l + 1]; ++k)
+                Bn = std::max(Bn, ((double)sw * hrs[l][k]) * B + (double)sb * hbq[l][k]);
+            const float s_next = Bn > 0.0 ? (float)std::ldexp(1.0, (int)std::ceil(std::log2(Bn / 448.0))) : 1.0f;
+            f.next_inv[l] = 1.0f / s_next;   // exact: a power of two
+            B = Bn;
+            s_in = s_next;
+        } else {
+            f.next_inv[l] = 1.0f;
+        }
+    }
+    c.valid = true;
+    return NQS_OK;
+}
+
 nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream)
 {
     const nqs_model_desc &d = m->desc;
-    if (dtype == NQS_FP8_E4M3) return set_error(NQS_EUNSUPPORTED, "FP8 dense copies are not built yet");
+    if (dtype == NQS_FP8_E4M3) return ffnn_build_e4m3(m, stream);
     Copy &c = m->copies[dtype];
     FfnnDev &f = c.ffnn;
     f.n_layers = d.n_layers;
@@ -460,12 +620,14 @@ nqs_status deep_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
 // (any depth) instead of the two-layer kernels with an incremental first layer.
 static nqs_status ffnn_mc_ready(nqs_model *m, int dtype, hipStream_t stream, bool *deep)
 {
-    if (dtype != NQS_F32 && dtype != NQS_BF16 && dtype != NQS_F16)
-        return set_error(NQS_EUNSUPPORTED, "dense networks sample in F32, BF16 or F16");
+    if (dtype != NQS_F32 && dtype != NQS_BF16 && dtype != NQS_F16 && dtype != NQS_FP8_E4M3)
+        return set_error(NQS_EUNSUPPORTED, "dense networks sample in F32, BF16, F16 or FP8_E4M3");
     nqs_status st = ensure_copy(m, dtype, stream);
     if (st != NQS_OK) return st;
     const FfnnDev &f = m->copies[dtype].ffnn;
-    *deep = m->desc.n_layers != 2 || f.m1p > 512 || (int64_t)f.widths[0] * f.m1p * (dtype == NQS_F32 ? 0 : 2) > 96 * 1024;
+    // the FP8 copy runs only the batched path (its layer products need whole E4M3 operand tiles)
+    *deep = dtype == NQS_FP8_E4M3 || m->desc.n_layers != 2 || f.m1p > 512 ||
+            (int64_t)f.widths[0] * f.m1p * (dtype == NQS_F32 ? 0 : 2) > 96 * 1024;
     return NQS_OK;
 }
 

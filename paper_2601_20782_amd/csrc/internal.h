@@ -52,8 +52,13 @@ struct FfnnDev {
     // batched-GEMM path of any depth: layer l padded to Np[l] outputs (multiple
     // of 128) x Kp[l] inputs (multiple of 64), zeros in the padding
     int Kp[NQS_MAX_LAYERS] = {0}, Np[NQS_MAX_LAYERS] = {0};
-    void *Wd[NQS_MAX_LAYERS] = {nullptr};  // [Np][Kp] bf16/f16 codes, or FP32 values
+    void *Wd[NQS_MAX_LAYERS] = {nullptr};  // [Np][Kp] bf16/f16/e4m3 codes, or FP32 values
     float *bd[NQS_MAX_LAYERS] = {nullptr}; // [Np]
+    // E4M3 copy: layer l computes z = (sum_k qW qA) acc_scale[l] + b, acc_scale = weight scale x input
+    // scale (the input scale a power of two, 1 for the spins), and stores the next layer's input as the
+    // code of ReLU(z) next_inv[l] (next_inv = 1 / the next input scale).  1 in the other formats.
+    float acc_scale[NQS_MAX_LAYERS] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
+    float next_inv[NQS_MAX_LAYERS] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
 };
 
 // Residual convolutional network copy in one sampling format: one FP32 array

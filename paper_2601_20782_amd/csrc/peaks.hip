@@ -22,24 +22,49 @@ constexpr int kProbeUnroll = 16;
 template <int KIND>
 __global__ void __launch_bounds__(kProbeThreads) probe_valu_kernel(float *__restrict__ out, int iters)
 {
+    constexpr int kChains = KIND == NQS_PROBE_FMA_F32_DEP ? 1 : 8;
     const int t = blockIdx.x * kProbeThreads + threadIdx.x;
-    float a[8];
+    float a[kChains];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = 1.5f + 1e-3f * (float)((t + k) & 255);
+    for (int k = 0; k < kChains; ++k) a[k] = 1.5f + 1e-3f * (float)((t + k) & 255);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u)
+#pragma unroll
+            for (int k = 0; k < kChains; ++k) {
+                if constexpr (KIND == NQS_PROBE_LOG_F32) a[k] = __builtin_amdgcn_logf(a[k]) + 2.0f;
+                else if constexpr (KIND == NQS_PROBE_EXP_F32) a[k] = __builtin_amdgcn_exp2f(a[k]) * 0.25f;
+                else if constexpr (KIND == NQS_PROBE_MUL_F32) a[k] = a[k] * 0.9999999f;
+                else if constexpr (KIND == NQS_PROBE_DPP_ADD_F32) a[k] = a[k] + dpp_f32<0x111, 0xF, 0xF>(a[k]);
+                else a[k] = fmaf(a[k], 0.9999999f, 1e-7f);   // the FMA kinds
+            }
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) s += a[k];
+    if (s == -1.0f) out[t] = s;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(kProbeThreads) probe_int_kernel(float *__restrict__ out, int iters)
+{
+    const uint32_t t = blockIdx.x * kProbeThreads + threadIdx.x;
+    uint32_t a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = 0x9E3779B9u * (t + (uint32_t)k) + 1u;
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
         for (int u = 0; u < kProbeUnroll; ++u)
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                if constexpr (KIND == NQS_PROBE_FMA_F32) a[k] = fmaf(a[k], 0.9999999f, 1e-7f);
-                else if constexpr (KIND == NQS_PROBE_LOG_F32) a[k] = __builtin_amdgcn_logf(a[k]) + 2.0f;
-                else a[k] = __builtin_amdgcn_exp2f(a[k]) * 0.25f;
+                if constexpr (KIND == NQS_PROBE_MULHI_U32) a[k] = __umulhi(a[k], 0xD2511F53u);
+                else asm volatile("v_xor_b32 %0, %1, %0" : "+v"(a[k]) : "v"(a[(k + 1) & 7]));   // kept as written
             }
     }
-    float s = 0.0f;
+    uint32_t s = 0u;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s += a[k];
-    if (s == -1.0f) out[t] = s;
+    for (int k = 0; k < 8; ++k) s ^= a[k];
+    if (s == 0x12345678u) out[t] = (float)s;
 }
 
 template <int KIND>
@@ -111,7 +136,8 @@ extern "C" nqs_status nqs_probe_rate(int32_t kind, int64_t size, const void *src
                                      void *stream)
 {
     if (!work) return set_error(NQS_EINVAL, "NULL work");
-    const bool compute = kind >= NQS_PROBE_FMA_F32 && kind <= NQS_PROBE_MFMA_F64;
+    const bool compute = (kind >= NQS_PROBE_FMA_F32 && kind <= NQS_PROBE_MFMA_F64) ||
+                         (kind >= NQS_PROBE_MUL_F32 && kind <= NQS_PROBE_FMA_F32_DEP);
     const bool memory = kind == NQS_PROBE_HBM_READ || kind == NQS_PROBE_HBM_COPY;
     if (!compute && !memory) return set_error(NQS_EINVAL, "unknown probe kind");
     if (compute && (size < 1 || size > (1 << 24))) return set_error(NQS_EINVAL, "iterations must be in [1, 2^24]");
@@ -141,6 +167,35 @@ extern "C" nqs_status nqs_probe_rate(int32_t kind, int64_t size, const void *src
             hipLaunchKernelGGL(probe_valu_kernel<NQS_PROBE_EXP_F32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
             *work = threads * per * 8;
             break;
+        case NQS_PROBE_MUL_F32:
+            hipLaunchKernelGGL(probe_valu_kernel<NQS_PROBE_MUL_F32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads * per * 8;
+            break;
+        case NQS_PROBE_DPP_ADD_F32:
+            hipLaunchKernelGGL(probe_valu_kernel<NQS_PROBE_DPP_ADD_F32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads * per * 8;
+            break;
+        case NQS_PROBE_XOR_U32:
+            hipLaunchKernelGGL(probe_int_kernel<NQS_PROBE_XOR_U32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads * per * 8;
+            break;
+        case NQS_PROBE_MULHI_U32:
+            hipLaunchKernelGGL(probe_int_kernel<NQS_PROBE_MULHI_U32>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
+            *work = threads * per * 8;
+            break;
+        case NQS_PROBE_FMA_F32_W1:
+        case NQS_PROBE_FMA_F32_W2: {
+            const int b = device_cus() * (kind == NQS_PROBE_FMA_F32_W1 ? 1 : 2);
+            hipLaunchKernelGGL(probe_valu_kernel<NQS_PROBE_FMA_F32_W1>, dim3(b), dim3(kProbeThreads), 0, s, o, it);
+            *work = (double)b * kProbeThreads * per * 8 * 2;
+            break;
+        }
+        case NQS_PROBE_FMA_F32_DEP: {
+            const int b = device_cus();
+            hipLaunchKernelGGL(probe_valu_kernel<NQS_PROBE_FMA_F32_DEP>, dim3(b), dim3(kProbeThreads), 0, s, o, it);
+            *work = (double)b * kProbeThreads * per * 2;
+            break;
+        }
         case NQS_PROBE_MFMA_BF16_K16:
             hipLaunchKernelGGL(probe_mfma_kernel<NQS_PROBE_MFMA_BF16_K16>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
             *work = threads / 64 * per * 4 * (2.0 * 16 * 16 * 16);
