@@ -48,6 +48,7 @@ Other workloads (--workload):
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -556,6 +557,9 @@ def run_uneven(a, torch, nqs, workloads):
 
     ms0 = timed(lambda: nqs.nqs_sample_batched(jobs, mode=0))
     ms1 = timed(lambda: nqs.nqs_sample_batched(jobs, mode=1))
+    # every instance at the tuner's choice between 32 and 64 lanes per chain (measured on the first call)
+    jobs_t = [dict(j, cfg=dataclasses.replace(j["cfg"], lanes_per_chain=nqs.LANES_TUNED)) for j in jobs]
+    ms_t = timed(lambda: nqs.nqs_sample_batched(jobs_t, mode=0))
     # the 32 separate launches captured once into a graph and replayed
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
@@ -573,7 +577,9 @@ def run_uneven(a, torch, nqs, workloads):
         "dtype": a.dtype, "data": "synthetic (32 seeded uneven TFIM/RBM instances)",
         "config": {"workload": "tfim2d_uneven_32", "instances": [w.name for w in insts], "chains_each": 1024,
                    "sweeps": 200, "burnin": 20, "proposals_per_step": props, "parallelism": "single GPU"},
-        "persistent_ms": ms0, "separate_launches_ms": ms1, "separate_launches_graph_ms": ms2,
+        "persistent_ms": ms0, "persistent_tuned_ms": ms_t, "separate_launches_ms": ms1,
+        "separate_launches_graph_ms": ms2,
+        "lanes_rule": "32 lanes per chain for M <= 256, else 64 (persistent_tuned_ms: the measured choice)",
         "speedup_vs_separate": ms1 / ms0, "speedup_vs_graph": ms2 / ms0,
         "arith": f"FP32 arithmetic on {a.dtype.upper()}-rounded weights",
         "roofline": {"kernel": "rbm_batched_kernel", "bound": "alu",

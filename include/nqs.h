@@ -140,12 +140,16 @@ typedef struct {
     uint64_t seed, step_offset;
     uint32_t instance_id;
     int64_t chain_id_offset;          /* global id of chain 0 (for splitting chains across devices) */
-    int32_t lanes_per_chain;          /* RBM: 0 = a fixed function of (N, M), else 16, 32 or 64 lanes per chain.
+    int32_t lanes_per_chain;          /* RBM: 0 = a fixed function of (N, M), 16, 32 or 64 lanes per chain
+                                         (raised until the model fits), or NQS_LANES_TUNED = the measured
+                                         choice (see nqs_sample_plan).
                                          Dense network: 0 = automatic, -1 = the batched-GEMM path
                                          (a full forward pass of every proposal; the path taken
                                          anyway for depth != 2 or wide first layers) */
     int32_t refresh_sweeps;           /* recompute the incremental state every k sweeps (0 => 1) */
 } nqs_sample_cfg;
+
+#define NQS_LANES_TUNED (-2)
 
 /* Optional per-proposal decision trace of the first n_chains_traced chains
  * (device buffers of n_chains_traced x total-proposals entries, row-major),
@@ -192,8 +196,30 @@ nqs_status nqs_downcast(const double *src, int64_t n, int32_t dtype, float *dst,
 nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_state, int8_t *samples,
                       float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, void *stream);
 
+/* Launch plan of the RBM sampler (single flips) for this model, cfg.dtype and
+ * cfg.n_chains: lanes per chain G, hidden units per lane K = ceil(M/G),
+ * chains per workgroup, and whether the (cosh 2W, sinh 2W) table sits in LDS.
+ * With cfg->lanes_per_chain = NQS_LANES_TUNED the plan is measured: every
+ * valid G in {16, 32, 64}, both table placements and two chains-per-workgroup
+ * counts are timed on a short burn-in from fresh states in scratch memory (no
+ * caller buffer is touched; `stream` is synchronised), and the fastest is kept
+ * for the life of the process, keyed by (device, N, M, dtype, n_chains).
+ * nqs_sample with NQS_LANES_TUNED then uses it, so its results equal those of
+ * a call with lanes_per_chain = plan->lanes_per_chain.  Any other
+ * lanes_per_chain gives the fixed rule's plan without running anything.
+ * NQS_EUNSUPPORTED for other networks. */
+typedef struct {
+    int32_t lanes_per_chain;
+    int32_t units_per_lane;
+    int32_t chains_per_block;
+    int32_t table_in_lds;
+    int32_t tuned;                    /* 1: measured */
+    float tuned_ms;                   /* the chosen candidate's time on the tuning burn-in (0 for the rule) */
+} nqs_launch_plan;
+nqs_status nqs_sample_plan(nqs_model *m, const nqs_sample_cfg *cfg, nqs_launch_plan *plan, void *stream);
+
 /* One sampling job of a batch: a model, its configuration and its buffers
- * (same meaning as the arguments of nqs_sample). */
+ * (same meaning as the arguments of nqs_sample; trace may be NULL). */
 typedef struct {
     nqs_model *model;
     nqs_sample_cfg cfg;
@@ -201,15 +227,25 @@ typedef struct {
     int8_t *samples;
     float *logpsi;
     uint64_t *n_accepted;
+    const nqs_trace *trace;
 } nqs_sample_job;
 
 /* Sample many independent instances (RBM, single flips) of uneven sizes.
- *   mode 0: one persistent launch; work items of 4 chains are sorted by
+ *   mode 0: one persistent launch; work items of 256 / G chains are sorted by
  *           decreasing cost and taken from a shared counter.
  *   mode 1: one launch per job, in order, on `stream`.
- * Both modes produce identical samples (64 lanes per chain).  The batch
- * descriptors are staged in the library workspace; the call synchronises
- * `stream` once before launching. */
+ * Each instance runs at its own lanes per chain G: cfg.lanes_per_chain = 32
+ * or 64 as given (32 serves M <= 256, 64 serves M <= 1024), 0 for 32 when
+ * M <= 256 and 64 above, NQS_LANES_TUNED for a measured choice made for the
+ * whole batch: the persistent launch is timed on a short burn-in from fresh
+ * states in scratch memory with the tuned instances at 32 lanes, at 64, and
+ * at each one's single-launch choice (nqs_sample_plan restricted to 32/64),
+ * and the fastest assignment is kept for the life of the process, keyed by
+ * the batch's (N, M, dtype, n_chains, request) list.  Both modes produce
+ * identical results, equal to nqs_sample of each job at its G; traced chains
+ * record their decisions.  The batch descriptors are staged in the library
+ * workspace; the call synchronises `stream` once before launching (and while
+ * tuning). */
 nqs_status nqs_sample_batched(const nqs_sample_job *jobs, int32_t n_jobs, int32_t mode, void *stream);
 
 /* Metropolis-Hastings sampling of the noisy target of Sec. IV.A:

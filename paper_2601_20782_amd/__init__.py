@@ -19,10 +19,13 @@ import torch
 from . import _abi
 from ._abi import DTYPE_CODES, NqsError, check, load
 
+LANES_TUNED = -2   # SampleConfig.lanes_per_chain: the measured launch plan (include/nqs.h NQS_LANES_TUNED)
+
 __all__ = [
-    "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc", "nqs_logpsi_grad",
+    "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_sample_plan", "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc", "nqs_logpsi_grad",
     "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
     "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_probe_rate", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
+    "LANES_TUNED",
 ]
 
 
@@ -166,6 +169,29 @@ def nqs_downcast(src: torch.Tensor, dtype, dst: torch.Tensor, scale_out: Optiona
     check(load().nqs_downcast(_ptr(src), src.numel(), _dtype(dtype), _ptr(dst), _ptr(scale_out), _stream(stream)))
 
 
+def _trace_struct(trace: Optional[dict], cfg: "SampleConfig", N: int):
+    if trace is None:
+        return None
+    tr = _abi.Trace()
+    tr.n_chains_traced = trace["n"]
+    total = (cfg.n_sweeps + cfg.n_burnin) * (cfg.sweep_size or N)
+    for key, dt in (("site", torch.int32), ("ubits", torch.int32), ("delta", torch.float32), ("accepted", torch.uint8)):
+        t = trace[key]
+        assert t.dtype == dt and t.numel() == trace["n"] * total, key
+        setattr(tr, key, t.data_ptr())
+    return tr
+
+
+def nqs_sample_plan(model: Model, cfg: SampleConfig, stream=None) -> dict:
+    """Launch plan of the RBM sampler for this model and cfg (measured when cfg.lanes_per_chain is LANES_TUNED)."""
+    plan = _abi.LaunchPlan()
+    c = cfg.to_c()
+    check(load().nqs_sample_plan(model.handle, ctypes.byref(c), ctypes.byref(plan), _stream(stream)))
+    return {"lanes_per_chain": plan.lanes_per_chain, "units_per_lane": plan.units_per_lane,
+            "chains_per_block": plan.chains_per_block, "table_in_lds": bool(plan.table_in_lds),
+            "tuned": bool(plan.tuned), "tuned_ms": plan.tuned_ms}
+
+
 def nqs_sample(model: Model, cfg: SampleConfig, chain_state: torch.Tensor, samples: Optional[torch.Tensor] = None,
                logpsi: Optional[torch.Tensor] = None, n_accepted: Optional[torch.Tensor] = None,
                trace: Optional[dict] = None, stream=None) -> None:
@@ -177,16 +203,7 @@ def nqs_sample(model: Model, cfg: SampleConfig, chain_state: torch.Tensor, sampl
         assert logpsi.dtype == torch.float32 and logpsi.numel() == cfg.n_sweeps * cfg.n_chains
     if n_accepted is not None:
         assert n_accepted.dtype in (torch.int64, torch.uint64) and n_accepted.numel() == cfg.n_chains
-    tr = None
-    if trace is not None:
-        tr = _abi.Trace()
-        tr.n_chains_traced = trace["n"]
-        total = (cfg.n_sweeps + cfg.n_burnin) * (cfg.sweep_size or N)
-        for key, dt in (("site", torch.int32), ("ubits", torch.int32), ("delta", torch.float32),
-                        ("accepted", torch.uint8)):
-            t = trace[key]
-            assert t.dtype == dt and t.numel() == trace["n"] * total, key
-            setattr(tr, key, t.data_ptr())
+    tr = _trace_struct(trace, cfg, N)
     c = cfg.to_c()
     check(load().nqs_sample(model.handle, ctypes.byref(c), _ptr(chain_state), _ptr(samples), _ptr(logpsi),
                             _ptr(n_accepted), ctypes.byref(tr) if tr is not None else None, _stream(stream)))
@@ -210,8 +227,9 @@ def nqs_sample_noisy(model: Model, cfg: SampleConfig, noise_sigma: float, noise_
 
 def nqs_sample_batched(jobs, mode: int = 0, stream=None) -> None:
     """Sample many RBM instances; `jobs` is a list of dicts with keys model, cfg, chain_state and
-    optionally samples, logpsi, n_accepted (same meaning as for nqs_sample)."""
+    optionally samples, logpsi, n_accepted, trace (same meaning as for nqs_sample)."""
     arr = (_abi.SampleJob * len(jobs))()
+    keep = []
     for k, j in enumerate(jobs):
         model, cfg = j["model"], j["cfg"]
         N = model.n_visible
@@ -224,6 +242,9 @@ def nqs_sample_batched(jobs, mode: int = 0, stream=None) -> None:
         arr[k].samples = j["samples"].data_ptr() if j.get("samples") is not None else None
         arr[k].logpsi = j["logpsi"].data_ptr() if j.get("logpsi") is not None else None
         arr[k].n_accepted = j["n_accepted"].data_ptr() if j.get("n_accepted") is not None else None
+        tr = _trace_struct(j.get("trace"), cfg, N)
+        keep.append(tr)
+        arr[k].trace = ctypes.addressof(tr) if tr is not None else None
     check(load().nqs_sample_batched(arr, len(jobs), mode, _stream(stream)))
 
 

@@ -19,7 +19,7 @@ DTYPE_CODES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "e4m3": FP8_E4M
 # every function the headers under include/ declare
 EXPORTS = [
     "nqs_model_create", "nqs_model_set_params", "nqs_model_set_params_device", "nqs_model_destroy",
-    "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched",
+    "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched", "nqs_sample_plan",
     "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc",
     "nqs_logpsi_grad", "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
     "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex",
@@ -54,7 +54,17 @@ class SampleCfg(ctypes.Structure):
 
 class SampleJob(ctypes.Structure):
     _fields_ = [("model", ctypes.c_void_p), ("cfg", SampleCfg), ("chain_state", ctypes.c_void_p),
-                ("samples", ctypes.c_void_p), ("logpsi", ctypes.c_void_p), ("n_accepted", ctypes.c_void_p)]
+                ("samples", ctypes.c_void_p), ("logpsi", ctypes.c_void_p), ("n_accepted", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p)]
+
+
+class LaunchPlan(ctypes.Structure):
+    _fields_ = [("lanes_per_chain", ctypes.c_int32), ("units_per_lane", ctypes.c_int32),
+                ("chains_per_block", ctypes.c_int32), ("table_in_lds", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("tuned_ms", ctypes.c_float)]
+
+
+LANES_TUNED = -2
 
 
 class Trace(ctypes.Structure):
@@ -92,6 +102,7 @@ def load() -> ctypes.CDLL:
         "nqs_downcast": ([P, i64, i32, P, P, P], st),
         "nqs_sample": ([P, P, P, P, P, P, P, P], st),
         "nqs_sample_batched": ([P, i32, i32, P], st),
+        "nqs_sample_plan": ([P, P, P, P], st),
         "nqs_local_energy": ([P, P, P, i64, i32, P, P], st),
         "nqs_energy_stats": ([P, i64, i64, P, P], st),
         "nqs_energy_stats_noalloc": ([P, i64, i64, P, P], st),

@@ -37,6 +37,18 @@ struct Workspace {
 static std::mutex g_ws_mutex;
 static std::vector<Workspace> g_ws;   // [device * kWorkspaceSlots + slot]
 
+hipStream_t capture_stream()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) streams[dev] = nullptr;
+    return streams[dev];
+}
+
 int device_cus()
 {
     int dev = 0;
@@ -217,6 +229,8 @@ nqs_status nqs_model_destroy(nqs_model *m)
 {
     if (!m) return NQS_OK;
     (void)hipDeviceSynchronize();
+    if (m->sweep_exec) (void)hipGraphExecDestroy(m->sweep_exec);
+    if (m->sweep_done) (void)hipEventDestroy(m->sweep_done);
     for (auto &c : m->copies)
         if (c.block) (void)hipFree(c.block);
     (void)hipFree(m->master);
@@ -257,8 +271,10 @@ nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_sta
     if (c.sweep_size < 0) return set_error(NQS_EINVAL, "sweep_size < 0");
     if (c.instance_id >= (1u << 24)) return set_error(NQS_EINVAL, "instance_id must fit in 24 bits");
     if (c.lanes_per_chain != 0 && c.lanes_per_chain != 16 && c.lanes_per_chain != 32 && c.lanes_per_chain != 64 &&
-        !(c.lanes_per_chain == -1 && (m->desc.arch == NQS_FFNN || m->desc.arch == NQS_RESCNN)))
-        return set_error(NQS_EINVAL, "lanes_per_chain must be 0, 16, 32 or 64 (or -1 for a dense network)");
+        !(c.lanes_per_chain == -1 && (m->desc.arch == NQS_FFNN || m->desc.arch == NQS_RESCNN)) &&
+        !(c.lanes_per_chain == NQS_LANES_TUNED && m->desc.arch == NQS_RBM))
+        return set_error(NQS_EINVAL, "lanes_per_chain must be 0, 16, 32 or 64 (-1 for a dense network, "
+                                     "NQS_LANES_TUNED for an RBM)");
     if (c.dtype != NQS_F32 && c.dtype != NQS_F16 && c.dtype != NQS_BF16 && c.dtype != NQS_FP8_E4M3)
         return set_error(NQS_EINVAL, "sampling dtype must be F32, F16, BF16 or FP8_E4M3");
     if (c.chain_id_offset < 0 || c.chain_id_offset + c.n_chains > ((int64_t)1 << 32))
@@ -311,6 +327,34 @@ nqs_status nqs_sample_noisy(nqs_model *m, const nqs_sample_cfg *cfg, double nois
         return set_error(NQS_EINVAL, "global chain ids must fit in 32 bits");
     return rbm_sample(m, c, chain_state, samples, logpsi, n_accepted, nullptr, (hipStream_t)stream, noise_sigma,
                       noise_seed);
+}
+
+nqs_status nqs_sample_plan(nqs_model *m, const nqs_sample_cfg *cfg, nqs_launch_plan *plan, void *stream)
+{
+    if (!m || !cfg || !plan) return set_error(NQS_EINVAL, "NULL model, cfg or plan");
+    if (m->desc.arch != NQS_RBM) return set_error(NQS_EUNSUPPORTED, "launch plans describe the RBM sampler");
+    const nqs_sample_cfg &c = *cfg;
+    if (c.n_chains <= 0 || c.n_chains > (int64_t)1 << 31) return set_error(NQS_EINVAL, "n_chains must be in [1, 2^31]");
+    if (c.dtype != NQS_F32 && c.dtype != NQS_F16 && c.dtype != NQS_BF16 && c.dtype != NQS_FP8_E4M3)
+        return set_error(NQS_EINVAL, "sampling dtype must be F32, F16, BF16 or FP8_E4M3");
+    if (c.lanes_per_chain != 0 && c.lanes_per_chain != 16 && c.lanes_per_chain != 32 && c.lanes_per_chain != 64 &&
+        c.lanes_per_chain != NQS_LANES_TUNED)
+        return set_error(NQS_EINVAL, "lanes_per_chain must be 0, 16, 32, 64 or NQS_LANES_TUNED");
+    hipStream_t s = (hipStream_t)stream;
+    nqs_status st = ensure_copy(m, c.dtype, s);
+    if (st != NQS_OK) return st;
+    RbmPlan P;
+    st = c.lanes_per_chain == NQS_LANES_TUNED
+             ? rbm_plan_tuned(m, c, nullptr, 0, s, &P)
+             : rbm_plan_rule(m->desc.n_visible, m->desc.widths[0], c.n_chains, c.lanes_per_chain, -1, 0, &P);
+    if (st != NQS_OK) return st;
+    plan->lanes_per_chain = P.G;
+    plan->units_per_lane = P.K;
+    plan->chains_per_block = P.cpb;
+    plan->table_in_lds = P.lds ? 1 : 0;
+    plan->tuned = P.tuned ? 1 : 0;
+    plan->tuned_ms = P.tuned_ms;
+    return NQS_OK;
 }
 
 nqs_status nqs_sample_batched(const nqs_sample_job *jobs, int32_t n_jobs, int32_t mode, void *stream)

@@ -408,6 +408,7 @@ struct DeepStepArgs {
     int npart;
     unsigned long long *acc;  // [C]
     int64_t total;            // proposals per chain in this call
+    const int64_t *kbase;     // device: index of the current sweep's first proposal (graph replays), or NULL
     int n_traced;
     int32_t *tr_site;
     uint32_t *tr_ubits;
@@ -415,10 +416,11 @@ struct DeepStepArgs {
     uint8_t *tr_acc;
 };
 
-__global__ void deep_propose_kernel(DeepStepArgs a, int64_t k)
+__global__ void deep_propose_kernel(DeepStepArgs a, int64_t kk)
 {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= a.C) return;
+    const int64_t k = (a.kbase ? *a.kbase : 0) + kk;
     const uint64_t step = a.step_offset + (uint64_t)k;
     const uint32_t gid = a.chain_id_offset + (uint32_t)c;
     const Block4 rb = philox4x32_10((uint32_t)step, (uint32_t)(step >> 32), gid, a.inst << 8, (uint32_t)a.seed,
@@ -453,8 +455,9 @@ __global__ void deep_propose_kernel(DeepStepArgs a, int64_t k)
     }
 }
 
-__global__ void deep_decide_kernel(DeepStepArgs a, int64_t k)
+__global__ void deep_decide_kernel(DeepStepArgs a, int64_t kk)
 {
+    const int64_t k = (a.kbase ? *a.kbase : 0) + kk;
     const int n = a.counter[k & 1];
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r == 0) a.counter[(k + 1) & 1] = 0;   // the next step's counter (not in use now)
@@ -515,6 +518,24 @@ __global__ void deep_emit_kernel(const int8_t *state, int64_t C, int N, const fl
         if (samples) samples[p] = state[p];
         if (logpsi && p < C) logpsi[p] = fcur[p];
     }
+}
+
+// graph replays: the emit of the sweep that starts at proposal *kbase, then the advance to the next sweep
+__global__ void deep_emit_sweep_kernel(const int8_t *state, int64_t C, int N, const float *fcur, int8_t *samples,
+                                       float *logpsi, const int64_t *kbase, int sweep_size, int n_burnin, int n_sweeps)
+{
+    const int64_t out = *kbase / sweep_size - n_burnin;
+    if (out < 0 || out >= n_sweeps) return;
+    const int64_t n = C * N;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        if (samples) samples[(size_t)out * n + p] = state[p];
+        if (logpsi && p < C) logpsi[(size_t)out * C + p] = fcur[p];
+    }
+}
+
+__global__ void deep_set_i64_kernel(int64_t *p, int64_t v, int64_t add)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = add ? *p + add : v;
 }
 
 __global__ void deep_copy_acc_kernel(const unsigned long long *acc, int64_t C, uint64_t *out)
@@ -630,7 +651,8 @@ nqs_status deep_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     if (C > INT32_MAX / 2) return set_error(NQS_EINVAL, "too many chains");
     // scratch: forward buffers + per-chain state
     const size_t fwd = deep_buffer_bytes(f, C, esize);
-    const size_t per_chain = al256(sizeof(uint32_t) * C) + al256(sizeof(float) * C) + al256(sizeof(unsigned long long) * C);
+    const size_t per_chain = al256(sizeof(uint32_t) * C) + al256(sizeof(float) * C) + al256(sizeof(unsigned long long) * C) +
+                             al256(sizeof(int64_t));
     char *ws = (char *)workspace(fwd + per_chain, stream);
     if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
     DeepBuffers b = deep_carve(f, C, esize, ws);
@@ -638,6 +660,8 @@ nqs_status deep_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     uint32_t *ubits = (uint32_t *)pc;
     float *fcur = (float *)(pc + al256(sizeof(uint32_t) * C));
     unsigned long long *acc = (unsigned long long *)(pc + al256(sizeof(uint32_t) * C) + al256(sizeof(float) * C));
+    int64_t *kbase = (int64_t *)(pc + al256(sizeof(uint32_t) * C) + al256(sizeof(float) * C) +
+                                 al256(sizeof(unsigned long long) * C));
 
     if (cfg.init_chains) {
         nqs_status st = launch_init_chains(chain_state, C, N, cfg.move, cfg.seed, cfg.instance_id, cfg.chain_id_offset,
@@ -677,6 +701,67 @@ nqs_status deep_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     a.tr_ubits = tr ? trace->ubits : nullptr;
     a.tr_delta = tr ? trace->delta : nullptr;
     a.tr_acc = tr ? trace->accepted : nullptr;
+    a.kbase = nullptr;
+
+    // Two or more sweeps of an even size: capture one sweep's launches (proposal, forward pass, decision for each
+    // of its proposals, then the sample emit) once into a graph and replay it per sweep; the proposal index and
+    // the sweep come from a device counter that the graph's last node advances, so every replay is the same graph.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    NQS_HIP_TRY(hipStreamIsCapturing(stream, &cap));
+    const int n_sw = cfg.n_burnin + cfg.n_sweeps;
+    if (sw % 2 == 0 && n_sw >= 2 && cap == hipStreamCaptureStatusNone) {
+        a.kbase = kbase;
+        hipLaunchKernelGGL(deep_set_i64_kernel, dim3(1), dim3(1), 0, stream, kbase, (int64_t)0, (int64_t)0);
+        std::string sig;
+        auto add = [&](const void *p, size_t n) { sig.append((const char *)p, n); };
+        add(&a, sizeof(a));
+        add(&b, sizeof(b));
+        add(&f, sizeof(f));
+        const int64_t ints[6] = {cfg.dtype, C, sw, cfg.n_burnin, cfg.n_sweeps, N};
+        add(ints, sizeof(ints));
+        add(&samples, sizeof(samples));
+        add(&logpsi, sizeof(logpsi));
+        if (!m->sweep_exec || m->sweep_sig != sig) {
+            if (m->sweep_exec) {
+                // the previous graph may still run on another stream
+                if (m->sweep_done) NQS_HIP_TRY(hipEventSynchronize(m->sweep_done));
+                NQS_HIP_TRY(hipGraphExecDestroy(m->sweep_exec));
+                m->sweep_exec = nullptr;
+            }
+            hipStream_t cs = capture_stream();
+            if (!cs) return set_error(NQS_EDEVICE, "could not create the capture stream");
+            NQS_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+            for (int j = 0; j < sw; ++j) {
+                hipLaunchKernelGGL(deep_propose_kernel, dim3(cb), dim3(256), 0, cs, a, (int64_t)j);
+                DeepBuffers bk = b;
+                bk.counter = b.counter + (j & 1);   // k = kbase + j with kbase even
+                deep_forward(cfg.dtype, f, bk, chain_state, C, cs);
+                hipLaunchKernelGGL(deep_decide_kernel, dim3(cb), dim3(256), 0, cs, a, (int64_t)j);
+            }
+            if (samples || logpsi) {
+                const int eb = (int)std::min<int64_t>((C * N + 255) / 256, 8192);
+                hipLaunchKernelGGL(deep_emit_sweep_kernel, dim3(eb), dim3(256), 0, cs, chain_state, C, N, fcur, samples,
+                                   logpsi, (const int64_t *)kbase, sw, cfg.n_burnin, cfg.n_sweeps);
+            }
+            hipLaunchKernelGGL(deep_set_i64_kernel, dim3(1), dim3(1), 0, cs, kbase, (int64_t)0, (int64_t)sw);
+            hipGraph_t graph = nullptr;
+            const hipError_t e1 = hipStreamEndCapture(cs, &graph);
+            if (e1 != hipSuccess || !graph) return set_error(NQS_EDEVICE, "stream capture of the sweep failed");
+            const hipError_t e2 = hipGraphInstantiate(&m->sweep_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e2 != hipSuccess) {
+                m->sweep_exec = nullptr;
+                return set_error(NQS_EDEVICE, "graph instantiation failed");
+            }
+            m->sweep_sig = sig;
+            if (!m->sweep_done) NQS_HIP_TRY(hipEventCreateWithFlags(&m->sweep_done, hipEventDisableTiming));
+        }
+        for (int q = 0; q < n_sw; ++q) NQS_HIP_TRY(hipGraphLaunch(m->sweep_exec, stream));
+        NQS_HIP_TRY(hipEventRecord(m->sweep_done, stream));
+        if (n_accepted) hipLaunchKernelGGL(deep_copy_acc_kernel, dim3(cb), dim3(256), 0, stream, acc, C, n_accepted);
+        NQS_HIP_TRY(hipGetLastError());
+        return NQS_OK;
+    }
 
     int in_sweep = 0;
     int64_t sweep = 0;

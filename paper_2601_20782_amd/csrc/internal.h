@@ -106,6 +106,11 @@ struct nqs_model {
     double *master = nullptr;           // FP64 master parameters on the device
     nqs::Copy copies[5];                // indexed by nqs_dtype
     float *wb_f32 = nullptr;            // scratch FP32 rounded parameter vector [P]
+    // the dense-network sampler's captured sweep: executable graph, the event after its last
+    // replay, and the launch arguments it was captured with
+    hipGraphExec_t sweep_exec = nullptr;
+    hipEvent_t sweep_done = nullptr;
+    std::string sweep_sig;
 };
 
 namespace nqs {
@@ -128,6 +133,8 @@ nqs_status launch_zero_u64(void *p, int64_t n, hipStream_t stream);
 
 // Compute units of the current device (cached per device).
 int device_cus();
+// A stream of the current device that only records captures (never runs work).
+hipStream_t capture_stream();
 
 // Per-device growable scratch (never shrinks; freed at process exit).
 void *workspace(size_t bytes, hipStream_t stream);
@@ -179,6 +186,21 @@ struct RbmLaunch {
     int init;              // 1: draw the start states inside the kernel (flip moves)
     size_t lds_bytes;
 };
+// Launch plan of the RBM sampler: lanes per chain G, units per lane K, chains
+// per block, table placement.
+struct RbmPlan {
+    int G, K, cpb;
+    bool lds;
+    size_t tab_bytes;
+    bool tuned;
+    float tuned_ms;
+};
+// lds_req: -1 = LDS when the table fits, 0 = through L2, 1 = LDS; cpb_req 0 = spread over every CU
+nqs_status rbm_plan_rule(int N, int M, int64_t n_chains, int G, int lds_req, int cpb_req, RbmPlan *P);
+nqs_status rbm_plan_tuned(nqs_model *m, const nqs_sample_cfg &cfg, const int *Gs, int nG, hipStream_t stream,
+                          RbmPlan *out);
+nqs_status rbm_launch_plan(const RbmSampleArgs &A, const RbmPlan &P, bool trace, bool noise, int init,
+                           hipStream_t stream);
 nqs_status rbm_sample_launch_g16(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s);
 nqs_status rbm_sample_launch_g32(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s);
 nqs_status rbm_sample_launch_g64(const RbmSampleArgs &A, const RbmLaunch &L, hipStream_t s);

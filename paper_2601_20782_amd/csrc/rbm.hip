@@ -18,6 +18,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "common.h"
 #include "internal.h"
@@ -164,38 +168,170 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
         return NQS_OK;
     }
 
-    // launch shape: lanes per chain G, hidden units per lane K = ceil(M/G), chains per block
-    int G = cfg.lanes_per_chain;
+    RbmPlan P;
+    st = cfg.lanes_per_chain == NQS_LANES_TUNED ? rbm_plan_tuned(m, cfg, nullptr, 0, stream, &P)
+                                                : rbm_plan_rule(N, M, cfg.n_chains, cfg.lanes_per_chain, -1, 0, &P);
+    if (st != NQS_OK) return st;
+    if (noisy && !P.lds) return set_error(NQS_EUNSUPPORTED, "the noisy sampler needs the ratio table in LDS");
+    return rbm_launch_plan(A, P, tr, noisy, cfg.init_chains ? 1 : 0, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Launch plans.  The rule: lanes per chain G from (N, M) (16 up to M = 48,
+// 32 up to 256, else 64; raised until the spin words and ceil(M/G) units per
+// lane fit), the (C,S) table in LDS when it fits in 160 KiB, and as many
+// chains per block as spread the chains over every CU.  G fixes the FP32
+// summation order of the log-ratio; the other two choices change no result.
+// ---------------------------------------------------------------------------
+static int kmax_of(int g) { return g == 16 ? 13 : 16; }
+
+nqs_status rbm_plan_rule(int N, int M, int64_t n_chains, int G, int lds_req, int cpb_req, RbmPlan *P)
+{
     if (G == 0) G = M > 256 ? 64 : (M > 48 ? 32 : 16);
-    auto kmax = [](int g) { return g == 16 ? 13 : 16; };
-    while (G < 64 && ((N + 31) / 32 > G || (M + G - 1) / G > kmax(G))) G *= 2;   // spin words and hidden units fit
-    if ((N + 31) / 32 > G) return set_error(NQS_EUNSUPPORTED, "too many sites for the sampler");
+    else if (G != 16 && G != 32 && G != 64) return set_error(NQS_EINVAL, "lanes_per_chain must be 0, 16, 32 or 64");
+    while (G < 64 && ((N + 31) / 32 > G || (M + G - 1) / G > kmax_of(G))) G *= 2;   // spin words and units fit
+    if ((N + 31) / 32 > G) return set_error(NQS_EUNSUPPORTED, "too many sites for this many lanes per chain");
     const int K = (M + G - 1) / G;
-    if (K > kmax(G)) return set_error(NQS_EUNSUPPORTED, "hidden width too large for the sampler (M <= 1024)");
+    if (K > kmax_of(G)) return set_error(NQS_EUNSUPPORTED, "hidden width too large for this many lanes per chain");
     const size_t tab_bytes = sizeof(float2) * ((size_t)N * M + 1);
-    const bool lds = tab_bytes <= kLdsBytes;
-    if (noisy && !lds) return set_error(NQS_EUNSUPPORTED, "the noisy sampler needs the ratio table in LDS");
+    const bool fits = tab_bytes <= kLdsBytes;
+    const bool lds = lds_req < 0 ? fits : lds_req == 1;
+    if (lds && !fits) return set_error(NQS_EUNSUPPORTED, "the ratio table does not fit in LDS");
     // one LDS copy of the table per block; spread the chains over every CU
-    const int max_threads = G == 16 ? 256 : (G == 32 ? 512 : 1024);
+    const int max_cpb = (G == 16 ? 256 : (G == 32 ? 512 : 1024)) / G;
     const int blocks_per_cu = lds ? (int)std::max<size_t>(1, std::min<size_t>(8, kLdsBytes / tab_bytes)) : 8;
     const int64_t slots = (int64_t)device_cus() * blocks_per_cu;
-    const int cpb = (int)std::min<int64_t>(max_threads / G, std::max<int64_t>(1, (cfg.n_chains + slots - 1) / slots));
-    const int64_t blocks64 = (cfg.n_chains + cpb - 1) / cpb;
+    const int cpb_auto = (int)std::min<int64_t>(max_cpb, std::max<int64_t>(1, (n_chains + slots - 1) / slots));
+    P->G = G;
+    P->K = K;
+    P->cpb = cpb_req > 0 ? std::min(cpb_req, max_cpb) : cpb_auto;
+    P->lds = lds;
+    P->tab_bytes = tab_bytes;
+    P->tuned = false;
+    P->tuned_ms = 0.0f;
+    return NQS_OK;
+}
+
+nqs_status rbm_launch_plan(const RbmSampleArgs &A, const RbmPlan &P, bool trace, bool noise, int init,
+                           hipStream_t stream)
+{
+    const int64_t blocks64 = (A.n_chains + P.cpb - 1) / P.cpb;
     if (blocks64 > INT32_MAX) return set_error(NQS_EINVAL, "too many chains");
     RbmLaunch L;
-    L.K = K;
-    L.threads = cpb * G;
+    L.K = P.K;
+    L.threads = P.cpb * P.G;
     L.blocks = (int)blocks64;
-    L.lds = lds;
-    L.trace = tr;
-    L.noise = noisy;
-    L.init = cfg.init_chains ? 1 : 0;
-    L.lds_bytes = lds ? tab_bytes : 0;
-    switch (G) {
+    L.lds = P.lds;
+    L.trace = trace;
+    L.noise = noise;
+    L.init = init;
+    L.lds_bytes = P.lds ? P.tab_bytes : 0;
+    switch (P.G) {
     case 16: return rbm_sample_launch_g16(A, L, stream);
     case 32: return rbm_sample_launch_g32(A, L, stream);
     default: return rbm_sample_launch_g64(A, L, stream);
     }
+}
+
+// The measured plan: every valid candidate among the lanes per chain `Gs`
+// (all of 16, 32, 64 when Gs is NULL), both table placements and two
+// chains-per-block counts is timed on a short burn-in from fresh start states
+// of this model copy and chain count (scratch states, no outputs; the stream is
+// synchronised), and the fastest is kept for the life of the process, keyed by
+// (device, N, M, dtype, n_chains, candidate set).  Later calls reuse it, so
+// results stay reproducible within a process.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int64_t, int>, RbmPlan> g_tune;
+}
+
+nqs_status rbm_plan_tuned(nqs_model *m, const nqs_sample_cfg &cfg, const int *Gs, int nG, hipStream_t stream,
+                          RbmPlan *out)
+{
+    static const int all[3] = {16, 32, 64};
+    if (!Gs) {
+        Gs = all;
+        nG = 3;
+    }
+    nqs_status st = ensure_copy(m, cfg.dtype, stream);
+    if (st != NQS_OK) return st;
+    const RbmDev &net = m->copies[cfg.dtype].rbm;
+    const int N = net.N, M = net.M;
+    int dev = 0;
+    NQS_HIP_TRY(hipGetDevice(&dev));
+    int set = 0;
+    for (int q = 0; q < nG; ++q) set |= Gs[q];
+    const auto key = std::make_tuple(dev, N, M, (int)cfg.dtype, cfg.n_chains, set);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *out = it->second;
+            return NQS_OK;
+        }
+    }
+    std::vector<RbmPlan> cand;
+    for (int q = 0; q < nG; ++q) {
+        for (int lds = 1; lds >= 0; --lds) {
+            RbmPlan P;
+            if (rbm_plan_rule(N, M, cfg.n_chains, Gs[q], lds, 0, &P) != NQS_OK) continue;
+            cand.push_back(P);
+            if (P.cpb >= 2) {
+                RbmPlan H;
+                if (rbm_plan_rule(N, M, cfg.n_chains, Gs[q], lds, P.cpb / 2, &H) == NQS_OK) cand.push_back(H);
+            }
+        }
+    }
+    if (cand.empty()) return set_error(NQS_EUNSUPPORTED, "no lanes-per-chain candidate fits this RBM");
+    const int64_t C = std::max<int64_t>(1, cfg.n_chains);
+    const int64_t per_sweep = C * N;
+    const int sweeps = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4000000 + per_sweep - 1) / per_sweep));
+    int8_t *scratch = nullptr;
+    NQS_HIP_TRY(hipMalloc(&scratch, (size_t)C * N));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    nqs_status result = NQS_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) result = set_error(NQS_EDEVICE, "hipEventCreate failed");
+    RbmSampleArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.net = net;
+    A.chain_state = scratch;
+    A.n_chains = C;
+    A.n_sweeps = 0;
+    A.n_burnin = sweeps;
+    A.sweep_size = N;
+    A.refresh_sweeps = cfg.refresh_sweeps > 0 ? cfg.refresh_sweeps : 1;
+    A.seed = cfg.seed;
+    A.inst = cfg.instance_id;
+    RbmPlan best = cand[0];
+    float best_ms = 3.4e38f;
+    for (size_t q = 0; q < cand.size() && result == NQS_OK; ++q) {
+        float t = 3.4e38f;
+        for (int rep = 0; rep < 3 && result == NQS_OK; ++rep) {   // the first run warms up
+            if (hipEventRecord(e0, stream) != hipSuccess) result = set_error(NQS_EDEVICE, "hipEventRecord failed");
+            if (result == NQS_OK) result = rbm_launch_plan(A, cand[q], false, false, 1, stream);
+            if (result == NQS_OK && hipEventRecord(e1, stream) != hipSuccess) result = set_error(NQS_EDEVICE, "hipEventRecord failed");
+            if (result == NQS_OK && hipEventSynchronize(e1) != hipSuccess) result = set_error(NQS_EDEVICE, "tuning run failed");
+            float ms = 0.0f;
+            if (result == NQS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) result = set_error(NQS_EDEVICE, "hipEventElapsedTime failed");
+            if (rep > 0) t = std::min(t, ms);
+        }
+        if (result == NQS_OK && t < best_ms) {
+            best_ms = t;
+            best = cand[q];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    if (result != NQS_OK) return result;
+    best.tuned = true;
+    best.tuned_ms = best_ms;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[key] = best;
+    }
+    *out = best;
+    return NQS_OK;
 }
 
 // ---------------------------------------------------------------------------

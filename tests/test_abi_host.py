@@ -130,3 +130,34 @@ def test_noalloc_stats_reject_more_chains_than_the_static_scratch(lib):
     n_chains = 131072 - 512 + 1
     assert lib.nqs_energy_stats_noalloc(fake, 2 * n_chains, n_chains, fake, None) == _abi.NQS_EINVAL
     assert b"static scratch" in lib.nqs_last_error()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the interface structs have the C layout: sizes and field offsets
+    printed by a program compiled against include/nqs.h."""
+    import shutil
+    import subprocess
+    from paper_2601_20782_amd import _abi
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"nqs_model_desc": _abi.ModelDesc, "nqs_ham_desc": _abi.HamDesc, "nqs_sample_cfg": _abi.SampleCfg,
+               "nqs_sample_job": _abi.SampleJob, "nqs_trace": _abi.Trace, "nqs_launch_plan": _abi.LaunchPlan}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "nqs.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -359,38 +359,3 @@ def test_gram_matches_oracle(nqs, mode, n, P):
     got = out.cpu().numpy()
     tol = 1e-5 * (np.abs(O64 - O64.mean(0)) ** 2).sum(axis=1 if mode == 1 else 0).max() / n
     assert np.max(np.abs(got - ref)) < tol + 1e-6
-
-
-# ---------------------------------------------------------------------------
-# Uneven instances in one persistent launch
-# ---------------------------------------------------------------------------
-
-def test_batched_persistent_equals_separate_launches(nqs):
-    insts = workloads.cfg4_instances(seed=4, n_inst=8, chains=64)
-    jobs0, jobs1, models = [], [], []
-    for k, wl in enumerate(insts):
-        wl = workloads.scaled(wl, n_sweeps=3, n_burnin=2)
-        m = nqs.Model.from_workload(wl)
-        models.append(m)
-        N = wl.model.n_visible
-        for jobs in (jobs0, jobs1):
-            cfg = nqs.SampleConfig(n_chains=wl.n_chains, n_sweeps=wl.n_sweeps, n_burnin=wl.n_burnin, seed=wl.seed,
-                                   dtype="bf16", instance_id=k)
-            jobs.append({"model": m, "cfg": cfg,
-                         "chain_state": torch.zeros(wl.n_chains, N, dtype=torch.int8, device=DEV),
-                         "samples": torch.empty(wl.n_sweeps, wl.n_chains, N, dtype=torch.int8, device=DEV),
-                         "n_accepted": torch.empty(wl.n_chains, dtype=torch.int64, device=DEV)})
-    _say("batched mode 0 / mode 1")
-    nqs.nqs_sample_batched(jobs0, mode=0)
-    nqs.nqs_sample_batched(jobs1, mode=1)
-    torch.cuda.synchronize()
-    for a, b in zip(jobs0, jobs1):
-        assert torch.equal(a["samples"], b["samples"])
-        assert torch.equal(a["chain_state"], b["chain_state"])
-        assert torch.equal(a["n_accepted"], b["n_accepted"])
-    # one instance against the oracle's replay-free trajectory (small N: free-running equality)
-    wl = workloads.scaled(insts[0], n_sweeps=3, n_burnin=2)
-    om = oracle.model_from_workload(wl, None, "bf16")
-    st, smp, _, acc = oracle.sample(om, oracle.make_cfg(64, 3, 2, seed=wl.seed, instance_id=0))
-    got = jobs0[0]["samples"].cpu().numpy()
-    assert (got == smp).all(axis=2).mean() > 0.99
