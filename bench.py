@@ -938,6 +938,29 @@ def run_crbm(a, torch, nqs, workloads):
     ev[1].record()
     torch.cuda.synchronize()
     eloc_ms = ev[0].elapsed_time(ev[1])
+    # one SR step with complex parameters on the last sweep's 4096 samples: O (FP32 copy), the real
+    # embedding of T (nqs_gram mode 3), the complex solve and the update
+    last = samples[S - 1].contiguous()
+    er, ei = re.view(S, C)[S - 1].contiguous(), im.view(S, C)[S - 1].contiguous()
+    Pc = N + M + M * N
+    O = torch.empty(C, 2 * Pc, dtype=torch.float32, device=dev)
+    T2 = torch.empty(2 * C, 2 * C, dtype=torch.float32, device=dev)
+    y2 = torch.empty(2 * C, dtype=torch.float64, device=dev)
+    master = torch.from_numpy(p.copy()).to(dev)
+    sr_ev = _events(torch, 5)
+    sr_ev[0].record()
+    nqs.nqs_logpsi_grad(model, last, None, O)
+    sr_ev[1].record()
+    nqs.nqs_gram(O, 3, T2)
+    sr_ev[2].record()
+    sr_it, sr_rr = nqs.nqs_sr_solve_complex(T2, er, ei, 1e-2, y2, tol=1e-8, max_iter=2000)
+    sr_ev[3].record()
+    nqs.nqs_sr_update(model, last, y2, 0.01, master)
+    sr_ev[4].record()
+    torch.cuda.synchronize()
+    sr_phases = {k: round(sr_ev[q].elapsed_time(sr_ev[q + 1]), 3)
+                 for q, k in enumerate(("logpsi_grad", "gram_T_complex", "solve", "update"))}
+    del O, T2
     real = nqs.Model("rbm", N, (M,), p[:N + M + M * N])
     real_ms, _, real_acc = time_sampling(real, dt, a.steps)
     model.close()
@@ -960,6 +983,10 @@ def run_crbm(a, torch, nqs, workloads):
         "real_rbm_ms": round(real_ms, 3), "real_rbm_acceptance": round(real_acc, 4),
         "complex_vs_real_time": round(ms / real_ms, 3),
         "eloc_complex_ms": round(eloc_ms, 3), "eloc_samples": int(flat.shape[0]),
+        "sr_step": {"samples": C, "params_complex": Pc, "phases_ms": sr_phases, "cg_iterations": sr_it,
+                    "rel_resid": sr_rr, "shift": 1e-2,
+                    "gram_tflop": round(2.0 * (2 * C) ** 2 * (2 * Pc) / 1e12, 3),
+                    "note": "T embedded as the 2n x 2n real matrix [[Re T, -Im T], [Im T, Re T]]; CG on 2n unknowns"},
         "roofline": {"kernel": "crbm_sample_kernel", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,

@@ -97,7 +97,12 @@ typedef enum { NQS_TFIM = 0, NQS_HEISENBERG = 1 } nqs_ham_kind;
  *   exp(2 Re log psi) is sampled.  Parameter vector of 2 (N + M + M N) reals:
  *   the real parts in the RBM order, then the imaginary parts; a format rounds
  *   both parts.  Sampling (single flips), TFIM local energies (nqs_local_energy
- *   gives the real part, nqs_local_energy_complex both); no log-derivatives.
+ *   gives the real part, nqs_local_energy_complex both), log-derivatives
+ *   (nqs_logpsi_grad: O_k = d log psi / d p_k with respect to the complex
+ *   parameters p_k, log psi being holomorphic in them: s_i, tanh theta_j,
+ *   tanh theta_j s_i; stored as [n][2P'] reals, Re O then Im O, P' = N + M + MN;
+ *   logpsi = Re log psi; no vector-Jacobian product), the complex T of
+ *   nqs_gram mode 3 and the SR step of nqs_sr_solve_complex / nqs_sr_update.
  * marshall = 1 multiplies psi by (-1)^{#up spins on sublattice A}, A = {(x+y) even}
  *   (lat_dim = 2) or {i even} (lat_dim = 1), on an L = lat_L lattice. */
 typedef struct {
@@ -313,6 +318,12 @@ nqs_status nqs_forces(const float *O, const double *eloc, int64_t n, int64_t P, 
  *   mode 1: T[n][n] = Obar Obar^T / n      (same non-zero spectrum)
  *   mode 2: T[n][n] += Obar Obar^T / n     (O a column block; summing the
  *           blocks of all parameters gives the T of mode 1)
+ *   mode 3: a complex network's O[n][2P'] (Re O, then Im O): T = Obar Obar^H / n,
+ *           the sample-space twin of S_nm = E[O_n* O_m] - E[O_n*] E[O_m]
+ *           (Eq. eq:smat), written as the real matrix out[2n][2n] =
+ *           [[Re T, -Im T], [Im T, Re T]] (the Gram matrix of the rows
+ *           [Re Obar, -Im Obar] and [Im Obar, Re Obar], divided by n); P even;
+ *           2n x P floats of library workspace
  * `out` is FP32, row-major; in mode 2 it must hold the sum so far. */
 nqs_status nqs_gram(const float *O, int64_t n, int64_t P, int32_t mode, float *out, void *stream);
 
@@ -360,9 +371,23 @@ nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t
  *   lr * delta, delta = O^T (y - mean y) / n through the FP32 copy's
  *   log-derivatives of `samples` (the n samples T was formed from).  The
  *   model's own copies are not touched: pass `master` to
- *   nqs_model_set_params_device for the next step. */
+ *   nqs_model_set_params_device for the next step.  For the complex RBM,
+ *   y[2n] = (Re z, Im z) from nqs_sr_solve_complex and delta =
+ *   O^H (z - mean z) / n, complex: master's real parts move by lr Re delta and
+ *   its imaginary parts by lr Im delta (Eq. eq:sr_step with complex S, F).
+ * nqs_sr_solve_complex: the complex system (T + shift) z = eps - mean eps of a
+ *   complex network, T2[2n][2n] its real embedding from nqs_gram mode 3,
+ *   eloc_re / eloc_im[n] the complex local energies (FP64); y2[2n] = (Re z,
+ *   Im z), the two halves of the right-hand side centred separately (in a
+ *   buffer of library workspace), then the same Jacobi conjugate gradients as
+ *   nqs_sr_solve on 2n unknowns.  Together with nqs_sr_update this gives the
+ *   parameter-space direction (S + shift) delta = F of Eqs. eq:smat and
+ *   eq:forces (the push-through identity). */
 nqs_status nqs_sr_solve(const float *T, const double *eloc, int64_t n, double shift, double tol, int32_t max_iter,
                         double *y, int32_t *iters, double *rel_resid, void *stream);
+nqs_status nqs_sr_solve_complex(const float *T2, const double *eloc_re, const double *eloc_im, int64_t n, double shift,
+                                double tol, int32_t max_iter, double *y2, int32_t *iters, double *rel_resid,
+                                void *stream);
 nqs_status nqs_sr_update(nqs_model *m, const int8_t *samples, int64_t n, const double *y, double lr, double *master,
                          void *stream);
 

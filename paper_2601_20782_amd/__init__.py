@@ -24,7 +24,7 @@ LANES_TUNED = -2   # SampleConfig.lanes_per_chain: the measured launch plan (inc
 __all__ = [
     "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_sample_plan", "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc", "nqs_logpsi_grad",
     "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
-    "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_probe_rate", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
+    "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_solve_complex", "nqs_sr_update", "nqs_sample_noisy", "nqs_probe_rate", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
     "LANES_TUNED",
 ]
 
@@ -345,10 +345,25 @@ def nqs_sr_solve_mixed(T: torch.Tensor, eloc: torch.Tensor, shift: float, y: tor
     return it.value, rr.value, nf.value, names.get(fu.value, "jacobi")
 
 
+def nqs_sr_solve_complex(T2: torch.Tensor, eloc_re: torch.Tensor, eloc_im: torch.Tensor, shift: float, y2: torch.Tensor,
+                         tol: float = 1e-10, max_iter: int = 1000, stream=None):
+    """(T + shift) z = eps - mean(eps) for a complex network, T given as its real 2n x 2n embedding T2
+    (nqs_gram mode 3), y2 = (Re z, Im z); returns (iterations, relative residual)."""
+    n = eloc_re.numel()
+    assert T2.dtype == torch.float32 and T2.numel() == 4 * n * n
+    assert eloc_re.dtype == torch.float64 and eloc_im.dtype == torch.float64 and eloc_im.numel() == n
+    assert y2.dtype == torch.float64 and y2.numel() == 2 * n
+    it = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    check(load().nqs_sr_solve_complex(_ptr(T2), _ptr(eloc_re), _ptr(eloc_im), n, float(shift), float(tol),
+                                      int(max_iter), _ptr(y2), ctypes.byref(it), ctypes.byref(rr), _stream(stream)))
+    return it.value, rr.value
+
+
 def nqs_sr_update(model: Model, samples: torch.Tensor, y: torch.Tensor, lr: float, master: torch.Tensor,
                   stream=None) -> None:
     n = samples.numel() // model.n_visible
-    assert y.dtype == torch.float64 and y.numel() == n
+    assert y.dtype == torch.float64 and y.numel() == (2 * n if model.arch == "crbm" else n)
     assert master.dtype == torch.float64 and master.numel() == model.n_params
     check(load().nqs_sr_update(model.handle, _ptr(samples), n, _ptr(y), float(lr), _ptr(master), _stream(stream)))
 
@@ -362,7 +377,7 @@ def nqs_forces(O: torch.Tensor, eloc: torch.Tensor, F: torch.Tensor, Omean: Opti
 
 def nqs_gram(O: torch.Tensor, mode: int, out: torch.Tensor, stream=None) -> None:
     n, P = O.shape
-    side = P if mode == 0 else n
+    side = P if mode == 0 else (2 * n if mode == 3 else n)
     assert O.dtype == torch.float32 and out.dtype == torch.float32 and out.numel() == side * side
     check(load().nqs_gram(_ptr(O), n, P, mode, _ptr(out), _stream(stream)))
 

@@ -22,7 +22,7 @@ EXPORTS = [
     "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched", "nqs_sample_plan",
     "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc",
     "nqs_logpsi_grad", "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
-    "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex",
+    "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_solve_complex", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex",
     "nqs_last_error",
     "nqs_version",
     "nqs_probe_rate",
@@ -113,6 +113,7 @@ def load() -> ctypes.CDLL:
         "nqs_sample_gram": ([P, P, i64, i64, P, P], st),
         "nqs_sample_gram_factored": ([P, P, i64, P, P], st),
         "nqs_sr_solve": ([P, P, i64, ctypes.c_double, ctypes.c_double, i32, P, P, P, P], st),
+        "nqs_sr_solve_complex": ([P, P, P, i64, ctypes.c_double, ctypes.c_double, i32, P, P, P, P], st),
         "nqs_probe_rate": ([i32, i64, P, P, P, P], st),
         "nqs_sr_solve_mixed": ([P, P, i64, ctypes.c_double, i32, ctypes.c_double, i32, P, P, P, P, P, P], st),
         "nqs_sr_update": ([P, P, i64, P, ctypes.c_double, P, P], st),

@@ -438,7 +438,10 @@ nqs_status nqs_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float
     if (!samples) return set_error(NQS_EINVAL, "NULL samples");
     if ((vjp_in == nullptr) != (vjp_out == nullptr)) return set_error(NQS_EINVAL, "vjp_in and vjp_out go together");
     hipStream_t s = (hipStream_t)stream;
-    if (m->desc.arch == NQS_CRBM) return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
+    if (m->desc.arch == NQS_CRBM) {
+        if (vjp_in) return set_error(NQS_EUNSUPPORTED, "the vector-Jacobian product of the complex RBM is not built");
+        return crbm_logpsi_grad(m, samples, n, logpsi, O, s);
+    }
     if (m->desc.arch == NQS_RESCNN) {
         if (!O && !vjp_in) return logpsi ? cnn_logpsi(m, samples, n, logpsi, s) : NQS_OK;
         return cnn_logpsi_grad(m, samples, n, logpsi, O, vjp_in, vjp_out, s);
@@ -451,7 +454,7 @@ nqs_status nqs_logpsi_grad_cols(nqs_model *m, const int8_t *samples, int64_t n, 
                                 void *stream)
 {
     if (m && m->desc.arch == NQS_CRBM)
-        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
+        return set_error(NQS_EUNSUPPORTED, "column blocks of the complex RBM's log-derivatives are not built");
     if (m && m->desc.arch == NQS_RESCNN)
         return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
     if (!m) return set_error(NQS_EINVAL, "NULL model");
@@ -467,7 +470,7 @@ nqs_status nqs_logpsi_grad_cols(nqs_model *m, const int8_t *samples, int64_t n, 
 nqs_status nqs_sample_gram_factored(nqs_model *m, const int8_t *samples, int64_t n, float *T, void *stream)
 {
     if (m && m->desc.arch == NQS_CRBM)
-        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
+        return set_error(NQS_EUNSUPPORTED, "column blocks of the complex RBM's log-derivatives are not built");
     if (m && m->desc.arch == NQS_RESCNN)
         return set_error(NQS_EUNSUPPORTED, "log-derivatives of the convolutional network are not built");
     if (!m) return set_error(NQS_EINVAL, "NULL model");
@@ -533,7 +536,7 @@ nqs_status nqs_sample_gram(nqs_model *m, const int8_t *samples, int64_t n, int64
                            void *stream)
 {
     if (m && m->desc.arch == NQS_CRBM)
-        return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
+        return set_error(NQS_EUNSUPPORTED, "column blocks of the complex RBM's log-derivatives are not built");
     if (m && m->desc.arch == NQS_RESCNN) {
         // weights shared across sites: O is formed whole (one block of all columns)
         if (n <= 0 || !samples || !T) return set_error(NQS_EINVAL, "bad samples/T");
@@ -585,7 +588,11 @@ nqs_status nqs_gram(const float *O, int64_t n, int64_t P, int32_t mode, float *o
 {
     if (n <= 0 || P <= 0) return set_error(NQS_EINVAL, "n and P must be positive");
     if (!O || !out) return set_error(NQS_EINVAL, "NULL O/out");
-    if (mode < 0 || mode > 2) return set_error(NQS_EINVAL, "mode must be 0 (S), 1 (T) or 2 (T accumulate)");
+    if (mode < 0 || mode > 3) return set_error(NQS_EINVAL, "mode must be 0 (S), 1 (T), 2 (T accumulate) or 3 (complex T)");
+    if (mode == 3) {
+        if (P % 2 != 0) return set_error(NQS_EINVAL, "mode 3 takes O as [n][2P'] (real parts, then imaginary parts)");
+        return cplx_gram_embedded(O, n, P, out, (hipStream_t)stream);
+    }
     return launch_gram(O, n, P, mode, out, (hipStream_t)stream);
 }
 

@@ -140,7 +140,7 @@ hipStream_t capture_stream();
 void *workspace(size_t bytes, hipStream_t stream);
 // Slot 1 is for entry points that hold vectors across calls into others
 // (which use slot 0).
-constexpr int kWorkspaceSlots = 2;
+constexpr int kWorkspaceSlots = 3;
 void *workspace_slot(int slot, size_t bytes, hipStream_t stream);
 // low-precision Cholesky factor of T + shift and its inverse (srmix.hip)
 size_t mix_workspace_bytes(int64_t n);
@@ -213,6 +213,15 @@ nqs_status rbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float
 nqs_status ffnn_build_copy(nqs_model *m, int dtype, hipStream_t stream);
 // complex-parameter RBM
 nqs_status crbm_build_copy(nqs_model *m, int dtype, hipStream_t stream);
+// complex RBM: log-derivatives O[n][2P'] (real parts, then imaginary parts) and Re log psi; the real
+// 2n x 2n embedding of T = Obar Obar^H / n; the centred right-hand side (Re eps, Im eps) of the complex
+// solve (library workspace); the SR update from y[2n] = (Re z, Im z)
+nqs_status crbm_logpsi_grad(nqs_model *m, const int8_t *samples, int64_t n, float *logpsi, float *O,
+                            hipStream_t stream);
+nqs_status cplx_gram_embedded(const float *O, int64_t n, int64_t P, float *T2, hipStream_t stream);
+nqs_status cplx_sr_rhs(const double *eloc_re, const double *eloc_im, int64_t n, double **e2, hipStream_t stream);
+nqs_status crbm_sr_update(nqs_model *m, const int8_t *samples, int64_t n, const double *y, double lr, double *master,
+                          hipStream_t stream);
 nqs_status crbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
                        uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream);
 nqs_status crbm_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t *samples, int64_t n, int dtype,

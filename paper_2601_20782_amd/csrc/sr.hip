@@ -453,14 +453,28 @@ nqs_status nqs_sr_solve_mixed(const float *T, const double *eloc, int64_t n, dou
     return NQS_OK;
 }
 
+nqs_status nqs_sr_solve_complex(const float *T2, const double *eloc_re, const double *eloc_im, int64_t n, double shift,
+                                double tol, int32_t max_iter, double *y2, int32_t *iters, double *rel_resid, void *stream)
+{
+    if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
+    if (!T2 || !eloc_re || !eloc_im || !y2) return set_error(NQS_EINVAL, "NULL T2/eloc/y2");
+    if (!(shift >= 0.0) || !(tol > 0.0) || max_iter < 1) return set_error(NQS_EINVAL, "need shift >= 0, tol > 0, max_iter >= 1");
+    if (n > (int64_t)INT32_MAX) return set_error(NQS_EINVAL, "n too large");
+    double *e2 = nullptr;
+    nqs_status st = cplx_sr_rhs(eloc_re, eloc_im, n, &e2, (hipStream_t)stream);
+    if (st != NQS_OK) return st;
+    // both halves are centred, so the solver's own centring (by the mean of all 2n values) changes nothing
+    return nqs_sr_solve(T2, e2, 2 * n, shift, tol, max_iter, y2, iters, rel_resid, stream);
+}
+
 nqs_status nqs_sr_update(nqs_model *m, const int8_t *samples, int64_t n, const double *y, double lr, double *master,
                          void *stream)
 {
     if (!m) return set_error(NQS_EINVAL, "NULL model");
     if (n <= 0) return set_error(NQS_EINVAL, "n must be positive");
     if (!samples || !y || !master) return set_error(NQS_EINVAL, "NULL samples/y/master");
-    if (m->desc.arch == NQS_CRBM) return set_error(NQS_EUNSUPPORTED, "log-derivatives of the complex RBM are not built");
     hipStream_t s = (hipStream_t)stream;
+    if (m->desc.arch == NQS_CRBM) return crbm_sr_update(m, samples, n, y, lr, master, s);   // y holds 2n values
     const int64_t P = m->P;
     const size_t yb = r256(sizeof(float) * (size_t)n), gb = r256(sizeof(float) * (size_t)P);
     char *ws = (char *)workspace_slot(1, yb + gb + 256, s);

@@ -100,6 +100,16 @@ def test_new_entry_points_reject_bad_arguments(lib):
     assert b"factor dtype" in lib.nqs_last_error()
     assert lib.nqs_sr_solve_mixed(fake, fake, 70000, 1e-2, _abi.F32, 1e-8, 10, fake, ctypes.byref(it),
                                   ctypes.byref(rr), ctypes.byref(nf), ctypes.byref(fu), None) == _abi.NQS_EINVAL
+    # the complex SR solve: n = 0, NULL buffers, a negative shift; the complex T needs an even column count
+    assert lib.nqs_sr_solve_complex(fake, fake, fake, 0, 1e-2, 1e-8, 10, fake, ctypes.byref(it), ctypes.byref(rr),
+                                    None) == _abi.NQS_EINVAL
+    assert lib.nqs_sr_solve_complex(fake, None, fake, 8, 1e-2, 1e-8, 10, fake, ctypes.byref(it), ctypes.byref(rr),
+                                    None) == _abi.NQS_EINVAL
+    assert lib.nqs_sr_solve_complex(fake, fake, fake, 8, -1.0, 1e-8, 10, fake, ctypes.byref(it), ctypes.byref(rr),
+                                    None) == _abi.NQS_EINVAL
+    assert lib.nqs_gram(fake, 4, 5, 3, fake, None) == _abi.NQS_EINVAL
+    assert b"[n][2P']" in lib.nqs_last_error()
+    assert lib.nqs_gram(fake, 4, 6, 4, fake, None) == _abi.NQS_EINVAL
     # complex local energies without a model
     h = _abi.HamDesc()
     assert lib.nqs_local_energy_complex(None, ctypes.byref(h), fake, 4, _abi.F32, fake, fake, None) == _abi.NQS_EINVAL

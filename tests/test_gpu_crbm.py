@@ -179,8 +179,11 @@ def test_rejections(nqs):
     N, M = 10, 20
     model = nqs.Model("crbm", N, (M,), workloads.crbm_params(N, M, 0.1, 0.1, 1))
     x = torch.from_numpy(workloads.random_spins(4, N, 1)).to(DEV)
-    with pytest.raises(nqs.NqsError):   # log-derivatives of the complex network are not built
-        nqs.nqs_logpsi_grad(model, x, O=torch.empty(4, model.n_params, dtype=torch.float32, device=DEV))
+    with pytest.raises(nqs.NqsError):   # no vector-Jacobian product for the complex network
+        nqs.nqs_logpsi_grad(model, x, vjp_in=torch.zeros(4, dtype=torch.float32, device=DEV),
+                            vjp_out=torch.empty(model.n_params, dtype=torch.float32, device=DEV))
+    with pytest.raises(nqs.NqsError):   # nor column blocks of O
+        nqs.nqs_logpsi_grad_cols(model, x, 0, 4, torch.empty(4, 4, dtype=torch.float32, device=DEV))
     with pytest.raises(nqs.NqsError):
         nqs.nqs_local_energy(model, nqs.Hamiltonian("heisenberg", 1, N, 1.0, 0.0, True), x,
                              torch.empty(4, dtype=torch.float64, device=DEV))
