@@ -91,9 +91,10 @@ def _args():
     return ap.parse_args()
 
 
-def kernel_traffic(kernel, profile):
-    """HBM bytes per launch of `kernel` from a committed counter summary, or None when the kernel's
-    sources have changed since the counters were taken (the summary records their hash)."""
+def kernel_traffic(kernel, profile, instance=None):
+    """HBM bytes per launch of `kernel` (the row naming `instance`, a template instantiation, when given)
+    from a committed counter summary, or None when the kernel's sources have changed since the counters
+    were taken (the summary records their hash)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -103,7 +104,7 @@ def kernel_traffic(kernel, profile):
         f = line.split()
         if len(f) >= 4 and f[0] == "source_sha256" and f[1] == kernel:
             want, files = f[2], f[3].split(",")
-        elif f and not line.startswith("#") and kernel in line and len(f) >= 4:
+        elif f and not line.startswith("#") and (instance or kernel) in line and len(f) >= 4:
             nbytes = float(f[-1])
     if want is None or nbytes is None:
         return None
@@ -411,7 +412,8 @@ def run_tfim10(a, torch, nqs, workloads):
     out["roofline"] = {"kernel": "rbm_sample_kernel", "bound": "alu", "achieved": round(achieved, 3),
                        "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
-                       "traffic": kernel_traffic("rbm_sample_kernel", "tfim2d_10x10_rbm_bf16_hbm_traffic.txt"),
+                       "traffic": kernel_traffic("rbm_sample_kernel", "tfim2d_10x10_rbm_bf16_hbm_traffic.txt",
+                                                 "rbm_sample_kernel<32, 7, true, false, false>"),
                        "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
                        "ops_per_proposal": alg, "ops_per_proposal_note": "M log-cosh (2M transcendentals) + 2M FMA",
                        "proposals_per_launch": props, "launch_ms": round(phases["sample"], 3),
@@ -426,6 +428,7 @@ def run_tfim10(a, torch, nqs, workloads):
                            "achieved": round(props * impl / t_k / 1e12, 3),
                            "frac": round(props * impl / t_k / 1e12 / PEAK_FP32_VALU_TFLOPS, 4)}}
     out["sr_step"] = _sr_step(nqs, torch, step)
+    out["detectors"] = _detectors(nqs, torch, wl, params, a.dtype, a.refresh)
     if not a.no_compare:
         out.update(_compare_fp32(a, nqs, torch, wl, params, step, ms, props, "f32", True, others=("f16", "e4m3")))
     del step
@@ -440,6 +443,22 @@ def run_tfim10(a, torch, nqs, workloads):
     if not a.headline_only:
         out["other_workloads"] = _other_workloads(a, torch, nqs, workloads)
     return out
+
+
+def _detectors(nqs, torch, wl, params, dtype, refresh):
+    """The run-time detectors on a short run of the headline workload (untimed): non-finite log-ratios, chains
+    without an accepted move for 10 sweeps, and the largest drift of log psi carried by the accepted
+    log-ratios against log psi recomputed at a refresh."""
+    N, C, S, B = wl.model.n_visible, wl.n_chains, 20, 10
+    model = nqs.Model.from_workload(wl, params)
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=wl.seed, dtype=dtype, refresh_sweeps=refresh)
+    state = torch.empty(C, N, dtype=torch.int8, device="cuda")
+    lp = torch.empty(S, C, dtype=torch.float32, device="cuda")
+    r = nqs.nqs_sample_checked(model, cfg, state, None, lp, stuck_after=10)
+    r["mean_abs_logpsi"] = round(float(lp.abs().mean().item()), 4)
+    r["run"] = f"{C} chains x ({B} + {S}) sweeps, refresh every {refresh} sweeps, {dtype} copy"
+    model.close()
+    return r
 
 
 def _antiparallel_bonds(torch, samples, L):

@@ -201,6 +201,39 @@ nqs_status nqs_downcast(const double *src, int64_t n, int32_t dtype, float *dst,
 nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_state, int8_t *samples,
                       float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, void *stream);
 
+/* Run-time detectors of a sampling call (the RBM single-flip sampler):
+ *   - proposals whose log-ratio Delta is NaN or infinite (such a proposal is
+ *     rejected, as the acceptance test of Sec. III.A is false for it): non-
+ *     finite parameters or an overflow in the network's arithmetic;
+ *   - the longest run of sweeps in which a chain accepted nothing (the loss
+ *     of ergodicity that Sec. IV.A describes when the perturbation grows);
+ *   - the drift of the incremental state: the largest difference between
+ *     log|psi| carried by the accepted log-ratios since the previous refresh
+ *     and log|psi| recomputed from theta = W s + b at the refresh (Eq.
+ *     eq:pert_chain needs the perturbation to be a fixed function of the
+ *     configuration, which a drifting incremental state would break).
+ * Per-chain device arrays (each may be NULL; the library then keeps them in
+ * its workspace), the host summary filled in when the call returns. */
+typedef struct {
+    int32_t stuck_after;              /* in: a chain counts as stuck after this many sweeps without an accepted
+                                         move (0 => 10) */
+    uint64_t *nonfinite;              /* [n_chains] device out: proposals with a non-finite Delta */
+    uint32_t *longest_stuck;          /* [n_chains] device out: longest run of sweeps without an accepted move */
+    float *drift;                     /* [n_chains] device out: largest |log psi drift| at a refresh */
+    uint64_t total_nonfinite;         /* host out */
+    int64_t chains_stuck;             /* host out: chains whose longest_stuck >= stuck_after */
+    float max_drift;                  /* host out */
+} nqs_sample_diag;
+
+/* nqs_sample with the run-time detectors above (RBM, single flips; the traced
+ * kernel, so slower than nqs_sample); samples, log psi, acceptances, traces and
+ * results equal nqs_sample's.  Synchronises `stream`; returns NQS_ENUMERIC
+ * (outputs written) when any Delta was not finite, NQS_EUNSUPPORTED for other
+ * networks or moves. */
+nqs_status nqs_sample_checked(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_state, int8_t *samples,
+                              float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, nqs_sample_diag *diag,
+                              void *stream);
+
 /* Launch plan of the RBM sampler (single flips) for this model, cfg.dtype and
  * cfg.n_chains: lanes per chain G, hidden units per lane K = ceil(M/G),
  * chains per workgroup, and whether the (cosh 2W, sinh 2W) table sits in LDS.

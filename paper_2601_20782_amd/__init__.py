@@ -22,7 +22,7 @@ from ._abi import DTYPE_CODES, NqsError, check, load
 LANES_TUNED = -2   # SampleConfig.lanes_per_chain: the measured launch plan (include/nqs.h NQS_LANES_TUNED)
 
 __all__ = [
-    "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_batched", "nqs_sample_plan", "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc", "nqs_logpsi_grad",
+    "Model", "SampleConfig", "Hamiltonian", "nqs_sample", "nqs_sample_checked", "nqs_sample_batched", "nqs_sample_plan", "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc", "nqs_logpsi_grad",
     "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
     "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_solve_complex", "nqs_sr_update", "nqs_sample_noisy", "nqs_probe_rate", "nqs_local_energy_complex", "nqs_downcast", "LogPsi", "NqsError", "load",
     "LANES_TUNED",
@@ -207,6 +207,38 @@ def nqs_sample(model: Model, cfg: SampleConfig, chain_state: torch.Tensor, sampl
     c = cfg.to_c()
     check(load().nqs_sample(model.handle, ctypes.byref(c), _ptr(chain_state), _ptr(samples), _ptr(logpsi),
                             _ptr(n_accepted), ctypes.byref(tr) if tr is not None else None, _stream(stream)))
+
+
+def nqs_sample_checked(model: Model, cfg: SampleConfig, chain_state: torch.Tensor,
+                       samples: Optional[torch.Tensor] = None, logpsi: Optional[torch.Tensor] = None,
+                       n_accepted: Optional[torch.Tensor] = None, trace: Optional[dict] = None, stuck_after: int = 0,
+                       nonfinite: Optional[torch.Tensor] = None, longest_stuck: Optional[torch.Tensor] = None,
+                       drift: Optional[torch.Tensor] = None, stream=None) -> dict:
+    """nqs_sample with the run-time detectors (include/nqs.h nqs_sample_checked).  Returns the host summary;
+    a non-finite log-ratio is reported as status NQS_ENUMERIC in it rather than raised."""
+    N = model.n_visible
+    assert chain_state.dtype == torch.int8 and chain_state.numel() == cfg.n_chains * N
+    if samples is not None:
+        assert samples.dtype == torch.int8 and samples.numel() == cfg.n_sweeps * cfg.n_chains * N
+    if logpsi is not None:
+        assert logpsi.dtype == torch.float32 and logpsi.numel() == cfg.n_sweeps * cfg.n_chains
+    if n_accepted is not None:
+        assert n_accepted.dtype in (torch.int64, torch.uint64) and n_accepted.numel() == cfg.n_chains
+    for t, dt in ((nonfinite, (torch.int64, torch.uint64)), (longest_stuck, (torch.int32,)), (drift, (torch.float32,))):
+        if t is not None:
+            assert t.dtype in dt and t.numel() == cfg.n_chains
+    tr = _trace_struct(trace, cfg, N)
+    d = _abi.SampleDiag()
+    d.stuck_after = int(stuck_after)
+    d.nonfinite, d.longest_stuck, d.drift = _ptr(nonfinite), _ptr(longest_stuck), _ptr(drift)
+    c = cfg.to_c()
+    st = load().nqs_sample_checked(model.handle, ctypes.byref(c), _ptr(chain_state), _ptr(samples), _ptr(logpsi),
+                                   _ptr(n_accepted), ctypes.byref(tr) if tr is not None else None, ctypes.byref(d),
+                                   _stream(stream))
+    if st != _abi.NQS_ENUMERIC:
+        check(st)
+    return {"status": int(st), "total_nonfinite": int(d.total_nonfinite), "chains_stuck": int(d.chains_stuck),
+            "max_drift": float(d.max_drift)}
 
 
 def nqs_sample_noisy(model: Model, cfg: SampleConfig, noise_sigma: float, noise_seed: int, chain_state: torch.Tensor,

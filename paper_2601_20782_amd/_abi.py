@@ -19,7 +19,7 @@ DTYPE_CODES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "e4m3": FP8_E4M
 # every function the headers under include/ declare
 EXPORTS = [
     "nqs_model_create", "nqs_model_set_params", "nqs_model_set_params_device", "nqs_model_destroy",
-    "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_batched", "nqs_sample_plan",
+    "nqs_model_num_params", "nqs_model_prepare", "nqs_downcast", "nqs_sample", "nqs_sample_checked", "nqs_sample_batched", "nqs_sample_plan",
     "nqs_local_energy", "nqs_energy_stats", "nqs_energy_stats_noalloc",
     "nqs_logpsi_grad", "nqs_logpsi_grad_cols", "nqs_forces", "nqs_gram", "nqs_sample_gram", "nqs_sample_gram_factored",
     "nqs_sr_solve", "nqs_sr_solve_mixed", "nqs_sr_solve_complex", "nqs_sr_update", "nqs_sample_noisy", "nqs_local_energy_complex",
@@ -56,6 +56,12 @@ class SampleJob(ctypes.Structure):
     _fields_ = [("model", ctypes.c_void_p), ("cfg", SampleCfg), ("chain_state", ctypes.c_void_p),
                 ("samples", ctypes.c_void_p), ("logpsi", ctypes.c_void_p), ("n_accepted", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p)]
+
+
+class SampleDiag(ctypes.Structure):
+    _fields_ = [("stuck_after", ctypes.c_int32), ("nonfinite", ctypes.c_void_p), ("longest_stuck", ctypes.c_void_p),
+                ("drift", ctypes.c_void_p), ("total_nonfinite", ctypes.c_uint64), ("chains_stuck", ctypes.c_int64),
+                ("max_drift", ctypes.c_float)]
 
 
 class LaunchPlan(ctypes.Structure):
@@ -103,6 +109,7 @@ def load() -> ctypes.CDLL:
         "nqs_sample": ([P, P, P, P, P, P, P, P], st),
         "nqs_sample_batched": ([P, i32, i32, P], st),
         "nqs_sample_plan": ([P, P, P, P], st),
+        "nqs_sample_checked": ([P, P, P, P, P, P, P, P, P], st),
         "nqs_local_energy": ([P, P, P, i64, i32, P, P], st),
         "nqs_energy_stats": ([P, i64, i64, P, P], st),
         "nqs_energy_stats_noalloc": ([P, i64, i64, P, P], st),

@@ -256,14 +256,11 @@ nqs_status nqs_downcast(const double *src, int64_t n, int32_t dtype, float *dst,
     return launch_downcast(src, n, dtype, dst, scale_out, (hipStream_t)stream);
 }
 
-nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
-                      uint64_t *n_accepted, const nqs_trace *trace, void *stream)
+// Argument checks shared by nqs_sample and nqs_sample_checked (n_chains > 0 here).
+static nqs_status check_sample_args(const nqs_model *m, const nqs_sample_cfg &c, const int8_t *chain_state,
+                                    const nqs_trace *trace)
 {
-    if (!m || !cfg) return set_error(NQS_EINVAL, "NULL model or cfg");
-    const nqs_sample_cfg &c = *cfg;
     const int N = m->desc.n_visible;
-    if (c.n_chains < 0 || c.n_sweeps < 0 || c.n_burnin < 0) return set_error(NQS_EINVAL, "negative sizes");
-    if (c.n_chains == 0) return NQS_OK;
     if (!chain_state) return set_error(NQS_EINVAL, "chain_state is NULL");
     if (c.n_chains > (int64_t)1 << 31) return set_error(NQS_EINVAL, "n_chains too large");
     if (c.move != NQS_MOVE_FLIP && c.move != NQS_MOVE_EXCHANGE) return set_error(NQS_EINVAL, "unknown move");
@@ -284,6 +281,18 @@ nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_sta
             return set_error(NQS_EINVAL, "trace buffers are NULL");
         if (trace->n_chains_traced > c.n_chains) return set_error(NQS_EINVAL, "n_chains_traced > n_chains");
     }
+    return NQS_OK;
+}
+
+nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
+                      uint64_t *n_accepted, const nqs_trace *trace, void *stream)
+{
+    if (!m || !cfg) return set_error(NQS_EINVAL, "NULL model or cfg");
+    const nqs_sample_cfg &c = *cfg;
+    if (c.n_chains < 0 || c.n_sweeps < 0 || c.n_burnin < 0) return set_error(NQS_EINVAL, "negative sizes");
+    if (c.n_chains == 0) return NQS_OK;
+    nqs_status st = check_sample_args(m, c, chain_state, trace);
+    if (st != NQS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     if (m->desc.arch == NQS_RBM) {
         if (c.move != NQS_MOVE_FLIP) return set_error(NQS_EUNSUPPORTED, "the RBM sampler implements single-flip moves");
@@ -300,6 +309,25 @@ nqs_status nqs_sample(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_sta
         return cnn_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
     }
     return ffnn_sample(m, c, chain_state, samples, logpsi, n_accepted, trace, s);
+}
+
+nqs_status nqs_sample_checked(nqs_model *m, const nqs_sample_cfg *cfg, int8_t *chain_state, int8_t *samples,
+                              float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, nqs_sample_diag *diag,
+                              void *stream)
+{
+    if (!m || !cfg || !diag) return set_error(NQS_EINVAL, "NULL model, cfg or diag");
+    const nqs_sample_cfg &c = *cfg;
+    if (c.n_chains < 0 || c.n_sweeps < 0 || c.n_burnin < 0) return set_error(NQS_EINVAL, "negative sizes");
+    if (diag->stuck_after < 0) return set_error(NQS_EINVAL, "stuck_after < 0");
+    diag->total_nonfinite = 0;
+    diag->chains_stuck = 0;
+    diag->max_drift = 0.0f;
+    if (c.n_chains == 0) return NQS_OK;
+    nqs_status st = check_sample_args(m, c, chain_state, trace);
+    if (st != NQS_OK) return st;
+    if (m->desc.arch != NQS_RBM || c.move != NQS_MOVE_FLIP)
+        return set_error(NQS_EUNSUPPORTED, "the run-time detectors are built into the RBM single-flip sampler");
+    return rbm_sample_checked(m, c, chain_state, samples, logpsi, n_accepted, trace, diag, (hipStream_t)stream);
 }
 
 nqs_status nqs_sample_noisy(nqs_model *m, const nqs_sample_cfg *cfg, double noise_sigma, uint64_t noise_seed,

@@ -156,9 +156,11 @@ nqs_status ensure_copy(nqs_model *m, int dtype, hipStream_t stream);
 nqs_status launch_downcast(const double *src, int64_t n, int dtype, float *dst, float *scale_out,
                            hipStream_t stream);
 nqs_status rbm_build_copy(nqs_model *m, int dtype, hipStream_t stream);
+// noise_sigma > 0: the noisy target; dg_*: the run-time detectors (all three per-chain arrays, or none)
 nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
                       float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream,
-                      double noise_sigma = 0.0, uint64_t noise_seed = 0);  // noise_sigma > 0: noisy target
+                      double noise_sigma = 0.0, uint64_t noise_seed = 0, unsigned long long *dg_nonfinite = nullptr,
+                      uint32_t *dg_stuck = nullptr, float *dg_drift = nullptr);
 
 // Sampler launch (one translation unit per lanes-per-chain G).
 struct RbmSampleArgs {
@@ -179,6 +181,12 @@ struct RbmSampleArgs {
     // noisy target: log pi~(x) = log pi(x) + sigma g(x), g(x) standard normal fixed per x
     float noise_sigma;
     uint32_t noise_key0, noise_key1;
+    // run-time detectors (the traced instantiation; all NULL or all set), per chain: proposals with a
+    // non-finite log-ratio, the longest run of sweeps without an accepted move, the largest
+    // |log psi carried by the accepted log-ratios - log psi recomputed from theta| at a refresh
+    unsigned long long *dg_nonfinite;
+    uint32_t *dg_stuck;
+    float *dg_drift;
 };
 struct RbmLaunch {
     int K, threads, blocks;
@@ -186,6 +194,10 @@ struct RbmLaunch {
     int init;              // 1: draw the start states inside the kernel (flip moves)
     size_t lds_bytes;
 };
+nqs_status rbm_sample_checked(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
+                              float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, nqs_sample_diag *diag,
+                              hipStream_t stream);
+
 // Launch plan of the RBM sampler: lanes per chain G, units per lane K, chains
 // per block, table placement.
 struct RbmPlan {

@@ -123,11 +123,12 @@ constexpr size_t kLdsBytes = 160 * 1024;
 
 nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples, float *logpsi,
                       uint64_t *n_accepted, const nqs_trace *trace, hipStream_t stream, double noise_sigma,
-                      uint64_t noise_seed)
+                      uint64_t noise_seed, unsigned long long *dg_nonfinite, uint32_t *dg_stuck, float *dg_drift)
 {
     nqs_status st = ensure_copy(m, cfg.dtype, stream);
     if (st != NQS_OK) return st;
     const RbmDev &net = m->copies[cfg.dtype].rbm;
+    if (!std::isfinite(net.max_abs_w)) return set_error(NQS_ENUMERIC, "non-finite weights W in the sampling copy");
     if (!(net.max_abs_w <= kMaxAbsW))
         return set_error(NQS_EUNSUPPORTED, "the product-form RBM sampler needs |W| <= 5");
     const int N = net.N, M = net.M;
@@ -155,8 +156,13 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
     A.noise_sigma = (float)noise_sigma;
     A.noise_key0 = (uint32_t)noise_seed;
     A.noise_key1 = (uint32_t)(noise_seed >> 32);
+    const bool diag = dg_drift != nullptr;
+    A.dg_nonfinite = diag ? dg_nonfinite : nullptr;
+    A.dg_stuck = diag ? dg_stuck : nullptr;
+    A.dg_drift = diag ? dg_drift : nullptr;
     const bool noisy = noise_sigma > 0.0;
-    if (noisy && (tr || N > 128)) return set_error(NQS_EUNSUPPORTED, "the noisy sampler takes N <= 128 and no trace");
+    if (noisy && (tr || diag || N > 128))
+        return set_error(NQS_EUNSUPPORTED, "the noisy sampler takes N <= 128, no trace and no detectors");
     if ((int64_t)(cfg.n_burnin + cfg.n_sweeps) * A.sweep_size == 0) {
         // nothing to propose: only the initial states (and acceptance counts) are defined
         if (cfg.init_chains) {
@@ -173,7 +179,85 @@ nqs_status rbm_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_sta
                                                 : rbm_plan_rule(N, M, cfg.n_chains, cfg.lanes_per_chain, -1, 0, &P);
     if (st != NQS_OK) return st;
     if (noisy && !P.lds) return set_error(NQS_EUNSUPPORTED, "the noisy sampler needs the ratio table in LDS");
-    return rbm_launch_plan(A, P, tr, noisy, cfg.init_chains ? 1 : 0, stream);
+    return rbm_launch_plan(A, P, tr || diag, noisy, cfg.init_chains ? 1 : 0, stream);   // detectors run traced
+}
+
+// ---------------------------------------------------------------------------
+// Run-time detectors: per-chain counters from the traced sampler, reduced to
+// the host summary.
+// ---------------------------------------------------------------------------
+__global__ void diag_zero_kernel(unsigned long long *nf, uint32_t *stuck, float *drift, int64_t C)
+{
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < C; c += (int64_t)gridDim.x * blockDim.x) {
+        nf[c] = 0ull;
+        stuck[c] = 0u;
+        drift[c] = 0.0f;
+    }
+}
+
+__global__ void __launch_bounds__(256) diag_reduce_kernel(const unsigned long long *nf, const uint32_t *stuck,
+                                                          const float *drift, int64_t C, uint32_t stuck_after,
+                                                          unsigned long long *out)
+{
+    __shared__ unsigned long long s_nf[256], s_st[256];
+    __shared__ float s_dr[256];
+    unsigned long long a = 0, b = 0;
+    float d = 0.0f;
+    for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+        a += nf[c];
+        b += stuck[c] >= stuck_after ? 1ull : 0ull;
+        d = fmaxf(d, drift[c]);
+    }
+    s_nf[threadIdx.x] = a;
+    s_st[threadIdx.x] = b;
+    s_dr[threadIdx.x] = d;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_nf[threadIdx.x] += s_nf[threadIdx.x + w];
+            s_st[threadIdx.x] += s_st[threadIdx.x + w];
+            s_dr[threadIdx.x] = fmaxf(s_dr[threadIdx.x], s_dr[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s_nf[0];
+        out[1] = s_st[0];
+        out[2] = (unsigned long long)__float_as_uint(s_dr[0]);
+    }
+}
+
+nqs_status rbm_sample_checked(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_state, int8_t *samples,
+                              float *logpsi, uint64_t *n_accepted, const nqs_trace *trace, nqs_sample_diag *diag,
+                              hipStream_t stream)
+{
+    const int64_t C = cfg.n_chains;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t b_nf = al(sizeof(unsigned long long) * C), b_st = al(sizeof(uint32_t) * C), b_dr = al(sizeof(float) * C);
+    char *ws = (char *)workspace_slot(2, b_nf + b_st + b_dr + 256, stream);
+    if (!ws) return set_error(NQS_ENOMEM, "workspace allocation failed");
+    unsigned long long *nf = diag->nonfinite ? (unsigned long long *)diag->nonfinite : (unsigned long long *)ws;
+    uint32_t *st = diag->longest_stuck ? diag->longest_stuck : (uint32_t *)(ws + b_nf);
+    float *dr = diag->drift ? diag->drift : (float *)(ws + b_nf + b_st);
+    unsigned long long *sum = (unsigned long long *)(ws + b_nf + b_st + b_dr);
+    const unsigned zb = (unsigned)std::min<int64_t>((C + 255) / 256, 4096);
+    hipLaunchKernelGGL(diag_zero_kernel, dim3(zb), dim3(256), 0, stream, nf, st, dr, C);
+    NQS_HIP_TRY(hipGetLastError());
+    nqs_status s = rbm_sample(m, cfg, chain_state, samples, logpsi, n_accepted, trace, stream, 0.0, 0, nf, st, dr);
+    if (s != NQS_OK) return s;
+    const uint32_t k = diag->stuck_after > 0 ? (uint32_t)diag->stuck_after : 10u;
+    hipLaunchKernelGGL(diag_reduce_kernel, dim3(1), dim3(256), 0, stream, (const unsigned long long *)nf,
+                       (const uint32_t *)st, (const float *)dr, C, k, sum);
+    NQS_HIP_TRY(hipGetLastError());
+    unsigned long long h[3] = {0, 0, 0};
+    NQS_HIP_TRY(hipMemcpyAsync(h, sum, sizeof(h), hipMemcpyDeviceToHost, stream));
+    NQS_HIP_TRY(hipStreamSynchronize(stream));
+    diag->total_nonfinite = h[0];
+    diag->chains_stuck = (int64_t)h[1];
+    const uint32_t bits = (uint32_t)h[2];
+    std::memcpy(&diag->max_drift, &bits, sizeof(float));
+    if (h[0] > 0) return set_error(NQS_ENUMERIC, "non-finite log-ratios in the sampler (proposals rejected)");
+    return NQS_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -177,7 +177,11 @@ __device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c,
     }
 
     float cc[K], sh[K], lpart;
-    float f = rbm_refresh<G, K>(A.net, word, gl, cc, sh, lpart, false);
+    const bool diag = TRACE && A.dg_drift != nullptr;
+    float f = rbm_refresh<G, K>(A.net, word, gl, cc, sh, lpart, diag);
+    unsigned long long dg_nonfinite = 0, dg_acc0 = 0;
+    uint32_t dg_run = 0, dg_longest = 0;
+    float dg_f = f, dg_drift = 0.0f;   // log psi carried by the accepted log-ratios since the last refresh
     uint32_t nw0 = 0u, nw1 = 0u, nw2 = 0u, nw3 = 0u;
     float zc = 0.0f;
     if constexpr (NOISE) {
@@ -277,6 +281,10 @@ __device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c,
             ++acc;
         }
         if constexpr (TRACE) {
+            if (diag) {
+                dg_nonfinite += __builtin_isfinite(d2) ? 0ull : 1ull;
+                if (accept) dg_f = fmaf(d2, 0.5f * kLn2, dg_f);
+            }
             if (c < A.n_traced && gl == 0) {
                 const size_t idx = (size_t)c * (size_t)total + (size_t)k;
                 A.tr_site[idx] = i_c | (0xFFFF << 16);
@@ -302,9 +310,22 @@ __device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c,
             const int64_t out = sweep - A.n_burnin;
             const bool emit = want_out && out >= 0;
             const bool need_logpsi = A.logpsi != nullptr && out >= 0;
+            if constexpr (TRACE) {
+                if (diag) {
+                    dg_run = acc == dg_acc0 ? dg_run + 1 : 0;
+                    dg_longest = max(dg_longest, dg_run);
+                    dg_acc0 = acc;
+                }
+            }
             if (++since_refresh == A.refresh_sweeps || need_logpsi) {
-                f = rbm_refresh<G, K>(A.net, word, gl, cc, sh, lpart, need_logpsi);
+                f = rbm_refresh<G, K>(A.net, word, gl, cc, sh, lpart, need_logpsi || diag);
                 since_refresh = 0;
+                if constexpr (TRACE) {
+                    if (diag) {
+                        dg_drift = fmaxf(dg_drift, fabsf(dg_f - f));
+                        dg_f = f;
+                    }
+                }
             }
             if (emit) {
                 if (A.samples && gl < NW) {
@@ -331,6 +352,13 @@ __device__ __forceinline__ void rbm_run_chain(const RbmSampleArgs &A, int64_t c,
         for (int bb = 0; bb < nb; ++bb) dst[bb] = ((word >> bb) & 1u) ? 1 : -1;
     }
     if (A.n_acc && gl == 0) A.n_acc[c] = acc;
+    if constexpr (TRACE) {
+        if (diag && gl == 0) {
+            A.dg_nonfinite[c] = dg_nonfinite;
+            A.dg_stuck[c] = dg_longest;
+            A.dg_drift[c] = dg_drift;
+        }
+    }
 }
 
 template <int G, int K, bool LDS_TAB, bool TRACE, bool NOISE = false>

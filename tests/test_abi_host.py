@@ -152,7 +152,8 @@ def test_binding_structs_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"nqs_model_desc": _abi.ModelDesc, "nqs_ham_desc": _abi.HamDesc, "nqs_sample_cfg": _abi.SampleCfg,
-               "nqs_sample_job": _abi.SampleJob, "nqs_trace": _abi.Trace, "nqs_launch_plan": _abi.LaunchPlan}
+               "nqs_sample_job": _abi.SampleJob, "nqs_trace": _abi.Trace, "nqs_launch_plan": _abi.LaunchPlan,
+               "nqs_sample_diag": _abi.SampleDiag}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "nqs.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -23,7 +23,8 @@ def test_committed_counter_summary_matches_the_sampler_sources():
     value recorded with the counters; the committed summary must be current."""
     sys.path.insert(0, ROOT)
     import bench
-    got = bench.kernel_traffic("rbm_sample_kernel", "tfim2d_10x10_rbm_bf16_hbm_traffic.txt")
+    got = bench.kernel_traffic("rbm_sample_kernel", "tfim2d_10x10_rbm_bf16_hbm_traffic.txt",
+                               "rbm_sample_kernel<32, 7, true, false, false>")
     if got is None:
         pytest.skip("the committed counter summary predates the current sampler sources: bench.py reports "
                     "traffic as null until the counters are taken again")
