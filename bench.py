@@ -1041,7 +1041,15 @@ def run_peaks(a, torch, nqs, workloads):
         "mfma_bf16_16x16x32_tflops": best_rate("mfma_bf16_k32", 2000) / 1e12,
         "mfma_f32_16x16x4_tflops": best_rate("mfma_f32", 1000) / 1e12,
         "mfma_f64_16x16x4_tflops": best_rate("mfma_f64", 500) / 1e12,
+        # one block of 512 threads per CU (two waves per SIMD, the local-energy kernel's occupancy), one
+        # accumulator chain per wave; the _lds figures read every product's B operand from LDS, issued two
+        # products ahead (_lds) or where the compiler schedules it (_lds_jit)
+        "mfma_bf16_32x32x16_tflops": best_rate("mfma_bf16_32", 2000) / 1e12,
+        "mfma_bf16_32x32x16_lds_tflops": best_rate("mfma_bf16_32_lds", 2000) / 1e12,
+        "mfma_bf16_32x32x16_lds_jit_tflops": best_rate("mfma_bf16_32_lds_jit", 2000) / 1e12,
+        "lds_read_b128_gbs": best_rate("lds_read", 4000) / 1e9,
     }
+    got["lds_read_bytes_per_cu_clock"] = got["lds_read_b128_gbs"] * 1e9 / (cus * 2.4e9)
     # issue rates of the vector instructions the samplers are made of, as cycles per wave64
     # instruction per SIMD at the 2.4 GHz peak clock (4 SIMDs per CU)
     simd_hz = cus * 4 * 2.4e9

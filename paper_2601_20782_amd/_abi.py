@@ -30,7 +30,9 @@ EXPORTS = [
 
 PROBE_KINDS = {"fma_f32": 0, "log_f32": 1, "exp_f32": 2, "mfma_bf16_k16": 3, "mfma_bf16_k32": 4, "mfma_f32": 5,
                "mfma_f64": 6, "hbm_read": 7, "hbm_copy": 8, "mul_f32": 9, "xor_u32": 10, "dpp_add_f32": 11,
-               "mulhi_u32": 12, "fma_f32_w1": 13, "fma_f32_w2": 14, "fma_f32_dep": 15}
+               "mulhi_u32": 12, "fma_f32_w1": 13, "fma_f32_w2": 14, "fma_f32_dep": 15,
+               "lds_read": 16, "mfma_bf16_32": 17, "mfma_bf16_32_lds": 18,
+               "mfma_bf16_32_lds_jit": 19}
 
 
 class ModelDesc(ctypes.Structure):

@@ -598,10 +598,12 @@ nqs_status ffnn_sample_dispatch(int dtype, int QK, bool trace, const FfnnSampleA
                                 hipStream_t s);
 nqs_status ffnn_eloc_dispatch(int dtype, int QK, const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s);
 size_t ffnn_reg_sample_lds(int dtype, int N, int m1p, int m2p);
-size_t ffnn_reg_eloc_lds(int dtype, int N, int m1p, int m2p);
+bool ffnn_reg_eloc_launch_bf16(int ke, const FfnnElocArgs &A, int G, int blocks, size_t lds, hipStream_t s);
+bool ffnn_reg_eloc_launch_f16(int ke, const FfnnElocArgs &A, int G, int blocks, size_t lds, hipStream_t s);
+size_t ffnn_reg_eloc_lds_bf16(int N, int ke, int m2p, int G);
+size_t ffnn_reg_eloc_lds_f16(int N, int ke, int m2p, int G);
 nqs_status ffnn_reg_sample_dispatch(int dtype, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds,
                                     hipStream_t s);
-nqs_status ffnn_reg_eloc_dispatch(int dtype, const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s);
 
 // Layer 2 can live in registers (8 waves x 32 output rows) for 16-bit operands
 // with 128 <= m1p <= 512 and m2p <= 256.
@@ -713,8 +715,16 @@ nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
     const FfnnDev &f = m->copies[dtype].ffnn;
     const int N = f.widths[0];
     size_t lds;
-    const size_t reg_lds = ffnn_reg_eloc_lds(dtype, N, f.m1p, f.m2p);
-    const bool use_reg = reg_path(dtype, f) && reg_lds <= 160 * 1024;
+    // the register-resident kernel: W1 (16 KE columns) in LDS and groups of G samples, the largest G of 8, 4, 2,
+    // 1 whose rows the LDS holds (N < 8191 for the packed row codes)
+    const int KE = f.n_layers >= 2 ? (f.widths[1] + 15) / 16 : 0;
+    auto reg_lds_for = [&](int G) {
+        return dtype == NQS_F16 ? ffnn_reg_eloc_lds_f16(N, KE, f.m2p, G) : ffnn_reg_eloc_lds_bf16(N, KE, f.m2p, G);
+    };
+    int reg_G = 8;
+    while (reg_G > 1 && reg_lds_for(reg_G) > 160 * 1024) reg_G /= 2;
+    const size_t reg_lds = reg_path(dtype, f) ? reg_lds_for(reg_G) : 0;
+    const bool use_reg = reg_path(dtype, f) && reg_lds <= 160 * 1024 && N < 8191;
     if (use_reg) lds = reg_lds;
     else if (dtype == NQS_F32) lds = ffnn_eloc_lds_bytes<float>(N, f.m1p, f.m2p);
     else if (dtype == NQS_F16) lds = ffnn_eloc_lds_bytes<_Float16>(N, f.m1p, f.m2p);
@@ -738,8 +748,12 @@ nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
     A.eloc = eloc;
     const int QK = (f.m1p + 63) / 64;
     if (use_reg) {
-        const int blocks = (int)std::min<int64_t>((n + kRegGroup - 1) / kRegGroup, device_cus());
-        return ffnn_reg_eloc_dispatch(dtype, A, blocks, lds, stream);
+        const int blocks = (int)std::min<int64_t>((n + reg_G - 1) / reg_G, device_cus());
+        const bool ok = dtype == NQS_F16 ? ffnn_reg_eloc_launch_f16(KE, A, reg_G, blocks, lds, stream)
+                                         : ffnn_reg_eloc_launch_bf16(KE, A, reg_G, blocks, lds, stream);
+        if (!ok) return set_error(NQS_EUNSUPPORTED, "first hidden width not supported by the local-energy kernel");
+        NQS_HIP_TRY(hipGetLastError());
+        return NQS_OK;
     }
     const int blocks = (int)std::min<int64_t>(n, 256 * 4);
     return ffnn_eloc_dispatch(dtype, QK, A, blocks, lds, stream);

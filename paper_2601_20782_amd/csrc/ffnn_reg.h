@@ -15,11 +15,13 @@
 // (flip) or rank-2 (exchange) change of an accepted move.  Proposals that
 // change nothing (an exchange of equal spins) are compacted away before the
 // matrix product, so a pass evaluates only the effective proposals.
-// Local energies: 4 samples per group; their connected configurations are
-// listed, laid end to end and evaluated 32 rows per pass.
+// Local energies: groups of samples whose connected configurations are listed,
+// laid end to end and evaluated 32 rows per pass, W1 and the rows in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "ffnn_mc.h"
 
@@ -28,8 +30,6 @@ namespace nqs {
 constexpr int kRegThreads = 512;
 constexpr int kRegWaves = kRegThreads / 64;
 constexpr int kRegRows = 64;       // chains per sampler block
-constexpr int kRegPass = 32;       // rows per local-energy pass
-constexpr int kRegGroup = 4;       // samples per local-energy group
 
 // A fragments of this wave's 32 rows of W2 ([m2p][m1p], operand format); zero
 // beyond m2p.
@@ -346,195 +346,352 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
 
 // ---------------------------------------------------------------------------
 // Local energies
+//
+// The W1 columns the network uses (16 KE hidden units, KE = ceil(m1 / 16)) are
+// copied to LDS once per block.  A group of G samples (G <= 8, as many as the
+// LDS holds): the block forms z1 = W1 s + b1 of each sample (lane pairs split
+// the sites), lists each sample's rows (the sample itself, then its connected
+// configurations) and evaluates the rows of the whole group end to end,
+// kElocRows = 32 at a time.  Passes are software-pipelined over two LDS
+// buffers of h1 rows: while wave w multiplies its 32 rows of W2 (registers, KE
+// fragments of 16) by the current buffer, it stages 4 rows of the next pass
+// into the other buffer (lane c: hidden units 8c .. 8c + 7, W1 and z1 read from
+// LDS) and, for KE <= 25, turns the previous pass's products into log-cosh
+// partials, both written in between the matrix instructions so that they
+// overlap them.  One barrier per pass; a pass's row sums over the waves are
+// taken one or two passes later.  Waves whose 32 outputs are all padding only
+// stage rows.
 // ---------------------------------------------------------------------------
+constexpr int kElocRows = 32;                        // rows per pass: one 32 x 32 tile per wave
+constexpr int kElocStage = kElocRows / kRegWaves;    // rows each wave stages per pass
+
 template <typename T>
-__host__ __device__ inline size_t reg_eloc_lds_bytes(int N, int m1p, int m2p)
+__host__ __device__ inline size_t reg_eloc_lds_bytes(int N, int KE, int m2p, int G)
 {
-    const size_t ldh = m1p + hs_pad<T>();
-    const size_t maxrows = (size_t)kRegGroup * (2 * N + 1);
+    const size_t K = 16 * (size_t)KE, ldh = K + hs_pad<T>();
+    const size_t maxrows = (size_t)G * (2 * N + 1);
     size_t b = 0;
-    b += sizeof(T) * (size_t)N * m1p;                   // W1 columns
-    b += sizeof(T) * (size_t)kRegPass * ldh;            // h1 rows of a pass
+    b += sizeof(T) * (size_t)N * K;                     // W1 columns
+    b += sizeof(T) * 2 * (size_t)kElocRows * ldh;       // h1 rows of two passes
+    b += sizeof(float) * (size_t)G * K;                 // z1 of the group's samples
     b += sizeof(float) * m2p;                           // b2
-    b += sizeof(float) * kRegWaves * kRegPass;          // partial sums
-    b += sizeof(float) * (size_t)kRegGroup * m1p;       // z1 of the group's samples
-    b += sizeof(float) * (size_t)kRegGroup * N;         // spins
-    b += (sizeof(int) * 3 + sizeof(float) * 2) * maxrows;   // rows: site i, site j, sample, coefficient, f
-    b += sizeof(double) * (kRegGroup + kRegWaves) + sizeof(int) * (kRegGroup + 2 + kRegWaves) + 16;
+    b += sizeof(float) * 2 * kRegWaves * kElocRows;     // partial sums of two passes
+    b += sizeof(float) * (size_t)G * N;                 // spins
+    b += (sizeof(int) + 2 * sizeof(float)) * maxrows;   // rows: packed (i, j, sample), coefficient, f
+    b += sizeof(double) * G + sizeof(int) * (2 * G + 2) + 32;
     return b;
 }
 
-template <typename T, int KF>
-__global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs A)
+// row code: (i + 1) | (j + 1) << 13 | s << 26, i = j = -1 for the sample itself
+__device__ __forceinline__ int eloc_row_code(int i, int j, int s) { return (i + 1) | ((j + 1) << 13) | (s << 26); }
+
+// h1 = ReLU(z1 + g (W1[:, i] - W1[:, j])) of row `row` (clamped into the group's rows), hidden units
+// 8c .. 8c + 7, c = min(lane, nch - 1) (lanes past the row's chunks repeat the last one), into Hs row lr.
+// W1l: [N][K] in LDS; zs: [G][K].
+template <typename T>
+__device__ __forceinline__ void eloc_stage_row(const T *W1l, const int *rcode, const float *sp, const float *zs,
+                                               T *Hs, int ldh, int N, int K, int nch, int row, int lr, int lane)
 {
     typedef typename Mc<T>::frag frag;
-    constexpr int G = kRegGroup;
+    const int code = __builtin_amdgcn_readfirstlane(rcode[row]);   // uniform over the wave
+    const int i = (code & 0x1FFF) - 1, j = ((code >> 13) & 0x1FFF) - 1, s = code >> 26;
+    const int ic = i >= 0 ? i : 0, jc = j >= 0 ? j : 0;
+    const float g = (i >= 0 ? -2.0f : 0.0f) * sp[s * N + ic];
+    const float jm = j >= 0 ? 1.0f : 0.0f;
+    const int c = lane < nch ? lane : nch - 1;
+    const frag wi = *reinterpret_cast<const frag *>(W1l + ic * K + 8 * c);
+    const frag wj = *reinterpret_cast<const frag *>(W1l + jc * K + 8 * c);
+    const float4 z0 = *reinterpret_cast<const float4 *>(zs + s * K + 8 * c);
+    const float4 z1 = *reinterpret_cast<const float4 *>(zs + s * K + 8 * c + 4);
+    const float zz[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
+    frag h;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float d = fmaf(-jm, Mc<T>::to_f32(wj[e]), Mc<T>::to_f32(wi[e]));
+        h[e] = Mc<T>::from_f32(fmaxf(fmaf(g, d, zz[e]), 0.0f));
+    }
+    *reinterpret_cast<frag *>(Hs + lr * ldh + 8 * c) = h;
+}
+
+// Four of the 16 outputs a lane holds of a 32 x 32 tile (registers 4q .. 4q + 3: outputs
+// 8q + 4 (lane / 32) + 0..3 of the wave's 32) into the running |z| sum and product of (1 + e^-2|z|).
+__device__ __forceinline__ void eloc_logcosh4(const mc_floatx16 &acc, int q, float4 b, float &abs_sum, float &prod)
+{
+    const float bb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float v = fabsf(acc[4 * q + r] + bb[r]);
+        abs_sum += v;
+        prod *= 1.0f + __expf(-2.0f * v);
+    }
+}
+
+template <typename T, int KE>
+__global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs A, int G)
+{
+    typedef typename Mc<T>::frag frag;
+    static_assert(KE >= kElocStage, "one staged row every KE / kElocStage fragments");
+    constexpr int K = 16 * KE;
     extern __shared__ __align__(16) unsigned char smem[];
     const FfnnDev &net = A.net;
     const int N = net.widths[0], m1p = net.m1p, m2p = net.m2p, m2 = net.widths[2];
-    const int ldh = m1p + hs_pad<T>();
-    const int nwt = (m2p + 31) >> 5;
+    const int ldh = K + hs_pad<T>();
+    const int nwt = (m2 + 31) >> 5;                    // waves with at least one real output
     const int maxrows = G * (2 * N + 1);
-    T *W1l = reinterpret_cast<T *>(smem);
-    T *Hs = W1l + (size_t)N * m1p;
-    float *b2s = reinterpret_cast<float *>(Hs + (size_t)kRegPass * ldh);
-    float *part = b2s + m2p;
-    float *zs = part + kRegWaves * kRegPass;           // [G][m1p]
-    float *sp = zs + (size_t)G * m1p;                  // [G][N]
-    int *ri = reinterpret_cast<int *>(sp + (size_t)G * N);
-    int *rj = ri + maxrows;
-    int *rs = rj + maxrows;
-    float *rc = reinterpret_cast<float *>(rs + maxrows);
+    const int nch = K >> 3;                            // 8-unit chunks of a row
+    T *W1l = reinterpret_cast<T *>(smem);              // [N][K]
+    T *Hs = W1l + (size_t)N * K;                       // [2][kElocRows][ldh]
+    float *zs = reinterpret_cast<float *>(Hs + 2 * (size_t)kElocRows * ldh);   // [G][K]
+    float *b2s = zs + (size_t)G * K;
+    float *part = b2s + m2p;                           // [2][kRegWaves][kElocRows]
+    float *sp = part + 2 * kRegWaves * kElocRows;      // [G][N]
+    int *rcode = reinterpret_cast<int *>(sp + (size_t)G * N);
+    float *rc = reinterpret_cast<float *>(rcode + maxrows);
     float *fr = rc + maxrows;
     double *diag = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(fr + maxrows) + 7) & ~(uintptr_t)7);
-    double *dred = diag + G;                           // [kRegWaves]
-    int *rbase = reinterpret_cast<int *>(dred + kRegWaves);   // [G] first row of each sample
-    int *s_nrows = rbase + G;
-    int *wcount = s_nrows + 2;                         // [kRegWaves]
+    int *rbase = reinterpret_cast<int *>(diag + G);    // [G + 1]
+    int *rcnt = rbase + G + 1;                         // [G]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    frag a[KF];
-    reg_load_w2<T, KF>(reinterpret_cast<const T *>(A.W2), m1p, m2p, a);
+    const int lr = lane & 31, lh = lane >> 5;
+    const bool live = __builtin_amdgcn_readfirstlane(wave) * 32 < m2;   // this wave owns real outputs (uniform)
+    frag a[KE];
+    reg_load_w2<T, KE>(reinterpret_cast<const T *>(A.W2), m1p, m2p, a);
     {
         const T *src = reinterpret_cast<const T *>(A.W1t);
-        for (int k = tid; k < N * m1p; k += kRegThreads) W1l[k] = src[k];
-        for (int k = tid; k < kRegPass * ldh; k += kRegThreads) Hs[k] = Mc<T>::from_f32(0.0f);
-        for (int k = tid; k < m2p; k += kRegThreads) b2s[k] = net.b2p[k];
+        for (int k = tid; k < N * nch; k += kRegThreads) {
+            const int i = k / nch, c = k % nch;
+            *reinterpret_cast<frag *>(W1l + i * K + 8 * c) = *reinterpret_cast<const frag *>(src + (size_t)i * m1p + 8 * c);
+        }
     }
+    for (int k = tid; k < m2p; k += kRegThreads) b2s[k] = net.b2p[k];
     const int nb = A.dim == 1 ? (A.pbc ? A.L : A.L - 1) : 2 * A.L * A.L;   // candidate bonds (2D: 2 per site)
     const int ncand = A.kind == NQS_TFIM ? N : 0;
     const int nloop = ncand > nb ? ncand : nb;
 
+    // candidate c of a sample: a flip (TFIM) and / or a bond; returns whether it gives a row
+    auto candidate = [&](const float *ss, int c, int &i, int &j, float &coef, double &dg) {
+        bool take = false;
+        i = -1;
+        j = -1;
+        coef = 0.0f;
+        if (c < ncand) {
+            i = c;
+            take = true;
+            coef = (float)A.h * ((A.marshall && on_sub_a(A.dim, A.L, i)) ? -1.0f : 1.0f);
+        }
+        if (c < nb) {
+            int bi, bj;
+            bool valid = true;
+            if (A.dim == 1) {
+                bi = c;
+                bj = c + 1 < A.L ? c + 1 : 0;
+            } else {
+                const int site = c >> 1, x = site / A.L, y = site % A.L;
+                bi = site;
+                if ((c & 1) == 0) {
+                    valid = A.pbc || x + 1 < A.L;
+                    bj = ((x + 1) % A.L) * A.L + y;
+                } else {
+                    valid = A.pbc || y + 1 < A.L;
+                    bj = x * A.L + (y + 1) % A.L;
+                }
+            }
+            if (valid) {
+                dg += A.J * (double)(ss[bi] * ss[bj]);
+                if (A.kind == NQS_HEISENBERG && ss[bi] != ss[bj]) {
+                    i = bi;
+                    j = bj;
+                    take = true;
+                    const bool flip = A.marshall && (on_sub_a(A.dim, A.L, bi) != on_sub_a(A.dim, A.L, bj));
+                    coef = 2.0f * (float)A.J * (flip ? -1.0f : 1.0f);
+                }
+            }
+        }
+        return take;
+    };
+    // f of the rows of pass q: the sum of the waves' partials (in wave order)
+    auto row_sums = [&](int q, int nrows) {
+        if (tid < kElocRows && q * kElocRows + tid < nrows) {
+            const float *pp = part + (size_t)(q & 1) * kRegWaves * kElocRows;
+            float f = 0.0f;
+            for (int w = 0; w < nwt; ++w) f += pp[w * kElocRows + tid];
+            fr[q * kElocRows + tid] = f;
+        }
+    };
+    // the log-cosh partial of a finished tile: sum_k log cosh z2 = sum |z2| + log prod (1 + e^-2|z2|) - n ln 2
+    // (16 factors in (1, 2]: the product stays below 2^16; padded outputs have z2 = 0 exactly and add 0)
+    auto finish_tile = [&](float abs_sum, float prod, int q) {
+        float sv = abs_sum + __logf(prod) - 16.0f * kLn2f;
+        sv += __shfl_xor(sv, 32, 64);
+        if (lane < 32) part[(size_t)(q & 1) * kRegWaves * kElocRows + wave * kElocRows + lane] = sv;
+    };
+    const float4 *b2v = reinterpret_cast<const float4 *>(b2s + wave * 32 + 4 * lh);   // outputs 8q + 4 lh + 0..3
+
     for (int64_t g0 = (int64_t)blockIdx.x * G; g0 < A.n; g0 += (int64_t)gridDim.x * G) {
         const int ns = (int)min<int64_t>(G, A.n - g0);
-        __syncthreads();
+        __syncthreads();   // the previous group's rows and energies are consumed (and W1, b2 are in place)
         for (int k = tid; k < G * N; k += kRegThreads) {
             const int s = k / N, i = k % N;
             sp[k] = s < ns ? (float)A.samples[(g0 + s) * N + i] : 1.0f;
         }
-        if (tid == 0) *s_nrows = 0;
         __syncthreads();
-        // z1 of the group's samples
-        for (int k = tid; k < G * m1p; k += kRegThreads) {
-            const int s = k / m1p, kk = k % m1p;
-            float z = net.b1p[kk];
-            for (int i = 0; i < N; ++i) z = fmaf(Mc<T>::to_f32(W1l[i * m1p + kk]), sp[s * N + i], z);
-            zs[k] = z;
-        }
-        // diagonal part and the rows: the sample itself, then its connected configurations
-        for (int s = 0; s < ns; ++s) {
+        // z1 = W1 s + b1: task (sample, chunk) per lane pair, lane l + 32 h sums the sites of half h
+        for (int q = wave * 32 + lr; q < G * nch; q += kRegWaves * 32) {
+            const int s = q / nch, c = q % nch;
             const float *ss = sp + s * N;
+            float z[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) z[e] = 0.0f;
+            const int i0 = lh ? N / 2 : 0, i1 = lh ? N : N / 2;
+#pragma unroll 4
+            for (int i = i0; i < i1; ++i) {
+                const frag w = *reinterpret_cast<const frag *>(W1l + i * K + 8 * c);
+                const float sv = ss[i];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) z[e] = fmaf(Mc<T>::to_f32(w[e]), sv, z[e]);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) z[e] += __shfl_xor(z[e], 32, 64);
+            if (lh == 0) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) z[e] += net.b1p[8 * c + e];
+                *reinterpret_cast<float4 *>(zs + s * K + 8 * c) = make_float4(z[0], z[1], z[2], z[3]);
+                *reinterpret_cast<float4 *>(zs + s * K + 8 * c + 4) = make_float4(z[4], z[5], z[6], z[7]);
+            }
+        }
+        // wave s: its sample's row count and diagonal part
+        if (wave < ns) {
+            const float *ss = sp + wave * N;
             double dg = 0.0;
             int cnt = 0;
-            if (tid == 0) {
-                const int r0 = *s_nrows;
-                rbase[s] = r0;
-                ri[r0] = -1;
-                rj[r0] = -1;
-                rs[r0] = s;
+            for (int c0 = 0; c0 < nloop; c0 += 64) {
+                int i, j;
+                float coef;
+                const bool take = c0 + lane < nloop && candidate(ss, c0 + lane, i, j, coef, dg);
+                cnt += __popcll(__ballot(take));
+            }
+            dg = group_sum<64>(dg);
+            if (lane == 0) {
+                rcnt[wave] = cnt;
+                diag[wave] = dg;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int r = 0;
+            for (int s = 0; s < ns; ++s) {
+                rbase[s] = r;
+                r += 1 + rcnt[s];
+            }
+            rbase[ns] = r;
+        }
+        __syncthreads();
+        // wave s: the rows of its sample, in candidate order after the sample's own row
+        if (wave < ns) {
+            const float *ss = sp + wave * N;
+            const int r0 = rbase[wave];
+            if (lane == 0) {
+                rcode[r0] = eloc_row_code(-1, -1, wave);
                 rc[r0] = 0.0f;
             }
-            __syncthreads();
-            const int first = *s_nrows + 1;
-            for (int base = 0; base < nloop; base += kRegThreads) {
-                const int c = base + tid;
-                int i = -1, j = -1;
-                bool take = false;
-                float coef = 0.0f;
-                if (c < ncand) {
-                    i = c;
-                    take = true;
-                    coef = (float)A.h * ((A.marshall && on_sub_a(A.dim, A.L, i)) ? -1.0f : 1.0f);
-                }
-                if (c < nb) {
-                    int bi, bj;
-                    bool valid = true;
-                    if (A.dim == 1) {
-                        bi = c;
-                        bj = c + 1 < A.L ? c + 1 : 0;
-                    } else {
-                        const int site = c >> 1, x = site / A.L, y = site % A.L;
-                        bi = site;
-                        if ((c & 1) == 0) {
-                            valid = A.pbc || x + 1 < A.L;
-                            bj = ((x + 1) % A.L) * A.L + y;
-                        } else {
-                            valid = A.pbc || y + 1 < A.L;
-                            bj = x * A.L + (y + 1) % A.L;
-                        }
-                    }
-                    if (valid) {
-                        dg += A.J * (double)(ss[bi] * ss[bj]);
-                        if (A.kind == NQS_HEISENBERG && ss[bi] != ss[bj]) {
-                            i = bi;
-                            j = bj;
-                            take = true;
-                            const bool flip = A.marshall && (on_sub_a(A.dim, A.L, bi) != on_sub_a(A.dim, A.L, bj));
-                            coef = 2.0f * (float)A.J * (flip ? -1.0f : 1.0f);
-                        }
-                    }
-                }
+            int pos0 = r0 + 1;
+            double unused = 0.0;
+            for (int c0 = 0; c0 < nloop; c0 += 64) {
+                int i, j;
+                float coef;
+                const bool take = c0 + lane < nloop && candidate(ss, c0 + lane, i, j, coef, unused);
                 const unsigned long long bal = __ballot(take);
-                if (lane == 0) wcount[wave] = __popcll(bal);
-                __syncthreads();
-                int off = first + cnt;
-                for (int w = 0; w < wave; ++w) off += wcount[w];
-                int tot = 0;
-                for (int w = 0; w < kRegWaves; ++w) tot += wcount[w];
                 if (take) {
-                    const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
-                    ri[pos] = i;
-                    rj[pos] = j;
-                    rs[pos] = s;
+                    const int pos = pos0 + __popcll(bal & ((1ull << lane) - 1ull));
+                    rcode[pos] = eloc_row_code(i, j, wave);
                     rc[pos] = coef;
                 }
-                cnt += tot;
-                __syncthreads();
+                pos0 += __popcll(bal);
             }
-            const double v = group_sum<64>(dg);
-            if (lane == 0) dred[wave] = v;
-            __syncthreads();
-            if (tid == 0) {
-                double d = 0.0;
-                for (int w = 0; w < kRegWaves; ++w) d += dred[w];
-                diag[s] = d;
-                *s_nrows = first + cnt;
-            }
-            __syncthreads();
         }
-        const int nrows = *s_nrows;
-        // all rows through the network, kRegPass at a time
-        for (int r0 = 0; r0 < nrows; r0 += kRegPass) {
-            for (int rr = 0; rr < kRegPass / kRegWaves; ++rr) {
-                const int lr = wave * (kRegPass / kRegWaves) + rr;
-                const int row = r0 + lr;
-                if (row < nrows) {
-                    const int i = ri[row], j = rj[row], s = rs[row];
-                    const float g = i >= 0 ? -2.0f * sp[s * N + i] : 0.0f;
-                    for (int k = lane; k < m1p; k += 64) {
-                        float d = 0.0f;
-                        if (i >= 0) {
-                            d = Mc<T>::to_f32(W1l[i * m1p + k]);
-                            if (j >= 0) d -= Mc<T>::to_f32(W1l[j * m1p + k]);
-                        }
-                        Hs[lr * ldh + k] = Mc<T>::from_f32(fmaxf(fmaf(g, d, zs[s * m1p + k]), 0.0f));
-                    }
+        __syncthreads();
+        const int nrows = rbase[ns];
+        const int npass = (nrows + kElocRows - 1) / kElocRows;
+        // prologue: pass 0 into buffer 0
+#pragma unroll
+        for (int rr = 0; rr < kElocStage; ++rr) {
+            const int r = wave * kElocStage + rr;
+            eloc_stage_row<T>(W1l, rcode, sp, zs, Hs, ldh, N, K, nch, min(r, nrows - 1), r, lane);
+        }
+        __syncthreads();
+        // one pass: pass p's products (LIVE waves) with pass p + 1 staged in between (the last pass stages
+        // clamped rows that nothing reads), each B fragment read two products ahead of its use, the order
+        // pinned against the scheduler.  kLate: pass p - 1's log-cosh partial is also taken in between (from
+        // accp; a zero tile at p = 0, not written); otherwise (wide layers, where the second accumulator would
+        // not fit in registers) pass p's own partial follows its products.
+        constexpr bool kLate = KE <= 25;
+        constexpr int kLag = kLate ? 2 : 1;              // a pass's row sums are taken kLag passes later
+        mc_floatx16 acc, accp;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accp[r] = 0.0f;
+        auto pass = [&](int p, auto live_c) {
+            constexpr bool LIVE = decltype(live_c)::value;
+            const T *Hc = Hs + (size_t)(p & 1) * kElocRows * ldh + lr * ldh + 8 * lh;
+            T *Hn = Hs + (size_t)((p + 1) & 1) * kElocRows * ldh;
+            const int nbase = (p + 1) * kElocRows;
+            constexpr int kStep = KE / kElocStage;       // a row staged at kf = 0, kStep, 2 kStep, 3 kStep
+            float abs_sum = 0.0f, prod = 1.0f;
+            frag b[3];
+            if constexpr (LIVE) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+                b[0] = *reinterpret_cast<const frag *>(Hc);
+                b[1] = *reinterpret_cast<const frag *>(Hc + 16);
+            }
+#pragma unroll
+            for (int kf = 0; kf < KE; ++kf) {
+                if constexpr (LIVE) {
+                    if (kf + 2 < KE) b[(kf + 2) % 3] = *reinterpret_cast<const frag *>(Hc + (kf + 2) * 16);
+                    __builtin_amdgcn_sched_barrier(0);
+                    acc = Mc<T>::mma(a[kf], b[kf % 3], acc);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (kf % kStep == 0 && kf / kStep < kElocStage) {
+                    const int r = wave * kElocStage + kf / kStep;
+                    eloc_stage_row<T>(W1l, rcode, sp, zs, Hn, ldh, N, K, nch, min(nbase + r, nrows - 1), r, lane);
+                }
+                if constexpr (LIVE && kLate) {
+                    if (kf % kStep == kStep / 2 && kf / kStep < 4)
+                        eloc_logcosh4(accp, kf / kStep, b2v[2 * (kf / kStep)], abs_sum, prod);
                 }
             }
-            __syncthreads();
-            const float sv = reg_tile_logcosh<T, KF>(a, Hs, ldh, 0, b2s, m2);
-            if (lane < 32) part[wave * kRegPass + lane] = sv;
-            __syncthreads();
-            if (tid < kRegPass && r0 + tid < nrows) {
-                float f = 0.0f;
-                for (int w = 0; w < nwt; ++w) f += part[w * kRegPass + tid];
-                fr[r0 + tid] = f;
+            if constexpr (LIVE && kLate) {
+                if (p > 0) finish_tile(abs_sum, prod, p - 1);
+                accp = acc;
+            } else if constexpr (LIVE) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) eloc_logcosh4(acc, q, b2v[2 * q], abs_sum, prod);
+                finish_tile(abs_sum, prod, p);
             }
+        };
+        for (int p = 0; p < npass; ++p) {
+            if (p >= kLag) row_sums(p - kLag, nrows);    // that pass's partials were written before the last barrier
+            if (live) pass(p, std::true_type{});
+            else pass(p, std::false_type{});
+            __syncthreads();
         }
+        // the partials still due (kLate: the last pass's), then the row sums still due
+        if constexpr (kLate) {
+            if (live) {
+                float abs_sum = 0.0f, prod = 1.0f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) eloc_logcosh4(accp, q, b2v[2 * q], abs_sum, prod);
+                finish_tile(abs_sum, prod, npass - 1);
+            }
+            if (npass >= 2) row_sums(npass - 2, nrows);
+            __syncthreads();
+        }
+        row_sums(npass - 1, nrows);
         __syncthreads();
         // wave s sums sample s:  eps = diag + sum_rows coef * exp(f_row - f_sample)   (FP64)
         if (wave < ns) {
-            const int s = wave, rb0 = rbase[s], rend = s + 1 < ns ? rbase[s + 1] : nrows;
+            const int s = wave, rb0 = rbase[s], rend = rbase[s + 1];
             const float f0 = fr[rb0];
             double off = 0.0;
             for (int r = rb0 + 1 + lane; r < rend; r += 64) off += (double)rc[r] * exp((double)(fr[r] - f0));

@@ -15,13 +15,6 @@ static void launch_reg_sample(bool trace, const FfnnSampleArgs &A, int blocks, s
     }
 }
 
-template <typename T, int KF>
-static void launch_reg_eloc(const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s)
-{
-    allow_lds(ffnn_eloc_reg_kernel<T, KF>, lds);
-    hipLaunchKernelGGL((ffnn_eloc_reg_kernel<T, KF>), dim3(blocks), dim3(kRegThreads), lds, s, A);
-}
-
 template <typename T>
 static bool reg_sample_t(int KF, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds, hipStream_t s)
 {
@@ -37,29 +30,9 @@ static bool reg_sample_t(int KF, bool trace, const FfnnSampleArgs &A, int blocks
     }
 }
 
-template <typename T>
-static bool reg_eloc_t(int KF, const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s)
-{
-    switch (KF) {
-    case 8: launch_reg_eloc<T, 8>(A, blocks, lds, s); return true;
-    case 12: launch_reg_eloc<T, 12>(A, blocks, lds, s); return true;
-    case 16: launch_reg_eloc<T, 16>(A, blocks, lds, s); return true;
-    case 20: launch_reg_eloc<T, 20>(A, blocks, lds, s); return true;
-    case 24: launch_reg_eloc<T, 24>(A, blocks, lds, s); return true;
-    case 28: launch_reg_eloc<T, 28>(A, blocks, lds, s); return true;
-    case 32: launch_reg_eloc<T, 32>(A, blocks, lds, s); return true;
-    default: return false;
-    }
-}
-
 size_t ffnn_reg_sample_lds(int dtype, int N, int m1p, int m2p)
 {
     return dtype == NQS_F16 ? RegSampleLds<_Float16>::bytes(N, m1p, m2p) : RegSampleLds<__bf16>::bytes(N, m1p, m2p);
-}
-
-size_t ffnn_reg_eloc_lds(int dtype, int N, int m1p, int m2p)
-{
-    return dtype == NQS_F16 ? reg_eloc_lds_bytes<_Float16>(N, m1p, m2p) : reg_eloc_lds_bytes<__bf16>(N, m1p, m2p);
 }
 
 nqs_status ffnn_reg_sample_dispatch(int dtype, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds,
@@ -69,15 +42,6 @@ nqs_status ffnn_reg_sample_dispatch(int dtype, bool trace, const FfnnSampleArgs 
     const bool ok = dtype == NQS_F16 ? reg_sample_t<_Float16>(KF, trace, A, blocks, lds, s)
                                      : reg_sample_t<__bf16>(KF, trace, A, blocks, lds, s);
     if (!ok) return set_error(NQS_EUNSUPPORTED, "first hidden width not supported by the register-resident sampler");
-    NQS_HIP_TRY(hipGetLastError());
-    return NQS_OK;
-}
-
-nqs_status ffnn_reg_eloc_dispatch(int dtype, const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s)
-{
-    const int KF = A.net.m1p / 16;
-    const bool ok = dtype == NQS_F16 ? reg_eloc_t<_Float16>(KF, A, blocks, lds, s) : reg_eloc_t<__bf16>(KF, A, blocks, lds, s);
-    if (!ok) return set_error(NQS_EUNSUPPORTED, "first hidden width not supported by the register-resident local energy");
     NQS_HIP_TRY(hipGetLastError());
     return NQS_OK;
 }

@@ -15,6 +15,7 @@ typedef float pk_f32x4 __attribute__((ext_vector_type(4)));
 typedef double pk_f64x4 __attribute__((ext_vector_type(4)));
 typedef short pk_s16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 pk_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float pk_f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kProbeThreads = 256;
 constexpr int kProbeUnroll = 16;
@@ -108,6 +109,74 @@ __global__ void __launch_bounds__(kProbeThreads) probe_mfma_kernel(float *__rest
     if (s == -1.0f) out[t] = s;
 }
 
+// One block of 512 threads per compute unit: LDS reads (KIND = LDS_READ), or one chain of 32 x 32 x 16 products per
+// wave with B from registers or from LDS (row lane % 32, columns 16 k + 8 (lane / 32) of a 32 x 512 tile whose
+// rows are padded by 8 values so that the 32 rows of a read fall in different banks; for _LDS each B read is issued
+// two products ahead of its use, the order pinned against the scheduler, for _LDS_JIT the compiler places them).  The offset of each iteration goes through an empty asm statement so that the
+// compiler cannot prove two iterations read the same words.
+constexpr int kProbeLdsThreads = 512;
+constexpr int kProbeLdsCols = 512;
+constexpr int kProbeLdsLd = kProbeLdsCols + 8;
+
+template <int KIND>
+__global__ void __launch_bounds__(kProbeLdsThreads) probe_lds_kernel(float *__restrict__ out, int iters)
+{
+    __shared__ __align__(16) __bf16 tile[32 * kProbeLdsLd];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int k = tid; k < 32 * kProbeLdsLd; k += kProbeLdsThreads) tile[k] = (__bf16)(1e-3f * (float)(k & 127));
+    __syncthreads();
+    float s = 0.0f;
+    if constexpr (KIND == NQS_PROBE_LDS_READ) {
+        // lane l reads word l + 64 m, m = (offset + u + wave) mod 32: consecutive lanes, consecutive words
+        const uint4 *w = reinterpret_cast<const uint4 *>(tile);
+        uint32_t x = 0u;
+        for (int it = 0; it < iters; ++it) {
+            int o = it * kProbeUnroll + (tid >> 6);
+            asm volatile("" : "+v"(o));
+#pragma unroll
+            for (int u = 0; u < kProbeUnroll; ++u) {
+                const uint4 v = w[lane + 64 * ((o + u) & 31)];
+                x += (v.x ^ v.y) + (v.z ^ v.w);
+            }
+        }
+        if (x == 0x12345678u) out[blockIdx.x * kProbeLdsThreads + tid] = 1.0f;
+    } else {
+        const pk_bf16x8 a = {(__bf16)1e-3f, (__bf16)2e-3f, (__bf16)3e-3f, (__bf16)4e-3f,
+                             (__bf16)5e-3f, (__bf16)6e-3f, (__bf16)7e-3f, (__bf16)8e-3f};
+        pk_f32x16 acc = {};
+        const __bf16 *row = tile + (lane & 31) * kProbeLdsLd + 8 * (lane >> 5);
+        for (int it = 0; it < iters; ++it) {
+            if constexpr (KIND == NQS_PROBE_MFMA_BF16_32_LDS_JIT) {
+                int o = it * kProbeUnroll;
+                asm volatile("" : "+v"(o));
+#pragma unroll
+                for (int u = 0; u < kProbeUnroll; ++u) {
+                    const pk_bf16x8 b = *reinterpret_cast<const pk_bf16x8 *>(row + 16 * ((o + u) & 31));
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+                }
+            } else if constexpr (KIND == NQS_PROBE_MFMA_BF16_32_LDS) {
+                int o = it * kProbeUnroll;
+                asm volatile("" : "+v"(o));
+                pk_bf16x8 b[kProbeUnroll];
+                b[0] = *reinterpret_cast<const pk_bf16x8 *>(row + 16 * (o & 31));
+                b[1] = *reinterpret_cast<const pk_bf16x8 *>(row + 16 * ((o + 1) & 31));
+#pragma unroll
+                for (int u = 0; u < kProbeUnroll; ++u) {
+                    if (u + 2 < kProbeUnroll) b[u + 2] = *reinterpret_cast<const pk_bf16x8 *>(row + 16 * ((o + u + 2) & 31));
+                    __builtin_amdgcn_sched_barrier(0);   // keep each read two products ahead of its use
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[u], acc, 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < kProbeUnroll; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, a, acc, 0, 0, 0);
+            }
+        }
+        s = acc[0] + acc[15];
+    }
+    if (s == -1.0f) out[blockIdx.x * kProbeLdsThreads + tid] = s;
+}
+
 __global__ void __launch_bounds__(kProbeThreads) probe_read_kernel(const float4 *__restrict__ src, int64_t n4,
                                                                    float *__restrict__ out)
 {
@@ -137,7 +206,7 @@ extern "C" nqs_status nqs_probe_rate(int32_t kind, int64_t size, const void *src
 {
     if (!work) return set_error(NQS_EINVAL, "NULL work");
     const bool compute = (kind >= NQS_PROBE_FMA_F32 && kind <= NQS_PROBE_MFMA_F64) ||
-                         (kind >= NQS_PROBE_MUL_F32 && kind <= NQS_PROBE_FMA_F32_DEP);
+                         (kind >= NQS_PROBE_MUL_F32 && kind <= NQS_PROBE_MFMA_BF16_32_LDS_JIT);
     const bool memory = kind == NQS_PROBE_HBM_READ || kind == NQS_PROBE_HBM_COPY;
     if (!compute && !memory) return set_error(NQS_EINVAL, "unknown probe kind");
     if (compute && (size < 1 || size > (1 << 24))) return set_error(NQS_EINVAL, "iterations must be in [1, 2^24]");
@@ -196,6 +265,26 @@ extern "C" nqs_status nqs_probe_rate(int32_t kind, int64_t size, const void *src
             *work = (double)b * kProbeThreads * per * 2;
             break;
         }
+        case NQS_PROBE_LDS_READ:
+            hipLaunchKernelGGL(probe_lds_kernel<NQS_PROBE_LDS_READ>, dim3(device_cus()), dim3(kProbeLdsThreads), 0, s,
+                               o, it);
+            *work = (double)device_cus() * kProbeLdsThreads * per * 16;
+            break;
+        case NQS_PROBE_MFMA_BF16_32:
+            hipLaunchKernelGGL(probe_lds_kernel<NQS_PROBE_MFMA_BF16_32>, dim3(device_cus()), dim3(kProbeLdsThreads), 0,
+                               s, o, it);
+            *work = (double)device_cus() * (kProbeLdsThreads / 64) * per * (2.0 * 32 * 32 * 16);
+            break;
+        case NQS_PROBE_MFMA_BF16_32_LDS:
+            hipLaunchKernelGGL(probe_lds_kernel<NQS_PROBE_MFMA_BF16_32_LDS>, dim3(device_cus()),
+                               dim3(kProbeLdsThreads), 0, s, o, it);
+            *work = (double)device_cus() * (kProbeLdsThreads / 64) * per * (2.0 * 32 * 32 * 16);
+            break;
+        case NQS_PROBE_MFMA_BF16_32_LDS_JIT:
+            hipLaunchKernelGGL(probe_lds_kernel<NQS_PROBE_MFMA_BF16_32_LDS_JIT>, dim3(device_cus()),
+                               dim3(kProbeLdsThreads), 0, s, o, it);
+            *work = (double)device_cus() * (kProbeLdsThreads / 64) * per * (2.0 * 32 * 32 * 16);
+            break;
         case NQS_PROBE_MFMA_BF16_K16:
             hipLaunchKernelGGL(probe_mfma_kernel<NQS_PROBE_MFMA_BF16_K16>, dim3(blocks), dim3(kProbeThreads), 0, s, o, it);
             *work = threads / 64 * per * 4 * (2.0 * 16 * 16 * 16);

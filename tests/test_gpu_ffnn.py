@@ -249,7 +249,8 @@ def test_register_path_replay(nqs, dtype, move, L, widths, C):
 
 @pytest.mark.parametrize("dtype,kind,dim,L,widths,n_s", [("bf16", "tfim", 2, 6, (144, 72), 41),
                                                          ("f16", "heisenberg", 2, 6, (130, 40), 37),
-                                                         ("bf16", "heisenberg", 1, 16, (256, 250), 10)])
+                                                         ("bf16", "heisenberg", 1, 16, (256, 250), 10),
+                                                         ("bf16", "heisenberg", 2, 4, (480, 96), 20)])
 def test_register_path_local_energy(nqs, dtype, kind, dim, L, widths, n_s):
     n = L if dim == 1 else L * L
     marshall = kind == "heisenberg"
