@@ -364,6 +364,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
 // ---------------------------------------------------------------------------
 constexpr int kElocRows = 32;                        // rows per pass: one 32 x 32 tile per wave
 constexpr int kElocStage = kElocRows / kRegWaves;    // rows each wave stages per pass
+constexpr int kElocPre = 1;                          // spins of the next group each thread prefetches
 
 template <typename T>
 __host__ __device__ inline size_t reg_eloc_lds_bytes(int N, int KE, int m2p, int G)
@@ -374,29 +375,31 @@ __host__ __device__ inline size_t reg_eloc_lds_bytes(int N, int KE, int m2p, int
     b += sizeof(T) * (size_t)N * K;                     // W1 columns
     b += sizeof(T) * 2 * (size_t)kElocRows * ldh;       // h1 rows of two passes
     b += sizeof(float) * (size_t)G * K;                 // z1 of the group's samples
+    b += sizeof(float) * K;                             // b1
     b += sizeof(float) * m2p;                           // b2
     b += sizeof(float) * 2 * kRegWaves * kElocRows;     // partial sums of two passes
     b += sizeof(float) * (size_t)G * N;                 // spins
-    b += (sizeof(int) + 2 * sizeof(float)) * maxrows;   // rows: packed (i, j, sample), coefficient, f
-    b += sizeof(double) * G + sizeof(int) * (2 * G + 2) + 32;
+    b += sizeof(int) * 2 * (size_t)N;                   // candidate table (flips and bonds)
+    b += (sizeof(int) + 3 * sizeof(float)) * maxrows;   // rows: packed (i, j, sample), coefficient, g, f
+    b += sizeof(double) * G + sizeof(int) * G + 32;
     return b;
 }
 
 // row code: (i + 1) | (j + 1) << 13 | s << 26, i = j = -1 for the sample itself
 __device__ __forceinline__ int eloc_row_code(int i, int j, int s) { return (i + 1) | ((j + 1) << 13) | (s << 26); }
 
-// h1 = ReLU(z1 + g (W1[:, i] - W1[:, j])) of row `row` (clamped into the group's rows), hidden units
-// 8c .. 8c + 7, c = min(lane, nch - 1) (lanes past the row's chunks repeat the last one), into Hs row lr.
-// W1l: [N][K] in LDS; zs: [G][K].
+// h1 = ReLU(z1 + g (W1[:, i] - W1[:, j])) of row `row` (g = -2 s_i, 0 for the sample's own row; the W1[:, j]
+// term only for an exchange), hidden units 8c .. 8c + 7, c = min(lane, nch - 1) (lanes past the row's chunks
+// repeat the last one), into Hs row lr.  W1l: [N][K] in LDS; zs: [G][K].
 template <typename T>
-__device__ __forceinline__ void eloc_stage_row(const T *W1l, const int *rcode, const float *sp, const float *zs,
-                                               T *Hs, int ldh, int N, int K, int nch, int row, int lr, int lane)
+__device__ __forceinline__ void eloc_stage_row(const T *W1l, const int *rcode, const float *rg, const float *zs,
+                                               T *Hs, int ldh, int K, int nch, int row, int lr, int lane)
 {
     typedef typename Mc<T>::frag frag;
     const int code = __builtin_amdgcn_readfirstlane(rcode[row]);   // uniform over the wave
+    const float g = rg[row];
     const int i = (code & 0x1FFF) - 1, j = ((code >> 13) & 0x1FFF) - 1, s = code >> 26;
     const int ic = i >= 0 ? i : 0, jc = j >= 0 ? j : 0;
-    const float g = (i >= 0 ? -2.0f : 0.0f) * sp[s * N + ic];
     const float jm = j >= 0 ? 1.0f : 0.0f;
     const int c = lane < nch ? lane : nch - 1;
     const frag wi = *reinterpret_cast<const frag *>(W1l + ic * K + 8 * c);
@@ -422,7 +425,7 @@ __device__ __forceinline__ void eloc_logcosh4(const mc_floatx16 &acc, int q, flo
     for (int r = 0; r < 4; ++r) {
         const float v = fabsf(acc[4 * q + r] + bb[r]);
         abs_sum += v;
-        prod *= 1.0f + __expf(-2.0f * v);
+        prod = fmaf(prod, __builtin_amdgcn_exp2f(v * -2.8853900817779268f), prod);   // e^-2v = 2^(-2 log2(e) v)
     }
 }
 
@@ -432,6 +435,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
     typedef typename Mc<T>::frag frag;
     static_assert(KE >= kElocStage, "one staged row every KE / kElocStage fragments");
     constexpr int K = 16 * KE;
+    constexpr int NT = kRegThreads, NWV = kRegWaves;
     extern __shared__ __align__(16) unsigned char smem[];
     const FfnnDev &net = A.net;
     const int N = net.widths[0], m1p = net.m1p, m2p = net.m2p, m2 = net.widths[2];
@@ -442,44 +446,41 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
     T *W1l = reinterpret_cast<T *>(smem);              // [N][K]
     T *Hs = W1l + (size_t)N * K;                       // [2][kElocRows][ldh]
     float *zs = reinterpret_cast<float *>(Hs + 2 * (size_t)kElocRows * ldh);   // [G][K]
-    float *b2s = zs + (size_t)G * K;
+    float *b1s = zs + (size_t)G * K;                   // [K]
+    float *b2s = b1s + K;                              // [m2p]
     float *part = b2s + m2p;                           // [2][kRegWaves][kElocRows]
     float *sp = part + 2 * kRegWaves * kElocRows;      // [G][N]
-    int *rcode = reinterpret_cast<int *>(sp + (size_t)G * N);
+    int *ctab = reinterpret_cast<int *>(sp + (size_t)G * N);   // [2N]
+    int *rcode = ctab + 2 * N;                         // [maxrows]
     float *rc = reinterpret_cast<float *>(rcode + maxrows);
-    float *fr = rc + maxrows;
+    float *rg = rc + maxrows;
+    float *fr = rg + maxrows;
     double *diag = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(fr + maxrows) + 7) & ~(uintptr_t)7);
-    int *rbase = reinterpret_cast<int *>(diag + G);    // [G + 1]
-    int *rcnt = rbase + G + 1;                         // [G]
+    int *rcnt = reinterpret_cast<int *>(diag + G);     // [G]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
     const int lr = lane & 31, lh = lane >> 5;
-    const bool live = __builtin_amdgcn_readfirstlane(wave) * 32 < m2;   // this wave owns real outputs (uniform)
+    const bool live = wave_u * 32 < m2;                // this wave owns real outputs
+    const bool late_phase = (wave_u >> 2) & 1;         // the second wave on a SIMD runs its pass shifted
     frag a[KE];
     reg_load_w2<T, KE>(reinterpret_cast<const T *>(A.W2), m1p, m2p, a);
     {
         const T *src = reinterpret_cast<const T *>(A.W1t);
-        for (int k = tid; k < N * nch; k += kRegThreads) {
+        for (int k = tid; k < N * nch; k += NT) {
             const int i = k / nch, c = k % nch;
             *reinterpret_cast<frag *>(W1l + i * K + 8 * c) = *reinterpret_cast<const frag *>(src + (size_t)i * m1p + 8 * c);
         }
     }
-    for (int k = tid; k < m2p; k += kRegThreads) b2s[k] = net.b2p[k];
+    for (int k = tid; k < K; k += NT) b1s[k] = net.b1p[k];
+    for (int k = tid; k < m2p; k += NT) b2s[k] = net.b2p[k];
     const int nb = A.dim == 1 ? (A.pbc ? A.L : A.L - 1) : 2 * A.L * A.L;   // candidate bonds (2D: 2 per site)
     const int ncand = A.kind == NQS_TFIM ? N : 0;
     const int nloop = ncand > nb ? ncand : nb;
-
-    // candidate c of a sample: a flip (TFIM) and / or a bond; returns whether it gives a row
-    auto candidate = [&](const float *ss, int c, int &i, int &j, float &coef, double &dg) {
-        bool take = false;
-        i = -1;
-        j = -1;
-        coef = 0.0f;
-        if (c < ncand) {
-            i = c;
-            take = true;
-            coef = (float)A.h * ((A.marshall && on_sub_a(A.dim, A.L, i)) ? -1.0f : 1.0f);
-        }
+    // candidate table: bond c as (bi + 1) | (bj + 1) << 13 | sign flip of the Marshall rule << 26 (0: no bond),
+    // and the Marshall sign of flipping site c << 27
+    for (int c = tid; c < nloop; c += NT) {
+        int t = 0;
         if (c < nb) {
             int bi, bj;
             bool valid = true;
@@ -497,15 +498,34 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
                     bj = x * A.L + (y + 1) % A.L;
                 }
             }
-            if (valid) {
-                dg += A.J * (double)(ss[bi] * ss[bj]);
-                if (A.kind == NQS_HEISENBERG && ss[bi] != ss[bj]) {
-                    i = bi;
-                    j = bj;
-                    take = true;
-                    const bool flip = A.marshall && (on_sub_a(A.dim, A.L, bi) != on_sub_a(A.dim, A.L, bj));
-                    coef = 2.0f * (float)A.J * (flip ? -1.0f : 1.0f);
-                }
+            const bool flip = A.marshall && (on_sub_a(A.dim, A.L, bi) != on_sub_a(A.dim, A.L, bj));
+            if (valid) t = (bi + 1) | ((bj + 1) << 13) | ((flip ? 1 : 0) << 26);
+        }
+        if (c < ncand && A.marshall && on_sub_a(A.dim, A.L, c)) t |= 1 << 27;
+        ctab[c] = t;
+    }
+
+    // candidate c of a sample: a flip (TFIM) and / or a bond; returns whether it gives a row
+    auto candidate = [&](const float *ss, int c, int &i, int &j, float &coef, double &dg) {
+        const int t = ctab[c];
+        bool take = false;
+        i = -1;
+        j = -1;
+        coef = 0.0f;
+        if (c < ncand) {
+            i = c;
+            take = true;
+            coef = (float)A.h * (((t >> 27) & 1) ? -1.0f : 1.0f);
+        }
+        const int bi = (t & 0x1FFF) - 1;
+        if (bi >= 0) {
+            const int bj = ((t >> 13) & 0x1FFF) - 1;
+            dg += A.J * (double)(ss[bi] * ss[bj]);
+            if (A.kind == NQS_HEISENBERG && ss[bi] != ss[bj]) {
+                i = bi;
+                j = bj;
+                take = true;
+                coef = 2.0f * (float)A.J * (((t >> 26) & 1) ? -1.0f : 1.0f);
             }
         }
         return take;
@@ -528,16 +548,31 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
     };
     const float4 *b2v = reinterpret_cast<const float4 *>(b2s + wave * 32 + 4 * lh);   // outputs 8q + 4 lh + 0..3
 
+    // spins of a group: the first directly, each later one from the registers loaded during the previous group
+    int8_t pre[kElocPre];
+    auto prefetch = [&](int64_t gs, int ngs) {
+#pragma unroll
+        for (int m = 0; m < kElocPre; ++m) {
+            const int k = tid + m * NT;
+            pre[m] = (k < G * N && k / N < ngs) ? A.samples[(gs + k / N) * N + k % N] : (int8_t)1;
+        }
+    };
+    bool have_pre = false;
     for (int64_t g0 = (int64_t)blockIdx.x * G; g0 < A.n; g0 += (int64_t)gridDim.x * G) {
         const int ns = (int)min<int64_t>(G, A.n - g0);
-        __syncthreads();   // the previous group's rows and energies are consumed (and W1, b2 are in place)
-        for (int k = tid; k < G * N; k += kRegThreads) {
-            const int s = k / N, i = k % N;
-            sp[k] = s < ns ? (float)A.samples[(g0 + s) * N + i] : 1.0f;
+        __syncthreads();   // the previous group's rows and energies are consumed (and the tables are in place)
+        for (int k = tid; k < G * N; k += NT) {
+            const int s = k / N, i = k % N, m = k / NT;
+            sp[k] = have_pre && m < kElocPre ? (float)pre[m] : (s < ns ? (float)A.samples[(g0 + s) * N + i] : 1.0f);
         }
         __syncthreads();
+        {
+            const int64_t gn = g0 + (int64_t)gridDim.x * G;
+            have_pre = gn < A.n;
+            if (have_pre) prefetch(gn, (int)min<int64_t>(G, A.n - gn));
+        }
         // z1 = W1 s + b1: task (sample, chunk) per lane pair, lane l + 32 h sums the sites of half h
-        for (int q = wave * 32 + lr; q < G * nch; q += kRegWaves * 32) {
+        for (int q = wave * 32 + lr; q < G * nch; q += NWV * 32) {
             const int s = q / nch, c = q % nch;
             const float *ss = sp + s * N;
             float z[8];
@@ -554,10 +589,12 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
 #pragma unroll
             for (int e = 0; e < 8; ++e) z[e] += __shfl_xor(z[e], 32, 64);
             if (lh == 0) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) z[e] += net.b1p[8 * c + e];
-                *reinterpret_cast<float4 *>(zs + s * K + 8 * c) = make_float4(z[0], z[1], z[2], z[3]);
-                *reinterpret_cast<float4 *>(zs + s * K + 8 * c + 4) = make_float4(z[4], z[5], z[6], z[7]);
+                const float4 c0 = *reinterpret_cast<const float4 *>(b1s + 8 * c);
+                const float4 c1 = *reinterpret_cast<const float4 *>(b1s + 8 * c + 4);
+                *reinterpret_cast<float4 *>(zs + s * K + 8 * c) =
+                    make_float4(z[0] + c0.x, z[1] + c0.y, z[2] + c0.z, z[3] + c0.w);
+                *reinterpret_cast<float4 *>(zs + s * K + 8 * c + 4) =
+                    make_float4(z[4] + c1.x, z[5] + c1.y, z[6] + c1.z, z[7] + c1.w);
             }
         }
         // wave s: its sample's row count and diagonal part
@@ -578,22 +615,19 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
             }
         }
         __syncthreads();
-        if (tid == 0) {
-            int r = 0;
-            for (int s = 0; s < ns; ++s) {
-                rbase[s] = r;
-                r += 1 + rcnt[s];
-            }
-            rbase[ns] = r;
+        // the group's rows, sample after sample (every thread forms the offsets from the counts)
+        int nrows = 0, r0 = 0;
+        for (int s = 0; s < ns; ++s) {
+            if (s == wave) r0 = nrows;
+            nrows += 1 + rcnt[s];
         }
-        __syncthreads();
         // wave s: the rows of its sample, in candidate order after the sample's own row
         if (wave < ns) {
             const float *ss = sp + wave * N;
-            const int r0 = rbase[wave];
             if (lane == 0) {
                 rcode[r0] = eloc_row_code(-1, -1, wave);
                 rc[r0] = 0.0f;
+                rg[r0] = 0.0f;
             }
             int pos0 = r0 + 1;
             double unused = 0.0;
@@ -606,95 +640,75 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
                     const int pos = pos0 + __popcll(bal & ((1ull << lane) - 1ull));
                     rcode[pos] = eloc_row_code(i, j, wave);
                     rc[pos] = coef;
+                    rg[pos] = -2.0f * ss[i];
                 }
                 pos0 += __popcll(bal);
             }
         }
         __syncthreads();
-        const int nrows = rbase[ns];
         const int npass = (nrows + kElocRows - 1) / kElocRows;
-        // prologue: pass 0 into buffer 0
+        // wave w stages rows w kElocStage .. w kElocStage + kElocStage - 1 of pass q into buffer q & 1 (rows
+        // past the group's end are clamped copies that nothing reads)
+        auto stage_pass = [&](int q) {
+            T *Hq = Hs + (size_t)(q & 1) * kElocRows * ldh;
 #pragma unroll
-        for (int rr = 0; rr < kElocStage; ++rr) {
-            const int r = wave * kElocStage + rr;
-            eloc_stage_row<T>(W1l, rcode, sp, zs, Hs, ldh, N, K, nch, min(r, nrows - 1), r, lane);
-        }
+            for (int rr = 0; rr < kElocStage; ++rr) {
+                const int r = wave * kElocStage + rr;
+                eloc_stage_row<T>(W1l, rcode, rg, zs, Hq, ldh, K, nch, min(q * kElocRows + r, nrows - 1), r, lane);
+            }
+        };
+        stage_pass(0);
         __syncthreads();
-        // one pass: pass p's products (LIVE waves) with pass p + 1 staged in between (the last pass stages
-        // clamped rows that nothing reads), each B fragment read two products ahead of its use, the order
-        // pinned against the scheduler.  kLate: pass p - 1's log-cosh partial is also taken in between (from
-        // accp; a zero tile at p = 0, not written); otherwise (wide layers, where the second accumulator would
-        // not fit in registers) pass p's own partial follows its products.
-        constexpr bool kLate = KE <= 25;
-        constexpr int kLag = kLate ? 2 : 1;              // a pass's row sums are taken kLag passes later
-        mc_floatx16 acc, accp;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) accp[r] = 0.0f;
-        auto pass = [&](int p, auto live_c) {
-            constexpr bool LIVE = decltype(live_c)::value;
+        // one pass of a multiplying wave: its 32 outputs for the 32 rows of pass p, each B fragment read two
+        // products ahead of its use (the order pinned against the scheduler), with its kElocStage rows of pass
+        // p + 1 staged in between the products, then the tile's log-cosh partial.  The two waves that share a
+        // SIMD (w and w + 4) place their staging slots half a period apart (PH), so that one of them issues
+        // products while the other stages.
+        auto pass = [&](int p, auto ph_c) {
+            constexpr bool PH = decltype(ph_c)::value;
+            constexpr int kStep = KE / kElocStage;           // staging slots every kStep fragments
+            constexpr int kStageAt = PH ? kStep / 2 : 0;     // first staging slot
             const T *Hc = Hs + (size_t)(p & 1) * kElocRows * ldh + lr * ldh + 8 * lh;
             T *Hn = Hs + (size_t)((p + 1) & 1) * kElocRows * ldh;
             const int nbase = (p + 1) * kElocRows;
-            constexpr int kStep = KE / kElocStage;       // a row staged at kf = 0, kStep, 2 kStep, 3 kStep
-            float abs_sum = 0.0f, prod = 1.0f;
-            frag b[3];
-            if constexpr (LIVE) {
+            mc_floatx16 acc;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-                b[0] = *reinterpret_cast<const frag *>(Hc);
-                b[1] = *reinterpret_cast<const frag *>(Hc + 16);
-            }
+            for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+            frag b[3];
+            b[0] = *reinterpret_cast<const frag *>(Hc);
+            b[1] = *reinterpret_cast<const frag *>(Hc + 16);
 #pragma unroll
             for (int kf = 0; kf < KE; ++kf) {
-                if constexpr (LIVE) {
-                    if (kf + 2 < KE) b[(kf + 2) % 3] = *reinterpret_cast<const frag *>(Hc + (kf + 2) * 16);
-                    __builtin_amdgcn_sched_barrier(0);
-                    acc = Mc<T>::mma(a[kf], b[kf % 3], acc);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                if (kf % kStep == 0 && kf / kStep < kElocStage) {
-                    const int r = wave * kElocStage + kf / kStep;
-                    eloc_stage_row<T>(W1l, rcode, sp, zs, Hn, ldh, N, K, nch, min(nbase + r, nrows - 1), r, lane);
-                }
-                if constexpr (LIVE && kLate) {
-                    if (kf % kStep == kStep / 2 && kf / kStep < 4)
-                        eloc_logcosh4(accp, kf / kStep, b2v[2 * (kf / kStep)], abs_sum, prod);
+                if (kf + 2 < KE) b[(kf + 2) % 3] = *reinterpret_cast<const frag *>(Hc + (kf + 2) * 16);
+                __builtin_amdgcn_sched_barrier(0);
+                acc = Mc<T>::mma(a[kf], b[kf % 3], acc);
+                __builtin_amdgcn_sched_barrier(0);
+                if (kf >= kStageAt && (kf - kStageAt) % kStep == 0 && (kf - kStageAt) / kStep < kElocStage) {
+                    const int r = wave * kElocStage + (kf - kStageAt) / kStep;
+                    eloc_stage_row<T>(W1l, rcode, rg, zs, Hn, ldh, K, nch, min(nbase + r, nrows - 1), r, lane);
                 }
             }
-            if constexpr (LIVE && kLate) {
-                if (p > 0) finish_tile(abs_sum, prod, p - 1);
-                accp = acc;
-            } else if constexpr (LIVE) {
+            float abs_sum = 0.0f, prod = 1.0f;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) eloc_logcosh4(acc, q, b2v[2 * q], abs_sum, prod);
-                finish_tile(abs_sum, prod, p);
-            }
+            for (int q = 0; q < 4; ++q) eloc_logcosh4(acc, q, b2v[2 * q], abs_sum, prod);
+            finish_tile(abs_sum, prod, p);
         };
+        constexpr bool kPhase = KE <= 26;                // wider layers: the shifted copy would spill registers
         for (int p = 0; p < npass; ++p) {
-            if (p >= kLag) row_sums(p - kLag, nrows);    // that pass's partials were written before the last barrier
-            if (live) pass(p, std::true_type{});
+            if (p >= 1) row_sums(p - 1, nrows);          // its partials were written before the last barrier
+            if (!live) stage_pass(p + 1);
+            else if (kPhase && late_phase) pass(p, std::true_type{});
             else pass(p, std::false_type{});
-            __syncthreads();
-        }
-        // the partials still due (kLate: the last pass's), then the row sums still due
-        if constexpr (kLate) {
-            if (live) {
-                float abs_sum = 0.0f, prod = 1.0f;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) eloc_logcosh4(accp, q, b2v[2 * q], abs_sum, prod);
-                finish_tile(abs_sum, prod, npass - 1);
-            }
-            if (npass >= 2) row_sums(npass - 2, nrows);
             __syncthreads();
         }
         row_sums(npass - 1, nrows);
         __syncthreads();
         // wave s sums sample s:  eps = diag + sum_rows coef * exp(f_row - f_sample)   (FP64)
         if (wave < ns) {
-            const int s = wave, rb0 = rbase[s], rend = rbase[s + 1];
-            const float f0 = fr[rb0];
+            const int s = wave, rend = r0 + 1 + rcnt[s];
+            const float f0 = fr[r0];
             double off = 0.0;
-            for (int r = rb0 + 1 + lane; r < rend; r += 64) off += (double)rc[r] * exp((double)(fr[r] - f0));
+            for (int r = r0 + 1 + lane; r < rend; r += 64) off += (double)rc[r] * exp((double)(fr[r] - f0));
             off = group_sum<64>(off);
             if (lane == 0) A.eloc[g0 + s] = diag[s] + off;
         }
