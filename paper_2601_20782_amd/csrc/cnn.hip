@@ -400,13 +400,13 @@ __global__ void __launch_bounds__(kCnnThreads) cnn_eloc_tfim_kernel(CnnDev net, 
 // proposed configurations is one batch: each convolution is a product of the
 // [B*S rows][9 F] im2col matrix (gathered from LDS, the input of the
 // convolution stored in the copy's format) with the [9 F][F] weights, in
-// 16 x 16 tiles (v_mfma_f32_16x16x16_bf16 / _f16 with 16 channels of one
-// offset per step, or v_mfma_f32_16x16x4_f32), FP32 accumulation; layer
+// 16 x 16 tiles (v_mfma_f32_16x16x32_bf16 / _f16, 32 of the 9 F products per
+// step, or v_mfma_f32_16x16x4_f32), FP32 accumulation; layer
 // norms, GELU, biases and the residual stream stay FP32 as in the one-chain
 // kernel.  Only the order of the FP32 sums differs from it.
 
-typedef short cnn_s16x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 cnn_h16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 cnn_bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 cnn_h16x8 __attribute__((ext_vector_type(8)));
 typedef float cnn_f32x4 __attribute__((ext_vector_type(4)));
 
 template <int DT> struct CnnMcT;
@@ -444,56 +444,92 @@ __host__ __device__ inline size_t cnn_mc_lds_bytes(int B, int S, int F, int esz)
     return b;
 }
 
-// one convolution of the batch: out = in (*) W + bias; GELU + store in the format, or add into h
+// one convolution of the batch: out = in (*) W + bias; GELU + store in the format, or add into h.  The 9 F
+// products of an output are one contraction over the (offset, channel) index kk = k F + c: FP32 takes it 4 at a
+// time (v_mfma_f32_16x16x4_f32, 4 channels of one offset), the 16-bit formats 32 at a time
+// (v_mfma_f32_16x16x32_bf16 / _f16: lane group lk = lane / 16 holds kk = 32 step + 8 lk .. + 7, eight channels
+// of one offset; for F = 16 the last step's second offset is past the ninth and reads zero).
 template <int DT, int F, bool RESID>
 __device__ inline void cnn_mc_conv(const typename CnnMcT<DT>::E *in, const void *wmc, const float *bias, int rows,
                                    int S, int L, typename CnnMcT<DT>::E *out, float *h)
 {
     typedef CnnMcT<DT> M;
     typedef typename M::E E;
+    static_assert(F == 16 || F == 32, "16 or 32 channels");
+    constexpr int kSteps = (9 * F + 31) / 32;             // 32-deep steps of the 16-bit forms
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, la = lane & 15, lk = lane >> 4;
     const E *W = reinterpret_cast<const E *>(wmc);
     for (int mt = wave; mt < rows / 16; mt += kCnnThreads / 64) {
         const int row = mt * 16 + la, b = row / S, s = row - b * S;
-        int nrow[9];
+        if constexpr (DT == kF32) {
+            int nrow[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) nrow[k] = b * S + cnn_nbr(s, k, L);
+            for (int k = 0; k < 9; ++k) nrow[k] = b * S + cnn_nbr(s, k, L);
 #pragma unroll
-        for (int nt = 0; nt < F / 16; ++nt) {
-            cnn_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            const int o = nt * 16 + la;
+            for (int nt = 0; nt < F / 16; ++nt) {
+                cnn_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                const int o = nt * 16 + la;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
+                for (int k = 0; k < 9; ++k) {
 #pragma unroll
-                for (int cs = 0; cs < F / M::KS; ++cs) {
-                    if constexpr (DT == kF32) {
+                    for (int cs = 0; cs < F / M::KS; ++cs) {
                         const int c = cs * 4 + lk;
                         const float a = in[(size_t)nrow[k] * F + c];
                         const float w = W[((size_t)k * F + o) * F + c];
                         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w, acc, 0, 0, 0);
-                    } else {
-                        const int c = cs * 16 + 4 * lk;
-                        const uint2 av = *reinterpret_cast<const uint2 *>(in + (size_t)nrow[k] * F + c);
-                        const uint2 wv = *reinterpret_cast<const uint2 *>(W + ((size_t)k * F + o) * F + c);
-                        if constexpr (DT == kBF16) {
-                            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(cnn_s16x4, av),
-                                                                             __builtin_bit_cast(cnn_s16x4, wv), acc,
-                                                                             0, 0, 0);
-                        } else {
-                            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(cnn_h16x4, av),
-                                                                        __builtin_bit_cast(cnn_h16x4, wv), acc, 0, 0,
-                                                                        0);
-                        }
                     }
                 }
-            }
-            // D[i][j] of a 16 x 16 block: j = lane % 16, i = 4 (lane / 16) + register
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int orow = mt * 16 + 4 * lk + r;
-                const float v = acc[r] + bias[o];
-                if constexpr (RESID) h[(size_t)orow * F + o] += v;
-                else out[(size_t)orow * F + o] = M::enc(cnn_round(cnn_gelu(v), DT));
+                for (int r = 0; r < 4; ++r) {
+                    const int orow = mt * 16 + 4 * lk + r;
+                    const float v = acc[r] + bias[o];
+                    if constexpr (RESID) h[(size_t)orow * F + o] += v;
+                    else out[(size_t)orow * F + o] = M::enc(cnn_round(cnn_gelu(v), DT));
+                }
+            }
+        } else {
+            // step st: F = 32, offset st, channels 8 lk .. 8 lk + 7; F = 16, offset 2 st + lk / 2, channels
+            // 8 (lk % 2) .. + 7 (offset 9 of the last step is zero)
+            int nrow[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) nrow[k] = b * S + cnn_nbr(s, k, L);
+            const int c = F == 32 ? 8 * lk : 8 * (lk & 1), hi = lk >> 1;
+#pragma unroll
+            for (int nt = 0; nt < F / 16; ++nt) {
+                cnn_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                const int o = nt * 16 + la;
+#pragma unroll
+                for (int st = 0; st < kSteps; ++st) {
+                    int k, nr;
+                    bool ok = true;
+                    if constexpr (F == 32) {
+                        k = st;
+                        nr = nrow[st];
+                    } else {
+                        const int k0 = 2 * st, k1 = 2 * st + 1 < 9 ? 2 * st + 1 : 8;
+                        k = hi ? k1 : k0;
+                        nr = hi ? nrow[k1] : nrow[k0];
+                        ok = 2 * st + 1 < 9 || !hi;
+                    }
+                    uint4 av = *reinterpret_cast<const uint4 *>(in + (size_t)nr * F + c);
+                    const uint4 wv = *reinterpret_cast<const uint4 *>(W + ((size_t)k * F + o) * F + c);
+                    if (!ok) av = make_uint4(0u, 0u, 0u, 0u);
+                    if constexpr (DT == kBF16) {
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(cnn_bf16x8, av),
+                                                                      __builtin_bit_cast(cnn_bf16x8, wv), acc, 0, 0, 0);
+                    } else {
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(cnn_h16x8, av),
+                                                                     __builtin_bit_cast(cnn_h16x8, wv), acc, 0, 0, 0);
+                    }
+                }
+                // D[i][j] of a 16 x 16 block: j = lane % 16, i = 4 (lane / 16) + register
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int orow = mt * 16 + 4 * lk + r;
+                    const float v = acc[r] + bias[o];
+                    if constexpr (RESID) h[(size_t)orow * F + o] += v;
+                    else out[(size_t)orow * F + o] = M::enc(cnn_round(cnn_gelu(v), DT));
+                }
             }
         }
     }
