@@ -1072,6 +1072,8 @@ def run_peaks(a, torch, nqs, workloads):
     got["hbm_copy_gbs"] = best_rate("hbm_copy", nbytes, x, y) / 1e9
     del x, y
     published = {"fma_f32_tflops": PEAK_FP32_VALU_TFLOPS, "mfma_bf16_16x16x32_tflops": PEAK_BF16_MFMA_TFLOPS,
+                 "mfma_bf16_32x32x16_tflops": PEAK_BF16_MFMA_TFLOPS, "mfma_bf16_32x32x16_lds_tflops": PEAK_BF16_MFMA_TFLOPS,
+                 "mfma_bf16_32x32x16_lds_jit_tflops": PEAK_BF16_MFMA_TFLOPS,
                  "mfma_f32_16x16x4_tflops": 157.3, "mfma_f64_16x16x4_tflops": 78.6, "hbm_read_gbs": 8000.0,
                  "hbm_copy_gbs": 8000.0}
     return {
