@@ -597,14 +597,14 @@ namespace nqs {
 nqs_status ffnn_sample_dispatch(int dtype, int QK, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds,
                                 hipStream_t s);
 nqs_status ffnn_eloc_dispatch(int dtype, int QK, const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s);
-size_t ffnn_reg_sample_lds(int dtype, int N, int m1p, int m2p);
+bool ffnn_reg_sample_launch_bf16(int ke, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds, hipStream_t s);
+bool ffnn_reg_sample_launch_f16(int ke, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds, hipStream_t s);
+size_t ffnn_reg_sample_lds_bf16(int N, int ke, int m2p);
+size_t ffnn_reg_sample_lds_f16(int N, int ke, int m2p);
 bool ffnn_reg_eloc_launch_bf16(int ke, const FfnnElocArgs &A, int G, int blocks, size_t lds, hipStream_t s);
 bool ffnn_reg_eloc_launch_f16(int ke, const FfnnElocArgs &A, int G, int blocks, size_t lds, hipStream_t s);
 size_t ffnn_reg_eloc_lds_bf16(int N, int ke, int m2p, int G);
 size_t ffnn_reg_eloc_lds_f16(int N, int ke, int m2p, int G);
-nqs_status ffnn_reg_sample_dispatch(int dtype, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds,
-                                    hipStream_t s);
-
 // Layer 2 can live in registers (8 waves x 32 output rows) for 16-bit operands
 // with 128 <= m1p <= 512 and m2p <= 256.
 static_assert(kRows == kRegRows, "both samplers take 64 chains per block");
@@ -660,7 +660,8 @@ nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     }
     const FfnnDev &f = m->copies[cfg.dtype].ffnn;
     const int N = f.widths[0];
-    const size_t reg_lds = ffnn_reg_sample_lds(cfg.dtype, N, f.m1p, f.m2p);
+    const int KE = f.n_layers >= 2 ? (f.widths[1] + 15) / 16 : 0;   // 16-wide fragments multiplied
+    const size_t reg_lds = cfg.dtype == NQS_F16 ? ffnn_reg_sample_lds_f16(N, KE, f.m2p) : ffnn_reg_sample_lds_bf16(N, KE, f.m2p);
     const bool use_reg = reg_path(cfg.dtype, f) && reg_lds <= 160 * 1024;
     const size_t lds = use_reg ? reg_lds : sample_lds_bytes(cfg.dtype, N, f.m1p, f.m2p);
     if (lds > 160 * 1024) return set_error(NQS_EUNSUPPORTED, "network too large for the LDS-resident sampler");
@@ -699,7 +700,13 @@ nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     }
     const int QK = (f.m1p + 63) / 64;
     const int64_t blocks = (cfg.n_chains + kRows - 1) / kRows;   // kRows == kRegRows: 64 chains per block
-    if (use_reg) return ffnn_reg_sample_dispatch(cfg.dtype, tr, A, (int)blocks, lds, stream);
+    if (use_reg) {
+        const bool ok = cfg.dtype == NQS_F16 ? ffnn_reg_sample_launch_f16(KE, tr, A, (int)blocks, lds, stream)
+                                             : ffnn_reg_sample_launch_bf16(KE, tr, A, (int)blocks, lds, stream);
+        if (!ok) return set_error(NQS_EUNSUPPORTED, "first hidden width not supported by the register-resident sampler");
+        NQS_HIP_TRY(hipGetLastError());
+        return NQS_OK;
+    }
     return ffnn_sample_dispatch(cfg.dtype, QK, tr, A, (int)blocks, lds, stream);
 }
 
@@ -717,7 +724,7 @@ nqs_status ffnn_local_energy(nqs_model *m, const nqs_ham_desc &ham, const int8_t
     size_t lds;
     // the register-resident kernel: W1 (16 KE columns) in LDS and groups of G samples, the largest G of 8, 4, 2,
     // 1 whose rows the LDS holds (N < 8191 for the packed row codes)
-    const int KE = f.n_layers >= 2 ? (f.widths[1] + 15) / 16 : 0;
+    const int KE = f.n_layers >= 2 ? (f.widths[1] + 15) / 16 : 0;   // 16-wide fragments multiplied
     auto reg_lds_for = [&](int G) {
         return dtype == NQS_F16 ? ffnn_reg_eloc_lds_f16(N, KE, f.m2p, G) : ffnn_reg_eloc_lds_bf16(N, KE, f.m2p, G);
     };

@@ -3,15 +3,16 @@
 //
 // A block of 512 threads (8 waves) keeps W2 resident for its whole life: wave w
 // holds output rows 32w .. 32w+31 of W2 as the A fragments of
-// v_mfma_f32_32x32x16_{bf16,f16} (KF fragments of 8 values per lane, K = 16 per
-// fragment).  The rows to evaluate are staged once per pass into LDS as the B
+// v_mfma_f32_32x32x16_{bf16,f16} (KE = ceil(m1 / 16) fragments of 8 values per
+// lane, K = 16 per fragment; W2's padding columns past m1 are never multiplied).  The rows to evaluate are staged once per pass into LDS as the B
 // operand (h1 rows, one row per matrix column), so the only per-pass traffic is
 // LDS reads of h1; no weight is re-read from L2 inside the loop.  Each wave
 // turns its 32 x 32 tile into per-row partial log-cosh sums over its 32
 // outputs; the partials of the waves are added in wave order.
 //
 // Sampler: 64 chains per block; wave w keeps z1 of chains 8w .. 8w+7 in
-// registers (lane owns hidden units lane + 64 q) and updates it by the rank-1
+// registers (lane c owns hidden units 8c .. 8c + 7, so that a W1 column or an h1
+// row moves in one 16-byte access per lane) and updates it by the rank-1
 // (flip) or rank-2 (exchange) change of an accepted move.  Proposals that
 // change nothing (an exchange of equal spins) are compacted away before the
 // matrix product, so a pass evaluates only the effective proposals.
@@ -105,12 +106,12 @@ __device__ __forceinline__ float reg_tile_logcosh(const typename Mc<T>::frag (&a
 // ---------------------------------------------------------------------------
 template <typename T>
 struct RegSampleLds {
-    static __host__ __device__ size_t bytes(int N, int m1p, int m2p)
+    static __host__ __device__ size_t bytes(int N, int KE, int m2p)
     {
-        const size_t ldh = m1p + hs_pad<T>();
+        const size_t K = 16 * (size_t)KE, ldh = K + hs_pad<T>();
         const int NW = (N + 31) / 32;
         size_t b = 0;
-        b += sizeof(T) * (size_t)N * m1p;                     // W1 columns
+        b += sizeof(T) * (size_t)N * K;                       // W1 columns
         b += sizeof(T) * (size_t)kRegRows * ldh;              // h1 rows
         b += sizeof(float) * m2p;                             // b2
         b += sizeof(float) * kRegWaves * kRegRows;            // partial sums
@@ -124,20 +125,21 @@ struct RegSampleLds {
 // effective ones at slots taken from a shared counter, and after the matrix
 // product decides them and updates their state.  Two barriers per step: after
 // the staging (h1 rows complete) and after the product (partial sums complete).
-template <typename T, int KF, bool TRACE>
+template <typename T, int KE, bool TRACE>
 __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSampleArgs A)
 {
     typedef typename Mc<T>::frag frag;
-    constexpr int QK = KF / 4;                      // hidden units per lane (m1p = 64 QK)
+    constexpr int K = 16 * KE;                      // hidden units multiplied (KE = ceil(m1 / 16) fragments)
+    constexpr int NCH = K / 8;                      // 8-unit chunks: lane c owns units 8c .. 8c + 7
     constexpr int RPW = kRegRows / kRegWaves;       // chains per wave (8)
     extern __shared__ __align__(16) unsigned char smem[];
     const FfnnDev &net = A.net;
     const int N = net.widths[0], m1p = net.m1p, m2p = net.m2p, m2 = net.widths[2];
     const int NW = (N + 31) >> 5;
-    const int ldh = m1p + hs_pad<T>();
+    const int ldh = K + hs_pad<T>();
     const int nwt = (m2p + 31) >> 5;                // waves that own output rows
-    T *W1l = reinterpret_cast<T *>(smem);
-    T *Hs = W1l + (size_t)N * m1p;
+    T *W1l = reinterpret_cast<T *>(smem);           // [N][K]
+    T *Hs = W1l + (size_t)N * K;
     float *b2s = reinterpret_cast<float *>(Hs + (size_t)kRegRows * ldh);
     float *part = b2s + m2p;
     uint32_t *words = reinterpret_cast<uint32_t *>(part + kRegWaves * kRegRows);
@@ -148,12 +150,16 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     const int nvalid = (int)min<int64_t>(kRegRows, A.n_chains - c0);
     const int myrow = wave * RPW + (lane & (RPW - 1));           // the chain of proposal lanes 0..7
     const bool plane = lane < RPW && myrow < nvalid;
+    const int c8 = 8 * (lane < NCH ? lane : NCH - 1);   // this lane's units (lanes past the last chunk repeat it)
 
-    frag a[KF];
-    reg_load_w2<T, KF>(reinterpret_cast<const T *>(A.W2), m1p, m2p, a);
+    frag a[KE];
+    reg_load_w2<T, KE>(reinterpret_cast<const T *>(A.W2), m1p, m2p, a);
     {
         const T *src = reinterpret_cast<const T *>(A.W1t);
-        for (int k = tid; k < N * m1p; k += kRegThreads) W1l[k] = src[k];
+        for (int k = tid; k < N * NCH; k += kRegThreads) {
+            const int i = k / NCH, c = k % NCH;
+            *reinterpret_cast<frag *>(W1l + i * K + 8 * c) = *reinterpret_cast<const frag *>(src + (size_t)i * m1p + 8 * c);
+        }
         for (int k = tid; k < kRegRows * ldh; k += kRegThreads) Hs[k] = Mc<T>::from_f32(0.0f);
         for (int k = tid; k < m2p; k += kRegThreads) b2s[k] = net.b2p[k];
         for (int k = tid; k < kRegRows * NW; k += kRegThreads) {
@@ -170,47 +176,51 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     }
     __syncthreads();
 
-    float z1[RPW][QK];
+    float z1[RPW][8];
     auto refresh_z1 = [&]() {
 #pragma unroll
         for (int r = 0; r < RPW; ++r)
 #pragma unroll
-            for (int q = 0; q < QK; ++q) z1[r][q] = net.b1p[lane + 64 * q];
+            for (int e = 0; e < 8; ++e) z1[r][e] = net.b1p[c8 + e];
         for (int i = 0; i < N; ++i) {
-            float w[QK];
-#pragma unroll
-            for (int q = 0; q < QK; ++q) w[q] = Mc<T>::to_f32(W1l[i * m1p + lane + 64 * q]);
+            const frag w = *reinterpret_cast<const frag *>(W1l + i * K + c8);
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
                 const int row = wave * RPW + r;
                 const float s = ((words[row * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1.0f : -1.0f;
 #pragma unroll
-                for (int q = 0; q < QK; ++q) z1[r][q] = fmaf(w[q], s, z1[r][q]);
+                for (int e = 0; e < 8; ++e) z1[r][e] = fmaf(Mc<T>::to_f32(w[e]), s, z1[r][e]);
             }
         }
     };
     // layer-1 change of flipping i (and j >= 0) where site i holds spin si
-    auto delta_z1 = [&](int i, int j, float si, float (&dz)[QK]) {
+    auto delta_z1 = [&](int i, int j, float si, float (&dz)[8]) {
         const float g = -2.0f * si;
+        const frag wi = *reinterpret_cast<const frag *>(W1l + i * K + c8);
+        if (j >= 0) {
+            const frag wj = *reinterpret_cast<const frag *>(W1l + j * K + c8);
 #pragma unroll
-        for (int q = 0; q < QK; ++q) {
-            const int k = lane + 64 * q;
-            float d = Mc<T>::to_f32(W1l[i * m1p + k]);
-            if (j >= 0) d -= Mc<T>::to_f32(W1l[j * m1p + k]);
-            dz[q] = g * d;
+            for (int e = 0; e < 8; ++e) dz[e] = g * (Mc<T>::to_f32(wi[e]) - Mc<T>::to_f32(wj[e]));
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dz[e] = g * Mc<T>::to_f32(wi[e]);
         }
+    };
+    // h1 = ReLU(z + dz) of one row, this lane's 8 units
+    auto store_row = [&](int row, const float (&z)[8], const float (&dz)[8]) {
+        frag h;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) h[e] = Mc<T>::from_f32(fmaxf(z[e] + dz[e], 0.0f));
+        *reinterpret_cast<frag *>(Hs + row * ldh + c8) = h;
     };
     // log|psi| of this wave's chains from the current z1 (lanes 0..7 return their chain's value)
     auto full_eval = [&]() -> float {
+        const float zero[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const int row = wave * RPW + r;
-#pragma unroll
-            for (int q = 0; q < QK; ++q) Hs[row * ldh + lane + 64 * q] = Mc<T>::from_f32(fmaxf(z1[r][q], 0.0f));
-        }
+        for (int r = 0; r < RPW; ++r) store_row(wave * RPW + r, z1[r], zero);
         __syncthreads();
         for (int t = 0; t < kRegRows / 32; ++t) {
-            const float s = reg_tile_logcosh<T, KF>(a, Hs, ldh, 32 * t, b2s, m2);
+            const float s = reg_tile_logcosh<T, KE>(a, Hs, ldh, 32 * t, b2s, m2);
             if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
         }
         __syncthreads();
@@ -256,17 +266,15 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             if (sl >= 0) {
                 const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
                 const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
-                float dz[QK];
+                float dz[8];
                 delta_z1(i, j, s_i, dz);
-#pragma unroll
-                for (int q = 0; q < QK; ++q)
-                    Hs[sl * ldh + lane + 64 * q] = Mc<T>::from_f32(fmaxf(z1[r][q] + dz[q], 0.0f));
+                store_row(sl, z1[r], dz);
             }
         }
         __syncthreads();
         const int neff = cnt[k & 1];
         for (int t = 0; 32 * t < neff; ++t) {
-            const float s = reg_tile_logcosh<T, KF>(a, Hs, ldh, 32 * t, b2s, m2);
+            const float s = reg_tile_logcosh<T, KE>(a, Hs, ldh, 32 * t, b2s, m2);
             if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
         }
         if (tid == 0) cnt[(k + 1) & 1] = 0;   // read next in step k + 1, after the barrier below
@@ -306,10 +314,10 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             if ((um >> r) & 1ull) {
                 const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
                 const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
-                float dz[QK];
+                float dz[8];
                 delta_z1(i, j, s_i, dz);
 #pragma unroll
-                for (int q = 0; q < QK; ++q) z1[r][q] += dz[q];
+                for (int e = 0; e < 8; ++e) z1[r][e] += dz[e];
             }
         }
         if (++in_sweep == sw) {

@@ -1,0 +1,16 @@
+// Register-resident dense-network sampler kernels with f16 operands.
+#include "ffnn_sample_inst.h"
+
+namespace nqs {
+
+bool ffnn_reg_sample_launch_f16(int ke, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds, hipStream_t s)
+{
+    return launch_sample_ke<_Float16, 32>(ke, trace, A, blocks, lds, s);
+}
+
+size_t ffnn_reg_sample_lds_f16(int N, int ke, int m2p)
+{
+    return RegSampleLds<_Float16>::bytes(N, ke, m2p);
+}
+
+}  // namespace nqs
