@@ -398,7 +398,8 @@ __device__ __forceinline__ int eloc_row_code(int i, int j, int s) { return (i + 
 
 // h1 = ReLU(z1 + g (W1[:, i] - W1[:, j])) of row `row` (g = -2 s_i, 0 for the sample's own row; the W1[:, j]
 // term only for an exchange), hidden units 8c .. 8c + 7, c = min(lane, nch - 1) (lanes past the row's chunks
-// repeat the last one), into Hs row lr.  W1l: [N][K] in LDS; zs: [G][K].
+// repeat the last one), into Hs row lr.  W1l: [N][K] in LDS; zs: [G][2][K / 8][4] (units 8c .. 8c + 3 of
+// every chunk, then units 8c + 4 .. 8c + 7, so that the 16-byte reads of consecutive lanes are consecutive).
 template <typename T>
 __device__ __forceinline__ void eloc_stage_row(const T *W1l, const int *rcode, const float *rg, const float *zs,
                                                T *Hs, int ldh, int K, int nch, int row, int lr, int lane)
@@ -412,8 +413,8 @@ __device__ __forceinline__ void eloc_stage_row(const T *W1l, const int *rcode, c
     const int c = lane < nch ? lane : nch - 1;
     const frag wi = *reinterpret_cast<const frag *>(W1l + ic * K + 8 * c);
     const frag wj = *reinterpret_cast<const frag *>(W1l + jc * K + 8 * c);
-    const float4 z0 = *reinterpret_cast<const float4 *>(zs + s * K + 8 * c);
-    const float4 z1 = *reinterpret_cast<const float4 *>(zs + s * K + 8 * c + 4);
+    const float4 z0 = *reinterpret_cast<const float4 *>(zs + s * K + 4 * c);
+    const float4 z1 = *reinterpret_cast<const float4 *>(zs + s * K + K / 2 + 4 * c);
     const float zz[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
     frag h;
 #pragma unroll
@@ -453,7 +454,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
     const int nch = K >> 3;                            // 8-unit chunks of a row
     T *W1l = reinterpret_cast<T *>(smem);              // [N][K]
     T *Hs = W1l + (size_t)N * K;                       // [2][kElocRows][ldh]
-    float *zs = reinterpret_cast<float *>(Hs + 2 * (size_t)kElocRows * ldh);   // [G][K]
+    float *zs = reinterpret_cast<float *>(Hs + 2 * (size_t)kElocRows * ldh);   // [G][2][K / 8][4]
     float *b1s = zs + (size_t)G * K;                   // [K]
     float *b2s = b1s + K;                              // [m2p]
     float *part = b2s + m2p;                           // [2][kRegWaves][kElocRows]
@@ -599,9 +600,9 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
             if (lh == 0) {
                 const float4 c0 = *reinterpret_cast<const float4 *>(b1s + 8 * c);
                 const float4 c1 = *reinterpret_cast<const float4 *>(b1s + 8 * c + 4);
-                *reinterpret_cast<float4 *>(zs + s * K + 8 * c) =
+                *reinterpret_cast<float4 *>(zs + s * K + 4 * c) =
                     make_float4(z[0] + c0.x, z[1] + c0.y, z[2] + c0.z, z[3] + c0.w);
-                *reinterpret_cast<float4 *>(zs + s * K + 8 * c + 4) =
+                *reinterpret_cast<float4 *>(zs + s * K + K / 2 + 4 * c) =
                     make_float4(z[4] + c1.x, z[5] + c1.y, z[6] + c1.z, z[7] + c1.w);
             }
         }
