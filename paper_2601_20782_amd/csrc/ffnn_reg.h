@@ -53,50 +53,53 @@ __device__ __forceinline__ void reg_load_w2(const T *__restrict__ W2, int m1p, i
     }
 }
 
+// Four of the 16 outputs a lane holds of a 32 x 32 tile (registers 4q .. 4q + 3: outputs
+// 8q + 4 (lane / 32) + 0..3 of the wave's 32) into the running |z| sum and product of (1 + e^-2|z|).
+__device__ __forceinline__ void eloc_logcosh4(const mc_floatx16 &acc, int q, float4 b, float &abs_sum, float &prod)
+{
+    const float bb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float v = fabsf(acc[4 * q + r] + bb[r]);
+        abs_sum += v;
+        prod = fmaf(prod, __builtin_amdgcn_exp2f(v * -2.8853900817779268f), prod);   // e^-2v = 2^(-2 log2(e) v)
+    }
+}
+
 // Rows row0 .. row0+31 of Hs (ldh elements per row) through layer 2 and the
-// log-cosh sum over this wave's outputs; lanes 0..31 return the partial of
-// row row0 + lane (other lanes return the same value for their row).
+// log-cosh sum over this wave's 32 outputs; lanes 0..31 return the partial of
+// row row0 + lane (lanes 32..63 the same value).  Each B fragment is read two
+// products ahead of its use, the order pinned against the scheduler.  Outputs
+// past m2 have zero W2 rows and a zero bias, so z2 = 0 exactly and they add
+// log cosh 0 = 0 (the caller skips waves with no real output).
 template <typename T, int KF>
 __device__ __forceinline__ float reg_tile_logcosh(const typename Mc<T>::frag (&a)[KF], const T *Hs, int ldh, int row0,
-                                                  const float *b2s, int m2)
+                                                  const float *b2s)
 {
     typedef typename Mc<T>::frag frag;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 31, lh = lane >> 5;
-    // two accumulators (even / odd fragments), so consecutive matrix-core steps do not wait on each other
-    mc_floatx16 acc, acc1;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        acc[r] = 0.0f;
-        acc1[r] = 0.0f;
-    }
     const T *hrow = Hs + (row0 + lr) * ldh + 8 * lh;
+    mc_floatx16 acc;
 #pragma unroll
-    for (int kf = 0; kf < KF; kf += 2) {
-        const frag b0 = *reinterpret_cast<const frag *>(hrow + kf * 16);
-        acc = Mc<T>::mma(a[kf], b0, acc);
-        if (kf + 1 < KF) {
-            const frag b1 = *reinterpret_cast<const frag *>(hrow + (kf + 1) * 16);
-            acc1 = Mc<T>::mma(a[kf + 1], b1, acc1);
-        }
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    frag b[3];
+    b[0] = *reinterpret_cast<const frag *>(hrow);
+    if (KF > 1) b[1] = *reinterpret_cast<const frag *>(hrow + 16);
+#pragma unroll
+    for (int kf = 0; kf < KF; ++kf) {
+        if (kf + 2 < KF) b[(kf + 2) % 3] = *reinterpret_cast<const frag *>(hrow + (kf + 2) * 16);
+        __builtin_amdgcn_sched_barrier(0);
+        acc = Mc<T>::mma(a[kf], b[kf % 3], acc);
+        __builtin_amdgcn_sched_barrier(0);
     }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] += acc1[r];
     // D[i][j]: i = output (row of W2), j = staged row; lane = j + 32*((i/4)%2), register = i%4 + 4*(i/8)
+    const float4 *bv = reinterpret_cast<const float4 *>(b2s + wave * 32 + 4 * lh);   // outputs 8q + 4 lh + 0..3
     float abs_sum = 0.0f, prod = 1.0f;
-    int cnt = 0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int out = wave * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-        if (out < m2) {
-            const float v = fabsf(acc[r] + b2s[out]);
-            abs_sum += v;
-            prod *= 1.0f + __expf(-2.0f * v);
-            ++cnt;
-        }
-    }
+    for (int q = 0; q < 4; ++q) eloc_logcosh4(acc, q, bv[2 * q], abs_sum, prod);
     // 16 factors in (1, 2]: the product stays below 2^16
-    float s = abs_sum + __logf(prod) - (float)cnt * kLn2f;
+    float s = abs_sum + __logf(prod) - 16.0f * kLn2f;
     s += __shfl_xor(s, 32, 64);
     return s;
 }
@@ -112,7 +115,7 @@ struct RegSampleLds {
         const int NW = (N + 31) / 32;
         size_t b = 0;
         b += sizeof(T) * (size_t)N * K;                       // W1 columns
-        b += sizeof(T) * (size_t)kRegRows * ldh;              // h1 rows
+        b += sizeof(T) * (size_t)(kRegRows + 1) * ldh;        // h1 rows (+1: where ineffective proposals go)
         b += sizeof(float) * m2p;                             // b2
         b += sizeof(float) * kRegWaves * kRegRows;            // partial sums
         b += sizeof(uint32_t) * (size_t)kRegRows * NW;        // spin words
@@ -137,10 +140,10 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     const int N = net.widths[0], m1p = net.m1p, m2p = net.m2p, m2 = net.widths[2];
     const int NW = (N + 31) >> 5;
     const int ldh = K + hs_pad<T>();
-    const int nwt = (m2p + 31) >> 5;                // waves that own output rows
+    const int nwt = (m2 + 31) >> 5;                 // waves that own real outputs
     T *W1l = reinterpret_cast<T *>(smem);           // [N][K]
-    T *Hs = W1l + (size_t)N * K;
-    float *b2s = reinterpret_cast<float *>(Hs + (size_t)kRegRows * ldh);
+    T *Hs = W1l + (size_t)N * K;                    // [kRegRows + 1][ldh]
+    float *b2s = reinterpret_cast<float *>(Hs + (size_t)(kRegRows + 1) * ldh);
     float *part = b2s + m2p;
     uint32_t *words = reinterpret_cast<uint32_t *>(part + kRegWaves * kRegRows);
     int *cnt = reinterpret_cast<int *>(words + kRegRows * NW);   // [2] slots taken in the current / next step
@@ -151,6 +154,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     const int myrow = wave * RPW + (lane & (RPW - 1));           // the chain of proposal lanes 0..7
     const bool plane = lane < RPW && myrow < nvalid;
     const int c8 = 8 * (lane < NCH ? lane : NCH - 1);   // this lane's units (lanes past the last chunk repeat it)
+    const bool live = __builtin_amdgcn_readfirstlane(wave) * 32 < m2;   // this wave owns real outputs
 
     frag a[KE];
     reg_load_w2<T, KE>(reinterpret_cast<const T *>(A.W2), m1p, m2p, a);
@@ -160,7 +164,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             const int i = k / NCH, c = k % NCH;
             *reinterpret_cast<frag *>(W1l + i * K + 8 * c) = *reinterpret_cast<const frag *>(src + (size_t)i * m1p + 8 * c);
         }
-        for (int k = tid; k < kRegRows * ldh; k += kRegThreads) Hs[k] = Mc<T>::from_f32(0.0f);
+        for (int k = tid; k < (kRegRows + 1) * ldh; k += kRegThreads) Hs[k] = Mc<T>::from_f32(0.0f);
         for (int k = tid; k < m2p; k += kRegThreads) b2s[k] = net.b2p[k];
         for (int k = tid; k < kRegRows * NW; k += kRegThreads) {
             const int r = k / NW, w = k % NW;
@@ -193,18 +197,14 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             }
         }
     };
-    // layer-1 change of flipping i (and j >= 0) where site i holds spin si
+    // layer-1 change of flipping i (and j >= 0) where site i holds spin si (no branch: W1[:, max(j, 0)] is read
+    // and weighted by 0 for a flip, which leaves W1[:, i] exact)
     auto delta_z1 = [&](int i, int j, float si, float (&dz)[8]) {
-        const float g = -2.0f * si;
+        const float g = -2.0f * si, jm = j >= 0 ? 1.0f : 0.0f;
         const frag wi = *reinterpret_cast<const frag *>(W1l + i * K + c8);
-        if (j >= 0) {
-            const frag wj = *reinterpret_cast<const frag *>(W1l + j * K + c8);
+        const frag wj = *reinterpret_cast<const frag *>(W1l + (j >= 0 ? j : 0) * K + c8);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) dz[e] = g * (Mc<T>::to_f32(wi[e]) - Mc<T>::to_f32(wj[e]));
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) dz[e] = g * Mc<T>::to_f32(wi[e]);
-        }
+        for (int e = 0; e < 8; ++e) dz[e] = g * fmaf(-jm, Mc<T>::to_f32(wj[e]), Mc<T>::to_f32(wi[e]));
     };
     // h1 = ReLU(z + dz) of one row, this lane's 8 units
     auto store_row = [&](int row, const float (&z)[8], const float (&dz)[8]) {
@@ -219,10 +219,11 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
 #pragma unroll
         for (int r = 0; r < RPW; ++r) store_row(wave * RPW + r, z1[r], zero);
         __syncthreads();
-        for (int t = 0; t < kRegRows / 32; ++t) {
-            const float s = reg_tile_logcosh<T, KE>(a, Hs, ldh, 32 * t, b2s, m2);
-            if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
-        }
+        if (live)
+            for (int t = 0; t < kRegRows / 32; ++t) {
+                const float s = reg_tile_logcosh<T, KE>(a, Hs, ldh, 32 * t, b2s);
+                if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
+            }
         __syncthreads();
         float f = 0.0f;
         for (int w = 0; w < nwt; ++w) f += part[w * kRegRows + myrow];
@@ -259,22 +260,22 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             if (eff) slot = atomicAdd(&cnt[k & 1], 1);
             ub = rb.r2 >> 8;
         }
-        // stage h1 of the effective proposals (rows are wave-uniform)
+        // stage h1 of the effective proposals (rows are wave-uniform); every chain's row is formed and an
+        // ineffective one goes to the spare row kRegRows, so that the code has no branch and the reads of later
+        // chains can be issued before earlier rows are stored
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int sl = __builtin_amdgcn_readlane(slot, r);
-            if (sl >= 0) {
-                const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
-                const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
-                float dz[8];
-                delta_z1(i, j, s_i, dz);
-                store_row(sl, z1[r], dz);
-            }
+            const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
+            const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
+            float dz[8];
+            delta_z1(i, j, s_i, dz);
+            store_row(sl >= 0 ? sl : kRegRows, z1[r], dz);
         }
         __syncthreads();
         const int neff = cnt[k & 1];
-        for (int t = 0; 32 * t < neff; ++t) {
-            const float s = reg_tile_logcosh<T, KE>(a, Hs, ldh, 32 * t, b2s, m2);
+        for (int t = 0; live && 32 * t < neff; ++t) {
+            const float s = reg_tile_logcosh<T, KE>(a, Hs, ldh, 32 * t, b2s);
             if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
         }
         if (tid == 0) cnt[(k + 1) & 1] = 0;   // read next in step k + 1, after the barrier below
@@ -423,19 +424,6 @@ __device__ __forceinline__ void eloc_stage_row(const T *W1l, const int *rcode, c
         h[e] = Mc<T>::from_f32(fmaxf(fmaf(g, d, zz[e]), 0.0f));
     }
     *reinterpret_cast<frag *>(Hs + lr * ldh + 8 * c) = h;
-}
-
-// Four of the 16 outputs a lane holds of a 32 x 32 tile (registers 4q .. 4q + 3: outputs
-// 8q + 4 (lane / 32) + 0..3 of the wave's 32) into the running |z| sum and product of (1 + e^-2|z|).
-__device__ __forceinline__ void eloc_logcosh4(const mc_floatx16 &acc, int q, float4 b, float &abs_sum, float &prod)
-{
-    const float bb[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const float v = fabsf(acc[4 * q + r] + bb[r]);
-        abs_sum += v;
-        prod = fmaf(prod, __builtin_amdgcn_exp2f(v * -2.8853900817779268f), prod);   // e^-2v = 2^(-2 log2(e) v)
-    }
 }
 
 template <typename T, int KE>
