@@ -252,64 +252,162 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
     T *lds = reinterpret_cast<T *>(smem);
 
     const int nrows = *g.nrows;
-    // The grid covers the largest row count; only the first `valid` blocks have
-    // work.  Those are renumbered so that each XCD (blocks are dealt to the 8
-    // XCDs round-robin) gets a contiguous range: consecutive ids share a row
-    // tile, whose rows then stay in that XCD's L2.
+    // The grid covers the largest row count; only `valid` tiles have work.  Block b takes tiles b, b + G,
+    // b + 2G, ... (G = gridDim.x, a multiple of 8): the loads of a tile's first two contraction steps are
+    // issued during the previous tile's last two, so a tile starts without waiting for memory.  Tile ids are
+    // renumbered so that each XCD (blocks are dealt to the 8 XCDs round-robin) gets a contiguous range:
+    // consecutive ids share a row tile, whose rows then stay in that XCD's L2.
     const int valid = ((nrows + kDT - 1) / kDT) * g.nct;
-    const int x = blockIdx.x;
-    if (x >= valid) return;
-    const int q8 = valid >> 3, r8 = valid & 7, xcd = x & 7;
-    const int lb = xcd * q8 + min(xcd, r8) + (x >> 3);
-    const int rt = lb / g.nct, ct = lb - (lb / g.nct) * g.nct;
-    const int m0 = rt * kDT, n0 = ct * kDT;
+    if ((int)blockIdx.x >= valid) return;
+    const int q8 = valid >> 3, r8 = valid & 7, G = gridDim.x;
+    auto coords = [&](int x, int &m0, int &n0, int &ct) {
+        const int xcd = x & 7, lb = xcd * q8 + min(xcd, r8) + (x >> 3);
+        const int rt = lb / g.nct;
+        ct = lb - rt * g.nct;
+        m0 = rt * kDT;
+        n0 = ct * kDT;
+    };
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
     const int l32 = lane & 31, h = lane >> 5;
 
-    int rc[4] = {0, 0, 0, 0}, ri[4] = {-1, -1, -1, -1}, rj[4] = {-1, -1, -1, -1};
-    if constexpr (SPINS) {
+    // the chain (or sample) and flipped sites of this thread's four staged rows of a tile
+    auto rowinfo = [&](int m0, int (&rc)[4], int (&ri)[4], int (&rj)[4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int row = m0 + (tid >> 3) + 32 * q;
-            if (row < nrows) {
-                rc[q] = g.row_chain[row];
-                ri[q] = g.row_i[row];
-                rj[q] = g.row_j[row];
+            rc[q] = 0;
+            ri[q] = -1;
+            rj[q] = -1;
+            if constexpr (SPINS) {
+                const int row = m0 + (tid >> 3) + 32 * q;
+                if (row < nrows) {
+                    rc[q] = g.row_chain[row];
+                    ri[q] = g.row_i[row];
+                    rj[q] = g.row_j[row];
+                }
             }
         }
+    };
+    int x = blockIdx.x, m0, n0, ct, m0n = 0, n0n = 0, ctn = 0;
+    int rc[4], ri[4], rj[4], rcn[4], rin[4], rjn[4];
+    coords(x, m0, n0, ct);
+    rowinfo(m0, rc, ri, rj);
+    bool has_next = x + G < valid;
+    if (has_next) {
+        coords(x + G, m0n, n0n, ctn);
+        rowinfo(m0n, rcn, rin, rjn);
     }
 
     mc_floatx16 acc[2][2];
+    auto zero_acc = [&]() {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    };
+    zero_acc();
+
+    // The tile's output: ReLU rows in the operand format, or per-row log-cosh partials per 64-output slice.
+    // The accumulators hold D[i = output][j = row]: lane = j + 32 ((i / 4) % 2), register = i % 4 + 4 (i / 8), so a
+    // lane has row l32 of its 32-row block and outputs 8q + 4h + 0..3 (q = 0..3) of each 32-output block: four
+    // consecutive outputs, stored together.  The bias of those outputs is read once, before any store.
+    auto epilogue = [&](int m0, int n0, int ct) {
+        float4 bq[2][4];
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+            for (int q = 0; q < 4; ++q)
+                bq[b][q] = *reinterpret_cast<const float4 *>(g.bias + n0 + wn + 32 * b + 8 * q + 4 * h);
+        auto pre = [&](int a, int b, int q, int e) {   // the pre-activation of output 8q + 4h + e
+            const float bb = e == 0 ? bq[b][q].x : (e == 1 ? bq[b][q].y : (e == 2 ? bq[b][q].z : bq[b][q].w));
+            return std::is_same<T, Fp8>::value ? fmaf(acc[a][b][4 * q + e], g.acc_scale, bb) : acc[a][b][4 * q + e] + bb;
+        };
+        if constexpr (LOGCOSH) {
+            float *part = reinterpret_cast<float *>(g.out);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                float abs_sum = 0.0f, prod = 1.0f;
+                int cnt = 0;
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int col = n0 + wn + 32 * b + 8 * q + 4 * h + e;
+                            if (col < g.Nout) {
+                                const float v = fabsf(pre(a, b, q, e));
+                                abs_sum += v;
+                                prod *= 1.0f + __expf(-2.0f * v);   // 32 factors in (1, 2]
+                                ++cnt;
+                            }
+                        }
+                float sv = abs_sum + __logf(prod) - (float)cnt * kLn2f;
+                sv += __shfl_xor(sv, 32, 64);
+                const int row = m0 + wm + 32 * a + l32;
+                if (h == 0 && row < nrows) part[(size_t)row * (2 * g.nct) + 2 * ct + (wn >> 6)] = sv;
+            }
+        } else {
+            struct alignas(4 * sizeof(T)) Out4 {
+                T v[4];
+            };
+            T *out = reinterpret_cast<T *>(g.out);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int row = m0 + wm + 32 * a + l32;
+                if (row >= nrows) continue;
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int col0 = n0 + wn + 32 * b + 8 * q + 4 * h;
+                        if (col0 >= g.ldo) continue;   // ldo is a multiple of 4: the group is whole
+                        Out4 o;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const float v = col0 + e < g.Nout ? fmaxf(pre(a, b, q, e), 0.0f) : 0.0f;
+                            if constexpr (std::is_same<T, Fp8>::value)
+                                // the next layer's input: ReLU(z) / s_next as an E4M3 code (s_next a power of two)
+                                o.v[e] = Fp8{(uint8_t)e4m3_code_nonneg(v * g.next_inv)};
+                            else
+                                o.v[e] = Mc<T>::from_f32(v);
+                        }
+                        *reinterpret_cast<Out4 *>(out + (size_t)row * g.ldo + col0) = o;
+                    }
+            }
+        }
+    };
 
-    // Two register stages: the loads of step k + 2 are issued before step k is
-    // computed, so each global load has two steps of matrix-core work to land.
+    // Contraction steps of all the block's tiles in sequence (ksteps >= 2 whenever a block has more than one
+    // tile).  Two register stages: the loads of step v + 2 are issued before step v is computed, so each
+    // global load has two steps of matrix-core work to land; across a tile boundary they are the next tile's.
     const int ksteps = g.Kp / BK;
+    const int ntile = (valid - 1 - (int)blockIdx.x) / G + 1;
+    const int V = ntile * ksteps;
+    int ks = 0;   // step within the current tile
+    auto load = [&](int ksd, Stage4 &av, Stage4 &bv) {   // step ks + d of the sequence, ksd = ks + d
+        if (ksd < ksteps) {
+            deep_load_a<T, SPINS>(g, m0, ksd, nrows, rc, ri, rj, av);
+            deep_load_w<T>(g, n0, ksd, bv);
+        } else if (has_next) {
+            deep_load_a<T, SPINS>(g, m0n, ksd - ksteps, nrows, rcn, rin, rjn, av);
+            deep_load_w<T>(g, n0n, ksd - ksteps, bv);
+        }
+    };
     Stage4 a0s, b0s, a1s, b1s;
-    deep_load_a<T, SPINS>(g, m0, 0, nrows, rc, ri, rj, a0s);
-    deep_load_w<T>(g, n0, 0, b0s);
-    if (ksteps > 1) {
-        deep_load_a<T, SPINS>(g, m0, 1, nrows, rc, ri, rj, a1s);
-        deep_load_w<T>(g, n0, 1, b1s);
-    }
+    load(0, a0s, b0s);
+    if (V > 1) load(1, a1s, b1s);
     deep_store<T>(lds, a0s);
     deep_store<T>(lds + TILE, b0s);
     __syncthreads();
-    auto step = [&](int ks, Stage4 &af, Stage4 &bf, const Stage4 &an, const Stage4 &bn) {
-        const int cur = ks & 1;
+    auto step = [&](int v, Stage4 &af, Stage4 &bf, const Stage4 &an, const Stage4 &bn) {
+        const int cur = v & 1;
         const T *As = lds + (2 * cur) * TILE;
         const T *Bs = As + TILE;
-        if (ks + 2 < ksteps) {
-            deep_load_a<T, SPINS>(g, m0, ks + 2, nrows, rc, ri, rj, af);
-            deep_load_w<T>(g, n0, ks + 2, bf);
-        }
+        if (v + 2 < V) load(ks + 2, af, bf);
 #pragma unroll
         for (int kk = 0; kk < KI; ++kk) {
             const int ko = kk * 2 * EPL + EPL * h;
@@ -317,77 +415,42 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
             const frag a1 = deep_frag<T>(As + (wm + 32 + l32) * LD + ko);
             const frag b0 = deep_frag<T>(Bs + (wn + l32) * LD + ko);
             const frag b1 = deep_frag<T>(Bs + (wn + 32 + l32) * LD + ko);
-            if constexpr (LOGCOSH) {   // D[i = output][j = row]
-                acc[0][0] = Mc<T>::mma(b0, a0, acc[0][0]);
-                acc[0][1] = Mc<T>::mma(b1, a0, acc[0][1]);
-                acc[1][0] = Mc<T>::mma(b0, a1, acc[1][0]);
-                acc[1][1] = Mc<T>::mma(b1, a1, acc[1][1]);
-            } else {                   // D[i = row][j = output]
-                acc[0][0] = Mc<T>::mma(a0, b0, acc[0][0]);
-                acc[0][1] = Mc<T>::mma(a0, b1, acc[0][1]);
-                acc[1][0] = Mc<T>::mma(a1, b0, acc[1][0]);
-                acc[1][1] = Mc<T>::mma(a1, b1, acc[1][1]);
-            }
+            // D[i = output][j = row]
+            acc[0][0] = Mc<T>::mma(b0, a0, acc[0][0]);
+            acc[0][1] = Mc<T>::mma(b1, a0, acc[0][1]);
+            acc[1][0] = Mc<T>::mma(b0, a1, acc[1][0]);
+            acc[1][1] = Mc<T>::mma(b1, a1, acc[1][1]);
         }
-        if (ks + 1 < ksteps) {
+        if (v + 1 < V) {
             T *nxt = lds + (2 * (cur ^ 1)) * TILE;
             deep_store<T>(nxt, an);
             deep_store<T>(nxt + TILE, bn);
         }
         __syncthreads();
-    };
-    for (int ks = 0; ks < ksteps; ks += 2) {
-        step(ks, a0s, b0s, a1s, b1s);
-        if (ks + 1 < ksteps) step(ks + 1, a1s, b1s, a0s, b0s);
-    }
-
-    // D[i][j] of a 32x32 accumulator: lane = j + 32*((i/4)%2), register = i%4 + 4*(i/8)
-    if constexpr (LOGCOSH) {
-        float *part = reinterpret_cast<float *>(g.out);
+        if (++ks == ksteps) {   // the tile is complete: its output, then the next tile becomes current
+            epilogue(m0, n0, ct);
+            zero_acc();
+            ks = 0;
+            x += G;
+            m0 = m0n;
+            n0 = n0n;
+            ct = ctn;
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            float abs_sum = 0.0f, prod = 1.0f;
-            int cnt = 0;
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int col = n0 + wn + 32 * b + 8 * (r >> 2) + 4 * h + (r & 3);
-                    if (col < g.Nout) {
-                        const float z = std::is_same<T, Fp8>::value ? fmaf(acc[a][b][r], g.acc_scale, g.bias[col])
-                                                                   : acc[a][b][r] + g.bias[col];
-                        const float v = fabsf(z);
-                        abs_sum += v;
-                        prod *= 1.0f + __expf(-2.0f * v);   // 32 factors in (1, 2]
-                        ++cnt;
-                    }
-                }
-            float s = abs_sum + __logf(prod) - (float)cnt * kLn2f;
-            s += __shfl_xor(s, 32, 64);
-            const int row = m0 + wm + 32 * a + l32;
-            if (h == 0 && row < nrows) part[(size_t)row * (2 * g.nct) + 2 * ct + (wn >> 6)] = s;
+            for (int q = 0; q < 4; ++q) {
+                rc[q] = rcn[q];
+                ri[q] = rin[q];
+                rj[q] = rjn[q];
+            }
+            has_next = x + G < valid;
+            if (has_next) {
+                coords(x + G, m0n, n0n, ctn);
+                rowinfo(m0n, rcn, rin, rjn);
+            }
         }
-    } else {
-        T *out = reinterpret_cast<T *>(g.out);
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = m0 + wm + 32 * a + 8 * (r >> 2) + 4 * h + (r & 3);
-                    const int col = n0 + wn + 32 * b + l32;
-                    if (row < nrows && col < g.ldo) {
-                        if constexpr (std::is_same<T, Fp8>::value) {
-                            // the next layer's input: ReLU(z) / s_next as an E4M3 code (s_next a power of two)
-                            const float v = col < g.Nout ? fmaxf(fmaf(acc[a][b][r], g.acc_scale, g.bias[col]), 0.0f) : 0.0f;
-                            out[(size_t)row * g.ldo + col] = Fp8{(uint8_t)e4m3_code_nonneg(v * g.next_inv)};
-                        } else {
-                            const float v = col < g.Nout ? fmaxf(acc[a][b][r] + g.bias[col], 0.0f) : 0.0f;
-                            out[(size_t)row * g.ldo + col] = Mc<T>::from_f32(v);
-                        }
-                    }
-                }
+    };
+    for (int v = 0; v < V; v += 2) {
+        step(v, a0s, b0s, a1s, b1s);
+        if (v + 1 < V) step(v + 1, a1s, b1s, a0s, b0s);
     }
 }
 
@@ -552,7 +615,11 @@ static void deep_gemm_launch(const DeepGemmArgs &g, hipStream_t s)
 {
     constexpr size_t lds = 4 * sizeof(T) * kDT * (kDBytes / sizeof(T) + 16 / sizeof(T));
     allow_lds(deep_gemm_kernel<T, SPINS, LOGCOSH>, lds);
-    hipLaunchKernelGGL((deep_gemm_kernel<T, SPINS, LOGCOSH>), dim3(g.max_row_tiles * g.nct), dim3(256), lds, s, g);
+    // persistent blocks (two per CU, a multiple of 8 for the XCD renumbering) when a tile has at least two
+    // contraction steps; otherwise one block per tile
+    int blocks = g.max_row_tiles * g.nct;
+    if (g.Kp / (kDBytes / (int)sizeof(T)) >= 2) blocks = std::min(blocks, 2 * device_cus());
+    hipLaunchKernelGGL((deep_gemm_kernel<T, SPINS, LOGCOSH>), dim3(blocks), dim3(256), lds, s, g);
 }
 
 template <typename T>
