@@ -118,8 +118,15 @@ __device__ __forceinline__ void deep_load_w(const DeepGemmArgs &g, int r0, int k
     v.x3 = W[3 * step];
 }
 
-// Rows -> registers: activations, or spins with the row's sites negated.
-template <typename T, bool SPINS>
+// The A operand of a GEMM: activations (AM_ACT), or the chain's spins with the row's sites negated, read 8
+// (16-bit formats) or 16 (E4M3) at a time when N is a multiple of that (AM_SPINS_VEC), else one by one
+// (AM_SPINS).  The AM_ACT and AM_SPINS_VEC paths have no branch: rows past the count and steps past N read a
+// valid address and are zeroed by selects, so the compiler can track the loads in flight exactly (a branch
+// around a load makes it wait for every outstanding load at the join).
+constexpr int AM_ACT = 0, AM_SPINS_VEC = 1, AM_SPINS = 2;
+
+// Rows -> registers (rows r0 + tid / 8 + 32 q, 16 bytes of step ks each)
+template <typename T, int AM>
 __device__ __forceinline__ void deep_load_a(const DeepGemmArgs &g, int r0, int ks, int nrows, const int (&rc)[4],
                                             const int (&ri)[4], const int (&rj)[4], Stage4 &v)
 {
@@ -128,60 +135,58 @@ __device__ __forceinline__ void deep_load_a(const DeepGemmArgs &g, int r0, int k
     const int k0 = ks * BK + (tid & 7) * EPC;
     auto one = [&](int q) -> u32x4 {
         const int row = r0 + (tid >> 3) + 32 * q;
-        if constexpr (SPINS) {
-            uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
+        if constexpr (AM == AM_ACT) {
+            const T *A = reinterpret_cast<const T *>(g.A);
+            const u32x4 d = *reinterpret_cast<const u32x4 *>(A + (size_t)(row < nrows ? row : 0) * g.lda + k0);
+            const bool ok = row < nrows;
+            return u32x4{ok ? d.x : 0u, ok ? d.y : 0u, ok ? d.z : 0u, ok ? d.w : 0u};
+        } else if constexpr (AM == AM_SPINS_VEC) {
+            static_assert(sizeof(T) <= 2, "vector spin loads for 16-bit and E4M3 operands");
+            const bool ok = row < nrows && k0 < g.N;   // N is a multiple of EPC: a group is whole or past N
+            const size_t at = (size_t)rc[q] * g.N + (k0 < g.N ? k0 : 0);
+            uint32_t w0, w1, w2, w3;
             if constexpr (sizeof(T) == 2) {
                 // 8 spins in one 8-byte load: the sign bit of each int8 (+1 = 0x01, -1 = 0xff)
                 // becomes the sign bit of a 16-bit +-1; then the row's sites are negated
-                if (row < nrows && (g.N & 7) == 0 && k0 + 8 <= g.N) {
-                    const uint2 raw = *reinterpret_cast<const uint2 *>(g.spins + (size_t)rc[q] * g.N + k0);
-                    constexpr uint32_t one2 = std::is_same<T, _Float16>::value ? 0x3C003C00u : 0x3F803F80u;
-                    const uint32_t lo = (raw.x >> 7) & 0x01010101u, hi = (raw.y >> 7) & 0x01010101u;
-                    w0 = one2 | ((lo & 0x1u) << 15) | ((lo & 0x100u) << 23);
-                    w1 = one2 | ((lo & 0x10000u) >> 1) | ((lo & 0x1000000u) << 7);
-                    w2 = one2 | ((hi & 0x1u) << 15) | ((hi & 0x100u) << 23);
-                    w3 = one2 | ((hi & 0x10000u) >> 1) | ((hi & 0x1000000u) << 7);
-                    const uint32_t ei = (uint32_t)(ri[q] - k0), ej = (uint32_t)(rj[q] - k0);
+                const uint2 raw = *reinterpret_cast<const uint2 *>(g.spins + at);
+                constexpr uint32_t one2 = std::is_same<T, _Float16>::value ? 0x3C003C00u : 0x3F803F80u;
+                const uint32_t lo = (raw.x >> 7) & 0x01010101u, hi = (raw.y >> 7) & 0x01010101u;
+                w0 = one2 | ((lo & 0x1u) << 15) | ((lo & 0x100u) << 23);
+                w1 = one2 | ((lo & 0x10000u) >> 1) | ((lo & 0x1000000u) << 7);
+                w2 = one2 | ((hi & 0x1u) << 15) | ((hi & 0x100u) << 23);
+                w3 = one2 | ((hi & 0x10000u) >> 1) | ((hi & 0x1000000u) << 7);
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        const uint32_t e = t == 0 ? ei : ej;
-                        if (e < 8u) {
-                            const uint32_t m = 1u << (15 + 16 * (e & 1u));
-                            const uint32_t wsel = e >> 1;
-                            w0 ^= wsel == 0 ? m : 0u;
-                            w1 ^= wsel == 1 ? m : 0u;
-                            w2 ^= wsel == 2 ? m : 0u;
-                            w3 ^= wsel == 3 ? m : 0u;
-                        }
-                    }
-                    return u32x4{w0, w1, w2, w3};
+                for (int t = 0; t < 2; ++t) {
+                    const uint32_t e = (uint32_t)((t == 0 ? ri[q] : rj[q]) - k0);
+                    const uint32_t m = e < 8u ? 1u << (15 + 16 * (e & 1u)) : 0u;
+                    const uint32_t wsel = e >> 1;
+                    w0 ^= wsel == 0 ? m : 0u;
+                    w1 ^= wsel == 1 ? m : 0u;
+                    w2 ^= wsel == 2 ? m : 0u;
+                    w3 ^= wsel == 3 ? m : 0u;
                 }
-            }
-            if constexpr (sizeof(T) == 1) {
+            } else {
                 // 16 spins in one 16-byte load: +1 = 0x01, -1 = 0xff, so the E4M3 code of the spin is
                 // 0x38 (1.0) with the spin's sign bit; then the row's sites are negated
-                if (row < nrows && (g.N & 15) == 0 && k0 + 16 <= g.N) {
-                    const u32x4 raw = *reinterpret_cast<const u32x4 *>(g.spins + (size_t)rc[q] * g.N + k0);
-                    w0 = 0x38383838u | (raw.x & 0x80808080u);
-                    w1 = 0x38383838u | (raw.y & 0x80808080u);
-                    w2 = 0x38383838u | (raw.z & 0x80808080u);
-                    w3 = 0x38383838u | (raw.w & 0x80808080u);
-                    const uint32_t ei = (uint32_t)(ri[q] - k0), ej = (uint32_t)(rj[q] - k0);
+                const u32x4 raw = *reinterpret_cast<const u32x4 *>(g.spins + at);
+                w0 = 0x38383838u | (raw.x & 0x80808080u);
+                w1 = 0x38383838u | (raw.y & 0x80808080u);
+                w2 = 0x38383838u | (raw.z & 0x80808080u);
+                w3 = 0x38383838u | (raw.w & 0x80808080u);
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        const uint32_t e = t == 0 ? ei : ej;
-                        if (e < 16u) {
-                            const uint32_t m = 0x80u << (8 * (e & 3u));
-                            const uint32_t wsel = e >> 2;
-                            w0 ^= wsel == 0 ? m : 0u;
-                            w1 ^= wsel == 1 ? m : 0u;
-                            w2 ^= wsel == 2 ? m : 0u;
-                            w3 ^= wsel == 3 ? m : 0u;
-                        }
-                    }
-                    return u32x4{w0, w1, w2, w3};
+                for (int t = 0; t < 2; ++t) {
+                    const uint32_t e = (uint32_t)((t == 0 ? ri[q] : rj[q]) - k0);
+                    const uint32_t m = e < 16u ? 0x80u << (8 * (e & 3u)) : 0u;
+                    const uint32_t wsel = e >> 2;
+                    w0 ^= wsel == 0 ? m : 0u;
+                    w1 ^= wsel == 1 ? m : 0u;
+                    w2 ^= wsel == 2 ? m : 0u;
+                    w3 ^= wsel == 3 ? m : 0u;
                 }
             }
+            return u32x4{ok ? w0 : 0u, ok ? w1 : 0u, ok ? w2 : 0u, ok ? w3 : 0u};
+        } else {
+            uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
             if (row < nrows) {
                 const int8_t *sp = g.spins + (size_t)rc[q] * g.N;
 #pragma unroll
@@ -199,12 +204,6 @@ __device__ __forceinline__ void deep_load_a(const DeepGemmArgs &g, int r0, int k
                 }
             }
             return u32x4{w0, w1, w2, w3};
-        } else {
-            if (row < nrows) {
-                const T *A = reinterpret_cast<const T *>(g.A);
-                return *reinterpret_cast<const u32x4 *>(A + (size_t)row * g.lda + k0);
-            }
-            return u32x4{0u, 0u, 0u, 0u};
         }
     };
     v.x0 = one(0);
@@ -239,9 +238,10 @@ __device__ __forceinline__ typename Mc<T>::frag deep_frag(const T *p)
     }
 }
 
-template <typename T, bool SPINS, bool LOGCOSH>
+template <typename T, int AM, bool LOGCOSH>
 __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
 {
+    constexpr bool SPINS = AM != AM_ACT;
     typedef typename Mc<T>::frag frag;
     constexpr int BK = kDBytes / sizeof(T);
     constexpr int LD = BK + 16 / sizeof(T);
@@ -388,18 +388,25 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
     const int ntile = (valid - 1 - (int)blockIdx.x) / G + 1;
     const int V = ntile * ksteps;
     int ks = 0;   // step within the current tile
-    auto load = [&](int ksd, Stage4 &av, Stage4 &bv) {   // step ks + d of the sequence, ksd = ks + d
-        if (ksd < ksteps) {
-            deep_load_a<T, SPINS>(g, m0, ksd, nrows, rc, ri, rj, av);
-            deep_load_w<T>(g, n0, ksd, bv);
-        } else if (has_next) {
-            deep_load_a<T, SPINS>(g, m0n, ksd - ksteps, nrows, rcn, rin, rjn, av);
-            deep_load_w<T>(g, n0n, ksd - ksteps, bv);
+    // loads of step ks + d of the sequence (ksd = ks + d), without a branch: past the current tile they are
+    // the next tile's; past the block's last step they read the current tile again and are never stored
+    auto load = [&](int ksd, Stage4 &av, Stage4 &bv) {
+        const bool nxt = ksd >= ksteps && has_next;
+        int k = ksd >= ksteps ? ksd - ksteps : ksd;
+        k = k < ksteps ? k : 0;
+        int rca[4], ria[4], rja[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            rca[q] = nxt ? rcn[q] : rc[q];
+            ria[q] = nxt ? rin[q] : ri[q];
+            rja[q] = nxt ? rjn[q] : rj[q];
         }
+        deep_load_a<T, AM>(g, nxt ? m0n : m0, k, nrows, rca, ria, rja, av);
+        deep_load_w<T>(g, nxt ? n0n : n0, k, bv);
     };
     Stage4 a0s, b0s, a1s, b1s;
     load(0, a0s, b0s);
-    if (V > 1) load(1, a1s, b1s);
+    load(1, a1s, b1s);
     deep_store<T>(lds, a0s);
     deep_store<T>(lds + TILE, b0s);
     __syncthreads();
@@ -407,7 +414,7 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
         const int cur = v & 1;
         const T *As = lds + (2 * cur) * TILE;
         const T *Bs = As + TILE;
-        if (v + 2 < V) load(ks + 2, af, bf);
+        load(ks + 2, af, bf);
 #pragma unroll
         for (int kk = 0; kk < KI; ++kk) {
             const int ko = kk * 2 * EPL + EPL * h;
@@ -421,7 +428,7 @@ __global__ void __launch_bounds__(256, 2) deep_gemm_kernel(DeepGemmArgs g)
             acc[1][0] = Mc<T>::mma(b0, a1, acc[1][0]);
             acc[1][1] = Mc<T>::mma(b1, a1, acc[1][1]);
         }
-        if (v + 1 < V) {
+        {   // after the last step this fills a buffer nothing reads
             T *nxt = lds + (2 * (cur ^ 1)) * TILE;
             deep_store<T>(nxt, an);
             deep_store<T>(nxt + TILE, bn);
@@ -610,27 +617,34 @@ __global__ void deep_copy_acc_kernel(const unsigned long long *acc, int64_t C, u
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-template <typename T, bool SPINS, bool LOGCOSH>
+template <typename T, int AM, bool LOGCOSH>
 static void deep_gemm_launch(const DeepGemmArgs &g, hipStream_t s)
 {
     constexpr size_t lds = 4 * sizeof(T) * kDT * (kDBytes / sizeof(T) + 16 / sizeof(T));
-    allow_lds(deep_gemm_kernel<T, SPINS, LOGCOSH>, lds);
+    allow_lds(deep_gemm_kernel<T, AM, LOGCOSH>, lds);
     // persistent blocks (two per CU, a multiple of 8 for the XCD renumbering) when a tile has at least two
     // contraction steps; otherwise one block per tile
     int blocks = g.max_row_tiles * g.nct;
     if (g.Kp / (kDBytes / (int)sizeof(T)) >= 2) blocks = std::min(blocks, 2 * device_cus());
-    hipLaunchKernelGGL((deep_gemm_kernel<T, SPINS, LOGCOSH>), dim3(blocks), dim3(256), lds, s, g);
+    hipLaunchKernelGGL((deep_gemm_kernel<T, AM, LOGCOSH>), dim3(blocks), dim3(256), lds, s, g);
 }
 
 template <typename T>
 static void deep_gemm_dispatch(bool spins, bool logcosh, const DeepGemmArgs &g, hipStream_t s)
 {
-    if (spins) {
-        if (logcosh) deep_gemm_launch<T, true, true>(g, s);
-        else deep_gemm_launch<T, true, false>(g, s);
+    // spins read EPC at a time when N is a multiple of EPC (16-bit and E4M3 operands)
+    constexpr int EPC = 16 / sizeof(T);
+    if (spins && sizeof(T) <= 2 && g.N % EPC == 0) {
+        if constexpr (sizeof(T) <= 2) {
+            if (logcosh) deep_gemm_launch<T, AM_SPINS_VEC, true>(g, s);
+            else deep_gemm_launch<T, AM_SPINS_VEC, false>(g, s);
+        }
+    } else if (spins) {
+        if (logcosh) deep_gemm_launch<T, AM_SPINS, true>(g, s);
+        else deep_gemm_launch<T, AM_SPINS, false>(g, s);
     } else {
-        if (logcosh) deep_gemm_launch<T, false, true>(g, s);
-        else deep_gemm_launch<T, false, false>(g, s);
+        if (logcosh) deep_gemm_launch<T, AM_ACT, true>(g, s);
+        else deep_gemm_launch<T, AM_ACT, false>(g, s);
     }
 }
 
