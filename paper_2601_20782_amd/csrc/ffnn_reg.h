@@ -452,7 +452,9 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
     float *rc = reinterpret_cast<float *>(rcode + maxrows);
     float *rg = rc + maxrows;
     float *fr = rg + maxrows;
-    double *diag = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(fr + maxrows) + 7) & ~(uintptr_t)7);
+    // (an offset from smem, not an integer cast of the pointer, so that the compiler keeps the LDS address space)
+    const size_t diag_off = ((size_t)(reinterpret_cast<unsigned char *>(fr + maxrows) - smem) + 7) & ~(size_t)7;
+    double *diag = reinterpret_cast<double *>(smem + diag_off);
     int *rcnt = reinterpret_cast<int *>(diag + G);     // [G]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
