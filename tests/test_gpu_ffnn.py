@@ -250,8 +250,13 @@ def test_register_path_replay(nqs, dtype, move, L, widths, C):
 @pytest.mark.parametrize("dtype,kind,dim,L,widths,n_s", [("bf16", "tfim", 2, 6, (144, 72), 41),
                                                          ("f16", "heisenberg", 2, 6, (130, 40), 37),
                                                          ("bf16", "heisenberg", 1, 16, (256, 250), 10),
-                                                         ("bf16", "heisenberg", 2, 4, (480, 96), 20)])
+                                                         ("bf16", "heisenberg", 2, 4, (480, 96), 20),
+                                                         ("bf16", "heisenberg", 2, 20, (128, 32), 6),
+                                                         ("f16", "heisenberg", 1, 440, (128, 32), 4)])
 def test_register_path_local_energy(nqs, dtype, kind, dim, L, widths, n_s):
+    """The register-resident local-energy kernel against the oracle: first-layer widths of 9 to 30 fragments
+    of 16 (the 480-wide one without the shifted second pass), and lattices whose rows leave room in LDS for
+    groups of 8, 4, 2 (20x20, 128 hidden units) and 1 (a 440-site chain) samples."""
     n = L if dim == 1 else L * L
     marshall = kind == "heisenberg"
     wl = workloads.Workload(f"reg_eloc_{kind}", workloads.Hamiltonian(kind, workloads.Lattice(dim, L), 1.0, 2.0, marshall),
