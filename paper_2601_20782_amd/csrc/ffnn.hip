@@ -597,8 +597,10 @@ namespace nqs {
 nqs_status ffnn_sample_dispatch(int dtype, int QK, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds,
                                 hipStream_t s);
 nqs_status ffnn_eloc_dispatch(int dtype, int QK, const FfnnElocArgs &A, int blocks, size_t lds, hipStream_t s);
-bool ffnn_reg_sample_launch_bf16(int ke, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds, hipStream_t s);
-bool ffnn_reg_sample_launch_f16(int ke, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds, hipStream_t s);
+bool ffnn_reg_sample_launch_bf16(int ke, bool trace, bool perchain, const FfnnSampleArgs &A, int blocks, size_t lds,
+                              hipStream_t s);
+bool ffnn_reg_sample_launch_f16(int ke, bool trace, bool perchain, const FfnnSampleArgs &A, int blocks, size_t lds,
+                              hipStream_t s);
 size_t ffnn_reg_sample_lds_bf16(int N, int ke, int m2p);
 size_t ffnn_reg_sample_lds_f16(int N, int ke, int m2p);
 bool ffnn_reg_eloc_launch_bf16(int ke, const FfnnElocArgs &A, int G, int blocks, size_t lds, hipStream_t s);
@@ -701,8 +703,13 @@ nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     const int QK = (f.m1p + 63) / 64;
     const int64_t blocks = (cfg.n_chains + kRows - 1) / kRows;   // kRows == kRegRows: 64 chains per block
     if (use_reg) {
-        const bool ok = cfg.dtype == NQS_F16 ? ffnn_reg_sample_launch_f16(KE, tr, A, (int)blocks, lds, stream)
-                                             : ffnn_reg_sample_launch_bf16(KE, tr, A, (int)blocks, lds, stream);
+        // Chains that advance on their own (skipping rejected exchanges and refreshing
+        // at their own sweep ends) win once the hidden pre-activations are rebuilt every
+        // few sweeps; a rebuild after every sweep is cheaper when all 64 chains of a
+        // block take it together.
+        const bool perchain = A.refresh_sweeps >= 4;
+        const bool ok = cfg.dtype == NQS_F16 ? ffnn_reg_sample_launch_f16(KE, tr, perchain, A, (int)blocks, lds, stream)
+                                             : ffnn_reg_sample_launch_bf16(KE, tr, perchain, A, (int)blocks, lds, stream);
         if (!ok) return set_error(NQS_EUNSUPPORTED, "first hidden width not supported by the register-resident sampler");
         NQS_HIP_TRY(hipGetLastError());
         return NQS_OK;

@@ -128,7 +128,7 @@ struct RegSampleLds {
 // effective ones at slots taken from a shared counter, and after the matrix
 // product decides them and updates their state.  Two barriers per step: after
 // the staging (h1 rows complete) and after the product (partial sums complete).
-template <typename T, int KE, bool TRACE>
+template <typename T, int KE, bool TRACE, bool PERCHAIN>
 __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSampleArgs A)
 {
     typedef typename Mc<T>::frag frag;
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     float *b2s = reinterpret_cast<float *>(Hs + (size_t)(kRegRows + 1) * ldh);
     float *part = b2s + m2p;
     uint32_t *words = reinterpret_cast<uint32_t *>(part + kRegWaves * kRegRows);
-    int *cnt = reinterpret_cast<int *>(words + kRegRows * NW);   // [2] slots taken in the current / next step
+    int *cnt = reinterpret_cast<int *>(words + kRegRows * NW);   // [4] rows and live chains of this / the next round
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * kRegRows;
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
             }
             words[k] = bits;
         }
-        if (tid < 2) cnt[tid] = 0;
+        if (tid < 4) cnt[tid] = 0;
     }
     __syncthreads();
 
@@ -233,116 +233,344 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     refresh_z1();
     float fcur = full_eval();   // meaningful on proposal lanes
 
-    const int sw = A.sweep_size;
-    const int64_t total = (int64_t)(A.n_burnin + A.n_sweeps) * sw;
-    const uint32_t key0 = (uint32_t)A.seed, key1 = (uint32_t)(A.seed >> 32);
-    unsigned long long acc = 0;
-    int in_sweep = 0, since_refresh = 0;
-    int64_t sweep = 0;
-    for (int64_t k = 0; k < total; ++k) {
-        // proposals of this wave's chains (lanes 0..7); effective ones take a slot
-        int pi = 0, pj = -1, slot = -1;
-        float si = 1.0f;
-        uint32_t ub = 0;
-        if (plane) {
-            const uint64_t step = A.step_offset + (uint64_t)k;
-            const uint32_t gid = A.chain_id_offset + (uint32_t)(c0 + myrow);
-            const Block4 rb = philox4x32_10((uint32_t)step, (uint32_t)(step >> 32), gid, A.inst << 8, key0, key1);
-            pi = index_from_word(rb.r0, N);
-            if (A.move == 1) {
-                pj = index_from_word(rb.r1, N - 1);
-                pj += (pj >= pi) ? 1 : 0;
-            }
-            const uint32_t *w = words + myrow * NW;
-            const bool up = (w[pi >> 5] >> (pi & 31)) & 1u;
-            si = up ? 1.0f : -1.0f;
-            const bool eff = pj < 0 || up != (bool)((w[pj >> 5] >> (pj & 31)) & 1u);
-            if (eff) slot = atomicAdd(&cnt[k & 1], 1);
-            ub = rb.r2 >> 8;
-        }
-        // stage h1 of the effective proposals (rows are wave-uniform); every chain's row is formed and an
-        // ineffective one goes to the spare row kRegRows, so that the code has no branch and the reads of later
-        // chains can be issued before earlier rows are stored
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const int sl = __builtin_amdgcn_readlane(slot, r);
-            const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
-            const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
-            float dz[8];
-            delta_z1(i, j, s_i, dz);
-            store_row(sl >= 0 ? sl : kRegRows, z1[r], dz);
-        }
-        __syncthreads();
-        const int neff = cnt[k & 1];
-        for (int t = 0; live && 32 * t < neff; ++t) {
-            const float s = reg_tile_logcosh<T, KE>(a, Hs, ldh, 32 * t, b2s);
-            if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
-        }
-        if (tid == 0) cnt[(k + 1) & 1] = 0;   // read next in step k + 1, after the barrier below
-        __syncthreads();
-        // decisions of this wave's chains
-        bool upd = false;
-        if (plane) {
-            float fnew = 0.0f;
-            if (slot >= 0)
-                for (int w = 0; w < nwt; ++w) fnew += part[w * kRegRows + slot];
-            const float d2 = slot >= 0 ? 2.0f * (fnew - fcur) / kLn2f : 0.0f;
-            const float l2u = __builtin_amdgcn_logf((float)ub * 5.9604644775390625e-8f);
-            const bool accept = l2u < d2;   // NaN rejects
-            if (accept) ++acc;
-            upd = accept && slot >= 0;
-            if (upd) {
-                uint32_t *w = words + myrow * NW;
-                w[pi >> 5] ^= 1u << (pi & 31);
-                if (pj >= 0) w[pj >> 5] ^= 1u << (pj & 31);
-                fcur = fnew;
-            }
+    unsigned long long acc = 0;   // accepted proposals of this lane's chain
+    if constexpr (PERCHAIN) {
+        // Each chain advances through its own steps.  Per round (two barriers) a chain draws proposals until one
+        // changes its state: the others (an exchange of equal spins) are accepted without an evaluation, so
+        // they are decided on the spot.  It stops early at the end of a sweep, where its sample is written out;
+        // at the ends of sweeps that refresh z1 it recomputes z1 and evaluates its current state in the next
+        // tile instead of a proposal, before that sample is written.  The rows of a round are those proposals
+        // and refreshes (compacted), so the tiles are full however many proposals were ineffective; every
+        // decision, value and output equals that of all chains stepping together.
+        const int sw = A.sweep_size;
+        const int64_t total = (int64_t)(A.n_burnin + A.n_sweeps) * sw;
+        const uint32_t key0 = (uint32_t)A.seed, key1 = (uint32_t)(A.seed >> 32);
+        int64_t kc = 0;              // the chain's next step (proposal lanes)
+        int in_sweep = 0, sweep = 0; // steps done in the current sweep; sweeps completed
+        bool need_refresh = false;   // z1 and f are recomputed before the pending sample is written
+        int emit_q = -1;             // sweep whose sample is still to be written
+        int par = 0;
+        int64_t rounds = 0;
+        // the decision of an ineffective proposal (its log-ratio is 0)
+        auto trace = [&](int64_t k, int pi_, int pj_, uint32_t ub_, float d2, bool accept) {
             if constexpr (TRACE) {
                 const int64_t c = c0 + myrow;
                 if (c < A.n_traced) {
                     const size_t idx = (size_t)c * (size_t)total + (size_t)k;
-                    A.tr_site[idx] = pi | ((pj < 0 ? 0xFFFF : pj) << 16);
-                    A.tr_ubits[idx] = ub;
+                    A.tr_site[idx] = pi_ | ((pj_ < 0 ? 0xFFFF : pj_) << 16);
+                    A.tr_ubits[idx] = ub_;
                     A.tr_delta[idx] = d2 * kLn2f;
                     A.tr_acc[idx] = accept ? 1 : 0;
                 }
             }
-        }
-        // apply the accepted moves to z1
-        const unsigned long long um = __ballot(upd);
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            if ((um >> r) & 1ull) {
+        };
+        // a step has been decided: at the end of a sweep its sample is due, after a refresh when one is due
+        auto end_of_step = [&]() {
+            if (++in_sweep == sw) {
+                in_sweep = 0;
+                emit_q = sweep++;
+                need_refresh = sweep % A.refresh_sweeps == 0;
+            }
+        };
+        while (true) {
+            // proposals of this wave's chains: mode 1 an effective proposal, 2 a refresh row.  The next 8 steps of
+            // chain r are drawn at once by lanes 8r .. 8r + 7 (lane 8r + d: step kc + d, up to the end of the sweep
+            // and of the call); the steps before the first effective one are ineffective and decided on the spot.
+            const int gr = lane >> 3, gd = lane & 7;                    // chain and look-ahead of this lane
+            const int64_t kc_g = ((int64_t)__shfl(int(kc >> 32), gr, 64) << 32) | (uint32_t)__shfl(int(kc), gr, 64);
+            const int in_g = __shfl(in_sweep, gr, 64);
+            const bool search = plane && !need_refresh && emit_q < 0 && kc < total;
+            const bool search_g = __shfl(search ? 1 : 0, gr, 64) != 0;
+            const int64_t left_g = total - kc_g;
+            const int lim_g = (int)min<int64_t>(min<int64_t>(8, left_g), (int64_t)(sw - in_g));   // steps of the window
+            const bool inwin = search_g && gd < lim_g;
+            int wpi = 0, wpj = -1;
+            uint32_t wub = 0;
+            bool wup = false, weff = false;
+            if (inwin) {
+                const uint64_t step = A.step_offset + (uint64_t)(kc_g + gd);
+                const uint32_t gidg = A.chain_id_offset + (uint32_t)(c0 + wave * RPW + gr);
+                const Block4 rb = philox4x32_10((uint32_t)step, (uint32_t)(step >> 32), gidg, A.inst << 8, key0, key1);
+                wpi = index_from_word(rb.r0, N);
+                if (A.move == 1) {
+                    wpj = index_from_word(rb.r1, N - 1);
+                    wpj += (wpj >= wpi) ? 1 : 0;
+                }
+                const uint32_t *w = words + (wave * RPW + gr) * NW;
+                wup = (w[wpi >> 5] >> (wpi & 31)) & 1u;
+                weff = wpj < 0 || wup != (bool)((w[wpj >> 5] >> (wpj & 31)) & 1u);
+                wub = rb.r2 >> 8;
+            }
+            const unsigned long long effb = __ballot(weff);
+            const unsigned gbits = (unsigned)(effb >> (8 * gr)) & 0xFFu;
+            const int first_g = gbits ? __builtin_ctz(gbits) : 8;        // look-ahead of the first effective step
+            // ineffective steps before it: log-ratio 0, accepted when log2 u < 0
+            const bool skip = inwin && gd < first_g;
+            bool skip_acc = false;
+            if (skip) {
+                const float l2u = __builtin_amdgcn_logf((float)wub * 5.9604644775390625e-8f);
+                skip_acc = l2u < 0.0f;
+                if constexpr (TRACE) {
+                    const int64_t c = c0 + wave * RPW + gr;
+                    if (c < A.n_traced) {
+                        const size_t idx = (size_t)c * (size_t)total + (size_t)(kc_g + gd);
+                        A.tr_site[idx] = wpi | ((wpj < 0 ? 0xFFFF : wpj) << 16);
+                        A.tr_ubits[idx] = wub;
+                        A.tr_delta[idx] = 0.0f;
+                        A.tr_acc[idx] = skip_acc ? 1 : 0;
+                    }
+                }
+            }
+            const unsigned long long accb = __ballot(skip_acc);
+            // the window's outcome for chain r = lane (lanes 0..7), read with every lane active (a shuffle from
+            // an inactive lane returns 0): the look-ahead of its first effective step, the window's length, and
+            // the effective proposal from lane 8r + first
+            const int first_c = __shfl(first_g, 8 * (lane & 7), 64), lim_c = __shfl(lim_g, 8 * (lane & 7), 64);
+            const int src = 8 * (lane & 7) + min(first_c, 7);
+            const int e_pi = __shfl(wpi, src, 64), e_pj = __shfl(wpj, src, 64);
+            const uint32_t e_ub = (uint32_t)__shfl((int)wub, src, 64);
+            const bool e_up = __shfl(wup ? 1 : 0, src, 64) != 0;
+            int pi = 0, pj = -1, slot = -1, mode = 0;
+            float si = 0.0f;   // 0 leaves a refresh row (or no row) without a layer-1 change
+            uint32_t ub = 0;
+            if (plane) {
+                if (need_refresh) {
+                    mode = 2;
+                } else if (search) {
+                    const int first = first_c, lim = lim_c;
+                    const int nskip = min(first, lim);
+                    acc += (unsigned long long)__popc((unsigned)(accb >> (8 * lane)) & 0xFFu);
+                    kc += nskip;
+                    in_sweep += nskip;
+                    if (in_sweep == sw) {   // the sweep ended on ineffective steps
+                        in_sweep = 0;
+                        emit_q = sweep++;
+                        need_refresh = sweep % A.refresh_sweeps == 0;
+                        if (need_refresh) mode = 2;   // the refresh row goes in this round
+                    } else if (first < lim) {
+                        pi = e_pi;
+                        pj = e_pj;
+                        ub = e_ub;
+                        si = e_up ? 1.0f : -1.0f;
+                        mode = 1;
+                    }
+                }
+                if (mode != 0) slot = atomicAdd(&cnt[par], 1);
+            }
+            // chains that refresh: z1 recomputed from the spins (the same arithmetic as the start of the call)
+            const unsigned long long rm = __ballot(mode == 2);
+    #pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                if ((rm >> r) & 1ull) {
+                    const int row = wave * RPW + r;
+    #pragma unroll
+                    for (int e = 0; e < 8; ++e) z1[r][e] = net.b1p[c8 + e];
+                    for (int i = 0; i < N; ++i) {
+                        const frag w = *reinterpret_cast<const frag *>(W1l + i * K + c8);
+                        const float sv = ((words[row * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1.0f : -1.0f;
+    #pragma unroll
+                        for (int e = 0; e < 8; ++e) z1[r][e] = fmaf(Mc<T>::to_f32(w[e]), sv, z1[r][e]);
+                    }
+                }
+            }
+            // stage the rows (wave-uniform per chain): every chain's row is formed, one without a row goes to the
+            // spare row kRegRows, so that the code has no branch and later reads overlap earlier stores
+    #pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int sl = __builtin_amdgcn_readlane(slot, r);
                 const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
                 const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
                 float dz[8];
                 delta_z1(i, j, s_i, dz);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) z1[r][e] += dz[e];
+                store_row(sl >= 0 ? sl : kRegRows, z1[r], dz);
             }
-        }
-        if (++in_sweep == sw) {
-            in_sweep = 0;
-            const int64_t out = sweep - A.n_burnin;
-            if (++since_refresh == A.refresh_sweeps) {
-                refresh_z1();
-                const float f = full_eval();
-                if (plane) fcur = f;
-                since_refresh = 0;
+            // chains with work left are counted with the rows: none left ends the call for the whole block
+            if (plane && (kc < total || need_refresh || emit_q >= 0)) atomicAdd(&cnt[2 + par], 1);
+            __syncthreads();
+            // every live chain advances each round (a step, a refresh or a sample written), so this count reaches
+            // zero within 3 total + 2 rounds; the bound only makes that explicit
+            if (cnt[2 + par] == 0 || ++rounds > 3 * total + 2) break;
+            const int neff = cnt[par];
+            for (int t = 0; live && 32 * t < neff; ++t) {
+                const float s = reg_tile_logcosh<T, KE>(a, Hs, ldh, 32 * t, b2s);
+                if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
             }
-            if (out >= 0) {
-                if (A.samples) {
-                    // this wave's chains: lane = site within a word row
-                    for (int idx = lane; idx < RPW * N; idx += 64) {
-                        const int r = idx / N, i = idx % N, row = wave * RPW + r;
-                        if (row < nvalid)
+            if (tid == 0) {   // read next in the following round, after the barrier below
+                cnt[par ^ 1] = 0;
+                cnt[2 + (par ^ 1)] = 0;
+            }
+            __syncthreads();
+            // decisions and refreshed values of this wave's chains
+            bool upd = false;
+            if (plane && mode != 0) {
+                float fnew = 0.0f;
+                for (int w = 0; w < nwt; ++w) fnew += part[w * kRegRows + slot];
+                if (mode == 2) {
+                    fcur = fnew;
+                    need_refresh = false;
+                } else {
+                    const float d2 = 2.0f * (fnew - fcur) / kLn2f;
+                    const float l2u = __builtin_amdgcn_logf((float)ub * 5.9604644775390625e-8f);
+                    const bool accept = l2u < d2;   // NaN rejects
+                    if (accept) ++acc;
+                    upd = accept;
+                    if (upd) {
+                        uint32_t *w = words + myrow * NW;
+                        w[pi >> 5] ^= 1u << (pi & 31);
+                        if (pj >= 0) w[pj >> 5] ^= 1u << (pj & 31);
+                        fcur = fnew;
+                    }
+                    trace((int64_t)kc, pi, pj, ub, d2, accept);
+                    ++kc;
+                    end_of_step();
+                }
+            }
+            // apply the accepted moves to z1
+            const unsigned long long um = __ballot(upd);
+    #pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                if ((um >> r) & 1ull) {
+                    const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
+                    const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
+                    float dz[8];
+                    delta_z1(i, j, s_i, dz);
+    #pragma unroll
+                    for (int e = 0; e < 8; ++e) z1[r][e] += dz[e];
+                }
+            }
+            // samples due (no refresh pending): the chain's spins and log|psi|
+            const bool emit = plane && emit_q >= 0 && !need_refresh;
+            const unsigned long long em = __ballot(emit);
+            const int out_lane = emit_q - A.n_burnin;
+    #pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                if ((em >> r) & 1ull) {
+                    const int out = __builtin_amdgcn_readlane(out_lane, r);
+                    const int row = wave * RPW + r;
+                    if (out >= 0 && A.samples)
+                        for (int i = lane; i < N; i += 64)
                             A.samples[((size_t)out * A.n_chains + c0 + row) * N + i] =
                                 ((words[row * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1 : -1;
+                }
+            }
+            if (emit) {
+                if (out_lane >= 0 && A.logpsi) A.logpsi[(size_t)out_lane * A.n_chains + c0 + myrow] = fcur;
+                emit_q = -1;
+            }
+            par ^= 1;
+        }
+    } else {
+        // All chains step together: one proposal per chain per step, the effective ones evaluated.
+        const int sw = A.sweep_size;
+        const int64_t total = (int64_t)(A.n_burnin + A.n_sweeps) * sw;
+        const uint32_t key0 = (uint32_t)A.seed, key1 = (uint32_t)(A.seed >> 32);
+        int in_sweep = 0, since_refresh = 0;
+        int64_t sweep = 0;
+        for (int64_t k = 0; k < total; ++k) {
+            // proposals of this wave's chains (lanes 0..7); effective ones take a slot
+            int pi = 0, pj = -1, slot = -1;
+            float si = 1.0f;
+            uint32_t ub = 0;
+            if (plane) {
+                const uint64_t step = A.step_offset + (uint64_t)k;
+                const uint32_t gid = A.chain_id_offset + (uint32_t)(c0 + myrow);
+                const Block4 rb = philox4x32_10((uint32_t)step, (uint32_t)(step >> 32), gid, A.inst << 8, key0, key1);
+                pi = index_from_word(rb.r0, N);
+                if (A.move == 1) {
+                    pj = index_from_word(rb.r1, N - 1);
+                    pj += (pj >= pi) ? 1 : 0;
+                }
+                const uint32_t *w = words + myrow * NW;
+                const bool up = (w[pi >> 5] >> (pi & 31)) & 1u;
+                si = up ? 1.0f : -1.0f;
+                const bool eff = pj < 0 || up != (bool)((w[pj >> 5] >> (pj & 31)) & 1u);
+                if (eff) slot = atomicAdd(&cnt[k & 1], 1);
+                ub = rb.r2 >> 8;
+            }
+            // stage h1 of the effective proposals (rows are wave-uniform); every chain's row is formed and an
+            // ineffective one goes to the spare row kRegRows, so that the code has no branch and the reads of later
+            // chains can be issued before earlier rows are stored
+    #pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int sl = __builtin_amdgcn_readlane(slot, r);
+                const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
+                const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
+                float dz[8];
+                delta_z1(i, j, s_i, dz);
+                store_row(sl >= 0 ? sl : kRegRows, z1[r], dz);
+            }
+            __syncthreads();
+            const int neff = cnt[k & 1];
+            for (int t = 0; live && 32 * t < neff; ++t) {
+                const float s = reg_tile_logcosh<T, KE>(a, Hs, ldh, 32 * t, b2s);
+                if (lane < 32) part[wave * kRegRows + 32 * t + lane] = s;
+            }
+            if (tid == 0) cnt[(k + 1) & 1] = 0;   // read next in step k + 1, after the barrier below
+            __syncthreads();
+            // decisions of this wave's chains
+            bool upd = false;
+            if (plane) {
+                float fnew = 0.0f;
+                if (slot >= 0)
+                    for (int w = 0; w < nwt; ++w) fnew += part[w * kRegRows + slot];
+                const float d2 = slot >= 0 ? 2.0f * (fnew - fcur) / kLn2f : 0.0f;
+                const float l2u = __builtin_amdgcn_logf((float)ub * 5.9604644775390625e-8f);
+                const bool accept = l2u < d2;   // NaN rejects
+                if (accept) ++acc;
+                upd = accept && slot >= 0;
+                if (upd) {
+                    uint32_t *w = words + myrow * NW;
+                    w[pi >> 5] ^= 1u << (pi & 31);
+                    if (pj >= 0) w[pj >> 5] ^= 1u << (pj & 31);
+                    fcur = fnew;
+                }
+                if constexpr (TRACE) {
+                    const int64_t c = c0 + myrow;
+                    if (c < A.n_traced) {
+                        const size_t idx = (size_t)c * (size_t)total + (size_t)k;
+                        A.tr_site[idx] = pi | ((pj < 0 ? 0xFFFF : pj) << 16);
+                        A.tr_ubits[idx] = ub;
+                        A.tr_delta[idx] = d2 * kLn2f;
+                        A.tr_acc[idx] = accept ? 1 : 0;
                     }
                 }
-                if (A.logpsi && plane) A.logpsi[(size_t)out * A.n_chains + c0 + myrow] = fcur;
             }
-            ++sweep;
+            // apply the accepted moves to z1
+            const unsigned long long um = __ballot(upd);
+    #pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                if ((um >> r) & 1ull) {
+                    const int i = __builtin_amdgcn_readlane(pi, r), j = __builtin_amdgcn_readlane(pj, r);
+                    const float s_i = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si), r));
+                    float dz[8];
+                    delta_z1(i, j, s_i, dz);
+    #pragma unroll
+                    for (int e = 0; e < 8; ++e) z1[r][e] += dz[e];
+                }
+            }
+            if (++in_sweep == sw) {
+                in_sweep = 0;
+                const int64_t out = sweep - A.n_burnin;
+                if (++since_refresh == A.refresh_sweeps) {
+                    refresh_z1();
+                    const float f = full_eval();
+                    if (plane) fcur = f;
+                    since_refresh = 0;
+                }
+                if (out >= 0) {
+                    if (A.samples) {
+                        // this wave's chains: lane = site within a word row
+                        for (int idx = lane; idx < RPW * N; idx += 64) {
+                            const int r = idx / N, i = idx % N, row = wave * RPW + r;
+                            if (row < nvalid)
+                                A.samples[((size_t)out * A.n_chains + c0 + row) * N + i] =
+                                    ((words[row * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1 : -1;
+                        }
+                    }
+                    if (A.logpsi && plane) A.logpsi[(size_t)out * A.n_chains + c0 + myrow] = fcur;
+                }
+                ++sweep;
+            }
         }
     }
     for (int idx = lane; idx < RPW * N; idx += 64) {

@@ -3,9 +3,10 @@
 
 namespace nqs {
 
-bool ffnn_reg_sample_launch_f16(int ke, bool trace, const FfnnSampleArgs &A, int blocks, size_t lds, hipStream_t s)
+bool ffnn_reg_sample_launch_f16(int ke, bool trace, bool perchain, const FfnnSampleArgs &A, int blocks, size_t lds,
+                              hipStream_t s)
 {
-    return launch_sample_ke<_Float16, 32>(ke, trace, A, blocks, lds, s);
+    return launch_sample_ke<_Float16, 32>(ke, trace, perchain, A, blocks, lds, s);
 }
 
 size_t ffnn_reg_sample_lds_f16(int N, int ke, int m2p)

@@ -67,16 +67,22 @@ def test_exchange_init_states_match_oracle(nqs):
     assert np.array_equal(r["state"], ref)
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "f16", "f32"])
-def test_cfg3_shape_exchange_replay(nqs, dtype):
-    """10x10 Heisenberg, FFNN 100 -> 400 -> 200, exchange moves: replay every traced decision in FP64."""
+@pytest.mark.parametrize("dtype,refresh", [("bf16", 1), ("f16", 1), ("f32", 1), ("bf16", 4), ("f16", 4)])
+def test_cfg3_shape_exchange_replay(nqs, dtype, refresh):
+    """10x10 Heisenberg, FFNN 100 -> 400 -> 200, exchange moves: replay every traced decision in FP64.
+
+    With the hidden pre-activations rebuilt every 4 sweeps the 16-bit sampler lets each
+    chain advance on its own (rejected exchanges of equal spins skipped, sweep ends taken
+    per chain); with a rebuild after every sweep the 64 chains of a block step together.
+    Both must make the oracle's decisions."""
     wl = workloads.cfg3_heis_10x10()
-    _say(f"cfg3 replay {dtype}")
+    _say(f"cfg3 replay {dtype} refresh {refresh}")
     params = workloads.params_for(wl)
     N = wl.model.n_visible
-    C, S, B, T = 128, 3, 2, 16
+    C, S, B, T = 128, 6, 3, 16
     model = nqs.Model.from_workload(wl, params)
-    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=wl.seed, dtype=dtype, move="exchange")
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=wl.seed, dtype=dtype, move="exchange",
+                           refresh_sweeps=refresh)
     r = _run(nqs, model, cfg, N, trace_chains=T)
     assert np.all(r["samples"].sum(axis=2) == 0)   # zero magnetisation is conserved
     om = oracle.model_from_workload(wl, params, dtype)
@@ -89,6 +95,7 @@ def test_cfg3_shape_exchange_replay(nqs, dtype):
     assert res["site_u_mismatch"] == 0
     assert res["decision_mismatch"] == 0
     assert np.array_equal(res["end_states"], r["state"][:T])
+    assert np.array_equal(r["acc"][:T], r["tr_accepted"].sum(axis=1))
     f, _ = om.logamp(r["samples"].reshape(-1, N))
     lp = r["logpsi"].ravel()
     assert np.max(np.abs(lp - f) / np.maximum(1.0, np.abs(f))) < 1e-5
@@ -218,24 +225,28 @@ def test_ffnn_logpsi_grad_matches_oracle(nqs, widths, n, N):
 # Register-resident layer 2 (16-bit operands, 128 <= padded width 1 <= 512)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("dtype,move,L,widths,C", [("f16", "exchange", 6, (200, 100), 100),
-                                                   ("bf16", "flip", 6, (144, 72), 70),
-                                                   ("bf16", "exchange", 8, (256, 250), 64)])
-def test_register_path_replay(nqs, dtype, move, L, widths, C):
+@pytest.mark.parametrize("dtype,move,L,widths,C,refresh", [("f16", "exchange", 6, (200, 100), 100, 1),
+                                                           ("bf16", "flip", 6, (144, 72), 70, 1),
+                                                           ("bf16", "exchange", 8, (256, 250), 64, 1),
+                                                           ("f16", "exchange", 6, (200, 100), 100, 4),
+                                                           ("bf16", "flip", 6, (144, 72), 70, 5),
+                                                           ("bf16", "exchange", 8, (512, 250), 130, 4)])
+def test_register_path_replay(nqs, dtype, move, L, widths, C, refresh):
     """Other first-layer widths (fragment counts), partial blocks, few output tiles, flip moves."""
     N = L * L
     kind = "heisenberg" if move == "exchange" else "tfim"
     wl = workloads.Workload(f"reg_{kind}_{L}", workloads.Hamiltonian(kind, workloads.Lattice(2, L), 1.0, 2.0,
                                                                      move == "exchange"),
                             workloads.Model("ffnn", N, widths), n_chains=C, n_sweeps=3, n_burnin=2, move=move, seed=21)
-    _say(f"register-path replay {dtype} {move} {widths}")
+    _say(f"register-path replay {dtype} {move} {widths} refresh {refresh}")
     params = 0.7 * workloads.params_for(wl)
     model = nqs.Model.from_workload(wl, params)
     T = 12
-    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=3, n_burnin=2, seed=21, dtype=dtype, move=move)
+    S, B = (3, 2) if refresh == 1 else (9, 2)
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=21, dtype=dtype, move=move, refresh_sweeps=refresh)
     r = _run(nqs, model, cfg, N, trace_chains=T)
     om = oracle.model_from_workload(wl, params, dtype)
-    ocfg = oracle.make_cfg(C, 3, 2, move=move, seed=21)
+    ocfg = oracle.make_cfg(C, S, B, move=move, seed=21)
     starts = np.array([oracle.init_chain(N, move, 21, c) for c in range(T)])
     res = oracle.replay(om, ocfg, list(range(T)), starts, r["tr_site"], r["tr_ubits"].view(np.uint32),
                         r["tr_delta"], r["tr_accepted"], tau_rel=1e-5)
@@ -243,6 +254,7 @@ def test_register_path_replay(nqs, dtype, move, L, widths, C):
          f"max |dDelta| {res['max_delta_err']:.2e}")
     assert res["site_u_mismatch"] == 0 and res["decision_mismatch"] == 0
     assert np.array_equal(res["end_states"], r["state"][:T])
+    assert np.array_equal(r["acc"][:T], r["tr_accepted"].sum(axis=1))
     f, _ = om.logamp(r["samples"].reshape(-1, N))
     assert np.max(np.abs(r["logpsi"].ravel() - f) / np.maximum(1.0, np.abs(f))) < 1e-5
 
