@@ -703,11 +703,10 @@ nqs_status ffnn_sample(nqs_model *m, const nqs_sample_cfg &cfg, int8_t *chain_st
     const int QK = (f.m1p + 63) / 64;
     const int64_t blocks = (cfg.n_chains + kRows - 1) / kRows;   // kRows == kRegRows: 64 chains per block
     if (use_reg) {
-        // Chains that advance on their own (skipping rejected exchanges and refreshing
-        // at their own sweep ends) win once the hidden pre-activations are rebuilt every
-        // few sweeps; a rebuild after every sweep is cheaper when all 64 chains of a
-        // block take it together.
-        const bool perchain = A.refresh_sweeps >= 4;
+        // With exchange moves about half the proposals swap equal spins: chains that
+        // advance on their own decide those on the spot and fill every tile with
+        // effective rows.  Flip moves are all effective, so the chains step together.
+        const bool perchain = A.move == NQS_MOVE_EXCHANGE;
         const bool ok = cfg.dtype == NQS_F16 ? ffnn_reg_sample_launch_f16(KE, tr, perchain, A, (int)blocks, lds, stream)
                                              : ffnn_reg_sample_launch_bf16(KE, tr, perchain, A, (int)blocks, lds, stream);
         if (!ok) return set_error(NQS_EUNSUPPORTED, "first hidden width not supported by the register-resident sampler");

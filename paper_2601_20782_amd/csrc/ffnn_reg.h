@@ -117,6 +117,7 @@ struct RegSampleLds {
         b += sizeof(T) * (size_t)N * K;                       // W1 columns
         b += sizeof(T) * (size_t)(kRegRows + 1) * ldh;        // h1 rows (+1: where ineffective proposals go)
         b += sizeof(float) * m2p;                             // b2
+        b += sizeof(float) * K;                               // b1 minus the W1 row sums
         b += sizeof(float) * kRegWaves * kRegRows;            // partial sums
         b += sizeof(uint32_t) * (size_t)kRegRows * NW;        // spin words
         b += sizeof(int) * 4 + 16;                            // slot counters
@@ -144,7 +145,8 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     T *W1l = reinterpret_cast<T *>(smem);           // [N][K]
     T *Hs = W1l + (size_t)N * K;                    // [kRegRows + 1][ldh]
     float *b2s = reinterpret_cast<float *>(Hs + (size_t)(kRegRows + 1) * ldh);
-    float *part = b2s + m2p;
+    float *b1c = b2s + m2p;                         // [K] b1 - sum_i W1[:, i]
+    float *part = b1c + K;
     uint32_t *words = reinterpret_cast<uint32_t *>(part + kRegWaves * kRegRows);
     int *cnt = reinterpret_cast<int *>(words + kRegRows * NW);   // [4] rows and live chains of this / the next round
 
@@ -179,24 +181,50 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
         if (tid < 4) cnt[tid] = 0;
     }
     __syncthreads();
+    for (int u = tid; u < K; u += kRegThreads) {
+        float sum = 0.0f;
+        for (int i = 0; i < N; ++i) sum += Mc<T>::to_f32(W1l[i * K + u]);
+        b1c[u] = net.b1p[u] - sum;
+    }
+    __syncthreads();
 
     float z1[RPW][8];
-    auto refresh_z1 = [&]() {
+    // z1 = W1 s + b1 of the wave's chains r in `mask` (bit r; wave-uniform), as (b1 - sum_i W1[:, i]) plus twice
+    // the sum of W1[:, i] over the chain's up spins: half the columns of a sum over all sites.  The up spins are
+    // taken in site order, four W1 columns read ahead of their use (a missing fourth weighted by 0).
+    auto refresh_rows = [&](unsigned mask) {
+        const float4 cb0 = *reinterpret_cast<const float4 *>(b1c + c8);
+        const float4 cb1 = *reinterpret_cast<const float4 *>(b1c + c8 + 4);
+        const float cb[8] = {cb0.x, cb0.y, cb0.z, cb0.w, cb1.x, cb1.y, cb1.z, cb1.w};
 #pragma unroll
-        for (int r = 0; r < RPW; ++r)
+        for (int r = 0; r < RPW; ++r) {
+            if (!((mask >> r) & 1u)) continue;
+            float up[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            for (int wi = 0; wi < NW; ++wi) {
+                uint32_t bits = __builtin_amdgcn_readfirstlane(words[(wave * RPW + r) * NW + wi]);
+                while (bits) {
+                    int idx[4];
+                    float m[4];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) z1[r][e] = net.b1p[c8 + e];
-        for (int i = 0; i < N; ++i) {
-            const frag w = *reinterpret_cast<const frag *>(W1l + i * K + c8);
+                    for (int u = 0; u < 4; ++u) {
+                        m[u] = bits ? 1.0f : 0.0f;
+                        idx[u] = bits ? 32 * wi + __builtin_ctz(bits) : 0;
+                        bits &= bits - 1u;
+                    }
+                    frag w[4];
 #pragma unroll
-            for (int r = 0; r < RPW; ++r) {
-                const int row = wave * RPW + r;
-                const float s = ((words[row * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1.0f : -1.0f;
+                    for (int u = 0; u < 4; ++u) w[u] = *reinterpret_cast<const frag *>(W1l + idx[u] * K + c8);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) z1[r][e] = fmaf(Mc<T>::to_f32(w[e]), s, z1[r][e]);
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) up[e] = fmaf(m[u], Mc<T>::to_f32(w[u][e]), up[e]);
+                }
             }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) z1[r][e] = fmaf(2.0f, up[e], cb[e]);
         }
     };
+    constexpr unsigned kAllRows = (1u << RPW) - 1u;
     // layer-1 change of flipping i (and j >= 0) where site i holds spin si (no branch: W1[:, max(j, 0)] is read
     // and weighted by 0 for a flip, which leaves W1[:, i] exact)
     auto delta_z1 = [&](int i, int j, float si, float (&dz)[8]) {
@@ -230,7 +258,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
         return f;
     };
 
-    refresh_z1();
+    refresh_rows(kAllRows);
     float fcur = full_eval();   // meaningful on proposal lanes
 
     unsigned long long acc = 0;   // accepted proposals of this lane's chain
@@ -357,22 +385,9 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
                 }
                 if (mode != 0) slot = atomicAdd(&cnt[par], 1);
             }
-            // chains that refresh: z1 recomputed from the spins (the same arithmetic as the start of the call)
-            const unsigned long long rm = __ballot(mode == 2);
-    #pragma unroll
-            for (int r = 0; r < RPW; ++r) {
-                if ((rm >> r) & 1ull) {
-                    const int row = wave * RPW + r;
-    #pragma unroll
-                    for (int e = 0; e < 8; ++e) z1[r][e] = net.b1p[c8 + e];
-                    for (int i = 0; i < N; ++i) {
-                        const frag w = *reinterpret_cast<const frag *>(W1l + i * K + c8);
-                        const float sv = ((words[row * NW + (i >> 5)] >> (i & 31)) & 1u) ? 1.0f : -1.0f;
-    #pragma unroll
-                        for (int e = 0; e < 8; ++e) z1[r][e] = fmaf(Mc<T>::to_f32(w[e]), sv, z1[r][e]);
-                    }
-                }
-            }
+            // chains that refresh: z1 recomputed from their spins
+            const unsigned rm = (unsigned)__ballot(mode == 2) & kAllRows;
+            if (rm) refresh_rows(rm);
             // stage the rows (wave-uniform per chain): every chain's row is formed, one without a row goes to the
             // spare row kRegRows, so that the code has no branch and later reads overlap earlier stores
     #pragma unroll
@@ -552,7 +567,7 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
                 in_sweep = 0;
                 const int64_t out = sweep - A.n_burnin;
                 if (++since_refresh == A.refresh_sweeps) {
-                    refresh_z1();
+                    refresh_rows(kAllRows);
                     const float f = full_eval();
                     if (plane) fcur = f;
                     since_refresh = 0;

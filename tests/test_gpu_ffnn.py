@@ -71,10 +71,9 @@ def test_exchange_init_states_match_oracle(nqs):
 def test_cfg3_shape_exchange_replay(nqs, dtype, refresh):
     """10x10 Heisenberg, FFNN 100 -> 400 -> 200, exchange moves: replay every traced decision in FP64.
 
-    With the hidden pre-activations rebuilt every 4 sweeps the 16-bit sampler lets each
-    chain advance on its own (rejected exchanges of equal spins skipped, sweep ends taken
-    per chain); with a rebuild after every sweep the 64 chains of a block step together.
-    Both must make the oracle's decisions."""
+    With exchange moves the 16-bit sampler lets each chain advance on its own (exchanges
+    of equal spins decided without an evaluation, sweep ends and rebuilds of the hidden
+    pre-activations taken per chain); rebuilt after every sweep and every 4 sweeps."""
     wl = workloads.cfg3_heis_10x10()
     _say(f"cfg3 replay {dtype} refresh {refresh}")
     params = workloads.params_for(wl)
@@ -232,7 +231,8 @@ def test_ffnn_logpsi_grad_matches_oracle(nqs, widths, n, N):
                                                            ("bf16", "flip", 6, (144, 72), 70, 5),
                                                            ("bf16", "exchange", 8, (512, 250), 130, 4)])
 def test_register_path_replay(nqs, dtype, move, L, widths, C, refresh):
-    """Other first-layer widths (fragment counts), partial blocks, few output tiles, flip moves."""
+    """Other first-layer widths (fragment counts), partial blocks, few output tiles, flip moves (chains in
+    lockstep) and exchange moves (chains on their own), z1 rebuilt after every sweep or every 4 or 5."""
     N = L * L
     kind = "heisenberg" if move == "exchange" else "tfim"
     wl = workloads.Workload(f"reg_{kind}_{L}", workloads.Hamiltonian(kind, workloads.Lattice(2, L), 1.0, 2.0,
