@@ -644,12 +644,12 @@ __device__ __forceinline__ int eloc_row_code(int i, int j, int s) { return (i + 
 // term only for an exchange), hidden units 8c .. 8c + 7, c = min(lane, nch - 1) (lanes past the row's chunks
 // repeat the last one), into Hs row lr.  W1l: [N][K] in LDS; zs: [G][2][K / 8][4] (units 8c .. 8c + 3 of
 // every chunk, then units 8c + 4 .. 8c + 7, so that the 16-byte reads of consecutive lanes are consecutive).
+// `code` is the row's code, uniform over the wave (read ahead by the caller or from rcode).
 template <typename T>
-__device__ __forceinline__ void eloc_stage_row(const T *W1l, const int *rcode, const float *rg, const float *zs,
-                                               T *Hs, int ldh, int K, int nch, int row, int lr, int lane)
+__device__ __forceinline__ void eloc_stage_row_code(const T *W1l, int code, const float *rg, const float *zs,
+                                                    T *Hs, int ldh, int K, int nch, int row, int lr, int lane)
 {
     typedef typename Mc<T>::frag frag;
-    const int code = __builtin_amdgcn_readfirstlane(rcode[row]);   // uniform over the wave
     const float g = rg[row];
     const int i = (code & 0x1FFF) - 1, j = ((code >> 13) & 0x1FFF) - 1, s = code >> 26;
     const int ic = i >= 0 ? i : 0, jc = j >= 0 ? j : 0;
@@ -667,6 +667,13 @@ __device__ __forceinline__ void eloc_stage_row(const T *W1l, const int *rcode, c
         h[e] = Mc<T>::from_f32(fmaxf(fmaf(g, d, zz[e]), 0.0f));
     }
     *reinterpret_cast<frag *>(Hs + lr * ldh + 8 * c) = h;
+}
+
+template <typename T>
+__device__ __forceinline__ void eloc_stage_row(const T *W1l, const int *rcode, const float *rg, const float *zs,
+                                               T *Hs, int ldh, int K, int nch, int row, int lr, int lane)
+{
+    eloc_stage_row_code<T>(W1l, __builtin_amdgcn_readfirstlane(rcode[row]), rg, zs, Hs, ldh, K, nch, row, lr, lane);
 }
 
 template <typename T, int KE>
@@ -906,8 +913,20 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
         // p + 1 staged in between the products, then the tile's log-cosh partial.  The two waves that share a
         // SIMD (w and w + 4) place their staging slots half a period apart (PH), so that one of them issues
         // products while the other stages.
+        // the codes of a wave's staging rows are read from LDS one pass ahead (across the barrier) and taken
+        // into scalar registers at the start of the pass, so that a staging slot waits for one LDS round trip
+        // (its W1 columns, z1 and g), not two
+        auto read_codes = [&](int q, int (&cv)[kElocStage]) {
+#pragma unroll
+            for (int rr = 0; rr < kElocStage; ++rr) cv[rr] = rcode[min(q * kElocRows + wave * kElocStage + rr, nrows - 1)];
+        };
+        int cv[kElocStage];
+        read_codes(1, cv);
         auto pass = [&](int p, auto ph_c) {
             constexpr bool PH = decltype(ph_c)::value;
+            int code[kElocStage];
+#pragma unroll
+            for (int rr = 0; rr < kElocStage; ++rr) code[rr] = __builtin_amdgcn_readfirstlane(cv[rr]);
             constexpr int kStep = KE / kElocStage;           // staging slots every kStep fragments
             constexpr int kStageAt = PH ? kStep / 2 : 0;     // first staging slot
             const T *Hc = Hs + (size_t)(p & 1) * kElocRows * ldh + lr * ldh + 8 * lh;
@@ -926,10 +945,11 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_eloc_reg_kernel(FfnnElocArgs
                 acc = Mc<T>::mma(a[kf], b[kf % 3], acc);
                 __builtin_amdgcn_sched_barrier(0);
                 if (kf >= kStageAt && (kf - kStageAt) % kStep == 0 && (kf - kStageAt) / kStep < kElocStage) {
-                    const int r = wave * kElocStage + (kf - kStageAt) / kStep;
-                    eloc_stage_row<T>(W1l, rcode, rg, zs, Hn, ldh, K, nch, min(nbase + r, nrows - 1), r, lane);
+                    const int rr = (kf - kStageAt) / kStep, r = wave * kElocStage + rr;
+                    eloc_stage_row_code<T>(W1l, code[rr], rg, zs, Hn, ldh, K, nch, min(nbase + r, nrows - 1), r, lane);
                 }
             }
+            read_codes(p + 2, cv);
             float abs_sum = 0.0f, prod = 1.0f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) eloc_logcosh4(acc, q, b2v[2 * q], abs_sum, prod);
