@@ -350,10 +350,13 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
                 }
             }
             const unsigned long long accb = __ballot(skip_acc);
-            // the window's outcome for chain r = lane (lanes 0..7), read with every lane active (a shuffle from
-            // an inactive lane returns 0): the look-ahead of its first effective step, the window's length, and
-            // the effective proposal from lane 8r + first
-            const int first_c = __shfl(first_g, 8 * (lane & 7), 64), lim_c = __shfl(lim_g, 8 * (lane & 7), 64);
+            // the window's outcome for chain r = lane (lanes 0..7): the look-ahead of its first effective step
+            // (from the ballot) and the window's length (from the chain's own counters), then the effective
+            // proposal from lane 8r + first, shuffled with every lane active (a shuffle from an inactive lane
+            // returns 0)
+            const unsigned cbits = (unsigned)(effb >> (8 * (lane & 7))) & 0xFFu;
+            const int first_c = cbits ? __builtin_ctz(cbits) : 8;
+            const int lim_c = (int)min<int64_t>(min<int64_t>(8, total - kc), (int64_t)(sw - in_sweep));
             const int src = 8 * (lane & 7) + min(first_c, 7);
             const int e_pi = __shfl(wpi, src, 64), e_pj = __shfl(wpj, src, 64);
             const uint32_t e_ub = (uint32_t)__shfl((int)wub, src, 64);
