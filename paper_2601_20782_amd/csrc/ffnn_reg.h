@@ -125,6 +125,36 @@ struct RegSampleLds {
     }
 };
 
+// a.lo * b.lo + a.hi * b.hi + c for two 16-bit values packed in a 32-bit word, on the 16-bit dot instruction;
+// pair(x, y) packs two values that the format holds exactly (0 and 1 here)
+template <typename T>
+struct Dot2;
+template <>
+struct Dot2<__bf16> {
+    typedef __bf16 v2 __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ uint32_t pair(float lo, float hi)
+    {
+        return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xFFFF0000u);
+    }
+    static __device__ __forceinline__ float dot(uint32_t a, uint32_t b, float c)
+    {
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2, a), __builtin_bit_cast(v2, b), c, false);
+    }
+};
+template <>
+struct Dot2<_Float16> {
+    typedef _Float16 v2 __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ uint32_t pair(float lo, float hi)
+    {
+        return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)lo) |
+               ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)hi) << 16);
+    }
+    static __device__ __forceinline__ float dot(uint32_t a, uint32_t b, float c)
+    {
+        return __builtin_amdgcn_fdot2(__builtin_bit_cast(v2, a), __builtin_bit_cast(v2, b), c, false);
+    }
+};
+
 // Each wave owns 8 chains: it draws their proposals (lanes 0..7), stages the
 // effective ones at slots taken from a shared counter, and after the matrix
 // product decides them and updates their state.  Two barriers per step: after
@@ -191,7 +221,9 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
     float z1[RPW][8];
     // z1 = W1 s + b1 of the wave's chains r in `mask` (bit r; wave-uniform), as (b1 - sum_i W1[:, i]) plus twice
     // the sum of W1[:, i] over the chain's up spins: half the columns of a sum over all sites.  The up spins are
-    // taken in site order, four W1 columns read ahead of their use (a missing fourth weighted by 0).
+    // taken in site order, four W1 columns read ahead of their use (a missing one weighted by 0), and two
+    // columns at a time added on the 16-bit dot instruction (each unit's pair of weights by the pair of weights
+    // 0 or 1, in FP32).
     auto refresh_rows = [&](unsigned mask) {
         const float4 cb0 = *reinterpret_cast<const float4 *>(b1c + c8);
         const float4 cb1 = *reinterpret_cast<const float4 *>(b1c + c8 + 4);
@@ -211,13 +243,21 @@ __global__ void __launch_bounds__(kRegThreads) ffnn_sample_reg_kernel(FfnnSample
                         idx[u] = bits ? 32 * wi + __builtin_ctz(bits) : 0;
                         bits &= bits - 1u;
                     }
-                    frag w[4];
+                    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+                    u32x4_t w[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) w[u] = *reinterpret_cast<const frag *>(W1l + idx[u] * K + c8);
+                    for (int u = 0; u < 4; ++u) w[u] = *reinterpret_cast<const u32x4_t *>(W1l + idx[u] * K + c8);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < 4; u += 2) {
+                        const uint32_t mp = Dot2<T>::pair(m[u], m[u + 1]);
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) up[e] = fmaf(m[u], Mc<T>::to_f32(w[u][e]), up[e]);
+                        for (int k = 0; k < 4; ++k) {
+                            // (unit 2k of columns u, u + 1), (unit 2k + 1 of columns u, u + 1)
+                            up[2 * k] = Dot2<T>::dot(__builtin_amdgcn_perm(w[u + 1][k], w[u][k], 0x05040100u), mp, up[2 * k]);
+                            up[2 * k + 1] =
+                                Dot2<T>::dot(__builtin_amdgcn_perm(w[u + 1][k], w[u][k], 0x07060302u), mp, up[2 * k + 1]);
+                        }
+                    }
                 }
             }
 #pragma unroll
