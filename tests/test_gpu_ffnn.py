@@ -259,6 +259,36 @@ def test_register_path_replay(nqs, dtype, move, L, widths, C, refresh):
     assert np.max(np.abs(r["logpsi"].ravel() - f) / np.maximum(1.0, np.abs(f))) < 1e-5
 
 
+@pytest.mark.parametrize("dtype,refresh,S1,S", [("bf16", 1, 3, 5), ("f16", 2, 2, 4)])
+def test_register_path_resume_bit_exact(nqs, dtype, refresh, S1, S):
+    """10x10 Heisenberg network, exchange moves (chains on their own): two calls, the second resuming from the
+    first one's end states at its step offset, give the samples, log-amplitudes, end states and accepted counts
+    of one call, bit for bit, when the split falls on a rebuild of z1 (each call starts from the same rebuild
+    as the ones inside a call); 130 chains, so the last block holds two."""
+    wl = workloads.cfg3_heis_10x10()
+    _say(f"register-path resume {dtype} refresh {refresh}")
+    params = workloads.params_for(wl)
+    N = wl.model.n_visible
+    C = 130
+    model = nqs.Model.from_workload(wl, params)
+    kw = dict(n_chains=C, n_burnin=0, seed=wl.seed, dtype=dtype, move="exchange", refresh_sweeps=refresh)
+    full = _run(nqs, model, nqs.SampleConfig(n_sweeps=S, **kw), N)
+    first = _run(nqs, model, nqs.SampleConfig(n_sweeps=S1, **kw), N)
+    state = torch.from_numpy(first["state"]).to(DEV)
+    samples = torch.empty(S - S1, C, N, dtype=torch.int8, device=DEV)
+    logpsi = torch.empty(S - S1, C, dtype=torch.float32, device=DEV)
+    acc = torch.empty(C, dtype=torch.int64, device=DEV)
+    nqs.nqs_sample(model, nqs.SampleConfig(n_sweeps=S - S1, step_offset=S1 * N, init_chains=False, **kw), state,
+                   samples, logpsi, acc)
+    torch.cuda.synchronize()
+    assert np.array_equal(full["samples"][:S1], first["samples"])
+    assert np.array_equal(full["samples"][S1:], samples.cpu().numpy())
+    assert np.array_equal(full["logpsi"][:S1], first["logpsi"])
+    assert np.array_equal(full["logpsi"][S1:], logpsi.cpu().numpy())
+    assert np.array_equal(full["state"], state.cpu().numpy())
+    assert np.array_equal(full["acc"], first["acc"] + acc.cpu().numpy())
+
+
 @pytest.mark.parametrize("dtype,kind,dim,L,widths,n_s", [("bf16", "tfim", 2, 6, (144, 72), 41),
                                                          ("f16", "heisenberg", 2, 6, (130, 40), 37),
                                                          ("bf16", "heisenberg", 1, 16, (256, 250), 10),
