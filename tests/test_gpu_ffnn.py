@@ -259,6 +259,37 @@ def test_register_path_replay(nqs, dtype, move, L, widths, C, refresh):
     assert np.max(np.abs(r["logpsi"].ravel() - f) / np.maximum(1.0, np.abs(f))) < 1e-5
 
 
+@pytest.mark.parametrize("dtype,sw,refresh", [("bf16", 37, 3), ("f16", 150, 1)])
+def test_register_path_replay_sweep_size(nqs, dtype, sw, refresh):
+    """Exchange moves (chains on their own) with sweeps of 37 and of 150 proposals on 64 sites, so that sweep ends
+    fall inside a chain's look-ahead window at every offset; 100 chains, FFNN 64 -> 256 -> 250."""
+    L, widths, C, S, B = 8, (256, 250), 100, 7, 2
+    N = L * L
+    wl = workloads.Workload("reg_heisenberg_8", workloads.Hamiltonian("heisenberg", workloads.Lattice(2, L), 1.0, 2.0,
+                                                                      True),
+                            workloads.Model("ffnn", N, widths), n_chains=C, n_sweeps=S, n_burnin=B, move="exchange",
+                            seed=23)
+    _say(f"register-path replay {dtype} sweep {sw} refresh {refresh}")
+    params = 0.7 * workloads.params_for(wl)
+    model = nqs.Model.from_workload(wl, params)
+    T = 12
+    cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=23, dtype=dtype, move="exchange",
+                           refresh_sweeps=refresh, sweep_size=sw)
+    r = _run(nqs, model, cfg, N, trace_chains=T)
+    om = oracle.model_from_workload(wl, params, dtype)
+    ocfg = oracle.make_cfg(C, S, B, move="exchange", seed=23, sweep_size=sw)
+    starts = np.array([oracle.init_chain(N, "exchange", 23, c) for c in range(T)])
+    res = oracle.replay(om, ocfg, list(range(T)), starts, r["tr_site"], r["tr_ubits"].view(np.uint32),
+                        r["tr_delta"], r["tr_accepted"], tau_rel=1e-5)
+    _say(f"  replay: {res['decisions_equal']} equal, {res['near_ties']} near ties, "
+         f"max |dDelta| {res['max_delta_err']:.2e}")
+    assert res["site_u_mismatch"] == 0 and res["decision_mismatch"] == 0
+    assert np.array_equal(res["end_states"], r["state"][:T])
+    assert np.array_equal(r["acc"][:T], r["tr_accepted"].sum(axis=1))
+    f, _ = om.logamp(r["samples"].reshape(-1, N))
+    assert np.max(np.abs(r["logpsi"].ravel() - f) / np.maximum(1.0, np.abs(f))) < 1e-5
+
+
 @pytest.mark.parametrize("dtype,refresh,S1,S", [("bf16", 1, 3, 5), ("f16", 2, 2, 4)])
 def test_register_path_resume_bit_exact(nqs, dtype, refresh, S1, S):
     """10x10 Heisenberg network, exchange moves (chains on their own): two calls, the second resuming from the
