@@ -229,10 +229,12 @@ def test_ffnn_logpsi_grad_matches_oracle(nqs, widths, n, N):
                                                            ("bf16", "exchange", 8, (256, 250), 64, 1),
                                                            ("f16", "exchange", 6, (200, 100), 100, 4),
                                                            ("bf16", "flip", 6, (144, 72), 70, 5),
-                                                           ("bf16", "exchange", 8, (512, 250), 130, 4)])
+                                                           ("bf16", "exchange", 8, (512, 250), 130, 4),
+                                                           ("bf16", "exchange", 6, (200, 100), 3, 4)])
 def test_register_path_replay(nqs, dtype, move, L, widths, C, refresh):
-    """Other first-layer widths (fragment counts), partial blocks, few output tiles, flip moves (chains in
-    lockstep) and exchange moves (chains on their own), z1 rebuilt after every sweep or every 4 or 5."""
+    """Other first-layer widths (fragment counts), partial blocks (down to 3 chains: seven waves without a
+    chain), few output tiles, flip moves (chains in lockstep) and exchange moves (chains on their own), z1
+    rebuilt after every sweep or every 4 or 5."""
     N = L * L
     kind = "heisenberg" if move == "exchange" else "tfim"
     wl = workloads.Workload(f"reg_{kind}_{L}", workloads.Hamiltonian(kind, workloads.Lattice(2, L), 1.0, 2.0,
@@ -241,7 +243,7 @@ def test_register_path_replay(nqs, dtype, move, L, widths, C, refresh):
     _say(f"register-path replay {dtype} {move} {widths} refresh {refresh}")
     params = 0.7 * workloads.params_for(wl)
     model = nqs.Model.from_workload(wl, params)
-    T = 12
+    T = min(12, C)
     S, B = (3, 2) if refresh == 1 else (9, 2)
     cfg = nqs.SampleConfig(n_chains=C, n_sweeps=S, n_burnin=B, seed=21, dtype=dtype, move=move, refresh_sweeps=refresh)
     r = _run(nqs, model, cfg, N, trace_chains=T)
