@@ -322,6 +322,30 @@ def test_register_path_resume_bit_exact(nqs, dtype, refresh, S1, S):
     assert np.array_equal(full["acc"], first["acc"] + acc.cpu().numpy())
 
 
+def test_register_path_burnin_only_then_resume(nqs):
+    """A call of burn-in sweeps only (nothing written but the chain states and accepted counts), then a call that
+    resumes from those states: the samples and log-amplitudes of one call with that burn-in, bit for bit."""
+    wl = workloads.cfg3_heis_10x10()
+    params = workloads.params_for(wl)
+    N, C, B, S = wl.model.n_visible, 70, 3, 2
+    model = nqs.Model.from_workload(wl, params)
+    kw = dict(n_chains=C, seed=wl.seed, dtype="bf16", move="exchange", refresh_sweeps=1)
+    full = _run(nqs, model, nqs.SampleConfig(n_sweeps=S, n_burnin=B, **kw), N)
+    state = torch.zeros(C, N, dtype=torch.int8, device=DEV)
+    acc = torch.empty(C, dtype=torch.int64, device=DEV)
+    nqs.nqs_sample(model, nqs.SampleConfig(n_sweeps=0, n_burnin=B, **kw), state, None, None, acc)
+    samples = torch.empty(S, C, N, dtype=torch.int8, device=DEV)
+    logpsi = torch.empty(S, C, dtype=torch.float32, device=DEV)
+    acc2 = torch.empty(C, dtype=torch.int64, device=DEV)
+    nqs.nqs_sample(model, nqs.SampleConfig(n_sweeps=S, n_burnin=0, step_offset=B * N, init_chains=False, **kw),
+                   state, samples, logpsi, acc2)
+    torch.cuda.synchronize()
+    assert np.array_equal(full["samples"], samples.cpu().numpy())
+    assert np.array_equal(full["logpsi"], logpsi.cpu().numpy())
+    assert np.array_equal(full["state"], state.cpu().numpy())
+    assert np.array_equal(full["acc"], acc.cpu().numpy() + acc2.cpu().numpy())
+
+
 @pytest.mark.parametrize("dtype,kind,dim,L,widths,n_s", [("bf16", "tfim", 2, 6, (144, 72), 41),
                                                          ("f16", "heisenberg", 2, 6, (130, 40), 37),
                                                          ("bf16", "heisenberg", 1, 16, (256, 250), 10),
