@@ -292,19 +292,27 @@ def test_register_path_replay_sweep_size(nqs, dtype, sw, refresh):
     assert np.max(np.abs(r["logpsi"].ravel() - f) / np.maximum(1.0, np.abs(f))) < 1e-5
 
 
-@pytest.mark.parametrize("dtype,refresh,S1,S", [("bf16", 1, 3, 5), ("f16", 2, 2, 4)])
-def test_register_path_resume_bit_exact(nqs, dtype, refresh, S1, S):
-    """10x10 Heisenberg network, exchange moves (chains on their own): two calls, the second resuming from the
-    first one's end states at its step offset, give the samples, log-amplitudes, end states and accepted counts
-    of one call, bit for bit, when the split falls on a rebuild of z1 (each call starts from the same rebuild
-    as the ones inside a call); 130 chains, so the last block holds two."""
-    wl = workloads.cfg3_heis_10x10()
-    _say(f"register-path resume {dtype} refresh {refresh}")
-    params = workloads.params_for(wl)
+@pytest.mark.parametrize("dtype,move,refresh,S1,S", [("bf16", "exchange", 1, 3, 5), ("f16", "exchange", 2, 2, 4),
+                                                     ("bf16", "flip", 2, 2, 5)])
+def test_register_path_resume_bit_exact(nqs, dtype, move, refresh, S1, S):
+    """Two calls, the second resuming from the first one's end states at its step offset, give the samples,
+    log-amplitudes, end states and accepted counts of one call, bit for bit, when the split falls on a rebuild
+    of z1 (each call starts from the same rebuild as the ones inside a call): the 10x10 Heisenberg network with
+    exchange moves (chains on their own) and a 6x6 TFIM network (144, 72) with flips (chains in lockstep);
+    130 chains, so the last block holds two."""
+    if move == "exchange":
+        wl = workloads.cfg3_heis_10x10()
+        params = workloads.params_for(wl)
+    else:
+        wl = workloads.Workload("reg_tfim_6", workloads.Hamiltonian("tfim", workloads.Lattice(2, 6), 1.0, 2.0, False),
+                                workloads.Model("ffnn", 36, (144, 72)), n_chains=130, n_sweeps=S, n_burnin=0,
+                                move="flip", seed=29)
+        params = 0.7 * workloads.params_for(wl)
+    _say(f"register-path resume {dtype} {move} refresh {refresh}")
     N = wl.model.n_visible
     C = 130
     model = nqs.Model.from_workload(wl, params)
-    kw = dict(n_chains=C, n_burnin=0, seed=wl.seed, dtype=dtype, move="exchange", refresh_sweeps=refresh)
+    kw = dict(n_chains=C, n_burnin=0, seed=wl.seed, dtype=dtype, move=move, refresh_sweeps=refresh)
     full = _run(nqs, model, nqs.SampleConfig(n_sweeps=S, **kw), N)
     first = _run(nqs, model, nqs.SampleConfig(n_sweeps=S1, **kw), N)
     state = torch.from_numpy(first["state"]).to(DEV)
