@@ -124,6 +124,17 @@ def test_heis10_full_size(nqs):
     f, _ = om.logamp(smp)
     scale = np.abs(ref) + 2 * 200 + 2 * 200 * np.exp(1.0)
     assert np.all(np.abs(el.cpu().numpy() - ref) < 4e-6 * np.maximum(1.0, np.abs(f)) * scale)
+    # the same run writing log|psi| of every sample: the samples are unchanged, and the values carried by the
+    # incremental z1 between rebuilds (every 4 sweeps) match the oracle's forward pass of the sampled spins
+    _say("heis10 full size: run with log|psi|")
+    state = torch.empty(C, N, dtype=torch.int8, device=DEV)
+    samples = torch.empty(S, C, N, dtype=torch.int8, device=DEV)
+    logpsi = torch.empty(S, C, dtype=torch.float32, device=DEV)
+    nqs.nqs_sample(model, cfg, state, samples, logpsi)
+    torch.cuda.synchronize()
+    assert torch.equal(a["samples"], samples)
+    lp = logpsi.reshape(-1)[torch.from_numpy(pick).to(DEV)].cpu().numpy()
+    assert np.max(np.abs(lp - f) / np.maximum(1.0, np.abs(f))) < 1e-5
 
 
 def test_heis20_full_size_sweep(nqs):
